@@ -1,0 +1,216 @@
+"""Dense state-vector simulator of the walk on tiny registers (test pin).
+
+Independent of the oracle: the full register space (j_c, j, b1, k_c, k, b2)
+of 2^(4n+2) amplitudes is held as one dense numpy vector whose flat index is
+the packed key [j_c | j | b1 | k_c | k | b2].  Each operator is built as a
+permutation, a block of small dense matrices or a sign, without an explicit
+data register: the three QRAM reads of Alg. 5 (O_A' compute, rotation,
+O_A' uncompute around O_s' / O_s'^dagger) collapse into one rotation on b2
+applied in the (l, z) frame, controlled by the row j, the slot l and the
+column register value z ^ k_{j,l}.
+
+Preprocessing is written out again here (scale by 1/max(1, max|a|), s = next
+power of two of the largest column count, filler rows = smallest missing
+indices with value 0) so that nothing is taken from the oracle.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+
+def preprocess(csc, scale=None):
+    n = csc.n
+    nbits = max(1, int(np.ceil(np.log2(n))))
+    N = 1 << nbits
+    counts = np.diff(csc.colptr)
+    s = 1 << int(np.ceil(np.log2(max(1, counts.max()))))
+    if scale is None:
+        scale = 1.0 / max(1.0, np.abs(csc.vals).max())
+    col = np.zeros((N, s), np.int64)
+    val = np.zeros((N, s))
+    for c in range(N):
+        rows = list(csc.rowidx[csc.colptr[c]:csc.colptr[c + 1]]) if c < n else []
+        vals = list(csc.vals[csc.colptr[c]:csc.colptr[c + 1]] * scale) if c < n else []
+        present = set(rows)
+        r = 0
+        while len(rows) < s:
+            if r not in present:
+                rows.append(r)
+                vals.append(0.0)
+            r += 1
+        order = np.argsort(rows)
+        col[c] = np.asarray(rows)[order]
+        val[c] = np.asarray(vals)[order]
+    return N, nbits, s, scale, col, val
+
+
+def _position(col, j, k):
+    row = col[j]
+    hit = np.nonzero(row == k)[0]
+    return int(hit[0]) if hit.size else 0
+
+
+class DenseWalk:
+    def __init__(self, csc, scale=None):
+        self.N, self.n, self.s, self.scale, self.col, self.val = preprocess(csc, scale)
+        N, s = self.N, self.s
+        self.shape = (N, N, 2, N, N, 2)
+        self.size = int(np.prod(self.shape))
+        c = np.indices(self.shape).reshape(6, -1)
+        jc, j, b1, kc, k, b2 = c
+        flat = lambda *a: np.ravel_multi_index(a, self.shape)
+        # position table pos[j, k] = i_j(k)
+        pos = np.zeros((N, N), np.int64)
+        for r in range(N):
+            for x in range(N):
+                pos[r, x] = _position(self.col, r, x)
+        # O_s': (l in k, z in k_c) -> (k, k_c) for l < s; registers swapped for l >= s
+        valid = k < s
+        knew = np.where(valid, kc ^ self.col[j, np.minimum(k, s - 1)], kc)
+        kcnew = np.where(valid, k ^ pos[j, knew], k)
+        self.os_perm = flat(jc, j, b1, kcnew, knew, b2)
+        assert np.unique(self.os_perm).size == self.size
+        self.s_perm = flat(kc, k, b2, jc, j, b1)
+        self.p_sign = np.where((jc == 0) & (b1 == 0) & (kc == 0) & (k == 0) & (b2 == 0), 1.0, -1.0)
+        # rotation in the (l, z) frame: controlled by j, l = k register, z = k_c register
+        ll = np.minimum(k, s - 1)
+        a = self.val[j, ll]
+        colk = kc ^ self.col[j, ll]
+        f = np.where(a >= 0, np.sqrt(np.abs(a)) + 0j,
+                     np.where(j <= colk, 1j, -1j) * np.sqrt(np.abs(a)))
+        g = np.sqrt(1.0 - np.abs(a))
+        self.rot_valid = valid
+        self.f, self.g = f, g
+        self.b2 = b2
+        self.partner = flat(jc, j, b1, kc, k, 1 - b2)
+        hs = np.array([[1.0]])
+        while hs.shape[0] < s:
+            hs = np.block([[hs, hs], [hs, -hs]])
+        self.hmat = hs / np.sqrt(s)
+
+    # --- operators on a dense vector
+    def OS(self, psi):
+        out = np.zeros_like(psi)
+        out[self.os_perm] = psi
+        return out
+
+    def OSinv(self, psi):
+        return psi[self.os_perm]
+
+    def S(self, psi):
+        out = np.zeros_like(psi)
+        out[self.s_perm] = psi
+        return out
+
+    def P(self, psi):
+        return psi * self.p_sign
+
+    def H(self, psi):
+        N, s = self.N, self.s
+        v = psi.reshape(N, N, 2, N, N // s, s, 2)
+        return np.einsum("xy,abcdeyg->abcdexg", self.hmat, v).reshape(-1)
+
+    def R(self, psi, dagger=False):
+        v = psi
+        w = v[self.partner]
+        f, g = self.f, self.g
+        if not dagger:
+            # [[f, -g], [g, conj f]]
+            new = np.where(self.b2 == 0, f * v - g * w, g * w + np.conj(f) * v)
+        else:
+            # [[conj f, g], [-g, f]]
+            new = np.where(self.b2 == 0, np.conj(f) * v + g * w, -g * w + f * v)
+        if np.any(~self.rot_valid & (np.abs(psi) > 0)):
+            raise AssertionError("amplitude outside the slot range at a rotation")
+        return np.where(self.rot_valid, new, psi)
+
+    def T(self, psi):
+        return self.OS(self.R(self.H(psi)))
+
+    def Tdag(self, psi):
+        return self.H(self.R(self.OSinv(psi), dagger=True))
+
+    def W(self, psi):
+        return self.S(self.T(self.P(self.Tdag(psi))))
+
+    def basis_b(self, b):
+        psi = np.zeros(self.size, complex)
+        for j, bj in enumerate(b):
+            psi[np.ravel_multi_index((0, j, 0, 0, 0, 0), self.shape)] = bj
+        return psi
+
+
+def torch_loss(csc, vals_scaled, b, w, nsteps, scale=1.0):
+    """Same dense walk written with torch ops, differentiable in the stored
+    (already scaled) CSC values and in b.  Returns (loss, vals tensor, b tensor).
+    Loss = sum_j w_j p_j with p the marginal of register j after
+    W^nsteps T~ |b~>."""
+    import torch
+
+    dw = DenseWalk(csc, scale=scale)
+    N, s = dw.N, dw.s
+    v = torch.tensor(np.asarray(vals_scaled, dtype=np.float64), requires_grad=True)
+    bt = torch.tensor(np.asarray(b, dtype=np.complex128), requires_grad=True)
+    # ELL value table as a differentiable gather of the CSC values
+    slot_of = np.full((N, s), -1, np.int64)
+    for c in range(csc.n):
+        for p in range(csc.colptr[c], csc.colptr[c + 1]):
+            l = int(np.nonzero(dw.col[c] == csc.rowidx[p])[0][0])
+            slot_of[c, l] = p
+    ell = torch.zeros(N * s, dtype=torch.float64)
+    idx = np.nonzero(slot_of.reshape(-1) >= 0)[0]
+    ell = ell.index_put((torch.tensor(idx),), v[torch.tensor(slot_of.reshape(-1)[idx])])
+    ell = ell.reshape(N, s)
+    c = np.indices(dw.shape).reshape(6, -1)
+    jc, j, b1, kc, k, b2 = c
+    ll = np.minimum(k, s - 1)
+    a = ell[torch.tensor(j), torch.tensor(ll)]
+    colk = kc ^ dw.col[j, ll]
+    neg_phase = np.where(j <= colk, 1j, -1j)
+    phase = torch.where(a >= 0, torch.ones_like(a, dtype=torch.complex128),
+                        torch.tensor(neg_phase, dtype=torch.complex128))
+    f = torch.sqrt(torch.abs(a)) * phase
+    g = torch.sqrt(1.0 - torch.abs(a)).to(torch.complex128)
+    valid = torch.tensor(dw.rot_valid)
+    b2t = torch.tensor(dw.b2)
+    partner = torch.tensor(dw.partner)
+    os_perm = torch.tensor(dw.os_perm)
+    s_perm = torch.tensor(dw.s_perm)
+    p_sign = torch.tensor(dw.p_sign, dtype=torch.complex128)
+    hmat = torch.tensor(dw.hmat, dtype=torch.complex128)
+
+    def R(psi, dagger):
+        wv = psi[partner]
+        if not dagger:
+            new = torch.where(b2t == 0, f * psi - g * wv, g * wv + torch.conj(f) * psi)
+        else:
+            new = torch.where(b2t == 0, torch.conj(f) * psi + g * wv, -g * wv + f * psi)
+        return torch.where(valid, new, psi)
+
+    def H(psi):
+        x = psi.reshape(N, N, 2, N, N // s, s, 2)
+        return torch.einsum("xy,abcdeyg->abcdexg", hmat, x).reshape(-1)
+
+    def OS(psi):
+        return torch.zeros_like(psi).index_put((os_perm,), psi)
+
+    def OSinv(psi):
+        return psi[os_perm]
+
+    def S(psi):
+        return torch.zeros_like(psi).index_put((s_perm,), psi)
+
+    psi = torch.zeros(dw.size, dtype=torch.complex128)
+    jidx = torch.tensor([np.ravel_multi_index((0, jj, 0, 0, 0, 0), dw.shape) for jj in range(len(b))])
+    psi = psi.index_put((jidx,), bt)
+    psi = OS(R(H(psi), False))
+    for _ in range(nsteps):
+        t = H(R(OSinv(psi), True))
+        t = t * p_sign
+        t = OS(R(H(t), False))
+        psi = S(t)
+    prob = (psi.real ** 2 + psi.imag ** 2).reshape(N, N, 2, N, N, 2).sum(dim=(0, 2, 3, 4, 5))
+    wt = torch.zeros(N, dtype=torch.float64)
+    wt[:len(w)] = torch.tensor(np.asarray(w, dtype=np.float64))
+    loss = (prob * wt).sum()
+    return loss, v, bt
