@@ -1,0 +1,190 @@
+/*
+ * qw.h -- C ABI of the MI355X quantum-walk library (libqw.so).
+ *
+ * The library simulates, at register level and on a sparse state, the quantum
+ * walk on a sparse real symmetric matrix stored in QRAM (Chen et al., arXiv
+ * 2303.06890): the walk step W = S T~ P T~^dagger of Alg. 6 on the six
+ * registers j_c, j, b1, k_c, k, b2 (Sec. IV, "Implementation of the quantum
+ * walk"), its inverse, the walk-based Chebyshev linear solver (Eq. "fx" and
+ * the iteration of Sec. V.B), measurements, a batched multi-instance form and
+ * a reverse-mode gradient.
+ *
+ * Conventions shared by every entry point
+ *   - Return value: QW_OK (0) or a negative qw_status.  Functions never throw
+ *     and never abort; qw_last_error() returns the text of the last error of
+ *     the calling thread.
+ *   - Host arrays are borrowed for the duration of the call only.
+ *   - Device memory comes from the caller's allocator (qw_allocator; NULL
+ *     means hipMalloc/hipFree) and belongs to the qw_ctx or qw_state that
+ *     allocated it until it is freed.  Nothing is allocated inside qw_step,
+ *     qw_step_adjoint or qls_run's step loop.
+ *   - `stream` is a hipStream_t passed as void* (NULL = the null stream).
+ *     qw_load_csc*, qw_state_init, qw_state_import, qw_step and
+ *     qw_step_adjoint only enqueue work; qw_measure, qw_export, qls_run,
+ *     qw_grad and qw_sync synchronise the stream and copy results to the host.
+ *     Errors raised on the device (state capacity exceeded) are reported by
+ *     the next synchronising call on that state.
+ *   - Indices are 0-based.  A matrix is given in CSC form (colptr[n+1],
+ *     rowidx[nnz] sorted and unique inside each column, vals[nnz] real).  The
+ *     walk's row register j addresses CSC column j: the QRAM row j holds the
+ *     row indices and values of column j (the same data for a symmetric
+ *     matrix, which the paper's "CSC" storage of Sec. II.C assumes).
+ *
+ * Register key layout (packed 64-bit, high to low bits)
+ *     [ inst | j_c (n) | j (n) | b1 | k_c (n) | k (n) | b2 ]
+ *   n = log2 of the padded dimension (the largest one over all instances of a
+ *   batched context); inst = instance index (0 for a single matrix).
+ *   4n+2 + bits(inst) must not exceed 64.
+ */
+#ifndef QW_H
+#define QW_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  QW_OK = 0,
+  QW_EINVAL = -1,    /* invalid argument or matrix */
+  QW_ENOMEM = -2,    /* allocation failed */
+  QW_ECAPACITY = -3, /* state list capacity exceeded (state is invalid) */
+  QW_EDEVICE = -4,   /* HIP runtime error */
+  QW_ENOTSUP = -5    /* valid request outside what this build supports */
+} qw_status;
+
+typedef struct qw_ctx qw_ctx;     /* preprocessed matrices resident on the GPU */
+typedef struct qw_state qw_state; /* a walk state (sparse, on the GPU) */
+
+/* Device allocator hooks; `alloc` returns a device pointer aligned to 256
+ * bytes or NULL.  The Python binding plugs in torch's caching allocator. */
+typedef struct {
+  void* (*alloc)(size_t bytes, void* user);
+  void (*free)(void* ptr, void* user);
+  void* user;
+} qw_allocator;
+
+/* flags for qw_load_csc / qw_load_csc_batched */
+#define QW_REQUIRE_SYMMETRIC 0x1u /* reject matrices that are not symmetric */
+
+/* flags for qw_state_init */
+#define QW_INIT_RAW 0x1u /* start from |b~> itself instead of T~|b~> */
+
+/* kinds for qw_measure */
+#define QW_COUNT 1      /* out: int64[1]   number of stored branches M */
+#define QW_NORM 2       /* out: double[1]  sum |amp|^2 */
+#define QW_J_MARGINAL 3 /* out: double[sum N_i]  probability of each j value */
+#define QW_PROJECT 4    /* out: double[2 sum N_i] interleaved complex <psi~_j|state> */
+#define QW_STATS 5      /* out: int64[4] {steps done, branches written by the last
+                           step, capacity, overflow flag} */
+
+/* Load one matrix (Sec. V.B, preprocessing list; Sec. II.C, Fig. 1):
+ *   scale: > 0 multiplies every value by `scale`; 0 selects 1/max(1, max|a|).
+ *   The QRAM row length s is the power of two >= the largest column count
+ *   (Table I, note b); each row is padded to s sorted unique slots with the
+ *   smallest absent indices carrying value 0; the dimension is padded to a
+ *   power of two N with empty columns.
+ * Errors: QW_EINVAL for n <= 0, bad colptr, row indices out of range,
+ *   unsorted or duplicate, |scale*a| > 1, a negative diagonal entry (not
+ *   encodable: <j~|T~^dagger S T~|j~> = |f|^2/s >= 0), a non-symmetric matrix
+ *   when QW_REQUIRE_SYMMETRIC is set; QW_ENOTSUP for s > 64 or 4n+2 > 64. */
+int qw_load_csc(qw_ctx** out, int32_t n, const int32_t* colptr, const int32_t* rowidx,
+                const double* vals, int64_t nnz, double scale, uint32_t flags,
+                const qw_allocator* alloc, void* stream);
+
+/* Load `ninst` independent matrices into one context (batched form).
+ * Instance i: dimension n[i], colptr at colptr + colptr_off[i] (n[i]+1
+ * entries, relative to the instance's first entry), rowidx/vals at
+ * nnz_off[i].  scales: NULL (automatic for every instance) or ninst values
+ * with the meaning of qw_load_csc's scale.  Same errors as qw_load_csc. */
+int qw_load_csc_batched(qw_ctx** out, int32_t ninst, const int32_t* n, const int64_t* colptr_off,
+                        const int64_t* nnz_off, const int32_t* colptr, const int32_t* rowidx,
+                        const double* vals, const double* scales, uint32_t flags,
+                        const qw_allocator* alloc, void* stream);
+
+/* Per-instance facts: padded dimension N, slots per row s, register width n
+ * of the key layout (common to all instances), scale applied. */
+int qw_ctx_info(const qw_ctx* ctx, int32_t inst, int32_t* n_padded, int32_t* s, int32_t* nbits,
+                double* scale);
+int32_t qw_ctx_ninst(const qw_ctx* ctx);
+
+/* Create a state holding T~ |b~> (Alg. 5 applied to |b~> = sum_j b_j |0,j,0,0,0,0>,
+ * Sec. IV) or |b~> itself with QW_INIT_RAW.  b_re/b_im (b_im may be NULL):
+ * sum_i n[i] values, instance after instance; b is used as given (callers
+ * normalise).  capacity: maximum number of branches the sparse branch list
+ * may hold; 0 selects 2 * sum N_i s_i + 2 * (nonzeros of b), which holds every
+ * state reachable from T~|b~> (they lie in the span of the reflection slots
+ * and their image under O_s'^-1 S O_s').  Errors: QW_EINVAL, QW_ENOMEM. */
+int qw_state_init(qw_state** out, qw_ctx* ctx, const double* b_re, const double* b_im, uint32_t flags,
+                  int64_t capacity, void* stream);
+
+/* Apply W^nsteps (Alg. 6: W = S T~ P T~^dagger), branches with |Re| and |Im|
+ * both <= tau (1e-13) removed after every step.  Asynchronous; the step loop
+ * is replayed from a captured HIP graph when `stream` is not NULL. */
+int qw_step(qw_state* st, int32_t nsteps, void* stream);
+
+/* Apply (W^dagger)^nsteps, W^dagger = T~ P T~^dagger S (unitarity of W). */
+int qw_step_adjoint(qw_state* st, int32_t nsteps, void* stream);
+
+/* Measurements (kinds above).  out_len is the number of elements of `out`. */
+int qw_measure(qw_state* st, int32_t kind, void* out, int64_t out_len, void* stream);
+
+/* Copy the state to the host, sorted by key.  cap = size of the host arrays;
+ * *m receives the branch count (QW_EINVAL with *m set if cap < count). */
+int qw_export(qw_state* st, uint64_t* keys, double* re, double* im, int64_t cap, int64_t* m,
+              void* stream);
+
+/* Replace the state by the given branches (equal keys are summed).  Keys must
+ * follow the layout above with valid instance and register ranges, and every
+ * branch must satisfy j_c < s and k_c < s (true of every state the walk
+ * reaches).  Errors: QW_EINVAL, QW_ECAPACITY. */
+int qw_state_import(qw_state* st, const uint64_t* keys, const double* re, const double* im, int64_t m,
+                    void* stream);
+
+/* Wait for the stream and report a device-side error of the state. */
+int qw_sync(qw_state* st, void* stream);
+
+/* Walk-based CKS linear solver on instance 0 (Sec. IV, CKS paragraph; Eq. "fx";
+ * Sec. V.B, iteration of tau_j):
+ *   beta = ceil(kappa^2 ln(kappa/eps)), j0 = ceil(sqrt(beta ln(4 beta/eps)))
+ *   (j0_override >= 0 replaces j0), a_k the coefficients of Eq. "fx";
+ *   omega = W T~ |b~>; for k = 0..j0: y += a_k Pi_0 T~^dagger omega; then
+ *   omega = W^2 omega (k < j0).  2 j0 + 1 walk steps in total.
+ * kappa: condition number of A/s (1 / smallest |eigenvalue|), > 1.
+ * y_re/y_im (N values, host): the unnormalised post-selected output
+ * sum_k a_k tau_k; the solution estimate is y/|y|.  p_succ = |y|^2 /
+ * (sum_k |a_k|)^2.  walk_steps receives 2 j0 + 1.  Either output pointer may
+ * be NULL.  Errors: QW_EINVAL (kappa <= 1, eps outside (0,1), b NULL). */
+int qls_run(qw_ctx* ctx, const double* b, double kappa, double eps, int32_t j0_override,
+            double* y_re, double* y_im, double* p_succ, int64_t* walk_steps, void* stream);
+
+/* Chebyshev coefficients a_0..a_j0 of Eq. "fx" for the given beta (host). */
+int qw_cks_coeffs(int64_t beta, int32_t j0, double* out);
+
+/* Reverse-mode gradient of L = sum_j w_j p_j, p = j-register marginal of the
+ * state, where the state was created by qw_state_init (T~ start) and then
+ * advanced by exactly `nsteps` calls' worth of qw_step.  Earlier states are
+ * recomputed with W^dagger (exact checkpointing: W is unitary), never stored.
+ * w: sum N_i weights.  dvals: gradient w.r.t. every stored CSC value after
+ * scaling (CSC order, instance after instance; entries whose value is 0 or
+ * has |value| = 1 are not differentiable and come out non-finite).
+ * db_re/db_im: dL/dRe b + i dL/dIm b (sum n_i values).  Any output may be
+ * NULL.  The state is consumed (left holding the recomputed T~|b~>). */
+int qw_grad(qw_state* st, const double* w, int32_t nsteps, double* dvals, double* db_re, double* db_im,
+            double* loss, void* stream);
+
+void qw_state_free(qw_state* st);
+void qw_ctx_free(qw_ctx* ctx);
+const char* qw_last_error(void);
+
+/* Kernel launch shape (work items per thread, workgroup size) of the step
+ * kernel; 0 keeps the current value.  Used by the autotuner. */
+int qw_set_launch(qw_state* st, int32_t wg_size, int32_t grid_limit);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* QW_H */

@@ -1,0 +1,302 @@
+"""MI355X quantum-walk library: Python binding of libqw.so.
+
+The walk of arXiv:2303.06890 (W = S T~ P T~^dagger on the registers
+j_c, j, b1, k_c, k, b2 of a sparse symmetric matrix stored in QRAM) runs in
+hand-written HIP kernels behind the C ABI of include/qw.h.  This module only
+marshals arguments: torch provides device memory (through the allocator
+hooks) and the current stream; every step of the walk runs in the library.
+"""
+from __future__ import annotations
+
+import ctypes
+
+import numpy as np
+
+from . import _lib
+from ._lib import QwError, check  # noqa: F401
+
+__all__ = ["Walk", "State", "QwError", "WalkObservable", "cks_coeffs", "schedule", "pack_key"]
+
+
+def _torch():
+    import torch
+
+    return torch
+
+
+def _stream():
+    torch = _torch()
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+class _TorchAllocator:
+    """Device memory from torch's caching allocator."""
+
+    def __init__(self, device):
+        self.device = device
+        self.live = {}
+        self._a = _lib.ALLOC_T(self._alloc)
+        self._f = _lib.FREE_T(self._free)
+        self.struct = _lib.QwAllocator(self._a, self._f, None)
+
+    def _alloc(self, nbytes, user):
+        try:
+            t = _torch().empty(int(nbytes), dtype=_torch().uint8, device=self.device)
+        except Exception:  # out of memory: report NULL to the library
+            return None
+        p = t.data_ptr()
+        self.live[p] = t
+        return p
+
+    def _free(self, p, user):
+        self.live.pop(p, None)
+
+
+def _dp(a):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+def _ip(a):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))
+
+
+def _lp(a):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_int64))
+
+
+def _up(a):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_uint64))
+
+
+class Walk:
+    """One or more sparse symmetric matrices preprocessed and resident on the
+    GPU (a ``qw_ctx``).  ``mats``: a CSC object (attributes n, colptr,
+    rowidx, vals) or a list of them (batched form).  ``scale``: None
+    (automatic 1/max(1, max|a|)), a float, or one float per matrix."""
+
+    def __init__(self, mats, scale=None, symmetric: bool = True, torch_alloc: bool = True):
+        lib = _lib.load()
+        self.mats = list(mats) if isinstance(mats, (list, tuple)) else [mats]
+        self.ninst = len(self.mats)
+        self._alloc = _TorchAllocator(_torch().device("cuda", _torch().cuda.current_device())) if torch_alloc else None
+        n = np.array([m.n for m in self.mats], np.int32)
+        colptr = np.concatenate([np.asarray(m.colptr, np.int32) for m in self.mats])
+        rowidx = np.concatenate([np.asarray(m.rowidx, np.int32) for m in self.mats])
+        vals = np.concatenate([np.asarray(m.vals, np.float64) for m in self.mats])
+        coff = np.cumsum([0] + [m.n + 1 for m in self.mats[:-1]]).astype(np.int64)
+        zoff = np.cumsum([0] + [len(m.rowidx) for m in self.mats[:-1]]).astype(np.int64)
+        if scale is None:
+            sc = None
+        else:
+            sc = np.broadcast_to(np.asarray(scale, np.float64), (self.ninst,)).copy()
+        self._keep = (n, colptr, rowidx, vals, coff, zoff, sc)
+        h = ctypes.c_void_p()
+        flags = _lib.QW_REQUIRE_SYMMETRIC if symmetric else 0
+        check(lib.qw_load_csc_batched(ctypes.byref(h), self.ninst, _ip(n), _lp(coff), _lp(zoff), _ip(colptr),
+                                      _ip(rowidx), _dp(vals), _dp(sc) if sc is not None else None, flags,
+                                      ctypes.byref(self._alloc.struct) if self._alloc else None, _stream()))
+        self._h = h
+        self.info = []
+        for i in range(self.ninst):
+            N, s, nb = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+            scv = ctypes.c_double()
+            check(lib.qw_ctx_info(h, i, ctypes.byref(N), ctypes.byref(s), ctypes.byref(nb), ctypes.byref(scv)))
+            self.info.append(dict(N=N.value, s=s.value, nbits=nb.value, scale=scv.value))
+        self.nbits = self.info[0]["nbits"]
+        self.N_total = sum(d["N"] for d in self.info)
+        self.n_total = int(n.sum())
+        self.nnz_total = int(vals.shape[0])
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _lib.load().qw_ctx_free(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def state(self, b, raw: bool = False, capacity: int = 0) -> "State":
+        """T~|b~> (or |b~> with raw=True); ``b``: sum n_i values, instance
+        after instance (a list of per-instance vectors is concatenated)."""
+        if isinstance(b, (list, tuple)):
+            b = np.concatenate([np.asarray(x) for x in b])
+        b = np.asarray(b)
+        if b.shape[0] != self.n_total:
+            raise ValueError(f"b has {b.shape[0]} entries, expected {self.n_total}")
+        br = np.ascontiguousarray(b.real, dtype=np.float64)
+        bi = np.ascontiguousarray(np.imag(b) if np.iscomplexobj(b) else np.zeros_like(br), dtype=np.float64)
+        h = ctypes.c_void_p()
+        check(_lib.load().qw_state_init(ctypes.byref(h), self._h, _dp(br), _dp(bi),
+                                         _lib.QW_INIT_RAW if raw else 0, int(capacity), _stream()))
+        return State(self, h)
+
+    def qls(self, b, kappa: float, eps: float = 1e-3, j0: int | None = None):
+        """Walk-based CKS solve on instance 0: returns (y, p_succ, walk_steps)
+        with y the unnormalised post-selected output (solution ~ y/|y|)."""
+        b = np.ascontiguousarray(b, dtype=np.float64)
+        n0 = self.mats[0].n
+        yr, yi = np.zeros(n0), np.zeros(n0)
+        p = ctypes.c_double()
+        steps = ctypes.c_int64()
+        check(_lib.load().qls_run(self._h, _dp(b), float(kappa), float(eps), -1 if j0 is None else int(j0),
+                                  _dp(yr), _dp(yi), ctypes.byref(p), ctypes.byref(steps), _stream()))
+        return yr + 1j * yi, p.value, steps.value
+
+
+class State:
+    """A walk state on the GPU (a ``qw_state``)."""
+
+    def __init__(self, walk: Walk, h):
+        self.walk = walk
+        self._h = h
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _lib.load().qw_state_free(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def step(self, n: int = 1) -> "State":
+        check(_lib.load().qw_step(self._h, int(n), _stream()))
+        return self
+
+    def step_adjoint(self, n: int = 1) -> "State":
+        check(_lib.load().qw_step_adjoint(self._h, int(n), _stream()))
+        return self
+
+    def sync(self) -> "State":
+        check(_lib.load().qw_sync(self._h, _stream()))
+        return self
+
+    def set_launch(self, wg_size: int = 0, grid: int = 0) -> "State":
+        check(_lib.load().qw_set_launch(self._h, int(wg_size), int(grid)))
+        return self
+
+    def _measure(self, kind, out):
+        check(_lib.load().qw_measure(self._h, kind, out.ctypes.data_as(ctypes.c_void_p), out.size, _stream()))
+        return out
+
+    def count(self) -> int:
+        return int(self._measure(_lib.QW_COUNT, np.zeros(1, np.int64))[0])
+
+    def norm2(self) -> float:
+        return float(self._measure(_lib.QW_NORM, np.zeros(1))[0])
+
+    def j_marginal(self) -> np.ndarray:
+        return self._measure(_lib.QW_J_MARGINAL, np.zeros(self.walk.N_total))
+
+    def project(self) -> np.ndarray:
+        out = self._measure(_lib.QW_PROJECT, np.zeros(2 * self.walk.N_total))
+        return out[0::2] + 1j * out[1::2]
+
+    def stats(self) -> dict:
+        o = self._measure(_lib.QW_STATS, np.zeros(4, np.int64))
+        return dict(steps=int(o[0]), last_written=int(o[1]), capacity=int(o[2]), overflow=int(o[3]))
+
+    def export(self):
+        """(keys uint64 sorted, amplitudes complex128)."""
+        m = self.count()
+        keys = np.zeros(m, np.uint64)
+        re, im = np.zeros(m), np.zeros(m)
+        got = ctypes.c_int64()
+        check(_lib.load().qw_export(self._h, _up(keys), _dp(re), _dp(im), m, ctypes.byref(got), _stream()))
+        return keys[:got.value], (re + 1j * im)[:got.value]
+
+    def import_(self, keys, amps) -> "State":
+        keys = np.ascontiguousarray(keys, dtype=np.uint64)
+        re = np.ascontiguousarray(np.real(amps), dtype=np.float64)
+        im = np.ascontiguousarray(np.imag(amps), dtype=np.float64)
+        check(_lib.load().qw_state_import(self._h, _up(keys), _dp(re), _dp(im), keys.shape[0], _stream()))
+        return self
+
+    def grad(self, w, nsteps: int):
+        """Reverse-mode gradient of sum_j w_j p_j after ``nsteps`` steps from
+        T~|b~>: returns (loss, dvals in CSC order, db complex)."""
+        w = np.ascontiguousarray(w, dtype=np.float64)
+        if w.shape[0] != self.walk.n_total:
+            raise ValueError("w must have one weight per column of every instance")
+        dv = np.zeros(self.walk.nnz_total)
+        dbr, dbi = np.zeros(self.walk.n_total), np.zeros(self.walk.n_total)
+        loss = ctypes.c_double()
+        check(_lib.load().qw_grad(self._h, _dp(w), int(nsteps), _dp(dv), _dp(dbr), _dp(dbi), ctypes.byref(loss),
+                                  _stream()))
+        return loss.value, dv, dbr + 1j * dbi
+
+
+def cks_coeffs(beta: int, j0: int) -> np.ndarray:
+    out = np.zeros(j0 + 1)
+    check(_lib.load().qw_cks_coeffs(int(beta), int(j0), _dp(out)))
+    return out
+
+
+def pack_key(nbits: int, jc, j, b1, kc, k, b2, inst=0) -> int:
+    """Key layout [inst | j_c | j | b1 | k_c | k | b2] (high to low bits)."""
+    key = int(inst)
+    for v, wdt in ((jc, nbits), (j, nbits), (b1, 1), (kc, nbits), (k, nbits), (b2, 1)):
+        key = (key << wdt) | int(v)
+    return key
+
+
+class _CscArrays:
+    def __init__(self, n, colptr, rowidx, vals):
+        self.n, self.colptr, self.rowidx, self.vals = n, colptr, rowidx, vals
+
+
+def _make_walk_observable():
+    torch = _torch()
+
+    class WalkObservable(torch.autograd.Function):
+        """p = j-register marginal of W^nsteps T~|b~> for the matrix with the
+        given CSC pattern and (already scaled) values; differentiable in the
+        values and in b.  The backward pass is the library's reverse sweep
+        (qw_grad): earlier states are recomputed with W^dagger."""
+
+        @staticmethod
+        def forward(ctx, vals, b, pattern, nsteps):
+            v = vals.detach().cpu().numpy().astype(np.float64)
+            mat = _CscArrays(pattern.n, np.asarray(pattern.colptr, np.int32), np.asarray(pattern.rowidx, np.int32), v)
+            walk = Walk(mat, scale=1.0)
+            st = walk.state(b.detach().cpu().numpy())
+            st.step(int(nsteps))
+            p = st.j_marginal()[: pattern.n]
+            ctx.walk, ctx.st, ctx.nsteps = walk, st, int(nsteps)
+            ctx.b_complex = b.is_complex()
+            return torch.from_numpy(p.copy())
+
+        @staticmethod
+        def backward(ctx, grad_p):
+            w = grad_p.detach().cpu().numpy().astype(np.float64)
+            _, dv, db = ctx.st.grad(w, ctx.nsteps)
+            ctx.st.close()
+            gv = torch.from_numpy(dv)
+            gb = torch.from_numpy(db) if ctx.b_complex else torch.from_numpy(db.real.copy())
+            return gv, gb, None, None
+
+    return WalkObservable
+
+
+class _Lazy:
+    _cls = None
+
+    def __getattr__(self, name):
+        if _Lazy._cls is None:
+            _Lazy._cls = _make_walk_observable()
+        return getattr(_Lazy._cls, name)
+
+
+WalkObservable = _Lazy()
+
+
+def schedule(kappa: float, eps: float = 1e-3):
+    """(beta, j0) of the CKS series: beta = ceil(kappa^2 ln(kappa/eps)),
+    j0 = ceil(sqrt(beta ln(4 beta/eps)))."""
+    b = float(np.ceil(kappa * kappa * np.log(kappa / eps)))
+    return int(b), int(np.ceil(np.sqrt(b * np.log(4.0 * b / eps))))

@@ -1,0 +1,958 @@
+// Host side of libqw: matrix preprocessing, state management, HIP-graph
+// replay of the step loop, the linear solver and the gradient sweep, behind
+// the C ABI declared in include/qw.h.
+#include "../../include/qw.h"
+#include "qw_internal.h"
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <numeric>
+#include <string>
+#include <vector>
+
+using qw::Buf;
+using qw::Ctl;
+
+namespace {
+
+thread_local std::string g_err;
+
+int set_err(int code, const std::string& msg) {
+  g_err = msg;
+  return code;
+}
+
+#define QW_HIP(call)                                                                              \
+  do {                                                                                            \
+    hipError_t e_ = (call);                                                                       \
+    if (e_ != hipSuccess) return set_err(QW_EDEVICE, std::string(#call ": ") + hipGetErrorString(e_)); \
+  } while (0)
+
+int ceil_log2(int64_t x) {
+  int r = 0;
+  while ((int64_t(1) << r) < x) ++r;
+  return r;
+}
+
+struct Alloc {
+  qw_allocator a{};
+  bool custom = false;
+  void* get(size_t bytes) {
+    bytes = (bytes + 255) & ~size_t(255);
+    if (bytes == 0) bytes = 256;
+    if (custom) return a.alloc(bytes, a.user);
+    void* p = nullptr;
+    if (hipMalloc(&p, bytes) != hipSuccess) return nullptr;
+    return p;
+  }
+  void put(void* p) {
+    if (!p) return;
+    if (custom)
+      a.free(p, a.user);
+    else
+      (void)hipFree(p);
+  }
+};
+
+struct HostInst {
+  int32_t n = 0, N = 0, nbits = 0, s = 0, hbits = 0;
+  double scale = 1.0;
+  int64_t item_base = 0, jbase = 0, nnz_base = 0, nnz = 0;
+};
+
+}  // namespace
+
+struct qw_ctx {
+  Alloc alloc;
+  int32_t ninst = 0;
+  int32_t nbits = 0;  // key register width
+  int64_t items = 0;  // ELL slots incl. alignment padding
+  int64_t jtotal = 0;
+  int64_t ntotal = 0;  // sum of unpadded n_i
+  int64_t nnz_total = 0;
+  std::vector<HostInst> inst;
+  std::vector<int64_t> csc_slot;  // ELL slot of every CSC entry
+  int32_t* col = nullptr;
+  double* val = nullptr;
+  qw::Inst* dinst = nullptr;
+  qw::Matrix mat() const {
+    qw::Matrix m;
+    m.col = col;
+    m.val = val;
+    m.inst = dinst;
+    m.ninst = ninst;
+    m.nbits = nbits;
+    m.items = items;
+    return m;
+  }
+};
+
+namespace {
+
+struct GraphEntry {
+  hipStream_t stream;
+  int parity;
+  int steps;
+  hipGraphExec_t exec;
+};
+
+}  // namespace
+
+struct qw_state {
+  qw_ctx* ctx = nullptr;
+  Buf buf[2]{};
+  Ctl* ctl = nullptr;
+  uint32_t cap = 0;
+  int cur = 0;
+  double2* b = nullptr;     // device copy of b (N-vector layout)
+  double* mbuf = nullptr;   // measurement scratch: max(4096, 2*jtotal) doubles
+  bool prepared = false;    // created by T~ |b~>
+  int64_t steps_since_init = 0;
+  int block = 256;
+  int grid = 0;             // 0 = automatic
+  std::vector<GraphEntry> graphs;
+  std::vector<void*> owned;
+};
+
+namespace {
+
+constexpr int kGraphSteps = 16;  // steps per captured graph (even: buffer parity is preserved)
+constexpr int kMaxGrid = 4096;
+
+void free_graphs(qw_state* st) {
+  for (auto& g : st->graphs) (void)hipGraphExecDestroy(g.exec);
+  st->graphs.clear();
+}
+
+int step_grid(const qw_state* st) {
+  if (st->grid > 0) return st->grid;
+  const int64_t work = 2 * st->ctx->items;  // slots + a list of similar size
+  int64_t g = (work + st->block - 1) / st->block;
+  g = std::max<int64_t>(64, std::min<int64_t>(g, 2048));
+  return int(g);
+}
+
+qw::StepArgs step_args(qw_state* st, int mode, double2* yacc, const double* coefm) {
+  qw::StepArgs a;
+  a.m = st->ctx->mat();
+  a.in = st->buf[st->cur];
+  a.out = st->buf[st->cur ^ 1];
+  a.ctl = st->ctl;
+  a.cap = st->cap;
+  a.mode = mode;
+  a.tau = qw::kTau;
+  a.yacc = yacc;
+  a.coefm = coefm;
+  return a;
+}
+
+int launch_one(qw_state* st, int mode, hipStream_t stream, double2* yacc = nullptr, const double* coefm = nullptr) {
+  qw::StepArgs a = step_args(st, mode, yacc, coefm);
+  QW_HIP(qw::launch_step(a, step_grid(st), st->block, stream));
+  st->cur ^= 1;
+  return QW_OK;
+}
+
+// Run `n` plain steps (or solver steps with accumulation), replaying a
+// captured graph of kGraphSteps steps when a stream is given.
+int run_steps(qw_state* st, int64_t n, hipStream_t stream, double2* yacc = nullptr, const double* coefm = nullptr) {
+  if (stream != nullptr && n >= kGraphSteps) {
+    GraphEntry* ge = nullptr;
+    for (auto& g : st->graphs)
+      if (g.stream == stream && g.parity == st->cur && g.steps == kGraphSteps && yacc == nullptr) ge = &g;
+    hipGraphExec_t exec = nullptr;
+    if (ge) {
+      exec = ge->exec;
+    } else {
+      hipGraph_t graph;
+      QW_HIP(hipStreamBeginCapture(stream, hipStreamCaptureModeThreadLocal));
+      const int cur0 = st->cur;
+      for (int i = 0; i < kGraphSteps; ++i) {
+        qw::StepArgs a = step_args(st, qw::kStep, yacc, coefm);
+        hipError_t e = qw::launch_step(a, step_grid(st), st->block, stream);
+        st->cur ^= 1;
+        if (e != hipSuccess) {
+          hipGraph_t dummy;
+          (void)hipStreamEndCapture(stream, &dummy);
+          st->cur = cur0;
+          return set_err(QW_EDEVICE, std::string("step capture: ") + hipGetErrorString(e));
+        }
+      }
+      QW_HIP(hipStreamEndCapture(stream, &graph));
+      hipError_t e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+      (void)hipGraphDestroy(graph);
+      if (e != hipSuccess) return set_err(QW_EDEVICE, std::string("graph instantiate: ") + hipGetErrorString(e));
+      if (yacc == nullptr) st->graphs.push_back({stream, cur0, kGraphSteps, exec});
+    }
+    const int64_t reps = n / kGraphSteps;
+    for (int64_t r = 0; r < reps; ++r) QW_HIP(hipGraphLaunch(exec, stream));
+    if (yacc != nullptr) {
+      QW_HIP(hipStreamSynchronize(stream));
+      (void)hipGraphExecDestroy(exec);
+    }
+    n -= reps * kGraphSteps;
+  }
+  for (int64_t i = 0; i < n; ++i) {
+    int rc = launch_one(st, qw::kStep, stream, yacc, coefm);
+    if (rc) return rc;
+  }
+  return QW_OK;
+}
+
+int check_overflow(qw_state* st, hipStream_t stream) {
+  Ctl h;
+  QW_HIP(hipMemcpyAsync(&h, st->ctl, sizeof(Ctl), hipMemcpyDeviceToHost, stream));
+  QW_HIP(hipStreamSynchronize(stream));
+  if (h.overflow)
+    return set_err(QW_ECAPACITY, "state branch list overflowed its capacity of " + std::to_string(st->cap) +
+                                     " entries; the state is invalid (create it with a larger capacity)");
+  return QW_OK;
+}
+
+// ---- matrix preprocessing ------------------------------------------------------
+
+struct Ell {
+  std::vector<int32_t> col;
+  std::vector<double> val;
+};
+
+// Validate one CSC instance, rescale, round s up to a power of two, pad every
+// column to s sorted unique slots (filler = smallest absent rows, value 0)
+// and the dimension to a power of two.
+int preprocess(int32_t n, const int32_t* colptr, const int32_t* rowidx, const double* vals, double scale_in,
+               uint32_t flags, HostInst& hi, Ell& ell, std::vector<int64_t>& slot_of) {
+  if (n <= 0) return set_err(QW_EINVAL, "matrix dimension must be positive");
+  if (colptr[0] != 0) return set_err(QW_EINVAL, "colptr[0] must be 0");
+  int64_t smax = 1;
+  double amax = 0.0;
+  for (int32_t c = 0; c < n; ++c) {
+    if (colptr[c + 1] < colptr[c]) return set_err(QW_EINVAL, "colptr is not monotone");
+    smax = std::max<int64_t>(smax, colptr[c + 1] - colptr[c]);
+    for (int64_t p = colptr[c]; p < colptr[c + 1]; ++p) {
+      if (rowidx[p] < 0 || rowidx[p] >= n) return set_err(QW_EINVAL, "row index out of range");
+      if (p > colptr[c] && rowidx[p] <= rowidx[p - 1])
+        return set_err(QW_EINVAL, "row indices must be sorted and unique inside a column");
+      if (!std::isfinite(vals[p])) return set_err(QW_EINVAL, "non-finite matrix value");
+      amax = std::max(amax, std::fabs(vals[p]));
+      if (rowidx[p] == c && vals[p] < 0.0)
+        return set_err(QW_EINVAL, "negative diagonal entry: not encodable by the walk (<j|T^+ S T|j> = |f|^2/s >= 0)");
+    }
+  }
+  const double scale = scale_in > 0.0 ? scale_in : 1.0 / std::max(1.0, amax);
+  if (amax * scale > 1.0) return set_err(QW_EINVAL, "|a| > 1 after scaling");
+  if (flags & QW_REQUIRE_SYMMETRIC) {
+    for (int32_t c = 0; c < n; ++c)
+      for (int64_t p = colptr[c]; p < colptr[c + 1]; ++p) {
+        const int32_t r = rowidx[p];
+        const int32_t* b = rowidx + colptr[r];
+        const int32_t* e = rowidx + colptr[r + 1];
+        const int32_t* f = std::lower_bound(b, e, c);
+        if (f == e || *f != c || vals[colptr[r] + (f - b)] != vals[p])
+          return set_err(QW_EINVAL, "matrix is not symmetric (pass flags=0 to accept it)");
+      }
+  }
+  hi.n = n;
+  hi.scale = scale;
+  hi.hbits = ceil_log2(smax);
+  hi.s = 1 << hi.hbits;
+  hi.nbits = std::max(1, ceil_log2(n));
+  hi.N = 1 << hi.nbits;
+  if (hi.s > qw::kMaxS) return set_err(QW_ENOTSUP, "rows with more than 64 slots are not supported");
+  if (hi.s > hi.N) return set_err(QW_EINVAL, "s exceeds the padded dimension");
+  ell.col.assign(size_t(hi.N) * hi.s, 0);
+  ell.val.assign(size_t(hi.N) * hi.s, 0.0);
+  slot_of.assign(size_t(colptr[n]), -1);
+  std::vector<int32_t> rows;
+  std::vector<char> present(hi.N, 0);
+  for (int32_t c = 0; c < hi.N; ++c) {
+    const int64_t p0 = c < n ? colptr[c] : 0, p1 = c < n ? colptr[c + 1] : 0;
+    for (int64_t p = p0; p < p1; ++p) present[rowidx[p]] = 1;
+    // merge the stored rows with the smallest absent ones
+    rows.clear();
+    int64_t need = hi.s - (p1 - p0);
+    for (int32_t r = 0; need > 0; ++r)
+      if (!present[r]) {
+        rows.push_back(r);
+        --need;
+      }
+    int64_t p = p0;
+    size_t f = 0;
+    for (int l = 0; l < hi.s; ++l) {
+      const size_t q = size_t(c) * hi.s + l;
+      if (p < p1 && (f >= rows.size() || rowidx[p] < rows[f])) {
+        ell.col[q] = rowidx[p];
+        ell.val[q] = vals[p] * scale;
+        slot_of[p] = int64_t(q);
+        ++p;
+      } else {
+        ell.col[q] = rows[f++];
+        ell.val[q] = 0.0;
+      }
+    }
+    for (int64_t pp = p0; pp < p1; ++pp) present[rowidx[pp]] = 0;
+  }
+  return QW_OK;
+}
+
+int load_impl(qw_ctx** out, int32_t ninst, const int32_t* n, const int64_t* colptr_off, const int64_t* nnz_off,
+              const int32_t* colptr, const int32_t* rowidx, const double* vals, const double* scales, uint32_t flags,
+              const qw_allocator* alloc, void* stream_v) {
+  if (!out) return set_err(QW_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (ninst <= 0 || !n || !colptr || !rowidx || !vals) return set_err(QW_EINVAL, "missing matrix arrays");
+  hipStream_t stream = static_cast<hipStream_t>(stream_v);
+  qw_ctx* ctx = new qw_ctx;
+  if (alloc) {
+    if (!alloc->alloc || !alloc->free) {
+      delete ctx;
+      return set_err(QW_EINVAL, "allocator needs alloc and free");
+    }
+    ctx->alloc.a = *alloc;
+    ctx->alloc.custom = true;
+  }
+  ctx->ninst = ninst;
+  ctx->inst.resize(ninst);
+  std::vector<int32_t> hcol;
+  std::vector<double> hval;
+  int64_t items = 0, jbase = 0, nnz_base = 0, ntot = 0;
+  int nbits = 1;
+  for (int32_t i = 0; i < ninst; ++i) {
+    const int64_t co = colptr_off ? colptr_off[i] : 0;
+    const int64_t zo = nnz_off ? nnz_off[i] : 0;
+    HostInst& hi = ctx->inst[i];
+    Ell ell;
+    std::vector<int64_t> slot_of;
+    int rc = preprocess(n[i], colptr + co, rowidx + zo, vals + zo, scales ? scales[i] : 0.0, flags, hi, ell, slot_of);
+    if (rc) {
+      g_err = "instance " + std::to_string(i) + ": " + g_err;
+      delete ctx;
+      return rc;
+    }
+    hi.item_base = items;
+    hi.jbase = jbase;
+    hi.nnz_base = nnz_base;
+    hi.nnz = colptr[co + n[i]];
+    const int64_t slots = int64_t(hi.N) * hi.s;
+    hcol.resize(size_t(items + slots), 0);
+    hval.resize(size_t(items + slots), 0.0);
+    std::copy(ell.col.begin(), ell.col.end(), hcol.begin() + items);
+    std::copy(ell.val.begin(), ell.val.end(), hval.begin() + items);
+    for (int64_t q : slot_of) ctx->csc_slot.push_back(q + items);
+    items += (slots + qw::kWave - 1) / qw::kWave * qw::kWave;
+    hcol.resize(size_t(items), 0);
+    hval.resize(size_t(items), 0.0);
+    jbase += hi.N;
+    nnz_base += hi.nnz;
+    ntot += n[i];
+    nbits = std::max(nbits, hi.nbits);
+  }
+  const int instbits = ceil_log2(ninst);
+  if (4 * nbits + 2 + instbits > 64) {
+    delete ctx;
+    return set_err(QW_ENOTSUP, "register key does not fit 64 bits (4n+2+instance bits > 64)");
+  }
+  ctx->nbits = nbits;
+  ctx->items = items;
+  ctx->jtotal = jbase;
+  ctx->ntotal = ntot;
+  ctx->nnz_total = nnz_base;
+  std::vector<qw::Inst> dinst(ninst);
+  for (int32_t i = 0; i < ninst; ++i) {
+    const HostInst& hi = ctx->inst[i];
+    dinst[i].item_base = hi.item_base;
+    dinst[i].jbase = hi.jbase;
+    dinst[i].N = hi.N;
+    dinst[i].s = hi.s;
+    dinst[i].hbits = hi.hbits;
+    dinst[i].pad_ = 0;
+    dinst[i].inv_sqrt_s = 1.0 / std::sqrt(double(hi.s));
+  }
+  ctx->col = static_cast<int32_t*>(ctx->alloc.get(sizeof(int32_t) * items));
+  ctx->val = static_cast<double*>(ctx->alloc.get(sizeof(double) * items));
+  ctx->dinst = static_cast<qw::Inst*>(ctx->alloc.get(sizeof(qw::Inst) * ninst));
+  if (!ctx->col || !ctx->val || !ctx->dinst) {
+    qw_ctx_free(ctx);
+    return set_err(QW_ENOMEM, "device allocation failed for the matrix");
+  }
+  hipError_t e = hipMemcpyAsync(ctx->col, hcol.data(), sizeof(int32_t) * items, hipMemcpyHostToDevice, stream);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(ctx->val, hval.data(), sizeof(double) * items, hipMemcpyHostToDevice, stream);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(ctx->dinst, dinst.data(), sizeof(qw::Inst) * ninst, hipMemcpyHostToDevice, stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(stream);  // host vectors go out of scope
+  if (e != hipSuccess) {
+    qw_ctx_free(ctx);
+    return set_err(QW_EDEVICE, std::string("matrix upload: ") + hipGetErrorString(e));
+  }
+  *out = ctx;
+  return QW_OK;
+}
+
+// ---- states ---------------------------------------------------------------------
+
+int state_alloc(qw_ctx* ctx, int64_t capacity, qw_state** out, hipStream_t stream) {
+  if (capacity <= 0 || capacity > int64_t(0xFFFFFFF0u)) return set_err(QW_EINVAL, "capacity out of range");
+  qw_state* st = new qw_state;
+  st->ctx = ctx;
+  st->cap = uint32_t(capacity);
+  auto get = [&](size_t bytes) {
+    void* p = ctx->alloc.get(bytes);
+    if (p) st->owned.push_back(p);
+    return p;
+  };
+  bool ok = true;
+  for (int k = 0; k < 2; ++k) {
+    st->buf[k].R = static_cast<double2*>(get(sizeof(double2) * 2 * ctx->items));
+    st->buf[k].key = static_cast<uint64_t*>(get(sizeof(uint64_t) * st->cap));
+    st->buf[k].amp = static_cast<double2*>(get(sizeof(double2) * st->cap));
+    ok = ok && st->buf[k].R && st->buf[k].key && st->buf[k].amp;
+  }
+  st->ctl = static_cast<Ctl*>(get(sizeof(Ctl)));
+  st->b = static_cast<double2*>(get(sizeof(double2) * ctx->jtotal));
+  st->mbuf = static_cast<double*>(get(sizeof(double) * std::max<int64_t>(kMaxGrid, 2 * ctx->jtotal)));
+  ok = ok && st->ctl && st->b && st->mbuf;
+  if (!ok) {
+    qw_state_free(st);
+    return set_err(QW_ENOMEM, "device allocation failed for the state");
+  }
+  st->buf[0].cnt = &st->ctl->cnt[0];
+  st->buf[1].cnt = &st->ctl->cnt[1];
+  st->buf[0].cap = st->cap;
+  st->buf[1].cap = st->cap;
+  hipError_t e = qw::launch_fill(st->buf[0].R, sizeof(double2) * 2 * ctx->items, stream);
+  if (e == hipSuccess) e = qw::launch_fill(st->buf[1].R, sizeof(double2) * 2 * ctx->items, stream);
+  if (e == hipSuccess) e = qw::launch_fill(st->ctl, sizeof(Ctl), stream);
+  if (e == hipSuccess) e = qw::launch_fill(st->b, sizeof(double2) * ctx->jtotal, stream);
+  if (e != hipSuccess) {
+    qw_state_free(st);
+    return set_err(QW_EDEVICE, std::string("state clear: ") + hipGetErrorString(e));
+  }
+  *out = st;
+  return QW_OK;
+}
+
+// Reset a state to empty (both R buffers and the control block cleared).
+int state_clear(qw_state* st, hipStream_t stream) {
+  const int64_t rb = sizeof(double2) * 2 * st->ctx->items;
+  QW_HIP(qw::launch_fill(st->buf[0].R, rb, stream));
+  QW_HIP(qw::launch_fill(st->buf[1].R, rb, stream));
+  QW_HIP(qw::launch_fill(st->ctl, sizeof(Ctl), stream));
+  st->cur = 0;
+  return QW_OK;
+}
+
+// Import unique, validated branches into buffer `cur`.
+int import_branches(qw_state* st, const std::vector<uint64_t>& keys, const std::vector<double2>& amps,
+                    hipStream_t stream) {
+  const int64_t m = int64_t(keys.size());
+  if (m == 0) return QW_OK;
+  qw_ctx* ctx = st->ctx;
+  void* dk = ctx->alloc.get(sizeof(uint64_t) * m);
+  void* da = ctx->alloc.get(sizeof(double2) * m);
+  if (!dk || !da) {
+    ctx->alloc.put(dk);
+    ctx->alloc.put(da);
+    return set_err(QW_ENOMEM, "device allocation failed for the import");
+  }
+  hipError_t e = hipMemcpyAsync(dk, keys.data(), sizeof(uint64_t) * m, hipMemcpyHostToDevice, stream);
+  if (e == hipSuccess) e = hipMemcpyAsync(da, amps.data(), sizeof(double2) * m, hipMemcpyHostToDevice, stream);
+  if (e == hipSuccess)
+    e = qw::launch_import(ctx->mat(), static_cast<uint64_t*>(dk), static_cast<double2*>(da), m, st->buf[st->cur],
+                          st->ctl, st->cap, stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(stream);
+  ctx->alloc.put(dk);
+  ctx->alloc.put(da);
+  if (e != hipSuccess) return set_err(QW_EDEVICE, std::string("import: ") + hipGetErrorString(e));
+  return check_overflow(st, stream);
+}
+
+// Validate keys against the context's layout; merge equal keys.
+int canonical_branches(const qw_ctx* ctx, const uint64_t* keys, const double* re, const double* im, int64_t m,
+                       std::vector<uint64_t>& ok, std::vector<double2>& oa) {
+  const int n = ctx->nbits;
+  const uint64_t nm = (uint64_t(1) << n) - 1;
+  std::vector<int64_t> idx(m);
+  std::iota(idx.begin(), idx.end(), 0);
+  std::sort(idx.begin(), idx.end(), [&](int64_t a, int64_t b) { return keys[a] < keys[b]; });
+  ok.clear();
+  oa.clear();
+  for (int64_t t = 0; t < m; ++t) {
+    const int64_t i = idx[t];
+    const uint64_t key = keys[i];
+    const uint64_t inst = key >> (4 * n + 2);
+    if (inst >= uint64_t(ctx->ninst)) return set_err(QW_EINVAL, "key with an instance index out of range");
+    const HostInst& hi = ctx->inst[inst];
+    const uint64_t k = (key >> 1) & nm, kc = (key >> (n + 1)) & nm, j = (key >> (2 * n + 2)) & nm,
+                   jc = (key >> (3 * n + 2)) & nm;
+    if (k >= uint64_t(hi.N) || j >= uint64_t(hi.N) || kc >= uint64_t(hi.s) || jc >= uint64_t(hi.s))
+      return set_err(QW_EINVAL, "key with a register value out of range (j,k < N and j_c,k_c < s required)");
+    const double2 a = make_double2(re ? re[i] : 0.0, im ? im[i] : 0.0);
+    if (!ok.empty() && ok.back() == key) {
+      oa.back().x += a.x;
+      oa.back().y += a.y;
+    } else {
+      ok.push_back(key);
+      oa.push_back(a);
+    }
+  }
+  // drop exact zeros
+  size_t w = 0;
+  for (size_t r = 0; r < ok.size(); ++r)
+    if (oa[r].x != 0.0 || oa[r].y != 0.0) {
+      ok[w] = ok[r];
+      oa[w] = oa[r];
+      ++w;
+    }
+  ok.resize(w);
+  oa.resize(w);
+  return QW_OK;
+}
+
+int measure_partials(qw_state* st, int kind, double* result, hipStream_t stream) {
+  const int grid = 256;
+  QW_HIP(qw::launch_measure(st->ctx->mat(), st->buf[st->cur], kind, st->mbuf, nullptr, grid, stream));
+  std::vector<double> h(grid);
+  QW_HIP(hipMemcpyAsync(h.data(), st->mbuf, sizeof(double) * grid, hipMemcpyDeviceToHost, stream));
+  QW_HIP(hipStreamSynchronize(stream));
+  double t = 0.0;
+  for (double v : h) t += v;
+  *result = t;
+  return QW_OK;
+}
+
+// ---- Chebyshev coefficients (Eq. "fx") --------------------------------------------
+// p_i = C(2 beta, beta+i)/4^beta from the central term by the ratio
+// p_{i+1} = p_i (beta - i)/(beta + i + 1) in long double; the central term is
+// the Wallis product for small beta and the Stirling series of
+// ln C(2n, n) - 2n ln 2 otherwise.  a_k = 4 (-1)^k sum_{i > k} p_i.
+void cks_coefficients(int64_t beta, int32_t j0, double* out) {
+  long double p0;
+  if (beta < 64) {
+    p0 = 1.0L;
+    for (int64_t i = 1; i <= beta; ++i) p0 *= (long double)(2 * i - 1) / (long double)(2 * i);
+  } else {
+    const long double x = (long double)beta;
+    const long double pi = 3.141592653589793238462643383279502884L;
+    const long double lp = -0.5L * std::log(pi * x) - 1.0L / (8.0L * x) + 1.0L / (192.0L * x * x * x) -
+                           1.0L / (640.0L * x * x * x * x * x) + 17.0L / (14336.0L * x * x * x * x * x * x * x);
+    p0 = std::exp(lp);
+  }
+  const int64_t sd = int64_t(std::sqrt((double)beta / 2.0)) + 1;
+  const int64_t imax = std::min<int64_t>(beta, int64_t(j0) + 64 + 40 * sd);
+  std::vector<long double> p(size_t(imax) + 2, 0.0L);
+  p[0] = p0;
+  for (int64_t i = 0; i < imax; ++i) p[i + 1] = p[i] * (long double)(beta - i) / (long double)(beta + i + 1);
+  std::vector<long double> suf(size_t(imax) + 2, 0.0L);
+  for (int64_t i = imax; i >= 0; --i) suf[i] = suf[i + 1] + p[i];
+  for (int32_t k = 0; k <= j0; ++k) {
+    const long double tail = (k + 1 <= imax) ? suf[k + 1] : 0.0L;
+    out[k] = double(((k & 1) ? -4.0L : 4.0L) * tail);
+  }
+}
+
+}  // namespace
+
+// ================================ C ABI ============================================
+extern "C" {
+
+const char* qw_last_error(void) { return g_err.c_str(); }
+
+int qw_load_csc(qw_ctx** out, int32_t n, const int32_t* colptr, const int32_t* rowidx, const double* vals,
+                int64_t nnz, double scale, uint32_t flags, const qw_allocator* alloc, void* stream) {
+  if (colptr && n > 0 && colptr[n] != nnz) return set_err(QW_EINVAL, "colptr[n] != nnz");
+  const int64_t zero = 0;
+  return load_impl(out, 1, &n, &zero, &zero, colptr, rowidx, vals, scale > 0.0 ? &scale : nullptr, flags, alloc,
+                   stream);
+}
+
+int qw_load_csc_batched(qw_ctx** out, int32_t ninst, const int32_t* n, const int64_t* colptr_off,
+                        const int64_t* nnz_off, const int32_t* colptr, const int32_t* rowidx, const double* vals,
+                        const double* scales, uint32_t flags, const qw_allocator* alloc, void* stream) {
+  if (!colptr_off || !nnz_off) return set_err(QW_EINVAL, "offset arrays are required");
+  return load_impl(out, ninst, n, colptr_off, nnz_off, colptr, rowidx, vals, scales, flags, alloc, stream);
+}
+
+int32_t qw_ctx_ninst(const qw_ctx* ctx) { return ctx ? ctx->ninst : 0; }
+
+int qw_ctx_info(const qw_ctx* ctx, int32_t inst, int32_t* n_padded, int32_t* s, int32_t* nbits, double* scale) {
+  if (!ctx || inst < 0 || inst >= ctx->ninst) return set_err(QW_EINVAL, "bad context or instance");
+  const HostInst& hi = ctx->inst[inst];
+  if (n_padded) *n_padded = hi.N;
+  if (s) *s = hi.s;
+  if (nbits) *nbits = ctx->nbits;
+  if (scale) *scale = hi.scale;
+  return QW_OK;
+}
+
+void qw_ctx_free(qw_ctx* ctx) {
+  if (!ctx) return;
+  (void)hipDeviceSynchronize();
+  ctx->alloc.put(ctx->col);
+  ctx->alloc.put(ctx->val);
+  ctx->alloc.put(ctx->dinst);
+  delete ctx;
+}
+
+int qw_state_init(qw_state** out, qw_ctx* ctx, const double* b_re, const double* b_im, uint32_t flags,
+                  int64_t capacity, void* stream_v) {
+  if (!out || !ctx || !b_re) return set_err(QW_EINVAL, "missing argument");
+  *out = nullptr;
+  hipStream_t stream = static_cast<hipStream_t>(stream_v);
+  // b in N-vector layout
+  std::vector<double2> hb(size_t(ctx->jtotal), make_double2(0.0, 0.0));
+  int64_t nzb = 0, src = 0;
+  for (int32_t i = 0; i < ctx->ninst; ++i) {
+    const HostInst& hi = ctx->inst[i];
+    for (int32_t j = 0; j < hi.n; ++j, ++src) {
+      const double2 v = make_double2(b_re[src], b_im ? b_im[src] : 0.0);
+      if (!std::isfinite(v.x) || !std::isfinite(v.y)) return set_err(QW_EINVAL, "non-finite b");
+      hb[size_t(hi.jbase + j)] = v;
+      nzb += (v.x != 0.0 || v.y != 0.0);
+    }
+  }
+  if (capacity == 0) capacity = 2 * (ctx->items + nzb) + 64;
+  qw_state* st;
+  int rc = state_alloc(ctx, capacity, &st, stream);
+  if (rc) return rc;
+  hipError_t e = hipMemcpyAsync(st->b, hb.data(), sizeof(double2) * ctx->jtotal, hipMemcpyHostToDevice, stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(stream);
+  if (e != hipSuccess) {
+    qw_state_free(st);
+    return set_err(QW_EDEVICE, std::string("b upload: ") + hipGetErrorString(e));
+  }
+  if (flags & QW_INIT_RAW) {
+    std::vector<uint64_t> keys;
+    std::vector<double2> amps;
+    const int n = ctx->nbits;
+    for (int32_t i = 0; i < ctx->ninst; ++i) {
+      const HostInst& hi = ctx->inst[i];
+      for (int32_t j = 0; j < hi.N; ++j) {
+        const double2 v = hb[size_t(hi.jbase + j)];
+        if (v.x == 0.0 && v.y == 0.0) continue;
+        keys.push_back((uint64_t(i) << (4 * n + 2)) | (uint64_t(j) << (2 * n + 2)));
+        amps.push_back(v);
+      }
+    }
+    rc = import_branches(st, keys, amps, stream);
+    if (rc) {
+      qw_state_free(st);
+      return rc;
+    }
+  } else {
+    e = qw::launch_init(ctx->mat(), st->b, st->buf[0], st->ctl, st->cap, 0, qw::kTau, stream);
+    if (e != hipSuccess) {
+      qw_state_free(st);
+      return set_err(QW_EDEVICE, std::string("init: ") + hipGetErrorString(e));
+    }
+    st->prepared = true;
+  }
+  *out = st;
+  return QW_OK;
+}
+
+void qw_state_free(qw_state* st) {
+  if (!st) return;
+  (void)hipDeviceSynchronize();
+  free_graphs(st);
+  for (void* p : st->owned) st->ctx->alloc.put(p);
+  delete st;
+}
+
+int qw_set_launch(qw_state* st, int32_t wg_size, int32_t grid_limit) {
+  if (!st) return set_err(QW_EINVAL, "state is NULL");
+  if (wg_size) {
+    if (wg_size < 64 || wg_size > 256 || wg_size % 64) return set_err(QW_EINVAL, "workgroup size must be 64..256, a multiple of 64");
+    st->block = wg_size;
+  }
+  if (grid_limit) {
+    if (grid_limit < 1 || grid_limit > 65536) return set_err(QW_EINVAL, "grid out of range");
+    st->grid = grid_limit;
+  }
+  free_graphs(st);
+  return QW_OK;
+}
+
+int qw_step(qw_state* st, int32_t nsteps, void* stream) {
+  if (!st || nsteps < 0) return set_err(QW_EINVAL, "bad state or step count");
+  int rc = run_steps(st, nsteps, static_cast<hipStream_t>(stream));
+  if (rc == QW_OK) st->steps_since_init += nsteps;
+  return rc;
+}
+
+int qw_step_adjoint(qw_state* st, int32_t nsteps, void* stream_v) {
+  if (!st || nsteps < 0) return set_err(QW_EINVAL, "bad state or step count");
+  if (nsteps == 0) return QW_OK;
+  hipStream_t stream = static_cast<hipStream_t>(stream_v);
+  // W^dagger = S W S: swap, walk, swap
+  int rc = launch_one(st, qw::kSwap, stream);
+  if (!rc) rc = run_steps(st, nsteps, stream);
+  if (!rc) rc = launch_one(st, qw::kSwap, stream);
+  if (rc == QW_OK) st->steps_since_init -= nsteps;
+  return rc;
+}
+
+int qw_sync(qw_state* st, void* stream) {
+  if (!st) return set_err(QW_EINVAL, "state is NULL");
+  return check_overflow(st, static_cast<hipStream_t>(stream));
+}
+
+int qw_measure(qw_state* st, int32_t kind, void* out, int64_t out_len, void* stream_v) {
+  if (!st || !out) return set_err(QW_EINVAL, "missing argument");
+  hipStream_t stream = static_cast<hipStream_t>(stream_v);
+  int rc = check_overflow(st, stream);
+  if (rc) return rc;
+  qw_ctx* ctx = st->ctx;
+  switch (kind) {
+    case QW_COUNT: {
+      if (out_len < 1) return set_err(QW_EINVAL, "out_len too small");
+      double c;
+      rc = measure_partials(st, 0, &c, stream);
+      if (!rc) static_cast<int64_t*>(out)[0] = int64_t(std::llround(c));
+      return rc;
+    }
+    case QW_NORM: {
+      if (out_len < 1) return set_err(QW_EINVAL, "out_len too small");
+      return measure_partials(st, 1, static_cast<double*>(out), stream);
+    }
+    case QW_J_MARGINAL:
+    case QW_PROJECT: {
+      const int64_t need = kind == QW_J_MARGINAL ? ctx->jtotal : 2 * ctx->jtotal;
+      if (out_len < need) return set_err(QW_EINVAL, "out_len too small");
+      QW_HIP(qw::launch_fill(st->mbuf, sizeof(double) * need + (need & 1 ? 8 : 0), stream));
+      QW_HIP(qw::launch_measure(ctx->mat(), st->buf[st->cur], kind == QW_J_MARGINAL ? 2 : 3, nullptr, st->mbuf, 256,
+                                stream));
+      QW_HIP(hipMemcpyAsync(out, st->mbuf, sizeof(double) * need, hipMemcpyDeviceToHost, stream));
+      QW_HIP(hipStreamSynchronize(stream));
+      return QW_OK;
+    }
+    case QW_STATS: {
+      if (out_len < 4) return set_err(QW_EINVAL, "out_len too small");
+      Ctl h;
+      QW_HIP(hipMemcpyAsync(&h, st->ctl, sizeof(Ctl), hipMemcpyDeviceToHost, stream));
+      QW_HIP(hipStreamSynchronize(stream));
+      int64_t* o = static_cast<int64_t*>(out);
+      o[0] = int64_t(h.steps);
+      o[1] = int64_t(h.last_written);
+      o[2] = int64_t(st->cap);
+      o[3] = int64_t(h.overflow);
+      return QW_OK;
+    }
+    default:
+      return set_err(QW_EINVAL, "unknown measurement kind");
+  }
+}
+
+int qw_export(qw_state* st, uint64_t* keys, double* re, double* im, int64_t cap, int64_t* m, void* stream_v) {
+  if (!st || !m) return set_err(QW_EINVAL, "missing argument");
+  hipStream_t stream = static_cast<hipStream_t>(stream_v);
+  int64_t count = 0;
+  int rc = qw_measure(st, QW_COUNT, &count, 1, stream_v);
+  if (rc) return rc;
+  *m = count;
+  if (cap < count) return set_err(QW_EINVAL, "output arrays too small: " + std::to_string(count) + " branches");
+  if (count == 0) return QW_OK;
+  qw_ctx* ctx = st->ctx;
+  void* dk = ctx->alloc.get(sizeof(uint64_t) * count);
+  void* da = ctx->alloc.get(sizeof(double2) * count);
+  void* dc = ctx->alloc.get(256);
+  if (!dk || !da || !dc) {
+    ctx->alloc.put(dk);
+    ctx->alloc.put(da);
+    ctx->alloc.put(dc);
+    return set_err(QW_ENOMEM, "device allocation failed for the export");
+  }
+  std::vector<uint64_t> hk(static_cast<size_t>(count));
+  std::vector<double2> ha(static_cast<size_t>(count));
+  uint32_t got = 0;
+  hipError_t e = qw::launch_fill(dc, 256, stream);
+  if (e == hipSuccess)
+    e = qw::launch_export(ctx->mat(), st->buf[st->cur], static_cast<uint64_t*>(dk), static_cast<double2*>(da),
+                          static_cast<uint32_t*>(dc), uint32_t(count), stream);
+  if (e == hipSuccess) e = hipMemcpyAsync(&got, dc, sizeof(uint32_t), hipMemcpyDeviceToHost, stream);
+  if (e == hipSuccess) e = hipMemcpyAsync(hk.data(), dk, sizeof(uint64_t) * count, hipMemcpyDeviceToHost, stream);
+  if (e == hipSuccess) e = hipMemcpyAsync(ha.data(), da, sizeof(double2) * count, hipMemcpyDeviceToHost, stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(stream);
+  ctx->alloc.put(dk);
+  ctx->alloc.put(da);
+  ctx->alloc.put(dc);
+  if (e != hipSuccess) return set_err(QW_EDEVICE, std::string("export: ") + hipGetErrorString(e));
+  if (int64_t(got) != count) return set_err(QW_EDEVICE, "export count mismatch");
+  std::vector<int64_t> idx(static_cast<size_t>(count));
+  std::iota(idx.begin(), idx.end(), 0);
+  std::sort(idx.begin(), idx.end(), [&](int64_t a, int64_t b) { return hk[a] < hk[b]; });
+  for (int64_t t = 0; t < count; ++t) {
+    keys[t] = hk[idx[t]];
+    if (re) re[t] = ha[idx[t]].x;
+    if (im) im[t] = ha[idx[t]].y;
+  }
+  return QW_OK;
+}
+
+int qw_state_import(qw_state* st, const uint64_t* keys, const double* re, const double* im, int64_t m,
+                    void* stream_v) {
+  if (!st || (m > 0 && (!keys || !re))) return set_err(QW_EINVAL, "missing argument");
+  hipStream_t stream = static_cast<hipStream_t>(stream_v);
+  std::vector<uint64_t> k;
+  std::vector<double2> a;
+  int rc = canonical_branches(st->ctx, keys, re, im, m, k, a);
+  if (rc) return rc;
+  rc = state_clear(st, stream);
+  if (rc) return rc;
+  st->prepared = false;
+  st->steps_since_init = 0;
+  return import_branches(st, k, a, stream);
+}
+
+int qw_cks_coeffs(int64_t beta, int32_t j0, double* out) {
+  if (beta < 1 || j0 < 0 || !out) return set_err(QW_EINVAL, "bad arguments");
+  cks_coefficients(beta, j0, out);
+  return QW_OK;
+}
+
+int qls_run(qw_ctx* ctx, const double* b, double kappa, double eps, int32_t j0_override, double* y_re,
+            double* y_im, double* p_succ, int64_t* walk_steps, void* stream_v) {
+  if (!ctx || !b) return set_err(QW_EINVAL, "missing argument");
+  if (!(kappa > 1.0) || !std::isfinite(kappa)) return set_err(QW_EINVAL, "kappa must be > 1");
+  if (!(eps > 0.0 && eps < 1.0)) return set_err(QW_EINVAL, "eps must lie in (0, 1)");
+  hipStream_t stream = static_cast<hipStream_t>(stream_v);
+  const double bb = std::ceil(kappa * kappa * std::log(kappa / eps));
+  const int64_t beta = int64_t(bb);
+  int32_t j0 = int32_t(std::ceil(std::sqrt(bb * std::log(4.0 * bb / eps))));
+  if (j0_override >= 0) j0 = j0_override;
+  std::vector<double> a(size_t(j0) + 1);
+  cks_coefficients(beta, j0, a.data());
+  const int64_t nsteps = 2 * int64_t(j0) + 1;
+  // coefficient per input step number m: a_{(m-1)/2} for odd m
+  std::vector<double> coefm(size_t(nsteps) + 1, 0.0);
+  for (int64_t m = 1; m <= nsteps; m += 2) coefm[size_t(m)] = a[size_t((m - 1) / 2)];
+  // the solver works on instance 0 only
+  std::vector<double> bfull(size_t(ctx->ntotal), 0.0);
+  for (int32_t j = 0; j < ctx->inst[0].n; ++j) bfull[size_t(j)] = b[j];
+  qw_state* st = nullptr;
+  int rc = qw_state_init(&st, ctx, bfull.data(), nullptr, 0, 0, stream_v);
+  if (rc) return rc;
+  const int64_t N = ctx->inst[0].N;
+  double* dcoef = static_cast<double*>(ctx->alloc.get(sizeof(double) * coefm.size()));
+  double2* y = static_cast<double2*>(ctx->alloc.get(sizeof(double2) * ctx->jtotal));
+  std::vector<double2> hy(static_cast<size_t>(ctx->jtotal));
+  std::vector<double> proj(2 * size_t(ctx->jtotal));
+  hipError_t e = (dcoef && y) ? hipSuccess : hipErrorOutOfMemory;
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(dcoef, coefm.data(), sizeof(double) * coefm.size(), hipMemcpyHostToDevice, stream);
+  if (e == hipSuccess) e = qw::launch_fill(y, sizeof(double2) * ctx->jtotal, stream);
+  if (e == hipSuccess) {
+    rc = run_steps(st, nsteps, stream, y, dcoef);
+    if (!rc) rc = check_overflow(st, stream);
+    if (!rc) rc = qw_measure(st, QW_PROJECT, proj.data(), int64_t(proj.size()), stream_v);
+    if (!rc) {
+      e = hipMemcpyAsync(hy.data(), y, sizeof(double2) * ctx->jtotal, hipMemcpyDeviceToHost, stream);
+      if (e == hipSuccess) e = hipStreamSynchronize(stream);
+    }
+  }
+  ctx->alloc.put(dcoef);
+  ctx->alloc.put(y);
+  qw_state_free(st);
+  if (e != hipSuccess) return set_err(e == hipErrorOutOfMemory ? QW_ENOMEM : QW_EDEVICE, "linear solver failed");
+  if (rc) return rc;
+  double norm2 = 0.0, asum = 0.0;
+  for (double v : a) asum += std::fabs(v);
+  for (int64_t j = 0; j < N; ++j) {
+    const double yr = hy[size_t(j)].x + a[size_t(j0)] * proj[2 * size_t(j)];
+    const double yi = hy[size_t(j)].y + a[size_t(j0)] * proj[2 * size_t(j) + 1];
+    if (y_re && j < ctx->inst[0].n) y_re[j] = yr;
+    if (y_im && j < ctx->inst[0].n) y_im[j] = yi;
+    norm2 += yr * yr + yi * yi;
+  }
+  if (p_succ) *p_succ = norm2 / (asum * asum);
+  if (walk_steps) *walk_steps = nsteps;
+  return QW_OK;
+}
+
+int qw_grad(qw_state* st, const double* w, int32_t nsteps, double* dvals, double* db_re, double* db_im,
+            double* loss, void* stream_v) {
+  if (!st || !w) return set_err(QW_EINVAL, "missing argument");
+  if (!st->prepared || st->steps_since_init != nsteps)
+    return set_err(QW_EINVAL, "qw_grad needs the state made by qw_state_init (T~ start) advanced by exactly nsteps");
+  hipStream_t stream = static_cast<hipStream_t>(stream_v);
+  int rc = check_overflow(st, stream);
+  if (rc) return rc;
+  qw_ctx* ctx = st->ctx;
+  // weights in N-vector layout
+  std::vector<double> hw(size_t(ctx->jtotal), 0.0);
+  int64_t src = 0;
+  for (int32_t i = 0; i < ctx->ninst; ++i)
+    for (int32_t j = 0; j < ctx->inst[i].n; ++j, ++src) hw[size_t(ctx->inst[i].jbase + j)] = w[src];
+  qw_state* lam = nullptr;
+  rc = state_alloc(ctx, st->cap, &lam, stream);
+  if (rc) return rc;
+  double* dw = static_cast<double*>(ctx->alloc.get(sizeof(double) * ctx->jtotal));
+  double* dv = static_cast<double*>(ctx->alloc.get(sizeof(double) * ctx->items));
+  double2* db = static_cast<double2*>(ctx->alloc.get(sizeof(double2) * ctx->jtotal));
+  std::vector<double> hdv(static_cast<size_t>(ctx->items));
+  std::vector<double2> hdb(static_cast<size_t>(ctx->jtotal));
+  std::vector<double> part(256);
+  hipError_t e = (dw && dv && db) ? hipSuccess : hipErrorOutOfMemory;
+  const qw::Matrix mm = ctx->mat();
+  if (e == hipSuccess) e = hipMemcpyAsync(dw, hw.data(), sizeof(double) * ctx->jtotal, hipMemcpyHostToDevice, stream);
+  if (e == hipSuccess) e = qw::launch_fill(dv, (sizeof(double) * ctx->items + 15) / 16 * 16, stream);
+  // Psi_n = S psi_n, Lambda_n = diag(w[k]) Psi_n
+  if (e == hipSuccess) {
+    rc = launch_one(st, qw::kSwap, stream);
+    if (!rc) e = qw::launch_weight(mm, st->buf[st->cur], lam->buf[0], lam->ctl, dw, lam->cap, st->mbuf, 256, stream);
+  }
+  if (e == hipSuccess && !rc) e = hipMemcpyAsync(part.data(), st->mbuf, sizeof(double) * 256, hipMemcpyDeviceToHost, stream);
+  for (int32_t t = nsteps; t >= 1 && e == hipSuccess && !rc; --t) {
+    qw::AdjArgs a;
+    a.m = mm;
+    a.in = st->buf[st->cur];
+    a.out = st->buf[st->cur ^ 1];
+    a.lin = lam->buf[lam->cur];
+    a.lout = lam->buf[lam->cur ^ 1];
+    a.ctl = st->ctl;
+    a.lctl = lam->ctl;
+    a.cap = st->cap;
+    a.tau = qw::kTau;
+    a.dv = dv;
+    e = qw::launch_adjoint(a, step_grid(st), st->block, stream);
+    st->cur ^= 1;
+    lam->cur ^= 1;
+  }
+  // back to the unconjugated frame: psi_0 and lambda_0
+  if (e == hipSuccess && !rc) rc = launch_one(st, qw::kSwap, stream);
+  if (e == hipSuccess && !rc) rc = launch_one(lam, qw::kSwap, stream);
+  if (e == hipSuccess && !rc) e = qw::launch_grad_init(mm, lam->buf[lam->cur], st->b, dv, db, stream);
+  if (e == hipSuccess && !rc) e = hipMemcpyAsync(hdv.data(), dv, sizeof(double) * ctx->items, hipMemcpyDeviceToHost, stream);
+  if (e == hipSuccess && !rc) e = hipMemcpyAsync(hdb.data(), db, sizeof(double2) * ctx->jtotal, hipMemcpyDeviceToHost, stream);
+  if (e == hipSuccess && !rc) e = hipStreamSynchronize(stream);
+  if (e == hipSuccess && !rc) rc = check_overflow(lam, stream);
+  if (e == hipSuccess && !rc) rc = check_overflow(st, stream);
+  ctx->alloc.put(dw);
+  ctx->alloc.put(dv);
+  ctx->alloc.put(db);
+  qw_state_free(lam);
+  st->steps_since_init = 0;
+  if (e != hipSuccess) return set_err(e == hipErrorOutOfMemory ? QW_ENOMEM : QW_EDEVICE,
+                                      std::string("gradient: ") + hipGetErrorString(e));
+  if (rc) return rc;
+  if (loss) {
+    double L = 0.0;
+    for (double v : part) L += v;
+    *loss = L;
+  }
+  if (dvals)
+    for (size_t p = 0; p < ctx->csc_slot.size(); ++p) dvals[p] = hdv[size_t(ctx->csc_slot[p])];
+  src = 0;
+  for (int32_t i = 0; i < ctx->ninst; ++i)
+    for (int32_t j = 0; j < ctx->inst[i].n; ++j, ++src) {
+      const double2 g = hdb[size_t(ctx->inst[i].jbase + j)];
+      if (db_re) db_re[src] = g.x;
+      if (db_im) db_im[src] = g.y;
+    }
+  return QW_OK;
+}
+
+}  // extern "C"

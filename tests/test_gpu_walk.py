@@ -1,0 +1,207 @@
+"""GPU parity of the walk (through the C ABI) against the CPU oracle.
+
+Keys must be bit-identical to the oracle's and every FP64 amplitude within
+1e-12 absolute, after up to 100 steps, at sizes that span many wavefronts and
+ragged tails, and at the full 16384-dimensional workload the benchmark times.
+"""
+import numpy as np
+import pytest
+
+import workloads as W
+from tests.parity import compare_states
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def Q():
+    import torch
+
+    assert torch.cuda.is_available()
+    import paper_2303_06890_amd as Q
+
+    return Q
+
+
+def _pair(Q, oracle_mod, csc, b, raw=False, scale=None):
+    walk = Q.Walk(csc, scale=scale)
+    st = walk.state(b, raw=raw)
+    om = oracle_mod.OracleMatrix(csc, scale=0.0 if scale is None else scale)
+    ost = oracle_mod.OracleState(om).set_b(b)
+    if not raw:
+        ost.T()
+    assert walk.info[0]["N"] == om.N and walk.info[0]["s"] == om.s
+    return walk, st, ost
+
+
+def _check(st, ost, where, atol=1e-12):
+    gk, ga = st.export()
+    ok, oa = ost.export()
+    return compare_states(gk, ga, ok, oa, atol=atol, where=where)
+
+
+def test_init_matches_oracle(Q, oracle_mod):
+    csc, b = W.tiny_tridiagonal()
+    walk, st, ost = _pair(Q, oracle_mod, csc, b)
+    _check(st, ost, "T~|b~>", atol=1e-15)
+    assert st.count() == ost.count()
+
+
+def test_tridiagonal_100_steps(Q, oracle_mod):
+    csc, b = W.tiny_tridiagonal()
+    walk, st, ost = _pair(Q, oracle_mod, csc, b)
+    for t in range(1, 11):
+        st.step(1)
+        ost.step(1)
+        _check(st, ost, f"step {t}")
+    st.step(90)
+    ost.step(90)
+    _check(st, ost, "step 100")
+    assert ost.ambiguous(total=True) == 0
+
+
+@pytest.mark.parametrize("n,c,seed", [(1024, 8, 4), (64, 5, 21), (200, 7, 5), (96, 3, 6)])
+def test_offset_matrices_100_steps(Q, oracle_mod, n, c, seed):
+    csc = W.offset_matrix(n, c, seed=seed)
+    b = W.gaussian_b(n, seed=seed + 1)
+    walk, st, ost = _pair(Q, oracle_mod, csc, b)
+    done = 0
+    for t in (1, 2, 3, 10, 37, 100):
+        st.step(t - done)
+        ost.step(t - done)
+        done = t
+        _check(st, ost, f"n={n} c={c} step {t}")
+
+
+def test_raw_start(Q, oracle_mod):
+    csc = W.offset_matrix(32, 6, seed=9)
+    b = W.gaussian_b(32, seed=10)
+    walk, st, ost = _pair(Q, oracle_mod, csc, b, raw=True)
+    _check(st, ost, "raw start", atol=0.0)
+    for t in range(1, 31):
+        st.step(1)
+        ost.step(1)
+        _check(st, ost, f"raw step {t}")
+
+
+def test_adjoint_steps(Q, oracle_mod):
+    csc = W.offset_matrix(128, 6, seed=11)
+    b = W.gaussian_b(128, seed=12)
+    walk, st, ost = _pair(Q, oracle_mod, csc, b)
+    st.step(7)
+    ost.step(7)
+    st.step_adjoint(3)
+    ost.step_adjoint(3)
+    _check(st, ost, "W^dagger 3")
+    k0, a0 = walk.state(b).export()
+    st.step_adjoint(4)
+    k1, a1 = st.export()
+    assert np.array_equal(k0, k1)
+    assert np.abs(a0 - a1).max() < 1e-13
+
+
+def test_measurements(Q, oracle_mod):
+    csc = W.offset_matrix(256, 8, seed=13)
+    b = W.gaussian_b(256, seed=14)
+    walk, st, ost = _pair(Q, oracle_mod, csc, b)
+    st.step(9)
+    ost.step(9)
+    assert st.count() == ost.count()
+    assert abs(st.norm2() - ost.norm2()) < 1e-13
+    assert abs(st.norm2() - 1.0) < 1e-13
+    assert np.abs(st.j_marginal() - ost.j_marginal()).max() < 1e-14
+    assert np.abs(st.project() - ost.project0()).max() < 1e-14
+    stats = st.stats()
+    assert stats["steps"] == 9 and stats["overflow"] == 0
+
+
+def test_checkpoint_resume(Q, oracle_mod):
+    csc = W.offset_matrix(256, 8, seed=15)
+    b = W.uniform_b(256)
+    walk, st, ost = _pair(Q, oracle_mod, csc, b)
+    st.step(5)
+    keys, amps = st.export()
+    st2 = walk.state(np.zeros(256))
+    st2.import_(keys, amps)
+    st.step(5)
+    st2.step(5)
+    k1, a1 = st.export()
+    k2, a2 = st2.export()
+    assert np.array_equal(k1, k2) and np.abs(a1 - a2).max() < 1e-15
+    ost.step(10)
+    _check(st2, ost, "resumed")
+
+
+def test_edge_shapes(Q, oracle_mod):
+    cases = [
+        (W.from_dense(np.diag(np.linspace(0.1, 0.9, 5))), 5),      # s = 1, ragged N
+        (W.from_dense(np.full((2, 2), 0.4)), 2),                    # N = 2
+        (W.offset_matrix(128, 64, seed=17), 128),                   # s = 64, one wave per group
+        (W.offset_matrix(40, 33, seed=18), 40),                     # s = 64 with 31 filler slots
+        (W.band_matrix(30, 3, seed=19), 30),                        # paper's band family, s = 8
+    ]
+    for csc, n in cases:
+        b = W.gaussian_b(n, seed=n)
+        walk, st, ost = _pair(Q, oracle_mod, csc, b)
+        _check(st, ost, f"n={n} init")
+        st.step(12)
+        ost.step(12)
+        _check(st, ost, f"n={n} step 12")
+
+
+def test_empty_state(Q):
+    csc = W.offset_matrix(64, 4, seed=1)
+    walk = Q.Walk(csc)
+    st = walk.state(np.zeros(64))
+    st.step(3)
+    assert st.count() == 0
+    k, a = st.export()
+    assert k.size == 0
+
+
+def test_capacity_overflow_reported(Q):
+    csc = W.offset_matrix(256, 8, seed=2)
+    walk = Q.Walk(csc)
+    st = walk.state(W.uniform_b(256), capacity=100)
+    st.step(2)
+    with pytest.raises(Q.QwError) as ei:
+        st.count()
+    assert ei.value.code == -3
+
+
+def test_paper_scale_5_steps(Q, oracle_mod):
+    """The benchmark's workload: G(16384, 8), uniform b, 5 steps, full parity."""
+    csc, b = W.paper_scale()
+    walk, st, ost = _pair(Q, oracle_mod, csc, b)
+    _check(st, ost, "16384 init")
+    for t in range(1, 6):
+        st.step(1)
+        ost.step(1)
+        _check(st, ost, f"16384 step {t}")
+    assert st.count() == ost.count() <= 4 * 16384 * 8
+
+
+def test_graph_replay_matches_direct(Q):
+    """Steps replayed from the captured graph equal direct launches bitwise."""
+    csc = W.offset_matrix(512, 8, seed=23)
+    b = W.gaussian_b(512, seed=24)
+    walk = Q.Walk(csc)
+    a = walk.state(b)
+    c = walk.state(b)
+    a.step(40)          # 2 graph replays of 16 + 8 direct
+    for _ in range(40):
+        c.step(1)       # direct only
+    ka, aa = a.export()
+    kc, ac = c.export()
+    assert np.array_equal(ka, kc) and np.array_equal(aa, ac)
+
+
+def test_deterministic(Q):
+    csc = W.offset_matrix(2048, 8, seed=25)
+    b = W.gaussian_b(2048, seed=26)
+    walk = Q.Walk(csc)
+    r = []
+    for _ in range(2):
+        st = walk.state(b).step(25)
+        r.append(st.export())
+    assert np.array_equal(r[0][0], r[1][0]) and np.array_equal(r[0][1], r[1][1])

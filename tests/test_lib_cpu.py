@@ -1,0 +1,122 @@
+"""CPU-side checks of the HIP library: it loads, exports every symbol its
+header declares, and rejects invalid matrices before touching the GPU."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+import workloads as W
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared_symbols():
+    text = open(os.path.join(ROOT, "include", "qw.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(q\w+)\s*\(", text)) - {"qw_allocator"})
+
+
+@pytest.fixture(scope="module")
+def lib():
+    from paper_2303_06890_amd import _lib
+
+    return _lib.load()
+
+
+def test_header_symbols_exported(lib):
+    from paper_2303_06890_amd import _lib
+
+    names = _declared_symbols()
+    assert len(names) >= 15
+    assert sorted(names) == sorted(_lib.SYMBOLS)
+    for name in names:
+        assert hasattr(lib, name), name
+
+
+def _load(lib, csc, scale=0.0, flags=1):
+    from paper_2303_06890_amd import _lib
+
+    h = ctypes.c_void_p()
+    cp = np.ascontiguousarray(csc.colptr, np.int32)
+    ri = np.ascontiguousarray(csc.rowidx, np.int32)
+    va = np.ascontiguousarray(csc.vals, np.float64)
+    rc = lib.qw_load_csc(ctypes.byref(h), csc.n, cp.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
+                         ri.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
+                         va.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), csc.nnz, scale, flags, None, None)
+    return rc, lib.qw_last_error().decode()
+
+
+def _mutate(csc, rowidx=None, vals=None):
+    return W.Csc(csc.n, csc.colptr, csc.rowidx if rowidx is None else rowidx,
+                 csc.vals if vals is None else vals)
+
+
+def test_rejects_unsorted_rows(lib):
+    csc = W.offset_matrix(16, 5, seed=1)
+    r = csc.rowidx.copy()
+    r[0], r[1] = r[1], r[0]
+    rc, msg = _load(lib, _mutate(csc, rowidx=r))
+    assert rc == -1 and "sorted" in msg
+
+
+def test_rejects_duplicate_rows(lib):
+    csc = W.offset_matrix(16, 5, seed=1)
+    r = csc.rowidx.copy()
+    r[1] = r[0]
+    rc, msg = _load(lib, _mutate(csc, rowidx=r))
+    assert rc == -1
+
+
+def test_rejects_negative_diagonal(lib):
+    a = np.diag([1.0, -0.5, 0.7, 0.2])
+    rc, msg = _load(lib, W.from_dense(a))
+    assert rc == -1 and "diagonal" in msg
+
+
+def test_rejects_value_above_one_after_scale(lib):
+    csc = W.tiny_tridiagonal()[0]
+    rc, msg = _load(lib, csc, scale=1.0)
+    assert rc == -1 and "|a| > 1" in msg
+
+
+def test_rejects_asymmetric(lib):
+    a = np.array([[0.5, 0.2, 0], [0.1, 0.5, 0], [0, 0, 0.5]])
+    rc, msg = _load(lib, W.from_dense(a))
+    assert rc == -1 and "symmetric" in msg
+
+
+def test_rejects_rows_longer_than_64(lib):
+    a = np.full((80, 80), 0.01)
+    rc, msg = _load(lib, W.from_dense(a))
+    assert rc == -5
+
+
+def test_rejects_row_index_out_of_range(lib):
+    csc = W.offset_matrix(16, 5, seed=2)
+    r = csc.rowidx.copy()
+    r[-1] = 99
+    rc, msg = _load(lib, _mutate(csc, rowidx=r))
+    assert rc == -1
+
+
+def test_cks_coeffs_host(lib):
+    """The library's coefficients (Stirling + ratio recurrence) agree with an
+    exact rational evaluation and with the binomial tail."""
+    from fractions import Fraction
+    from math import comb
+
+    from scipy.stats import binom
+
+    import paper_2303_06890_amd as Q
+
+    for beta, j0 in ((1, 0), (7, 4), (63, 20), (64, 20), (200, 50)):
+        got = Q.cks_coeffs(beta, j0)
+        ref = [float(4 * (-1) ** j * Fraction(sum(comb(2 * beta, beta + i) for i in range(j + 1, beta + 1)),
+                                               4 ** beta)) for j in range(j0 + 1)]
+        assert np.allclose(got, ref, rtol=1e-13, atol=0)
+    beta, j0 = 966624, 4620
+    got = Q.cks_coeffs(beta, j0)
+    ks = np.array([0, 3, 50, 700, 3000, 4620])
+    assert np.allclose(got[ks], 4 * (-1.0) ** ks * binom.sf(beta + ks, 2 * beta, 0.5), rtol=1e-9)
