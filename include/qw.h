@@ -77,8 +77,9 @@ typedef struct {
 #define QW_NORM 2       /* out: double[1]  sum |amp|^2 */
 #define QW_J_MARGINAL 3 /* out: double[sum N_i]  probability of each j value */
 #define QW_PROJECT 4    /* out: double[2 sum N_i] interleaved complex <psi~_j|state> */
-#define QW_STATS 5      /* out: int64[4] {steps done, branches written by the last
-                           step, capacity, overflow flag} */
+#define QW_STATS 5      /* out: int64[5] {step launches done, branches written by the
+                           last launch, capacity, overflow flag, branches written
+                           by all launches} */
 
 /* Load one matrix (Sec. V.B, preprocessing list; Sec. II.C, Fig. 1):
  *   scale: > 0 multiplies every value by `scale`; 0 selects 1/max(1, max|a|).
@@ -179,8 +180,10 @@ void qw_state_free(qw_state* st);
 void qw_ctx_free(qw_ctx* ctx);
 const char* qw_last_error(void);
 
-/* Kernel launch shape (work items per thread, workgroup size) of the step
- * kernel; 0 keeps the current value.  Used by the autotuner. */
+/* Launch shape of the step kernel: workgroup size (64..256, a multiple of
+ * 64) and number of workgroups (the kernel strides over its work); 0 keeps
+ * the current value (default: 256 and min(2048, work/256)).  Captured graphs
+ * are discarded.  Used by the autotuner. */
 int qw_set_launch(qw_state* st, int32_t wg_size, int32_t grid_limit);
 
 #ifdef __cplusplus

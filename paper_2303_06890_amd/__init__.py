@@ -8,14 +8,35 @@ hooks) and the current stream; every step of the walk runs in the library.
 """
 from __future__ import annotations
 
+import atexit
 import ctypes
+import weakref
 
 import numpy as np
+import torch  # noqa: F401  (imported before the atexit hook below is registered, so the hook runs first)
 
 from . import _lib
 from ._lib import QwError, check  # noqa: F401
 
 __all__ = ["Walk", "State", "QwError", "WalkObservable", "cks_coeffs", "schedule", "pack_key"]
+
+
+# Library objects still alive at interpreter exit are freed by an atexit hook,
+# while Python, torch and the HIP runtime are intact; freeing them later, from
+# finalisers, would call the torch allocator callback after teardown began.
+_live_states: "weakref.WeakSet" = weakref.WeakSet()
+_live_walks: "weakref.WeakSet" = weakref.WeakSet()
+_exiting = False
+
+
+@atexit.register
+def _release_all():
+    global _exiting
+    for w in list(_live_walks):
+        w.close()
+    for st in list(_live_states):
+        st.close()
+    _exiting = True
 
 
 def _torch():
@@ -96,6 +117,8 @@ class Walk:
                                       _ip(rowidx), _dp(vals), _dp(sc) if sc is not None else None, flags,
                                       ctypes.byref(self._alloc.struct) if self._alloc else None, _stream()))
         self._h = h
+        self._states = weakref.WeakSet()
+        _live_walks.add(self)
         self.info = []
         for i in range(self.ninst):
             N, s, nb = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
@@ -108,9 +131,11 @@ class Walk:
         self.nnz_total = int(vals.shape[0])
 
     def close(self):
-        if getattr(self, "_h", None):
+        for st in list(getattr(self, "_states", ())):
+            st.close()  # states use the context's allocator: free them first
+        if getattr(self, "_h", None) and not _exiting:
             _lib.load().qw_ctx_free(self._h)
-            self._h = None
+        self._h = None
 
     def __del__(self):
         try:
@@ -152,11 +177,13 @@ class State:
     def __init__(self, walk: Walk, h):
         self.walk = walk
         self._h = h
+        walk._states.add(self)
+        _live_states.add(self)
 
     def close(self):
-        if getattr(self, "_h", None):
+        if getattr(self, "_h", None) and not _exiting:
             _lib.load().qw_state_free(self._h)
-            self._h = None
+        self._h = None
 
     def __del__(self):
         try:
@@ -198,8 +225,9 @@ class State:
         return out[0::2] + 1j * out[1::2]
 
     def stats(self) -> dict:
-        o = self._measure(_lib.QW_STATS, np.zeros(4, np.int64))
-        return dict(steps=int(o[0]), last_written=int(o[1]), capacity=int(o[2]), overflow=int(o[3]))
+        o = self._measure(_lib.QW_STATS, np.zeros(5, np.int64))
+        return dict(steps=int(o[0]), last_written=int(o[1]), capacity=int(o[2]), overflow=int(o[3]),
+                    total_written=int(o[4]))
 
     def export(self):
         """(keys uint64 sorted, amplitudes complex128)."""

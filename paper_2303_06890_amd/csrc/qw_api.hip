@@ -730,7 +730,7 @@ int qw_measure(qw_state* st, int32_t kind, void* out, int64_t out_len, void* str
       return QW_OK;
     }
     case QW_STATS: {
-      if (out_len < 4) return set_err(QW_EINVAL, "out_len too small");
+      if (out_len < 5) return set_err(QW_EINVAL, "out_len too small");
       Ctl h;
       QW_HIP(hipMemcpyAsync(&h, st->ctl, sizeof(Ctl), hipMemcpyDeviceToHost, stream));
       QW_HIP(hipStreamSynchronize(stream));
@@ -739,6 +739,7 @@ int qw_measure(qw_state* st, int32_t kind, void* out, int64_t out_len, void* str
       o[1] = int64_t(h.last_written);
       o[2] = int64_t(st->cap);
       o[3] = int64_t(h.overflow);
+      o[4] = int64_t(h.total_written);
       return QW_OK;
     }
     default:

@@ -47,8 +47,9 @@ struct Ctl {
   unsigned long long written;       // branches kept by the current launch
   unsigned long long last_written;  // ... by the last completed launch
   unsigned long long steps;         // completed step launches
+  unsigned long long total_written; // branches kept, summed over all launches
   uint32_t stepno;                  // solver step counter (indexes the coefficient table)
-  uint32_t pad3[25];
+  uint32_t pad3[23];
 };
 
 struct Matrix {

@@ -208,7 +208,9 @@ __device__ __forceinline__ void finish_launch(Ctl* ctl, uint32_t* in_cnt, unsign
       __threadfence();
       *in_cnt = 0;
       ctl->done = 0;
-      ctl->last_written = atomicExch(&ctl->written, 0ull);
+      const unsigned long long w = atomicExch(&ctl->written, 0ull);
+      ctl->last_written = w;
+      ctl->total_written += w;
       ctl->steps += 1;
       ctl->stepno += 1;
       __threadfence();
