@@ -180,6 +180,12 @@ void qw_state_free(qw_state* st);
 void qw_ctx_free(qw_ctx* ctx);
 const char* qw_last_error(void);
 
+/* Release the library's kernels from the HIP runtime (they are loaded on
+ * first use, per device).  Call after every qw_state and qw_ctx has been
+ * freed, while the runtime is alive (e.g. at the start of process exit); a
+ * later call into the library loads them again. */
+void qw_shutdown(void);
+
 /* Launch shape of the step kernel: workgroup size (64..256, a multiple of
  * 64) and number of workgroups (the kernel strides over its work); 0 keeps
  * the current value (default: 256 and min(2048, work/256)).  Captured graphs

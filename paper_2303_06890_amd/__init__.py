@@ -21,9 +21,10 @@ from ._lib import QwError, check  # noqa: F401
 __all__ = ["Walk", "State", "QwError", "WalkObservable", "cks_coeffs", "schedule", "pack_key"]
 
 
-# Library objects still alive at interpreter exit are freed by an atexit hook,
-# while Python, torch and the HIP runtime are intact; freeing them later, from
-# finalisers, would call the torch allocator callback after teardown began.
+# At interpreter exit, library objects still alive are freed and the kernels
+# are released from the HIP runtime (qw_shutdown) by an atexit hook, while
+# Python, torch and the runtime are intact; nothing of the library is left
+# for the process's native teardown.
 _live_states: "weakref.WeakSet" = weakref.WeakSet()
 _live_walks: "weakref.WeakSet" = weakref.WeakSet()
 _exiting = False
@@ -36,6 +37,8 @@ def _release_all():
         w.close()
     for st in list(_live_states):
         st.close()
+    if _lib._lib is not None:
+        _lib._lib.qw_shutdown()
     _exiting = True
 
 

@@ -17,6 +17,7 @@ SYMBOLS = [
     "qw_load_csc", "qw_load_csc_batched", "qw_ctx_info", "qw_ctx_ninst", "qw_state_init", "qw_step",
     "qw_step_adjoint", "qw_measure", "qw_export", "qw_state_import", "qw_sync", "qls_run",
     "qw_cks_coeffs", "qw_grad", "qw_state_free", "qw_ctx_free", "qw_last_error", "qw_set_launch",
+    "qw_shutdown",
 ]
 
 ALLOC_T = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p)
@@ -73,6 +74,7 @@ def load() -> ctypes.CDLL:
         "qw_ctx_free": (None, [P]),
         "qw_last_error": (ctypes.c_char_p, []),
         "qw_set_launch": (c_int, [P, i32, i32]),
+        "qw_shutdown": (None, []),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)

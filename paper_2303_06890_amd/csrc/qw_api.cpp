@@ -19,11 +19,18 @@ using qw::Ctl;
 
 namespace {
 
-thread_local std::string g_err;
+// Last error text of the calling thread (trivially destructible, so the
+// library registers nothing to run at thread or process exit).
+thread_local char g_err[1024];
 
 int set_err(int code, const std::string& msg) {
-  g_err = msg;
+  std::snprintf(g_err, sizeof(g_err), "%s", msg.c_str());
   return code;
+}
+
+void prefix_err(const std::string& prefix) {
+  const std::string m = prefix + g_err;
+  std::snprintf(g_err, sizeof(g_err), "%s", m.c_str());
 }
 
 #define QW_HIP(call)                                                                              \
@@ -328,7 +335,7 @@ int load_impl(qw_ctx** out, int32_t ninst, const int32_t* n, const int64_t* colp
     std::vector<int64_t> slot_of;
     int rc = preprocess(n[i], colptr + co, rowidx + zo, vals + zo, scales ? scales[i] : 0.0, flags, hi, ell, slot_of);
     if (rc) {
-      g_err = "instance " + std::to_string(i) + ": " + g_err;
+      prefix_err("instance " + std::to_string(i) + ": ");
       delete ctx;
       return rc;
     }
@@ -559,7 +566,7 @@ void cks_coefficients(int64_t beta, int32_t j0, double* out) {
 // ================================ C ABI ============================================
 extern "C" {
 
-const char* qw_last_error(void) { return g_err.c_str(); }
+const char* qw_last_error(void) { return g_err; }
 
 int qw_load_csc(qw_ctx** out, int32_t n, const int32_t* colptr, const int32_t* rowidx, const double* vals,
                 int64_t nnz, double scale, uint32_t flags, const qw_allocator* alloc, void* stream) {

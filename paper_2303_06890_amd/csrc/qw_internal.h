@@ -3,6 +3,7 @@
 #pragma once
 
 #include <hip/hip_runtime.h>
+#include <stddef.h>
 #include <stdint.h>
 
 namespace qw {
@@ -86,7 +87,15 @@ struct AdjArgs {
   double* dv;     // gradient per ELL slot, accumulated
 };
 
-// Launchers (qw_kernels.hip).  All enqueue on `stream` and allocate nothing.
+// The host side is compiled by the host compiler and the kernels by the GPU
+// compiler; the argument structures must have one layout on both.
+static_assert(sizeof(Inst) == 40 && offsetof(Inst, inv_sqrt_s) == 32, "Inst layout");
+static_assert(sizeof(Buf) == 40 && offsetof(Buf, cap) == 32, "Buf layout");
+static_assert(sizeof(Matrix) == 40 && offsetof(Matrix, items) == 32, "Matrix layout");
+static_assert(sizeof(StepArgs) == 160 && offsetof(StepArgs, coefm) == 152, "StepArgs layout");
+static_assert(sizeof(AdjArgs) == 240 && offsetof(AdjArgs, dv) == 232, "AdjArgs layout");
+
+// Launchers (qw_launch.cpp).  All enqueue on `stream` and allocate nothing.
 hipError_t launch_step(const StepArgs& a, int grid, int block, hipStream_t stream);
 hipError_t launch_adjoint(const AdjArgs& a, int grid, int block, hipStream_t stream);
 hipError_t launch_init(const Matrix& m, const double2* b, Buf out, Ctl* ctl, uint32_t cap, int32_t raw,

@@ -221,7 +221,7 @@ __device__ __forceinline__ void finish_launch(Ctl* ctl, uint32_t* in_cnt, unsign
 // ----------------------------------------------------------------- walk step
 
 template <bool ACC>
-__global__ void __launch_bounds__(256) step_kernel(StepArgs a) {
+__device__ __forceinline__ void step_body(StepArgs a) {
   const int lane = threadIdx.x & (kWave - 1);
   const int n = a.m.nbits;
   const int64_t A = a.m.items;
@@ -318,13 +318,13 @@ __global__ void __launch_bounds__(256) step_kernel(StepArgs a) {
   finish_launch(a.ctl, a.in.cnt, kept, overflow);
 }
 
-hipError_t launch_step(const StepArgs& a, int grid, int block, hipStream_t stream) {
-  if (a.yacc)
-    hipLaunchKernelGGL(step_kernel<true>, dim3(grid), dim3(block), 0, stream, a);
-  else
-    hipLaunchKernelGGL(step_kernel<false>, dim3(grid), dim3(block), 0, stream, a);
-  return hipGetLastError();
-}
+}  // namespace qw
+
+extern "C" __global__ void __launch_bounds__(256) qwk_step(qw::StepArgs a) { qw::step_body<false>(a); }
+extern "C" __global__ void __launch_bounds__(256) qwk_step_acc(qw::StepArgs a) { qw::step_body<true>(a); }
+
+namespace qw {
+
 
 // ----------------------------------------------------------------- adjoint sweep step
 // One reverse step of the gradient: both the recomputed state Psi_t and the
@@ -336,7 +336,7 @@ hipError_t launch_step(const StepArgs& a, int grid, int block, hipStream_t strea
 // group sums, and psi' = (2/s) c phi - chi the forward state before the
 // reflection of step t.
 
-__global__ void __launch_bounds__(256) adjoint_kernel(AdjArgs a) {
+extern "C" __global__ void __launch_bounds__(256) qwk_adjoint(AdjArgs a) {
   const int lane = threadIdx.x & (kWave - 1);
   const int n = a.m.nbits;
   const int64_t A = a.m.items;
@@ -454,16 +454,12 @@ __global__ void __launch_bounds__(256) adjoint_kernel(AdjArgs a) {
   finish_launch(a.ctl, a.in.cnt, kept, overflow);
 }
 
-hipError_t launch_adjoint(const AdjArgs& a, int grid, int block, hipStream_t stream) {
-  hipLaunchKernelGGL(adjoint_kernel, dim3(grid), dim3(block), 0, stream, a);
-  return hipGetLastError();
-}
 
 // ----------------------------------------------------------------- T~ |b~>
 // T~ on |0, j, 0, 0, 0, 0> gives the group of j with amplitudes b_j phi_j:
 // slot (j, l) receives b_j f/sqrt(s) and b_j g/sqrt(s) (Alg. 5).
 
-__global__ void __launch_bounds__(256) init_kernel(Matrix m, const double2* __restrict__ b, Buf out, double tau) {
+extern "C" __global__ void __launch_bounds__(256) qwk_init(Matrix m, const double2* __restrict__ b, Buf out, double tau) {
   const int64_t stride = int64_t(gridDim.x) * blockDim.x;
   for (int64_t it = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; it < m.items; it += stride) {
     const int ii = find_inst(m, it);
@@ -482,30 +478,15 @@ __global__ void __launch_bounds__(256) init_kernel(Matrix m, const double2* __re
   }
 }
 
-hipError_t launch_init(const Matrix& m, const double2* b, Buf out, Ctl*, uint32_t, int32_t, double tau,
-                       hipStream_t stream) {
-  const int64_t blocks = (m.items + 255) / 256;
-  const int grid = int(blocks < 4096 ? blocks : 4096);
-  hipLaunchKernelGGL(init_kernel, dim3(grid), dim3(256), 0, stream, m, b, out, tau);
-  return hipGetLastError();
-}
 
 // ----------------------------------------------------------------- fill (zero)
 
-__global__ void fill_kernel(uint4* p, int64_t n16) {
+extern "C" __global__ void qwk_fill(uint4* p, int64_t n16) {
   const int64_t stride = int64_t(gridDim.x) * blockDim.x;
   for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n16; i += stride)
     p[i] = make_uint4(0u, 0u, 0u, 0u);
 }
 
-hipError_t launch_fill(void* p, int64_t bytes, hipStream_t stream) {
-  const int64_t n16 = bytes / 16;  // callers pass multiples of 16 bytes
-  if (n16 <= 0) return hipSuccess;
-  const int64_t blocks = (n16 + 255) / 256;
-  const int grid = int(blocks < 4096 ? blocks : 4096);
-  hipLaunchKernelGGL(fill_kernel, dim3(grid), dim3(256), 0, stream, static_cast<uint4*>(p), n16);
-  return hipGetLastError();
-}
 
 // ----------------------------------------------------------------- measurements
 
@@ -523,7 +504,7 @@ __device__ __forceinline__ double block_sum(double v, double* sh) {
 
 // kind 0: count, 1: norm^2 -> partial[block]; kind 2: j marginal (R part
 // stored, list part added atomically); kind 3: projection.
-__global__ void __launch_bounds__(256) measure_kernel(Matrix m, Buf b, int32_t kind, double* partial, double* out) {
+extern "C" __global__ void __launch_bounds__(256) qwk_measure(Matrix m, Buf b, int32_t kind, double* partial, double* out) {
   __shared__ double sh[16];
   const int lane = threadIdx.x & (kWave - 1);
   const int n = m.nbits;
@@ -579,7 +560,7 @@ __global__ void __launch_bounds__(256) measure_kernel(Matrix m, Buf b, int32_t k
 }
 
 // list part of the j marginal
-__global__ void __launch_bounds__(256) marginal_list_kernel(Matrix m, Buf b, double* out) {
+extern "C" __global__ void __launch_bounds__(256) qwk_marginal_list(Matrix m, Buf b, double* out) {
   const int n = m.nbits;
   const uint64_t nm = (uint64_t(1) << n) - 1;
   const uint32_t B = min(*b.cnt, b.cap);
@@ -594,16 +575,10 @@ __global__ void __launch_bounds__(256) marginal_list_kernel(Matrix m, Buf b, dou
   }
 }
 
-hipError_t launch_measure(const Matrix& m, Buf b, int32_t kind, double* partial, double* out, int grid,
-                          hipStream_t stream) {
-  hipLaunchKernelGGL(measure_kernel, dim3(grid), dim3(256), 0, stream, m, b, kind, partial, out);
-  if (kind == 2) hipLaunchKernelGGL(marginal_list_kernel, dim3(grid), dim3(256), 0, stream, m, b, out);
-  return hipGetLastError();
-}
 
 // ----------------------------------------------------------------- export / import
 
-__global__ void __launch_bounds__(256) export_kernel(Matrix m, Buf b, uint64_t* keys, double2* amps, uint32_t* count,
+extern "C" __global__ void __launch_bounds__(256) qwk_export(Matrix m, Buf b, uint64_t* keys, double2* amps, uint32_t* count,
                                                      uint32_t cap) {
   const int lane = threadIdx.x & (kWave - 1);
   const int n = m.nbits;
@@ -647,14 +622,9 @@ __global__ void __launch_bounds__(256) export_kernel(Matrix m, Buf b, uint64_t* 
   }
 }
 
-hipError_t launch_export(const Matrix& m, Buf b, uint64_t* keys, double2* amps, uint32_t* count, uint32_t cap,
-                         hipStream_t stream) {
-  hipLaunchKernelGGL(export_kernel, dim3(1024), dim3(256), 0, stream, m, b, keys, amps, count, cap);
-  return hipGetLastError();
-}
 
 // Place branches (unique keys, validated on the host) at their homes.
-__global__ void __launch_bounds__(256) import_kernel(Matrix m, const uint64_t* keys, const double2* amps, int64_t cnt,
+extern "C" __global__ void __launch_bounds__(256) qwk_import(Matrix m, const uint64_t* keys, const double2* amps, int64_t cnt,
                                                      Buf out, Ctl* ctl, uint32_t cap) {
   bool overflow = false;
   const int64_t stride = int64_t(gridDim.x) * blockDim.x;
@@ -678,20 +648,13 @@ __global__ void __launch_bounds__(256) import_kernel(Matrix m, const uint64_t* k
   if (__ballot(overflow) != 0 && (threadIdx.x & 63) == 0) atomicOr(&ctl->overflow, 1u);
 }
 
-hipError_t launch_import(const Matrix& m, const uint64_t* keys, const double2* amps, int64_t n, Buf out, Ctl* ctl,
-                         uint32_t cap, hipStream_t stream) {
-  const int64_t blocks = (n + 255) / 256;
-  const int grid = int(blocks < 2048 ? (blocks > 0 ? blocks : 1) : 2048);
-  hipLaunchKernelGGL(import_kernel, dim3(grid), dim3(256), 0, stream, m, keys, amps, n, out, ctl, cap);
-  return hipGetLastError();
-}
 
 // ----------------------------------------------------------------- gradient set-up and finish
 
 // Lambda = diag(w[k register]) Psi for a state kept S-conjugated (the j
 // register of the true state is the k register of the stored one), and the
 // loss sum_branches w |amp|^2 as per-block partials.
-__global__ void __launch_bounds__(256) weight_kernel(Matrix m, Buf in, Buf out, const double* w, uint32_t cap,
+extern "C" __global__ void __launch_bounds__(256) qwk_weight(Matrix m, Buf in, Buf out, const double* w, uint32_t cap,
                                                      double* partial) {
   __shared__ double sh[16];
   const int lane = threadIdx.x & (kWave - 1);
@@ -736,16 +699,11 @@ __global__ void __launch_bounds__(256) weight_kernel(Matrix m, Buf in, Buf out, 
   if (threadIdx.x == 0) partial[blockIdx.x] = t;
 }
 
-hipError_t launch_weight(const Matrix& m, Buf in, Buf out, Ctl*, const double* w, uint32_t cap, double* partial,
-                         int grid, hipStream_t stream) {
-  hipLaunchKernelGGL(weight_kernel, dim3(grid), dim3(256), 0, stream, m, in, out, w, cap, partial);
-  return hipGetLastError();
-}
 
 // Gradient through the initial T~: psi_0 holds b_j phi_j in the group of j,
 // so dL/dv_{jl} += 2 Re[b_j (conj(nu_0) f' + conj(nu_1) g')] / sqrt(s) with
 // nu the slot amplitudes of lambda_0, and dL/db_j = 2 <psi~_j|lambda_0>.
-__global__ void __launch_bounds__(256) grad_init_kernel(Matrix m, Buf lam, const double2* b, double* dv, double2* db) {
+extern "C" __global__ void __launch_bounds__(256) qwk_grad_init(Matrix m, Buf lam, const double2* b, double* dv, double2* db) {
   const int lane = threadIdx.x & (kWave - 1);
   const int64_t stride = int64_t(gridDim.x) * blockDim.x;
   for (int64_t it = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; it < m.items; it += stride) {
@@ -776,12 +734,5 @@ __global__ void __launch_bounds__(256) grad_init_kernel(Matrix m, Buf lam, const
   }
 }
 
-hipError_t launch_grad_init(const Matrix& m, Buf lam, const double2* b, double* dv, double2* db,
-                            hipStream_t stream) {
-  const int64_t blocks = (m.items + 255) / 256;
-  const int grid = int(blocks < 4096 ? blocks : 4096);
-  hipLaunchKernelGGL(grad_init_kernel, dim3(grid), dim3(256), 0, stream, m, lam, b, dv, db);
-  return hipGetLastError();
-}
 
 }  // namespace qw

@@ -1,0 +1,179 @@
+// Host launchers of libqw's kernels.
+//
+// The kernels are compiled into a separate gfx950 code object that is
+// embedded in libqw.so (qw_code_object, generated at build time) and loaded
+// into the HIP runtime explicitly, once per device, on first use
+// (hipModuleLoadData); qw_shutdown() unloads it.  The library therefore holds
+// no compiler-generated static registration of device code: what it puts into
+// the runtime is created and released by explicit calls, independent of the
+// order in which a process tears down its runtime(s) at exit.
+#include <hip/hip_runtime.h>
+
+#include <mutex>
+
+#include "../../include/qw.h"
+#include "qw_internal.h"
+
+extern "C" const unsigned char qw_code_object[];
+extern "C" const size_t qw_code_object_size;
+
+namespace qw {
+namespace {
+
+enum Fn {
+  F_STEP,
+  F_STEP_ACC,
+  F_ADJOINT,
+  F_INIT,
+  F_FILL,
+  F_MEASURE,
+  F_MARGINAL_LIST,
+  F_EXPORT,
+  F_IMPORT,
+  F_WEIGHT,
+  F_GRAD_INIT,
+  F_COUNT
+};
+
+const char* const kNames[F_COUNT] = {"qwk_step",   "qwk_step_acc", "qwk_adjoint", "qwk_init",
+                                     "qwk_fill",   "qwk_measure",  "qwk_marginal_list", "qwk_export",
+                                     "qwk_import", "qwk_weight",   "qwk_grad_init"};
+
+constexpr int kMaxDevices = 64;
+
+struct DeviceModule {
+  hipModule_t mod;
+  hipFunction_t fn[F_COUNT];
+  bool loaded;
+};
+
+DeviceModule g_dev[kMaxDevices];  // trivially destructible: nothing runs at exit
+std::mutex g_mu;
+
+hipError_t function(Fn f, hipFunction_t* out) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(g_mu);
+  DeviceModule& d = g_dev[dev];
+  if (!d.loaded) {
+    hipModule_t mod;
+    e = hipModuleLoadData(&mod, qw_code_object);
+    if (e != hipSuccess) return e;
+    for (int i = 0; i < F_COUNT; ++i) {
+      e = hipModuleGetFunction(&d.fn[i], mod, kNames[i]);
+      if (e != hipSuccess) {
+        (void)hipModuleUnload(mod);
+        return e;
+      }
+    }
+    d.mod = mod;
+    d.loaded = true;
+  }
+  *out = d.fn[f];
+  return hipSuccess;
+}
+
+hipError_t launch(Fn f, int grid, int block, hipStream_t stream, void** params) {
+  hipFunction_t fn;
+  hipError_t e = function(f, &fn);
+  if (e != hipSuccess) return e;
+  return hipModuleLaunchKernel(fn, unsigned(grid), 1, 1, unsigned(block), 1, 1, 0, stream, params, nullptr);
+}
+
+int clamp_grid(int64_t work, int64_t limit) {
+  int64_t g = (work + 255) / 256;
+  if (g < 1) g = 1;
+  if (g > limit) g = limit;
+  return int(g);
+}
+
+}  // namespace
+
+hipError_t launch_step(const StepArgs& a, int grid, int block, hipStream_t stream) {
+  StepArgs c = a;
+  void* p[] = {&c};
+  return launch(a.yacc ? F_STEP_ACC : F_STEP, grid, block, stream, p);
+}
+
+hipError_t launch_adjoint(const AdjArgs& a, int grid, int block, hipStream_t stream) {
+  AdjArgs c = a;
+  void* p[] = {&c};
+  return launch(F_ADJOINT, grid, block, stream, p);
+}
+
+hipError_t launch_init(const Matrix& m, const double2* b, Buf out, Ctl*, uint32_t, int32_t, double tau,
+                       hipStream_t stream) {
+  Matrix mm = m;
+  const double2* bb = b;
+  double t = tau;
+  void* p[] = {&mm, &bb, &out, &t};
+  return launch(F_INIT, clamp_grid(m.items, 4096), 256, stream, p);
+}
+
+hipError_t launch_fill(void* ptr, int64_t bytes, hipStream_t stream) {
+  int64_t n16 = bytes / 16;  // callers pass multiples of 16 bytes
+  if (n16 <= 0) return hipSuccess;
+  uint4* q = static_cast<uint4*>(ptr);
+  void* p[] = {&q, &n16};
+  return launch(F_FILL, clamp_grid(n16, 4096), 256, stream, p);
+}
+
+hipError_t launch_measure(const Matrix& m, Buf b, int32_t kind, double* partial, double* out, int grid,
+                          hipStream_t stream) {
+  Matrix mm = m;
+  int32_t k = kind;
+  void* p[] = {&mm, &b, &k, &partial, &out};
+  hipError_t e = launch(F_MEASURE, grid, 256, stream, p);
+  if (e != hipSuccess || kind != 2) return e;
+  void* q[] = {&mm, &b, &out};
+  return launch(F_MARGINAL_LIST, grid, 256, stream, q);
+}
+
+hipError_t launch_export(const Matrix& m, Buf b, uint64_t* keys, double2* amps, uint32_t* count, uint32_t cap,
+                         hipStream_t stream) {
+  Matrix mm = m;
+  void* p[] = {&mm, &b, &keys, &amps, &count, &cap};
+  return launch(F_EXPORT, 1024, 256, stream, p);
+}
+
+hipError_t launch_import(const Matrix& m, const uint64_t* keys, const double2* amps, int64_t n, Buf out, Ctl* ctl,
+                         uint32_t cap, hipStream_t stream) {
+  Matrix mm = m;
+  const uint64_t* k = keys;
+  const double2* a = amps;
+  int64_t cnt = n;
+  void* p[] = {&mm, &k, &a, &cnt, &out, &ctl, &cap};
+  return launch(F_IMPORT, clamp_grid(n, 2048), 256, stream, p);
+}
+
+hipError_t launch_weight(const Matrix& m, Buf in, Buf out, Ctl*, const double* w, uint32_t cap, double* partial,
+                         int grid, hipStream_t stream) {
+  Matrix mm = m;
+  const double* ww = w;
+  void* p[] = {&mm, &in, &out, &ww, &cap, &partial};
+  return launch(F_WEIGHT, grid, 256, stream, p);
+}
+
+hipError_t launch_grad_init(const Matrix& m, Buf lam, const double2* b, double* dv, double2* db,
+                            hipStream_t stream) {
+  Matrix mm = m;
+  const double2* bb = b;
+  void* p[] = {&mm, &lam, &bb, &dv, &db};
+  return launch(F_GRAD_INIT, clamp_grid(m.items, 4096), 256, stream, p);
+}
+
+}  // namespace qw
+
+extern "C" void qw_shutdown(void) {
+  std::lock_guard<std::mutex> lock(qw::g_mu);
+  int cur = 0;
+  const bool have_dev = hipGetDevice(&cur) == hipSuccess;
+  for (int d = 0; d < qw::kMaxDevices; ++d) {
+    if (!qw::g_dev[d].loaded) continue;
+    if (hipSetDevice(d) == hipSuccess) (void)hipModuleUnload(qw::g_dev[d].mod);
+    qw::g_dev[d].loaded = false;
+  }
+  if (have_dev) (void)hipSetDevice(cur);
+}
