@@ -176,7 +176,11 @@ int qw_cks_coeffs(int64_t beta, int32_t j0, double* out);
 int qw_grad(qw_state* st, const double* w, int32_t nsteps, double* dvals, double* db_re, double* db_im,
             double* loss, void* stream);
 
+/* Free a state (waits for the device).  NULL is ignored. */
 void qw_state_free(qw_state* st);
+/* Release the caller's reference to a context.  Each state holds its own
+ * reference, so a context and its states may be freed in any order; the
+ * device arrays go when the last reference does.  NULL is ignored. */
 void qw_ctx_free(qw_ctx* ctx);
 const char* qw_last_error(void);
 

@@ -33,10 +33,10 @@ _exiting = False
 @atexit.register
 def _release_all():
     global _exiting
-    for w in list(_live_walks):
-        w.close()
     for st in list(_live_states):
         st.close()
+    for w in list(_live_walks):
+        w.close()
     if _lib._lib is not None:
         _lib._lib.qw_shutdown()
     _exiting = True
@@ -120,7 +120,6 @@ class Walk:
                                       _ip(rowidx), _dp(vals), _dp(sc) if sc is not None else None, flags,
                                       ctypes.byref(self._alloc.struct) if self._alloc else None, _stream()))
         self._h = h
-        self._states = weakref.WeakSet()
         _live_walks.add(self)
         self.info = []
         for i in range(self.ninst):
@@ -134,8 +133,8 @@ class Walk:
         self.nnz_total = int(vals.shape[0])
 
     def close(self):
-        for st in list(getattr(self, "_states", ())):
-            st.close()  # states use the context's allocator: free them first
+        """Release this handle; states made from the walk stay valid (each
+        holds its own reference to the library context)."""
         if getattr(self, "_h", None) and not _exiting:
             _lib.load().qw_ctx_free(self._h)
         self._h = None
@@ -180,7 +179,6 @@ class State:
     def __init__(self, walk: Walk, h):
         self.walk = walk
         self._h = h
-        walk._states.add(self)
         _live_states.add(self)
 
     def close(self):

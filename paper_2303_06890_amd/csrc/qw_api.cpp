@@ -7,6 +7,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -74,6 +75,10 @@ struct HostInst {
 }  // namespace
 
 struct qw_ctx {
+  // one reference for the caller (dropped by qw_ctx_free) plus one per live
+  // state made from this context: the context outlives its states whatever
+  // order the caller frees them in
+  std::atomic<int> refs{1};
   Alloc alloc;
   int32_t ninst = 0;
   int32_t nbits = 0;  // key register width
@@ -399,12 +404,23 @@ int load_impl(qw_ctx** out, int32_t ninst, const int32_t* n, const int64_t* colp
   return QW_OK;
 }
 
+// Drop one reference; the last one frees the context's device arrays.
+void ctx_release(qw_ctx* ctx) {
+  if (ctx->refs.fetch_sub(1) != 1) return;
+  (void)hipDeviceSynchronize();
+  ctx->alloc.put(ctx->col);
+  ctx->alloc.put(ctx->val);
+  ctx->alloc.put(ctx->dinst);
+  delete ctx;
+}
+
 // ---- states ---------------------------------------------------------------------
 
 int state_alloc(qw_ctx* ctx, int64_t capacity, qw_state** out, hipStream_t stream) {
   if (capacity <= 0 || capacity > int64_t(0xFFFFFFF0u)) return set_err(QW_EINVAL, "capacity out of range");
   qw_state* st = new qw_state;
   st->ctx = ctx;
+  ctx->refs.fetch_add(1);
   st->cap = uint32_t(capacity);
   auto get = [&](size_t bytes) {
     void* p = ctx->alloc.get(bytes);
@@ -596,12 +612,7 @@ int qw_ctx_info(const qw_ctx* ctx, int32_t inst, int32_t* n_padded, int32_t* s, 
 }
 
 void qw_ctx_free(qw_ctx* ctx) {
-  if (!ctx) return;
-  (void)hipDeviceSynchronize();
-  ctx->alloc.put(ctx->col);
-  ctx->alloc.put(ctx->val);
-  ctx->alloc.put(ctx->dinst);
-  delete ctx;
+  if (ctx) ctx_release(ctx);
 }
 
 int qw_state_init(qw_state** out, qw_ctx* ctx, const double* b_re, const double* b_im, uint32_t flags,
@@ -665,8 +676,10 @@ void qw_state_free(qw_state* st) {
   if (!st) return;
   (void)hipDeviceSynchronize();
   free_graphs(st);
-  for (void* p : st->owned) st->ctx->alloc.put(p);
+  qw_ctx* ctx = st->ctx;
+  for (void* p : st->owned) ctx->alloc.put(p);
   delete st;
+  ctx_release(ctx);
 }
 
 int qw_set_launch(qw_state* st, int32_t wg_size, int32_t grid_limit) {

@@ -205,3 +205,29 @@ def test_deterministic(Q):
         st = walk.state(b).step(25)
         r.append(st.export())
     assert np.array_equal(r[0][0], r[1][0]) and np.array_equal(r[0][1], r[1][1])
+
+
+def test_free_order_and_cycles(Q):
+    """Regression: a state must stay valid when its context handle is
+    released first, including when both are reclaimed by cycle collection
+    (which clears weak references before running finalisers)."""
+    import gc
+
+    csc = W.offset_matrix(256, 8, seed=27)
+    b = W.uniform_b(256)
+    walk = Q.Walk(csc)
+    st = walk.state(b)
+    walk.close()
+    st.step(3)
+    k, a = st.export()
+    assert k.size > 0 and abs(np.vdot(a, a).real - 1.0) < 1e-13
+    st.close()
+    for _ in range(3):
+        w2 = Q.Walk(csc)
+        s2 = w2.state(b).step(2)
+        holder = {"walk": w2, "state": s2}
+        holder["self"] = holder  # reference cycle holding both objects
+        s2.cycle = holder
+        del w2, s2, holder
+    gc.collect()
+    gc.collect()
