@@ -97,15 +97,14 @@ def main():
     ev0 = torch.cuda.Event(enable_timing=True)
     ev1 = torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
-    ev0.record()
+    ev0.record(Q.stream())  # the stream the step kernels are launched on
     st.step(args.steps)
-    ev1.record()
+    ev1.record(Q.stream())
     torch.cuda.synchronize()
     ms = ev0.elapsed_time(ev1)
     s1 = st.stats()
-    st.sync()
     out_total = s1["total_written"] - s0["total_written"]
-    in_total = out_total - s1["last_written"] + m_in0
+    in_total = out_total - s1["branches"] + m_in0
     alg_bytes = 24.0 * (in_total + out_total) + 12.0 * N * s * args.steps
     launch_s = ms / 1e3 / args.steps
     achieved = alg_bytes / args.steps / launch_s / 1e9
@@ -128,7 +127,7 @@ def main():
             "N": N,
             "nnz_per_col": 8,
             "s": s,
-            "branches": s1["last_written"],
+            "branches": s1["branches"],
             "graph_steps_per_replay": 16,
         },
         "roofline": {

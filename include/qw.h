@@ -50,7 +50,7 @@ typedef enum {
   QW_OK = 0,
   QW_EINVAL = -1,    /* invalid argument or matrix */
   QW_ENOMEM = -2,    /* allocation failed */
-  QW_ECAPACITY = -3, /* state list capacity exceeded (state is invalid) */
+  QW_ECAPACITY = -3, /* general branch list capacity exceeded */
   QW_EDEVICE = -4,   /* HIP runtime error */
   QW_ENOTSUP = -5    /* valid request outside what this build supports */
 } qw_status;
@@ -77,9 +77,9 @@ typedef struct {
 #define QW_NORM 2       /* out: double[1]  sum |amp|^2 */
 #define QW_J_MARGINAL 3 /* out: double[sum N_i]  probability of each j value */
 #define QW_PROJECT 4    /* out: double[2 sum N_i] interleaved complex <psi~_j|state> */
-#define QW_STATS 5      /* out: int64[5] {step launches done, branches written by the
-                           last launch, capacity, overflow flag, branches written
-                           by all launches} */
+#define QW_STATS 5      /* out: int64[5] {step launches so far (walk steps and
+                           swaps), current branch count, general-list capacity,
+                           general-list count, branches written by all launches} */
 
 /* Load one matrix (Sec. V.B, preprocessing list; Sec. II.C, Fig. 1):
  *   scale: > 0 multiplies every value by `scale`; 0 selects 1/max(1, max|a|).
@@ -114,16 +114,19 @@ int32_t qw_ctx_ninst(const qw_ctx* ctx);
 /* Create a state holding T~ |b~> (Alg. 5 applied to |b~> = sum_j b_j |0,j,0,0,0,0>,
  * Sec. IV) or |b~> itself with QW_INIT_RAW.  b_re/b_im (b_im may be NULL):
  * sum_i n[i] values, instance after instance; b is used as given (callers
- * normalise).  capacity: maximum number of branches the sparse branch list
- * may hold; 0 selects 2 * sum N_i s_i + 2 * (nonzeros of b), which holds every
- * state reachable from T~|b~> (they lie in the span of the reflection slots
- * and their image under O_s'^-1 S O_s').  Errors: QW_EINVAL, QW_ENOMEM. */
+ * normalise).  Every branch reachable from T~|b~> has a fixed address (the
+ * group members (0,j,0,0,k_{j,l},b2) of every QRAM slot and their swaps), so
+ * such a state needs no capacity and can never overflow; branches outside
+ * that span (raw starts, imports) go to a general list whose size the walk
+ * never changes.  capacity: initial general-list capacity (0 = as needed).
+ * Errors: QW_EINVAL, QW_ENOMEM. */
 int qw_state_init(qw_state** out, qw_ctx* ctx, const double* b_re, const double* b_im, uint32_t flags,
                   int64_t capacity, void* stream);
 
 /* Apply W^nsteps (Alg. 6: W = S T~ P T~^dagger), branches with |Re| and |Im|
- * both <= tau (1e-13) removed after every step.  Asynchronous; the step loop
- * is replayed from a captured HIP graph when `stream` is not NULL. */
+ * both <= tau (1e-13) removed after every step.  One kernel launch per step;
+ * asynchronous; the step loop is replayed from a captured HIP graph (16 steps
+ * per graph) when `stream` is not NULL.  Allocates nothing. */
 int qw_step(qw_state* st, int32_t nsteps, void* stream);
 
 /* Apply (W^dagger)^nsteps, W^dagger = T~ P T~^dagger S (unitarity of W). */
@@ -144,7 +147,7 @@ int qw_export(qw_state* st, uint64_t* keys, double* re, double* im, int64_t cap,
 int qw_state_import(qw_state* st, const uint64_t* keys, const double* re, const double* im, int64_t m,
                     void* stream);
 
-/* Wait for the stream and report a device-side error of the state. */
+/* Wait for the stream. */
 int qw_sync(qw_state* st, void* stream);
 
 /* Walk-based CKS linear solver on instance 0 (Sec. IV, CKS paragraph; Eq. "fx";

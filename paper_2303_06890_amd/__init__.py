@@ -18,7 +18,7 @@ import torch  # noqa: F401  (imported before the atexit hook below is registered
 from . import _lib
 from ._lib import QwError, check  # noqa: F401
 
-__all__ = ["Walk", "State", "QwError", "WalkObservable", "cks_coeffs", "schedule", "pack_key"]
+__all__ = ["Walk", "State", "QwError", "WalkObservable", "cks_coeffs", "schedule", "pack_key", "stream"]
 
 
 # At interpreter exit, library objects still alive are freed and the kernels
@@ -48,9 +48,23 @@ def _torch():
     return torch
 
 
-def _stream():
+_streams = {}
+
+
+def stream():
+    """The torch stream every library call of this binding runs on (one per
+    device, default priority).  Work on it is ordered; record timing events
+    on it.  A non-null stream lets the library replay step loops from
+    captured HIP graphs."""
     torch = _torch()
-    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+    dev = torch.cuda.current_device()
+    if dev not in _streams:
+        _streams[dev] = torch.cuda.Stream(device=dev)
+    return _streams[dev]
+
+
+def _stream():
+    return ctypes.c_void_p(stream().cuda_stream)
 
 
 class _TorchAllocator:
@@ -227,7 +241,7 @@ class State:
 
     def stats(self) -> dict:
         o = self._measure(_lib.QW_STATS, np.zeros(5, np.int64))
-        return dict(steps=int(o[0]), last_written=int(o[1]), capacity=int(o[2]), overflow=int(o[3]),
+        return dict(launches=int(o[0]), branches=int(o[1]), list_capacity=int(o[2]), list_count=int(o[3]),
                     total_written=int(o[4]))
 
     def export(self):

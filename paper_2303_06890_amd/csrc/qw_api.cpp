@@ -15,8 +15,8 @@
 #include <string>
 #include <vector>
 
-using qw::Buf;
-using qw::Ctl;
+using qw::List;
+using qw::Slots;
 
 namespace {
 
@@ -34,9 +34,9 @@ void prefix_err(const std::string& prefix) {
   std::snprintf(g_err, sizeof(g_err), "%s", m.c_str());
 }
 
-#define QW_HIP(call)                                                                              \
-  do {                                                                                            \
-    hipError_t e_ = (call);                                                                       \
+#define QW_HIP(call)                                                                                  \
+  do {                                                                                                \
+    hipError_t e_ = (call);                                                                           \
     if (e_ != hipSuccess) return set_err(QW_EDEVICE, std::string(#call ": ") + hipGetErrorString(e_)); \
   } while (0)
 
@@ -90,11 +90,13 @@ struct qw_ctx {
   std::vector<int64_t> csc_slot;  // ELL slot of every CSC entry
   int32_t* col = nullptr;
   double* val = nullptr;
+  int32_t* rev = nullptr;
   qw::Inst* dinst = nullptr;
   qw::Matrix mat() const {
     qw::Matrix m;
     m.col = col;
     m.val = val;
+    m.rev = rev;
     m.inst = dinst;
     m.ninst = ninst;
     m.nbits = nbits;
@@ -116,14 +118,16 @@ struct GraphEntry {
 
 struct qw_state {
   qw_ctx* ctx = nullptr;
-  Buf buf[2]{};
-  Ctl* ctl = nullptr;
-  uint32_t cap = 0;
-  int cur = 0;
+  Slots buf[2]{};           // amplitudes with a static home, two parities
+  int cur = 0;              // parity holding the state
+  List L{};                 // branches without a static home (count on the host)
+  unsigned long long* acc = nullptr;  // per-workgroup counts of branches written
+  uint32_t* stepno = nullptr;         // per-workgroup solver step counters
   double2* b = nullptr;     // device copy of b (N-vector layout)
-  double* mbuf = nullptr;   // measurement scratch: max(4096, 2*jtotal) doubles
+  double* mbuf = nullptr;   // measurement scratch: max(kMaxGrid, 2*jtotal) doubles
   bool prepared = false;    // created by T~ |b~>
   int64_t steps_since_init = 0;
+  int64_t launches = 0;     // step launches (walk steps and swaps)
   int block = 256;
   int grid = 0;             // 0 = automatic
   std::vector<GraphEntry> graphs;
@@ -132,8 +136,7 @@ struct qw_state {
 
 namespace {
 
-constexpr int kGraphSteps = 16;  // steps per captured graph (even: buffer parity is preserved)
-constexpr int kMaxGrid = 4096;
+constexpr int kGraphSteps = 16;  // steps per captured graph (even: the parity is preserved)
 
 void free_graphs(qw_state* st) {
   for (auto& g : st->graphs) (void)hipGraphExecDestroy(g.exec);
@@ -142,9 +145,8 @@ void free_graphs(qw_state* st) {
 
 int step_grid(const qw_state* st) {
   if (st->grid > 0) return st->grid;
-  const int64_t work = 2 * st->ctx->items;  // slots + a list of similar size
-  int64_t g = (work + st->block - 1) / st->block;
-  g = std::max<int64_t>(64, std::min<int64_t>(g, 2048));
+  int64_t g = (st->ctx->items + st->block - 1) / st->block;
+  g = std::max<int64_t>(1, std::min<int64_t>(g, 2048));
   return int(g);
 }
 
@@ -153,9 +155,11 @@ qw::StepArgs step_args(qw_state* st, int mode, double2* yacc, const double* coef
   a.m = st->ctx->mat();
   a.in = st->buf[st->cur];
   a.out = st->buf[st->cur ^ 1];
-  a.ctl = st->ctl;
-  a.cap = st->cap;
+  a.L = st->L;
+  a.acc = st->acc;
+  a.stepno = st->stepno;
   a.mode = mode;
+  a.pad_ = 0;
   a.tau = qw::kTau;
   a.yacc = yacc;
   a.coefm = coefm;
@@ -166,11 +170,12 @@ int launch_one(qw_state* st, int mode, hipStream_t stream, double2* yacc = nullp
   qw::StepArgs a = step_args(st, mode, yacc, coefm);
   QW_HIP(qw::launch_step(a, step_grid(st), st->block, stream));
   st->cur ^= 1;
+  ++st->launches;
   return QW_OK;
 }
 
-// Run `n` plain steps (or solver steps with accumulation), replaying a
-// captured graph of kGraphSteps steps when a stream is given.
+// Run `n` walk steps (with the solver's fused projection when yacc is set),
+// replaying a captured graph of kGraphSteps launches when a stream is given.
 int run_steps(qw_state* st, int64_t n, hipStream_t stream, double2* yacc = nullptr, const double* coefm = nullptr) {
   if (stream != nullptr && n >= kGraphSteps) {
     GraphEntry* ge = nullptr;
@@ -202,6 +207,7 @@ int run_steps(qw_state* st, int64_t n, hipStream_t stream, double2* yacc = nullp
     }
     const int64_t reps = n / kGraphSteps;
     for (int64_t r = 0; r < reps; ++r) QW_HIP(hipGraphLaunch(exec, stream));
+    st->launches += reps * kGraphSteps;
     if (yacc != nullptr) {
       QW_HIP(hipStreamSynchronize(stream));
       (void)hipGraphExecDestroy(exec);
@@ -212,16 +218,6 @@ int run_steps(qw_state* st, int64_t n, hipStream_t stream, double2* yacc = nullp
     int rc = launch_one(st, qw::kStep, stream, yacc, coefm);
     if (rc) return rc;
   }
-  return QW_OK;
-}
-
-int check_overflow(qw_state* st, hipStream_t stream) {
-  Ctl h;
-  QW_HIP(hipMemcpyAsync(&h, st->ctl, sizeof(Ctl), hipMemcpyDeviceToHost, stream));
-  QW_HIP(hipStreamSynchronize(stream));
-  if (h.overflow)
-    return set_err(QW_ECAPACITY, "state branch list overflowed its capacity of " + std::to_string(st->cap) +
-                                     " entries; the state is invalid (create it with a larger capacity)");
   return QW_OK;
 }
 
@@ -312,6 +308,21 @@ int preprocess(int32_t n, const int32_t* colptr, const int32_t* rowidx, const do
 
 int load_impl(qw_ctx** out, int32_t ninst, const int32_t* n, const int64_t* colptr_off, const int64_t* nnz_off,
               const int32_t* colptr, const int32_t* rowidx, const double* vals, const double* scales, uint32_t flags,
+              const qw_allocator* alloc, void* stream_v);
+
+// Drop one reference; the last one frees the context's device arrays.
+void ctx_release(qw_ctx* ctx) {
+  if (ctx->refs.fetch_sub(1) != 1) return;
+  (void)hipDeviceSynchronize();
+  ctx->alloc.put(ctx->col);
+  ctx->alloc.put(ctx->val);
+  ctx->alloc.put(ctx->rev);
+  ctx->alloc.put(ctx->dinst);
+  delete ctx;
+}
+
+int load_impl(qw_ctx** out, int32_t ninst, const int32_t* n, const int64_t* colptr_off, const int64_t* nnz_off,
+              const int32_t* colptr, const int32_t* rowidx, const double* vals, const double* scales, uint32_t flags,
               const qw_allocator* alloc, void* stream_v) {
   if (!out) return set_err(QW_EINVAL, "out is NULL");
   *out = nullptr;
@@ -385,9 +396,10 @@ int load_impl(qw_ctx** out, int32_t ninst, const int32_t* n, const int64_t* colp
   }
   ctx->col = static_cast<int32_t*>(ctx->alloc.get(sizeof(int32_t) * items));
   ctx->val = static_cast<double*>(ctx->alloc.get(sizeof(double) * items));
+  ctx->rev = static_cast<int32_t*>(ctx->alloc.get(sizeof(int32_t) * items));
   ctx->dinst = static_cast<qw::Inst*>(ctx->alloc.get(sizeof(qw::Inst) * ninst));
-  if (!ctx->col || !ctx->val || !ctx->dinst) {
-    qw_ctx_free(ctx);
+  if (!ctx->col || !ctx->val || !ctx->rev || !ctx->dinst) {
+    ctx_release(ctx);
     return set_err(QW_ENOMEM, "device allocation failed for the matrix");
   }
   hipError_t e = hipMemcpyAsync(ctx->col, hcol.data(), sizeof(int32_t) * items, hipMemcpyHostToDevice, stream);
@@ -395,60 +407,68 @@ int load_impl(qw_ctx** out, int32_t ninst, const int32_t* n, const int64_t* colp
     e = hipMemcpyAsync(ctx->val, hval.data(), sizeof(double) * items, hipMemcpyHostToDevice, stream);
   if (e == hipSuccess)
     e = hipMemcpyAsync(ctx->dinst, dinst.data(), sizeof(qw::Inst) * ninst, hipMemcpyHostToDevice, stream);
+  // O_s'^-1 of every reflected output: the QBS of j in row col[q], once per matrix
+  if (e == hipSuccess) e = qw::launch_qbs_table(ctx->mat(), ctx->rev, stream);
   if (e == hipSuccess) e = hipStreamSynchronize(stream);  // host vectors go out of scope
   if (e != hipSuccess) {
-    qw_ctx_free(ctx);
+    ctx_release(ctx);
     return set_err(QW_EDEVICE, std::string("matrix upload: ") + hipGetErrorString(e));
   }
   *out = ctx;
   return QW_OK;
 }
 
-// Drop one reference; the last one frees the context's device arrays.
-void ctx_release(qw_ctx* ctx) {
-  if (ctx->refs.fetch_sub(1) != 1) return;
-  (void)hipDeviceSynchronize();
-  ctx->alloc.put(ctx->col);
-  ctx->alloc.put(ctx->val);
-  ctx->alloc.put(ctx->dinst);
-  delete ctx;
-}
-
 // ---- states ---------------------------------------------------------------------
 
-int state_alloc(qw_ctx* ctx, int64_t capacity, qw_state** out, hipStream_t stream) {
-  if (capacity <= 0 || capacity > int64_t(0xFFFFFFF0u)) return set_err(QW_EINVAL, "capacity out of range");
+void* state_get(qw_state* st, size_t bytes) {
+  void* p = st->ctx->alloc.get(bytes);
+  if (p) st->owned.push_back(p);
+  return p;
+}
+
+// Allocate the general list for `cap` branches (previous contents dropped).
+int list_alloc(qw_state* st, uint32_t cap) {
+  st->L.cnt = 0;
+  if (cap <= st->L.cap) return QW_OK;
+  st->L.key = static_cast<uint64_t*>(state_get(st, sizeof(uint64_t) * cap));
+  st->L.amp = static_cast<double2*>(state_get(st, sizeof(double2) * cap));
+  if (!st->L.key || !st->L.amp) {
+    st->L.cap = 0;
+    return set_err(QW_ENOMEM, "device allocation failed for the branch list");
+  }
+  st->L.cap = cap;
+  return QW_OK;
+}
+
+int state_alloc(qw_ctx* ctx, int64_t list_cap, qw_state** out, hipStream_t stream) {
+  if (list_cap < 0 || list_cap > int64_t(0xFFFFFFF0u)) return set_err(QW_EINVAL, "capacity out of range");
   qw_state* st = new qw_state;
   st->ctx = ctx;
   ctx->refs.fetch_add(1);
-  st->cap = uint32_t(capacity);
-  auto get = [&](size_t bytes) {
-    void* p = ctx->alloc.get(bytes);
-    if (p) st->owned.push_back(p);
-    return p;
-  };
+  const size_t sb = sizeof(double2) * 2 * ctx->items;
   bool ok = true;
   for (int k = 0; k < 2; ++k) {
-    st->buf[k].R = static_cast<double2*>(get(sizeof(double2) * 2 * ctx->items));
-    st->buf[k].key = static_cast<uint64_t*>(get(sizeof(uint64_t) * st->cap));
-    st->buf[k].amp = static_cast<double2*>(get(sizeof(double2) * st->cap));
-    ok = ok && st->buf[k].R && st->buf[k].key && st->buf[k].amp;
+    st->buf[k].R = static_cast<double2*>(state_get(st, sb));
+    st->buf[k].Q = static_cast<double2*>(state_get(st, sb));
+    ok = ok && st->buf[k].R && st->buf[k].Q;
   }
-  st->ctl = static_cast<Ctl*>(get(sizeof(Ctl)));
-  st->b = static_cast<double2*>(get(sizeof(double2) * ctx->jtotal));
-  st->mbuf = static_cast<double*>(get(sizeof(double) * std::max<int64_t>(kMaxGrid, 2 * ctx->jtotal)));
-  ok = ok && st->ctl && st->b && st->mbuf;
+  st->acc = static_cast<unsigned long long*>(state_get(st, sizeof(unsigned long long) * qw::kMaxGrid));
+  st->stepno = static_cast<uint32_t*>(state_get(st, sizeof(uint32_t) * qw::kMaxGrid));
+  st->b = static_cast<double2*>(state_get(st, sizeof(double2) * ctx->jtotal));
+  st->mbuf = static_cast<double*>(state_get(st, sizeof(double) * std::max<int64_t>(qw::kMaxGrid, 2 * ctx->jtotal + 2)));
+  ok = ok && st->acc && st->stepno && st->b && st->mbuf;
+  if (ok && list_cap > 0) ok = list_alloc(st, uint32_t(list_cap)) == QW_OK;
   if (!ok) {
     qw_state_free(st);
     return set_err(QW_ENOMEM, "device allocation failed for the state");
   }
-  st->buf[0].cnt = &st->ctl->cnt[0];
-  st->buf[1].cnt = &st->ctl->cnt[1];
-  st->buf[0].cap = st->cap;
-  st->buf[1].cap = st->cap;
-  hipError_t e = qw::launch_fill(st->buf[0].R, sizeof(double2) * 2 * ctx->items, stream);
-  if (e == hipSuccess) e = qw::launch_fill(st->buf[1].R, sizeof(double2) * 2 * ctx->items, stream);
-  if (e == hipSuccess) e = qw::launch_fill(st->ctl, sizeof(Ctl), stream);
+  hipError_t e = hipSuccess;
+  for (int k = 0; k < 2 && e == hipSuccess; ++k) {
+    e = qw::launch_fill(st->buf[k].R, sb, stream);
+    if (e == hipSuccess) e = qw::launch_fill(st->buf[k].Q, sb, stream);
+  }
+  if (e == hipSuccess) e = qw::launch_fill(st->acc, sizeof(unsigned long long) * qw::kMaxGrid, stream);
+  if (e == hipSuccess) e = qw::launch_fill(st->stepno, sizeof(uint32_t) * qw::kMaxGrid, stream);
   if (e == hipSuccess) e = qw::launch_fill(st->b, sizeof(double2) * ctx->jtotal, stream);
   if (e != hipSuccess) {
     qw_state_free(st);
@@ -458,53 +478,61 @@ int state_alloc(qw_ctx* ctx, int64_t capacity, qw_state** out, hipStream_t strea
   return QW_OK;
 }
 
-// Reset a state to empty (both R buffers and the control block cleared).
+// Empty the state: both parities cleared, list emptied.
 int state_clear(qw_state* st, hipStream_t stream) {
-  const int64_t rb = sizeof(double2) * 2 * st->ctx->items;
-  QW_HIP(qw::launch_fill(st->buf[0].R, rb, stream));
-  QW_HIP(qw::launch_fill(st->buf[1].R, rb, stream));
-  QW_HIP(qw::launch_fill(st->ctl, sizeof(Ctl), stream));
+  const int64_t sb = sizeof(double2) * 2 * st->ctx->items;
+  for (int k = 0; k < 2; ++k) {
+    QW_HIP(qw::launch_fill(st->buf[k].R, sb, stream));
+    QW_HIP(qw::launch_fill(st->buf[k].Q, sb, stream));
+  }
   st->cur = 0;
+  st->L.cnt = 0;
   return QW_OK;
 }
 
-// Import unique, validated branches into buffer `cur`.
+// Place unique, validated branches (the state must be empty).
 int import_branches(qw_state* st, const std::vector<uint64_t>& keys, const std::vector<double2>& amps,
                     hipStream_t stream) {
   const int64_t m = int64_t(keys.size());
   if (m == 0) return QW_OK;
   qw_ctx* ctx = st->ctx;
+  int rc = list_alloc(st, uint32_t(m));
+  if (rc) return rc;
   void* dk = ctx->alloc.get(sizeof(uint64_t) * m);
   void* da = ctx->alloc.get(sizeof(double2) * m);
-  if (!dk || !da) {
-    ctx->alloc.put(dk);
-    ctx->alloc.put(da);
-    return set_err(QW_ENOMEM, "device allocation failed for the import");
-  }
-  hipError_t e = hipMemcpyAsync(dk, keys.data(), sizeof(uint64_t) * m, hipMemcpyHostToDevice, stream);
+  void* dc = ctx->alloc.get(256);
+  uint32_t lcnt = 0;
+  hipError_t e = (dk && da && dc) ? hipSuccess : hipErrorOutOfMemory;
+  if (e == hipSuccess) e = hipMemcpyAsync(dk, keys.data(), sizeof(uint64_t) * m, hipMemcpyHostToDevice, stream);
   if (e == hipSuccess) e = hipMemcpyAsync(da, amps.data(), sizeof(double2) * m, hipMemcpyHostToDevice, stream);
+  if (e == hipSuccess) e = qw::launch_fill(dc, 256, stream);
   if (e == hipSuccess)
     e = qw::launch_import(ctx->mat(), static_cast<uint64_t*>(dk), static_cast<double2*>(da), m, st->buf[st->cur],
-                          st->ctl, st->cap, stream);
+                          st->L, static_cast<uint32_t*>(dc), stream);
+  if (e == hipSuccess) e = hipMemcpyAsync(&lcnt, dc, sizeof(uint32_t), hipMemcpyDeviceToHost, stream);
   if (e == hipSuccess) e = hipStreamSynchronize(stream);
   ctx->alloc.put(dk);
   ctx->alloc.put(da);
-  if (e != hipSuccess) return set_err(QW_EDEVICE, std::string("import: ") + hipGetErrorString(e));
-  return check_overflow(st, stream);
+  ctx->alloc.put(dc);
+  if (e != hipSuccess)
+    return set_err(e == hipErrorOutOfMemory ? QW_ENOMEM : QW_EDEVICE, std::string("import: ") + hipGetErrorString(e));
+  if (lcnt > st->L.cap) return set_err(QW_ECAPACITY, "branch list overflow during import");
+  st->L.cnt = lcnt;
+  return QW_OK;
 }
 
-// Validate keys against the context's layout; merge equal keys.
+// Validate keys against the context's layout; merge equal keys; drop zeros.
 int canonical_branches(const qw_ctx* ctx, const uint64_t* keys, const double* re, const double* im, int64_t m,
                        std::vector<uint64_t>& ok, std::vector<double2>& oa) {
   const int n = ctx->nbits;
   const uint64_t nm = (uint64_t(1) << n) - 1;
-  std::vector<int64_t> idx(m);
+  std::vector<int64_t> idx(static_cast<size_t>(m));
   std::iota(idx.begin(), idx.end(), 0);
   std::sort(idx.begin(), idx.end(), [&](int64_t a, int64_t b) { return keys[a] < keys[b]; });
   ok.clear();
   oa.clear();
   for (int64_t t = 0; t < m; ++t) {
-    const int64_t i = idx[t];
+    const int64_t i = idx[size_t(t)];
     const uint64_t key = keys[i];
     const uint64_t inst = key >> (4 * n + 2);
     if (inst >= uint64_t(ctx->ninst)) return set_err(QW_EINVAL, "key with an instance index out of range");
@@ -514,6 +542,7 @@ int canonical_branches(const qw_ctx* ctx, const uint64_t* keys, const double* re
     if (k >= uint64_t(hi.N) || j >= uint64_t(hi.N) || kc >= uint64_t(hi.s) || jc >= uint64_t(hi.s))
       return set_err(QW_EINVAL, "key with a register value out of range (j,k < N and j_c,k_c < s required)");
     const double2 a = make_double2(re ? re[i] : 0.0, im ? im[i] : 0.0);
+    if (!std::isfinite(a.x) || !std::isfinite(a.y)) return set_err(QW_EINVAL, "non-finite amplitude");
     if (!ok.empty() && ok.back() == key) {
       oa.back().x += a.x;
       oa.back().y += a.y;
@@ -522,7 +551,6 @@ int canonical_branches(const qw_ctx* ctx, const uint64_t* keys, const double* re
       oa.push_back(a);
     }
   }
-  // drop exact zeros
   size_t w = 0;
   for (size_t r = 0; r < ok.size(); ++r)
     if (oa[r].x != 0.0 || oa[r].y != 0.0) {
@@ -537,13 +565,23 @@ int canonical_branches(const qw_ctx* ctx, const uint64_t* keys, const double* re
 
 int measure_partials(qw_state* st, int kind, double* result, hipStream_t stream) {
   const int grid = 256;
-  QW_HIP(qw::launch_measure(st->ctx->mat(), st->buf[st->cur], kind, st->mbuf, nullptr, grid, stream));
+  QW_HIP(qw::launch_measure(st->ctx->mat(), st->buf[st->cur], st->L, kind, st->mbuf, nullptr, grid, stream));
   std::vector<double> h(grid);
   QW_HIP(hipMemcpyAsync(h.data(), st->mbuf, sizeof(double) * grid, hipMemcpyDeviceToHost, stream));
   QW_HIP(hipStreamSynchronize(stream));
   double t = 0.0;
   for (double v : h) t += v;
   *result = t;
+  return QW_OK;
+}
+
+int total_written(qw_state* st, hipStream_t stream, int64_t* out) {
+  std::vector<unsigned long long> h(qw::kMaxGrid);
+  QW_HIP(hipMemcpyAsync(h.data(), st->acc, sizeof(unsigned long long) * qw::kMaxGrid, hipMemcpyDeviceToHost, stream));
+  QW_HIP(hipStreamSynchronize(stream));
+  unsigned long long t = 0;
+  for (auto v : h) t += v;
+  *out = int64_t(t);
   return QW_OK;
 }
 
@@ -620,19 +658,17 @@ int qw_state_init(qw_state** out, qw_ctx* ctx, const double* b_re, const double*
   if (!out || !ctx || !b_re) return set_err(QW_EINVAL, "missing argument");
   *out = nullptr;
   hipStream_t stream = static_cast<hipStream_t>(stream_v);
-  // b in N-vector layout
-  std::vector<double2> hb(size_t(ctx->jtotal), make_double2(0.0, 0.0));
-  int64_t nzb = 0, src = 0;
+  std::vector<double2> hb(static_cast<size_t>(ctx->jtotal), make_double2(0.0, 0.0));
+  int64_t src = 0;
   for (int32_t i = 0; i < ctx->ninst; ++i) {
     const HostInst& hi = ctx->inst[i];
     for (int32_t j = 0; j < hi.n; ++j, ++src) {
       const double2 v = make_double2(b_re[src], b_im ? b_im[src] : 0.0);
       if (!std::isfinite(v.x) || !std::isfinite(v.y)) return set_err(QW_EINVAL, "non-finite b");
       hb[size_t(hi.jbase + j)] = v;
-      nzb += (v.x != 0.0 || v.y != 0.0);
     }
   }
-  if (capacity == 0) capacity = 2 * (ctx->items + nzb) + 64;
+  if (capacity < 0) return set_err(QW_EINVAL, "capacity must be >= 0");
   qw_state* st;
   int rc = state_alloc(ctx, capacity, &st, stream);
   if (rc) return rc;
@@ -661,7 +697,7 @@ int qw_state_init(qw_state** out, qw_ctx* ctx, const double* b_re, const double*
       return rc;
     }
   } else {
-    e = qw::launch_init(ctx->mat(), st->b, st->buf[0], st->ctl, st->cap, 0, qw::kTau, stream);
+    e = qw::launch_init(ctx->mat(), st->b, st->buf[0], qw::kTau, stream);
     if (e != hipSuccess) {
       qw_state_free(st);
       return set_err(QW_EDEVICE, std::string("init: ") + hipGetErrorString(e));
@@ -682,15 +718,16 @@ void qw_state_free(qw_state* st) {
   ctx_release(ctx);
 }
 
-int qw_set_launch(qw_state* st, int32_t wg_size, int32_t grid_limit) {
+int qw_set_launch(qw_state* st, int32_t wg_size, int32_t grid) {
   if (!st) return set_err(QW_EINVAL, "state is NULL");
   if (wg_size) {
-    if (wg_size < 64 || wg_size > 256 || wg_size % 64) return set_err(QW_EINVAL, "workgroup size must be 64..256, a multiple of 64");
+    if (wg_size < 64 || wg_size > 256 || wg_size % 64)
+      return set_err(QW_EINVAL, "workgroup size must be 64..256, a multiple of 64");
     st->block = wg_size;
   }
-  if (grid_limit) {
-    if (grid_limit < 1 || grid_limit > 65536) return set_err(QW_EINVAL, "grid out of range");
-    st->grid = grid_limit;
+  if (grid) {
+    if (grid < 1 || grid > qw::kMaxGrid) return set_err(QW_EINVAL, "grid out of range (1..8192)");
+    st->grid = grid;
   }
   free_graphs(st);
   return QW_OK;
@@ -717,20 +754,19 @@ int qw_step_adjoint(qw_state* st, int32_t nsteps, void* stream_v) {
 
 int qw_sync(qw_state* st, void* stream) {
   if (!st) return set_err(QW_EINVAL, "state is NULL");
-  return check_overflow(st, static_cast<hipStream_t>(stream));
+  QW_HIP(hipStreamSynchronize(static_cast<hipStream_t>(stream)));
+  return QW_OK;
 }
 
 int qw_measure(qw_state* st, int32_t kind, void* out, int64_t out_len, void* stream_v) {
   if (!st || !out) return set_err(QW_EINVAL, "missing argument");
   hipStream_t stream = static_cast<hipStream_t>(stream_v);
-  int rc = check_overflow(st, stream);
-  if (rc) return rc;
   qw_ctx* ctx = st->ctx;
   switch (kind) {
     case QW_COUNT: {
       if (out_len < 1) return set_err(QW_EINVAL, "out_len too small");
       double c;
-      rc = measure_partials(st, 0, &c, stream);
+      int rc = measure_partials(st, 0, &c, stream);
       if (!rc) static_cast<int64_t*>(out)[0] = int64_t(std::llround(c));
       return rc;
     }
@@ -742,24 +778,27 @@ int qw_measure(qw_state* st, int32_t kind, void* out, int64_t out_len, void* str
     case QW_PROJECT: {
       const int64_t need = kind == QW_J_MARGINAL ? ctx->jtotal : 2 * ctx->jtotal;
       if (out_len < need) return set_err(QW_EINVAL, "out_len too small");
-      QW_HIP(qw::launch_fill(st->mbuf, sizeof(double) * need + (need & 1 ? 8 : 0), stream));
-      QW_HIP(qw::launch_measure(ctx->mat(), st->buf[st->cur], kind == QW_J_MARGINAL ? 2 : 3, nullptr, st->mbuf, 256,
-                                stream));
+      QW_HIP(qw::launch_fill(st->mbuf, (sizeof(double) * need + 15) / 16 * 16, stream));
+      QW_HIP(qw::launch_measure(ctx->mat(), st->buf[st->cur], st->L, kind == QW_J_MARGINAL ? 2 : 3, nullptr,
+                                st->mbuf, 256, stream));
       QW_HIP(hipMemcpyAsync(out, st->mbuf, sizeof(double) * need, hipMemcpyDeviceToHost, stream));
       QW_HIP(hipStreamSynchronize(stream));
       return QW_OK;
     }
     case QW_STATS: {
       if (out_len < 5) return set_err(QW_EINVAL, "out_len too small");
-      Ctl h;
-      QW_HIP(hipMemcpyAsync(&h, st->ctl, sizeof(Ctl), hipMemcpyDeviceToHost, stream));
-      QW_HIP(hipStreamSynchronize(stream));
       int64_t* o = static_cast<int64_t*>(out);
-      o[0] = int64_t(h.steps);
-      o[1] = int64_t(h.last_written);
-      o[2] = int64_t(st->cap);
-      o[3] = int64_t(h.overflow);
-      o[4] = int64_t(h.total_written);
+      double c;
+      int rc = measure_partials(st, 0, &c, stream);
+      if (rc) return rc;
+      int64_t tw;
+      rc = total_written(st, stream, &tw);
+      if (rc) return rc;
+      o[0] = st->launches;
+      o[1] = int64_t(std::llround(c));
+      o[2] = int64_t(st->L.cap);
+      o[3] = int64_t(st->L.cnt);
+      o[4] = tw;
       return QW_OK;
     }
     default:
@@ -776,23 +815,19 @@ int qw_export(qw_state* st, uint64_t* keys, double* re, double* im, int64_t cap,
   *m = count;
   if (cap < count) return set_err(QW_EINVAL, "output arrays too small: " + std::to_string(count) + " branches");
   if (count == 0) return QW_OK;
+  if (!keys) return set_err(QW_EINVAL, "keys is NULL");
   qw_ctx* ctx = st->ctx;
   void* dk = ctx->alloc.get(sizeof(uint64_t) * count);
   void* da = ctx->alloc.get(sizeof(double2) * count);
   void* dc = ctx->alloc.get(256);
-  if (!dk || !da || !dc) {
-    ctx->alloc.put(dk);
-    ctx->alloc.put(da);
-    ctx->alloc.put(dc);
-    return set_err(QW_ENOMEM, "device allocation failed for the export");
-  }
   std::vector<uint64_t> hk(static_cast<size_t>(count));
   std::vector<double2> ha(static_cast<size_t>(count));
   uint32_t got = 0;
-  hipError_t e = qw::launch_fill(dc, 256, stream);
+  hipError_t e = (dk && da && dc) ? hipSuccess : hipErrorOutOfMemory;
+  if (e == hipSuccess) e = qw::launch_fill(dc, 256, stream);
   if (e == hipSuccess)
-    e = qw::launch_export(ctx->mat(), st->buf[st->cur], static_cast<uint64_t*>(dk), static_cast<double2*>(da),
-                          static_cast<uint32_t*>(dc), uint32_t(count), stream);
+    e = qw::launch_export(ctx->mat(), st->buf[st->cur], st->L, static_cast<uint64_t*>(dk),
+                          static_cast<double2*>(da), static_cast<uint32_t*>(dc), uint32_t(count), stream);
   if (e == hipSuccess) e = hipMemcpyAsync(&got, dc, sizeof(uint32_t), hipMemcpyDeviceToHost, stream);
   if (e == hipSuccess) e = hipMemcpyAsync(hk.data(), dk, sizeof(uint64_t) * count, hipMemcpyDeviceToHost, stream);
   if (e == hipSuccess) e = hipMemcpyAsync(ha.data(), da, sizeof(double2) * count, hipMemcpyDeviceToHost, stream);
@@ -800,22 +835,23 @@ int qw_export(qw_state* st, uint64_t* keys, double* re, double* im, int64_t cap,
   ctx->alloc.put(dk);
   ctx->alloc.put(da);
   ctx->alloc.put(dc);
-  if (e != hipSuccess) return set_err(QW_EDEVICE, std::string("export: ") + hipGetErrorString(e));
+  if (e != hipSuccess)
+    return set_err(e == hipErrorOutOfMemory ? QW_ENOMEM : QW_EDEVICE, std::string("export: ") + hipGetErrorString(e));
   if (int64_t(got) != count) return set_err(QW_EDEVICE, "export count mismatch");
   std::vector<int64_t> idx(static_cast<size_t>(count));
   std::iota(idx.begin(), idx.end(), 0);
-  std::sort(idx.begin(), idx.end(), [&](int64_t a, int64_t b) { return hk[a] < hk[b]; });
+  std::sort(idx.begin(), idx.end(), [&](int64_t a, int64_t b) { return hk[size_t(a)] < hk[size_t(b)]; });
   for (int64_t t = 0; t < count; ++t) {
-    keys[t] = hk[idx[t]];
-    if (re) re[t] = ha[idx[t]].x;
-    if (im) im[t] = ha[idx[t]].y;
+    keys[t] = hk[size_t(idx[size_t(t)])];
+    if (re) re[t] = ha[size_t(idx[size_t(t)])].x;
+    if (im) im[t] = ha[size_t(idx[size_t(t)])].y;
   }
   return QW_OK;
 }
 
 int qw_state_import(qw_state* st, const uint64_t* keys, const double* re, const double* im, int64_t m,
                     void* stream_v) {
-  if (!st || (m > 0 && (!keys || !re))) return set_err(QW_EINVAL, "missing argument");
+  if (!st || m < 0 || (m > 0 && (!keys || !re))) return set_err(QW_EINVAL, "missing argument");
   hipStream_t stream = static_cast<hipStream_t>(stream_v);
   std::vector<uint64_t> k;
   std::vector<double2> a;
@@ -825,6 +861,7 @@ int qw_state_import(qw_state* st, const uint64_t* keys, const double* re, const 
   if (rc) return rc;
   st->prepared = false;
   st->steps_since_init = 0;
+  free_graphs(st);  // the list pointers may change
   return import_branches(st, k, a, stream);
 }
 
@@ -844,14 +881,14 @@ int qls_run(qw_ctx* ctx, const double* b, double kappa, double eps, int32_t j0_o
   const int64_t beta = int64_t(bb);
   int32_t j0 = int32_t(std::ceil(std::sqrt(bb * std::log(4.0 * bb / eps))));
   if (j0_override >= 0) j0 = j0_override;
-  std::vector<double> a(size_t(j0) + 1);
+  std::vector<double> a(static_cast<size_t>(j0) + 1);
   cks_coefficients(beta, j0, a.data());
   const int64_t nsteps = 2 * int64_t(j0) + 1;
   // coefficient per input step number m: a_{(m-1)/2} for odd m
-  std::vector<double> coefm(size_t(nsteps) + 1, 0.0);
-  for (int64_t m = 1; m <= nsteps; m += 2) coefm[size_t(m)] = a[size_t((m - 1) / 2)];
+  std::vector<double> coefm(static_cast<size_t>(nsteps) + 1, 0.0);
+  for (int64_t mm = 1; mm <= nsteps; mm += 2) coefm[size_t(mm)] = a[size_t((mm - 1) / 2)];
   // the solver works on instance 0 only
-  std::vector<double> bfull(size_t(ctx->ntotal), 0.0);
+  std::vector<double> bfull(static_cast<size_t>(ctx->ntotal), 0.0);
   for (int32_t j = 0; j < ctx->inst[0].n; ++j) bfull[size_t(j)] = b[j];
   qw_state* st = nullptr;
   int rc = qw_state_init(&st, ctx, bfull.data(), nullptr, 0, 0, stream_v);
@@ -860,14 +897,13 @@ int qls_run(qw_ctx* ctx, const double* b, double kappa, double eps, int32_t j0_o
   double* dcoef = static_cast<double*>(ctx->alloc.get(sizeof(double) * coefm.size()));
   double2* y = static_cast<double2*>(ctx->alloc.get(sizeof(double2) * ctx->jtotal));
   std::vector<double2> hy(static_cast<size_t>(ctx->jtotal));
-  std::vector<double> proj(2 * size_t(ctx->jtotal));
+  std::vector<double> proj(2 * static_cast<size_t>(ctx->jtotal));
   hipError_t e = (dcoef && y) ? hipSuccess : hipErrorOutOfMemory;
   if (e == hipSuccess)
     e = hipMemcpyAsync(dcoef, coefm.data(), sizeof(double) * coefm.size(), hipMemcpyHostToDevice, stream);
   if (e == hipSuccess) e = qw::launch_fill(y, sizeof(double2) * ctx->jtotal, stream);
   if (e == hipSuccess) {
     rc = run_steps(st, nsteps, stream, y, dcoef);
-    if (!rc) rc = check_overflow(st, stream);
     if (!rc) rc = qw_measure(st, QW_PROJECT, proj.data(), int64_t(proj.size()), stream_v);
     if (!rc) {
       e = hipMemcpyAsync(hy.data(), y, sizeof(double2) * ctx->jtotal, hipMemcpyDeviceToHost, stream);
@@ -899,17 +935,15 @@ int qw_grad(qw_state* st, const double* w, int32_t nsteps, double* dvals, double
   if (!st->prepared || st->steps_since_init != nsteps)
     return set_err(QW_EINVAL, "qw_grad needs the state made by qw_state_init (T~ start) advanced by exactly nsteps");
   hipStream_t stream = static_cast<hipStream_t>(stream_v);
-  int rc = check_overflow(st, stream);
-  if (rc) return rc;
   qw_ctx* ctx = st->ctx;
-  // weights in N-vector layout
-  std::vector<double> hw(size_t(ctx->jtotal), 0.0);
+  std::vector<double> hw(static_cast<size_t>(ctx->jtotal), 0.0);
   int64_t src = 0;
   for (int32_t i = 0; i < ctx->ninst; ++i)
     for (int32_t j = 0; j < ctx->inst[i].n; ++j, ++src) hw[size_t(ctx->inst[i].jbase + j)] = w[src];
   qw_state* lam = nullptr;
-  rc = state_alloc(ctx, st->cap, &lam, stream);
+  int rc = state_alloc(ctx, st->L.cap, &lam, stream);
   if (rc) return rc;
+  lam->L.cnt = st->L.cnt;
   double* dw = static_cast<double*>(ctx->alloc.get(sizeof(double) * ctx->jtotal));
   double* dv = static_cast<double*>(ctx->alloc.get(sizeof(double) * ctx->items));
   double2* db = static_cast<double2*>(ctx->alloc.get(sizeof(double2) * ctx->jtotal));
@@ -923,9 +957,11 @@ int qw_grad(qw_state* st, const double* w, int32_t nsteps, double* dvals, double
   // Psi_n = S psi_n, Lambda_n = diag(w[k]) Psi_n
   if (e == hipSuccess) {
     rc = launch_one(st, qw::kSwap, stream);
-    if (!rc) e = qw::launch_weight(mm, st->buf[st->cur], lam->buf[0], lam->ctl, dw, lam->cap, st->mbuf, 256, stream);
+    if (!rc)
+      e = qw::launch_weight(mm, st->buf[st->cur], st->L, lam->buf[0], lam->L, dw, st->mbuf, 256, stream);
   }
-  if (e == hipSuccess && !rc) e = hipMemcpyAsync(part.data(), st->mbuf, sizeof(double) * 256, hipMemcpyDeviceToHost, stream);
+  if (e == hipSuccess && !rc)
+    e = hipMemcpyAsync(part.data(), st->mbuf, sizeof(double) * 256, hipMemcpyDeviceToHost, stream);
   for (int32_t t = nsteps; t >= 1 && e == hipSuccess && !rc; --t) {
     qw::AdjArgs a;
     a.m = mm;
@@ -933,31 +969,33 @@ int qw_grad(qw_state* st, const double* w, int32_t nsteps, double* dvals, double
     a.out = st->buf[st->cur ^ 1];
     a.lin = lam->buf[lam->cur];
     a.lout = lam->buf[lam->cur ^ 1];
-    a.ctl = st->ctl;
-    a.lctl = lam->ctl;
-    a.cap = st->cap;
+    a.L = st->L;
+    a.LL = lam->L;
+    a.acc = st->acc;
+    a.lacc = lam->acc;
     a.tau = qw::kTau;
     a.dv = dv;
     e = qw::launch_adjoint(a, step_grid(st), st->block, stream);
     st->cur ^= 1;
     lam->cur ^= 1;
+    ++st->launches;
   }
   // back to the unconjugated frame: psi_0 and lambda_0
   if (e == hipSuccess && !rc) rc = launch_one(st, qw::kSwap, stream);
   if (e == hipSuccess && !rc) rc = launch_one(lam, qw::kSwap, stream);
   if (e == hipSuccess && !rc) e = qw::launch_grad_init(mm, lam->buf[lam->cur], st->b, dv, db, stream);
-  if (e == hipSuccess && !rc) e = hipMemcpyAsync(hdv.data(), dv, sizeof(double) * ctx->items, hipMemcpyDeviceToHost, stream);
-  if (e == hipSuccess && !rc) e = hipMemcpyAsync(hdb.data(), db, sizeof(double2) * ctx->jtotal, hipMemcpyDeviceToHost, stream);
+  if (e == hipSuccess && !rc)
+    e = hipMemcpyAsync(hdv.data(), dv, sizeof(double) * ctx->items, hipMemcpyDeviceToHost, stream);
+  if (e == hipSuccess && !rc)
+    e = hipMemcpyAsync(hdb.data(), db, sizeof(double2) * ctx->jtotal, hipMemcpyDeviceToHost, stream);
   if (e == hipSuccess && !rc) e = hipStreamSynchronize(stream);
-  if (e == hipSuccess && !rc) rc = check_overflow(lam, stream);
-  if (e == hipSuccess && !rc) rc = check_overflow(st, stream);
   ctx->alloc.put(dw);
   ctx->alloc.put(dv);
   ctx->alloc.put(db);
   qw_state_free(lam);
   st->steps_since_init = 0;
-  if (e != hipSuccess) return set_err(e == hipErrorOutOfMemory ? QW_ENOMEM : QW_EDEVICE,
-                                      std::string("gradient: ") + hipGetErrorString(e));
+  if (e != hipSuccess)
+    return set_err(e == hipErrorOutOfMemory ? QW_ENOMEM : QW_EDEVICE, std::string("gradient: ") + hipGetErrorString(e));
   if (rc) return rc;
   if (loss) {
     double L = 0.0;

@@ -1,5 +1,6 @@
-// Internal declarations shared by the host API (qw_api.hip) and the kernels
-// (qw_kernels.hip) of libqw.  Not part of the public ABI.
+// Internal declarations shared by the host API (qw_api.cpp), the launchers
+// (qw_launch.cpp) and the kernels (qw_kernels.hip) of libqw.  Not part of the
+// public ABI.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -8,15 +9,16 @@
 
 namespace qw {
 
-constexpr int kWave = 64;      // CDNA wavefront width
-constexpr int kMaxS = 64;      // largest QRAM row length handled (one wave per group)
+constexpr int kWave = 64;       // CDNA wavefront width
+constexpr int kMaxS = 64;       // largest QRAM row length handled (one wave per group)
+constexpr int kMaxGrid = 8192;  // largest step-kernel grid (per-workgroup counters)
 constexpr double kTau = 1e-13;  // pruning threshold applied after every step
 
-// Per-instance facts, resident on the device.  The reflection slots of
-// instance i are the ELL entries [item_base, item_base + N*s); the base is a
-// multiple of 64 so that a wavefront never straddles two instances.
+// Per-instance facts, resident on the device.  The ELL slots of instance i
+// are [item_base, item_base + N*s); the base is a multiple of 64 so that a
+// wavefront never straddles two instances.
 struct Inst {
-  int64_t item_base;  // first ELL slot (= first phase-A work item)
+  int64_t item_base;  // first ELL slot (= first work item)
   int64_t jbase;      // offset of this instance in N-vectors
   int32_t N;          // padded dimension (power of two)
   int32_t s;          // slots per row (power of two, <= 64)
@@ -25,37 +27,30 @@ struct Inst {
   double inv_sqrt_s;  // 1/sqrt(s)
 };
 
-// One branch list (the sparse part of a state) plus its reflection-slot
-// array.  R holds, for every ELL slot q = (inst, j, l), the amplitudes of the
-// two keys (0, j, 0, 0, col[q], b2), b2 = 0 at R[2q] and b2 = 1 at R[2q+1]
-// (interleaved complex double).  Every other branch lives in the list.
-struct Buf {
+// Amplitudes with a static home, for every ELL slot q = (inst, j, l):
+//   R[2q + b2]: key (0, j, 0, 0, col[q], b2)                (a group member)
+//   Q[2q + b2]: key S(above) = (0, col[q], b2, 0, j, 0)     when it is not itself
+//               a group member (always for b2 = 1; for b2 = 0 only when
+//               rev[q] < 0); Q[2q] stays 0 when rev[q] >= 0.
+// Interleaved complex double; an exact 0 means "no branch".
+struct Slots {
   double2* R;
-  uint64_t* key;
-  double2* amp;
-  uint32_t* cnt;  // number of list entries (may exceed cap after an overflow)
-  uint32_t cap;   // list capacity
+  double2* Q;
 };
 
-// Device-side bookkeeping of a state (one cache line each to avoid sharing).
-struct Ctl {
-  uint32_t cnt[2];         // list counts of the two buffers
-  uint32_t pad0[30];
-  uint32_t done;           // workgroups finished in the current launch
-  uint32_t pad1[31];
-  uint32_t overflow;       // set when a list append exceeded the capacity
-  uint32_t pad2[31];
-  unsigned long long written;       // branches kept by the current launch
-  unsigned long long last_written;  // ... by the last completed launch
-  unsigned long long steps;         // completed step launches
-  unsigned long long total_written; // branches kept, summed over all launches
-  uint32_t stepno;                  // solver step counter (indexes the coefficient table)
-  uint32_t pad3[23];
+// Branches outside the span of those keys (imports, raw starts): the walk
+// maps each to -S(itself), so the list keeps its size and order.
+struct List {
+  uint64_t* key;
+  double2* amp;
+  uint32_t cnt;
+  uint32_t cap;
 };
 
 struct Matrix {
   const int32_t* col;  // ELL column indices, sorted inside each row
   const double* val;   // ELL values
+  const int32_t* rev;  // rev[q] = position of j in row col[q] (QBS), -1 if absent
   const Inst* inst;
   int32_t ninst;
   int32_t nbits;       // register width n of the key layout
@@ -66,53 +61,58 @@ enum Mode : int32_t { kStep = 0, kSwap = 1 };
 
 struct StepArgs {
   Matrix m;
-  Buf in, out;
-  Ctl* ctl;
-  uint32_t cap;
-  int32_t mode;
+  Slots in, out;
+  List L;
+  unsigned long long* acc;  // per-workgroup running count of branches written
+  uint32_t* stepno;         // per-workgroup step counter (indexes coefm)
+  int32_t mode;             // kStep: W; kSwap: S only
+  int32_t pad_;
   double tau;
-  // optional fused projection accumulation (linear solver): y[j] += coefm[stepno] * <psi~_j|state>
+  // optional fused projection (linear solver): y[j] += coefm[step] <psi~_j|state>
   double2* yacc;
   const double* coefm;
 };
 
 struct AdjArgs {
   Matrix m;
-  Buf in, out;    // the recomputed state
-  Buf lin, lout;  // the adjoint state
-  Ctl* ctl;
-  Ctl* lctl;
-  uint32_t cap;
+  Slots in, out;    // recomputed state (kept S-conjugated)
+  Slots lin, lout;  // adjoint state (kept S-conjugated)
+  List L, LL;
+  unsigned long long* acc;
+  unsigned long long* lacc;
   double tau;
-  double* dv;     // gradient per ELL slot, accumulated
+  double* dv;       // gradient per ELL slot, accumulated
 };
 
 // The host side is compiled by the host compiler and the kernels by the GPU
 // compiler; the argument structures must have one layout on both.
 static_assert(sizeof(Inst) == 40 && offsetof(Inst, inv_sqrt_s) == 32, "Inst layout");
-static_assert(sizeof(Buf) == 40 && offsetof(Buf, cap) == 32, "Buf layout");
-static_assert(sizeof(Matrix) == 40 && offsetof(Matrix, items) == 32, "Matrix layout");
-static_assert(sizeof(StepArgs) == 160 && offsetof(StepArgs, coefm) == 152, "StepArgs layout");
-static_assert(sizeof(AdjArgs) == 240 && offsetof(AdjArgs, dv) == 232, "AdjArgs layout");
+static_assert(sizeof(Slots) == 16, "Slots layout");
+static_assert(sizeof(List) == 24 && offsetof(List, cap) == 20, "List layout");
+static_assert(sizeof(Matrix) == 48 && offsetof(Matrix, items) == 40, "Matrix layout");
+static_assert(sizeof(StepArgs) == 152 && offsetof(StepArgs, coefm) == 144, "StepArgs layout");
+static_assert(sizeof(AdjArgs) == 192 && offsetof(AdjArgs, dv) == 184, "AdjArgs layout");
 
 // Launchers (qw_launch.cpp).  All enqueue on `stream` and allocate nothing.
 hipError_t launch_step(const StepArgs& a, int grid, int block, hipStream_t stream);
 hipError_t launch_adjoint(const AdjArgs& a, int grid, int block, hipStream_t stream);
-hipError_t launch_init(const Matrix& m, const double2* b, Buf out, Ctl* ctl, uint32_t cap, int32_t raw,
-                       double tau, hipStream_t stream);
+hipError_t launch_qbs_table(const Matrix& m, int32_t* rev, hipStream_t stream);
+hipError_t launch_init(const Matrix& m, const double2* b, Slots out, double tau, hipStream_t stream);
 hipError_t launch_fill(void* p, int64_t bytes, hipStream_t stream);
-// Reductions over a state: kind 0 = count, 1 = norm^2 (per-block partials
-// in `partial`, length >= grid), 2 = j marginal (atomics into out[N-vector]),
-// 3 = projection <psi~_j|state> into out (interleaved complex).
-hipError_t launch_measure(const Matrix& m, Buf b, int32_t kind, double* partial, double* out, int grid,
+// Reductions over a state: kind 0 = count, 1 = norm^2 (per-block partials in
+// `partial`, length >= grid); kind 2 = j marginal into out (N-vector, must be
+// zero); kind 3 = projection <psi~_j|state> into out (interleaved complex).
+hipError_t launch_measure(const Matrix& m, Slots st, List L, int32_t kind, double* partial, double* out, int grid,
                           hipStream_t stream);
-hipError_t launch_export(const Matrix& m, Buf b, uint64_t* keys, double2* amps, uint32_t* count,
+hipError_t launch_export(const Matrix& m, Slots st, List L, uint64_t* keys, double2* amps, uint32_t* count,
                          uint32_t cap, hipStream_t stream);
-hipError_t launch_import(const Matrix& m, const uint64_t* keys, const double2* amps, int64_t n, Buf out,
-                         Ctl* ctl, uint32_t cap, hipStream_t stream);
-hipError_t launch_weight(const Matrix& m, Buf in, Buf out, Ctl* octl, const double* w, uint32_t cap,
-                         double* partial, int grid, hipStream_t stream);
-hipError_t launch_grad_init(const Matrix& m, Buf lam, const double2* b, double* dv, double2* db,
+// Place unique branches at their homes; keys with no static home are appended
+// to the list (count in *lcnt, which must start at 0).
+hipError_t launch_import(const Matrix& m, const uint64_t* keys, const double2* amps, int64_t n, Slots out, List L,
+                         uint32_t* lcnt, hipStream_t stream);
+hipError_t launch_weight(const Matrix& m, Slots in, List L, Slots out, List LL, const double* w, double* partial,
+                         int grid, hipStream_t stream);
+hipError_t launch_grad_init(const Matrix& m, Slots lam, const double2* b, double* dv, double2* db,
                             hipStream_t stream);
 
 }  // namespace qw

@@ -9,33 +9,36 @@
 //   -1                    on every other branch,
 // with phi_j(l, 0) = f_{jl}/sqrt(s), phi_j(l, 1) = g_{jl}/sqrt(s) (P of
 // Eq. "impl" flips every branch but |j~>).  O_s' and S are bijections of the
-// keys, so the only interference in a step is one reduction per group j; no
-// global sort is needed.  The group of j is exactly the set of keys
-// (0, j, 0, 0, k_{j,l}, b2), l < s: it has a fixed address, the ELL slot
-// (j, l).  A state is therefore held as
-//   R[2q + b2]  amplitude of key (0, j, 0, 0, col[q], b2) for ELL slot q=(j,l)
-//   a list      (key, amplitude) of every other branch (structure of arrays)
-// and one kernel per step does, for every slot q (phase A): read the pair,
-// reduce c_j = sum_l conj(f) psi(l,0) + g psi(l,1) over the s lanes of the
-// group (wave shuffles), write 2c_j phi - psi, apply S, and send each output
-// branch to its home for the next step (a slot when the output key is a group
-// member, found with the quantum binary search of the row; else a list
-// append compacted with wave ballots and one atomic per wave); and for every
-// list entry (phase B): negate, apply S, send home.  Branches with |Re| and
-// |Im| <= tau are dropped on output.  The consumed R entries are zeroed as
-// they are read, so the two R buffers alternate without a clearing pass.
+// keys, so the only interference in a step is one reduction per group j.
+//
+// The members of group j are the keys K(q, b2) = (0, j, 0, 0, col[q], b2) of
+// the ELL slots q = (j, l) of row j; after O_s' and S the reflected outputs
+// are S K(q, b2) = (0, col[q], b2, 0, j, 0).  S K(q, 1) is never a group
+// member (b1 = 1); S K(q, 0) is the member K(q', 0) of slot
+// q' = (col[q], rev[q]) when j is in row col[q] (rev = the quantum binary
+// search of j in that row, tabulated once per matrix), and not a member
+// otherwise.  One step later every S K(q, b2) that is not a member is mapped
+// back to K(q, b2) (by -S).  So every branch reachable from T~|b~> has a
+// fixed address: R[q][b2] for K(q, b2), Q[q][b2] for a non-member S K(q, b2).
+// One launch per step reads R_in and Q_in of its slot, reduces the group with
+// wave shuffles, and writes each output to its address for the next step:
+//   R_in  -> reflection -> Q_out[q][1] and R_out[q'][0] (or Q_out[q][0])
+//   Q_in  -> negation   -> R_out[q][b2]
+// Every output address receives exactly one write per step (0 when pruned),
+// so there is no atomic, no compaction and no clearing pass; the result is
+// independent of scheduling.  Branches outside that span (only from raw
+// starts or imports) sit in a list that W maps in place to -S(key).
 #include "qw_internal.h"
 
 #include <hip/hip_runtime.h>
 
 namespace qw {
 
-static_assert(sizeof(Ctl) == 512, "control block layout");
-
 // ----------------------------------------------------------------- helpers
 
 __device__ __forceinline__ double2 cadd(double2 a, double2 b) { return make_double2(a.x + b.x, a.y + b.y); }
 __device__ __forceinline__ double2 csub(double2 a, double2 b) { return make_double2(a.x - b.x, a.y - b.y); }
+__device__ __forceinline__ double2 cneg(double2 a) { return make_double2(-a.x, -a.y); }
 __device__ __forceinline__ double2 cscale(double2 a, double t) { return make_double2(a.x * t, a.y * t); }
 __device__ __forceinline__ double2 cmul(double2 a, double2 b) {
   return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
@@ -44,7 +47,17 @@ __device__ __forceinline__ double2 cmul(double2 a, double2 b) {
 __device__ __forceinline__ double2 cjmul(double2 a, double2 b) {
   return make_double2(a.x * b.x + a.y * b.y, a.x * b.y - a.y * b.x);
 }
-__device__ __forceinline__ bool nonzero_tau(double2 v, double tau) { return fabs(v.x) > tau || fabs(v.y) > tau; }
+__device__ __forceinline__ bool kept(double2 v, double tau) { return fabs(v.x) > tau || fabs(v.y) > tau; }
+__device__ __forceinline__ bool nonzero(double2 v) { return v.x != 0.0 || v.y != 0.0; }
+__device__ __forceinline__ double2 zero2() { return make_double2(0.0, 0.0); }
+// value, or exact 0 when it falls to the pruning threshold
+__device__ __forceinline__ double2 prune(double2 v, double tau, unsigned& cnt) {
+  if (kept(v, tau)) {
+    ++cnt;
+    return v;
+  }
+  return zero2();
+}
 
 // Rotation amplitudes of Sec. IV (footnote on negative elements):
 // f = sqrt(a) for a >= 0, +-i sqrt|a| (+ when row j <= column k) for a < 0,
@@ -126,196 +139,144 @@ __device__ __forceinline__ uint64_t swap_halves(uint64_t key, int n) {
   return (top << (2 * h)) | (lo << h) | hi;
 }
 
-// Key of the slot entry (0, j, 0, 0, col, b2) of instance `inst`.
-__device__ __forceinline__ uint64_t slot_key(uint64_t inst, int n, int j, int col, int b2) {
+// K(q, b2) = (0, j, 0, 0, col, b2) of instance `inst`.
+__device__ __forceinline__ uint64_t member_key(uint64_t inst, int n, int j, int col, int b2) {
   return (inst << (4 * n + 2)) | (uint64_t(j) << (2 * n + 2)) | (uint64_t(col) << 1) | uint64_t(b2);
 }
-
-// Home of a branch for the next step: if the key is a group member
-// (j_c = b1 = k_c = 0 and k in row j) return true and its slot index.
-__device__ __forceinline__ bool home_slot(const Matrix& m, uint64_t key, int64_t& slot, int& b2) {
-  const int n = m.nbits;
-  const uint64_t nm = (uint64_t(1) << n) - 1;
-  b2 = int(key & 1);
-  const int k = int((key >> 1) & nm);
-  const uint64_t kc = (key >> (n + 1)) & nm;
-  const uint64_t b1 = (key >> (2 * n + 1)) & 1;
-  const int j = int((key >> (2 * n + 2)) & nm);
-  const uint64_t jc = (key >> (3 * n + 2)) & nm;
-  const uint64_t inst = key >> (4 * n + 2);
-  if (jc != 0 || b1 != 0 || kc != 0 || inst >= uint64_t(m.ninst)) return false;
-  const Inst I = m.inst[inst];
-  if (j >= I.N || k >= I.N) return false;
-  const int64_t row = I.item_base + int64_t(j) * I.s;
-  int p;
-  if (!qbs(m.col + row, I.s, k, p)) return false;
-  slot = row + p;
-  return true;
+// S K(q, b2) = (0, col, b2, 0, j, 0).
+__device__ __forceinline__ uint64_t swapped_key(uint64_t inst, int n, int j, int col, int b2) {
+  return (inst << (4 * n + 2)) | (uint64_t(col) << (2 * n + 2)) | (uint64_t(b2) << (2 * n + 1)) |
+         (uint64_t(j) << 1);
 }
 
-// Wave-level compacted append of up to two values per lane to a list.
-__device__ __forceinline__ void wave_append(const Buf& out, uint32_t cap, bool app0, uint64_t k0, double2 v0,
-                                            bool app1, uint64_t k1, double2 v1, bool& overflow) {
+// Work item of a dense pass: instance (wave-uniform), slot, row, position.
+struct Item {
+  Inst I;
+  int inst;
+  int j, l;
+  bool live;
+};
+__device__ __forceinline__ Item item_of(const Matrix& m, int64_t it) {
+  Item x;
   const int lane = threadIdx.x & (kWave - 1);
-  const uint64_t lt = (uint64_t(1) << lane) - 1;
-  const uint64_t m0 = __ballot(app0);
-  const uint64_t m1 = __ballot(app1);
-  const uint32_t n0 = __popcll(m0), n1 = __popcll(m1);
-  if (n0 + n1 == 0) return;
-  uint32_t base = 0;
-  if (lane == 0) base = atomicAdd(out.cnt, n0 + n1);
-  base = __shfl(base, 0);
-  if (app0) {
-    const uint32_t idx = base + __popcll(m0 & lt);
-    if (idx < cap) {
-      out.key[idx] = k0;
-      out.amp[idx] = v0;
-    } else {
-      overflow = true;
-    }
-  }
-  if (app1) {
-    const uint32_t idx = base + n0 + __popcll(m1 & lt);
-    if (idx < cap) {
-      out.key[idx] = k1;
-      out.amp[idx] = v1;
-    } else {
-      overflow = true;
-    }
-  }
+  x.inst = __builtin_amdgcn_readfirstlane(find_inst(m, it - lane));
+  x.I = m.inst[x.inst];
+  const int64_t local = it - x.I.item_base;
+  x.live = local < int64_t(x.I.N) * x.I.s;
+  x.l = int(local) & (x.I.s - 1);
+  x.j = int(local >> x.I.hbits);
+  return x;
 }
 
-__device__ __forceinline__ unsigned long long wave_sum_u64(unsigned long long v) {
+__device__ __forceinline__ unsigned long long block_sum_u64(unsigned long long v, unsigned long long* sh) {
   for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
-  return v;
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = v;
+  __syncthreads();
+  unsigned long long t = 0;
+  if (threadIdx.x == 0)
+    for (int i = 0; i < int(blockDim.x >> 6); ++i) t += sh[i];
+  return t;
 }
 
-// Last-workgroup bookkeeping: the input list has been consumed, counters
-// advance.  Called by every thread after its work.
-__device__ __forceinline__ void finish_launch(Ctl* ctl, uint32_t* in_cnt, unsigned long long kept, bool overflow) {
-  const int lane = threadIdx.x & (kWave - 1);
-  kept = wave_sum_u64(kept);
-  const bool any_over = __ballot(overflow) != 0;
-  if (lane == 0) {
-    if (kept) atomicAdd(&ctl->written, kept);
-    if (any_over) atomicOr(&ctl->overflow, 1u);
-  }
+__device__ __forceinline__ double block_sum(double v, double* sh) {
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
   __syncthreads();
-  if (threadIdx.x == 0) {
-    __threadfence();
-    const uint32_t ticket = atomicAdd(&ctl->done, 1u);
-    if (ticket == gridDim.x - 1) {
-      __threadfence();
-      *in_cnt = 0;
-      ctl->done = 0;
-      const unsigned long long w = atomicExch(&ctl->written, 0ull);
-      ctl->last_written = w;
-      ctl->total_written += w;
-      ctl->steps += 1;
-      ctl->stepno += 1;
-      __threadfence();
-    }
+  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = v;
+  __syncthreads();
+  double t = 0.0;
+  if (threadIdx.x == 0)
+    for (int i = 0; i < int(blockDim.x >> 6); ++i) t += sh[i];
+  return t;
+}
+
+// Outputs of one slot for the next step (shared by the step and adjoint
+// kernels).  o0, o1: reflected group amplitudes of K(q, b2) before S;
+// n0, n1: outputs of Q_in[q][b2] (already negated or not).
+__device__ __forceinline__ void write_slot(const Slots& out, const Item& x, int64_t q, int colq, int pr, double2 o0,
+                                           double2 o1, double2 n0, double2 n1) {
+  out.Q[2 * q + 1] = o1;
+  if (pr >= 0) {
+    out.R[2 * (x.I.item_base + int64_t(colq) * x.I.s + pr)] = o0;
+  } else {
+    out.Q[2 * q] = o0;
+    out.R[2 * q] = n0;
   }
+  out.R[2 * q + 1] = n1;
 }
 
 // ----------------------------------------------------------------- walk step
 
 template <bool ACC>
 __device__ __forceinline__ void step_body(StepArgs a) {
-  const int lane = threadIdx.x & (kWave - 1);
-  const int n = a.m.nbits;
+  __shared__ unsigned long long sh[16];
   const int64_t A = a.m.items;
-  const uint32_t B = min(*a.in.cnt, a.in.cap);
-  const int64_t total = A + ((int64_t(B) + kWave - 1) & ~int64_t(kWave - 1));
-  double coef = 0.0;
-  if (ACC) coef = a.coefm[a.ctl->stepno];
+  const int64_t total = A + ((int64_t(a.L.cnt) + kWave - 1) & ~int64_t(kWave - 1));
   const bool reflect = a.mode == kStep;
-  unsigned long long kept = 0;
-  bool overflow = false;
+  const int n = a.m.nbits;
+  double coef = 0.0;
+  uint32_t stepno = 0;
+  if (ACC) {
+    stepno = a.stepno[blockIdx.x];
+    coef = a.coefm[stepno];
+  }
+  unsigned cnt = 0;
   const int64_t stride = int64_t(gridDim.x) * blockDim.x;
   for (int64_t it = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; it < total; it += stride) {
-    bool app0 = false, app1 = false;
-    uint64_t k0 = 0, k1 = 0;
-    double2 v0 = make_double2(0.0, 0.0), v1 = v0;
     if (it < A) {
-      // ---- phase A: one ELL slot (j, l) per lane, a group of s lanes per row j
-      const int ii = __builtin_amdgcn_readfirstlane(find_inst(a.m, it - lane));
-      const Inst I = a.m.inst[ii];
-      const int64_t local = it - I.item_base;
-      const bool live = local < int64_t(I.N) * I.s;
-      const int l = int(local) & (I.s - 1);
-      const int j = int(local >> I.hbits);
-      double2 p0 = make_double2(0.0, 0.0), p1 = p0;
+      const Item x = item_of(a.m, it);
+      double2 x0 = zero2(), x1 = zero2(), y0 = zero2(), y1 = zero2();
       Rot r;
-      r.f = p0;
+      r.f = zero2();
       r.g = 0.0;
-      int colq = 0;
-      if (live) {
-        p0 = a.in.R[2 * it];
-        p1 = a.in.R[2 * it + 1];
-        a.in.R[2 * it] = make_double2(0.0, 0.0);
-        a.in.R[2 * it + 1] = make_double2(0.0, 0.0);
+      int colq = 0, pr = -1;
+      if (x.live) {
+        x0 = a.in.R[2 * it];
+        x1 = a.in.R[2 * it + 1];
+        y1 = a.in.Q[2 * it + 1];
         colq = a.m.col[it];
-        r = rotation(a.m.val[it], j, colq);
+        pr = a.m.rev[it];
+        if (pr < 0) y0 = a.in.Q[2 * it];
+        r = rotation(a.m.val[it], x.j, colq);
       }
-      double2 o0 = p0, o1 = p1;
+      double2 o0 = x0, o1 = x1, n0 = y0, n1 = y1;
       if (reflect) {
-        double2 c = cadd(cjmul(r.f, p0), cscale(p1, r.g));
-        c = group_sum(c, I.s);
-        if (ACC && live && l == 0) {
-          double2 y = a.yacc[I.jbase + j];
-          y.x += coef * (c.x * I.inv_sqrt_s);
-          y.y += coef * (c.y * I.inv_sqrt_s);
-          a.yacc[I.jbase + j] = y;
+        const double2 c = group_sum(cadd(cjmul(r.f, x0), cscale(x1, r.g)), x.I.s);
+        if (ACC && x.live && x.l == 0) {
+          double2 y = a.yacc[x.I.jbase + x.j];
+          y.x += coef * (c.x * x.I.inv_sqrt_s);
+          y.y += coef * (c.y * x.I.inv_sqrt_s);
+          a.yacc[x.I.jbase + x.j] = y;
         }
-        const double2 tc = cscale(c, 2.0 / double(I.s));
-        o0 = csub(cmul(tc, r.f), p0);
-        o1 = csub(cscale(tc, r.g), p1);
+        const double2 tc = cscale(c, 2.0 / double(x.I.s));
+        o0 = csub(cmul(tc, r.f), x0);
+        o1 = csub(cscale(tc, r.g), x1);
+        n0 = cneg(y0);
+        n1 = cneg(y1);
       }
-      const bool keep0 = live && nonzero_tau(o0, a.tau);
-      const bool keep1 = live && nonzero_tau(o1, a.tau);
-      // after S the keys are (0, col, b2, 0, j, 0)
-      k0 = (uint64_t(ii) << (4 * n + 2)) | (uint64_t(colq) << (2 * n + 2)) | (uint64_t(j) << 1);
-      k1 = k0 | (uint64_t(1) << (2 * n + 1));
-      if (keep0) {
-        int p;
-        if (qbs(a.m.col + I.item_base + int64_t(colq) * I.s, I.s, j, p)) {
-          a.out.R[2 * (I.item_base + int64_t(colq) * I.s + p)] = o0;
-        } else {
-          app0 = true;
-          v0 = o0;
-        }
+      if (x.live) {
+        o0 = prune(o0, a.tau, cnt);
+        o1 = prune(o1, a.tau, cnt);
+        n1 = prune(n1, a.tau, cnt);
+        if (pr < 0) n0 = prune(n0, a.tau, cnt);
+        write_slot(a.out, x, it, colq, pr, o0, o1, n0, n1);
       }
-      if (keep1) {
-        app1 = true;
-        v1 = o1;
-      }
-      kept += unsigned(keep0) + unsigned(keep1);
     } else {
-      // ---- phase B: one list entry per lane; P R H P H R^dagger = -1 there
       const int64_t e = it - A;
-      if (e < int64_t(B)) {
-        const uint64_t key = a.in.key[e];
-        double2 v = a.in.amp[e];
-        if (reflect) v = make_double2(-v.x, -v.y);
-        if (nonzero_tau(v, a.tau)) {
-          ++kept;
-          const uint64_t kk = swap_halves(key, n);
-          int64_t slot;
-          int b2;
-          if (home_slot(a.m, kk, slot, b2)) {
-            a.out.R[2 * slot + b2] = v;
-          } else {
-            app0 = true;
-            k0 = kk;
-            v0 = v;
-          }
-        }
+      if (e < int64_t(a.L.cnt)) {
+        double2 v = a.L.amp[e];
+        if (reflect) v = cneg(v);
+        a.L.amp[e] = v;
+        a.L.key[e] = swap_halves(a.L.key[e], n);
+        cnt += nonzero(v);
       }
     }
-    wave_append(a.out, a.cap, app0, k0, v0, app1, k1, v1, overflow);
   }
-  finish_launch(a.ctl, a.in.cnt, kept, overflow);
+  const unsigned long long t = block_sum_u64(cnt, sh);
+  if (threadIdx.x == 0) {
+    a.acc[blockIdx.x] += t;
+    if (ACC) a.stepno[blockIdx.x] = stepno + 1;
+  }
 }
 
 }  // namespace qw
@@ -325,141 +286,121 @@ extern "C" __global__ void __launch_bounds__(256) qwk_step_acc(qw::StepArgs a) {
 
 namespace qw {
 
+// ----------------------------------------------------------------- QBS table
+// rev[q] = i_{col[q]}(j): where row j's slot q points back into its column's
+// row, or -1 (filler or asymmetric pattern).
+
+extern "C" __global__ void __launch_bounds__(256) qwk_qbs_table(Matrix m, int32_t* rev) {
+  const int64_t stride = int64_t(gridDim.x) * blockDim.x;
+  for (int64_t it = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; it < m.items; it += stride) {
+    const int ii = find_inst(m, it);
+    const Inst I = m.inst[ii];
+    const int64_t local = it - I.item_base;
+    int32_t r = -1;
+    if (local < int64_t(I.N) * I.s) {
+      const int j = int(local >> I.hbits);
+      const int c = m.col[it];
+      int p;
+      if (qbs(m.col + I.item_base + int64_t(c) * I.s, I.s, j, p)) r = p;
+    }
+    rev[it] = r;
+  }
+}
 
 // ----------------------------------------------------------------- adjoint sweep step
-// One reverse step of the gradient: both the recomputed state Psi_t and the
-// adjoint state Lambda_t (each kept S-conjugated, so that W^dagger acts as W)
+// One reverse step of the gradient: the recomputed state Psi_t and the
+// adjoint state Lambda_t (both kept S-conjugated, so that W^dagger acts as W)
 // advance by one walk step, and every slot (j, l) accumulates
 //   dL/dv_{jl} += 2 Re[ (2/s) ( c (conj(mu_0) f' + conj(mu_1) g')
 //                              + conj(d) (conj(f') psi'_0 + g' psi'_1) ) ]
-// where chi, mu are the slot amplitudes of Psi_t and Lambda_t, c, d their
-// group sums, and psi' = (2/s) c phi - chi the forward state before the
-// reflection of step t.
+// with chi, mu the group amplitudes of Psi_t and Lambda_t, c, d their group
+// sums, and psi' = (2/s) c phi - chi the forward state before the reflection
+// of step t.
 
 extern "C" __global__ void __launch_bounds__(256) qwk_adjoint(AdjArgs a) {
-  const int lane = threadIdx.x & (kWave - 1);
+  __shared__ unsigned long long sh[16];
   const int n = a.m.nbits;
   const int64_t A = a.m.items;
-  const uint32_t B = min(*a.in.cnt, a.in.cap);
-  const uint32_t BL = min(*a.lin.cnt, a.lin.cap);
-  const int64_t padB = (int64_t(B) + kWave - 1) & ~int64_t(kWave - 1);
-  const int64_t padBL = (int64_t(BL) + kWave - 1) & ~int64_t(kWave - 1);
-  const int64_t total = A + padB + padBL;
-  unsigned long long kept = 0, lkept = 0;
-  bool overflow = false, loverflow = false;
+  const int64_t padL = (int64_t(a.L.cnt) + kWave - 1) & ~int64_t(kWave - 1);
+  const int64_t padLL = (int64_t(a.LL.cnt) + kWave - 1) & ~int64_t(kWave - 1);
+  const int64_t total = A + padL + padLL;
+  unsigned cnt = 0, lcnt = 0;
   const int64_t stride = int64_t(gridDim.x) * blockDim.x;
   for (int64_t it = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; it < total; it += stride) {
     if (it < A) {
-      const int ii = __builtin_amdgcn_readfirstlane(find_inst(a.m, it - lane));
-      const Inst I = a.m.inst[ii];
-      const int64_t local = it - I.item_base;
-      const bool live = local < int64_t(I.N) * I.s;
-      const int l = int(local) & (I.s - 1);
-      const int j = int(local >> I.hbits);
-      double2 x0 = make_double2(0.0, 0.0), x1 = x0, m0 = x0, m1 = x0;
+      const Item x = item_of(a.m, it);
+      double2 x0 = zero2(), x1 = zero2(), m0 = zero2(), m1 = zero2();
+      double2 y0 = zero2(), y1 = zero2(), z0 = zero2(), z1 = zero2();
       Rot r, d;
-      r.f = x0;
+      r.f = zero2();
       r.g = 0.0;
       d = r;
-      int colq = 0;
-      if (live) {
+      int colq = 0, pr = -1;
+      if (x.live) {
         x0 = a.in.R[2 * it];
         x1 = a.in.R[2 * it + 1];
         m0 = a.lin.R[2 * it];
         m1 = a.lin.R[2 * it + 1];
-        a.in.R[2 * it] = make_double2(0.0, 0.0);
-        a.in.R[2 * it + 1] = make_double2(0.0, 0.0);
-        a.lin.R[2 * it] = make_double2(0.0, 0.0);
-        a.lin.R[2 * it + 1] = make_double2(0.0, 0.0);
+        y1 = a.in.Q[2 * it + 1];
+        z1 = a.lin.Q[2 * it + 1];
         colq = a.m.col[it];
+        pr = a.m.rev[it];
+        if (pr < 0) {
+          y0 = a.in.Q[2 * it];
+          z0 = a.lin.Q[2 * it];
+        }
         const double v = a.m.val[it];
-        r = rotation(v, j, colq);
-        d = rotation_deriv(v, j, colq);
+        r = rotation(v, x.j, colq);
+        d = rotation_deriv(v, x.j, colq);
       }
-      const double2 c = group_sum(cadd(cjmul(r.f, x0), cscale(x1, r.g)), I.s);
-      const double2 dd = group_sum(cadd(cjmul(r.f, m0), cscale(m1, r.g)), I.s);
-      const double t = 2.0 / double(I.s);
+      const double2 c = group_sum(cadd(cjmul(r.f, x0), cscale(x1, r.g)), x.I.s);
+      const double2 dd = group_sum(cadd(cjmul(r.f, m0), cscale(m1, r.g)), x.I.s);
+      const double t = 2.0 / double(x.I.s);
       const double2 tc = cscale(c, t), td = cscale(dd, t);
-      const double2 q0 = csub(cmul(tc, r.f), x0);  // psi'
-      const double2 q1 = csub(cscale(tc, r.g), x1);
-      const double2 w0 = csub(cmul(td, r.f), m0);  // reflected adjoint
-      const double2 w1 = csub(cscale(td, r.g), m1);
-      if (live) {
+      double2 q0 = csub(cmul(tc, r.f), x0);  // psi'
+      double2 q1 = csub(cscale(tc, r.g), x1);
+      double2 w0 = csub(cmul(td, r.f), m0);  // reflected adjoint
+      double2 w1 = csub(cscale(td, r.g), m1);
+      if (x.live) {
         // c (conj(mu_0) f' + conj(mu_1) g') + conj(d) (conj(f') psi'_0 + g' psi'_1)
         const double2 u = cadd(cmul(c, cadd(cjmul(m0, d.f), make_double2(m1.x * d.g, -m1.y * d.g))),
                                cjmul(dd, cadd(cjmul(d.f, q0), cscale(q1, d.g))));
         a.dv[it] += 2.0 * t * u.x;
-      }
-      const uint64_t kbase = (uint64_t(ii) << (4 * n + 2)) | (uint64_t(colq) << (2 * n + 2)) | (uint64_t(j) << 1);
-      const uint64_t kb1 = kbase | (uint64_t(1) << (2 * n + 1));
-      int p = 0;
-      const bool found = live && qbs(a.m.col + I.item_base + int64_t(colq) * I.s, I.s, j, p);
-      const int64_t dst = 2 * (I.item_base + int64_t(colq) * I.s + p);
-      // recomputed state
-      {
-        const bool keep0 = live && nonzero_tau(q0, a.tau);
-        const bool keep1 = live && nonzero_tau(q1, a.tau);
-        bool app0 = false;
-        if (keep0) {
-          if (found)
-            a.out.R[dst] = q0;
-          else
-            app0 = true;
-        }
-        kept += unsigned(keep0) + unsigned(keep1);
-        wave_append(a.out, a.cap, app0, kbase, q0, keep1, kb1, q1, overflow);
-      }
-      // adjoint state
-      {
-        const bool keep0 = live && nonzero_tau(w0, a.tau);
-        const bool keep1 = live && nonzero_tau(w1, a.tau);
-        bool app0 = false;
-        if (keep0) {
-          if (found)
-            a.lout.R[dst] = w0;
-          else
-            app0 = true;
-        }
-        lkept += unsigned(keep0) + unsigned(keep1);
-        wave_append(a.lout, a.cap, app0, kbase, w0, keep1, kb1, w1, loverflow);
+        q0 = prune(q0, a.tau, cnt);
+        q1 = prune(q1, a.tau, cnt);
+        const double2 ny1 = prune(cneg(y1), a.tau, cnt);
+        const double2 ny0 = pr < 0 ? prune(cneg(y0), a.tau, cnt) : zero2();
+        write_slot(a.out, x, it, colq, pr, q0, q1, ny0, ny1);
+        w0 = prune(w0, a.tau, lcnt);
+        w1 = prune(w1, a.tau, lcnt);
+        const double2 nz1 = prune(cneg(z1), a.tau, lcnt);
+        const double2 nz0 = pr < 0 ? prune(cneg(z0), a.tau, lcnt) : zero2();
+        write_slot(a.lout, x, it, colq, pr, w0, w1, nz0, nz1);
       }
     } else {
-      const bool second = it >= A + padB;
-      const int64_t e = second ? it - A - padB : it - A;
-      const Buf& src = second ? a.lin : a.in;
-      const Buf& dst = second ? a.lout : a.out;
-      const uint32_t cnt = second ? BL : B;
-      bool app = false;
-      uint64_t kk = 0;
-      double2 v = make_double2(0.0, 0.0);
-      if (e < int64_t(cnt)) {
-        v = src.amp[e];
-        v = make_double2(-v.x, -v.y);
-        if (nonzero_tau(v, a.tau)) {
-          (second ? lkept : kept) += 1;
-          kk = swap_halves(src.key[e], n);
-          int64_t slot;
-          int b2;
-          if (home_slot(a.m, kk, slot, b2))
-            dst.R[2 * slot + b2] = v;
-          else
-            app = true;
-        }
+      const bool second = it >= A + padL;
+      const int64_t e = second ? it - A - padL : it - A;
+      const List& Ls = second ? a.LL : a.L;
+      if (e < int64_t(Ls.cnt)) {
+        const double2 v = cneg(Ls.amp[e]);
+        Ls.amp[e] = v;
+        Ls.key[e] = swap_halves(Ls.key[e], n);
+        (second ? lcnt : cnt) += nonzero(v);
       }
-      // `second` is wave-uniform (the list ranges are wave aligned)
-      wave_append(dst, a.cap, app, kk, v, false, 0, v, second ? loverflow : overflow);
     }
   }
-  finish_launch(a.lctl, a.lin.cnt, lkept, loverflow);
-  finish_launch(a.ctl, a.in.cnt, kept, overflow);
+  const unsigned long long t1 = block_sum_u64(cnt, sh);
+  if (threadIdx.x == 0) a.acc[blockIdx.x] += t1;
+  const unsigned long long t2 = block_sum_u64(lcnt, sh);
+  if (threadIdx.x == 0) a.lacc[blockIdx.x] += t2;
 }
-
 
 // ----------------------------------------------------------------- T~ |b~>
 // T~ on |0, j, 0, 0, 0, 0> gives the group of j with amplitudes b_j phi_j:
 // slot (j, l) receives b_j f/sqrt(s) and b_j g/sqrt(s) (Alg. 5).
 
-extern "C" __global__ void __launch_bounds__(256) qwk_init(Matrix m, const double2* __restrict__ b, Buf out, double tau) {
+extern "C" __global__ void __launch_bounds__(256) qwk_init(Matrix m, const double2* __restrict__ b, Slots out,
+                                                           double tau) {
   const int64_t stride = int64_t(gridDim.x) * blockDim.x;
   for (int64_t it = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; it < m.items; it += stride) {
     const int ii = find_inst(m, it);
@@ -471,13 +412,12 @@ extern "C" __global__ void __launch_bounds__(256) qwk_init(Matrix m, const doubl
     const double2 bj = cscale(b[I.jbase + j], I.inv_sqrt_s);
     double2 o0 = cmul(r.f, bj);
     double2 o1 = cscale(bj, r.g);
-    if (!nonzero_tau(o0, tau)) o0 = make_double2(0.0, 0.0);
-    if (!nonzero_tau(o1, tau)) o1 = make_double2(0.0, 0.0);
+    if (!kept(o0, tau)) o0 = zero2();
+    if (!kept(o1, tau)) o1 = zero2();
     out.R[2 * it] = o0;
     out.R[2 * it + 1] = o1;
   }
 }
-
 
 // ----------------------------------------------------------------- fill (zero)
 
@@ -487,69 +427,68 @@ extern "C" __global__ void qwk_fill(uint4* p, int64_t n16) {
     p[i] = make_uint4(0u, 0u, 0u, 0u);
 }
 
-
 // ----------------------------------------------------------------- measurements
 
-__device__ __forceinline__ double block_sum(double v, double* sh) {
-  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
-  const int w = threadIdx.x >> 6;
-  __syncthreads();
-  if ((threadIdx.x & 63) == 0) sh[w] = v;
-  __syncthreads();
-  double t = 0.0;
-  if (threadIdx.x == 0)
-    for (int i = 0; i < int(blockDim.x >> 6); ++i) t += sh[i];
-  return t;
-}
-
-// kind 0: count, 1: norm^2 -> partial[block]; kind 2: j marginal (R part
-// stored, list part added atomically); kind 3: projection.
-extern "C" __global__ void __launch_bounds__(256) qwk_measure(Matrix m, Buf b, int32_t kind, double* partial, double* out) {
+// kind 0: count, 1: norm^2 -> partial[block]; kind 2: j marginal (atomics
+// into out, which starts at zero); kind 3: projection (stored).
+extern "C" __global__ void __launch_bounds__(256) qwk_measure(Matrix m, Slots st, List L, int32_t kind,
+                                                              double* partial, double* out) {
   __shared__ double sh[16];
-  const int lane = threadIdx.x & (kWave - 1);
   const int n = m.nbits;
-  const uint32_t B = min(*b.cnt, b.cap);
-  const int64_t padA = m.items;
-  const int64_t total = padA + ((int64_t(B) + kWave - 1) & ~int64_t(kWave - 1));
+  const uint64_t nm = (uint64_t(1) << n) - 1;
+  const int64_t total = m.items + ((int64_t(L.cnt) + kWave - 1) & ~int64_t(kWave - 1));
   double acc = 0.0;
   const int64_t stride = int64_t(gridDim.x) * blockDim.x;
   for (int64_t it = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; it < total; it += stride) {
-    if (it < padA) {
-      const int ii = __builtin_amdgcn_readfirstlane(find_inst(m, it - lane));
-      const Inst I = m.inst[ii];
-      const int64_t local = it - I.item_base;
-      const bool live = local < int64_t(I.N) * I.s;
-      const int l = int(local) & (I.s - 1);
-      const int j = int(local >> I.hbits);
-      double2 p0 = make_double2(0.0, 0.0), p1 = p0;
-      if (live) {
-        p0 = b.R[2 * it];
-        p1 = b.R[2 * it + 1];
+    if (it < m.items) {
+      const Item x = item_of(m, it);
+      double2 p0 = zero2(), p1 = zero2(), s0 = zero2(), s1 = zero2();
+      int colq = 0;
+      if (x.live) {
+        p0 = st.R[2 * it];
+        p1 = st.R[2 * it + 1];
+        s0 = st.Q[2 * it];
+        s1 = st.Q[2 * it + 1];
+        colq = m.col[it];
       }
       if (kind == 0) {
-        acc += double((p0.x != 0.0 || p0.y != 0.0) + (p1.x != 0.0 || p1.y != 0.0));
+        acc += double(int(nonzero(p0)) + int(nonzero(p1)) + int(nonzero(s0)) + int(nonzero(s1)));
       } else if (kind == 1) {
-        acc += p0.x * p0.x + p0.y * p0.y + p1.x * p1.x + p1.y * p1.y;
+        acc += p0.x * p0.x + p0.y * p0.y + p1.x * p1.x + p1.y * p1.y + s0.x * s0.x + s0.y * s0.y + s1.x * s1.x +
+               s1.y * s1.y;
       } else if (kind == 2) {
         double2 q = make_double2(p0.x * p0.x + p0.y * p0.y + p1.x * p1.x + p1.y * p1.y, 0.0);
-        q = group_sum(q, I.s);
-        if (live && l == 0) out[I.jbase + j] = q.x;
+        q = group_sum(q, x.I.s);
+        if (x.live) {
+          if (x.l == 0) atomicAdd(&out[x.I.jbase + x.j], q.x);
+          const double sw = s0.x * s0.x + s0.y * s0.y + s1.x * s1.x + s1.y * s1.y;
+          if (sw != 0.0) atomicAdd(&out[x.I.jbase + colq], sw);
+        }
       } else {
         Rot r;
-        r.f = make_double2(0.0, 0.0);
+        r.f = zero2();
         r.g = 0.0;
-        if (live) r = rotation(m.val[it], j, m.col[it]);
-        double2 c = group_sum(cadd(cjmul(r.f, p0), cscale(p1, r.g)), I.s);
-        if (live && l == 0) {
-          out[2 * (I.jbase + j)] = c.x * I.inv_sqrt_s;
-          out[2 * (I.jbase + j) + 1] = c.y * I.inv_sqrt_s;
+        if (x.live) r = rotation(m.val[it], x.j, colq);
+        const double2 c = group_sum(cadd(cjmul(r.f, p0), cscale(p1, r.g)), x.I.s);
+        if (x.live && x.l == 0) {
+          out[2 * (x.I.jbase + x.j)] = c.x * x.I.inv_sqrt_s;
+          out[2 * (x.I.jbase + x.j) + 1] = c.y * x.I.inv_sqrt_s;
         }
       }
-    } else if (kind <= 1) {
-      const int64_t e = it - padA;
-      if (e < int64_t(B)) {
-        const double2 v = b.amp[e];
-        acc += kind == 0 ? 1.0 : v.x * v.x + v.y * v.y;
+    } else {
+      const int64_t e = it - m.items;
+      if (e < int64_t(L.cnt)) {
+        const double2 v = L.amp[e];
+        if (kind == 0) {
+          acc += double(nonzero(v));
+        } else if (kind == 1) {
+          acc += v.x * v.x + v.y * v.y;
+        } else if (kind == 2) {
+          const uint64_t key = L.key[e];
+          const uint64_t inst = key >> (4 * n + 2);
+          const int j = int((key >> (2 * n + 2)) & nm);
+          if (inst < uint64_t(m.ninst)) atomicAdd(&out[m.inst[inst].jbase + j], v.x * v.x + v.y * v.y);
+        }
       }
     }
   }
@@ -559,180 +498,194 @@ extern "C" __global__ void __launch_bounds__(256) qwk_measure(Matrix m, Buf b, i
   }
 }
 
-// list part of the j marginal
-extern "C" __global__ void __launch_bounds__(256) qwk_marginal_list(Matrix m, Buf b, double* out) {
-  const int n = m.nbits;
-  const uint64_t nm = (uint64_t(1) << n) - 1;
-  const uint32_t B = min(*b.cnt, b.cap);
-  const int64_t stride = int64_t(gridDim.x) * blockDim.x;
-  for (int64_t e = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; e < int64_t(B); e += stride) {
-    const uint64_t key = b.key[e];
-    const double2 v = b.amp[e];
-    const uint64_t inst = key >> (4 * n + 2);
-    if (inst >= uint64_t(m.ninst)) continue;
-    const int j = int((key >> (2 * n + 2)) & nm);
-    atomicAdd(&out[m.inst[inst].jbase + j], v.x * v.x + v.y * v.y);
+// ----------------------------------------------------------------- export / import
+
+// Wave-level compacted append of up to four values per lane.
+__device__ __forceinline__ void wave_append4(uint64_t* keys, double2* amps, uint32_t* count, uint32_t cap,
+                                             const bool* app, const uint64_t* k, const double2* v) {
+  const int lane = threadIdx.x & (kWave - 1);
+  const uint64_t lt = (uint64_t(1) << lane) - 1;
+  uint64_t mk[4];
+  uint32_t nk[4], tot = 0;
+  for (int i = 0; i < 4; ++i) {
+    mk[i] = __ballot(app[i]);
+    nk[i] = __popcll(mk[i]);
+    tot += nk[i];
+  }
+  if (tot == 0) return;
+  uint32_t base = 0;
+  if (lane == 0) base = atomicAdd(count, tot);
+  base = __shfl(base, 0);
+  for (int i = 0; i < 4; ++i) {
+    if (app[i]) {
+      const uint32_t idx = base + __popcll(mk[i] & lt);
+      if (idx < cap) {
+        keys[idx] = k[i];
+        amps[idx] = v[i];
+      }
+    }
+    base += nk[i];
   }
 }
 
-
-// ----------------------------------------------------------------- export / import
-
-extern "C" __global__ void __launch_bounds__(256) qwk_export(Matrix m, Buf b, uint64_t* keys, double2* amps, uint32_t* count,
-                                                     uint32_t cap) {
-  const int lane = threadIdx.x & (kWave - 1);
+extern "C" __global__ void __launch_bounds__(256) qwk_export(Matrix m, Slots st, List L, uint64_t* keys,
+                                                             double2* amps, uint32_t* count, uint32_t cap) {
   const int n = m.nbits;
-  const uint32_t B = min(*b.cnt, b.cap);
-  const int64_t total = m.items + ((int64_t(B) + kWave - 1) & ~int64_t(kWave - 1));
-  Buf out;
-  out.key = keys;
-  out.amp = amps;
-  out.cnt = count;
-  out.cap = cap;
-  out.R = nullptr;
-  bool overflow = false;
+  const int64_t total = m.items + ((int64_t(L.cnt) + kWave - 1) & ~int64_t(kWave - 1));
   const int64_t stride = int64_t(gridDim.x) * blockDim.x;
   for (int64_t it = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; it < total; it += stride) {
-    bool a0 = false, a1 = false;
-    uint64_t k0 = 0, k1 = 0;
-    double2 v0 = make_double2(0.0, 0.0), v1 = v0;
+    bool app[4] = {false, false, false, false};
+    uint64_t k[4] = {0, 0, 0, 0};
+    double2 v[4] = {zero2(), zero2(), zero2(), zero2()};
     if (it < m.items) {
-      const int ii = __builtin_amdgcn_readfirstlane(find_inst(m, it - lane));
-      const Inst I = m.inst[ii];
-      const int64_t local = it - I.item_base;
-      if (local < int64_t(I.N) * I.s) {
-        const int j = int(local >> I.hbits);
+      const Item x = item_of(m, it);
+      if (x.live) {
         const int colq = m.col[it];
-        v0 = b.R[2 * it];
-        v1 = b.R[2 * it + 1];
-        a0 = v0.x != 0.0 || v0.y != 0.0;
-        a1 = v1.x != 0.0 || v1.y != 0.0;
-        k0 = slot_key(uint64_t(ii), n, j, colq, 0);
-        k1 = slot_key(uint64_t(ii), n, j, colq, 1);
+        for (int b2 = 0; b2 < 2; ++b2) {
+          v[b2] = st.R[2 * it + b2];
+          app[b2] = nonzero(v[b2]);
+          k[b2] = member_key(uint64_t(x.inst), n, x.j, colq, b2);
+          v[2 + b2] = st.Q[2 * it + b2];
+          app[2 + b2] = nonzero(v[2 + b2]);
+          k[2 + b2] = swapped_key(uint64_t(x.inst), n, x.j, colq, b2);
+        }
       }
     } else {
       const int64_t e = it - m.items;
-      if (e < int64_t(B)) {
-        a0 = true;
-        k0 = b.key[e];
-        v0 = b.amp[e];
+      if (e < int64_t(L.cnt)) {
+        v[0] = L.amp[e];
+        k[0] = L.key[e];
+        app[0] = nonzero(v[0]);
       }
     }
-    wave_append(out, cap, a0, k0, v0, a1, k1, v1, overflow);
+    wave_append4(keys, amps, count, cap, app, k, v);
   }
 }
 
+// Home of a key: 0 = R (group member), 1 = Q (swap of a member), 2 = list.
+__device__ __forceinline__ int home_of(const Matrix& m, uint64_t key, int64_t& idx) {
+  const int n = m.nbits;
+  const uint64_t nm = (uint64_t(1) << n) - 1;
+  const int b2 = int(key & 1);
+  const int k = int((key >> 1) & nm);
+  const uint64_t kc = (key >> (n + 1)) & nm;
+  const int b1 = int((key >> (2 * n + 1)) & 1);
+  const int j = int((key >> (2 * n + 2)) & nm);
+  const uint64_t jc = (key >> (3 * n + 2)) & nm;
+  const uint64_t inst = key >> (4 * n + 2);
+  if (jc != 0 || kc != 0 || inst >= uint64_t(m.ninst)) return 2;
+  const Inst I = m.inst[inst];
+  if (j >= I.N || k >= I.N) return 2;
+  int p;
+  if (b1 == 0 && qbs(m.col + I.item_base + int64_t(j) * I.s, I.s, k, p)) {
+    idx = 2 * (I.item_base + int64_t(j) * I.s + p) + b2;
+    return 0;
+  }
+  // (0, J, B1, 0, K, 0) = S K(q, B1) with q = (K, position of J in row K)
+  if (b2 == 0 && qbs(m.col + I.item_base + int64_t(k) * I.s, I.s, j, p)) {
+    idx = 2 * (I.item_base + int64_t(k) * I.s + p) + b1;
+    return 1;
+  }
+  return 2;
+}
 
-// Place branches (unique keys, validated on the host) at their homes.
-extern "C" __global__ void __launch_bounds__(256) qwk_import(Matrix m, const uint64_t* keys, const double2* amps, int64_t cnt,
-                                                     Buf out, Ctl* ctl, uint32_t cap) {
-  bool overflow = false;
+extern "C" __global__ void __launch_bounds__(256) qwk_import(Matrix m, const uint64_t* keys, const double2* amps,
+                                                             int64_t cnt, Slots out, List L, uint32_t* lcnt) {
   const int64_t stride = int64_t(gridDim.x) * blockDim.x;
   const int64_t total = (cnt + kWave - 1) & ~int64_t(kWave - 1);
   for (int64_t e = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; e < total; e += stride) {
-    bool app = false;
-    uint64_t key = 0;
-    double2 v = make_double2(0.0, 0.0);
+    bool app[4] = {false, false, false, false};
+    uint64_t k[4] = {0, 0, 0, 0};
+    double2 v[4] = {zero2(), zero2(), zero2(), zero2()};
     if (e < cnt) {
-      key = keys[e];
-      v = amps[e];
-      int64_t slot;
-      int b2;
-      if (home_slot(m, key, slot, b2))
-        out.R[2 * slot + b2] = v;
+      k[0] = keys[e];
+      v[0] = amps[e];
+      int64_t idx = 0;
+      const int h = home_of(m, k[0], idx);
+      if (h == 0)
+        out.R[idx] = v[0];
+      else if (h == 1)
+        out.Q[idx] = v[0];
       else
-        app = true;
+        app[0] = true;
     }
-    wave_append(out, cap, app, key, v, false, 0, v, overflow);
+    wave_append4(L.key, L.amp, lcnt, L.cap, app, k, v);
   }
-  if (__ballot(overflow) != 0 && (threadIdx.x & 63) == 0) atomicOr(&ctl->overflow, 1u);
 }
-
 
 // ----------------------------------------------------------------- gradient set-up and finish
 
 // Lambda = diag(w[k register]) Psi for a state kept S-conjugated (the j
 // register of the true state is the k register of the stored one), and the
-// loss sum_branches w |amp|^2 as per-block partials.
-extern "C" __global__ void __launch_bounds__(256) qwk_weight(Matrix m, Buf in, Buf out, const double* w, uint32_t cap,
-                                                     double* partial) {
+// loss sum_branches w |amp|^2 as per-block partials.  K(q, b2) has k = col[q];
+// S K(q, b2) has k = j.
+extern "C" __global__ void __launch_bounds__(256) qwk_weight(Matrix m, Slots in, List L, Slots out, List LL,
+                                                             const double* w, double* partial) {
   __shared__ double sh[16];
-  const int lane = threadIdx.x & (kWave - 1);
   const int n = m.nbits;
   const uint64_t nm = (uint64_t(1) << n) - 1;
-  const uint32_t B = min(*in.cnt, in.cap);
-  const int64_t total = m.items + ((int64_t(B) + kWave - 1) & ~int64_t(kWave - 1));
+  const int64_t total = m.items + ((int64_t(L.cnt) + kWave - 1) & ~int64_t(kWave - 1));
   double acc = 0.0;
-  bool overflow = false;
   const int64_t stride = int64_t(gridDim.x) * blockDim.x;
   for (int64_t it = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; it < total; it += stride) {
-    bool app = false;
-    uint64_t key = 0;
-    double2 v = make_double2(0.0, 0.0);
     if (it < m.items) {
-      const int ii = __builtin_amdgcn_readfirstlane(find_inst(m, it - lane));
-      const Inst I = m.inst[ii];
-      const int64_t local = it - I.item_base;
-      if (local < int64_t(I.N) * I.s) {
-        const double wk = w[I.jbase + m.col[it]];
-        const double2 p0 = in.R[2 * it], p1 = in.R[2 * it + 1];
-        acc += wk * (p0.x * p0.x + p0.y * p0.y + p1.x * p1.x + p1.y * p1.y);
-        out.R[2 * it] = cscale(p0, wk);
-        out.R[2 * it + 1] = cscale(p1, wk);
+      const Item x = item_of(m, it);
+      if (x.live) {
+        const double wr = w[x.I.jbase + m.col[it]];
+        const double wq = w[x.I.jbase + x.j];
+        for (int b2 = 0; b2 < 2; ++b2) {
+          const double2 p = in.R[2 * it + b2];
+          const double2 s = in.Q[2 * it + b2];
+          acc += wr * (p.x * p.x + p.y * p.y) + wq * (s.x * s.x + s.y * s.y);
+          out.R[2 * it + b2] = cscale(p, wr);
+          out.Q[2 * it + b2] = cscale(s, wq);
+        }
       }
     } else {
       const int64_t e = it - m.items;
-      if (e < int64_t(B)) {
-        key = in.key[e];
-        const double2 p = in.amp[e];
+      if (e < int64_t(L.cnt)) {
+        const uint64_t key = L.key[e];
+        const double2 p = L.amp[e];
         const uint64_t inst = key >> (4 * n + 2);
         const int k = int((key >> 1) & nm);
         const double wk = inst < uint64_t(m.ninst) ? w[m.inst[inst].jbase + k] : 0.0;
         acc += wk * (p.x * p.x + p.y * p.y);
-        v = cscale(p, wk);
-        app = wk != 0.0;
+        LL.key[e] = key;
+        LL.amp[e] = cscale(p, wk);
       }
     }
-    wave_append(out, cap, app, key, v, false, 0, v, overflow);
   }
   const double t = block_sum(acc, sh);
   if (threadIdx.x == 0) partial[blockIdx.x] = t;
 }
 
-
 // Gradient through the initial T~: psi_0 holds b_j phi_j in the group of j,
 // so dL/dv_{jl} += 2 Re[b_j (conj(nu_0) f' + conj(nu_1) g')] / sqrt(s) with
-// nu the slot amplitudes of lambda_0, and dL/db_j = 2 <psi~_j|lambda_0>.
-extern "C" __global__ void __launch_bounds__(256) qwk_grad_init(Matrix m, Buf lam, const double2* b, double* dv, double2* db) {
-  const int lane = threadIdx.x & (kWave - 1);
+// nu the group amplitudes of lambda_0, and dL/db_j = 2 <psi~_j|lambda_0>.
+extern "C" __global__ void __launch_bounds__(256) qwk_grad_init(Matrix m, Slots lam, const double2* b, double* dv,
+                                                                double2* db) {
   const int64_t stride = int64_t(gridDim.x) * blockDim.x;
   for (int64_t it = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; it < m.items; it += stride) {
-    const int ii = __builtin_amdgcn_readfirstlane(find_inst(m, it - lane));
-    const Inst I = m.inst[ii];
-    const int64_t local = it - I.item_base;
-    const bool live = local < int64_t(I.N) * I.s;
-    const int l = int(local) & (I.s - 1);
-    const int j = int(local >> I.hbits);
-    double2 n0 = make_double2(0.0, 0.0), n1 = n0, bj = n0;
+    const Item x = item_of(m, it);
+    double2 n0 = zero2(), n1 = zero2();
     Rot r, d;
-    r.f = n0;
+    r.f = zero2();
     r.g = 0.0;
     d = r;
-    if (live) {
+    if (x.live) {
       n0 = lam.R[2 * it];
       n1 = lam.R[2 * it + 1];
       const int colq = m.col[it];
       const double v = m.val[it];
-      r = rotation(v, j, colq);
-      d = rotation_deriv(v, j, colq);
-      bj = b[I.jbase + j];
+      r = rotation(v, x.j, colq);
+      d = rotation_deriv(v, x.j, colq);
+      const double2 bj = b[x.I.jbase + x.j];
       const double2 u = cmul(bj, cadd(cjmul(n0, d.f), make_double2(n1.x * d.g, -n1.y * d.g)));
-      dv[it] += 2.0 * u.x * I.inv_sqrt_s;
+      dv[it] += 2.0 * u.x * x.I.inv_sqrt_s;
     }
-    const double2 c = group_sum(cadd(cjmul(r.f, n0), cscale(n1, r.g)), I.s);
-    if (live && l == 0) db[I.jbase + j] = cscale(c, 2.0 * I.inv_sqrt_s);
+    const double2 c = group_sum(cadd(cjmul(r.f, n0), cscale(n1, r.g)), x.I.s);
+    if (x.live && x.l == 0) db[x.I.jbase + x.j] = cscale(c, 2.0 * x.I.inv_sqrt_s);
   }
 }
-
 
 }  // namespace qw

@@ -24,10 +24,10 @@ enum Fn {
   F_STEP,
   F_STEP_ACC,
   F_ADJOINT,
+  F_QBS_TABLE,
   F_INIT,
   F_FILL,
   F_MEASURE,
-  F_MARGINAL_LIST,
   F_EXPORT,
   F_IMPORT,
   F_WEIGHT,
@@ -35,9 +35,9 @@ enum Fn {
   F_COUNT
 };
 
-const char* const kNames[F_COUNT] = {"qwk_step",   "qwk_step_acc", "qwk_adjoint", "qwk_init",
-                                     "qwk_fill",   "qwk_measure",  "qwk_marginal_list", "qwk_export",
-                                     "qwk_import", "qwk_weight",   "qwk_grad_init"};
+const char* const kNames[F_COUNT] = {"qwk_step", "qwk_step_acc", "qwk_adjoint", "qwk_qbs_table",
+                                     "qwk_init", "qwk_fill",     "qwk_measure", "qwk_export",
+                                     "qwk_import", "qwk_weight", "qwk_grad_init"};
 
 constexpr int kMaxDevices = 64;
 
@@ -103,8 +103,13 @@ hipError_t launch_adjoint(const AdjArgs& a, int grid, int block, hipStream_t str
   return launch(F_ADJOINT, grid, block, stream, p);
 }
 
-hipError_t launch_init(const Matrix& m, const double2* b, Buf out, Ctl*, uint32_t, int32_t, double tau,
-                       hipStream_t stream) {
+hipError_t launch_qbs_table(const Matrix& m, int32_t* rev, hipStream_t stream) {
+  Matrix mm = m;
+  void* p[] = {&mm, &rev};
+  return launch(F_QBS_TABLE, clamp_grid(m.items, 4096), 256, stream, p);
+}
+
+hipError_t launch_init(const Matrix& m, const double2* b, Slots out, double tau, hipStream_t stream) {
   Matrix mm = m;
   const double2* bb = b;
   double t = tau;
@@ -120,43 +125,40 @@ hipError_t launch_fill(void* ptr, int64_t bytes, hipStream_t stream) {
   return launch(F_FILL, clamp_grid(n16, 4096), 256, stream, p);
 }
 
-hipError_t launch_measure(const Matrix& m, Buf b, int32_t kind, double* partial, double* out, int grid,
+hipError_t launch_measure(const Matrix& m, Slots st, List L, int32_t kind, double* partial, double* out, int grid,
                           hipStream_t stream) {
   Matrix mm = m;
   int32_t k = kind;
-  void* p[] = {&mm, &b, &k, &partial, &out};
-  hipError_t e = launch(F_MEASURE, grid, 256, stream, p);
-  if (e != hipSuccess || kind != 2) return e;
-  void* q[] = {&mm, &b, &out};
-  return launch(F_MARGINAL_LIST, grid, 256, stream, q);
+  void* p[] = {&mm, &st, &L, &k, &partial, &out};
+  return launch(F_MEASURE, grid, 256, stream, p);
 }
 
-hipError_t launch_export(const Matrix& m, Buf b, uint64_t* keys, double2* amps, uint32_t* count, uint32_t cap,
-                         hipStream_t stream) {
+hipError_t launch_export(const Matrix& m, Slots st, List L, uint64_t* keys, double2* amps, uint32_t* count,
+                         uint32_t cap, hipStream_t stream) {
   Matrix mm = m;
-  void* p[] = {&mm, &b, &keys, &amps, &count, &cap};
+  void* p[] = {&mm, &st, &L, &keys, &amps, &count, &cap};
   return launch(F_EXPORT, 1024, 256, stream, p);
 }
 
-hipError_t launch_import(const Matrix& m, const uint64_t* keys, const double2* amps, int64_t n, Buf out, Ctl* ctl,
-                         uint32_t cap, hipStream_t stream) {
+hipError_t launch_import(const Matrix& m, const uint64_t* keys, const double2* amps, int64_t n, Slots out, List L,
+                         uint32_t* lcnt, hipStream_t stream) {
   Matrix mm = m;
   const uint64_t* k = keys;
   const double2* a = amps;
   int64_t cnt = n;
-  void* p[] = {&mm, &k, &a, &cnt, &out, &ctl, &cap};
+  void* p[] = {&mm, &k, &a, &cnt, &out, &L, &lcnt};
   return launch(F_IMPORT, clamp_grid(n, 2048), 256, stream, p);
 }
 
-hipError_t launch_weight(const Matrix& m, Buf in, Buf out, Ctl*, const double* w, uint32_t cap, double* partial,
+hipError_t launch_weight(const Matrix& m, Slots in, List L, Slots out, List LL, const double* w, double* partial,
                          int grid, hipStream_t stream) {
   Matrix mm = m;
   const double* ww = w;
-  void* p[] = {&mm, &in, &out, &ww, &cap, &partial};
+  void* p[] = {&mm, &in, &L, &out, &LL, &ww, &partial};
   return launch(F_WEIGHT, grid, 256, stream, p);
 }
 
-hipError_t launch_grad_init(const Matrix& m, Buf lam, const double2* b, double* dv, double2* db,
+hipError_t launch_grad_init(const Matrix& m, Slots lam, const double2* b, double* dv, double2* db,
                             hipStream_t stream) {
   Matrix mm = m;
   const double2* bb = b;

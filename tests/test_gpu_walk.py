@@ -112,7 +112,7 @@ def test_measurements(Q, oracle_mod):
     assert np.abs(st.j_marginal() - ost.j_marginal()).max() < 1e-14
     assert np.abs(st.project() - ost.project0()).max() < 1e-14
     stats = st.stats()
-    assert stats["steps"] == 9 and stats["overflow"] == 0
+    assert stats["launches"] == 9 and stats["branches"] == ost.count() and stats["list_count"] == 0
 
 
 def test_checkpoint_resume(Q, oracle_mod):
@@ -159,14 +159,34 @@ def test_empty_state(Q):
     assert k.size == 0
 
 
-def test_capacity_overflow_reported(Q):
-    csc = W.offset_matrix(256, 8, seed=2)
-    walk = Q.Walk(csc)
-    st = walk.state(W.uniform_b(256), capacity=100)
-    st.step(2)
-    with pytest.raises(Q.QwError) as ei:
-        st.count()
-    assert ei.value.code == -3
+def test_general_list_branches(Q, oracle_mod):
+    """Branches outside the span of the group members and their swaps (here
+    from an imported state with j_c, k_c != 0) live in the general list and
+    follow W exactly like in the oracle."""
+    csc = W.offset_matrix(64, 6, seed=31)
+    b = W.gaussian_b(64, seed=32)
+    walk, st, ost = _pair(Q, oracle_mod, csc, b)
+    st.step(3)
+    ost.step(3)
+    keys, amps = ost.export()
+    nb = walk.nbits
+    rng = np.random.default_rng(33)
+    s = walk.info[0]["s"]
+    extra = [Q.pack_key(nb, int(rng.integers(1, s)), int(rng.integers(64)), int(rng.integers(2)),
+                        int(rng.integers(s)), int(rng.integers(64)), int(rng.integers(2))) for _ in range(40)]
+    extra = np.unique(np.array(extra, np.uint64))
+    keys = np.concatenate([keys, extra])
+    amps = np.concatenate([amps, 0.01 * (rng.normal(size=extra.size) + 1j * rng.normal(size=extra.size))])
+    st.import_(keys, amps)
+    ost.import_(keys, amps)
+    assert st.stats()["list_count"] == extra.size
+    for t in range(1, 8):
+        st.step(1)
+        ost.step(1)
+        _check(st, ost, f"list step {t}")
+    st.step_adjoint(7)
+    ost.step_adjoint(7)
+    _check(st, ost, "list adjoint")
 
 
 def test_paper_scale_5_steps(Q, oracle_mod):
