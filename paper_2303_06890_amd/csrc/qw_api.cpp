@@ -101,8 +101,13 @@ struct qw_ctx {
     m.ninst = ninst;
     m.nbits = nbits;
     m.items = items;
+    m.inst0 = inst0;
+    m.smax = smax;
+    m.pad_ = 0;
     return m;
   }
+  qw::Inst inst0{};
+  int32_t smax = 1;
 };
 
 namespace {
@@ -145,7 +150,8 @@ void free_graphs(qw_state* st) {
 
 int step_grid(const qw_state* st) {
   if (st->grid > 0) return st->grid;
-  int64_t g = (st->ctx->items + st->block - 1) / st->block;
+  const int64_t lanes = st->ctx->items * (st->ctx->smax <= 32 ? 2 : 1);  // as in the step kernel
+  int64_t g = (lanes + st->block - 1) / st->block;
   g = std::max<int64_t>(1, std::min<int64_t>(g, 2048));
   return int(g);
 }
@@ -393,7 +399,9 @@ int load_impl(qw_ctx** out, int32_t ninst, const int32_t* n, const int64_t* colp
     dinst[i].hbits = hi.hbits;
     dinst[i].pad_ = 0;
     dinst[i].inv_sqrt_s = 1.0 / std::sqrt(double(hi.s));
+    ctx->smax = std::max(ctx->smax, hi.s);
   }
+  ctx->inst0 = dinst[0];
   ctx->col = static_cast<int32_t*>(ctx->alloc.get(sizeof(int32_t) * items));
   ctx->val = static_cast<double*>(ctx->alloc.get(sizeof(double) * items));
   ctx->rev = static_cast<int32_t*>(ctx->alloc.get(sizeof(int32_t) * items));

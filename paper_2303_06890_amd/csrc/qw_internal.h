@@ -55,6 +55,9 @@ struct Matrix {
   int32_t ninst;
   int32_t nbits;       // register width n of the key layout
   int64_t items;       // total ELL slots including alignment padding
+  Inst inst0;          // copy of inst[0] (used directly when ninst == 1)
+  int32_t smax;        // largest s over the instances
+  int32_t pad_;
 };
 
 enum Mode : int32_t { kStep = 0, kSwap = 1 };
@@ -89,9 +92,10 @@ struct AdjArgs {
 static_assert(sizeof(Inst) == 40 && offsetof(Inst, inv_sqrt_s) == 32, "Inst layout");
 static_assert(sizeof(Slots) == 16, "Slots layout");
 static_assert(sizeof(List) == 24 && offsetof(List, cap) == 20, "List layout");
-static_assert(sizeof(Matrix) == 48 && offsetof(Matrix, items) == 40, "Matrix layout");
-static_assert(sizeof(StepArgs) == 152 && offsetof(StepArgs, coefm) == 144, "StepArgs layout");
-static_assert(sizeof(AdjArgs) == 192 && offsetof(AdjArgs, dv) == 184, "AdjArgs layout");
+static_assert(sizeof(Matrix) == 96 && offsetof(Matrix, inst0) == 48 && offsetof(Matrix, smax) == 88,
+              "Matrix layout");
+static_assert(sizeof(StepArgs) == 200 && offsetof(StepArgs, coefm) == 192, "StepArgs layout");
+static_assert(sizeof(AdjArgs) == 240 && offsetof(AdjArgs, dv) == 232, "AdjArgs layout");
 
 // Launchers (qw_launch.cpp).  All enqueue on `stream` and allocate nothing.
 hipError_t launch_step(const StepArgs& a, int grid, int block, hipStream_t stream);

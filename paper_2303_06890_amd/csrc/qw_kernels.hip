@@ -156,11 +156,17 @@ struct Item {
   int j, l;
   bool live;
 };
-__device__ __forceinline__ Item item_of(const Matrix& m, int64_t it) {
+// `first` is the first slot of the lane's wavefront (a wavefront never
+// straddles two instances, so its instance is looked up once, uniformly).
+__device__ __forceinline__ Item item_of(const Matrix& m, int64_t it, int64_t first) {
   Item x;
-  const int lane = threadIdx.x & (kWave - 1);
-  x.inst = __builtin_amdgcn_readfirstlane(find_inst(m, it - lane));
-  x.I = m.inst[x.inst];
+  if (m.ninst == 1) {
+    x.inst = 0;
+    x.I = m.inst0;
+  } else {
+    x.inst = __builtin_amdgcn_readfirstlane(find_inst(m, first));
+    x.I = m.inst[x.inst];
+  }
   const int64_t local = it - x.I.item_base;
   x.live = local < int64_t(x.I.N) * x.I.s;
   x.l = int(local) & (x.I.s - 1);
@@ -207,12 +213,87 @@ __device__ __forceinline__ void write_slot(const Slots& out, const Item& x, int6
 
 // ----------------------------------------------------------------- walk step
 
+// One lane per slot and b2 (groups of 2s lanes, s <= 32).  The data loads of
+// a lane do not depend on each other or on the instance record: padding slots
+// hold zeros (col 0, val 0, rev -1), so every load is in bounds and issued at
+// once.
 template <bool ACC>
-__device__ __forceinline__ void step_body(StepArgs a) {
+__device__ __forceinline__ void step_pairs(const StepArgs& a, int64_t it, double coef, unsigned& cnt) {
+  const int64_t q = it >> 1;
+  const int b2 = int(it & 1);
+  const double2 x = a.in.R[it];
+  const double2 y = a.in.Q[it];
+  const int colq = a.m.col[q];
+  const double v = a.m.val[q];
+  const int pr = a.m.rev[q];
+  const Item xi = item_of(a.m, q, (it - (threadIdx.x & (kWave - 1))) >> 1);
+  const Rot r = rotation(v, xi.j, colq);
+  double2 o = x, n = y;
+  if (a.mode == kStep) {
+    const double2 part = b2 == 0 ? cjmul(r.f, x) : cscale(x, r.g);
+    const double2 c = group_sum(part, 2 * xi.I.s);
+    if (ACC && xi.live && xi.l == 0 && b2 == 0) {
+      double2 yv = a.yacc[xi.I.jbase + xi.j];
+      yv.x += coef * (c.x * xi.I.inv_sqrt_s);
+      yv.y += coef * (c.y * xi.I.inv_sqrt_s);
+      a.yacc[xi.I.jbase + xi.j] = yv;
+    }
+    const double2 tc = cscale(c, 2.0 / double(xi.I.s));
+    o = csub(b2 == 0 ? cmul(tc, r.f) : cscale(tc, r.g), x);
+    n = cneg(y);
+  }
+  if (!xi.live) return;
+  o = prune(o, a.tau, cnt);
+  if (b2 == 1) {
+    a.out.Q[it] = o;
+    a.out.R[it] = prune(n, a.tau, cnt);
+  } else if (pr >= 0) {
+    a.out.R[2 * (xi.I.item_base + int64_t(colq) * xi.I.s + pr)] = o;
+  } else {
+    a.out.Q[it] = o;
+    a.out.R[it] = prune(n, a.tau, cnt);
+  }
+}
+
+// One lane per slot (both b2), for s = 64 where a group fills a wavefront.
+template <bool ACC>
+__device__ __forceinline__ void step_slot(const StepArgs& a, int64_t it, double coef, unsigned& cnt) {
+  const double2 x0 = a.in.R[2 * it], x1 = a.in.R[2 * it + 1];
+  const double2 y0 = a.in.Q[2 * it], y1 = a.in.Q[2 * it + 1];
+  const int colq = a.m.col[it];
+  const double v = a.m.val[it];
+  const int pr = a.m.rev[it];
+  const Item x = item_of(a.m, it, it - (threadIdx.x & (kWave - 1)));
+  const Rot r = rotation(v, x.j, colq);
+  double2 o0 = x0, o1 = x1, n0 = y0, n1 = y1;
+  if (a.mode == kStep) {
+    const double2 c = group_sum(cadd(cjmul(r.f, x0), cscale(x1, r.g)), x.I.s);
+    if (ACC && x.live && x.l == 0) {
+      double2 yv = a.yacc[x.I.jbase + x.j];
+      yv.x += coef * (c.x * x.I.inv_sqrt_s);
+      yv.y += coef * (c.y * x.I.inv_sqrt_s);
+      a.yacc[x.I.jbase + x.j] = yv;
+    }
+    const double2 tc = cscale(c, 2.0 / double(x.I.s));
+    o0 = csub(cmul(tc, r.f), x0);
+    o1 = csub(cscale(tc, r.g), x1);
+    n0 = cneg(y0);
+    n1 = cneg(y1);
+  }
+  if (!x.live) return;
+  o0 = prune(o0, a.tau, cnt);
+  o1 = prune(o1, a.tau, cnt);
+  n1 = prune(n1, a.tau, cnt);
+  if (pr < 0) n0 = prune(n0, a.tau, cnt);
+  write_slot(a.out, x, it, colq, pr, o0, o1, n0, n1);
+}
+
+template <bool ACC>
+__device__ __forceinline__ void step_body(const StepArgs& a) {
   __shared__ unsigned long long sh[16];
-  const int64_t A = a.m.items;
+  const int lps = a.m.smax <= 32 ? 2 : 1;  // lanes per slot
+  const int64_t A = a.m.items * lps;
   const int64_t total = A + ((int64_t(a.L.cnt) + kWave - 1) & ~int64_t(kWave - 1));
-  const bool reflect = a.mode == kStep;
   const int n = a.m.nbits;
   double coef = 0.0;
   uint32_t stepno = 0;
@@ -224,48 +305,15 @@ __device__ __forceinline__ void step_body(StepArgs a) {
   const int64_t stride = int64_t(gridDim.x) * blockDim.x;
   for (int64_t it = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; it < total; it += stride) {
     if (it < A) {
-      const Item x = item_of(a.m, it);
-      double2 x0 = zero2(), x1 = zero2(), y0 = zero2(), y1 = zero2();
-      Rot r;
-      r.f = zero2();
-      r.g = 0.0;
-      int colq = 0, pr = -1;
-      if (x.live) {
-        x0 = a.in.R[2 * it];
-        x1 = a.in.R[2 * it + 1];
-        y1 = a.in.Q[2 * it + 1];
-        colq = a.m.col[it];
-        pr = a.m.rev[it];
-        if (pr < 0) y0 = a.in.Q[2 * it];
-        r = rotation(a.m.val[it], x.j, colq);
-      }
-      double2 o0 = x0, o1 = x1, n0 = y0, n1 = y1;
-      if (reflect) {
-        const double2 c = group_sum(cadd(cjmul(r.f, x0), cscale(x1, r.g)), x.I.s);
-        if (ACC && x.live && x.l == 0) {
-          double2 y = a.yacc[x.I.jbase + x.j];
-          y.x += coef * (c.x * x.I.inv_sqrt_s);
-          y.y += coef * (c.y * x.I.inv_sqrt_s);
-          a.yacc[x.I.jbase + x.j] = y;
-        }
-        const double2 tc = cscale(c, 2.0 / double(x.I.s));
-        o0 = csub(cmul(tc, r.f), x0);
-        o1 = csub(cscale(tc, r.g), x1);
-        n0 = cneg(y0);
-        n1 = cneg(y1);
-      }
-      if (x.live) {
-        o0 = prune(o0, a.tau, cnt);
-        o1 = prune(o1, a.tau, cnt);
-        n1 = prune(n1, a.tau, cnt);
-        if (pr < 0) n0 = prune(n0, a.tau, cnt);
-        write_slot(a.out, x, it, colq, pr, o0, o1, n0, n1);
-      }
+      if (lps == 2)
+        step_pairs<ACC>(a, it, coef, cnt);
+      else
+        step_slot<ACC>(a, it, coef, cnt);
     } else {
       const int64_t e = it - A;
       if (e < int64_t(a.L.cnt)) {
         double2 v = a.L.amp[e];
-        if (reflect) v = cneg(v);
+        if (a.mode == kStep) v = cneg(v);
         a.L.amp[e] = v;
         a.L.key[e] = swap_halves(a.L.key[e], n);
         cnt += nonzero(v);
@@ -328,7 +376,7 @@ extern "C" __global__ void __launch_bounds__(256) qwk_adjoint(AdjArgs a) {
   const int64_t stride = int64_t(gridDim.x) * blockDim.x;
   for (int64_t it = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; it < total; it += stride) {
     if (it < A) {
-      const Item x = item_of(a.m, it);
+      const Item x = item_of(a.m, it, it - (threadIdx.x & (kWave - 1)));
       double2 x0 = zero2(), x1 = zero2(), m0 = zero2(), m1 = zero2();
       double2 y0 = zero2(), y1 = zero2(), z0 = zero2(), z1 = zero2();
       Rot r, d;
@@ -441,7 +489,7 @@ extern "C" __global__ void __launch_bounds__(256) qwk_measure(Matrix m, Slots st
   const int64_t stride = int64_t(gridDim.x) * blockDim.x;
   for (int64_t it = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; it < total; it += stride) {
     if (it < m.items) {
-      const Item x = item_of(m, it);
+      const Item x = item_of(m, it, it - (threadIdx.x & (kWave - 1)));
       double2 p0 = zero2(), p1 = zero2(), s0 = zero2(), s1 = zero2();
       int colq = 0;
       if (x.live) {
@@ -538,7 +586,7 @@ extern "C" __global__ void __launch_bounds__(256) qwk_export(Matrix m, Slots st,
     uint64_t k[4] = {0, 0, 0, 0};
     double2 v[4] = {zero2(), zero2(), zero2(), zero2()};
     if (it < m.items) {
-      const Item x = item_of(m, it);
+      const Item x = item_of(m, it, it - (threadIdx.x & (kWave - 1)));
       if (x.live) {
         const int colq = m.col[it];
         for (int b2 = 0; b2 < 2; ++b2) {
@@ -629,7 +677,7 @@ extern "C" __global__ void __launch_bounds__(256) qwk_weight(Matrix m, Slots in,
   const int64_t stride = int64_t(gridDim.x) * blockDim.x;
   for (int64_t it = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; it < total; it += stride) {
     if (it < m.items) {
-      const Item x = item_of(m, it);
+      const Item x = item_of(m, it, it - (threadIdx.x & (kWave - 1)));
       if (x.live) {
         const double wr = w[x.I.jbase + m.col[it]];
         const double wq = w[x.I.jbase + x.j];
@@ -666,7 +714,7 @@ extern "C" __global__ void __launch_bounds__(256) qwk_grad_init(Matrix m, Slots 
                                                                 double2* db) {
   const int64_t stride = int64_t(gridDim.x) * blockDim.x;
   for (int64_t it = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; it < m.items; it += stride) {
-    const Item x = item_of(m, it);
+    const Item x = item_of(m, it, it - (threadIdx.x & (kWave - 1)));
     double2 n0 = zero2(), n1 = zero2();
     Rot r, d;
     r.f = zero2();
