@@ -101,12 +101,10 @@ struct qw_ctx {
     m.ninst = ninst;
     m.nbits = nbits;
     m.items = items;
-    m.inst0 = inst0;
     m.smax = smax;
     m.pad_ = 0;
     return m;
   }
-  qw::Inst inst0{};
   int32_t smax = 1;
 };
 
@@ -401,7 +399,6 @@ int load_impl(qw_ctx** out, int32_t ninst, const int32_t* n, const int64_t* colp
     dinst[i].inv_sqrt_s = 1.0 / std::sqrt(double(hi.s));
     ctx->smax = std::max(ctx->smax, hi.s);
   }
-  ctx->inst0 = dinst[0];
   ctx->col = static_cast<int32_t*>(ctx->alloc.get(sizeof(int32_t) * items));
   ctx->val = static_cast<double*>(ctx->alloc.get(sizeof(double) * items));
   ctx->rev = static_cast<int32_t*>(ctx->alloc.get(sizeof(int32_t) * items));

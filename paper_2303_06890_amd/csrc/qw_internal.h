@@ -55,7 +55,6 @@ struct Matrix {
   int32_t ninst;
   int32_t nbits;       // register width n of the key layout
   int64_t items;       // total ELL slots including alignment padding
-  Inst inst0;          // copy of inst[0] (used directly when ninst == 1)
   int32_t smax;        // largest s over the instances
   int32_t pad_;
 };
@@ -92,10 +91,9 @@ struct AdjArgs {
 static_assert(sizeof(Inst) == 40 && offsetof(Inst, inv_sqrt_s) == 32, "Inst layout");
 static_assert(sizeof(Slots) == 16, "Slots layout");
 static_assert(sizeof(List) == 24 && offsetof(List, cap) == 20, "List layout");
-static_assert(sizeof(Matrix) == 96 && offsetof(Matrix, inst0) == 48 && offsetof(Matrix, smax) == 88,
-              "Matrix layout");
-static_assert(sizeof(StepArgs) == 200 && offsetof(StepArgs, coefm) == 192, "StepArgs layout");
-static_assert(sizeof(AdjArgs) == 240 && offsetof(AdjArgs, dv) == 232, "AdjArgs layout");
+static_assert(sizeof(Matrix) == 56 && offsetof(Matrix, smax) == 48, "Matrix layout");
+static_assert(sizeof(StepArgs) == 160 && offsetof(StepArgs, coefm) == 152, "StepArgs layout");
+static_assert(sizeof(AdjArgs) == 200 && offsetof(AdjArgs, dv) == 192, "AdjArgs layout");
 
 // Launchers (qw_launch.cpp).  All enqueue on `stream` and allocate nothing.
 hipError_t launch_step(const StepArgs& a, int grid, int block, hipStream_t stream);

@@ -68,26 +68,17 @@ struct Rot {
 };
 __device__ __forceinline__ Rot rotation(double a, int j, int k) {
   Rot r;
-  if (a >= 0.0) {
-    r.f = make_double2(sqrt(a), 0.0);
-  } else {
-    const double q = sqrt(-a);
-    r.f = make_double2(0.0, j <= k ? q : -q);
-  }
+  const double q = sqrt(fabs(a));  // one square root, no divergent branch
+  r.f = a >= 0.0 ? make_double2(q, 0.0) : make_double2(0.0, j <= k ? q : -q);
   r.g = sqrt(1.0 - fabs(a));
   return r;
 }
 // d f/da and d g/da (not finite at a = 0 and |a| = 1).
 __device__ __forceinline__ Rot rotation_deriv(double a, int j, int k) {
   Rot d;
-  if (a > 0.0) {
-    d.f = make_double2(0.5 / sqrt(a), 0.0);
-  } else if (a < 0.0) {
-    const double q = -0.5 / sqrt(-a);
-    d.f = make_double2(0.0, j <= k ? q : -q);
-  } else {
-    d.f = make_double2(__builtin_inf(), 0.0);
-  }
+  const double q = 0.5 / sqrt(fabs(a));  // +inf at a = 0
+  d.f = a > 0.0 ? make_double2(q, 0.0)
+                : (a < 0.0 ? make_double2(0.0, j <= k ? -q : q) : make_double2(__builtin_inf(), 0.0));
   const double sg = a > 0.0 ? 1.0 : (a < 0.0 ? -1.0 : 0.0);
   d.g = -sg * 0.5 / sqrt(1.0 - fabs(a));
   return d;
@@ -160,13 +151,8 @@ struct Item {
 // straddles two instances, so its instance is looked up once, uniformly).
 __device__ __forceinline__ Item item_of(const Matrix& m, int64_t it, int64_t first) {
   Item x;
-  if (m.ninst == 1) {
-    x.inst = 0;
-    x.I = m.inst0;
-  } else {
-    x.inst = __builtin_amdgcn_readfirstlane(find_inst(m, first));
-    x.I = m.inst[x.inst];
-  }
+  x.inst = m.ninst == 1 ? 0 : __builtin_amdgcn_readfirstlane(find_inst(m, first));
+  x.I = m.inst[x.inst];  // uniform address: scalar loads that overlap the data loads
   const int64_t local = it - x.I.item_base;
   x.live = local < int64_t(x.I.N) * x.I.s;
   x.l = int(local) & (x.I.s - 1);
@@ -216,63 +202,67 @@ __device__ __forceinline__ void write_slot(const Slots& out, const Item& x, int6
 // One lane per slot and b2 (groups of 2s lanes, s <= 32).  The data loads of
 // a lane do not depend on each other or on the instance record: padding slots
 // hold zeros (col 0, val 0, rev -1), so every load is in bounds and issued at
-// once.
+// once.  Returns the number of branches the lane wrote.
 template <bool ACC>
-__device__ __forceinline__ void step_pairs(const StepArgs& a, int64_t it, double coef, unsigned& cnt) {
+__device__ __forceinline__ unsigned step_pairs(const Matrix& m, Slots in, Slots out, int32_t mode, double tau,
+                                               double2* yacc, double coef, int64_t it, int64_t first) {
   const int64_t q = it >> 1;
   const int b2 = int(it & 1);
-  const double2 x = a.in.R[it];
-  const double2 y = a.in.Q[it];
-  const int colq = a.m.col[q];
-  const double v = a.m.val[q];
-  const int pr = a.m.rev[q];
-  const Item xi = item_of(a.m, q, (it - (threadIdx.x & (kWave - 1))) >> 1);
+  const double2 x = in.R[it];
+  const double2 y = in.Q[it];
+  const int colq = m.col[q];
+  const double v = m.val[q];
+  const int pr = m.rev[q];
+  const Item xi = item_of(m, q, first);
   const Rot r = rotation(v, xi.j, colq);
   double2 o = x, n = y;
-  if (a.mode == kStep) {
+  if (mode == kStep) {
     const double2 part = b2 == 0 ? cjmul(r.f, x) : cscale(x, r.g);
     const double2 c = group_sum(part, 2 * xi.I.s);
     if (ACC && xi.live && xi.l == 0 && b2 == 0) {
-      double2 yv = a.yacc[xi.I.jbase + xi.j];
+      double2 yv = yacc[xi.I.jbase + xi.j];
       yv.x += coef * (c.x * xi.I.inv_sqrt_s);
       yv.y += coef * (c.y * xi.I.inv_sqrt_s);
-      a.yacc[xi.I.jbase + xi.j] = yv;
+      yacc[xi.I.jbase + xi.j] = yv;
     }
     const double2 tc = cscale(c, 2.0 / double(xi.I.s));
     o = csub(b2 == 0 ? cmul(tc, r.f) : cscale(tc, r.g), x);
     n = cneg(y);
   }
-  if (!xi.live) return;
-  o = prune(o, a.tau, cnt);
+  unsigned cnt = 0;
+  if (!xi.live) return 0;
+  o = prune(o, tau, cnt);
   if (b2 == 1) {
-    a.out.Q[it] = o;
-    a.out.R[it] = prune(n, a.tau, cnt);
+    out.Q[it] = o;
+    out.R[it] = prune(n, tau, cnt);
   } else if (pr >= 0) {
-    a.out.R[2 * (xi.I.item_base + int64_t(colq) * xi.I.s + pr)] = o;
+    out.R[2 * (xi.I.item_base + int64_t(colq) * xi.I.s + pr)] = o;
   } else {
-    a.out.Q[it] = o;
-    a.out.R[it] = prune(n, a.tau, cnt);
+    out.Q[it] = o;
+    out.R[it] = prune(n, tau, cnt);
   }
+  return cnt;
 }
 
 // One lane per slot (both b2), for s = 64 where a group fills a wavefront.
 template <bool ACC>
-__device__ __forceinline__ void step_slot(const StepArgs& a, int64_t it, double coef, unsigned& cnt) {
-  const double2 x0 = a.in.R[2 * it], x1 = a.in.R[2 * it + 1];
-  const double2 y0 = a.in.Q[2 * it], y1 = a.in.Q[2 * it + 1];
-  const int colq = a.m.col[it];
-  const double v = a.m.val[it];
-  const int pr = a.m.rev[it];
-  const Item x = item_of(a.m, it, it - (threadIdx.x & (kWave - 1)));
+__device__ __forceinline__ unsigned step_slot(const Matrix& m, Slots in, Slots out, int32_t mode, double tau,
+                                              double2* yacc, double coef, int64_t it, int64_t first) {
+  const double2 x0 = in.R[2 * it], x1 = in.R[2 * it + 1];
+  const double2 y0 = in.Q[2 * it], y1 = in.Q[2 * it + 1];
+  const int colq = m.col[it];
+  const double v = m.val[it];
+  const int pr = m.rev[it];
+  const Item x = item_of(m, it, first);
   const Rot r = rotation(v, x.j, colq);
   double2 o0 = x0, o1 = x1, n0 = y0, n1 = y1;
-  if (a.mode == kStep) {
+  if (mode == kStep) {
     const double2 c = group_sum(cadd(cjmul(r.f, x0), cscale(x1, r.g)), x.I.s);
     if (ACC && x.live && x.l == 0) {
-      double2 yv = a.yacc[x.I.jbase + x.j];
+      double2 yv = yacc[x.I.jbase + x.j];
       yv.x += coef * (c.x * x.I.inv_sqrt_s);
       yv.y += coef * (c.y * x.I.inv_sqrt_s);
-      a.yacc[x.I.jbase + x.j] = yv;
+      yacc[x.I.jbase + x.j] = yv;
     }
     const double2 tc = cscale(c, 2.0 / double(x.I.s));
     o0 = csub(cmul(tc, r.f), x0);
@@ -280,21 +270,22 @@ __device__ __forceinline__ void step_slot(const StepArgs& a, int64_t it, double 
     n0 = cneg(y0);
     n1 = cneg(y1);
   }
-  if (!x.live) return;
-  o0 = prune(o0, a.tau, cnt);
-  o1 = prune(o1, a.tau, cnt);
-  n1 = prune(n1, a.tau, cnt);
-  if (pr < 0) n0 = prune(n0, a.tau, cnt);
-  write_slot(a.out, x, it, colq, pr, o0, o1, n0, n1);
+  unsigned cnt = 0;
+  if (!x.live) return 0;
+  o0 = prune(o0, tau, cnt);
+  o1 = prune(o1, tau, cnt);
+  n1 = prune(n1, tau, cnt);
+  if (pr < 0) n0 = prune(n0, tau, cnt);
+  write_slot(out, x, it, colq, pr, o0, o1, n0, n1);
+  return cnt;
 }
 
-template <bool ACC>
-__device__ __forceinline__ void step_body(const StepArgs& a) {
+// LPS: lanes per slot (2 when every s <= 32, else 1).
+template <bool ACC, int LPS>
+__device__ __forceinline__ void step_body(StepArgs a) {
   __shared__ unsigned long long sh[16];
-  const int lps = a.m.smax <= 32 ? 2 : 1;  // lanes per slot
-  const int64_t A = a.m.items * lps;
+  const int64_t A = a.m.items * LPS;
   const int64_t total = A + ((int64_t(a.L.cnt) + kWave - 1) & ~int64_t(kWave - 1));
-  const int n = a.m.nbits;
   double coef = 0.0;
   uint32_t stepno = 0;
   if (ACC) {
@@ -303,34 +294,37 @@ __device__ __forceinline__ void step_body(const StepArgs& a) {
   }
   unsigned cnt = 0;
   const int64_t stride = int64_t(gridDim.x) * blockDim.x;
+  const int lane = threadIdx.x & (kWave - 1);
   for (int64_t it = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; it < total; it += stride) {
     if (it < A) {
-      if (lps == 2)
-        step_pairs<ACC>(a, it, coef, cnt);
+      if (LPS == 2)
+        cnt += step_pairs<ACC>(a.m, a.in, a.out, a.mode, a.tau, a.yacc, coef, it, (it - lane) >> 1);
       else
-        step_slot<ACC>(a, it, coef, cnt);
+        cnt += step_slot<ACC>(a.m, a.in, a.out, a.mode, a.tau, a.yacc, coef, it, it - lane);
     } else {
       const int64_t e = it - A;
       if (e < int64_t(a.L.cnt)) {
         double2 v = a.L.amp[e];
         if (a.mode == kStep) v = cneg(v);
         a.L.amp[e] = v;
-        a.L.key[e] = swap_halves(a.L.key[e], n);
+        a.L.key[e] = swap_halves(a.L.key[e], a.m.nbits);
         cnt += nonzero(v);
       }
     }
   }
   const unsigned long long t = block_sum_u64(cnt, sh);
   if (threadIdx.x == 0) {
-    a.acc[blockIdx.x] += t;
+    atomicAdd(&a.acc[blockIdx.x], t);  // per-workgroup counter: no contention, no return value
     if (ACC) a.stepno[blockIdx.x] = stepno + 1;
   }
 }
 
 }  // namespace qw
 
-extern "C" __global__ void __launch_bounds__(256) qwk_step(qw::StepArgs a) { qw::step_body<false>(a); }
-extern "C" __global__ void __launch_bounds__(256) qwk_step_acc(qw::StepArgs a) { qw::step_body<true>(a); }
+extern "C" __global__ void __launch_bounds__(256) qwk_step2(qw::StepArgs a) { qw::step_body<false, 2>(a); }
+extern "C" __global__ void __launch_bounds__(256) qwk_step2_acc(qw::StepArgs a) { qw::step_body<true, 2>(a); }
+extern "C" __global__ void __launch_bounds__(256) qwk_step1(qw::StepArgs a) { qw::step_body<false, 1>(a); }
+extern "C" __global__ void __launch_bounds__(256) qwk_step1_acc(qw::StepArgs a) { qw::step_body<true, 1>(a); }
 
 namespace qw {
 

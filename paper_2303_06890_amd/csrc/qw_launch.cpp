@@ -21,8 +21,10 @@ namespace qw {
 namespace {
 
 enum Fn {
-  F_STEP,
-  F_STEP_ACC,
+  F_STEP2,
+  F_STEP2_ACC,
+  F_STEP1,
+  F_STEP1_ACC,
   F_ADJOINT,
   F_QBS_TABLE,
   F_INIT,
@@ -35,7 +37,8 @@ enum Fn {
   F_COUNT
 };
 
-const char* const kNames[F_COUNT] = {"qwk_step", "qwk_step_acc", "qwk_adjoint", "qwk_qbs_table",
+const char* const kNames[F_COUNT] = {"qwk_step2", "qwk_step2_acc", "qwk_step1", "qwk_step1_acc",
+                                     "qwk_adjoint", "qwk_qbs_table",
                                      "qwk_init", "qwk_fill",     "qwk_measure", "qwk_export",
                                      "qwk_import", "qwk_weight", "qwk_grad_init"};
 
@@ -94,7 +97,9 @@ int clamp_grid(int64_t work, int64_t limit) {
 hipError_t launch_step(const StepArgs& a, int grid, int block, hipStream_t stream) {
   StepArgs c = a;
   void* p[] = {&c};
-  return launch(a.yacc ? F_STEP_ACC : F_STEP, grid, block, stream, p);
+  const bool pairs = a.m.smax <= 32;  // two lanes per slot
+  const Fn f = pairs ? (a.yacc ? F_STEP2_ACC : F_STEP2) : (a.yacc ? F_STEP1_ACC : F_STEP1);
+  return launch(f, grid, block, stream, p);
 }
 
 hipError_t launch_adjoint(const AdjArgs& a, int grid, int block, hipStream_t stream) {
