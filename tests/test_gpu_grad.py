@@ -1,0 +1,109 @@
+"""GPU reverse-mode gradient (qw_grad: reverse sweep with W^dagger
+recomputation) against the oracle's stored-state reverse mode and central
+finite differences."""
+import numpy as np
+import pytest
+
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def Q():
+    import torch
+
+    assert torch.cuda.is_available()
+    import paper_2303_06890_amd as Q
+
+    return Q
+
+
+def _scaled(csc):
+    sc = 1.0 / np.abs(csc.vals).max()
+    return W.Csc(csc.n, csc.colptr, csc.rowidx, csc.vals * sc)
+
+
+def _oracle_csc_grad(oracle_mod, csc, b, w, nsteps):
+    m = oracle_mod.OracleMatrix(csc, scale=1.0)
+    loss, dv, db = m.grad(b, w, nsteps)
+    col, _, _ = m.ell()
+    g = np.zeros(csc.nnz)
+    for c in range(csc.n):
+        for p in range(csc.colptr[c], csc.colptr[c + 1]):
+            g[p] = dv[c, int(np.nonzero(col[c] == csc.rowidx[p])[0][0])]
+    return loss, g, db[:csc.n]
+
+
+def _gpu_grad(Q, csc, b, w, nsteps):
+    walk = Q.Walk(csc, scale=1.0)
+    st = walk.state(b).step(nsteps)
+    return st.grad(w, nsteps)
+
+
+def _gpu_loss(Q, csc, b, w, nsteps):
+    walk = Q.Walk(csc, scale=1.0)
+    st = walk.state(b).step(nsteps)
+    return float(np.dot(st.j_marginal()[:csc.n], w))
+
+
+def _close(a, b, rel):
+    fin = np.isfinite(a) & np.isfinite(b)
+    scale = np.abs(b[fin]).max()
+    assert np.abs(a[fin] - b[fin]).max() <= rel * scale
+    return fin
+
+
+@pytest.mark.parametrize("n,c,seed,nsteps", [(16, 5, 81, 5), (64, 7, 82, 9)])
+def test_grad_matches_oracle_small(Q, oracle_mod, n, c, seed, nsteps):
+    csc = _scaled(W.offset_matrix(n, c, seed=seed))
+    b = W.gaussian_b(n, seed=seed + 1) * (1 + 0.3j)
+    b = b / np.linalg.norm(b)
+    w = np.zeros(n)
+    w[np.random.default_rng(seed).choice(n, size=max(2, n // 4), replace=False)] = 1.0
+    ol, og, odb = _oracle_csc_grad(oracle_mod, csc, b, w, nsteps)
+    gl, gg, gdb = _gpu_grad(Q, csc, b, w, nsteps)
+    assert gl == pytest.approx(ol, rel=1e-12)
+    fin = _close(gg, og, 1e-8)
+    assert fin.sum() >= csc.nnz - 2  # |a| = 1 entries are not differentiable
+    assert np.abs(gdb - odb).max() <= 1e-8 * np.abs(odb).max()
+
+
+def test_grad_1024_vs_oracle_and_fd(Q, oracle_mod):
+    """G(1024, 8), uniform b, 20 steps, loss = total probability of 32 seeded
+    column outcomes: gradient over all 8192 values against the oracle's
+    reverse mode, and 16 entries against central differences (h = 1e-6)."""
+    a, b, w = W.adjoint_problem()
+    csc = _scaled(a)
+    nsteps = 20
+    gl, gg, gdb = _gpu_grad(Q, csc, b, w, nsteps)
+    ol, og, odb = _oracle_csc_grad(oracle_mod, csc, b, w, nsteps)
+    assert gl == pytest.approx(ol, rel=1e-12)
+    assert gl == pytest.approx(_gpu_loss(Q, csc, b, w, nsteps), rel=1e-13)
+    _close(gg, og, 1e-8)
+    assert np.abs(gdb - odb).max() <= 1e-8 * np.abs(odb).max()
+    h = 1e-6
+    for p in W.fd_sample(csc.vals):
+        vp, vm = csc.vals.copy(), csc.vals.copy()
+        vp[p] += h
+        vm[p] -= h
+        fd = (_gpu_loss(Q, W.Csc(csc.n, csc.colptr, csc.rowidx, vp), b, w, nsteps)
+              - _gpu_loss(Q, W.Csc(csc.n, csc.colptr, csc.rowidx, vm), b, w, nsteps)) / (2 * h)
+        assert abs(fd - gg[p]) <= 1e-8 * abs(gg[p]) + 1e-10, (p, fd, gg[p])
+
+
+def test_walk_observable_autograd(Q):
+    import torch
+
+    csc = _scaled(W.offset_matrix(64, 6, seed=91))
+    b = W.gaussian_b(64, seed=92)
+    w = np.random.default_rng(93).uniform(size=64)
+    vals = torch.tensor(csc.vals, requires_grad=True)
+    bt = torch.tensor(b, requires_grad=True)
+    p = Q.WalkObservable.apply(vals, bt, csc, 7)
+    loss = (p * torch.tensor(w)).sum()
+    loss.backward()
+    gl, gg, gdb = _gpu_grad(Q, csc, b, w, 7)
+    assert float(loss) == pytest.approx(gl, rel=1e-12)
+    assert np.allclose(vals.grad.numpy(), gg, rtol=1e-12, atol=1e-14, equal_nan=True)
+    assert np.allclose(bt.grad.numpy(), gdb.real, rtol=1e-12, atol=1e-14)
