@@ -306,7 +306,7 @@ def _make_walk_observable():
         def forward(ctx, vals, b, pattern, nsteps):
             v = vals.detach().cpu().numpy().astype(np.float64)
             mat = _CscArrays(pattern.n, np.asarray(pattern.colptr, np.int32), np.asarray(pattern.rowidx, np.int32), v)
-            walk = Walk(mat, scale=1.0)
+            walk = Walk(mat, scale=1.0, symmetric=False)  # entries are independent parameters
             st = walk.state(b.detach().cpu().numpy())
             st.step(int(nsteps))
             p = st.j_marginal()[: pattern.n]
