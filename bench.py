@@ -66,6 +66,86 @@ def cpu_baseline(csc, b, steps: int):
     }
 
 
+def _timed(Q, fn):
+    """GPU time (ms) of fn() on the library's stream, by HIP events."""
+    import torch
+
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record(Q.stream())
+    fn()
+    e1.record(Q.stream())
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1)
+
+
+def batched_leg(Q, W, autotune, tune: bool, steps: int = 50):
+    """256 instances (n = 2^U{6..12}, 4..16 entries per column, single-column
+    starts) in one launch per step, against the same instances advanced one
+    walk at a time on the same GPU."""
+    inst = W.batched_instances()
+    mats, bs = [a for a, _ in inst], [b for _, b in inst]
+    walk = Q.Walk(mats)
+    shape = autotune.tune(walk, bs) if tune else None
+    st = walk.state(bs)
+    if shape:
+        autotune.apply(st, shape)
+    s0 = st.stats()
+    ms = _timed(Q, lambda: st.step(steps))
+    upd = st.stats()["total_written"] - s0["total_written"]
+    singles = []
+    for a, b in inst:
+        w1 = Q.Walk(a)
+        singles.append((w1, w1.state(b)))
+    t0 = [x[1].stats()["total_written"] for x in singles]
+    ms_plain = _timed(Q, lambda: [x[1].step(steps) for x in singles])
+    upd_plain = sum(x[1].stats()["total_written"] - t for x, t in zip(singles, t0))
+    assert upd_plain == upd, (upd_plain, upd)
+    return {
+        "workload": "256 instances, n = 2^U{6..12}, 4..16 entries/column, single-column T~ starts, 50 steps",
+        "slots": int(sum(d["N"] * d["s"] for d in walk.info)),
+        "steps": steps,
+        "ms": ms,
+        "value": upd / (ms / 1e3),
+        "plain_ms": ms_plain,
+        "plain_value": upd_plain / (ms_plain / 1e3),
+        "speedup_vs_plain": ms_plain / ms,
+        "launch_shape": list(shape) if shape else "default",
+    }
+
+
+def adjoint_leg(Q, W, steps: int = 20, reps: int = 5):
+    """Gradient of the total probability of 32 column outcomes after 20 steps
+    on G(1024, 8) w.r.t. all 8192 values and b (forward walk + reverse sweep
+    with recomputation), against the forward walk alone."""
+    import numpy as np
+
+    a, b, w = W.adjoint_problem()
+    sc = 1.0 / np.abs(a.vals).max()
+    a = W.Csc(a.n, a.colptr, a.rowidx, a.vals * sc)
+    walk = Q.Walk(a, scale=1.0)
+
+    def forward():
+        st = walk.state(b).step(steps)
+        st.sync()
+        return st
+
+    def gradient():
+        st = walk.state(b).step(steps)
+        st.grad(w, steps)
+
+    forward(), gradient()
+    t_fwd = min(_timed(Q, forward) for _ in range(reps))
+    t_grad = min(_timed(Q, gradient) for _ in range(reps))
+    return {
+        "workload": "G(1024, 8), uniform b, 20 steps, loss over 32 outcomes, 8192 values",
+        "forward_ms": t_fwd,
+        "forward_plus_gradient_ms": t_grad,
+        "gradient_over_forward": t_grad / t_fwd,
+    }
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -73,6 +153,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=64)
     ap.add_argument("--cpu-steps", type=int, default=5, help="walk steps of the oracle sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extras", action="store_true", help="skip the batched and adjoint legs")
+    ap.add_argument("--no-tune", action="store_true", help="keep the default launch shape")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on exactly one GPU: this build has no multi-GPU path "
@@ -85,11 +167,16 @@ def main():
     import paper_2303_06890_amd as Q
     import workloads as W
 
+    from paper_2303_06890_amd import autotune
+
     torch.cuda.set_device(0)
     csc, b = W.paper_scale()
     walk = Q.Walk(csc)
     N, s = walk.info[0]["N"], walk.info[0]["s"]
+    shape = None if args.no_tune else autotune.tune(walk, b)
     st = walk.state(b)
+    if shape:
+        autotune.apply(st, shape)
     st.step(args.warmup)
     torch.cuda.synchronize()
     m_in0 = st.count()
@@ -129,6 +216,7 @@ def main():
             "s": s,
             "branches": s1["branches"],
             "graph_steps_per_replay": 16,
+            "launch_shape": list(shape) if shape else "default",
         },
         "roofline": {
             "bound": "hbm",
@@ -144,6 +232,11 @@ def main():
     }
     print(f"[bench] {args.steps} steps in {ms:.2f} ms ({launch_s * 1e6:.2f} us/step), "
           f"{value:.3e} updates/s, {achieved:.0f} GB/s algorithmic", file=sys.stderr, flush=True)
+    if not args.no_extras:
+        line["batched"] = batched_leg(Q, W, autotune, not args.no_tune)
+        print(f"[bench] batched: {line['batched']}", file=sys.stderr, flush=True)
+        line["adjoint"] = adjoint_leg(Q, W)
+        print(f"[bench] adjoint: {line['adjoint']}", file=sys.stderr, flush=True)
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(csc, b, args.cpu_steps)
         print(f"[bench] oracle: {line['cpu_baseline']['value']:.3e} updates/s", file=sys.stderr, flush=True)
