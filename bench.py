@@ -156,6 +156,11 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true", help="skip the batched and adjoint legs")
     ap.add_argument("--no-tune", action="store_true", help="keep the default launch shape")
+    ap.add_argument("--only", choices=["batched", "adjoint"], default=None,
+                    help="run one extra leg alone (for profiling) and print its JSON")
+    ap.add_argument("--pmc-run", action="store_true",
+                    help="counter run: a torch copy of 64 MiB (byte calibration), then 64 walk steps of "
+                         "the main workload with the default launch shape; prints nothing else")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on exactly one GPU: this build has no multi-GPU path "
@@ -171,6 +176,22 @@ def main():
     from paper_2303_06890_amd import autotune
 
     torch.cuda.set_device(0)
+    if args.pmc_run:
+        src = torch.ones(8 << 20, dtype=torch.float64, device="cuda")  # 64 MiB
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        csc, b = W.paper_scale()
+        st = Q.Walk(csc).state(b).step(64)
+        st.sync()
+        print(json.dumps({"pmc_run": True, "copy_bytes": 8 << 23, "steps": 64}), flush=True)
+        return
+    if args.only == "batched":
+        print(json.dumps(batched_leg(Q, W, autotune, not args.no_tune)), flush=True)
+        return
+    if args.only == "adjoint":
+        print(json.dumps(adjoint_leg(Q, W)), flush=True)
+        return
     csc, b = W.paper_scale()
     walk = Q.Walk(csc)
     N, s = walk.info[0]["N"], walk.info[0]["s"]
