@@ -91,12 +91,14 @@ struct qw_ctx {
   int32_t* col = nullptr;
   double* val = nullptr;
   int32_t* rev = nullptr;
+  qw::SlotRec* rec = nullptr;
   qw::Inst* dinst = nullptr;
   qw::Matrix mat() const {
     qw::Matrix m;
     m.col = col;
     m.val = val;
     m.rev = rev;
+    m.rec = rec;
     m.inst = dinst;
     m.ninst = ninst;
     m.nbits = nbits;
@@ -321,6 +323,7 @@ void ctx_release(qw_ctx* ctx) {
   ctx->alloc.put(ctx->col);
   ctx->alloc.put(ctx->val);
   ctx->alloc.put(ctx->rev);
+  ctx->alloc.put(ctx->rec);
   ctx->alloc.put(ctx->dinst);
   delete ctx;
 }
@@ -402,8 +405,9 @@ int load_impl(qw_ctx** out, int32_t ninst, const int32_t* n, const int64_t* colp
   ctx->col = static_cast<int32_t*>(ctx->alloc.get(sizeof(int32_t) * items));
   ctx->val = static_cast<double*>(ctx->alloc.get(sizeof(double) * items));
   ctx->rev = static_cast<int32_t*>(ctx->alloc.get(sizeof(int32_t) * items));
+  ctx->rec = static_cast<qw::SlotRec*>(ctx->alloc.get(sizeof(qw::SlotRec) * items));
   ctx->dinst = static_cast<qw::Inst*>(ctx->alloc.get(sizeof(qw::Inst) * ninst));
-  if (!ctx->col || !ctx->val || !ctx->rev || !ctx->dinst) {
+  if (!ctx->col || !ctx->val || !ctx->rev || !ctx->rec || !ctx->dinst) {
     ctx_release(ctx);
     return set_err(QW_ENOMEM, "device allocation failed for the matrix");
   }
@@ -413,7 +417,7 @@ int load_impl(qw_ctx** out, int32_t ninst, const int32_t* n, const int64_t* colp
   if (e == hipSuccess)
     e = hipMemcpyAsync(ctx->dinst, dinst.data(), sizeof(qw::Inst) * ninst, hipMemcpyHostToDevice, stream);
   // O_s'^-1 of every reflected output: the QBS of j in row col[q], once per matrix
-  if (e == hipSuccess) e = qw::launch_qbs_table(ctx->mat(), ctx->rev, stream);
+  if (e == hipSuccess) e = qw::launch_qbs_table(ctx->mat(), ctx->rev, ctx->rec, stream);
   if (e == hipSuccess) e = hipStreamSynchronize(stream);  // host vectors go out of scope
   if (e != hipSuccess) {
     ctx_release(ctx);

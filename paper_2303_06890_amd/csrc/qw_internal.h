@@ -47,10 +47,18 @@ struct List {
   uint32_t cap;
 };
 
+// The three per-slot words the step reads, packed into one 16-byte load.
+struct SlotRec {
+  int32_t col;
+  int32_t rev;
+  double val;
+};
+
 struct Matrix {
   const int32_t* col;  // ELL column indices, sorted inside each row
   const double* val;   // ELL values
   const int32_t* rev;  // rev[q] = position of j in row col[q] (QBS), -1 if absent
+  const SlotRec* rec;  // {col, rev, val} per slot
   const Inst* inst;
   int32_t ninst;
   int32_t nbits;       // register width n of the key layout
@@ -91,14 +99,16 @@ struct AdjArgs {
 static_assert(sizeof(Inst) == 40 && offsetof(Inst, inv_sqrt_s) == 32, "Inst layout");
 static_assert(sizeof(Slots) == 16, "Slots layout");
 static_assert(sizeof(List) == 24 && offsetof(List, cap) == 20, "List layout");
-static_assert(sizeof(Matrix) == 56 && offsetof(Matrix, smax) == 48, "Matrix layout");
-static_assert(sizeof(StepArgs) == 160 && offsetof(StepArgs, coefm) == 152, "StepArgs layout");
-static_assert(sizeof(AdjArgs) == 200 && offsetof(AdjArgs, dv) == 192, "AdjArgs layout");
+static_assert(sizeof(SlotRec) == 16, "SlotRec layout");
+static_assert(sizeof(Matrix) == 64 && offsetof(Matrix, smax) == 56, "Matrix layout");
+static_assert(sizeof(StepArgs) == 168 && offsetof(StepArgs, coefm) == 160, "StepArgs layout");
+static_assert(sizeof(AdjArgs) == 208 && offsetof(AdjArgs, dv) == 200, "AdjArgs layout");
 
 // Launchers (qw_launch.cpp).  All enqueue on `stream` and allocate nothing.
 hipError_t launch_step(const StepArgs& a, int grid, int block, hipStream_t stream);
 hipError_t launch_adjoint(const AdjArgs& a, int grid, int block, hipStream_t stream);
-hipError_t launch_qbs_table(const Matrix& m, int32_t* rev, hipStream_t stream);
+// rev = QBS table; then rec = {col, rev, val} per slot.
+hipError_t launch_qbs_table(const Matrix& m, int32_t* rev, SlotRec* rec, hipStream_t stream);
 hipError_t launch_init(const Matrix& m, const double2* b, Slots out, double tau, hipStream_t stream);
 hipError_t launch_fill(void* p, int64_t bytes, hipStream_t stream);
 // Reductions over a state: kind 0 = count, 1 = norm^2 (per-block partials in

@@ -101,10 +101,30 @@ __device__ __forceinline__ bool qbs(const int32_t* __restrict__ row, int s, int 
   return vp == target;
 }
 
-// Sum over aligned groups of `width` lanes (width a power of two <= 64).
-// Every lane of a group ends with the bitwise-identical sum.
+// Value of a double in the lane selected by a DPP pattern (within rows of 16).
+template <int CTRL>
+__device__ __forceinline__ double dpp(double v) {
+  const int lo = __double2loint(v), hi = __double2hiint(v);
+  return __hiloint2double(__builtin_amdgcn_update_dpp(0, hi, CTRL, 0xF, 0xF, false),
+                          __builtin_amdgcn_update_dpp(0, lo, CTRL, 0xF, 0xF, false));
+}
+
+template <int CTRL>
+__device__ __forceinline__ double2 dpp_add(double2 v) {
+  return make_double2(v.x + dpp<CTRL>(v.x), v.y + dpp<CTRL>(v.y));
+}
+
+// Sum over aligned groups of `width` lanes (width a power of two <= 64,
+// uniform across the wavefront).  Each stage adds the value of a partner lane
+// in the other half of the current block (DPP quad permutations and row
+// mirrors inside rows of 16 lanes, lane shuffles beyond), so every lane of a
+// group ends with the bitwise-identical sum.
 __device__ __forceinline__ double2 group_sum(double2 v, int width) {
-  for (int off = 1; off < width; off <<= 1) {
+  if (width >= 2) v = dpp_add<0xB1>(v);   // quad_perm [1,0,3,2]: lane ^ 1
+  if (width >= 4) v = dpp_add<0x4E>(v);   // quad_perm [2,3,0,1]: lane ^ 2
+  if (width >= 8) v = dpp_add<0x141>(v);  // row_half_mirror: the other quad of 8
+  if (width >= 16) v = dpp_add<0x140>(v); // row_mirror: the other 8 of 16
+  for (int off = 16; off < width; off <<= 1) {
     v.x += __shfl_xor(v.x, off);
     v.y += __shfl_xor(v.y, off);
   }
@@ -208,25 +228,26 @@ __device__ __forceinline__ unsigned step_pairs(const Matrix& m, Slots in, Slots 
                                                double2* yacc, double coef, int64_t it, int64_t first) {
   const int64_t q = it >> 1;
   const int b2 = int(it & 1);
+  const SlotRec rc = m.rec[q];
   const double2 x = in.R[it];
-  const double2 y = in.Q[it];
-  const int colq = m.col[q];
-  const double v = m.val[q];
-  const int pr = m.rev[q];
+  const double2 y1 = in.Q[2 * q + 1];  // the b2 = 1 lane's input; same line as its partner lane's
   const Item xi = item_of(m, q, first);
-  const Rot r = rotation(v, xi.j, colq);
+  // the lane's component of sqrt(s) phi_j: f for b2 = 0, g for b2 = 1 (one square root)
+  const double a = rc.val;
+  const double sq = sqrt(b2 == 0 ? fabs(a) : 1.0 - fabs(a));
+  const double2 w = (b2 == 1 || a >= 0.0) ? make_double2(sq, 0.0) : make_double2(0.0, xi.j <= rc.col ? sq : -sq);
+  double2 y = b2 == 1 ? y1 : zero2();
+  if (b2 == 0 && rc.rev < 0) y = in.Q[it];  // only slots whose swap is not a group member
   double2 o = x, n = y;
   if (mode == kStep) {
-    const double2 part = b2 == 0 ? cjmul(r.f, x) : cscale(x, r.g);
-    const double2 c = group_sum(part, 2 * xi.I.s);
+    const double2 c = group_sum(cjmul(w, x), 2 * xi.I.s);
     if (ACC && xi.live && xi.l == 0 && b2 == 0) {
       double2 yv = yacc[xi.I.jbase + xi.j];
       yv.x += coef * (c.x * xi.I.inv_sqrt_s);
       yv.y += coef * (c.y * xi.I.inv_sqrt_s);
       yacc[xi.I.jbase + xi.j] = yv;
     }
-    const double2 tc = cscale(c, 2.0 / double(xi.I.s));
-    o = csub(b2 == 0 ? cmul(tc, r.f) : cscale(tc, r.g), x);
+    o = csub(cmul(cscale(c, 2.0 / double(xi.I.s)), w), x);
     n = cneg(y);
   }
   unsigned cnt = 0;
@@ -235,8 +256,8 @@ __device__ __forceinline__ unsigned step_pairs(const Matrix& m, Slots in, Slots 
   if (b2 == 1) {
     out.Q[it] = o;
     out.R[it] = prune(n, tau, cnt);
-  } else if (pr >= 0) {
-    out.R[2 * (xi.I.item_base + int64_t(colq) * xi.I.s + pr)] = o;
+  } else if (rc.rev >= 0) {
+    out.R[2 * (xi.I.item_base + int64_t(rc.col) * xi.I.s + rc.rev)] = o;
   } else {
     out.Q[it] = o;
     out.R[it] = prune(n, tau, cnt);
@@ -332,7 +353,7 @@ namespace qw {
 // rev[q] = i_{col[q]}(j): where row j's slot q points back into its column's
 // row, or -1 (filler or asymmetric pattern).
 
-extern "C" __global__ void __launch_bounds__(256) qwk_qbs_table(Matrix m, int32_t* rev) {
+extern "C" __global__ void __launch_bounds__(256) qwk_qbs_table(Matrix m, int32_t* rev, SlotRec* rec) {
   const int64_t stride = int64_t(gridDim.x) * blockDim.x;
   for (int64_t it = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; it < m.items; it += stride) {
     const int ii = find_inst(m, it);
@@ -346,6 +367,11 @@ extern "C" __global__ void __launch_bounds__(256) qwk_qbs_table(Matrix m, int32_
       if (qbs(m.col + I.item_base + int64_t(c) * I.s, I.s, j, p)) r = p;
     }
     rev[it] = r;
+    SlotRec sr;
+    sr.col = m.col[it];
+    sr.rev = r;
+    sr.val = m.val[it];
+    rec[it] = sr;
   }
 }
 

@@ -108,9 +108,9 @@ hipError_t launch_adjoint(const AdjArgs& a, int grid, int block, hipStream_t str
   return launch(F_ADJOINT, grid, block, stream, p);
 }
 
-hipError_t launch_qbs_table(const Matrix& m, int32_t* rev, hipStream_t stream) {
+hipError_t launch_qbs_table(const Matrix& m, int32_t* rev, SlotRec* rec, hipStream_t stream) {
   Matrix mm = m;
-  void* p[] = {&mm, &rev};
+  void* p[] = {&mm, &rev, &rec};
   return launch(F_QBS_TABLE, clamp_grid(m.items, 4096), 256, stream, p);
 }
 
