@@ -1,8 +1,8 @@
 """Launch-shape autotuner of the step kernel.
 
-The step kernel strides over its work items (two lanes per QRAM slot when
-every row has at most 32 slots), so its launch shape is free: workgroup size
-and number of workgroups.  `tune` times candidate shapes on a scratch state
+The step kernel strides over wavefronts (each covers 64 / min(s, 8) rows,
+min(s, 8) lanes per row), so its launch shape is free: workgroup size and
+number of workgroups.  `tune` times candidate shapes on a scratch state
 of the given workload (HIP events on the library's stream), keeps the fastest,
 and remembers it under (device name, padded dimensions, largest s, instance
 count, branch-count bucket), in memory and optionally in a JSON file.
@@ -26,8 +26,11 @@ def _key(walk, branches: int) -> str:
 
 
 def candidates(walk):
-    items = sum(d["N"] * d["s"] for d in walk.info)
-    lanes = items * (2 if max(d["s"] for d in walk.info) <= 32 else 1)
+    waves = 0
+    for d in walk.info:
+        rows_per_wave = 64 // min(d["s"], 8)
+        waves += -(-d["N"] // rows_per_wave)
+    lanes = 64 * waves
     out = []
     for wg in (64, 128, 256):
         one_pass = max(1, -(-lanes // wg))

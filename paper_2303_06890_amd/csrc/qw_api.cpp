@@ -83,31 +83,33 @@ struct qw_ctx {
   int32_t ninst = 0;
   int32_t nbits = 0;  // key register width
   int64_t items = 0;  // ELL slots incl. alignment padding
+  int64_t waves = 0;  // wavefronts of one step-kernel pass
   int64_t jtotal = 0;
   int64_t ntotal = 0;  // sum of unpadded n_i
   int64_t nnz_total = 0;
   std::vector<HostInst> inst;
-  std::vector<int64_t> csc_slot;  // ELL slot of every CSC entry
+  std::vector<int64_t> csc_slot;  // home of every CSC entry's slot
   int32_t* col = nullptr;
   double* val = nullptr;
-  int32_t* rev = nullptr;
   qw::SlotRec* rec = nullptr;
   qw::Inst* dinst = nullptr;
   qw::Matrix mat() const {
     qw::Matrix m;
     m.col = col;
     m.val = val;
-    m.rev = rev;
     m.rec = rec;
     m.inst = dinst;
+    m.items = items;
+    m.waves = waves;
+    m.rows = jtotal;
     m.ninst = ninst;
     m.nbits = nbits;
-    m.items = items;
     m.smax = smax;
-    m.pad_ = 0;
+    m.slmax = slmax;
     return m;
   }
   int32_t smax = 1;
+  int32_t slmax = 1;
 };
 
 namespace {
@@ -150,9 +152,9 @@ void free_graphs(qw_state* st) {
 
 int step_grid(const qw_state* st) {
   if (st->grid > 0) return st->grid;
-  const int64_t lanes = st->ctx->items * (st->ctx->smax <= 32 ? 2 : 1);  // as in the step kernel
+  const int64_t lanes = st->ctx->waves * qw::kWave;  // one pass of the step kernel
   int64_t g = (lanes + st->block - 1) / st->block;
-  g = std::max<int64_t>(1, std::min<int64_t>(g, 2048));
+  g = std::max<int64_t>(1, std::min<int64_t>(g, qw::kMaxGrid));
   return int(g);
 }
 
@@ -322,7 +324,6 @@ void ctx_release(qw_ctx* ctx) {
   (void)hipDeviceSynchronize();
   ctx->alloc.put(ctx->col);
   ctx->alloc.put(ctx->val);
-  ctx->alloc.put(ctx->rev);
   ctx->alloc.put(ctx->rec);
   ctx->alloc.put(ctx->dinst);
   delete ctx;
@@ -371,7 +372,8 @@ int load_impl(qw_ctx** out, int32_t ninst, const int32_t* n, const int64_t* colp
     hval.resize(size_t(items + slots), 0.0);
     std::copy(ell.col.begin(), ell.col.end(), hcol.begin() + items);
     std::copy(ell.val.begin(), ell.val.end(), hval.begin() + items);
-    for (int64_t q : slot_of) ctx->csc_slot.push_back(q + items);
+    for (int64_t q : slot_of)  // row-major ELL slot j*s + l -> home l*N + j
+      ctx->csc_slot.push_back(items + ((q & (hi.s - 1)) << hi.nbits) + (q >> hi.hbits));
     items += (slots + qw::kWave - 1) / qw::kWave * qw::kWave;
     hcol.resize(size_t(items), 0);
     hval.resize(size_t(items), 0.0);
@@ -390,24 +392,34 @@ int load_impl(qw_ctx** out, int32_t ninst, const int32_t* n, const int64_t* colp
   ctx->jtotal = jbase;
   ctx->ntotal = ntot;
   ctx->nnz_total = nnz_base;
+  // Step-kernel wavefronts: min(s, 8) lanes share a row and hold s / min(s, 8)
+  // slots each, so a wavefront covers 64 / min(s, 8) rows.
   std::vector<qw::Inst> dinst(ninst);
+  int64_t waves = 0;
   for (int32_t i = 0; i < ninst; ++i) {
     const HostInst& hi = ctx->inst[i];
+    const int lpr_log = std::min(hi.hbits, 3);
+    const int rpw_log = 6 - lpr_log;
     dinst[i].item_base = hi.item_base;
     dinst[i].jbase = hi.jbase;
+    dinst[i].wave_base = waves;
     dinst[i].N = hi.N;
     dinst[i].s = hi.s;
     dinst[i].hbits = hi.hbits;
-    dinst[i].pad_ = 0;
+    dinst[i].nlog = hi.nbits;
+    dinst[i].lpr_log = lpr_log;
+    dinst[i].sl = hi.s >> lpr_log;
     dinst[i].inv_sqrt_s = 1.0 / std::sqrt(double(hi.s));
+    waves += (int64_t(hi.N) + (int64_t(1) << rpw_log) - 1) >> rpw_log;
     ctx->smax = std::max(ctx->smax, hi.s);
+    ctx->slmax = std::max(ctx->slmax, dinst[i].sl);
   }
+  ctx->waves = waves;
   ctx->col = static_cast<int32_t*>(ctx->alloc.get(sizeof(int32_t) * items));
   ctx->val = static_cast<double*>(ctx->alloc.get(sizeof(double) * items));
-  ctx->rev = static_cast<int32_t*>(ctx->alloc.get(sizeof(int32_t) * items));
   ctx->rec = static_cast<qw::SlotRec*>(ctx->alloc.get(sizeof(qw::SlotRec) * items));
   ctx->dinst = static_cast<qw::Inst*>(ctx->alloc.get(sizeof(qw::Inst) * ninst));
-  if (!ctx->col || !ctx->val || !ctx->rev || !ctx->rec || !ctx->dinst) {
+  if (!ctx->col || !ctx->val || !ctx->rec || !ctx->dinst) {
     ctx_release(ctx);
     return set_err(QW_ENOMEM, "device allocation failed for the matrix");
   }
@@ -417,7 +429,8 @@ int load_impl(qw_ctx** out, int32_t ninst, const int32_t* n, const int64_t* colp
   if (e == hipSuccess)
     e = hipMemcpyAsync(ctx->dinst, dinst.data(), sizeof(qw::Inst) * ninst, hipMemcpyHostToDevice, stream);
   // O_s'^-1 of every reflected output: the QBS of j in row col[q], once per matrix
-  if (e == hipSuccess) e = qw::launch_qbs_table(ctx->mat(), ctx->rev, ctx->rec, stream);
+  if (e == hipSuccess) e = qw::launch_fill(ctx->rec, int64_t(sizeof(qw::SlotRec)) * items, stream);
+  if (e == hipSuccess) e = qw::launch_qbs_table(ctx->mat(), ctx->rec, stream);
   if (e == hipSuccess) e = hipStreamSynchronize(stream);  // host vectors go out of scope
   if (e != hipSuccess) {
     ctx_release(ctx);
@@ -454,12 +467,12 @@ int state_alloc(qw_ctx* ctx, int64_t list_cap, qw_state** out, hipStream_t strea
   qw_state* st = new qw_state;
   st->ctx = ctx;
   ctx->refs.fetch_add(1);
-  const size_t sb = sizeof(double2) * 2 * ctx->items;
+  const size_t pb = sizeof(double2) * ctx->items;  // one plane
   bool ok = true;
   for (int k = 0; k < 2; ++k) {
-    st->buf[k].R = static_cast<double2*>(state_get(st, sb));
-    st->buf[k].Q = static_cast<double2*>(state_get(st, sb));
-    ok = ok && st->buf[k].R && st->buf[k].Q;
+    double2* p = static_cast<double2*>(state_get(st, 4 * pb));
+    ok = ok && p;
+    st->buf[k] = p ? qw::Slots{p, p + ctx->items, p + 2 * ctx->items, p + 3 * ctx->items} : qw::Slots{};
   }
   st->acc = static_cast<unsigned long long*>(state_get(st, sizeof(unsigned long long) * qw::kMaxGrid));
   st->stepno = static_cast<uint32_t*>(state_get(st, sizeof(uint32_t) * qw::kMaxGrid));
@@ -472,10 +485,7 @@ int state_alloc(qw_ctx* ctx, int64_t list_cap, qw_state** out, hipStream_t strea
     return set_err(QW_ENOMEM, "device allocation failed for the state");
   }
   hipError_t e = hipSuccess;
-  for (int k = 0; k < 2 && e == hipSuccess; ++k) {
-    e = qw::launch_fill(st->buf[k].R, sb, stream);
-    if (e == hipSuccess) e = qw::launch_fill(st->buf[k].Q, sb, stream);
-  }
+  for (int k = 0; k < 2 && e == hipSuccess; ++k) e = qw::launch_fill(st->buf[k].R0, int64_t(4 * pb), stream);
   if (e == hipSuccess) e = qw::launch_fill(st->acc, sizeof(unsigned long long) * qw::kMaxGrid, stream);
   if (e == hipSuccess) e = qw::launch_fill(st->stepno, sizeof(uint32_t) * qw::kMaxGrid, stream);
   if (e == hipSuccess) e = qw::launch_fill(st->b, sizeof(double2) * ctx->jtotal, stream);
@@ -489,11 +499,8 @@ int state_alloc(qw_ctx* ctx, int64_t list_cap, qw_state** out, hipStream_t strea
 
 // Empty the state: both parities cleared, list emptied.
 int state_clear(qw_state* st, hipStream_t stream) {
-  const int64_t sb = sizeof(double2) * 2 * st->ctx->items;
-  for (int k = 0; k < 2; ++k) {
-    QW_HIP(qw::launch_fill(st->buf[k].R, sb, stream));
-    QW_HIP(qw::launch_fill(st->buf[k].Q, sb, stream));
-  }
+  const int64_t sb = int64_t(sizeof(double2)) * 4 * st->ctx->items;  // the four planes, contiguous
+  for (int k = 0; k < 2; ++k) QW_HIP(qw::launch_fill(st->buf[k].R0, sb, stream));
   st->cur = 0;
   st->L.cnt = 0;
   return QW_OK;

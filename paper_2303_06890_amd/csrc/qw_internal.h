@@ -14,32 +14,41 @@ constexpr int kMaxS = 64;       // largest QRAM row length handled (one wave per
 constexpr int kMaxGrid = 8192;  // largest step-kernel grid (per-workgroup counters)
 constexpr double kTau = 1e-13;  // pruning threshold applied after every step
 
-// Per-instance facts, resident on the device.  The ELL slots of instance i
-// are [item_base, item_base + N*s); the base is a multiple of 64 so that a
-// wavefront never straddles two instances.
+// Per-instance facts, resident on the device.  The slots of instance i are
+// [item_base, item_base + N*s); the base is a multiple of 64 so that a
+// wavefront of a pass over slots never straddles two instances.  The ELL
+// arrays col/val hold slot (j, l) at item_base + j*s + l (row-major, for the
+// binary searches); the state planes and the slot records hold it at its
+// home item_base + l*N + j.
 struct Inst {
-  int64_t item_base;  // first ELL slot (= first work item)
+  int64_t item_base;  // first slot
   int64_t jbase;      // offset of this instance in N-vectors
+  int64_t wave_base;  // first wavefront of this instance in the step kernels
   int32_t N;          // padded dimension (power of two)
   int32_t s;          // slots per row (power of two, <= 64)
   int32_t hbits;      // log2 s
-  int32_t pad_;
+  int32_t nlog;       // log2 N
+  int32_t lpr_log;    // log2 of the lanes that share a row in the step kernels: min(s, 8)
+  int32_t sl;         // slots per lane there: s / min(s, 8)
   double inv_sqrt_s;  // 1/sqrt(s)
 };
 
-// Amplitudes with a static home, for every ELL slot q = (inst, j, l):
-//   R[2q + b2]: key (0, j, 0, 0, col[q], b2)                (a group member)
-//   Q[2q + b2]: key S(above) = (0, col[q], b2, 0, j, 0)     when it is not itself
-//               a group member (always for b2 = 1; for b2 = 0 only when
-//               rev[q] < 0); Q[2q] stays 0 when rev[q] >= 0.
-// Interleaved complex double; an exact 0 means "no branch".
+// Amplitudes with a static home, four planes indexed by home h of slot
+// q = (j, l):
+//   R0[h], R1[h]: key K(q, b2) = (0, j, 0, 0, col[q], b2)    (group members)
+//   Q0[h], Q1[h]: key S K(q, b2) = (0, col[q], b2, 0, j, 0)  when it is not
+//                 itself a group member (always for b2 = 1; for b2 = 0 only
+//                 when j is absent from row col[q]); Q0 stays 0 otherwise.
+// Complex double; an exact 0 means "no branch".
 struct Slots {
-  double2* R;
-  double2* Q;
+  double2* R0;
+  double2* R1;
+  double2* Q0;
+  double2* Q1;
 };
 
 // Branches outside the span of those keys (imports, raw starts): the walk
-// maps each to -S(itself), so the list keeps its size and order.
+// maps each to -S(key), so the list keeps its size and order.
 struct List {
   uint64_t* key;
   double2* amp;
@@ -47,24 +56,25 @@ struct List {
   uint32_t cap;
 };
 
-// The three per-slot words the step reads, packed into one 16-byte load.
+// What the step reads of a slot, in one 16-byte load at the slot's home.
 struct SlotRec {
-  int32_t col;
-  int32_t rev;
-  double val;
+  int32_t col;   // column index col[q]
+  int32_t part;  // home of K(q', 0) relative to item_base (q' = (col[q], rev[q])), or -1
+  double val;    // a_{j,l} after scaling
 };
 
 struct Matrix {
-  const int32_t* col;  // ELL column indices, sorted inside each row
-  const double* val;   // ELL values
-  const int32_t* rev;  // rev[q] = position of j in row col[q] (QBS), -1 if absent
-  const SlotRec* rec;  // {col, rev, val} per slot
+  const int32_t* col;  // ELL column indices (row-major), sorted inside each row
+  const double* val;   // ELL values (row-major)
+  const SlotRec* rec;  // slot records (by home)
   const Inst* inst;
+  int64_t items;       // total slots including alignment padding
+  int64_t waves;       // wavefronts of one step-kernel pass
+  int64_t rows;        // sum of N over the instances (length of N-vectors)
   int32_t ninst;
   int32_t nbits;       // register width n of the key layout
-  int64_t items;       // total ELL slots including alignment padding
   int32_t smax;        // largest s over the instances
-  int32_t pad_;
+  int32_t slmax;       // largest slots-per-lane over the instances
 };
 
 enum Mode : int32_t { kStep = 0, kSwap = 1 };
@@ -96,24 +106,25 @@ struct AdjArgs {
 
 // The host side is compiled by the host compiler and the kernels by the GPU
 // compiler; the argument structures must have one layout on both.
-static_assert(sizeof(Inst) == 40 && offsetof(Inst, inv_sqrt_s) == 32, "Inst layout");
-static_assert(sizeof(Slots) == 16, "Slots layout");
+static_assert(sizeof(Inst) == 56 && offsetof(Inst, inv_sqrt_s) == 48, "Inst layout");
+static_assert(sizeof(Slots) == 32, "Slots layout");
 static_assert(sizeof(List) == 24 && offsetof(List, cap) == 20, "List layout");
-static_assert(sizeof(SlotRec) == 16, "SlotRec layout");
-static_assert(sizeof(Matrix) == 64 && offsetof(Matrix, smax) == 56, "Matrix layout");
-static_assert(sizeof(StepArgs) == 168 && offsetof(StepArgs, coefm) == 160, "StepArgs layout");
-static_assert(sizeof(AdjArgs) == 208 && offsetof(AdjArgs, dv) == 200, "AdjArgs layout");
+static_assert(sizeof(SlotRec) == 16 && offsetof(SlotRec, val) == 8, "SlotRec layout");
+static_assert(sizeof(Matrix) == 72 && offsetof(Matrix, slmax) == 68, "Matrix layout");
+static_assert(sizeof(StepArgs) == 208 && offsetof(StepArgs, coefm) == 200, "StepArgs layout");
+static_assert(sizeof(AdjArgs) == 280 && offsetof(AdjArgs, dv) == 272, "AdjArgs layout");
 
 // Launchers (qw_launch.cpp).  All enqueue on `stream` and allocate nothing.
 hipError_t launch_step(const StepArgs& a, int grid, int block, hipStream_t stream);
 hipError_t launch_adjoint(const AdjArgs& a, int grid, int block, hipStream_t stream);
-// rev = QBS table; then rec = {col, rev, val} per slot.
-hipError_t launch_qbs_table(const Matrix& m, int32_t* rev, SlotRec* rec, hipStream_t stream);
+// Slot records (the QBS of every reflected output, once per matrix).
+hipError_t launch_qbs_table(const Matrix& m, SlotRec* rec, hipStream_t stream);
 hipError_t launch_init(const Matrix& m, const double2* b, Slots out, double tau, hipStream_t stream);
 hipError_t launch_fill(void* p, int64_t bytes, hipStream_t stream);
 // Reductions over a state: kind 0 = count, 1 = norm^2 (per-block partials in
 // `partial`, length >= grid); kind 2 = j marginal into out (N-vector, must be
 // zero); kind 3 = projection <psi~_j|state> into out (interleaved complex).
+// `grid` applies to kinds 0 and 1.
 hipError_t launch_measure(const Matrix& m, Slots st, List L, int32_t kind, double* partial, double* out, int grid,
                           hipStream_t stream);
 hipError_t launch_export(const Matrix& m, Slots st, List L, uint64_t* keys, double2* amps, uint32_t* count,

@@ -19,15 +19,23 @@
 // search of j in that row, tabulated once per matrix), and not a member
 // otherwise.  One step later every S K(q, b2) that is not a member is mapped
 // back to K(q, b2) (by -S).  So every branch reachable from T~|b~> has a
-// fixed address: R[q][b2] for K(q, b2), Q[q][b2] for a non-member S K(q, b2).
-// One launch per step reads R_in and Q_in of its slot, reduces the group with
-// wave shuffles, and writes each output to its address for the next step:
-//   R_in  -> reflection -> Q_out[q][1] and R_out[q'][0] (or Q_out[q][0])
-//   Q_in  -> negation   -> R_out[q][b2]
+// fixed address, in four planes indexed by the slot's home
+// h = base + l*N + j (slot-position-major, so that the slots of one position
+// l of consecutive rows are contiguous):
+//   R0[h], R1[h]: K(q, 0), K(q, 1)         (group members)
+//   Q1[h]:        S K(q, 1)
+//   Q0[h]:        S K(q, 0) when rev[q] < 0 (never written otherwise)
+// One launch per step reads the planes of a row's slots, reduces the group
+// across the lanes of the row, and writes each output to its address for the
+// next step:
+//   R0, R1 -> reflection -> Q1_out[h] and R0_out[h'] (or Q0_out[h])
+//   Q1, Q0 -> negation   -> R1_out[h], R0_out[h]
 // Every output address receives exactly one write per step (0 when pruned),
 // so there is no atomic, no compaction and no clearing pass; the result is
-// independent of scheduling.  Branches outside that span (only from raw
-// starts or imports) sit in a list that W maps in place to -S(key).
+// independent of scheduling.  For matrices whose rows share their offset
+// pattern (band and circulant-offset matrices) the partner writes R0_out[h']
+// of a wavefront are contiguous too.  Branches outside that span (only from
+// raw starts or imports) sit in a list that W maps in place to -S(key).
 #include "qw_internal.h"
 
 #include <hip/hip_runtime.h>
@@ -47,6 +55,7 @@ __device__ __forceinline__ double2 cmul(double2 a, double2 b) {
 __device__ __forceinline__ double2 cjmul(double2 a, double2 b) {
   return make_double2(a.x * b.x + a.y * b.y, a.x * b.y - a.y * b.x);
 }
+__device__ __forceinline__ double norm2(double2 a) { return a.x * a.x + a.y * a.y; }
 __device__ __forceinline__ bool kept(double2 v, double tau) { return fabs(v.x) > tau || fabs(v.y) > tau; }
 __device__ __forceinline__ bool nonzero(double2 v) { return v.x != 0.0 || v.y != 0.0; }
 __device__ __forceinline__ double2 zero2() { return make_double2(0.0, 0.0); }
@@ -68,7 +77,7 @@ struct Rot {
 };
 __device__ __forceinline__ Rot rotation(double a, int j, int k) {
   Rot r;
-  const double q = sqrt(fabs(a));  // one square root, no divergent branch
+  const double q = sqrt(fabs(a));  // no divergent branch
   r.f = a >= 0.0 ? make_double2(q, 0.0) : make_double2(0.0, j <= k ? q : -q);
   r.g = sqrt(1.0 - fabs(a));
   return r;
@@ -82,6 +91,10 @@ __device__ __forceinline__ Rot rotation_deriv(double a, int j, int k) {
   const double sg = a > 0.0 ? 1.0 : (a < 0.0 ? -1.0 : 0.0);
   d.g = -sg * 0.5 / sqrt(1.0 - fabs(a));
   return d;
+}
+// conj(f) x0 + g x1: the component of an amplitude pair along sqrt(s) phi
+__device__ __forceinline__ double2 along(const Rot& r, double2 x0, double2 x1) {
+  return cadd(cjmul(r.f, x0), cscale(x1, r.g));
 }
 
 // Quantum binary search (Definition of QBS, Sec. III.A) as a per-branch
@@ -108,40 +121,36 @@ __device__ __forceinline__ double dpp(double v) {
   return __hiloint2double(__builtin_amdgcn_update_dpp(0, hi, CTRL, 0xF, 0xF, false),
                           __builtin_amdgcn_update_dpp(0, lo, CTRL, 0xF, 0xF, false));
 }
-
-template <int CTRL>
-__device__ __forceinline__ double2 dpp_add(double2 v) {
-  return make_double2(v.x + dpp<CTRL>(v.x), v.y + dpp<CTRL>(v.y));
+__device__ __forceinline__ double2 xor_add_8(double2 v) {  // lane ^ 8: rotate each row of 16 lanes by 8
+  return make_double2(v.x + dpp<0x128>(v.x), v.y + dpp<0x128>(v.y));
 }
-
-// Sum over aligned groups of `width` lanes (width a power of two <= 64,
-// uniform across the wavefront).  Each stage adds the value of a partner lane
-// in the other half of the current block (DPP quad permutations and row
-// mirrors inside rows of 16 lanes, lane shuffles beyond), so every lane of a
-// group ends with the bitwise-identical sum.
-__device__ __forceinline__ double2 group_sum(double2 v, int width) {
-  if (width >= 2) v = dpp_add<0xB1>(v);   // quad_perm [1,0,3,2]: lane ^ 1
-  if (width >= 4) v = dpp_add<0x4E>(v);   // quad_perm [2,3,0,1]: lane ^ 2
-  if (width >= 8) v = dpp_add<0x141>(v);  // row_half_mirror: the other quad of 8
-  if (width >= 16) v = dpp_add<0x140>(v); // row_mirror: the other 8 of 16
-  for (int off = 16; off < width; off <<= 1) {
-    v.x += __shfl_xor(v.x, off);
-    v.y += __shfl_xor(v.y, off);
-  }
+__device__ __forceinline__ double2 xor_add(double2 v, int off) {
+  return make_double2(v.x + __shfl_xor(v.x, off), v.y + __shfl_xor(v.y, off));
+}
+// Sum over the lanes that hold one row in the step kernels: lanes
+// jj + h * 2^rpw_log, h < 2^(6 - rpw_log), rpw_log >= 3.  Every lane of a
+// row ends with the bitwise-identical sum (each stage adds a commuted pair).
+__device__ __forceinline__ double2 row_sum(double2 v, int rpw_log) {
+  if (rpw_log <= 3) v = xor_add_8(v);
+  if (rpw_log <= 4) v = xor_add(v, 16);
+  if (rpw_log <= 5) v = xor_add(v, 32);
   return v;
 }
 
-__device__ __forceinline__ int find_inst(const Matrix& m, int64_t item) {
+// Instance whose range starts at or before x (ranges ordered by field F).
+template <int64_t Inst::*F>
+__device__ __forceinline__ int find_inst(const Matrix& m, int64_t x) {
   int lo = 0, hi = m.ninst - 1;
   while (lo < hi) {
     const int mid = (lo + hi + 1) >> 1;
-    if (m.inst[mid].item_base <= item)
+    if (m.inst[mid].*F <= x)
       lo = mid;
     else
       hi = mid - 1;
   }
   return lo;
 }
+__device__ __forceinline__ int uniform(int v) { return __builtin_amdgcn_readfirstlane(v); }
 
 __device__ __forceinline__ uint64_t swap_halves(uint64_t key, int n) {
   const int h = 2 * n + 1;
@@ -160,23 +169,64 @@ __device__ __forceinline__ uint64_t swapped_key(uint64_t inst, int n, int j, int
          (uint64_t(j) << 1);
 }
 
-// Work item of a dense pass: instance (wave-uniform), slot, row, position.
-struct Item {
+// Home of slot (j, l): the state planes and the slot records; the ELL arrays
+// col/val are row-major (base + j*s + l) for the binary searches.
+__device__ __forceinline__ int64_t home(const Inst& I, int j, int l) {
+  return I.item_base + (int64_t(l) << I.nlog) + j;
+}
+
+// A lane of a pass over homes.  `first` is the first home of the lane's
+// wavefront: instances start at multiples of 64, so a wavefront never
+// straddles two and its instance is looked up once, uniformly.
+struct Home {
   Inst I;
   int inst;
   int j, l;
   bool live;
 };
-// `first` is the first slot of the lane's wavefront (a wavefront never
-// straddles two instances, so its instance is looked up once, uniformly).
-__device__ __forceinline__ Item item_of(const Matrix& m, int64_t it, int64_t first) {
-  Item x;
-  x.inst = m.ninst == 1 ? 0 : __builtin_amdgcn_readfirstlane(find_inst(m, first));
-  x.I = m.inst[x.inst];  // uniform address: scalar loads that overlap the data loads
+__device__ __forceinline__ Home home_item(const Matrix& m, int64_t it, int64_t first) {
+  Home x;
+  x.inst = m.ninst == 1 ? 0 : uniform(find_inst<&Inst::item_base>(m, first));
+  x.I = m.inst[x.inst];  // uniform address: scalar loads
   const int64_t local = it - x.I.item_base;
-  x.live = local < int64_t(x.I.N) * x.I.s;
-  x.l = int(local) & (x.I.s - 1);
-  x.j = int(local >> x.I.hbits);
+  x.live = local < (int64_t(x.I.N) << x.I.hbits);
+  x.l = int(local >> x.I.nlog);
+  x.j = int(local & (x.I.N - 1));
+  return x;
+}
+
+// A lane of a pass over rows (one lane per row j of every instance).
+struct Row {
+  Inst I;
+  int inst;
+  int j;
+};
+__device__ __forceinline__ Row row_item(const Matrix& m, int64_t r) {
+  Row x;
+  x.inst = m.ninst == 1 ? 0 : find_inst<&Inst::jbase>(m, r);
+  x.I = m.inst[x.inst];
+  x.j = int(r - x.I.jbase);
+  return x;
+}
+
+// A lane of the step kernels: wavefront w of the instance covers rows
+// [w * 2^rpw_log, (w + 1) * 2^rpw_log); lane = h * 2^rpw_log + jj holds slots
+// l = h * sl + i (i < sl) of row w * 2^rpw_log + jj.
+struct Lanes {
+  Inst I;
+  int inst;
+  int j, h, rpw_log;
+  bool live;
+};
+__device__ __forceinline__ Lanes lanes_of(const Matrix& m, int64_t w, int lane) {
+  Lanes x;
+  x.inst = m.ninst == 1 ? 0 : uniform(find_inst<&Inst::wave_base>(m, w));
+  x.I = m.inst[x.inst];
+  x.rpw_log = 6 - x.I.lpr_log;
+  x.h = lane >> x.rpw_log;
+  const int64_t j = ((w - x.I.wave_base) << x.rpw_log) + (lane & ((1 << x.rpw_log) - 1));
+  x.live = j < x.I.N;
+  x.j = x.live ? int(j) : 0;  // rows past N (instances with N < 2^rpw_log) read row 0 and write nothing
   return x;
 }
 
@@ -202,111 +252,99 @@ __device__ __forceinline__ double block_sum(double v, double* sh) {
   return t;
 }
 
-// Outputs of one slot for the next step (shared by the step and adjoint
-// kernels).  o0, o1: reflected group amplitudes of K(q, b2) before S;
-// n0, n1: outputs of Q_in[q][b2] (already negated or not).
-__device__ __forceinline__ void write_slot(const Slots& out, const Item& x, int64_t q, int colq, int pr, double2 o0,
-                                           double2 o1, double2 n0, double2 n1) {
-  out.Q[2 * q + 1] = o1;
-  if (pr >= 0) {
-    out.R[2 * (x.I.item_base + int64_t(colq) * x.I.s + pr)] = o0;
+// Outputs of one slot for the next step (step and adjoint kernels).
+// o0, o1: reflected (or swapped) group amplitudes of K(q, b2) before S;
+// n1: output of Q1_in; y0: Q0_in (read only for slots without a partner),
+// negated when `neg`.
+__device__ __forceinline__ void write_slot(const Slots& in, const Slots& out, int64_t base, int64_t h,
+                                           const SlotRec& rc, double2 o0, double2 o1, double2 n1, bool neg,
+                                           double tau, unsigned& cnt) {
+  out.Q1[h] = prune(o1, tau, cnt);
+  out.R1[h] = prune(n1, tau, cnt);
+  if (rc.part >= 0) {
+    out.R0[base + rc.part] = prune(o0, tau, cnt);
   } else {
-    out.Q[2 * q] = o0;
-    out.R[2 * q] = n0;
+    const double2 y0 = in.Q0[h];
+    out.Q0[h] = prune(o0, tau, cnt);
+    out.R0[h] = prune(neg ? cneg(y0) : y0, tau, cnt);
   }
-  out.R[2 * q + 1] = n1;
+}
+
+// In-place image of a list entry: W maps it to -S(key), S to S(key).
+__device__ __forceinline__ unsigned list_entry(const List& L, int64_t e, int n, bool neg) {
+  if (e >= int64_t(L.cnt)) return 0;
+  double2 v = L.amp[e];
+  if (neg) v = cneg(v);
+  L.amp[e] = v;
+  L.key[e] = swap_halves(L.key[e], n);
+  return nonzero(v);
 }
 
 // ----------------------------------------------------------------- walk step
 
-// One lane per slot and b2 (groups of 2s lanes, s <= 32).  The data loads of
-// a lane do not depend on each other or on the instance record: padding slots
-// hold zeros (col 0, val 0, rev -1), so every load is in bounds and issued at
-// once.  Returns the number of branches the lane wrote.
-template <bool ACC>
-__device__ __forceinline__ unsigned step_pairs(const Matrix& m, Slots in, Slots out, int32_t mode, double tau,
-                                               double2* yacc, double coef, int64_t it, int64_t first) {
-  const int64_t q = it >> 1;
-  const int b2 = int(it & 1);
-  const SlotRec rc = m.rec[q];
-  const double2 x = in.R[it];
-  const double2 y1 = in.Q[2 * q + 1];  // the b2 = 1 lane's input; same line as its partner lane's
-  const Item xi = item_of(m, q, first);
-  // the lane's component of sqrt(s) phi_j: f for b2 = 0, g for b2 = 1 (one square root)
-  const double a = rc.val;
-  const double sq = sqrt(b2 == 0 ? fabs(a) : 1.0 - fabs(a));
-  const double2 w = (b2 == 1 || a >= 0.0) ? make_double2(sq, 0.0) : make_double2(0.0, xi.j <= rc.col ? sq : -sq);
-  double2 y = b2 == 1 ? y1 : zero2();
-  if (b2 == 0 && rc.rev < 0) y = in.Q[it];  // only slots whose swap is not a group member
-  double2 o = x, n = y;
-  if (mode == kStep) {
-    const double2 c = group_sum(cjmul(w, x), 2 * xi.I.s);
-    if (ACC && xi.live && xi.l == 0 && b2 == 0) {
-      double2 yv = yacc[xi.I.jbase + xi.j];
-      yv.x += coef * (c.x * xi.I.inv_sqrt_s);
-      yv.y += coef * (c.y * xi.I.inv_sqrt_s);
-      yacc[xi.I.jbase + xi.j] = yv;
+// One wavefront of the step: up to SLM slots per lane, held in registers.
+// The data loads do not depend on each other or on the instance record
+// beyond its base, so they are issued together.
+template <bool ACC, int SLM>
+__device__ __forceinline__ unsigned step_wave(const StepArgs& a, int64_t w, int lane, double coef) {
+  const Lanes x = lanes_of(a.m, w, lane);
+  const int sl = SLM == 1 ? 1 : x.I.sl;
+  const int64_t base = x.I.item_base;
+  int64_t h[SLM];
+  SlotRec rc[SLM];
+  double2 x0[SLM], x1[SLM], y1[SLM];
+  Rot r[SLM];
+#pragma unroll
+  for (int i = 0; i < SLM; ++i) {
+    if (i < sl) {
+      h[i] = base + (int64_t(x.h * sl + i) << x.I.nlog) + x.j;
+      rc[i] = a.m.rec[h[i]];
+      x0[i] = a.in.R0[h[i]];
+      x1[i] = a.in.R1[h[i]];
+      y1[i] = a.in.Q1[h[i]];
     }
-    o = csub(cmul(cscale(c, 2.0 / double(xi.I.s)), w), x);
-    n = cneg(y);
   }
-  unsigned cnt = 0;
-  if (!xi.live) return 0;
-  o = prune(o, tau, cnt);
-  if (b2 == 1) {
-    out.Q[it] = o;
-    out.R[it] = prune(n, tau, cnt);
-  } else if (rc.rev >= 0) {
-    out.R[2 * (xi.I.item_base + int64_t(rc.col) * xi.I.s + rc.rev)] = o;
-  } else {
-    out.Q[it] = o;
-    out.R[it] = prune(n, tau, cnt);
-  }
-  return cnt;
-}
-
-// One lane per slot (both b2), for s = 64 where a group fills a wavefront.
-template <bool ACC>
-__device__ __forceinline__ unsigned step_slot(const Matrix& m, Slots in, Slots out, int32_t mode, double tau,
-                                              double2* yacc, double coef, int64_t it, int64_t first) {
-  const double2 x0 = in.R[2 * it], x1 = in.R[2 * it + 1];
-  const double2 y0 = in.Q[2 * it], y1 = in.Q[2 * it + 1];
-  const int colq = m.col[it];
-  const double v = m.val[it];
-  const int pr = m.rev[it];
-  const Item x = item_of(m, it, first);
-  const Rot r = rotation(v, x.j, colq);
-  double2 o0 = x0, o1 = x1, n0 = y0, n1 = y1;
-  if (mode == kStep) {
-    const double2 c = group_sum(cadd(cjmul(r.f, x0), cscale(x1, r.g)), x.I.s);
-    if (ACC && x.live && x.l == 0) {
-      double2 yv = yacc[x.I.jbase + x.j];
-      yv.x += coef * (c.x * x.I.inv_sqrt_s);
-      yv.y += coef * (c.y * x.I.inv_sqrt_s);
-      yacc[x.I.jbase + x.j] = yv;
+  const bool step = a.mode == kStep;
+  double2 c = zero2();
+#pragma unroll
+  for (int i = 0; i < SLM; ++i) {
+    if (i < sl) {
+      r[i] = rotation(rc[i].val, x.j, rc[i].col);
+      c = cadd(c, along(r[i], x0[i], x1[i]));
     }
-    const double2 tc = cscale(c, 2.0 / double(x.I.s));
-    o0 = csub(cmul(tc, r.f), x0);
-    o1 = csub(cscale(tc, r.g), x1);
-    n0 = cneg(y0);
-    n1 = cneg(y1);
   }
-  unsigned cnt = 0;
+  if (step) c = row_sum(c, x.rpw_log);
+  if (ACC && x.live && x.h == 0) {
+    double2 yv = a.yacc[x.I.jbase + x.j];
+    yv.x += coef * (c.x * x.I.inv_sqrt_s);
+    yv.y += coef * (c.y * x.I.inv_sqrt_s);
+    a.yacc[x.I.jbase + x.j] = yv;
+  }
   if (!x.live) return 0;
-  o0 = prune(o0, tau, cnt);
-  o1 = prune(o1, tau, cnt);
-  n1 = prune(n1, tau, cnt);
-  if (pr < 0) n0 = prune(n0, tau, cnt);
-  write_slot(out, x, it, colq, pr, o0, o1, n0, n1);
+  const double2 tc = cscale(c, 2.0 / double(x.I.s));
+  unsigned cnt = 0;
+#pragma unroll
+  for (int i = 0; i < SLM; ++i) {
+    if (i < sl) {
+      double2 o0 = x0[i], o1 = x1[i], n1 = y1[i];
+      if (step) {
+        o0 = csub(cmul(tc, r[i].f), x0[i]);
+        o1 = csub(cscale(tc, r[i].g), x1[i]);
+        n1 = cneg(y1[i]);
+      }
+      write_slot(a.in, a.out, base, h[i], rc[i], o0, o1, n1, step, a.tau, cnt);
+    }
+  }
   return cnt;
 }
 
-// LPS: lanes per slot (2 when every s <= 32, else 1).
-template <bool ACC, int LPS>
-__device__ __forceinline__ void step_body(StepArgs a) {
+template <bool ACC, int SLM>
+__device__ __forceinline__ void step_body(const StepArgs& a) {
   __shared__ unsigned long long sh[16];
-  const int64_t A = a.m.items * LPS;
-  const int64_t total = A + ((int64_t(a.L.cnt) + kWave - 1) & ~int64_t(kWave - 1));
+  const int lane = threadIdx.x & (kWave - 1);
+  const int64_t wpb = blockDim.x >> 6;
+  const int64_t lw = (int64_t(a.L.cnt) + kWave - 1) / kWave;
+  const int64_t total = a.m.waves + lw;
   double coef = 0.0;
   uint32_t stepno = 0;
   if (ACC) {
@@ -314,24 +352,12 @@ __device__ __forceinline__ void step_body(StepArgs a) {
     coef = a.coefm[stepno];
   }
   unsigned cnt = 0;
-  const int64_t stride = int64_t(gridDim.x) * blockDim.x;
-  const int lane = threadIdx.x & (kWave - 1);
-  for (int64_t it = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; it < total; it += stride) {
-    if (it < A) {
-      if (LPS == 2)
-        cnt += step_pairs<ACC>(a.m, a.in, a.out, a.mode, a.tau, a.yacc, coef, it, (it - lane) >> 1);
-      else
-        cnt += step_slot<ACC>(a.m, a.in, a.out, a.mode, a.tau, a.yacc, coef, it, it - lane);
-    } else {
-      const int64_t e = it - A;
-      if (e < int64_t(a.L.cnt)) {
-        double2 v = a.L.amp[e];
-        if (a.mode == kStep) v = cneg(v);
-        a.L.amp[e] = v;
-        a.L.key[e] = swap_halves(a.L.key[e], a.m.nbits);
-        cnt += nonzero(v);
-      }
-    }
+  const int64_t wstride = int64_t(gridDim.x) * wpb;
+  for (int64_t w = uniform(int(blockIdx.x * wpb + (threadIdx.x >> 6))); w < total; w += wstride) {
+    if (w < a.m.waves)
+      cnt += step_wave<ACC, SLM>(a, w, lane, coef);
+    else
+      cnt += list_entry(a.L, (w - a.m.waves) * kWave + lane, a.m.nbits, a.mode == kStep);
   }
   const unsigned long long t = block_sum_u64(cnt, sh);
   if (threadIdx.x == 0) {
@@ -342,36 +368,42 @@ __device__ __forceinline__ void step_body(StepArgs a) {
 
 }  // namespace qw
 
-extern "C" __global__ void __launch_bounds__(256) qwk_step2(qw::StepArgs a) { qw::step_body<false, 2>(a); }
-extern "C" __global__ void __launch_bounds__(256) qwk_step2_acc(qw::StepArgs a) { qw::step_body<true, 2>(a); }
-extern "C" __global__ void __launch_bounds__(256) qwk_step1(qw::StepArgs a) { qw::step_body<false, 1>(a); }
-extern "C" __global__ void __launch_bounds__(256) qwk_step1_acc(qw::StepArgs a) { qw::step_body<true, 1>(a); }
+#define QW_STEP_KERNELS(S)                                                                          \
+  extern "C" __global__ void __launch_bounds__(256) qwk_step_s##S(qw::StepArgs a) {                \
+    qw::step_body<false, S>(a);                                                                     \
+  }                                                                                                 \
+  extern "C" __global__ void __launch_bounds__(256) qwk_step_s##S##_acc(qw::StepArgs a) {          \
+    qw::step_body<true, S>(a);                                                                      \
+  }
+QW_STEP_KERNELS(1)
+QW_STEP_KERNELS(2)
+QW_STEP_KERNELS(4)
+QW_STEP_KERNELS(8)
+#undef QW_STEP_KERNELS
 
 namespace qw {
 
 // ----------------------------------------------------------------- QBS table
-// rev[q] = i_{col[q]}(j): where row j's slot q points back into its column's
-// row, or -1 (filler or asymmetric pattern).
+// rev = i_{col[q]}(j): where row j's slot q points back into its column's
+// row (-1: filler or asymmetric pattern).  The record of slot (j, l) at its
+// home holds col, the partner's home relative to the instance base
+// (rev * N + col, or -1) and the value.
 
-extern "C" __global__ void __launch_bounds__(256) qwk_qbs_table(Matrix m, int32_t* rev, SlotRec* rec) {
+extern "C" __global__ void __launch_bounds__(256) qwk_qbs_table(Matrix m, SlotRec* rec) {
   const int64_t stride = int64_t(gridDim.x) * blockDim.x;
   for (int64_t it = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; it < m.items; it += stride) {
-    const int ii = find_inst(m, it);
-    const Inst I = m.inst[ii];
+    const Inst I = m.inst[find_inst<&Inst::item_base>(m, it)];
     const int64_t local = it - I.item_base;
-    int32_t r = -1;
-    if (local < int64_t(I.N) * I.s) {
-      const int j = int(local >> I.hbits);
-      const int c = m.col[it];
-      int p;
-      if (qbs(m.col + I.item_base + int64_t(c) * I.s, I.s, j, p)) r = p;
-    }
-    rev[it] = r;
+    if (local >= (int64_t(I.N) << I.hbits)) continue;
+    const int j = int(local >> I.hbits);
+    const int l = int(local & (I.s - 1));
+    const int c = m.col[it];
+    int p;
     SlotRec sr;
-    sr.col = m.col[it];
-    sr.rev = r;
+    sr.col = c;
+    sr.part = qbs(m.col + I.item_base + (int64_t(c) << I.hbits), I.s, j, p) ? (p << I.nlog) + c : -1;
     sr.val = m.val[it];
-    rec[it] = sr;
+    rec[home(I, j, l)] = sr;
   }
 }
 
@@ -383,85 +415,95 @@ extern "C" __global__ void __launch_bounds__(256) qwk_qbs_table(Matrix m, int32_
 //                              + conj(d) (conj(f') psi'_0 + g' psi'_1) ) ]
 // with chi, mu the group amplitudes of Psi_t and Lambda_t, c, d their group
 // sums, and psi' = (2/s) c phi - chi the forward state before the reflection
-// of step t.
+// of step t.  dv is indexed by home.
 
-extern "C" __global__ void __launch_bounds__(256) qwk_adjoint(AdjArgs a) {
-  __shared__ unsigned long long sh[16];
-  const int n = a.m.nbits;
-  const int64_t A = a.m.items;
-  const int64_t padL = (int64_t(a.L.cnt) + kWave - 1) & ~int64_t(kWave - 1);
-  const int64_t padLL = (int64_t(a.LL.cnt) + kWave - 1) & ~int64_t(kWave - 1);
-  const int64_t total = A + padL + padLL;
-  unsigned cnt = 0, lcnt = 0;
-  const int64_t stride = int64_t(gridDim.x) * blockDim.x;
-  for (int64_t it = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; it < total; it += stride) {
-    if (it < A) {
-      const Item x = item_of(a.m, it, it - (threadIdx.x & (kWave - 1)));
-      double2 x0 = zero2(), x1 = zero2(), m0 = zero2(), m1 = zero2();
-      double2 y0 = zero2(), y1 = zero2(), z0 = zero2(), z1 = zero2();
-      Rot r, d;
-      r.f = zero2();
-      r.g = 0.0;
-      d = r;
-      int colq = 0, pr = -1;
-      if (x.live) {
-        x0 = a.in.R[2 * it];
-        x1 = a.in.R[2 * it + 1];
-        m0 = a.lin.R[2 * it];
-        m1 = a.lin.R[2 * it + 1];
-        y1 = a.in.Q[2 * it + 1];
-        z1 = a.lin.Q[2 * it + 1];
-        colq = a.m.col[it];
-        pr = a.m.rev[it];
-        if (pr < 0) {
-          y0 = a.in.Q[2 * it];
-          z0 = a.lin.Q[2 * it];
-        }
-        const double v = a.m.val[it];
-        r = rotation(v, x.j, colq);
-        d = rotation_deriv(v, x.j, colq);
-      }
-      const double2 c = group_sum(cadd(cjmul(r.f, x0), cscale(x1, r.g)), x.I.s);
-      const double2 dd = group_sum(cadd(cjmul(r.f, m0), cscale(m1, r.g)), x.I.s);
-      const double t = 2.0 / double(x.I.s);
-      const double2 tc = cscale(c, t), td = cscale(dd, t);
-      double2 q0 = csub(cmul(tc, r.f), x0);  // psi'
-      double2 q1 = csub(cscale(tc, r.g), x1);
-      double2 w0 = csub(cmul(td, r.f), m0);  // reflected adjoint
-      double2 w1 = csub(cscale(td, r.g), m1);
-      if (x.live) {
-        // c (conj(mu_0) f' + conj(mu_1) g') + conj(d) (conj(f') psi'_0 + g' psi'_1)
-        const double2 u = cadd(cmul(c, cadd(cjmul(m0, d.f), make_double2(m1.x * d.g, -m1.y * d.g))),
-                               cjmul(dd, cadd(cjmul(d.f, q0), cscale(q1, d.g))));
-        a.dv[it] += 2.0 * t * u.x;
-        q0 = prune(q0, a.tau, cnt);
-        q1 = prune(q1, a.tau, cnt);
-        const double2 ny1 = prune(cneg(y1), a.tau, cnt);
-        const double2 ny0 = pr < 0 ? prune(cneg(y0), a.tau, cnt) : zero2();
-        write_slot(a.out, x, it, colq, pr, q0, q1, ny0, ny1);
-        w0 = prune(w0, a.tau, lcnt);
-        w1 = prune(w1, a.tau, lcnt);
-        const double2 nz1 = prune(cneg(z1), a.tau, lcnt);
-        const double2 nz0 = pr < 0 ? prune(cneg(z0), a.tau, lcnt) : zero2();
-        write_slot(a.lout, x, it, colq, pr, w0, w1, nz0, nz1);
-      }
-    } else {
-      const bool second = it >= A + padL;
-      const int64_t e = second ? it - A - padL : it - A;
-      const List& Ls = second ? a.LL : a.L;
-      if (e < int64_t(Ls.cnt)) {
-        const double2 v = cneg(Ls.amp[e]);
-        Ls.amp[e] = v;
-        Ls.key[e] = swap_halves(Ls.key[e], n);
-        (second ? lcnt : cnt) += nonzero(v);
-      }
+template <int SLM>
+__device__ __forceinline__ void adjoint_wave(const AdjArgs& a, int64_t w, int lane, unsigned& cnt,
+                                             unsigned& lcnt) {
+  const Lanes x = lanes_of(a.m, w, lane);
+  const int sl = SLM == 1 ? 1 : x.I.sl;
+  const int64_t base = x.I.item_base;
+  int64_t h[SLM];
+  SlotRec rc[SLM];
+  double2 x0[SLM], x1[SLM], y1[SLM], m0[SLM], m1[SLM], z1[SLM];
+  Rot r[SLM];
+#pragma unroll
+  for (int i = 0; i < SLM; ++i) {
+    if (i < sl) {
+      h[i] = base + (int64_t(x.h * sl + i) << x.I.nlog) + x.j;
+      rc[i] = a.m.rec[h[i]];
+      x0[i] = a.in.R0[h[i]];
+      x1[i] = a.in.R1[h[i]];
+      y1[i] = a.in.Q1[h[i]];
+      m0[i] = a.lin.R0[h[i]];
+      m1[i] = a.lin.R1[h[i]];
+      z1[i] = a.lin.Q1[h[i]];
     }
+  }
+  double2 c = zero2(), d = zero2();
+#pragma unroll
+  for (int i = 0; i < SLM; ++i) {
+    if (i < sl) {
+      r[i] = rotation(rc[i].val, x.j, rc[i].col);
+      c = cadd(c, along(r[i], x0[i], x1[i]));
+      d = cadd(d, along(r[i], m0[i], m1[i]));
+    }
+  }
+  c = row_sum(c, x.rpw_log);
+  d = row_sum(d, x.rpw_log);
+  if (!x.live) return;
+  const double t = 2.0 / double(x.I.s);
+  const double2 tc = cscale(c, t), td = cscale(d, t);
+#pragma unroll
+  for (int i = 0; i < SLM; ++i) {
+    if (i < sl) {
+      const double2 q0 = csub(cmul(tc, r[i].f), x0[i]);  // psi'
+      const double2 q1 = csub(cscale(tc, r[i].g), x1[i]);
+      const double2 w0 = csub(cmul(td, r[i].f), m0[i]);  // reflected adjoint
+      const double2 w1 = csub(cscale(td, r[i].g), m1[i]);
+      const Rot dr = rotation_deriv(rc[i].val, x.j, rc[i].col);
+      // c (conj(mu_0) f' + conj(mu_1) g') + conj(d) (conj(f') psi'_0 + g' psi'_1)
+      const double2 u = cadd(cmul(c, cadd(cjmul(m0[i], dr.f), make_double2(m1[i].x * dr.g, -m1[i].y * dr.g))),
+                             cjmul(d, cadd(cjmul(dr.f, q0), cscale(q1, dr.g))));
+      a.dv[h[i]] += 2.0 * t * u.x;
+      write_slot(a.in, a.out, base, h[i], rc[i], q0, q1, cneg(y1[i]), true, a.tau, cnt);
+      write_slot(a.lin, a.lout, base, h[i], rc[i], w0, w1, cneg(z1[i]), true, a.tau, lcnt);
+    }
+  }
+}
+
+template <int SLM>
+__device__ __forceinline__ void adjoint_body(const AdjArgs& a) {
+  __shared__ unsigned long long sh[16];
+  const int lane = threadIdx.x & (kWave - 1);
+  const int64_t wpb = blockDim.x >> 6;
+  const int64_t lw = (int64_t(a.L.cnt) + kWave - 1) / kWave;
+  const int64_t llw = (int64_t(a.LL.cnt) + kWave - 1) / kWave;
+  const int64_t total = a.m.waves + lw + llw;
+  unsigned cnt = 0, lcnt = 0;
+  const int64_t wstride = int64_t(gridDim.x) * wpb;
+  for (int64_t w = uniform(int(blockIdx.x * wpb + (threadIdx.x >> 6))); w < total; w += wstride) {
+    if (w < a.m.waves)
+      adjoint_wave<SLM>(a, w, lane, cnt, lcnt);
+    else if (w < a.m.waves + lw)
+      cnt += list_entry(a.L, (w - a.m.waves) * kWave + lane, a.m.nbits, true);
+    else
+      lcnt += list_entry(a.LL, (w - a.m.waves - lw) * kWave + lane, a.m.nbits, true);
   }
   const unsigned long long t1 = block_sum_u64(cnt, sh);
   if (threadIdx.x == 0) a.acc[blockIdx.x] += t1;
   const unsigned long long t2 = block_sum_u64(lcnt, sh);
   if (threadIdx.x == 0) a.lacc[blockIdx.x] += t2;
 }
+
+}  // namespace qw
+
+extern "C" __global__ void __launch_bounds__(256) qwk_adjoint_s1(qw::AdjArgs a) { qw::adjoint_body<1>(a); }
+extern "C" __global__ void __launch_bounds__(256) qwk_adjoint_s2(qw::AdjArgs a) { qw::adjoint_body<2>(a); }
+extern "C" __global__ void __launch_bounds__(256) qwk_adjoint_s4(qw::AdjArgs a) { qw::adjoint_body<4>(a); }
+extern "C" __global__ void __launch_bounds__(256) qwk_adjoint_s8(qw::AdjArgs a) { qw::adjoint_body<8>(a); }
+
+namespace qw {
 
 // ----------------------------------------------------------------- T~ |b~>
 // T~ on |0, j, 0, 0, 0, 0> gives the group of j with amplitudes b_j phi_j:
@@ -471,19 +513,17 @@ extern "C" __global__ void __launch_bounds__(256) qwk_init(Matrix m, const doubl
                                                            double tau) {
   const int64_t stride = int64_t(gridDim.x) * blockDim.x;
   for (int64_t it = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; it < m.items; it += stride) {
-    const int ii = find_inst(m, it);
-    const Inst I = m.inst[ii];
-    const int64_t local = it - I.item_base;
-    if (local >= int64_t(I.N) * I.s) continue;
-    const int j = int(local >> I.hbits);
-    const Rot r = rotation(m.val[it], j, m.col[it]);
-    const double2 bj = cscale(b[I.jbase + j], I.inv_sqrt_s);
+    const Home x = home_item(m, it, it - (threadIdx.x & (kWave - 1)));
+    if (!x.live) continue;
+    const SlotRec rc = m.rec[it];
+    const Rot r = rotation(rc.val, x.j, rc.col);
+    const double2 bj = cscale(b[x.I.jbase + x.j], x.I.inv_sqrt_s);
     double2 o0 = cmul(r.f, bj);
     double2 o1 = cscale(bj, r.g);
     if (!kept(o0, tau)) o0 = zero2();
     if (!kept(o1, tau)) o1 = zero2();
-    out.R[2 * it] = o0;
-    out.R[2 * it + 1] = o1;
+    out.R0[it] = o0;
+    out.R1[it] = o1;
   }
 }
 
@@ -497,72 +537,73 @@ extern "C" __global__ void qwk_fill(uint4* p, int64_t n16) {
 
 // ----------------------------------------------------------------- measurements
 
-// kind 0: count, 1: norm^2 -> partial[block]; kind 2: j marginal (atomics
-// into out, which starts at zero); kind 3: projection (stored).
+// Over homes and the list: kind 0 = branch count, 1 = norm^2, as per-block
+// partials.
 extern "C" __global__ void __launch_bounds__(256) qwk_measure(Matrix m, Slots st, List L, int32_t kind,
-                                                              double* partial, double* out) {
+                                                              double* partial) {
   __shared__ double sh[16];
-  const int n = m.nbits;
-  const uint64_t nm = (uint64_t(1) << n) - 1;
   const int64_t total = m.items + ((int64_t(L.cnt) + kWave - 1) & ~int64_t(kWave - 1));
   double acc = 0.0;
   const int64_t stride = int64_t(gridDim.x) * blockDim.x;
   for (int64_t it = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; it < total; it += stride) {
+    double2 v[4] = {zero2(), zero2(), zero2(), zero2()};
     if (it < m.items) {
-      const Item x = item_of(m, it, it - (threadIdx.x & (kWave - 1)));
-      double2 p0 = zero2(), p1 = zero2(), s0 = zero2(), s1 = zero2();
-      int colq = 0;
+      const Home x = home_item(m, it, it - (threadIdx.x & (kWave - 1)));
       if (x.live) {
-        p0 = st.R[2 * it];
-        p1 = st.R[2 * it + 1];
-        s0 = st.Q[2 * it];
-        s1 = st.Q[2 * it + 1];
-        colq = m.col[it];
+        v[0] = st.R0[it];
+        v[1] = st.R1[it];
+        v[2] = st.Q0[it];
+        v[3] = st.Q1[it];
       }
-      if (kind == 0) {
-        acc += double(int(nonzero(p0)) + int(nonzero(p1)) + int(nonzero(s0)) + int(nonzero(s1)));
-      } else if (kind == 1) {
-        acc += p0.x * p0.x + p0.y * p0.y + p1.x * p1.x + p1.y * p1.y + s0.x * s0.x + s0.y * s0.y + s1.x * s1.x +
-               s1.y * s1.y;
-      } else if (kind == 2) {
-        double2 q = make_double2(p0.x * p0.x + p0.y * p0.y + p1.x * p1.x + p1.y * p1.y, 0.0);
-        q = group_sum(q, x.I.s);
-        if (x.live) {
-          if (x.l == 0) atomicAdd(&out[x.I.jbase + x.j], q.x);
-          const double sw = s0.x * s0.x + s0.y * s0.y + s1.x * s1.x + s1.y * s1.y;
-          if (sw != 0.0) atomicAdd(&out[x.I.jbase + colq], sw);
-        }
-      } else {
-        Rot r;
-        r.f = zero2();
-        r.g = 0.0;
-        if (x.live) r = rotation(m.val[it], x.j, colq);
-        const double2 c = group_sum(cadd(cjmul(r.f, p0), cscale(p1, r.g)), x.I.s);
-        if (x.live && x.l == 0) {
-          out[2 * (x.I.jbase + x.j)] = c.x * x.I.inv_sqrt_s;
-          out[2 * (x.I.jbase + x.j) + 1] = c.y * x.I.inv_sqrt_s;
-        }
-      }
-    } else {
-      const int64_t e = it - m.items;
-      if (e < int64_t(L.cnt)) {
-        const double2 v = L.amp[e];
-        if (kind == 0) {
-          acc += double(nonzero(v));
-        } else if (kind == 1) {
-          acc += v.x * v.x + v.y * v.y;
-        } else if (kind == 2) {
-          const uint64_t key = L.key[e];
-          const uint64_t inst = key >> (4 * n + 2);
-          const int j = int((key >> (2 * n + 2)) & nm);
-          if (inst < uint64_t(m.ninst)) atomicAdd(&out[m.inst[inst].jbase + j], v.x * v.x + v.y * v.y);
-        }
-      }
+    } else if (it - m.items < int64_t(L.cnt)) {
+      v[0] = L.amp[it - m.items];
     }
+    for (int i = 0; i < 4; ++i) acc += kind == 0 ? double(nonzero(v[i])) : norm2(v[i]);
   }
-  if (kind <= 1) {
-    const double t = block_sum(acc, sh);
-    if (threadIdx.x == 0) partial[blockIdx.x] = t;
+  const double t = block_sum(acc, sh);
+  if (threadIdx.x == 0) partial[blockIdx.x] = t;
+}
+
+// Over rows (one lane per row) and the list: kind 2 = j-register marginal
+// (atomics into out, an N-vector that starts at zero), kind 3 = projection
+// <psi~_j|state> (interleaved complex, stored).
+extern "C" __global__ void __launch_bounds__(256) qwk_measure_rows(Matrix m, Slots st, List L, int32_t kind,
+                                                                   double* out) {
+  const int n = m.nbits;
+  const uint64_t nm = (uint64_t(1) << n) - 1;
+  const int64_t total = m.rows + int64_t(L.cnt);
+  const int64_t stride = int64_t(gridDim.x) * blockDim.x;
+  for (int64_t it = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; it < total; it += stride) {
+    if (it < m.rows) {
+      const Row x = row_item(m, it);
+      double p = 0.0;
+      double2 c = zero2();
+      for (int l = 0; l < x.I.s; ++l) {
+        const int64_t h = home(x.I, x.j, l);
+        const double2 p0 = st.R0[h], p1 = st.R1[h];
+        if (kind == 2) {
+          p += norm2(p0) + norm2(p1);
+          const double sw = norm2(st.Q0[h]) + norm2(st.Q1[h]);
+          if (sw != 0.0) atomicAdd(&out[x.I.jbase + m.rec[h].col], sw);
+        } else {
+          const SlotRec rc = m.rec[h];
+          c = cadd(c, along(rotation(rc.val, x.j, rc.col), p0, p1));
+        }
+      }
+      if (kind == 2) {
+        if (p != 0.0) atomicAdd(&out[it], p);
+      } else {
+        out[2 * it] = c.x * x.I.inv_sqrt_s;
+        out[2 * it + 1] = c.y * x.I.inv_sqrt_s;
+      }
+    } else if (kind == 2) {
+      const int64_t e = it - m.rows;
+      const double2 v = L.amp[e];
+      const uint64_t key = L.key[e];
+      const uint64_t inst = key >> (4 * n + 2);
+      const int j = int((key >> (2 * n + 2)) & nm);
+      if (inst < uint64_t(m.ninst) && norm2(v) != 0.0) atomicAdd(&out[m.inst[inst].jbase + j], norm2(v));
+    }
   }
 }
 
@@ -606,17 +647,18 @@ extern "C" __global__ void __launch_bounds__(256) qwk_export(Matrix m, Slots st,
     uint64_t k[4] = {0, 0, 0, 0};
     double2 v[4] = {zero2(), zero2(), zero2(), zero2()};
     if (it < m.items) {
-      const Item x = item_of(m, it, it - (threadIdx.x & (kWave - 1)));
+      const Home x = home_item(m, it, it - (threadIdx.x & (kWave - 1)));
       if (x.live) {
-        const int colq = m.col[it];
+        const int colq = m.rec[it].col;
+        v[0] = st.R0[it];
+        v[1] = st.R1[it];
+        v[2] = st.Q0[it];
+        v[3] = st.Q1[it];
         for (int b2 = 0; b2 < 2; ++b2) {
-          v[b2] = st.R[2 * it + b2];
-          app[b2] = nonzero(v[b2]);
           k[b2] = member_key(uint64_t(x.inst), n, x.j, colq, b2);
-          v[2 + b2] = st.Q[2 * it + b2];
-          app[2 + b2] = nonzero(v[2 + b2]);
           k[2 + b2] = swapped_key(uint64_t(x.inst), n, x.j, colq, b2);
         }
+        for (int i = 0; i < 4; ++i) app[i] = nonzero(v[i]);
       }
     } else {
       const int64_t e = it - m.items;
@@ -630,7 +672,8 @@ extern "C" __global__ void __launch_bounds__(256) qwk_export(Matrix m, Slots st,
   }
 }
 
-// Home of a key: 0 = R (group member), 1 = Q (swap of a member), 2 = list.
+// Static home of a key: 0..3 = plane R0, R1, Q0, Q1 (at home idx), 4 = none
+// (the list).
 __device__ __forceinline__ int home_of(const Matrix& m, uint64_t key, int64_t& idx) {
   const int n = m.nbits;
   const uint64_t nm = (uint64_t(1) << n) - 1;
@@ -641,20 +684,20 @@ __device__ __forceinline__ int home_of(const Matrix& m, uint64_t key, int64_t& i
   const int j = int((key >> (2 * n + 2)) & nm);
   const uint64_t jc = (key >> (3 * n + 2)) & nm;
   const uint64_t inst = key >> (4 * n + 2);
-  if (jc != 0 || kc != 0 || inst >= uint64_t(m.ninst)) return 2;
+  if (jc != 0 || kc != 0 || inst >= uint64_t(m.ninst)) return 4;
   const Inst I = m.inst[inst];
-  if (j >= I.N || k >= I.N) return 2;
+  if (j >= I.N || k >= I.N) return 4;
   int p;
-  if (b1 == 0 && qbs(m.col + I.item_base + int64_t(j) * I.s, I.s, k, p)) {
-    idx = 2 * (I.item_base + int64_t(j) * I.s + p) + b2;
-    return 0;
+  if (b1 == 0 && qbs(m.col + I.item_base + (int64_t(j) << I.hbits), I.s, k, p)) {
+    idx = home(I, j, p);
+    return b2;
   }
   // (0, J, B1, 0, K, 0) = S K(q, B1) with q = (K, position of J in row K)
-  if (b2 == 0 && qbs(m.col + I.item_base + int64_t(k) * I.s, I.s, j, p)) {
-    idx = 2 * (I.item_base + int64_t(k) * I.s + p) + b1;
-    return 1;
+  if (b2 == 0 && qbs(m.col + I.item_base + (int64_t(k) << I.hbits), I.s, j, p)) {
+    idx = home(I, k, p);
+    return 2 + b1;
   }
-  return 2;
+  return 4;
 }
 
 extern "C" __global__ void __launch_bounds__(256) qwk_import(Matrix m, const uint64_t* keys, const double2* amps,
@@ -671,9 +714,13 @@ extern "C" __global__ void __launch_bounds__(256) qwk_import(Matrix m, const uin
       int64_t idx = 0;
       const int h = home_of(m, k[0], idx);
       if (h == 0)
-        out.R[idx] = v[0];
+        out.R0[idx] = v[0];
       else if (h == 1)
-        out.Q[idx] = v[0];
+        out.R1[idx] = v[0];
+      else if (h == 2)
+        out.Q0[idx] = v[0];
+      else if (h == 3)
+        out.Q1[idx] = v[0];
       else
         app[0] = true;
     }
@@ -697,17 +744,16 @@ extern "C" __global__ void __launch_bounds__(256) qwk_weight(Matrix m, Slots in,
   const int64_t stride = int64_t(gridDim.x) * blockDim.x;
   for (int64_t it = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; it < total; it += stride) {
     if (it < m.items) {
-      const Item x = item_of(m, it, it - (threadIdx.x & (kWave - 1)));
+      const Home x = home_item(m, it, it - (threadIdx.x & (kWave - 1)));
       if (x.live) {
-        const double wr = w[x.I.jbase + m.col[it]];
+        const double wr = w[x.I.jbase + m.rec[it].col];
         const double wq = w[x.I.jbase + x.j];
-        for (int b2 = 0; b2 < 2; ++b2) {
-          const double2 p = in.R[2 * it + b2];
-          const double2 s = in.Q[2 * it + b2];
-          acc += wr * (p.x * p.x + p.y * p.y) + wq * (s.x * s.x + s.y * s.y);
-          out.R[2 * it + b2] = cscale(p, wr);
-          out.Q[2 * it + b2] = cscale(s, wq);
-        }
+        const double2 p0 = in.R0[it], p1 = in.R1[it], s0 = in.Q0[it], s1 = in.Q1[it];
+        acc += wr * (norm2(p0) + norm2(p1)) + wq * (norm2(s0) + norm2(s1));
+        out.R0[it] = cscale(p0, wr);
+        out.R1[it] = cscale(p1, wr);
+        out.Q0[it] = cscale(s0, wq);
+        out.Q1[it] = cscale(s1, wq);
       }
     } else {
       const int64_t e = it - m.items;
@@ -717,7 +763,7 @@ extern "C" __global__ void __launch_bounds__(256) qwk_weight(Matrix m, Slots in,
         const uint64_t inst = key >> (4 * n + 2);
         const int k = int((key >> 1) & nm);
         const double wk = inst < uint64_t(m.ninst) ? w[m.inst[inst].jbase + k] : 0.0;
-        acc += wk * (p.x * p.x + p.y * p.y);
+        acc += wk * norm2(p);
         LL.key[e] = key;
         LL.amp[e] = cscale(p, wk);
       }
@@ -727,32 +773,27 @@ extern "C" __global__ void __launch_bounds__(256) qwk_weight(Matrix m, Slots in,
   if (threadIdx.x == 0) partial[blockIdx.x] = t;
 }
 
-// Gradient through the initial T~: psi_0 holds b_j phi_j in the group of j,
-// so dL/dv_{jl} += 2 Re[b_j (conj(nu_0) f' + conj(nu_1) g')] / sqrt(s) with
-// nu the group amplitudes of lambda_0, and dL/db_j = 2 <psi~_j|lambda_0>.
+// Gradient through the initial T~ (one lane per row): psi_0 holds b_j phi_j
+// in the group of j, so dL/dv_{jl} += 2 Re[b_j (conj(nu_0) f' + conj(nu_1) g')]
+// / sqrt(s) with nu the group amplitudes of lambda_0, and
+// dL/db_j = 2 <psi~_j|lambda_0>.
 extern "C" __global__ void __launch_bounds__(256) qwk_grad_init(Matrix m, Slots lam, const double2* b, double* dv,
                                                                 double2* db) {
   const int64_t stride = int64_t(gridDim.x) * blockDim.x;
-  for (int64_t it = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; it < m.items; it += stride) {
-    const Item x = item_of(m, it, it - (threadIdx.x & (kWave - 1)));
-    double2 n0 = zero2(), n1 = zero2();
-    Rot r, d;
-    r.f = zero2();
-    r.g = 0.0;
-    d = r;
-    if (x.live) {
-      n0 = lam.R[2 * it];
-      n1 = lam.R[2 * it + 1];
-      const int colq = m.col[it];
-      const double v = m.val[it];
-      r = rotation(v, x.j, colq);
-      d = rotation_deriv(v, x.j, colq);
-      const double2 bj = b[x.I.jbase + x.j];
+  for (int64_t it = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; it < m.rows; it += stride) {
+    const Row x = row_item(m, it);
+    const double2 bj = b[it];
+    double2 c = zero2();
+    for (int l = 0; l < x.I.s; ++l) {
+      const int64_t h = home(x.I, x.j, l);
+      const double2 n0 = lam.R0[h], n1 = lam.R1[h];
+      const SlotRec rc = m.rec[h];
+      const Rot d = rotation_deriv(rc.val, x.j, rc.col);
       const double2 u = cmul(bj, cadd(cjmul(n0, d.f), make_double2(n1.x * d.g, -n1.y * d.g)));
-      dv[it] += 2.0 * u.x * x.I.inv_sqrt_s;
+      dv[h] += 2.0 * u.x * x.I.inv_sqrt_s;
+      c = cadd(c, along(rotation(rc.val, x.j, rc.col), n0, n1));
     }
-    const double2 c = group_sum(cadd(cjmul(r.f, n0), cscale(n1, r.g)), x.I.s);
-    if (x.live && x.l == 0) db[x.I.jbase + x.j] = cscale(c, 2.0 * x.I.inv_sqrt_s);
+    db[it] = cscale(c, 2.0 * x.I.inv_sqrt_s);
   }
 }
 

@@ -20,16 +20,26 @@ extern "C" const size_t qw_code_object_size;
 namespace qw {
 namespace {
 
+// Step and adjoint kernels come in four widths: up to 1, 2, 4 or 8 slots
+// held per lane (s <= 8, 16, 32, 64).
 enum Fn {
-  F_STEP2,
-  F_STEP2_ACC,
-  F_STEP1,
-  F_STEP1_ACC,
-  F_ADJOINT,
+  F_STEP_S1,
+  F_STEP_S2,
+  F_STEP_S4,
+  F_STEP_S8,
+  F_STEP_S1_ACC,
+  F_STEP_S2_ACC,
+  F_STEP_S4_ACC,
+  F_STEP_S8_ACC,
+  F_ADJOINT_S1,
+  F_ADJOINT_S2,
+  F_ADJOINT_S4,
+  F_ADJOINT_S8,
   F_QBS_TABLE,
   F_INIT,
   F_FILL,
   F_MEASURE,
+  F_MEASURE_ROWS,
   F_EXPORT,
   F_IMPORT,
   F_WEIGHT,
@@ -37,10 +47,14 @@ enum Fn {
   F_COUNT
 };
 
-const char* const kNames[F_COUNT] = {"qwk_step2", "qwk_step2_acc", "qwk_step1", "qwk_step1_acc",
-                                     "qwk_adjoint", "qwk_qbs_table",
-                                     "qwk_init", "qwk_fill",     "qwk_measure", "qwk_export",
-                                     "qwk_import", "qwk_weight", "qwk_grad_init"};
+const char* const kNames[F_COUNT] = {
+    "qwk_step_s1",    "qwk_step_s2",    "qwk_step_s4",      "qwk_step_s8",    "qwk_step_s1_acc", "qwk_step_s2_acc",
+    "qwk_step_s4_acc", "qwk_step_s8_acc", "qwk_adjoint_s1",  "qwk_adjoint_s2", "qwk_adjoint_s4",  "qwk_adjoint_s8",
+    "qwk_qbs_table",  "qwk_init",       "qwk_fill",         "qwk_measure",    "qwk_measure_rows", "qwk_export",
+    "qwk_import",     "qwk_weight",     "qwk_grad_init"};
+
+// 0..3 for slmax = 1, 2, 4, 8
+int width_index(int32_t slmax) { return slmax <= 1 ? 0 : slmax <= 2 ? 1 : slmax <= 4 ? 2 : 3; }
 
 constexpr int kMaxDevices = 64;
 
@@ -97,20 +111,19 @@ int clamp_grid(int64_t work, int64_t limit) {
 hipError_t launch_step(const StepArgs& a, int grid, int block, hipStream_t stream) {
   StepArgs c = a;
   void* p[] = {&c};
-  const bool pairs = a.m.smax <= 32;  // two lanes per slot
-  const Fn f = pairs ? (a.yacc ? F_STEP2_ACC : F_STEP2) : (a.yacc ? F_STEP1_ACC : F_STEP1);
+  const Fn f = Fn((a.yacc ? F_STEP_S1_ACC : F_STEP_S1) + width_index(a.m.slmax));
   return launch(f, grid, block, stream, p);
 }
 
 hipError_t launch_adjoint(const AdjArgs& a, int grid, int block, hipStream_t stream) {
   AdjArgs c = a;
   void* p[] = {&c};
-  return launch(F_ADJOINT, grid, block, stream, p);
+  return launch(Fn(F_ADJOINT_S1 + width_index(a.m.slmax)), grid, block, stream, p);
 }
 
-hipError_t launch_qbs_table(const Matrix& m, int32_t* rev, SlotRec* rec, hipStream_t stream) {
+hipError_t launch_qbs_table(const Matrix& m, SlotRec* rec, hipStream_t stream) {
   Matrix mm = m;
-  void* p[] = {&mm, &rev, &rec};
+  void* p[] = {&mm, &rec};
   return launch(F_QBS_TABLE, clamp_grid(m.items, 4096), 256, stream, p);
 }
 
@@ -134,8 +147,12 @@ hipError_t launch_measure(const Matrix& m, Slots st, List L, int32_t kind, doubl
                           hipStream_t stream) {
   Matrix mm = m;
   int32_t k = kind;
-  void* p[] = {&mm, &st, &L, &k, &partial, &out};
-  return launch(F_MEASURE, grid, 256, stream, p);
+  if (kind <= 1) {
+    void* p[] = {&mm, &st, &L, &k, &partial};
+    return launch(F_MEASURE, grid, 256, stream, p);
+  }
+  void* p[] = {&mm, &st, &L, &k, &out};
+  return launch(F_MEASURE_ROWS, clamp_grid(m.rows + L.cnt, 4096), 256, stream, p);
 }
 
 hipError_t launch_export(const Matrix& m, Slots st, List L, uint64_t* keys, double2* amps, uint32_t* count,
@@ -168,7 +185,7 @@ hipError_t launch_grad_init(const Matrix& m, Slots lam, const double2* b, double
   Matrix mm = m;
   const double2* bb = b;
   void* p[] = {&mm, &lam, &bb, &dv, &db};
-  return launch(F_GRAD_INIT, clamp_grid(m.items, 4096), 256, stream, p);
+  return launch(F_GRAD_INIT, clamp_grid(m.rows, 4096), 256, stream, p);
 }
 
 }  // namespace qw
