@@ -156,6 +156,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true", help="skip the batched and adjoint legs")
     ap.add_argument("--no-tune", action="store_true", help="keep the default launch shape")
+    ap.add_argument("--launch", default=None, metavar="WG,GRID",
+                    help="fixed launch shape of the main leg (workgroup size, workgroups)")
     ap.add_argument("--only", choices=["batched", "adjoint"], default=None,
                     help="run one extra leg alone (for profiling) and print its JSON")
     ap.add_argument("--pmc-run", action="store_true",
@@ -195,7 +197,10 @@ def main():
     csc, b = W.paper_scale()
     walk = Q.Walk(csc)
     N, s = walk.info[0]["N"], walk.info[0]["s"]
-    shape = None if args.no_tune else autotune.tune(walk, b)
+    if args.launch:
+        shape = tuple(int(v) for v in args.launch.split(","))
+    else:
+        shape = None if args.no_tune else autotune.tune(walk, b)
     st = walk.state(b)
     if shape:
         autotune.apply(st, shape)

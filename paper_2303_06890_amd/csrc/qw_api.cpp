@@ -93,12 +93,15 @@ struct qw_ctx {
   double* val = nullptr;
   qw::SlotRec* rec = nullptr;
   qw::Inst* dinst = nullptr;
+  int32_t* wave_inst = nullptr;
+  qw::Inst inst0{};
   qw::Matrix mat() const {
     qw::Matrix m;
     m.col = col;
     m.val = val;
     m.rec = rec;
     m.inst = dinst;
+    m.wave_inst = wave_inst;
     m.items = items;
     m.waves = waves;
     m.rows = jtotal;
@@ -106,10 +109,14 @@ struct qw_ctx {
     m.nbits = nbits;
     m.smax = smax;
     m.slmax = slmax;
+    m.suni = suni;
+    m.pad_ = 0;
+    m.inst0 = inst0;
     return m;
   }
   int32_t smax = 1;
   int32_t slmax = 1;
+  int32_t suni = 0;  // s shared by every instance, 0 when they differ
 };
 
 namespace {
@@ -129,7 +136,7 @@ struct qw_state {
   int cur = 0;              // parity holding the state
   List L{};                 // branches without a static home (count on the host)
   unsigned long long* acc = nullptr;  // per-workgroup counts of branches written
-  uint32_t* stepno = nullptr;         // per-workgroup solver step counters
+  uint32_t* stepno = nullptr;         // per-wavefront solver step counters
   double2* b = nullptr;     // device copy of b (N-vector layout)
   double* mbuf = nullptr;   // measurement scratch: max(kMaxGrid, 2*jtotal) doubles
   bool prepared = false;    // created by T~ |b~>
@@ -326,6 +333,7 @@ void ctx_release(qw_ctx* ctx) {
   ctx->alloc.put(ctx->val);
   ctx->alloc.put(ctx->rec);
   ctx->alloc.put(ctx->dinst);
+  ctx->alloc.put(ctx->wave_inst);
   delete ctx;
 }
 
@@ -415,11 +423,21 @@ int load_impl(qw_ctx** out, int32_t ninst, const int32_t* n, const int64_t* colp
     ctx->slmax = std::max(ctx->slmax, dinst[i].sl);
   }
   ctx->waves = waves;
+  ctx->inst0 = dinst[0];
+  ctx->suni = dinst[0].s;
+  for (int32_t i = 1; i < ninst; ++i)
+    if (dinst[i].s != ctx->suni) ctx->suni = 0;
+  std::vector<int32_t> hwave(static_cast<size_t>(waves));
+  for (int32_t i = 0; i < ninst; ++i) {
+    const int64_t end = i + 1 < ninst ? dinst[i + 1].wave_base : waves;
+    std::fill(hwave.begin() + dinst[i].wave_base, hwave.begin() + end, i);
+  }
   ctx->col = static_cast<int32_t*>(ctx->alloc.get(sizeof(int32_t) * items));
   ctx->val = static_cast<double*>(ctx->alloc.get(sizeof(double) * items));
   ctx->rec = static_cast<qw::SlotRec*>(ctx->alloc.get(sizeof(qw::SlotRec) * items));
   ctx->dinst = static_cast<qw::Inst*>(ctx->alloc.get(sizeof(qw::Inst) * ninst));
-  if (!ctx->col || !ctx->val || !ctx->rec || !ctx->dinst) {
+  ctx->wave_inst = static_cast<int32_t*>(ctx->alloc.get(sizeof(int32_t) * waves));
+  if (!ctx->col || !ctx->val || !ctx->rec || !ctx->dinst || !ctx->wave_inst) {
     ctx_release(ctx);
     return set_err(QW_ENOMEM, "device allocation failed for the matrix");
   }
@@ -428,6 +446,8 @@ int load_impl(qw_ctx** out, int32_t ninst, const int32_t* n, const int64_t* colp
     e = hipMemcpyAsync(ctx->val, hval.data(), sizeof(double) * items, hipMemcpyHostToDevice, stream);
   if (e == hipSuccess)
     e = hipMemcpyAsync(ctx->dinst, dinst.data(), sizeof(qw::Inst) * ninst, hipMemcpyHostToDevice, stream);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(ctx->wave_inst, hwave.data(), sizeof(int32_t) * waves, hipMemcpyHostToDevice, stream);
   // O_s'^-1 of every reflected output: the QBS of j in row col[q], once per matrix
   if (e == hipSuccess) e = qw::launch_fill(ctx->rec, int64_t(sizeof(qw::SlotRec)) * items, stream);
   if (e == hipSuccess) e = qw::launch_qbs_table(ctx->mat(), ctx->rec, stream);
@@ -475,7 +495,7 @@ int state_alloc(qw_ctx* ctx, int64_t list_cap, qw_state** out, hipStream_t strea
     st->buf[k] = p ? qw::Slots{p, p + ctx->items, p + 2 * ctx->items, p + 3 * ctx->items} : qw::Slots{};
   }
   st->acc = static_cast<unsigned long long*>(state_get(st, sizeof(unsigned long long) * qw::kMaxGrid));
-  st->stepno = static_cast<uint32_t*>(state_get(st, sizeof(uint32_t) * qw::kMaxGrid));
+  st->stepno = static_cast<uint32_t*>(state_get(st, sizeof(uint32_t) * qw::kMaxWaves));
   st->b = static_cast<double2*>(state_get(st, sizeof(double2) * ctx->jtotal));
   st->mbuf = static_cast<double*>(state_get(st, sizeof(double) * std::max<int64_t>(qw::kMaxGrid, 2 * ctx->jtotal + 2)));
   ok = ok && st->acc && st->stepno && st->b && st->mbuf;
@@ -487,7 +507,7 @@ int state_alloc(qw_ctx* ctx, int64_t list_cap, qw_state** out, hipStream_t strea
   hipError_t e = hipSuccess;
   for (int k = 0; k < 2 && e == hipSuccess; ++k) e = qw::launch_fill(st->buf[k].R0, int64_t(4 * pb), stream);
   if (e == hipSuccess) e = qw::launch_fill(st->acc, sizeof(unsigned long long) * qw::kMaxGrid, stream);
-  if (e == hipSuccess) e = qw::launch_fill(st->stepno, sizeof(uint32_t) * qw::kMaxGrid, stream);
+  if (e == hipSuccess) e = qw::launch_fill(st->stepno, sizeof(uint32_t) * qw::kMaxWaves, stream);
   if (e == hipSuccess) e = qw::launch_fill(st->b, sizeof(double2) * ctx->jtotal, stream);
   if (e != hipSuccess) {
     qw_state_free(st);

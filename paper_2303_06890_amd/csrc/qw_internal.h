@@ -12,6 +12,8 @@ namespace qw {
 constexpr int kWave = 64;       // CDNA wavefront width
 constexpr int kMaxS = 64;       // largest QRAM row length handled (one wave per group)
 constexpr int kMaxGrid = 8192;  // largest step-kernel grid (per-workgroup counters)
+constexpr int kMaxBlock = 256;  // largest step-kernel workgroup
+constexpr int kMaxWaves = kMaxGrid * (kMaxBlock / kWave);  // per-wavefront counters
 constexpr double kTau = 1e-13;  // pruning threshold applied after every step
 
 // Per-instance facts, resident on the device.  The slots of instance i are
@@ -64,17 +66,21 @@ struct SlotRec {
 };
 
 struct Matrix {
-  const int32_t* col;  // ELL column indices (row-major), sorted inside each row
-  const double* val;   // ELL values (row-major)
-  const SlotRec* rec;  // slot records (by home)
+  const int32_t* col;        // ELL column indices (row-major), sorted inside each row
+  const double* val;         // ELL values (row-major)
+  const SlotRec* rec;        // slot records (by home)
   const Inst* inst;
-  int64_t items;       // total slots including alignment padding
-  int64_t waves;       // wavefronts of one step-kernel pass
-  int64_t rows;        // sum of N over the instances (length of N-vectors)
+  const int32_t* wave_inst;  // instance of every step-kernel wavefront
+  int64_t items;             // total slots including alignment padding
+  int64_t waves;             // wavefronts of one step-kernel pass
+  int64_t rows;              // sum of N over the instances (length of N-vectors)
   int32_t ninst;
-  int32_t nbits;       // register width n of the key layout
-  int32_t smax;        // largest s over the instances
-  int32_t slmax;       // largest slots-per-lane over the instances
+  int32_t nbits;             // register width n of the key layout
+  int32_t smax;              // largest s over the instances
+  int32_t slmax;             // largest slots-per-lane over the instances
+  int32_t suni;              // s of every instance when they all share it, else 0
+  int32_t pad_;
+  Inst inst0;                // copy of inst[0] (a single instance needs no table read)
 };
 
 enum Mode : int32_t { kStep = 0, kSwap = 1 };
@@ -84,7 +90,7 @@ struct StepArgs {
   Slots in, out;
   List L;
   unsigned long long* acc;  // per-workgroup running count of branches written
-  uint32_t* stepno;         // per-workgroup step counter (indexes coefm)
+  uint32_t* stepno;         // per-wavefront step counter (indexes coefm), kMaxWaves entries
   int32_t mode;             // kStep: W; kSwap: S only
   int32_t pad_;
   double tau;
@@ -110,9 +116,9 @@ static_assert(sizeof(Inst) == 56 && offsetof(Inst, inv_sqrt_s) == 48, "Inst layo
 static_assert(sizeof(Slots) == 32, "Slots layout");
 static_assert(sizeof(List) == 24 && offsetof(List, cap) == 20, "List layout");
 static_assert(sizeof(SlotRec) == 16 && offsetof(SlotRec, val) == 8, "SlotRec layout");
-static_assert(sizeof(Matrix) == 72 && offsetof(Matrix, slmax) == 68, "Matrix layout");
-static_assert(sizeof(StepArgs) == 208 && offsetof(StepArgs, coefm) == 200, "StepArgs layout");
-static_assert(sizeof(AdjArgs) == 280 && offsetof(AdjArgs, dv) == 272, "AdjArgs layout");
+static_assert(sizeof(Matrix) == 144 && offsetof(Matrix, inst0) == 88, "Matrix layout");
+static_assert(sizeof(StepArgs) == 280 && offsetof(StepArgs, coefm) == 272, "StepArgs layout");
+static_assert(sizeof(AdjArgs) == 352 && offsetof(AdjArgs, dv) == 344, "AdjArgs layout");
 
 // Launchers (qw_launch.cpp).  All enqueue on `stream` and allocate nothing.
 hipError_t launch_step(const StepArgs& a, int grid, int block, hipStream_t stream);

@@ -137,7 +137,32 @@ __device__ __forceinline__ double2 row_sum(double2 v, int rpw_log) {
   return v;
 }
 
-// Instance whose range starts at or before x (ranges ordered by field F).
+__device__ __forceinline__ int uniform(int v) { return __builtin_amdgcn_readfirstlane(v); }
+
+// Read-only loads from a wavefront-uniform address, through the scalar cache
+// (the constant address space).
+typedef const __attribute__((address_space(4))) Inst* ConstInstPtr;
+__device__ __forceinline__ int32_t uload(const int32_t* p) {
+  return *(const __attribute__((address_space(4))) int32_t*)p;
+}
+__device__ __forceinline__ Inst uload(const Inst* p) {
+  const ConstInstPtr c = (ConstInstPtr)p;
+  Inst I;
+  I.item_base = c->item_base;
+  I.jbase = c->jbase;
+  I.wave_base = c->wave_base;
+  I.N = c->N;
+  I.s = c->s;
+  I.hbits = c->hbits;
+  I.nlog = c->nlog;
+  I.lpr_log = c->lpr_log;
+  I.sl = c->sl;
+  I.inv_sqrt_s = c->inv_sqrt_s;
+  return I;
+}
+
+// Instance whose range starts at or before x (ranges ordered by field F);
+// x may differ between lanes.
 template <int64_t Inst::*F>
 __device__ __forceinline__ int find_inst(const Matrix& m, int64_t x) {
   int lo = 0, hi = m.ninst - 1;
@@ -150,7 +175,28 @@ __device__ __forceinline__ int find_inst(const Matrix& m, int64_t x) {
   }
   return lo;
 }
-__device__ __forceinline__ int uniform(int v) { return __builtin_amdgcn_readfirstlane(v); }
+// The same for a wavefront-uniform x, with scalar loads.
+template <int64_t Inst::*F>
+__device__ __forceinline__ int find_inst_uniform(const Matrix& m, int64_t x) {
+  int lo = 0, hi = m.ninst - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (((ConstInstPtr)(m.inst + mid))->*F <= x)
+      lo = mid;
+    else
+      hi = mid - 1;
+  }
+  return lo;
+}
+// Instance record by wavefront-uniform index.
+__device__ __forceinline__ Inst inst_uniform(const Matrix& m, int i) {
+  Inst I;
+  if (m.ninst == 1)
+    I = m.inst0;
+  else
+    I = uload(m.inst + i);
+  return I;
+}
 
 __device__ __forceinline__ uint64_t swap_halves(uint64_t key, int n) {
   const int h = 2 * n + 1;
@@ -186,8 +232,8 @@ struct Home {
 };
 __device__ __forceinline__ Home home_item(const Matrix& m, int64_t it, int64_t first) {
   Home x;
-  x.inst = m.ninst == 1 ? 0 : uniform(find_inst<&Inst::item_base>(m, first));
-  x.I = m.inst[x.inst];  // uniform address: scalar loads
+  x.inst = m.ninst == 1 ? 0 : find_inst_uniform<&Inst::item_base>(m, uniform(int(first >> 6)) * int64_t(64));
+  x.I = inst_uniform(m, x.inst);
   const int64_t local = it - x.I.item_base;
   x.live = local < (int64_t(x.I.N) << x.I.hbits);
   x.l = int(local >> x.I.nlog);
@@ -209,20 +255,31 @@ __device__ __forceinline__ Row row_item(const Matrix& m, int64_t r) {
   return x;
 }
 
+// Lane mapping of the step kernels for s = S: min(S, 8) lanes share a row,
+// each holding S / min(S, 8) slots.
+template <int S>
+struct Shape {
+  static constexpr int lpr_log = S >= 8 ? 3 : (S == 4 ? 2 : (S == 2 ? 1 : 0));
+  static constexpr int rpw_log = 6 - lpr_log;
+  static constexpr int sl = S >> lpr_log;
+};
+
 // A lane of the step kernels: wavefront w of the instance covers rows
 // [w * 2^rpw_log, (w + 1) * 2^rpw_log); lane = h * 2^rpw_log + jj holds slots
-// l = h * sl + i (i < sl) of row w * 2^rpw_log + jj.
+// l = h * sl + i (i < sl) of row w * 2^rpw_log + jj.  S != 0: every instance
+// has s = S (the mapping is known at compile time).
 struct Lanes {
   Inst I;
   int inst;
   int j, h, rpw_log;
   bool live;
 };
+template <int S>
 __device__ __forceinline__ Lanes lanes_of(const Matrix& m, int64_t w, int lane) {
   Lanes x;
-  x.inst = m.ninst == 1 ? 0 : uniform(find_inst<&Inst::wave_base>(m, w));
-  x.I = m.inst[x.inst];
-  x.rpw_log = 6 - x.I.lpr_log;
+  x.inst = m.ninst == 1 ? 0 : uload(m.wave_inst + w);
+  x.I = inst_uniform(m, x.inst);
+  x.rpw_log = S ? Shape<S>::rpw_log : 6 - x.I.lpr_log;
   x.h = lane >> x.rpw_log;
   const int64_t j = ((w - x.I.wave_base) << x.rpw_log) + (lane & ((1 << x.rpw_log) - 1));
   x.live = j < x.I.N;
@@ -230,15 +287,12 @@ __device__ __forceinline__ Lanes lanes_of(const Matrix& m, int64_t w, int lane) 
   return x;
 }
 
-__device__ __forceinline__ unsigned long long block_sum_u64(unsigned long long v, unsigned long long* sh) {
+// Count of a wavefront added to its workgroup's counter by one lane (no
+// barrier: the wavefronts of a workgroup finish independently).
+__device__ __forceinline__ void wave_count(unsigned cnt, unsigned long long* acc) {
+  unsigned long long v = cnt;
   for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
-  __syncthreads();
-  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = v;
-  __syncthreads();
-  unsigned long long t = 0;
-  if (threadIdx.x == 0)
-    for (int i = 0; i < int(blockDim.x >> 6); ++i) t += sh[i];
-  return t;
+  if ((threadIdx.x & (kWave - 1)) == 0) atomicAdd(&acc[blockIdx.x], v);
 }
 
 __device__ __forceinline__ double block_sum(double v, double* sh) {
@@ -285,10 +339,10 @@ __device__ __forceinline__ unsigned list_entry(const List& L, int64_t e, int n, 
 // One wavefront of the step: up to SLM slots per lane, held in registers.
 // The data loads do not depend on each other or on the instance record
 // beyond its base, so they are issued together.
-template <bool ACC, int SLM>
+template <bool ACC, int SLM, int S>
 __device__ __forceinline__ unsigned step_wave(const StepArgs& a, int64_t w, int lane, double coef) {
-  const Lanes x = lanes_of(a.m, w, lane);
-  const int sl = SLM == 1 ? 1 : x.I.sl;
+  const Lanes x = lanes_of<S>(a.m, w, lane);
+  const int sl = S ? Shape<S>::sl : (SLM == 1 ? 1 : x.I.sl);
   const int64_t base = x.I.item_base;
   int64_t h[SLM];
   SlotRec rc[SLM];
@@ -338,48 +392,57 @@ __device__ __forceinline__ unsigned step_wave(const StepArgs& a, int64_t w, int 
   return cnt;
 }
 
-template <bool ACC, int SLM>
+// SLM: slots per lane held in registers; S: s of every instance, or 0 (read
+// per instance, slots per lane <= SLM).
+template <bool ACC, int SLM, int S>
 __device__ __forceinline__ void step_body(const StepArgs& a) {
-  __shared__ unsigned long long sh[16];
   const int lane = threadIdx.x & (kWave - 1);
   const int64_t wpb = blockDim.x >> 6;
+  const int64_t wid = int64_t(blockIdx.x) * wpb + (threadIdx.x >> 6);  // this wavefront's counter
   const int64_t lw = (int64_t(a.L.cnt) + kWave - 1) / kWave;
   const int64_t total = a.m.waves + lw;
   double coef = 0.0;
   uint32_t stepno = 0;
   if (ACC) {
-    stepno = a.stepno[blockIdx.x];
+    stepno = a.stepno[wid];
     coef = a.coefm[stepno];
   }
   unsigned cnt = 0;
   const int64_t wstride = int64_t(gridDim.x) * wpb;
-  for (int64_t w = uniform(int(blockIdx.x * wpb + (threadIdx.x >> 6))); w < total; w += wstride) {
+  for (int64_t w = uniform(int(wid)); w < total; w += wstride) {
     if (w < a.m.waves)
-      cnt += step_wave<ACC, SLM>(a, w, lane, coef);
+      cnt += step_wave<ACC, SLM, S>(a, w, lane, coef);
     else
       cnt += list_entry(a.L, (w - a.m.waves) * kWave + lane, a.m.nbits, a.mode == kStep);
   }
-  const unsigned long long t = block_sum_u64(cnt, sh);
-  if (threadIdx.x == 0) {
-    atomicAdd(&a.acc[blockIdx.x], t);  // per-workgroup counter: no contention, no return value
-    if (ACC) a.stepno[blockIdx.x] = stepno + 1;
-  }
+  wave_count(cnt, a.acc);
+  if (ACC && lane == 0) a.stepno[wid] = stepno + 1;
 }
 
 }  // namespace qw
 
-#define QW_STEP_KERNELS(S)                                                                          \
-  extern "C" __global__ void __launch_bounds__(256) qwk_step_s##S(qw::StepArgs a) {                \
-    qw::step_body<false, S>(a);                                                                     \
+// qwk_step_sN: any s per instance, up to N slots per lane (s <= 8N);
+// qwk_step_fS: every instance has s = S.
+#define QW_STEP_KERNEL(NAME, SLM, S)                                                               \
+  extern "C" __global__ void __launch_bounds__(256) NAME(qw::StepArgs a) {                         \
+    qw::step_body<false, SLM, S>(a);                                                                \
   }                                                                                                 \
-  extern "C" __global__ void __launch_bounds__(256) qwk_step_s##S##_acc(qw::StepArgs a) {          \
-    qw::step_body<true, S>(a);                                                                      \
+  extern "C" __global__ void __launch_bounds__(256) NAME##_acc(qw::StepArgs a) {                   \
+    qw::step_body<true, SLM, S>(a);                                                                 \
   }
-QW_STEP_KERNELS(1)
-QW_STEP_KERNELS(2)
-QW_STEP_KERNELS(4)
-QW_STEP_KERNELS(8)
-#undef QW_STEP_KERNELS
+QW_STEP_KERNEL(qwk_step_s1, 1, 0)
+QW_STEP_KERNEL(qwk_step_s2, 2, 0)
+QW_STEP_KERNEL(qwk_step_s4, 4, 0)
+QW_STEP_KERNEL(qwk_step_s8, 8, 0)
+QW_STEP_KERNEL(qwk_step_f1, 1, 1)
+QW_STEP_KERNEL(qwk_step_f2, 1, 2)
+QW_STEP_KERNEL(qwk_step_f4, 1, 4)
+QW_STEP_KERNEL(qwk_step_f8, 1, 8)
+QW_STEP_KERNEL(qwk_step_f16, 2, 16)
+QW_STEP_KERNEL(qwk_step_f32, 4, 32)
+QW_STEP_KERNEL(qwk_step_f64, 8, 64)
+#undef QW_STEP_KERNEL
+
 
 namespace qw {
 
@@ -420,7 +483,7 @@ extern "C" __global__ void __launch_bounds__(256) qwk_qbs_table(Matrix m, SlotRe
 template <int SLM>
 __device__ __forceinline__ void adjoint_wave(const AdjArgs& a, int64_t w, int lane, unsigned& cnt,
                                              unsigned& lcnt) {
-  const Lanes x = lanes_of(a.m, w, lane);
+  const Lanes x = lanes_of<0>(a.m, w, lane);
   const int sl = SLM == 1 ? 1 : x.I.sl;
   const int64_t base = x.I.item_base;
   int64_t h[SLM];
@@ -474,7 +537,6 @@ __device__ __forceinline__ void adjoint_wave(const AdjArgs& a, int64_t w, int la
 
 template <int SLM>
 __device__ __forceinline__ void adjoint_body(const AdjArgs& a) {
-  __shared__ unsigned long long sh[16];
   const int lane = threadIdx.x & (kWave - 1);
   const int64_t wpb = blockDim.x >> 6;
   const int64_t lw = (int64_t(a.L.cnt) + kWave - 1) / kWave;
@@ -490,10 +552,8 @@ __device__ __forceinline__ void adjoint_body(const AdjArgs& a) {
     else
       lcnt += list_entry(a.LL, (w - a.m.waves - lw) * kWave + lane, a.m.nbits, true);
   }
-  const unsigned long long t1 = block_sum_u64(cnt, sh);
-  if (threadIdx.x == 0) a.acc[blockIdx.x] += t1;
-  const unsigned long long t2 = block_sum_u64(lcnt, sh);
-  if (threadIdx.x == 0) a.lacc[blockIdx.x] += t2;
+  wave_count(cnt, a.acc);
+  wave_count(lcnt, a.lacc);
 }
 
 }  // namespace qw

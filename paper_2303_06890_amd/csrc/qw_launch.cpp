@@ -20,18 +20,24 @@ extern "C" const size_t qw_code_object_size;
 namespace qw {
 namespace {
 
-// Step and adjoint kernels come in four widths: up to 1, 2, 4 or 8 slots
-// held per lane (s <= 8, 16, 32, 64).
+// Step kernels: qwk_step_s{1,2,4,8} take any s per instance with up to that
+// many slots held per lane (s <= 8, 16, 32, 64); qwk_step_f{S} are compiled
+// for matrices whose instances all have s = S.  Each has an _acc twin (the
+// solver's fused projection).  Adjoint kernels come in the four widths.
 enum Fn {
   F_STEP_S1,
   F_STEP_S2,
   F_STEP_S4,
   F_STEP_S8,
-  F_STEP_S1_ACC,
-  F_STEP_S2_ACC,
-  F_STEP_S4_ACC,
-  F_STEP_S8_ACC,
-  F_ADJOINT_S1,
+  F_STEP_F1,
+  F_STEP_F2,
+  F_STEP_F4,
+  F_STEP_F8,
+  F_STEP_F16,
+  F_STEP_F32,
+  F_STEP_F64,
+  F_STEP_COUNT_,  // _acc twins follow at + F_STEP_COUNT_
+  F_ADJOINT_S1 = 2 * F_STEP_COUNT_,
   F_ADJOINT_S2,
   F_ADJOINT_S4,
   F_ADJOINT_S8,
@@ -48,13 +54,26 @@ enum Fn {
 };
 
 const char* const kNames[F_COUNT] = {
-    "qwk_step_s1",    "qwk_step_s2",    "qwk_step_s4",      "qwk_step_s8",    "qwk_step_s1_acc", "qwk_step_s2_acc",
-    "qwk_step_s4_acc", "qwk_step_s8_acc", "qwk_adjoint_s1",  "qwk_adjoint_s2", "qwk_adjoint_s4",  "qwk_adjoint_s8",
-    "qwk_qbs_table",  "qwk_init",       "qwk_fill",         "qwk_measure",    "qwk_measure_rows", "qwk_export",
-    "qwk_import",     "qwk_weight",     "qwk_grad_init"};
+    "qwk_step_s1",     "qwk_step_s2",     "qwk_step_s4",      "qwk_step_s8",      "qwk_step_f1",
+    "qwk_step_f2",     "qwk_step_f4",     "qwk_step_f8",      "qwk_step_f16",     "qwk_step_f32",
+    "qwk_step_f64",    "qwk_step_s1_acc", "qwk_step_s2_acc",  "qwk_step_s4_acc",  "qwk_step_s8_acc",
+    "qwk_step_f1_acc", "qwk_step_f2_acc", "qwk_step_f4_acc",  "qwk_step_f8_acc",  "qwk_step_f16_acc",
+    "qwk_step_f32_acc", "qwk_step_f64_acc", "qwk_adjoint_s1", "qwk_adjoint_s2",   "qwk_adjoint_s4",
+    "qwk_adjoint_s8",  "qwk_qbs_table",   "qwk_init",         "qwk_fill",         "qwk_measure",
+    "qwk_measure_rows", "qwk_export",     "qwk_import",       "qwk_weight",       "qwk_grad_init"};
 
 // 0..3 for slmax = 1, 2, 4, 8
 int width_index(int32_t slmax) { return slmax <= 1 ? 0 : slmax <= 2 ? 1 : slmax <= 4 ? 2 : 3; }
+
+Fn step_kernel(const Matrix& m, bool acc) {
+  int f = F_STEP_S1 + width_index(m.slmax);
+  if (m.suni > 0) {
+    int lg = 0;
+    while ((1 << lg) < m.suni) ++lg;
+    f = F_STEP_F1 + lg;
+  }
+  return Fn(f + (acc ? int(F_STEP_COUNT_) : 0));
+}
 
 constexpr int kMaxDevices = 64;
 
@@ -111,8 +130,7 @@ int clamp_grid(int64_t work, int64_t limit) {
 hipError_t launch_step(const StepArgs& a, int grid, int block, hipStream_t stream) {
   StepArgs c = a;
   void* p[] = {&c};
-  const Fn f = Fn((a.yacc ? F_STEP_S1_ACC : F_STEP_S1) + width_index(a.m.slmax));
-  return launch(f, grid, block, stream, p);
+  return launch(step_kernel(a.m, a.yacc != nullptr), grid, block, stream, p);
 }
 
 hipError_t launch_adjoint(const AdjArgs& a, int grid, int block, hipStream_t stream) {

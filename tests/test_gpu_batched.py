@@ -91,6 +91,30 @@ def test_batched_vs_oracle(Q, oracle_mod):
         compare_states(gk, ga, ok, oa, where=f"instance {i}")
 
 
+@pytest.mark.parametrize("kind", ["small_s", "wide_s"])
+def test_batched_mixed_row_lengths(Q, oracle_mod, kind):
+    """Instances whose s differ (1 ... 8, or up to 64): the step kernel reads
+    each wavefront's lane mapping from its instance; every slice must match
+    the oracle."""
+    diag = W.from_dense(np.diag(np.linspace(0.2, 0.8, 12)))           # s = 1
+    pair = W.from_dense(np.array([[0.3, 0.5], [0.5, 0.6]]))           # s = 2
+    if kind == "small_s":
+        mats = [diag, W.offset_matrix(40, 3, seed=51), pair, W.offset_matrix(100, 7, seed=52)]
+    else:
+        mats = [W.offset_matrix(64, 33, seed=53), W.offset_matrix(24, 3, seed=54),
+                diag, W.offset_matrix(128, 20, seed=55), W.offset_matrix(96, 12, seed=56)]
+    bs = [W.gaussian_b(m.n, seed=60 + i) for i, m in enumerate(mats)]
+    walk = Q.Walk(mats)
+    st = walk.state(bs).step(15)
+    keys, amps = st.export()
+    F = unpack(keys, walk.nbits)
+    for i, (a, b) in enumerate(zip(mats, bs)):
+        om = oracle_mod.OracleMatrix(a)
+        ok, oa = oracle_mod.OracleState(om).set_b(b).T().step(15).export()
+        gk, ga = _slice(F, amps, i, om.nbits)
+        compare_states(gk, ga, ok, oa, where=f"{kind} instance {i}")
+
+
 def test_batched_workload_256(Q):
     """The 256-instance workload (n in 64..4096, 4..16 entries per column,
     single-column starts, 50 graph-replayed steps): every instance keeps unit

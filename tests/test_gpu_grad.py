@@ -55,7 +55,7 @@ def _close(a, b, rel):
     return fin
 
 
-@pytest.mark.parametrize("n,c,seed,nsteps", [(16, 5, 81, 5), (64, 7, 82, 9)])
+@pytest.mark.parametrize("n,c,seed,nsteps", [(16, 5, 81, 5), (64, 7, 82, 9), (64, 12, 83, 5), (64, 20, 84, 4)])
 def test_grad_matches_oracle_small(Q, oracle_mod, n, c, seed, nsteps):
     csc = _scaled(W.offset_matrix(n, c, seed=seed))
     b = W.gaussian_b(n, seed=seed + 1) * (1 + 0.3j)

@@ -139,6 +139,10 @@ def test_edge_shapes(Q, oracle_mod):
         (W.offset_matrix(128, 64, seed=17), 128),                   # s = 64, one wave per group
         (W.offset_matrix(40, 33, seed=18), 40),                     # s = 64 with 31 filler slots
         (W.band_matrix(30, 3, seed=19), 30),                        # paper's band family, s = 8
+        (W.offset_matrix(256, 16, seed=41), 256),                   # s = 16: two slots per lane
+        (W.offset_matrix(128, 20, seed=42), 128),                   # s = 32: four slots per lane
+        (W.offset_matrix(16, 3, seed=43), 16),                      # s = 4, N = rows of one wavefront
+        (W.offset_matrix(8, 3, seed=44), 8),                        # s = 4, N below one wavefront's rows
     ]
     for csc, n in cases:
         b = W.gaussian_b(n, seed=n)
