@@ -174,7 +174,7 @@ qw::StepArgs step_args(qw_state* st, int mode, double2* yacc, const double* coef
   a.acc = st->acc;
   a.stepno = st->stepno;
   a.mode = mode;
-  a.pad_ = 0;
+  a.wpb = 0;  // set by the launcher
   a.tau = qw::kTau;
   a.yacc = yacc;
   a.coefm = coefm;

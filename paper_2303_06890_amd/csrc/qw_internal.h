@@ -92,7 +92,7 @@ struct StepArgs {
   unsigned long long* acc;  // per-workgroup running count of branches written
   uint32_t* stepno;         // per-wavefront step counter (indexes coefm), kMaxWaves entries
   int32_t mode;             // kStep: W; kSwap: S only
-  int32_t pad_;
+  int32_t wpb;              // wavefronts per workgroup (set by the launcher)
   double tau;
   // optional fused projection (linear solver): y[j] += coefm[step] <psi~_j|state>
   double2* yacc;
@@ -107,7 +107,9 @@ struct AdjArgs {
   unsigned long long* acc;
   unsigned long long* lacc;
   double tau;
-  double* dv;       // gradient per ELL slot, accumulated
+  double* dv;       // gradient per slot (by home), accumulated
+  int32_t wpb;      // wavefronts per workgroup (set by the launcher)
+  int32_t pad_;
 };
 
 // The host side is compiled by the host compiler and the kernels by the GPU
@@ -118,7 +120,7 @@ static_assert(sizeof(List) == 24 && offsetof(List, cap) == 20, "List layout");
 static_assert(sizeof(SlotRec) == 16 && offsetof(SlotRec, val) == 8, "SlotRec layout");
 static_assert(sizeof(Matrix) == 144 && offsetof(Matrix, inst0) == 88, "Matrix layout");
 static_assert(sizeof(StepArgs) == 280 && offsetof(StepArgs, coefm) == 272, "StepArgs layout");
-static_assert(sizeof(AdjArgs) == 352 && offsetof(AdjArgs, dv) == 344, "AdjArgs layout");
+static_assert(sizeof(AdjArgs) == 360 && offsetof(AdjArgs, wpb) == 352, "AdjArgs layout");
 
 // Launchers (qw_launch.cpp).  All enqueue on `stream` and allocate nothing.
 hipError_t launch_step(const StepArgs& a, int grid, int block, hipStream_t stream);

@@ -397,7 +397,7 @@ __device__ __forceinline__ unsigned step_wave(const StepArgs& a, int64_t w, int 
 template <bool ACC, int SLM, int S>
 __device__ __forceinline__ void step_body(const StepArgs& a) {
   const int lane = threadIdx.x & (kWave - 1);
-  const int64_t wpb = blockDim.x >> 6;
+  const int64_t wpb = a.wpb;  // a kernel argument: reading the workgroup size costs a vector load
   const int64_t wid = int64_t(blockIdx.x) * wpb + (threadIdx.x >> 6);  // this wavefront's counter
   const int64_t lw = (int64_t(a.L.cnt) + kWave - 1) / kWave;
   const int64_t total = a.m.waves + lw;
@@ -538,7 +538,7 @@ __device__ __forceinline__ void adjoint_wave(const AdjArgs& a, int64_t w, int la
 template <int SLM>
 __device__ __forceinline__ void adjoint_body(const AdjArgs& a) {
   const int lane = threadIdx.x & (kWave - 1);
-  const int64_t wpb = blockDim.x >> 6;
+  const int64_t wpb = a.wpb;
   const int64_t lw = (int64_t(a.L.cnt) + kWave - 1) / kWave;
   const int64_t llw = (int64_t(a.LL.cnt) + kWave - 1) / kWave;
   const int64_t total = a.m.waves + lw + llw;

@@ -128,13 +128,18 @@ int clamp_grid(int64_t work, int64_t limit) {
 }  // namespace
 
 hipError_t launch_step(const StepArgs& a, int grid, int block, hipStream_t stream) {
+  if (block < kWave || block > kMaxBlock || block % kWave) return hipErrorInvalidValue;
   StepArgs c = a;
+  c.wpb = block / kWave;
   void* p[] = {&c};
   return launch(step_kernel(a.m, a.yacc != nullptr), grid, block, stream, p);
 }
 
 hipError_t launch_adjoint(const AdjArgs& a, int grid, int block, hipStream_t stream) {
+  if (block < kWave || block > kMaxBlock || block % kWave) return hipErrorInvalidValue;
   AdjArgs c = a;
+  c.wpb = block / kWave;
+  c.pad_ = 0;
   void* p[] = {&c};
   return launch(Fn(F_ADJOINT_S1 + width_index(a.m.slmax)), grid, block, stream, p);
 }
