@@ -116,7 +116,7 @@ struct qw_ctx {
   }
   int32_t smax = 1;
   int32_t slmax = 1;
-  int32_t suni = 0;  // s shared by every instance, 0 when they differ
+  int32_t suni = 0;  // s shared by every instance (each with >= one wavefront of rows), else 0
 };
 
 namespace {
@@ -159,7 +159,8 @@ void free_graphs(qw_state* st) {
 
 int step_grid(const qw_state* st) {
   if (st->grid > 0) return st->grid;
-  const int64_t lanes = st->ctx->waves * qw::kWave;  // one pass of the step kernel
+  // one pass of the step kernel over the slots and the list
+  const int64_t lanes = (st->ctx->waves + (int64_t(st->L.cnt) + qw::kWave - 1) / qw::kWave) * qw::kWave;
   int64_t g = (lanes + st->block - 1) / st->block;
   g = std::max<int64_t>(1, std::min<int64_t>(g, qw::kMaxGrid));
   return int(g);
@@ -425,8 +426,8 @@ int load_impl(qw_ctx** out, int32_t ninst, const int32_t* n, const int64_t* colp
   ctx->waves = waves;
   ctx->inst0 = dinst[0];
   ctx->suni = dinst[0].s;
-  for (int32_t i = 1; i < ninst; ++i)
-    if (dinst[i].s != ctx->suni) ctx->suni = 0;
+  for (int32_t i = 0; i < ninst; ++i)
+    if (dinst[i].s != ctx->suni || dinst[i].N < (64 >> dinst[i].lpr_log)) ctx->suni = 0;
   std::vector<int32_t> hwave(static_cast<size_t>(waves));
   for (int32_t i = 0; i < ninst; ++i) {
     const int64_t end = i + 1 < ninst ? dinst[i + 1].wave_base : waves;

@@ -274,7 +274,7 @@ struct Lanes {
   int j, h, rpw_log;
   bool live;
 };
-template <int S>
+template <int S, bool FULL = false>
 __device__ __forceinline__ Lanes lanes_of(const Matrix& m, int64_t w, int lane) {
   Lanes x;
   x.inst = m.ninst == 1 ? 0 : uload(m.wave_inst + w);
@@ -282,8 +282,8 @@ __device__ __forceinline__ Lanes lanes_of(const Matrix& m, int64_t w, int lane) 
   x.rpw_log = S ? Shape<S>::rpw_log : 6 - x.I.lpr_log;
   x.h = lane >> x.rpw_log;
   const int64_t j = ((w - x.I.wave_base) << x.rpw_log) + (lane & ((1 << x.rpw_log) - 1));
-  x.live = j < x.I.N;
-  x.j = x.live ? int(j) : 0;  // rows past N (instances with N < 2^rpw_log) read row 0 and write nothing
+  x.live = FULL || j < x.I.N;  // FULL: every N is a multiple of 2^rpw_log
+  x.j = x.live ? int(j) : 0;   // rows past N (instances with N < 2^rpw_log) read row 0 and write nothing
   return x;
 }
 
@@ -338,10 +338,11 @@ __device__ __forceinline__ unsigned list_entry(const List& L, int64_t e, int n, 
 
 // One wavefront of the step: up to SLM slots per lane, held in registers.
 // The data loads do not depend on each other or on the instance record
-// beyond its base, so they are issued together.
-template <bool ACC, int SLM, int S>
+// beyond its base, so they are issued together.  FAST: walk step (not the
+// swap) and every row of every wavefront exists.
+template <bool ACC, int SLM, int S, bool FAST>
 __device__ __forceinline__ unsigned step_wave(const StepArgs& a, int64_t w, int lane, double coef) {
-  const Lanes x = lanes_of<S>(a.m, w, lane);
+  const Lanes x = lanes_of<S, FAST>(a.m, w, lane);
   const int sl = S ? Shape<S>::sl : (SLM == 1 ? 1 : x.I.sl);
   const int64_t base = x.I.item_base;
   int64_t h[SLM];
@@ -358,7 +359,7 @@ __device__ __forceinline__ unsigned step_wave(const StepArgs& a, int64_t w, int 
       y1[i] = a.in.Q1[h[i]];
     }
   }
-  const bool step = a.mode == kStep;
+  const bool step = FAST || a.mode == kStep;
   double2 c = zero2();
 #pragma unroll
   for (int i = 0; i < SLM; ++i) {
@@ -393,14 +394,13 @@ __device__ __forceinline__ unsigned step_wave(const StepArgs& a, int64_t w, int 
 }
 
 // SLM: slots per lane held in registers; S: s of every instance, or 0 (read
-// per instance, slots per lane <= SLM).
-template <bool ACC, int SLM, int S>
+// per instance, slots per lane <= SLM).  FAST: one pass (the grid covers
+// every wavefront and the list), walk step only, every row exists.
+template <bool ACC, int SLM, int S, bool FAST>
 __device__ __forceinline__ void step_body(const StepArgs& a) {
   const int lane = threadIdx.x & (kWave - 1);
   const int64_t wpb = a.wpb;  // a kernel argument: reading the workgroup size costs a vector load
   const int64_t wid = int64_t(blockIdx.x) * wpb + (threadIdx.x >> 6);  // this wavefront's counter
-  const int64_t lw = (int64_t(a.L.cnt) + kWave - 1) / kWave;
-  const int64_t total = a.m.waves + lw;
   double coef = 0.0;
   uint32_t stepno = 0;
   if (ACC) {
@@ -408,12 +408,21 @@ __device__ __forceinline__ void step_body(const StepArgs& a) {
     coef = a.coefm[stepno];
   }
   unsigned cnt = 0;
-  const int64_t wstride = int64_t(gridDim.x) * wpb;
-  for (int64_t w = uniform(int(wid)); w < total; w += wstride) {
+  if (FAST) {
+    const int64_t w = uniform(int(wid));
     if (w < a.m.waves)
-      cnt += step_wave<ACC, SLM, S>(a, w, lane, coef);
+      cnt = step_wave<ACC, SLM, S, true>(a, w, lane, coef);
     else
-      cnt += list_entry(a.L, (w - a.m.waves) * kWave + lane, a.m.nbits, a.mode == kStep);
+      cnt = list_entry(a.L, (w - a.m.waves) * kWave + lane, a.m.nbits, true);
+  } else {
+    const int64_t total = a.m.waves + (int64_t(a.L.cnt) + kWave - 1) / kWave;
+    const int64_t wstride = int64_t(gridDim.x) * wpb;
+    for (int64_t w = uniform(int(wid)); w < total; w += wstride) {
+      if (w < a.m.waves)
+        cnt += step_wave<ACC, SLM, S, false>(a, w, lane, coef);
+      else
+        cnt += list_entry(a.L, (w - a.m.waves) * kWave + lane, a.m.nbits, a.mode == kStep);
+    }
   }
   wave_count(cnt, a.acc);
   if (ACC && lane == 0) a.stepno[wid] = stepno + 1;
@@ -421,26 +430,27 @@ __device__ __forceinline__ void step_body(const StepArgs& a) {
 
 }  // namespace qw
 
-// qwk_step_sN: any s per instance, up to N slots per lane (s <= 8N);
-// qwk_step_fS: every instance has s = S.
-#define QW_STEP_KERNEL(NAME, SLM, S)                                                               \
+// qwk_step_sN: any s per instance, up to N slots per lane (s <= 8N), any
+// launch shape, walk step or swap; qwk_step_fS: every instance has s = S and
+// at least 64 / min(S, 8) rows, one pass, walk step.
+#define QW_STEP_KERNEL(NAME, SLM, S, FAST)                                                         \
   extern "C" __global__ void __launch_bounds__(256) NAME(qw::StepArgs a) {                         \
-    qw::step_body<false, SLM, S>(a);                                                                \
+    qw::step_body<false, SLM, S, FAST>(a);                                                          \
   }                                                                                                 \
   extern "C" __global__ void __launch_bounds__(256) NAME##_acc(qw::StepArgs a) {                   \
-    qw::step_body<true, SLM, S>(a);                                                                 \
+    qw::step_body<true, SLM, S, FAST>(a);                                                           \
   }
-QW_STEP_KERNEL(qwk_step_s1, 1, 0)
-QW_STEP_KERNEL(qwk_step_s2, 2, 0)
-QW_STEP_KERNEL(qwk_step_s4, 4, 0)
-QW_STEP_KERNEL(qwk_step_s8, 8, 0)
-QW_STEP_KERNEL(qwk_step_f1, 1, 1)
-QW_STEP_KERNEL(qwk_step_f2, 1, 2)
-QW_STEP_KERNEL(qwk_step_f4, 1, 4)
-QW_STEP_KERNEL(qwk_step_f8, 1, 8)
-QW_STEP_KERNEL(qwk_step_f16, 2, 16)
-QW_STEP_KERNEL(qwk_step_f32, 4, 32)
-QW_STEP_KERNEL(qwk_step_f64, 8, 64)
+QW_STEP_KERNEL(qwk_step_s1, 1, 0, false)
+QW_STEP_KERNEL(qwk_step_s2, 2, 0, false)
+QW_STEP_KERNEL(qwk_step_s4, 4, 0, false)
+QW_STEP_KERNEL(qwk_step_s8, 8, 0, false)
+QW_STEP_KERNEL(qwk_step_f1, 1, 1, true)
+QW_STEP_KERNEL(qwk_step_f2, 1, 2, true)
+QW_STEP_KERNEL(qwk_step_f4, 1, 4, true)
+QW_STEP_KERNEL(qwk_step_f8, 1, 8, true)
+QW_STEP_KERNEL(qwk_step_f16, 2, 16, true)
+QW_STEP_KERNEL(qwk_step_f32, 4, 32, true)
+QW_STEP_KERNEL(qwk_step_f64, 8, 64, true)
 #undef QW_STEP_KERNEL
 
 
@@ -483,7 +493,7 @@ extern "C" __global__ void __launch_bounds__(256) qwk_qbs_table(Matrix m, SlotRe
 template <int SLM>
 __device__ __forceinline__ void adjoint_wave(const AdjArgs& a, int64_t w, int lane, unsigned& cnt,
                                              unsigned& lcnt) {
-  const Lanes x = lanes_of<0>(a.m, w, lane);
+  const Lanes x = lanes_of<0, false>(a.m, w, lane);
   const int sl = SLM == 1 ? 1 : x.I.sl;
   const int64_t base = x.I.item_base;
   int64_t h[SLM];

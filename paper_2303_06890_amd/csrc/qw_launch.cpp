@@ -21,9 +21,11 @@ namespace qw {
 namespace {
 
 // Step kernels: qwk_step_s{1,2,4,8} take any s per instance with up to that
-// many slots held per lane (s <= 8, 16, 32, 64); qwk_step_f{S} are compiled
-// for matrices whose instances all have s = S.  Each has an _acc twin (the
-// solver's fused projection).  Adjoint kernels come in the four widths.
+// many slots held per lane (s <= 8, 16, 32, 64), any launch shape and either
+// mode; qwk_step_f{S} are compiled for matrices whose instances all have
+// s = S (and at least one wavefront's rows), a grid that covers the work in
+// one pass, and the walk step.  Each has an _acc twin (the solver's fused
+// projection).  Adjoint kernels come in the four widths.
 enum Fn {
   F_STEP_S1,
   F_STEP_S2,
@@ -65,9 +67,12 @@ const char* const kNames[F_COUNT] = {
 // 0..3 for slmax = 1, 2, 4, 8
 int width_index(int32_t slmax) { return slmax <= 1 ? 0 : slmax <= 2 ? 1 : slmax <= 4 ? 2 : 3; }
 
-Fn step_kernel(const Matrix& m, bool acc) {
+Fn step_kernel(const StepArgs& a, int grid, int block) {
+  const Matrix& m = a.m;
+  const bool acc = a.yacc != nullptr;
+  const int64_t work = m.waves + (int64_t(a.L.cnt) + kWave - 1) / kWave;
   int f = F_STEP_S1 + width_index(m.slmax);
-  if (m.suni > 0) {
+  if (m.suni > 0 && a.mode == kStep && int64_t(grid) * (block / kWave) >= work) {
     int lg = 0;
     while ((1 << lg) < m.suni) ++lg;
     f = F_STEP_F1 + lg;
@@ -132,7 +137,7 @@ hipError_t launch_step(const StepArgs& a, int grid, int block, hipStream_t strea
   StepArgs c = a;
   c.wpb = block / kWave;
   void* p[] = {&c};
-  return launch(step_kernel(a.m, a.yacc != nullptr), grid, block, stream, p);
+  return launch(step_kernel(c, grid, block), grid, block, stream, p);
 }
 
 hipError_t launch_adjoint(const AdjArgs& a, int grid, int block, hipStream_t stream) {

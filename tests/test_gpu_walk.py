@@ -220,6 +220,28 @@ def test_graph_replay_matches_direct(Q):
     assert np.array_equal(ka, kc) and np.array_equal(aa, ac)
 
 
+@pytest.mark.parametrize("n,c", [(2048, 8), (512, 16), (256, 3)])
+def test_launch_shapes_agree(Q, oracle_mod, n, c):
+    """The one-pass kernel compiled for the matrix's s (default shape) and the
+    general grid-stride kernel (grids too small for one pass) give the same
+    state, and both match the oracle."""
+    csc = W.offset_matrix(n, c, seed=n + c)
+    b = W.gaussian_b(n, seed=n)
+    walk = Q.Walk(csc)
+    runs = []
+    for shape in (None, (64, 3), (256, 1), (128, 7)):
+        st = walk.state(b)
+        if shape:
+            st.set_launch(*shape)
+        runs.append(st.step(21).export())
+    for k, a in runs[1:]:
+        assert np.array_equal(k, runs[0][0])
+        assert np.abs(a - runs[0][1]).max() <= 1e-15
+    om = oracle_mod.OracleMatrix(csc)
+    ok, oa = oracle_mod.OracleState(om).set_b(b).T().step(21).export()
+    compare_states(runs[0][0], runs[0][1], ok, oa, where=f"n={n} c={c}")
+
+
 def test_deterministic(Q):
     csc = W.offset_matrix(2048, 8, seed=25)
     b = W.gaussian_b(2048, seed=26)
