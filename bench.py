@@ -18,8 +18,10 @@ average launch time measured with HIP events on the kernels' stream, against
 8 TB/s), and the oracle's rate on the host CPU for a bounded sample.
 """
 import argparse
+import hashlib
 import json
 import os
+import re
 import platform
 import sys
 import time
@@ -28,6 +30,25 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "step_kernel_G16384x8_traffic.md")
+KERNEL_SOURCES = [os.path.join(ROOT, "paper_2303_06890_amd", "csrc", f) for f in ("qw_kernels.hip", "qw_internal.h")]
+
+
+def measured_traffic():
+    """HBM bytes per step launch from the committed counter summary (calibrated
+    FETCH_SIZE + WRITE_SIZE), or None when the summary is missing or was taken
+    on other kernel sources than the ones in this tree."""
+    try:
+        with open(TRAFFIC_PROFILE) as f:
+            text = f.read()
+        digest = hashlib.sha256(b"".join(open(p, "rb").read() for p in KERNEL_SOURCES)).hexdigest()
+    except OSError:
+        return None
+    m = re.search(r"traffic_bytes_per_launch: (\d+)", text)
+    h = re.search(r"sha256 ([0-9a-f]{64})", text)
+    if not m or not h or h.group(1) != digest:
+        return None
+    return float(m.group(1))
 
 
 def cpu_model() -> str:
@@ -162,7 +183,7 @@ def main():
                     help="run one extra leg alone (for profiling) and print its JSON")
     ap.add_argument("--pmc-run", action="store_true",
                     help="counter run: a torch copy of 64 MiB (byte calibration), then 64 walk steps of "
-                         "the main workload with the default launch shape; prints nothing else")
+                         "the main workload (default launch shape unless --launch); prints nothing else")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on exactly one GPU: this build has no multi-GPU path "
@@ -184,7 +205,10 @@ def main():
         dst.copy_(src)
         torch.cuda.synchronize()
         csc, b = W.paper_scale()
-        st = Q.Walk(csc).state(b).step(64)
+        st = Q.Walk(csc).state(b)
+        if args.launch:
+            st.set_launch(*(int(v) for v in args.launch.split(",")))
+        st.step(64)
         st.sync()
         print(json.dumps({"pmc_run": True, "copy_bytes": 8 << 23, "steps": 64}), flush=True)
         return
@@ -252,7 +276,8 @@ def main():
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS,
-            "traffic": None,
+            "traffic": measured_traffic(),
+            "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
             "alg_bytes_per_launch": alg_bytes / args.steps,
             "avg_launch_us": launch_s * 1e6,
         },
