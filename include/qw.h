@@ -194,9 +194,9 @@ const char* qw_last_error(void);
 void qw_shutdown(void);
 
 /* Launch shape of the step kernel: workgroup size (64..256, a multiple of
- * 64) and number of workgroups, 1..8192 (a grid smaller than one pass over
+ * 64) and number of workgroups, 1..65536 (a grid smaller than one pass over
  * the work makes the kernel stride); 0 keeps the current value (default: 256
- * and one pass, at most 8192).  Captured graphs are discarded.  Used by the
+ * and one pass, at most 65536).  Captured graphs are discarded.  Used by the
  * autotuner.  Errors: QW_EINVAL for sizes out of range. */
 int qw_set_launch(qw_state* st, int32_t wg_size, int32_t grid_limit);
 

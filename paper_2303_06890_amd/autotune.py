@@ -34,8 +34,8 @@ def candidates(walk):
     out = []
     for wg in (64, 128, 256):
         one_pass = max(1, -(-lanes // wg))
-        for grid in sorted({min(one_pass, 8192), 1024, 2048, 4096, 8192}):
-            if grid <= one_pass or grid == min(one_pass, 8192):
+        for grid in sorted({min(one_pass, 65536), 1024, 2048, 4096, 8192}):
+            if grid <= one_pass:
                 out.append((wg, grid))
     return out
 

@@ -110,13 +110,14 @@ struct qw_ctx {
     m.smax = smax;
     m.slmax = slmax;
     m.suni = suni;
-    m.pad_ = 0;
+    m.full = full;
     m.inst0 = inst0;
     return m;
   }
   int32_t smax = 1;
   int32_t slmax = 1;
-  int32_t suni = 0;  // s shared by every instance (each with >= one wavefront of rows), else 0
+  int32_t suni = 0;  // s shared by every instance, else 0
+  int32_t full = 0;  // every instance has at least one step-kernel wavefront of rows
 };
 
 namespace {
@@ -426,8 +427,11 @@ int load_impl(qw_ctx** out, int32_t ninst, const int32_t* n, const int64_t* colp
   ctx->waves = waves;
   ctx->inst0 = dinst[0];
   ctx->suni = dinst[0].s;
-  for (int32_t i = 0; i < ninst; ++i)
-    if (dinst[i].s != ctx->suni || dinst[i].N < (64 >> dinst[i].lpr_log)) ctx->suni = 0;
+  ctx->full = 1;
+  for (int32_t i = 0; i < ninst; ++i) {
+    if (dinst[i].s != ctx->suni) ctx->suni = 0;
+    if (dinst[i].N < (64 >> dinst[i].lpr_log)) ctx->full = 0;
+  }
   std::vector<int32_t> hwave(static_cast<size_t>(waves));
   for (int32_t i = 0; i < ninst; ++i) {
     const int64_t end = i + 1 < ninst ? dinst[i + 1].wave_base : waves;
@@ -763,7 +767,7 @@ int qw_set_launch(qw_state* st, int32_t wg_size, int32_t grid) {
     st->block = wg_size;
   }
   if (grid) {
-    if (grid < 1 || grid > qw::kMaxGrid) return set_err(QW_EINVAL, "grid out of range (1..8192)");
+    if (grid < 1 || grid > qw::kMaxGrid) return set_err(QW_EINVAL, "grid out of range (1..65536)");
     st->grid = grid;
   }
   free_graphs(st);

@@ -11,7 +11,7 @@ namespace qw {
 
 constexpr int kWave = 64;       // CDNA wavefront width
 constexpr int kMaxS = 64;       // largest QRAM row length handled (one wave per group)
-constexpr int kMaxGrid = 8192;  // largest step-kernel grid (per-workgroup counters)
+constexpr int kMaxGrid = 65536;  // largest step-kernel grid (per-workgroup counters)
 constexpr int kMaxBlock = 256;  // largest step-kernel workgroup
 constexpr int kMaxWaves = kMaxGrid * (kMaxBlock / kWave);  // per-wavefront counters
 constexpr double kTau = 1e-13;  // pruning threshold applied after every step
@@ -79,7 +79,7 @@ struct Matrix {
   int32_t smax;              // largest s over the instances
   int32_t slmax;             // largest slots-per-lane over the instances
   int32_t suni;              // s of every instance when they all share it, else 0
-  int32_t pad_;
+  int32_t full;              // 1 when every instance has at least one wavefront of rows
   Inst inst0;                // copy of inst[0] (a single instance needs no table read)
 };
 

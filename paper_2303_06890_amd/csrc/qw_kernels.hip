@@ -289,9 +289,15 @@ __device__ __forceinline__ Lanes lanes_of(const Matrix& m, int64_t w, int lane) 
 
 // Count of a wavefront added to its workgroup's counter by one lane (no
 // barrier: the wavefronts of a workgroup finish independently).
+// The wavefront sum is taken bit plane by bit plane with ballots and
+// population counts (scalar work), not with a chain of lane shuffles: it
+// sits on the path to the end of every wavefront.
 __device__ __forceinline__ void wave_count(unsigned cnt, unsigned long long* acc) {
-  unsigned long long v = cnt;
-  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+  unsigned long long v = 0;
+  for (int b = 0; b < 32; ++b) {
+    v += static_cast<unsigned long long>(__popcll(__ballot((cnt >> b) & 1u))) << b;
+    if (__ballot((cnt >> b) > 1u) == 0) break;  // no higher bit set in any lane
+  }
   if ((threadIdx.x & (kWave - 1)) == 0) atomicAdd(&acc[blockIdx.x], v);
 }
 
@@ -431,8 +437,9 @@ __device__ __forceinline__ void step_body(const StepArgs& a) {
 }  // namespace qw
 
 // qwk_step_sN: any s per instance, up to N slots per lane (s <= 8N), any
-// launch shape, walk step or swap; qwk_step_fS: every instance has s = S and
-// at least 64 / min(S, 8) rows, one pass, walk step.
+// launch shape, walk step or swap; qwk_step_gN: the same s per instance, but
+// every instance has at least one wavefront of rows, one pass, walk step;
+// qwk_step_fS: as gN with s = S for every instance.
 #define QW_STEP_KERNEL(NAME, SLM, S, FAST)                                                         \
   extern "C" __global__ void __launch_bounds__(256) NAME(qw::StepArgs a) {                         \
     qw::step_body<false, SLM, S, FAST>(a);                                                          \
@@ -444,6 +451,10 @@ QW_STEP_KERNEL(qwk_step_s1, 1, 0, false)
 QW_STEP_KERNEL(qwk_step_s2, 2, 0, false)
 QW_STEP_KERNEL(qwk_step_s4, 4, 0, false)
 QW_STEP_KERNEL(qwk_step_s8, 8, 0, false)
+QW_STEP_KERNEL(qwk_step_g1, 1, 0, true)
+QW_STEP_KERNEL(qwk_step_g2, 2, 0, true)
+QW_STEP_KERNEL(qwk_step_g4, 4, 0, true)
+QW_STEP_KERNEL(qwk_step_g8, 8, 0, true)
 QW_STEP_KERNEL(qwk_step_f1, 1, 1, true)
 QW_STEP_KERNEL(qwk_step_f2, 1, 2, true)
 QW_STEP_KERNEL(qwk_step_f4, 1, 4, true)

@@ -22,15 +22,20 @@ namespace {
 
 // Step kernels: qwk_step_s{1,2,4,8} take any s per instance with up to that
 // many slots held per lane (s <= 8, 16, 32, 64), any launch shape and either
-// mode; qwk_step_f{S} are compiled for matrices whose instances all have
-// s = S (and at least one wavefront's rows), a grid that covers the work in
-// one pass, and the walk step.  Each has an _acc twin (the solver's fused
-// projection).  Adjoint kernels come in the four widths.
+// mode; qwk_step_g{1,2,4,8} need every instance to have at least one
+// wavefront's rows, a grid that covers the work in one pass, and the walk
+// step; qwk_step_f{S} need that and s = S for every instance.  Each has an
+// _acc twin (the solver's fused projection).  Adjoint kernels come in the
+// four widths.
 enum Fn {
   F_STEP_S1,
   F_STEP_S2,
   F_STEP_S4,
   F_STEP_S8,
+  F_STEP_G1,
+  F_STEP_G2,
+  F_STEP_G4,
+  F_STEP_G8,
   F_STEP_F1,
   F_STEP_F2,
   F_STEP_F4,
@@ -56,13 +61,15 @@ enum Fn {
 };
 
 const char* const kNames[F_COUNT] = {
-    "qwk_step_s1",     "qwk_step_s2",     "qwk_step_s4",      "qwk_step_s8",      "qwk_step_f1",
-    "qwk_step_f2",     "qwk_step_f4",     "qwk_step_f8",      "qwk_step_f16",     "qwk_step_f32",
-    "qwk_step_f64",    "qwk_step_s1_acc", "qwk_step_s2_acc",  "qwk_step_s4_acc",  "qwk_step_s8_acc",
-    "qwk_step_f1_acc", "qwk_step_f2_acc", "qwk_step_f4_acc",  "qwk_step_f8_acc",  "qwk_step_f16_acc",
-    "qwk_step_f32_acc", "qwk_step_f64_acc", "qwk_adjoint_s1", "qwk_adjoint_s2",   "qwk_adjoint_s4",
-    "qwk_adjoint_s8",  "qwk_qbs_table",   "qwk_init",         "qwk_fill",         "qwk_measure",
-    "qwk_measure_rows", "qwk_export",     "qwk_import",       "qwk_weight",       "qwk_grad_init"};
+    "qwk_step_s1",      "qwk_step_s2",      "qwk_step_s4",      "qwk_step_s8",      "qwk_step_g1",
+    "qwk_step_g2",      "qwk_step_g4",      "qwk_step_g8",      "qwk_step_f1",      "qwk_step_f2",
+    "qwk_step_f4",      "qwk_step_f8",      "qwk_step_f16",     "qwk_step_f32",     "qwk_step_f64",
+    "qwk_step_s1_acc",  "qwk_step_s2_acc",  "qwk_step_s4_acc",  "qwk_step_s8_acc",  "qwk_step_g1_acc",
+    "qwk_step_g2_acc",  "qwk_step_g4_acc",  "qwk_step_g8_acc",  "qwk_step_f1_acc",  "qwk_step_f2_acc",
+    "qwk_step_f4_acc",  "qwk_step_f8_acc",  "qwk_step_f16_acc", "qwk_step_f32_acc", "qwk_step_f64_acc",
+    "qwk_adjoint_s1",   "qwk_adjoint_s2",   "qwk_adjoint_s4",   "qwk_adjoint_s8",   "qwk_qbs_table",
+    "qwk_init",         "qwk_fill",         "qwk_measure",      "qwk_measure_rows", "qwk_export",
+    "qwk_import",       "qwk_weight",       "qwk_grad_init"};
 
 // 0..3 for slmax = 1, 2, 4, 8
 int width_index(int32_t slmax) { return slmax <= 1 ? 0 : slmax <= 2 ? 1 : slmax <= 4 ? 2 : 3; }
@@ -72,10 +79,13 @@ Fn step_kernel(const StepArgs& a, int grid, int block) {
   const bool acc = a.yacc != nullptr;
   const int64_t work = m.waves + (int64_t(a.L.cnt) + kWave - 1) / kWave;
   int f = F_STEP_S1 + width_index(m.slmax);
-  if (m.suni > 0 && a.mode == kStep && int64_t(grid) * (block / kWave) >= work) {
-    int lg = 0;
-    while ((1 << lg) < m.suni) ++lg;
-    f = F_STEP_F1 + lg;
+  if (m.full && a.mode == kStep && int64_t(grid) * (block / kWave) >= work) {
+    f = F_STEP_G1 + width_index(m.slmax);
+    if (m.suni > 0) {
+      int lg = 0;
+      while ((1 << lg) < m.suni) ++lg;
+      f = F_STEP_F1 + lg;
+    }
   }
   return Fn(f + (acc ? int(F_STEP_COUNT_) : 0));
 }

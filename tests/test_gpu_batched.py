@@ -93,16 +93,16 @@ def test_batched_vs_oracle(Q, oracle_mod):
 
 @pytest.mark.parametrize("kind", ["small_s", "wide_s"])
 def test_batched_mixed_row_lengths(Q, oracle_mod, kind):
-    """Instances whose s differ (1 ... 8, or up to 64): the step kernel reads
-    each wavefront's lane mapping from its instance; every slice must match
-    the oracle."""
+    """Instances whose s differ (1 ... 8 with instances smaller than a
+    wavefront's rows, or 4 ... 64): the step kernel reads each wavefront's
+    lane mapping from its instance; every slice must match the oracle."""
     diag = W.from_dense(np.diag(np.linspace(0.2, 0.8, 12)))           # s = 1
     pair = W.from_dense(np.array([[0.3, 0.5], [0.5, 0.6]]))           # s = 2
     if kind == "small_s":
         mats = [diag, W.offset_matrix(40, 3, seed=51), pair, W.offset_matrix(100, 7, seed=52)]
-    else:
+    else:  # every instance has a full wavefront of rows: the one-pass kernel
         mats = [W.offset_matrix(64, 33, seed=53), W.offset_matrix(24, 3, seed=54),
-                diag, W.offset_matrix(128, 20, seed=55), W.offset_matrix(96, 12, seed=56)]
+                W.offset_matrix(128, 20, seed=55), W.offset_matrix(96, 12, seed=56)]
     bs = [W.gaussian_b(m.n, seed=60 + i) for i, m in enumerate(mats)]
     walk = Q.Walk(mats)
     st = walk.state(bs).step(15)
