@@ -137,6 +137,32 @@ def batched_leg(Q, W, autotune, tune: bool, steps: int = 50):
     }
 
 
+def band_leg(Q, W, autotune, tune: bool, steps: int = 200):
+    """The paper's band family at 16384 columns, 63 entries per interior column
+    (s = 64), uniform start: the shape of the paper's largest single-core
+    walk-step measurement (context only; another machine, another code)."""
+    csc, b = W.paper_band()
+    walk = Q.Walk(csc)
+    shape = autotune.tune(walk, b) if tune else None
+    st = walk.state(b)
+    if shape:
+        autotune.apply(st, shape)
+    st.step(32)
+    s0 = st.stats()
+    ms = _timed(Q, lambda: st.step(steps))
+    upd = st.stats()["total_written"] - s0["total_written"]
+    return {
+        "workload": "band matrix n = 16384, bandwidth 31 (s = 64), seed 7, uniform b, T~ start",
+        "slots": int(walk.info[0]["N"] * walk.info[0]["s"]),
+        "branches": st.count(),
+        "steps": steps,
+        "us_per_step": 1e3 * ms / steps,
+        "value": upd / (ms / 1e3),
+        "launch_shape": list(shape) if shape else "default",
+        "paper_single_core_s_per_step": 66.0,
+    }
+
+
 def adjoint_leg(Q, W, steps: int = 20, reps: int = 5):
     """Gradient of the total probability of 32 column outcomes after 20 steps
     on G(1024, 8) w.r.t. all 8192 values and b (forward walk + reverse sweep
@@ -175,11 +201,11 @@ def main():
     ap.add_argument("--warmup", type=int, default=64)
     ap.add_argument("--cpu-steps", type=int, default=5, help="walk steps of the oracle sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-extras", action="store_true", help="skip the batched and adjoint legs")
+    ap.add_argument("--no-extras", action="store_true", help="skip the batched, adjoint and band legs")
     ap.add_argument("--no-tune", action="store_true", help="keep the default launch shape")
     ap.add_argument("--launch", default=None, metavar="WG,GRID",
                     help="fixed launch shape of the main leg (workgroup size, workgroups)")
-    ap.add_argument("--only", choices=["batched", "adjoint"], default=None,
+    ap.add_argument("--only", choices=["batched", "adjoint", "band"], default=None,
                     help="run one extra leg alone (for profiling) and print its JSON")
     ap.add_argument("--pmc-run", action="store_true",
                     help="counter run: a torch copy of 64 MiB (byte calibration), then 64 walk steps of "
@@ -217,6 +243,9 @@ def main():
         return
     if args.only == "adjoint":
         print(json.dumps(adjoint_leg(Q, W)), flush=True)
+        return
+    if args.only == "band":
+        print(json.dumps(band_leg(Q, W, autotune, not args.no_tune)), flush=True)
         return
     csc, b = W.paper_scale()
     walk = Q.Walk(csc)
@@ -289,6 +318,8 @@ def main():
         print(f"[bench] batched: {line['batched']}", file=sys.stderr, flush=True)
         line["adjoint"] = adjoint_leg(Q, W)
         print(f"[bench] adjoint: {line['adjoint']}", file=sys.stderr, flush=True)
+        line["band"] = band_leg(Q, W, autotune, not args.no_tune)
+        print(f"[bench] band: {line['band']}", file=sys.stderr, flush=True)
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(csc, b, args.cpu_steps)
         print(f"[bench] oracle: {line['cpu_baseline']['value']:.3e} updates/s", file=sys.stderr, flush=True)

@@ -153,6 +153,21 @@ def test_edge_shapes(Q, oracle_mod):
         _check(st, ost, f"n={n} step 12")
 
 
+def test_band_s64_20_steps(Q, oracle_mod):
+    """The paper's band family with 63 entries per interior column (s = 64,
+    eight slots per lane, filler slots at the band's ends)."""
+    csc = W.band_matrix(96, 31, seed=71)
+    b = W.gaussian_b(96, seed=72)
+    walk, st, ost = _pair(Q, oracle_mod, csc, b)
+    assert walk.info[0]["s"] == 64
+    done = 0
+    for t in (1, 5, 20):
+        st.step(t - done)
+        ost.step(t - done)
+        done = t
+        _check(st, ost, f"band step {t}")
+
+
 def test_empty_state(Q):
     csc = W.offset_matrix(64, 4, seed=1)
     walk = Q.Walk(csc)

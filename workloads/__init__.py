@@ -124,11 +124,11 @@ def band_matrix(n: int, bandwidth: int, seed: int = 0) -> Csc:
     rows, cols, vals = [], [], []
     for d in range(0, bandwidth + 1):
         v = rng.uniform(0.0, 1.0, n - d)
-        for j in range(n - d):
-            rows.append(j), cols.append(j + d), vals.append(v[j])
-            if d:
-                rows.append(j + d), cols.append(j), vals.append(v[j])
-    return _from_triplets(n, rows, cols, vals)
+        j = np.arange(n - d)
+        rows.append(j), cols.append(j + d), vals.append(v)
+        if d:
+            rows.append(j + d), cols.append(j), vals.append(v)
+    return _from_triplets(n, np.concatenate(rows), np.concatenate(cols), np.concatenate(vals))
 
 
 def laplacian_2d(m: int = 32, shift: float = 0.1) -> Csc:
@@ -170,6 +170,13 @@ def tiny_tridiagonal():
 def paper_scale(n: int = 16384, c: int = 8, seed: int = 2):
     """G(16384, 8), uniform superposition over all columns."""
     return offset_matrix(n, c, seed=seed), uniform_b(n)
+
+
+def paper_band(n: int = 16384, bandwidth: int = 31, seed: int = 7):
+    """The paper's matrix family at its largest simulated size: a positive
+    symmetric band matrix with 2*31 + 1 = 63 entries per interior column
+    (s = 64), uniform superposition over all columns."""
+    return band_matrix(n, bandwidth, seed=seed), uniform_b(n)
 
 
 def batched_instances(count: int = 256, seed: int = 3, emin: int = 6, emax: int = 12,
