@@ -22,8 +22,8 @@
  *     qw_load_csc*, qw_state_init, qw_state_import, qw_step and
  *     qw_step_adjoint only enqueue work; qw_measure, qw_export, qls_run,
  *     qw_grad and qw_sync synchronise the stream and copy results to the host.
- *     Errors raised on the device (state capacity exceeded) are reported by
- *     the next synchronising call on that state.
+ *     No error is raised on the device: a state's storage is fixed when it is
+ *     created (see qw_state_init), so a step cannot overflow it.
  *   - Indices are 0-based.  A matrix is given in CSC form (colptr[n+1],
  *     rowidx[nnz] sorted and unique inside each column, vals[nnz] real).  The
  *     walk's row register j addresses CSC column j: the QRAM row j holds the
@@ -106,9 +106,12 @@ int qw_load_csc_batched(qw_ctx** out, int32_t ninst, const int32_t* n, const int
                         const qw_allocator* alloc, void* stream);
 
 /* Per-instance facts: padded dimension N, slots per row s, register width n
- * of the key layout (common to all instances), scale applied. */
+ * of the key layout (common to all instances), scale applied.  Any output
+ * pointer may be NULL.  Errors: QW_EINVAL for a NULL context or an instance
+ * index out of range. */
 int qw_ctx_info(const qw_ctx* ctx, int32_t inst, int32_t* n_padded, int32_t* s, int32_t* nbits,
                 double* scale);
+/* Number of instances of a context (0 for NULL). */
 int32_t qw_ctx_ninst(const qw_ctx* ctx);
 
 /* Create a state holding T~ |b~> (Alg. 5 applied to |b~> = sum_j b_j |0,j,0,0,0,0>,
@@ -126,13 +129,20 @@ int qw_state_init(qw_state** out, qw_ctx* ctx, const double* b_re, const double*
 /* Apply W^nsteps (Alg. 6: W = S T~ P T~^dagger), branches with |Re| and |Im|
  * both <= tau (1e-13) removed after every step.  One kernel launch per step;
  * asynchronous; the step loop is replayed from a captured HIP graph (16 steps
- * per graph) when `stream` is not NULL.  Allocates nothing. */
+ * per graph, built on first use for the stream and kept with the state) when
+ * `stream` is not NULL.  The state's amplitude planes are double-buffered
+ * inside the state; nothing is allocated once the graph exists.
+ * Errors: QW_EINVAL (NULL state, nsteps < 0), QW_EDEVICE (launch or graph
+ * failure). */
 int qw_step(qw_state* st, int32_t nsteps, void* stream);
 
-/* Apply (W^dagger)^nsteps, W^dagger = T~ P T~^dagger S (unitarity of W). */
+/* Apply (W^dagger)^nsteps, W^dagger = T~ P T~^dagger S (unitarity of W):
+ * a swap pass, nsteps walk steps, a swap pass.  Errors as qw_step. */
 int qw_step_adjoint(qw_state* st, int32_t nsteps, void* stream);
 
-/* Measurements (kinds above).  out_len is the number of elements of `out`. */
+/* Measurements (kinds above).  out_len is the number of elements of `out`.
+ * Synchronises the stream.  Errors: QW_EINVAL (unknown kind, NULL pointers,
+ * out_len too small), QW_EDEVICE. */
 int qw_measure(qw_state* st, int32_t kind, void* out, int64_t out_len, void* stream);
 
 /* Copy the state to the host, sorted by key.  cap = size of the host arrays;
@@ -147,7 +157,7 @@ int qw_export(qw_state* st, uint64_t* keys, double* re, double* im, int64_t cap,
 int qw_state_import(qw_state* st, const uint64_t* keys, const double* re, const double* im, int64_t m,
                     void* stream);
 
-/* Wait for the stream. */
+/* Wait for the stream (QW_EDEVICE reports an earlier asynchronous failure). */
 int qw_sync(qw_state* st, void* stream);
 
 /* Walk-based CKS linear solver on instance 0 (Sec. IV, CKS paragraph; Eq. "fx";
@@ -164,7 +174,12 @@ int qw_sync(qw_state* st, void* stream);
 int qls_run(qw_ctx* ctx, const double* b, double kappa, double eps, int32_t j0_override,
             double* y_re, double* y_im, double* p_succ, int64_t* walk_steps, void* stream);
 
-/* Chebyshev coefficients a_0..a_j0 of Eq. "fx" for the given beta (host). */
+/* Chebyshev coefficients a_0..a_j0 of Eq. "fx" for the given beta, computed
+ * on the host into out[j0 + 1]: a_j = 4 (-1)^j sum_{i > j} C(2 beta, beta + i)
+ * / 2^(2 beta), evaluated in long double from the central term (a Stirling
+ * series for beta >= 64) by the ratio recurrence of consecutive terms and
+ * summed from the far tail.
+ * Errors: QW_EINVAL (beta < 1, j0 < 0, out NULL). */
 int qw_cks_coeffs(int64_t beta, int32_t j0, double* out);
 
 /* Reverse-mode gradient of L = sum_j w_j p_j, p = j-register marginal of the
