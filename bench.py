@@ -87,6 +87,41 @@ def cpu_baseline(csc, b, steps: int):
     }
 
 
+def batched_cpu_baseline(inst, steps: int = 10, count: int = 64):
+    """The oracle over independent instances on the host's cores (a thread
+    pool; the oracle's C calls release the interpreter lock): T~|b~> then
+    `steps` walk steps of the first `count` instances of the batched
+    workload."""
+    from concurrent.futures import ThreadPoolExecutor
+
+    import oracle
+
+    threads = max(1, min(16, os.cpu_count() or 1))
+    sample = inst[:count]
+    mats = [oracle.OracleMatrix(a) for a, _ in sample]
+
+    def run(i):
+        ost = oracle.OracleState(mats[i]).set_b(sample[i][1]).T()
+        written = 0
+        for _ in range(steps):
+            ost.step(1)
+            written += ost.count()
+        return written
+
+    t0 = time.perf_counter()
+    with ThreadPoolExecutor(max_workers=threads) as pool:
+        written = sum(pool.map(run, range(len(sample))))
+    dt = time.perf_counter() - t0
+    return {
+        "value": written / dt,
+        "unit": "amplitude updates/s",
+        "cores": threads,
+        "kind": "oracle",
+        "sample": f"first {len(sample)} of the 256 instances, T~|b~> then {steps} walk steps each "
+                  f"({written} branch updates in {dt:.1f} s), {threads} threads on {cpu_model()}",
+    }
+
+
 def _timed(Q, fn):
     """GPU time (ms) of fn() on the library's stream, by HIP events."""
     import torch
@@ -101,7 +136,7 @@ def _timed(Q, fn):
     return e0.elapsed_time(e1)
 
 
-def batched_leg(Q, W, autotune, tune: bool, steps: int = 50):
+def batched_leg(Q, W, autotune, tune: bool, steps: int = 50, cpu: bool = True):
     """256 instances (n = 2^U{6..12}, 4..16 entries per column, single-column
     starts) in one launch per step, against the same instances advanced one
     walk at a time on the same GPU."""
@@ -134,6 +169,7 @@ def batched_leg(Q, W, autotune, tune: bool, steps: int = 50):
         "plain_value": upd_plain / (ms_plain / 1e3),
         "speedup_vs_plain": ms_plain / ms,
         "launch_shape": list(shape) if shape else "default",
+        "cpu_baseline": batched_cpu_baseline(inst) if cpu else None,
     }
 
 
@@ -239,7 +275,7 @@ def main():
         print(json.dumps({"pmc_run": True, "copy_bytes": 8 << 23, "steps": 64}), flush=True)
         return
     if args.only == "batched":
-        print(json.dumps(batched_leg(Q, W, autotune, not args.no_tune)), flush=True)
+        print(json.dumps(batched_leg(Q, W, autotune, not args.no_tune, cpu=not args.no_cpu_baseline)), flush=True)
         return
     if args.only == "adjoint":
         print(json.dumps(adjoint_leg(Q, W)), flush=True)
@@ -314,7 +350,7 @@ def main():
     print(f"[bench] {args.steps} steps in {ms:.2f} ms ({launch_s * 1e6:.2f} us/step), "
           f"{value:.3e} updates/s, {achieved:.0f} GB/s algorithmic", file=sys.stderr, flush=True)
     if not args.no_extras:
-        line["batched"] = batched_leg(Q, W, autotune, not args.no_tune)
+        line["batched"] = batched_leg(Q, W, autotune, not args.no_tune, cpu=not args.no_cpu_baseline)
         print(f"[bench] batched: {line['batched']}", file=sys.stderr, flush=True)
         line["adjoint"] = adjoint_leg(Q, W)
         print(f"[bench] adjoint: {line['adjoint']}", file=sys.stderr, flush=True)
