@@ -88,7 +88,7 @@ struct qw_ctx {
   int64_t ntotal = 0;  // sum of unpadded n_i
   int64_t nnz_total = 0;
   std::vector<HostInst> inst;
-  std::vector<int64_t> csc_slot;  // home of every CSC entry's slot
+  std::vector<int64_t> csc_home;  // home of every CSC entry's slot
   int32_t* col = nullptr;
   double* val = nullptr;
   qw::SlotRec* rec = nullptr;
@@ -383,7 +383,7 @@ int load_impl(qw_ctx** out, int32_t ninst, const int32_t* n, const int64_t* colp
     std::copy(ell.col.begin(), ell.col.end(), hcol.begin() + items);
     std::copy(ell.val.begin(), ell.val.end(), hval.begin() + items);
     for (int64_t q : slot_of)  // row-major ELL slot j*s + l -> home l*N + j
-      ctx->csc_slot.push_back(items + ((q & (hi.s - 1)) << hi.nbits) + (q >> hi.hbits));
+      ctx->csc_home.push_back(items + ((q & (hi.s - 1)) << hi.nbits) + (q >> hi.hbits));
     items += (slots + qw::kWave - 1) / qw::kWave * qw::kWave;
     hcol.resize(size_t(items), 0);
     hval.resize(size_t(items), 0.0);
@@ -1044,7 +1044,7 @@ int qw_grad(qw_state* st, const double* w, int32_t nsteps, double* dvals, double
     *loss = L;
   }
   if (dvals)
-    for (size_t p = 0; p < ctx->csc_slot.size(); ++p) dvals[p] = hdv[size_t(ctx->csc_slot[p])];
+    for (size_t p = 0; p < ctx->csc_home.size(); ++p) dvals[p] = hdv[size_t(ctx->csc_home[p])];
   src = 0;
   for (int32_t i = 0; i < ctx->ninst; ++i)
     for (int32_t j = 0; j < ctx->inst[i].n; ++j, ++src) {

@@ -120,3 +120,14 @@ def test_cks_coeffs_host(lib):
     got = Q.cks_coeffs(beta, j0)
     ks = np.array([0, 3, 50, 700, 3000, 4620])
     assert np.allclose(got[ks], 4 * (-1.0) ** ks * binom.sf(beta + ks, 2 * beta, 0.5), rtol=1e-9)
+
+
+def test_missing_library_fails_loudly(monkeypatch, tmp_path):
+    """Without the built library the binding raises at load: the walk has no
+    CPU fallback."""
+    from paper_2303_06890_amd import _lib
+
+    monkeypatch.setattr(_lib, "_lib", None)
+    monkeypatch.setattr(_lib, "LIB_PATH", str(tmp_path / "libqw.so"))
+    with pytest.raises(ImportError, match="no CPU fallback"):
+        _lib.load()
