@@ -1,0 +1,75 @@
+"""Band matrices of the shapes of the paper's five experiments (its table of
+experimental settings: n = 16 ... 16384, s = 8 ... 64).  Shapes A and B are
+checked against the oracle step by step; the large shapes, where the oracle
+is too slow, against the Chebyshev closed form of the walk (Sec. IV, CKS
+paragraph): Pi_0 T~^dagger W^n T~ |b~> = T_n(A/s) b, by a sparse three-term
+recurrence on the host, plus norm preservation."""
+import numpy as np
+import pytest
+import scipy.sparse as sp
+
+import workloads as W
+from tests.parity import compare_states
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def Q():
+    import torch
+
+    assert torch.cuda.is_available()
+    import paper_2303_06890_amd as Q
+
+    return Q
+
+
+@pytest.mark.parametrize("name,nsteps", [("A", 50), ("B", 20)])
+def test_table1_shapes_vs_oracle(Q, oracle_mod, name, nsteps):
+    csc, b = W.table1_band(name)
+    walk = Q.Walk(csc)
+    st = walk.state(b)
+    om = oracle_mod.OracleMatrix(csc)
+    ost = oracle_mod.OracleState(om).set_b(b).T()
+    done = 0
+    for t in (1, 3, nsteps):
+        st.step(t - done)
+        ost.step(t - done)
+        done = t
+        gk, ga = st.export()
+        ok, oa = ost.export()
+        compare_states(gk, ga, ok, oa, where=f"shape {name} step {t}")
+
+
+def _chebyshev(csc, scale, s, b, ns):
+    """T_n(A/s) b for n in ns (A scaled as the library scales it)."""
+    A = sp.csc_matrix((csc.vals * scale, csc.rowidx, csc.colptr), shape=(csc.n, csc.n))
+    H = (A / s).tocsr()
+    prev, cur = b.astype(complex), H @ b.astype(complex)
+    out = {0: prev.copy(), 1: cur.copy()}
+    for n in range(2, max(ns) + 1):
+        prev, cur = cur, 2 * (H @ cur) - prev
+        out[n] = cur.copy()
+    return out
+
+
+@pytest.mark.parametrize("name,nsteps", [("paper_scale", 100), ("D", 50), ("E", 50)])
+def test_chebyshev_closed_form_full_size(Q, name, nsteps):
+    if name == "paper_scale":
+        csc, b = W.paper_scale()
+    else:
+        csc, b = W.table1_band(name)
+    walk = Q.Walk(csc)
+    info = walk.info[0]
+    assert info["N"] == csc.n  # powers of two: no padded rows
+    checks = (1, 2, 10, nsteps)
+    ref = _chebyshev(csc, info["scale"], info["s"], b, checks)
+    st = walk.state(b)
+    done = 0
+    for t in checks:
+        st.step(t - done)
+        done = t
+        y = st.project()
+        err = np.abs(y - ref[t]).max()
+        assert err < 1e-11, (name, t, err)
+        assert abs(st.norm2() - 1.0) < 1e-12, (name, t)

@@ -172,11 +172,31 @@ def paper_scale(n: int = 16384, c: int = 8, seed: int = 2):
     return offset_matrix(n, c, seed=seed), uniform_b(n)
 
 
-def paper_band(n: int = 16384, bandwidth: int = 31, seed: int = 7):
-    """The paper's matrix family at its largest simulated size: a positive
-    symmetric band matrix with 2*31 + 1 = 63 entries per interior column
-    (s = 64), uniform superposition over all columns."""
-    return band_matrix(n, bandwidth, seed=seed), uniform_b(n)
+# The shapes of the paper's five experimental matrices (its table of
+# experimental settings): positive symmetric band matrices of n rows and
+# bandwidth w, so 2w + 1 entries per interior column and s = 2^ceil(log2(2w+1)).
+# The paper's values are not published; these are seeded stand-ins.
+TABLE1_SHAPES = {
+    "A": (16, 3, 11),      # s = 8
+    "B": (128, 7, 12),     # s = 16
+    "C": (1024, 15, 13),   # s = 32
+    "D": (8192, 15, 14),   # s = 32
+    "E": (16384, 31, 7),   # s = 64
+}
+# The paper's single-core time per walk step for each shape (context only).
+TABLE1_PAPER_SECONDS_PER_STEP = {"A": 1.1e-3, "B": 12e-3, "C": 1.2, "D": 14.0, "E": 66.0}
+
+
+def table1_band(name: str):
+    """Band matrix of the given shape of the paper's table, uniform b."""
+    n, w, seed = TABLE1_SHAPES[name]
+    return band_matrix(n, w, seed=seed), uniform_b(n)
+
+
+def paper_band():
+    """Shape E: 16384 rows, bandwidth 31 (s = 64), the paper's largest
+    single-core walk-step measurement."""
+    return table1_band("E")
 
 
 def batched_instances(count: int = 256, seed: int = 3, emin: int = 6, emax: int = 12,
