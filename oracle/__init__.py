@@ -47,10 +47,10 @@ def _load():
     i64p = ctypes.POINTER(ctypes.c_int64)
     sig = {
         "orc_last_error": (ctypes.c_char_p, []),
-        "orc_matrix_new": (P, [i32, ip, ip, dp, i64, dbl]),
+        "orc_matrix_new": (P, [i32, ip, ip, dp, dp, i64, dbl]),
         "orc_matrix_free": (None, [P]),
         "orc_matrix_info": (None, [P, ip, ip, ip, dp]),
-        "orc_matrix_ell": (None, [P, ip, dp, u8p]),
+        "orc_matrix_ell": (None, [P, ip, dp, dp, u8p]),
         "orc_qbs": (u64, [ip, i32, u64]),
         "orc_state_new": (P, [P, dbl]),
         "orc_state_free": (None, [P]),
@@ -70,7 +70,7 @@ def _load():
         "orc_project0": (ctypes.c_int, [P, dp, dp]),
         "orc_schedule": (None, [dbl, dbl, i64p, ip]),
         "orc_cks_coeffs": (None, [i64, i32, dp]),
-        "orc_cheb_series": (None, [P, dp, i32, i32, dp, dp]),
+        "orc_cheb_series": (None, [P, dp, dp, i32, i32, dp, dp, dp]),
         "orc_qls_walk": (ctypes.c_int, [P, dp, i32, i32, dp, dbl, dp, dp]),
         "orc_grad": (ctypes.c_int, [P, dp, dp, i32, i32, dp, dbl, dp, dp, dp, dp]),
     }
@@ -108,8 +108,10 @@ class OracleMatrix:
         lib = _load()
         cp, cpp = _i(csc.colptr)
         ri, rip = _i(csc.rowidx)
-        va, vap = _d(csc.vals)
-        self._h = lib.orc_matrix_new(csc.n, cpp, rip, vap, csc.nnz, float(scale))
+        self.complex = np.iscomplexobj(csc.vals)
+        va, vap = _d(np.real(csc.vals))
+        vi, vip = _d(np.imag(csc.vals)) if self.complex else (None, None)
+        self._h = lib.orc_matrix_new(csc.n, cpp, rip, vap, vip, csc.nnz, float(scale))
         if not self._h:
             raise ValueError("oracle: " + lib.orc_last_error().decode())
         N, s, nb = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
@@ -124,21 +126,29 @@ class OracleMatrix:
             self._h = None
 
     def ell(self):
+        """(col, value, stored-entry flag), each N x s; values are complex for
+        a complex matrix."""
         col = np.zeros(self.N * self.s, np.int32)
         val = np.zeros(self.N * self.s, np.float64)
+        vim = np.zeros(self.N * self.s, np.float64)
         real = np.zeros(self.N * self.s, np.uint8)
         _load().orc_matrix_ell(self._h, col.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
                                val.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                               vim.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
                                real.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8)))
-        return col.reshape(self.N, self.s), val.reshape(self.N, self.s), real.reshape(self.N, self.s)
+        v = val + 1j * vim if self.complex else val
+        return col.reshape(self.N, self.s), v.reshape(self.N, self.s), real.reshape(self.N, self.s)
 
     # --- solver helpers
     def cheb_series(self, b, j0: int, coef):
-        b, bp = _d(b)
+        """sum_k a_k T_{2k+1}(A/s) b (complex for a complex matrix or b)."""
+        b = np.asarray(b)
+        br, brp = _d(np.real(b))
+        bi, bip = _d(np.imag(b) if np.iscomplexobj(b) else np.zeros(b.shape[0]))
         coef, cp = _d(coef)
-        y = np.zeros(self.N)
-        _load().orc_cheb_series(self._h, bp, b.shape[0], int(j0), cp, _d(y)[1])
-        return y
+        yr, yi = np.zeros(self.N), np.zeros(self.N)
+        _load().orc_cheb_series(self._h, brp, bip, br.shape[0], int(j0), cp, _d(yr)[1], _d(yi)[1])
+        return yr + 1j * yi if (self.complex or np.iscomplexobj(b)) else yr
 
     def qls_walk(self, b, j0: int, coef, tau: float = TAU):
         b, bp = _d(b)

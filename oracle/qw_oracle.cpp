@@ -8,7 +8,8 @@
 // path never does.  It shares no code with the GPU library.
 //
 // The state is an ordered map from the full register tuple
-// (j_c, j, b1, k_c, k, b2, A) to a complex double, i.e. the "state array +
+// (j_c, j, b1, k_c, k, b2, A) to a complex double (A is the data register:
+// one 64-bit word for a real value, two for a complex one), i.e. the "state array +
 // amplitude vector" of Sec. V.A ("Main idea") with only nonzero branches kept.
 // Every operator is applied literally, one register-level operation at a time:
 //   * semi-quantum (per-branch) maps: QRAM/O_A' (XOR of the value word into the
@@ -30,7 +31,10 @@
 //   * The Hadamard acts on the low log2(s) qubits of register k.
 //   * R(a, j, k) = [[f, -g], [g, conj f]], f = sqrt(a) for a >= 0,
 //     f = +i sqrt|a| if j <= k and -i sqrt|a| if j > k for a < 0,
-//     g = sqrt(1 - |a|)  (Sec. IV, footnote on negative elements).
+//     g = sqrt(1 - |a|)  (Sec. IV, footnote on negative elements).  For a
+//     complex value off the real axis, f = the principal sqrt(a) (the row of
+//     j holds A*_{jk} of a Hermitian matrix, so this is sqrt(A*_{jk}) of
+//     psi_j, Sec. IV) and g = sqrt(1 - |a|).
 //   * O_s' uses the relative slot index l (Eq. "Newprocess").
 //   * Padding: each column gets s sorted unique slots; the filler indices are
 //     the smallest row indices missing from that column, with value 0.
@@ -51,13 +55,16 @@ namespace {
 
 using cplx = std::complex<double>;
 
+// A holds the 64-bit word of a value's real part, A2 that of its imaginary
+// part (zero for real matrices): together the data register that O_A' loads.
 struct Reg {
-  uint64_t jc, j, b1, kc, k, b2, A;
+  uint64_t jc, j, b1, kc, k, b2, A, A2;
   bool operator<(const Reg& o) const {
-    return std::tie(jc, j, b1, kc, k, b2, A) < std::tie(o.jc, o.j, o.b1, o.kc, o.k, o.b2, o.A);
+    return std::tie(jc, j, b1, kc, k, b2, A, A2) < std::tie(o.jc, o.j, o.b1, o.kc, o.k, o.b2, o.A, o.A2);
   }
   bool operator==(const Reg& o) const {
-    return jc == o.jc && j == o.j && b1 == o.b1 && kc == o.kc && k == o.k && b2 == o.b2 && A == o.A;
+    return jc == o.jc && j == o.j && b1 == o.b1 && kc == o.kc && k == o.k && b2 == o.b2 && A == o.A &&
+           A2 == o.A2;
   }
 };
 
@@ -71,8 +78,10 @@ struct Matrix {
   int32_t hbits = 0;  // log2 s
   double scale = 1.0;
   std::vector<int32_t> col;   // N*s, row j: sorted unique indices
-  std::vector<double> val;    // N*s
+  std::vector<double> val;    // N*s, real part of the stored value
+  std::vector<double> vim;    // N*s, imaginary part (all zero for a real matrix)
   std::vector<uint8_t> real;  // N*s, 1 for a stored entry, 0 for filler
+  bool complex_values = false;
 };
 
 std::string g_err;
@@ -137,11 +146,13 @@ void per_branch(State& st, F f) {
   st.swap(out);
 }
 
-// O_A' (Alg. 3): A ^= word(a_{j,l}) where register k holds the slot l.
+// O_A' (Alg. 3): A ^= word(a_{j,l}) where register k holds the slot l (for
+// a complex value, both words: real part into A, imaginary part into A2).
 void op_OA(State& st, const Matrix& m) {
   per_branch(st, [&](Reg& r, cplx&) {
     if (r.k >= uint64_t(m.s) || r.j >= uint64_t(m.N)) fail("O_A' address outside the row");
     r.A ^= bits_of(m.val[r.j * m.s + r.k]);
+    r.A2 ^= bits_of(m.vim[r.j * m.s + r.k]);
   });
 }
 
@@ -176,7 +187,7 @@ void op_OSinv(State& st, const Matrix& m) {
 void op_P(State& st) {
   for (auto& kv : st) {
     const Reg& r = kv.first;
-    if (r.A != 0) fail("A register not clean at P");
+    if (r.A != 0 || r.A2 != 0) fail("A register not clean at P");
     const bool zero = r.jc == 0 && r.b1 == 0 && r.kc == 0 && r.k == 0 && r.b2 == 0;
     if (!zero) kv.second = -kv.second;
   }
@@ -234,9 +245,19 @@ struct Rot {
   double g;
 };
 
-// Amplitudes of the conditional rotation on b2 for value a, row j, column k.
-Rot rotation(double a, uint64_t j, uint64_t k) {
+// Amplitudes of the conditional rotation on b2 for the value a + i b held in
+// row j at column k: f = sqrt(a + i b) (the principal root; the row holds
+// A*_{jk} of a Hermitian matrix, so this is the sqrt(A*_{jk}) of psi_j), with
+// the footnote's rule on the negative real axis, where the principal root is
+// not conjugation-symmetric: f = +i sqrt|a| when j <= k, -i sqrt|a| otherwise;
+// g = sqrt(1 - |a + i b|).
+Rot rotation(double a, double b, uint64_t j, uint64_t k) {
   Rot r;
+  if (b != 0.0) {
+    r.f = std::sqrt(cplx(a, b));
+    r.g = std::sqrt(1.0 - std::abs(cplx(a, b)));
+    return r;
+  }
   if (a >= 0.0) {
     r.f = cplx(std::sqrt(a), 0.0);
   } else {
@@ -292,7 +313,7 @@ void op_CR(State& st, bool dagger) {
   State out;
   for (auto& gv : groups) {
     const Reg& g = gv.first;
-    const Rot r = rotation(double_of(g.A), g.j, g.k);
+    const Rot r = rotation(double_of(g.A), double_of(g.A2), g.j, g.k);
     cplx M[2][2];
     rot_matrix(r, dagger, M);
     const cplx v0 = gv.second.first, v1 = gv.second.second;
@@ -421,6 +442,7 @@ Reg unpack(const Matrix& m, uint64_t key) {
   key >>= n;
   r.jc = key & nm;
   r.A = 0;
+  r.A2 = 0;
   return r;
 }
 
@@ -465,8 +487,10 @@ const char* orc_last_error() { return g_err.c_str(); }
 
 // Preprocessing (Sec. V.B, numbered list): rescale, CSC rows per column, s,
 // zero fill.  scale_in > 0 fixes the scale; otherwise 1/max(1, max|a|).
+// vals_im: imaginary parts (NULL for a real matrix).  The matrix is taken as
+// given (Hermitian or symmetric input is the caller's business).
 void* orc_matrix_new(int32_t n, const int32_t* colptr, const int32_t* rowidx, const double* vals,
-                     int64_t nnz, double scale_in) {
+                     const double* vals_im, int64_t nnz, double scale_in) {
   Matrix* m = new Matrix;
   int rc = guarded([&] {
     if (n <= 0) fail("n must be positive");
@@ -479,7 +503,7 @@ void* orc_matrix_new(int32_t n, const int32_t* colptr, const int32_t* rowidx, co
       for (int64_t p = colptr[c]; p < colptr[c + 1]; ++p) {
         if (rowidx[p] < 0 || rowidx[p] >= n) fail("row index out of range");
         if (p > colptr[c] && rowidx[p] <= rowidx[p - 1]) fail("row indices not sorted/unique");
-        amax = std::max(amax, std::fabs(vals[p]));
+        amax = std::max(amax, vals_im ? std::abs(cplx(vals[p], vals_im[p])) : std::fabs(vals[p]));
       }
     }
     m->n_orig = n;
@@ -489,21 +513,23 @@ void* orc_matrix_new(int32_t n, const int32_t* colptr, const int32_t* rowidx, co
     m->hbits = ceil_log2(smax);
     m->s = 1 << m->hbits;
     if (m->s > m->N) fail("s exceeds N");
+    m->complex_values = vals_im != nullptr;
     m->col.assign(size_t(m->N) * m->s, 0);
     m->val.assign(size_t(m->N) * m->s, 0.0);
+    m->vim.assign(size_t(m->N) * m->s, 0.0);
     m->real.assign(size_t(m->N) * m->s, 0);
     for (int32_t c = 0; c < m->N; ++c) {
-      std::vector<std::pair<int32_t, double>> ent;
+      std::vector<std::pair<int32_t, cplx>> ent;
       std::vector<uint8_t> present(m->N, 0);
       if (c < n) {
         for (int64_t p = colptr[c]; p < colptr[c + 1]; ++p) {
-          ent.push_back({rowidx[p], vals[p] * m->scale});
+          ent.push_back({rowidx[p], cplx(vals[p] * m->scale, vals_im ? vals_im[p] * m->scale : 0.0)});
           present[rowidx[p]] = 1;
         }
       }
       const size_t nreal = ent.size();
       for (int32_t r = 0; int64_t(ent.size()) < m->s; ++r)
-        if (!present[r]) ent.push_back({r, 0.0});
+        if (!present[r]) ent.push_back({r, cplx(0.0, 0.0)});
       std::vector<uint8_t> isreal(ent.size(), 0);
       for (size_t q = 0; q < nreal; ++q) isreal[q] = 1;
       std::vector<size_t> idx(ent.size());
@@ -511,12 +537,13 @@ void* orc_matrix_new(int32_t n, const int32_t* colptr, const int32_t* rowidx, co
       std::sort(idx.begin(), idx.end(), [&](size_t a, size_t b) { return ent[a].first < ent[b].first; });
       for (int l = 0; l < m->s; ++l) {
         m->col[size_t(c) * m->s + l] = ent[idx[l]].first;
-        m->val[size_t(c) * m->s + l] = ent[idx[l]].second;
+        m->val[size_t(c) * m->s + l] = ent[idx[l]].second.real();
+        m->vim[size_t(c) * m->s + l] = ent[idx[l]].second.imag();
         m->real[size_t(c) * m->s + l] = isreal[idx[l]];
       }
     }
     for (size_t q = 0; q < m->val.size(); ++q)
-      if (std::fabs(m->val[q]) > 1.0) fail("|a| > 1 after scaling");
+      if (std::abs(cplx(m->val[q], m->vim[q])) > 1.0) fail("|a| > 1 after scaling");
   });
   if (rc) {
     delete m;
@@ -535,10 +562,11 @@ void orc_matrix_info(void* p, int32_t* N, int32_t* s, int32_t* nbits, double* sc
   *scale = m->scale;
 }
 
-void orc_matrix_ell(void* p, int32_t* col, double* val, uint8_t* real) {
+void orc_matrix_ell(void* p, int32_t* col, double* val, double* vim, uint8_t* real) {
   const Matrix* m = static_cast<Matrix*>(p);
   std::copy(m->col.begin(), m->col.end(), col);
   std::copy(m->val.begin(), m->val.end(), val);
+  std::copy(m->vim.begin(), m->vim.end(), vim);
   std::copy(m->real.begin(), m->real.end(), real);
 }
 
@@ -633,7 +661,7 @@ int orc_export(void* p, uint64_t* keys, double* re, double* im) {
     std::vector<std::pair<uint64_t, cplx>> v;
     v.reserve(o->st.size());
     for (auto& kv : o->st) {
-      if (kv.first.A != 0) fail("A register not clean");
+      if (kv.first.A != 0 || kv.first.A2 != 0) fail("A register not clean");
       v.push_back({pack(*o->m, kv.first), kv.second});
     }
     std::sort(v.begin(), v.end(), [](const auto& a, const auto& b) { return a.first < b.first; });
@@ -669,7 +697,7 @@ int orc_project0(void* p, double* yre, double* yim) {
     std::fill(yim, yim + o->m->N, 0.0);
     for (auto& kv : st) {
       const Reg& r = kv.first;
-      if (r.jc == 0 && r.b1 == 0 && r.kc == 0 && r.k == 0 && r.b2 == 0 && r.A == 0) {
+      if (r.jc == 0 && r.b1 == 0 && r.kc == 0 && r.k == 0 && r.b2 == 0 && r.A == 0 && r.A2 == 0) {
         yre[r.j] = kv.second.real();
         yim[r.j] = kv.second.imag();
       }
@@ -689,22 +717,25 @@ void orc_schedule(double kappa, double eps, int64_t* beta, int32_t* j0) {
 void orc_cks_coeffs(int64_t beta, int32_t j0, double* out) { cks_coeffs(beta, j0, out); }
 
 // Classical truncated series y = sum_{k<=j0} a_k T_{2k+1}(A/s) b by the
-// three-term Chebyshev recurrence on the padded, scaled matrix.
-void orc_cheb_series(void* mat, const double* b, int32_t nb, int32_t j0, const double* coef,
-                     double* y) {
+// three-term Chebyshev recurrence on the padded, scaled matrix.  Row j of the
+// table holds column j of A (entries A_{col, j}), so A x is a scatter:
+// (A x)_{col[j,l]} += a_{j,l} x_j.
+void orc_cheb_series(void* mat, const double* bre, const double* bim, int32_t nb, int32_t j0,
+                     const double* coef, double* yre, double* yim) {
   const Matrix& m = *static_cast<Matrix*>(mat);
   const int N = m.N;
-  auto apply_h = [&](const std::vector<double>& x, std::vector<double>& out) {
-    for (int r = 0; r < N; ++r) {
-      double acc = 0.0;
-      for (int l = 0; l < m.s; ++l) acc += m.val[size_t(r) * m.s + l] * x[m.col[size_t(r) * m.s + l]];
-      out[r] = acc / m.s;
-    }
+  auto apply_h = [&](const std::vector<cplx>& x, std::vector<cplx>& out) {
+    std::fill(out.begin(), out.end(), cplx(0.0, 0.0));
+    for (int r = 0; r < N; ++r)
+      for (int l = 0; l < m.s; ++l) {
+        const size_t q = size_t(r) * m.s + l;
+        out[m.col[q]] += cplx(m.val[q], m.vim[q]) * x[r];
+      }
+    for (int r = 0; r < N; ++r) out[r] /= double(m.s);
   };
-  std::vector<double> tprev(N, 0.0), tcur(N), tnext(N), hx(N);
-  for (int r = 0; r < nb; ++r) tprev[r] = b[r];  // T_0 b
-  apply_h(tprev, tcur);                          // T_1 b
-  std::fill(y, y + N, 0.0);
+  std::vector<cplx> tprev(N, cplx(0.0, 0.0)), tcur(N), tnext(N), hx(N), y(N, cplx(0.0, 0.0));
+  for (int r = 0; r < nb; ++r) tprev[r] = cplx(bre[r], bim ? bim[r] : 0.0);  // T_0 b
+  apply_h(tprev, tcur);                                                         // T_1 b
   for (int32_t k = 0; k <= j0; ++k) {
     // tcur holds T_{2k+1} b
     for (int r = 0; r < N; ++r) y[r] += coef[k] * tcur[r];
@@ -715,6 +746,10 @@ void orc_cheb_series(void* mat, const double* b, int32_t nb, int32_t j0, const d
       tprev.swap(tcur);
       tcur.swap(tnext);
     }
+  }
+  for (int r = 0; r < N; ++r) {
+    yre[r] = y[r].real();
+    yim[r] = y[r].imag();
   }
 }
 
@@ -765,6 +800,7 @@ int orc_grad(void* mat, const double* bre, const double* bim, int32_t nb, int32_
              const double* w, double tau, double* dv, double* dbre, double* dbim, double* loss) {
   const Matrix& m = *static_cast<Matrix*>(mat);
   return guarded([&] {
+    if (m.complex_values) fail("the gradient is defined for real matrices only");
     OState o;
     o.m = &m;
     o.tau = tau;
@@ -822,7 +858,7 @@ int orc_grad(void* mat, const double* bre, const double* bim, int32_t nb, int32_
           if (it == lout.end()) continue;
           const Reg& g = gv.first;
           const double a = double_of(g.A);
-          const Rot d = rotation_deriv(a, g.j, g.k);
+          const Rot d = rotation_deriv(a, g.j, g.k);  // real matrices: A2 = 0
           cplx D[2][2];
           rot_matrix(d, dag, D);  // derivative of R or of R^dagger (a is real)
           const cplx x0 = gv.second.first, x1 = gv.second.second;
@@ -843,7 +879,7 @@ int orc_grad(void* mat, const double* bre, const double* bim, int32_t nb, int32_
     std::fill(dbim, dbim + m.N, 0.0);
     for (auto& kv : lam) {
       const Reg& r = kv.first;
-      if (r.jc == 0 && r.b1 == 0 && r.kc == 0 && r.k == 0 && r.b2 == 0 && r.A == 0) {
+      if (r.jc == 0 && r.b1 == 0 && r.kc == 0 && r.k == 0 && r.b2 == 0 && r.A == 0 && r.A2 == 0) {
         dbre[r.j] = 2.0 * kv.second.real();
         dbim[r.j] = 2.0 * kv.second.imag();
       }

@@ -27,7 +27,7 @@ def preprocess(csc, scale=None):
     if scale is None:
         scale = 1.0 / max(1.0, np.abs(csc.vals).max())
     col = np.zeros((N, s), np.int64)
-    val = np.zeros((N, s))
+    val = np.zeros((N, s), dtype=csc.vals.dtype)
     for c in range(N):
         rows = list(csc.rowidx[csc.colptr[c]:csc.colptr[c + 1]]) if c < n else []
         vals = list(csc.vals[csc.colptr[c]:csc.colptr[c + 1]] * scale) if c < n else []
@@ -76,8 +76,11 @@ class DenseWalk:
         ll = np.minimum(k, s - 1)
         a = self.val[j, ll]
         colk = kc ^ self.col[j, ll]
-        f = np.where(a >= 0, np.sqrt(np.abs(a)) + 0j,
-                     np.where(j <= colk, 1j, -1j) * np.sqrt(np.abs(a)))
+        # real values: sqrt(a) for a >= 0, +-i sqrt|a| by the order of row and
+        # column for a < 0; values off the real axis: the principal sqrt(a)
+        ar, ai = np.real(a), np.imag(a)
+        f_real = np.where(ar >= 0, np.sqrt(np.abs(ar)) + 0j, np.where(j <= colk, 1j, -1j) * np.sqrt(np.abs(ar)))
+        f = np.where(ai != 0, np.sqrt(a + 0j), f_real)
         g = np.sqrt(1.0 - np.abs(a))
         self.rot_valid = valid
         self.f, self.g = f, g

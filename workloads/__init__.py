@@ -35,14 +35,14 @@ class Csc:
     n: int
     colptr: np.ndarray  # int32, n+1
     rowidx: np.ndarray  # int32, nnz, sorted inside each column
-    vals: np.ndarray  # float64, nnz
+    vals: np.ndarray  # float64 (or complex128 for a Hermitian matrix), nnz
 
     @property
     def nnz(self) -> int:
         return int(self.rowidx.shape[0])
 
     def dense(self) -> np.ndarray:
-        a = np.zeros((self.n, self.n))
+        a = np.zeros((self.n, self.n), dtype=self.vals.dtype)
         for c in range(self.n):
             for p in range(self.colptr[c], self.colptr[c + 1]):
                 a[self.rowidx[p], c] = self.vals[p]
@@ -116,6 +116,46 @@ def offset_matrix(n: int, c: int, seed=None, rng: np.random.Generator | None = N
     diag = rng.uniform(-1.0, 1.0, n) + (c - 1)
     vals = [diag] + pieces
     return _from_triplets(n, np.concatenate(rows), np.concatenate(cols), np.concatenate(vals))
+
+
+def hermitian_offset_matrix(n: int, c: int, seed=None, rng: np.random.Generator | None = None) -> Csc:
+    """Complex Hermitian counterpart of ``offset_matrix``: the same pattern of
+    exactly ``c`` entries per column; the pair at offset d holds v at (j, j+d)
+    and conj(v) at (j+d, j) with v = U[-1,1] + i U[-1,1], except the first
+    offset, which keeps real values U[-1,1] (negative ones included) so that
+    the real axis is exercised as well; the diagonal is real, U[-1,1] + (c-1)."""
+    if rng is None:
+        rng = np.random.default_rng(seed)
+    if c < 1 or c > n:
+        raise ValueError("need 1 <= c <= n")
+    p = (c - 1) // 2
+    half = (c - 1) % 2 == 1
+    if p > max(0, n // 2 - 1):
+        raise ValueError("too many offsets for this n")
+    offsets = rng.choice(np.arange(1, n // 2), size=p, replace=False) if p else np.zeros(0, np.int64)
+    j = np.arange(n)
+    rows, cols, vals = [j], [j], [rng.uniform(-1.0, 1.0, n) + (c - 1) + 0j]
+    for i, d in enumerate(offsets):
+        v = rng.uniform(-1.0, 1.0, n) + (0.0 if i == 0 else 1j * rng.uniform(-1.0, 1.0, n))
+        k = (j + int(d)) % n
+        rows += [j, k]
+        cols += [k, j]
+        vals += [v, np.conj(v)]
+    if half:
+        h = n // 2
+        v = rng.uniform(-1.0, 1.0, h) + 1j * rng.uniform(-1.0, 1.0, h)
+        lo = np.arange(h)
+        rows += [lo, lo + h]
+        cols += [lo + h, lo]
+        vals += [v, np.conj(v)]
+    r, cc, vv = np.concatenate(rows), np.concatenate(cols), np.concatenate(vals)
+    order = np.lexsort((r, cc))
+    r, cc, vv = r[order], cc[order], vv[order]
+    if np.any(np.diff(cc * n + r) == 0):
+        raise ValueError("duplicate entry in generated matrix")
+    colptr = np.zeros(n + 1, dtype=np.int32)
+    colptr[1:] = np.cumsum(np.bincount(cc, minlength=n))
+    return Csc(n, colptr, r.astype(np.int32), vv.astype(np.complex128))
 
 
 def band_matrix(n: int, bandwidth: int, seed: int = 0) -> Csc:
