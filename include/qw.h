@@ -7,7 +7,7 @@
  * registers j_c, j, b1, k_c, k, b2 (Sec. IV, "Implementation of the quantum
  * walk"), its inverse, the walk-based Chebyshev linear solver (Eq. "fx" and
  * the iteration of Sec. V.B), measurements, a batched multi-instance form and
- * a reverse-mode gradient.
+ * a reverse-mode gradient.  Real symmetric and complex Hermitian matrices.
  *
  * Conventions shared by every entry point
  *   - Return value: QW_OK (0) or a negative qw_status.  Functions never throw
@@ -67,7 +67,7 @@ typedef struct {
 } qw_allocator;
 
 /* flags for qw_load_csc / qw_load_csc_batched */
-#define QW_REQUIRE_SYMMETRIC 0x1u /* reject matrices that are not symmetric */
+#define QW_REQUIRE_SYMMETRIC 0x1u /* reject matrices that are not symmetric (Hermitian) */
 
 /* flags for qw_state_init */
 #define QW_INIT_RAW 0x1u /* start from |b~> itself instead of T~|b~> */
@@ -104,6 +104,22 @@ int qw_load_csc_batched(qw_ctx** out, int32_t ninst, const int32_t* n, const int
                         const int64_t* nnz_off, const int32_t* colptr, const int32_t* rowidx,
                         const double* vals, const double* scales, uint32_t flags,
                         const qw_allocator* alloc, void* stream);
+
+/* Load `ninst` complex Hermitian matrices (ninst = 1: one matrix; the offset
+ * arrays may then be NULL), with the layout and meaning of
+ * qw_load_csc_batched's arguments; vals_re/vals_im are the real and imaginary
+ * parts of the stored entries (vals_im required).  The QRAM row j holds
+ * column j of A, i.e. the entries A*_{jk} of row j of a Hermitian A, and
+ * psi_j takes sqrt(A*_{jk}) (Sec. IV): the principal root off the real
+ * axis, the real rule of qw_load_csc on it (entries with a zero imaginary
+ * part).  QW_REQUIRE_SYMMETRIC requires A_kj = conj(A_jk) exactly.  Scaling
+ * uses |a| = hypot(re, im).  Errors: as qw_load_csc, plus QW_EINVAL for a
+ * diagonal entry with a nonzero imaginary part.  qw_grad is not provided for
+ * such a context (QW_ENOTSUP); every other entry point is. */
+int qw_load_csc_hermitian(qw_ctx** out, int32_t ninst, const int32_t* n, const int64_t* colptr_off,
+                          const int64_t* nnz_off, const int32_t* colptr, const int32_t* rowidx,
+                          const double* vals_re, const double* vals_im, const double* scales, uint32_t flags,
+                          const qw_allocator* alloc, void* stream);
 
 /* Per-instance facts: padded dimension N, slots per row s, register width n
  * of the key layout (common to all instances), scale applied.  Any output

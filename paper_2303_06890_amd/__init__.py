@@ -107,9 +107,10 @@ def _up(a):
 
 
 class Walk:
-    """One or more sparse symmetric matrices preprocessed and resident on the
-    GPU (a ``qw_ctx``).  ``mats``: a CSC object (attributes n, colptr,
-    rowidx, vals) or a list of them (batched form).  ``scale``: None
+    """One or more sparse symmetric (or complex Hermitian) matrices
+    preprocessed and resident on the GPU (a ``qw_ctx``).  ``mats``: a CSC
+    object (attributes n, colptr, rowidx, vals) or a list of them (batched
+    form); complex values select the Hermitian loader.  ``scale``: None
     (automatic 1/max(1, max|a|)), a float, or one float per matrix."""
 
     def __init__(self, mats, scale=None, symmetric: bool = True, torch_alloc: bool = True):
@@ -120,19 +121,27 @@ class Walk:
         n = np.array([m.n for m in self.mats], np.int32)
         colptr = np.concatenate([np.asarray(m.colptr, np.int32) for m in self.mats])
         rowidx = np.concatenate([np.asarray(m.rowidx, np.int32) for m in self.mats])
-        vals = np.concatenate([np.asarray(m.vals, np.float64) for m in self.mats])
+        self.complex = any(np.iscomplexobj(m.vals) for m in self.mats)
+        allv = np.concatenate([np.asarray(m.vals) for m in self.mats])
+        vals = np.ascontiguousarray(np.real(allv), np.float64)
+        vim = np.ascontiguousarray(np.imag(allv), np.float64) if self.complex else None
         coff = np.cumsum([0] + [m.n + 1 for m in self.mats[:-1]]).astype(np.int64)
         zoff = np.cumsum([0] + [len(m.rowidx) for m in self.mats[:-1]]).astype(np.int64)
         if scale is None:
             sc = None
         else:
             sc = np.broadcast_to(np.asarray(scale, np.float64), (self.ninst,)).copy()
-        self._keep = (n, colptr, rowidx, vals, coff, zoff, sc)
+        self._keep = (n, colptr, rowidx, vals, vim, coff, zoff, sc)
         h = ctypes.c_void_p()
         flags = _lib.QW_REQUIRE_SYMMETRIC if symmetric else 0
-        check(lib.qw_load_csc_batched(ctypes.byref(h), self.ninst, _ip(n), _lp(coff), _lp(zoff), _ip(colptr),
-                                      _ip(rowidx), _dp(vals), _dp(sc) if sc is not None else None, flags,
-                                      ctypes.byref(self._alloc.struct) if self._alloc else None, _stream()))
+        alloc = ctypes.byref(self._alloc.struct) if self._alloc else None
+        scp = _dp(sc) if sc is not None else None
+        if self.complex:
+            check(lib.qw_load_csc_hermitian(ctypes.byref(h), self.ninst, _ip(n), _lp(coff), _lp(zoff), _ip(colptr),
+                                            _ip(rowidx), _dp(vals), _dp(vim), scp, flags, alloc, _stream()))
+        else:
+            check(lib.qw_load_csc_batched(ctypes.byref(h), self.ninst, _ip(n), _lp(coff), _lp(zoff), _ip(colptr),
+                                          _ip(rowidx), _dp(vals), scp, flags, alloc, _stream()))
         self._h = h
         _live_walks.add(self)
         self.info = []

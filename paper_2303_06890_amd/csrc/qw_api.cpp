@@ -92,6 +92,8 @@ struct qw_ctx {
   int32_t* col = nullptr;
   double* val = nullptr;
   qw::SlotRec* rec = nullptr;
+  double* vim = nullptr;          // imaginary parts by home (complex matrices only)
+  bool complex_values = false;
   qw::Inst* dinst = nullptr;
   int32_t* wave_inst = nullptr;
   qw::Inst inst0{};
@@ -100,6 +102,7 @@ struct qw_ctx {
     m.col = col;
     m.val = val;
     m.rec = rec;
+    m.vim = vim;
     m.inst = dinst;
     m.wave_inst = wave_inst;
     m.items = items;
@@ -243,13 +246,17 @@ int run_steps(qw_state* st, int64_t n, hipStream_t stream, double2* yacc = nullp
 struct Ell {
   std::vector<int32_t> col;
   std::vector<double> val;
+  std::vector<double> vim;  // imaginary parts (complex input only)
 };
 
 // Validate one CSC instance, rescale, round s up to a power of two, pad every
 // column to s sorted unique slots (filler = smallest absent rows, value 0)
-// and the dimension to a power of two.
-int preprocess(int32_t n, const int32_t* colptr, const int32_t* rowidx, const double* vals, double scale_in,
-               uint32_t flags, HostInst& hi, Ell& ell, std::vector<int64_t>& slot_of) {
+// and the dimension to a power of two.  vals_im: imaginary parts of a
+// complex Hermitian matrix, or NULL for a real one.
+int preprocess(int32_t n, const int32_t* colptr, const int32_t* rowidx, const double* vals,
+               const double* vals_im, double scale_in, uint32_t flags, HostInst& hi, Ell& ell,
+               std::vector<int64_t>& slot_of) {
+  auto mag = [&](int64_t p) { return vals_im ? std::hypot(vals[p], vals_im[p]) : std::fabs(vals[p]); };
   if (n <= 0) return set_err(QW_EINVAL, "matrix dimension must be positive");
   if (colptr[0] != 0) return set_err(QW_EINVAL, "colptr[0] must be 0");
   int64_t smax = 1;
@@ -261,10 +268,13 @@ int preprocess(int32_t n, const int32_t* colptr, const int32_t* rowidx, const do
       if (rowidx[p] < 0 || rowidx[p] >= n) return set_err(QW_EINVAL, "row index out of range");
       if (p > colptr[c] && rowidx[p] <= rowidx[p - 1])
         return set_err(QW_EINVAL, "row indices must be sorted and unique inside a column");
-      if (!std::isfinite(vals[p])) return set_err(QW_EINVAL, "non-finite matrix value");
-      amax = std::max(amax, std::fabs(vals[p]));
+      if (!std::isfinite(vals[p]) || (vals_im && !std::isfinite(vals_im[p])))
+        return set_err(QW_EINVAL, "non-finite matrix value");
+      amax = std::max(amax, mag(p));
       if (rowidx[p] == c && vals[p] < 0.0)
         return set_err(QW_EINVAL, "negative diagonal entry: not encodable by the walk (<j|T^+ S T|j> = |f|^2/s >= 0)");
+      if (rowidx[p] == c && vals_im && vals_im[p] != 0.0)
+        return set_err(QW_EINVAL, "diagonal entry with an imaginary part: the matrix is not Hermitian");
     }
   }
   const double scale = scale_in > 0.0 ? scale_in : 1.0 / std::max(1.0, amax);
@@ -276,8 +286,10 @@ int preprocess(int32_t n, const int32_t* colptr, const int32_t* rowidx, const do
         const int32_t* b = rowidx + colptr[r];
         const int32_t* e = rowidx + colptr[r + 1];
         const int32_t* f = std::lower_bound(b, e, c);
-        if (f == e || *f != c || vals[colptr[r] + (f - b)] != vals[p])
-          return set_err(QW_EINVAL, "matrix is not symmetric (pass flags=0 to accept it)");
+        const int64_t t = colptr[r] + (f - b);  // the mirrored entry (c, r)
+        if (f == e || *f != c || vals[t] != vals[p] || (vals_im && vals_im[t] != -vals_im[p]))
+          return set_err(QW_EINVAL, vals_im ? "matrix is not Hermitian (pass flags=0 to accept it)"
+                                            : "matrix is not symmetric (pass flags=0 to accept it)");
       }
   }
   hi.n = n;
@@ -290,6 +302,7 @@ int preprocess(int32_t n, const int32_t* colptr, const int32_t* rowidx, const do
   if (hi.s > hi.N) return set_err(QW_EINVAL, "s exceeds the padded dimension");
   ell.col.assign(size_t(hi.N) * hi.s, 0);
   ell.val.assign(size_t(hi.N) * hi.s, 0.0);
+  ell.vim.assign(vals_im ? size_t(hi.N) * hi.s : 0, 0.0);
   slot_of.assign(size_t(colptr[n]), -1);
   std::vector<int32_t> rows;
   std::vector<char> present(hi.N, 0);
@@ -311,6 +324,7 @@ int preprocess(int32_t n, const int32_t* colptr, const int32_t* rowidx, const do
       if (p < p1 && (f >= rows.size() || rowidx[p] < rows[f])) {
         ell.col[q] = rowidx[p];
         ell.val[q] = vals[p] * scale;
+        if (vals_im) ell.vim[q] = vals_im[p] * scale;
         slot_of[p] = int64_t(q);
         ++p;
       } else {
@@ -324,8 +338,8 @@ int preprocess(int32_t n, const int32_t* colptr, const int32_t* rowidx, const do
 }
 
 int load_impl(qw_ctx** out, int32_t ninst, const int32_t* n, const int64_t* colptr_off, const int64_t* nnz_off,
-              const int32_t* colptr, const int32_t* rowidx, const double* vals, const double* scales, uint32_t flags,
-              const qw_allocator* alloc, void* stream_v);
+              const int32_t* colptr, const int32_t* rowidx, const double* vals, const double* vals_im,
+              const double* scales, uint32_t flags, const qw_allocator* alloc, void* stream_v);
 
 // Drop one reference; the last one frees the context's device arrays.
 void ctx_release(qw_ctx* ctx) {
@@ -334,14 +348,15 @@ void ctx_release(qw_ctx* ctx) {
   ctx->alloc.put(ctx->col);
   ctx->alloc.put(ctx->val);
   ctx->alloc.put(ctx->rec);
+  ctx->alloc.put(ctx->vim);
   ctx->alloc.put(ctx->dinst);
   ctx->alloc.put(ctx->wave_inst);
   delete ctx;
 }
 
 int load_impl(qw_ctx** out, int32_t ninst, const int32_t* n, const int64_t* colptr_off, const int64_t* nnz_off,
-              const int32_t* colptr, const int32_t* rowidx, const double* vals, const double* scales, uint32_t flags,
-              const qw_allocator* alloc, void* stream_v) {
+              const int32_t* colptr, const int32_t* rowidx, const double* vals, const double* vals_im,
+              const double* scales, uint32_t flags, const qw_allocator* alloc, void* stream_v) {
   if (!out) return set_err(QW_EINVAL, "out is NULL");
   *out = nullptr;
   if (ninst <= 0 || !n || !colptr || !rowidx || !vals) return set_err(QW_EINVAL, "missing matrix arrays");
@@ -359,6 +374,8 @@ int load_impl(qw_ctx** out, int32_t ninst, const int32_t* n, const int64_t* colp
   ctx->inst.resize(ninst);
   std::vector<int32_t> hcol;
   std::vector<double> hval;
+  std::vector<double> hvim;  // imaginary parts by home (complex input)
+  ctx->complex_values = vals_im != nullptr;
   int64_t items = 0, jbase = 0, nnz_base = 0, ntot = 0;
   int nbits = 1;
   for (int32_t i = 0; i < ninst; ++i) {
@@ -367,7 +384,8 @@ int load_impl(qw_ctx** out, int32_t ninst, const int32_t* n, const int64_t* colp
     HostInst& hi = ctx->inst[i];
     Ell ell;
     std::vector<int64_t> slot_of;
-    int rc = preprocess(n[i], colptr + co, rowidx + zo, vals + zo, scales ? scales[i] : 0.0, flags, hi, ell, slot_of);
+    int rc = preprocess(n[i], colptr + co, rowidx + zo, vals + zo, vals_im ? vals_im + zo : nullptr,
+                        scales ? scales[i] : 0.0, flags, hi, ell, slot_of);
     if (rc) {
       prefix_err("instance " + std::to_string(i) + ": ");
       delete ctx;
@@ -382,11 +400,17 @@ int load_impl(qw_ctx** out, int32_t ninst, const int32_t* n, const int64_t* colp
     hval.resize(size_t(items + slots), 0.0);
     std::copy(ell.col.begin(), ell.col.end(), hcol.begin() + items);
     std::copy(ell.val.begin(), ell.val.end(), hval.begin() + items);
+    if (vals_im) {
+      hvim.resize(size_t(items + slots), 0.0);
+      for (int64_t q = 0; q < slots; ++q)  // row-major j*s + l -> home l*N + j
+        hvim[size_t(items + ((q & (hi.s - 1)) << hi.nbits) + (q >> hi.hbits))] = ell.vim[size_t(q)];
+    }
     for (int64_t q : slot_of)  // row-major ELL slot j*s + l -> home l*N + j
       ctx->csc_home.push_back(items + ((q & (hi.s - 1)) << hi.nbits) + (q >> hi.hbits));
     items += (slots + qw::kWave - 1) / qw::kWave * qw::kWave;
     hcol.resize(size_t(items), 0);
     hval.resize(size_t(items), 0.0);
+    if (vals_im) hvim.resize(size_t(items), 0.0);
     jbase += hi.N;
     nnz_base += hi.nnz;
     ntot += n[i];
@@ -442,7 +466,8 @@ int load_impl(qw_ctx** out, int32_t ninst, const int32_t* n, const int64_t* colp
   ctx->rec = static_cast<qw::SlotRec*>(ctx->alloc.get(sizeof(qw::SlotRec) * items));
   ctx->dinst = static_cast<qw::Inst*>(ctx->alloc.get(sizeof(qw::Inst) * ninst));
   ctx->wave_inst = static_cast<int32_t*>(ctx->alloc.get(sizeof(int32_t) * waves));
-  if (!ctx->col || !ctx->val || !ctx->rec || !ctx->dinst || !ctx->wave_inst) {
+  if (vals_im) ctx->vim = static_cast<double*>(ctx->alloc.get(sizeof(double) * items));
+  if (!ctx->col || !ctx->val || !ctx->rec || !ctx->dinst || !ctx->wave_inst || (vals_im && !ctx->vim)) {
     ctx_release(ctx);
     return set_err(QW_ENOMEM, "device allocation failed for the matrix");
   }
@@ -451,6 +476,8 @@ int load_impl(qw_ctx** out, int32_t ninst, const int32_t* n, const int64_t* colp
     e = hipMemcpyAsync(ctx->val, hval.data(), sizeof(double) * items, hipMemcpyHostToDevice, stream);
   if (e == hipSuccess)
     e = hipMemcpyAsync(ctx->dinst, dinst.data(), sizeof(qw::Inst) * ninst, hipMemcpyHostToDevice, stream);
+  if (e == hipSuccess && vals_im)
+    e = hipMemcpyAsync(ctx->vim, hvim.data(), sizeof(double) * items, hipMemcpyHostToDevice, stream);
   if (e == hipSuccess)
     e = hipMemcpyAsync(ctx->wave_inst, hwave.data(), sizeof(int32_t) * waves, hipMemcpyHostToDevice, stream);
   // O_s'^-1 of every reflected output: the QBS of j in row col[q], once per matrix
@@ -667,15 +694,25 @@ int qw_load_csc(qw_ctx** out, int32_t n, const int32_t* colptr, const int32_t* r
                 int64_t nnz, double scale, uint32_t flags, const qw_allocator* alloc, void* stream) {
   if (colptr && n > 0 && colptr[n] != nnz) return set_err(QW_EINVAL, "colptr[n] != nnz");
   const int64_t zero = 0;
-  return load_impl(out, 1, &n, &zero, &zero, colptr, rowidx, vals, scale > 0.0 ? &scale : nullptr, flags, alloc,
-                   stream);
+  return load_impl(out, 1, &n, &zero, &zero, colptr, rowidx, vals, nullptr, scale > 0.0 ? &scale : nullptr, flags,
+                   alloc, stream);
 }
 
 int qw_load_csc_batched(qw_ctx** out, int32_t ninst, const int32_t* n, const int64_t* colptr_off,
                         const int64_t* nnz_off, const int32_t* colptr, const int32_t* rowidx, const double* vals,
                         const double* scales, uint32_t flags, const qw_allocator* alloc, void* stream) {
   if (!colptr_off || !nnz_off) return set_err(QW_EINVAL, "offset arrays are required");
-  return load_impl(out, ninst, n, colptr_off, nnz_off, colptr, rowidx, vals, scales, flags, alloc, stream);
+  return load_impl(out, ninst, n, colptr_off, nnz_off, colptr, rowidx, vals, nullptr, scales, flags, alloc, stream);
+}
+
+int qw_load_csc_hermitian(qw_ctx** out, int32_t ninst, const int32_t* n, const int64_t* colptr_off,
+                          const int64_t* nnz_off, const int32_t* colptr, const int32_t* rowidx, const double* vals_re,
+                          const double* vals_im, const double* scales, uint32_t flags, const qw_allocator* alloc,
+                          void* stream) {
+  if (!vals_im) return set_err(QW_EINVAL, "vals_im is required (use qw_load_csc for real matrices)");
+  if (ninst > 1 && (!colptr_off || !nnz_off)) return set_err(QW_EINVAL, "offset arrays are required");
+  return load_impl(out, ninst, n, colptr_off, nnz_off, colptr, rowidx, vals_re, vals_im, scales, flags, alloc,
+                   stream);
 }
 
 int32_t qw_ctx_ninst(const qw_ctx* ctx) { return ctx ? ctx->ninst : 0; }
@@ -975,6 +1012,8 @@ int qw_grad(qw_state* st, const double* w, int32_t nsteps, double* dvals, double
   if (!st || !w) return set_err(QW_EINVAL, "missing argument");
   if (!st->prepared || st->steps_since_init != nsteps)
     return set_err(QW_EINVAL, "qw_grad needs the state made by qw_state_init (T~ start) advanced by exactly nsteps");
+  if (st->ctx->complex_values)
+    return set_err(QW_ENOTSUP, "the gradient is provided for real matrices only");
   hipStream_t stream = static_cast<hipStream_t>(stream_v);
   qw_ctx* ctx = st->ctx;
   std::vector<double> hw(static_cast<size_t>(ctx->jtotal), 0.0);

@@ -69,6 +69,7 @@ struct Matrix {
   const int32_t* col;        // ELL column indices (row-major), sorted inside each row
   const double* val;         // ELL values (row-major)
   const SlotRec* rec;        // slot records (by home)
+  const double* vim;         // imaginary parts of the values by home (NULL: a real matrix)
   const Inst* inst;
   const int32_t* wave_inst;  // instance of every step-kernel wavefront
   int64_t items;             // total slots including alignment padding
@@ -118,9 +119,9 @@ static_assert(sizeof(Inst) == 56 && offsetof(Inst, inv_sqrt_s) == 48, "Inst layo
 static_assert(sizeof(Slots) == 32, "Slots layout");
 static_assert(sizeof(List) == 24 && offsetof(List, cap) == 20, "List layout");
 static_assert(sizeof(SlotRec) == 16 && offsetof(SlotRec, val) == 8, "SlotRec layout");
-static_assert(sizeof(Matrix) == 144 && offsetof(Matrix, inst0) == 88, "Matrix layout");
-static_assert(sizeof(StepArgs) == 280 && offsetof(StepArgs, coefm) == 272, "StepArgs layout");
-static_assert(sizeof(AdjArgs) == 360 && offsetof(AdjArgs, wpb) == 352, "AdjArgs layout");
+static_assert(sizeof(Matrix) == 152 && offsetof(Matrix, inst0) == 96, "Matrix layout");
+static_assert(sizeof(StepArgs) == 288 && offsetof(StepArgs, coefm) == 280, "StepArgs layout");
+static_assert(sizeof(AdjArgs) == 368 && offsetof(AdjArgs, wpb) == 360, "AdjArgs layout");
 
 // Launchers (qw_launch.cpp).  All enqueue on `stream` and allocate nothing.
 hipError_t launch_step(const StepArgs& a, int grid, int block, hipStream_t stream);

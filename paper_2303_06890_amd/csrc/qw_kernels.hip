@@ -82,6 +82,19 @@ __device__ __forceinline__ Rot rotation(double a, int j, int k) {
   r.g = sqrt(1.0 - fabs(a));
   return r;
 }
+// A complex value a + i b held by row j (the row holds A*_{jk} of a Hermitian
+// matrix): off the real axis f = the principal sqrt(a + i b), so that
+// sqrt(A*_{jk}) of psi_j appears as in Sec. IV, and g = sqrt(1 - |a + i b|);
+// on the axis the real rule above.
+__device__ __forceinline__ Rot rotation(double a, double b, int j, int k) {
+  if (b == 0.0) return rotation(a, j, k);
+  Rot r;
+  const double m = hypot(a, b);
+  const double t = sqrt(0.5 * (m + fabs(a)));  // > 0 since b != 0
+  r.f = a >= 0.0 ? make_double2(t, 0.5 * b / t) : make_double2(0.5 * fabs(b) / t, copysign(t, b));
+  r.g = sqrt(1.0 - m);
+  return r;
+}
 // d f/da and d g/da (not finite at a = 0 and |a| = 1).
 __device__ __forceinline__ Rot rotation_deriv(double a, int j, int k) {
   Rot d;
@@ -346,7 +359,7 @@ __device__ __forceinline__ unsigned list_entry(const List& L, int64_t e, int n, 
 // The data loads do not depend on each other or on the instance record
 // beyond its base, so they are issued together.  FAST: walk step (not the
 // swap) and every row of every wavefront exists.
-template <bool ACC, int SLM, int S, bool FAST>
+template <bool ACC, int SLM, int S, bool FAST, bool CPLX>
 __device__ __forceinline__ unsigned step_wave(const StepArgs& a, int64_t w, int lane, double coef) {
   const Lanes x = lanes_of<S, FAST>(a.m, w, lane);
   const int sl = S ? Shape<S>::sl : (SLM == 1 ? 1 : x.I.sl);
@@ -354,12 +367,14 @@ __device__ __forceinline__ unsigned step_wave(const StepArgs& a, int64_t w, int 
   int64_t h[SLM];
   SlotRec rc[SLM];
   double2 x0[SLM], x1[SLM], y1[SLM];
+  double vi[SLM];
   Rot r[SLM];
 #pragma unroll
   for (int i = 0; i < SLM; ++i) {
     if (i < sl) {
       h[i] = base + (int64_t(x.h * sl + i) << x.I.nlog) + x.j;
       rc[i] = a.m.rec[h[i]];
+      if (CPLX) vi[i] = a.m.vim[h[i]];
       x0[i] = a.in.R0[h[i]];
       x1[i] = a.in.R1[h[i]];
       y1[i] = a.in.Q1[h[i]];
@@ -370,7 +385,7 @@ __device__ __forceinline__ unsigned step_wave(const StepArgs& a, int64_t w, int 
 #pragma unroll
   for (int i = 0; i < SLM; ++i) {
     if (i < sl) {
-      r[i] = rotation(rc[i].val, x.j, rc[i].col);
+      r[i] = CPLX ? rotation(rc[i].val, vi[i], x.j, rc[i].col) : rotation(rc[i].val, x.j, rc[i].col);
       c = cadd(c, along(r[i], x0[i], x1[i]));
     }
   }
@@ -402,7 +417,7 @@ __device__ __forceinline__ unsigned step_wave(const StepArgs& a, int64_t w, int 
 // SLM: slots per lane held in registers; S: s of every instance, or 0 (read
 // per instance, slots per lane <= SLM).  FAST: one pass (the grid covers
 // every wavefront and the list), walk step only, every row exists.
-template <bool ACC, int SLM, int S, bool FAST>
+template <bool ACC, int SLM, int S, bool FAST, bool CPLX>
 __device__ __forceinline__ void step_body(const StepArgs& a) {
   const int lane = threadIdx.x & (kWave - 1);
   const int64_t wpb = a.wpb;  // a kernel argument: reading the workgroup size costs a vector load
@@ -417,7 +432,7 @@ __device__ __forceinline__ void step_body(const StepArgs& a) {
   if (FAST) {
     const int64_t w = uniform(int(wid));
     if (w < a.m.waves)
-      cnt = step_wave<ACC, SLM, S, true>(a, w, lane, coef);
+      cnt = step_wave<ACC, SLM, S, true, CPLX>(a, w, lane, coef);
     else
       cnt = list_entry(a.L, (w - a.m.waves) * kWave + lane, a.m.nbits, true);
   } else {
@@ -425,7 +440,7 @@ __device__ __forceinline__ void step_body(const StepArgs& a) {
     const int64_t wstride = int64_t(gridDim.x) * wpb;
     for (int64_t w = uniform(int(wid)); w < total; w += wstride) {
       if (w < a.m.waves)
-        cnt += step_wave<ACC, SLM, S, false>(a, w, lane, coef);
+        cnt += step_wave<ACC, SLM, S, false, CPLX>(a, w, lane, coef);
       else
         cnt += list_entry(a.L, (w - a.m.waves) * kWave + lane, a.m.nbits, a.mode == kStep);
     }
@@ -439,29 +454,34 @@ __device__ __forceinline__ void step_body(const StepArgs& a) {
 // qwk_step_sN: any s per instance, up to N slots per lane (s <= 8N), any
 // launch shape, walk step or swap; qwk_step_gN: the same s per instance, but
 // every instance has at least one wavefront of rows, one pass, walk step;
-// qwk_step_fS: as gN with s = S for every instance.
-#define QW_STEP_KERNEL(NAME, SLM, S, FAST)                                                         \
+// qwk_step_fS: as gN with s = S for every instance; qwk_step_cN: as sN for a
+// complex Hermitian matrix.
+#define QW_STEP_KERNEL(NAME, SLM, S, FAST, CPLX)                                                   \
   extern "C" __global__ void __launch_bounds__(256) NAME(qw::StepArgs a) {                         \
-    qw::step_body<false, SLM, S, FAST>(a);                                                          \
+    qw::step_body<false, SLM, S, FAST, CPLX>(a);                                                    \
   }                                                                                                 \
   extern "C" __global__ void __launch_bounds__(256) NAME##_acc(qw::StepArgs a) {                   \
-    qw::step_body<true, SLM, S, FAST>(a);                                                           \
+    qw::step_body<true, SLM, S, FAST, CPLX>(a);                                                     \
   }
-QW_STEP_KERNEL(qwk_step_s1, 1, 0, false)
-QW_STEP_KERNEL(qwk_step_s2, 2, 0, false)
-QW_STEP_KERNEL(qwk_step_s4, 4, 0, false)
-QW_STEP_KERNEL(qwk_step_s8, 8, 0, false)
-QW_STEP_KERNEL(qwk_step_g1, 1, 0, true)
-QW_STEP_KERNEL(qwk_step_g2, 2, 0, true)
-QW_STEP_KERNEL(qwk_step_g4, 4, 0, true)
-QW_STEP_KERNEL(qwk_step_g8, 8, 0, true)
-QW_STEP_KERNEL(qwk_step_f1, 1, 1, true)
-QW_STEP_KERNEL(qwk_step_f2, 1, 2, true)
-QW_STEP_KERNEL(qwk_step_f4, 1, 4, true)
-QW_STEP_KERNEL(qwk_step_f8, 1, 8, true)
-QW_STEP_KERNEL(qwk_step_f16, 2, 16, true)
-QW_STEP_KERNEL(qwk_step_f32, 4, 32, true)
-QW_STEP_KERNEL(qwk_step_f64, 8, 64, true)
+QW_STEP_KERNEL(qwk_step_s1, 1, 0, false, false)
+QW_STEP_KERNEL(qwk_step_s2, 2, 0, false, false)
+QW_STEP_KERNEL(qwk_step_s4, 4, 0, false, false)
+QW_STEP_KERNEL(qwk_step_s8, 8, 0, false, false)
+QW_STEP_KERNEL(qwk_step_g1, 1, 0, true, false)
+QW_STEP_KERNEL(qwk_step_g2, 2, 0, true, false)
+QW_STEP_KERNEL(qwk_step_g4, 4, 0, true, false)
+QW_STEP_KERNEL(qwk_step_g8, 8, 0, true, false)
+QW_STEP_KERNEL(qwk_step_f1, 1, 1, true, false)
+QW_STEP_KERNEL(qwk_step_f2, 1, 2, true, false)
+QW_STEP_KERNEL(qwk_step_f4, 1, 4, true, false)
+QW_STEP_KERNEL(qwk_step_f8, 1, 8, true, false)
+QW_STEP_KERNEL(qwk_step_f16, 2, 16, true, false)
+QW_STEP_KERNEL(qwk_step_f32, 4, 32, true, false)
+QW_STEP_KERNEL(qwk_step_f64, 8, 64, true, false)
+QW_STEP_KERNEL(qwk_step_c1, 1, 0, false, true)
+QW_STEP_KERNEL(qwk_step_c2, 2, 0, false, true)
+QW_STEP_KERNEL(qwk_step_c4, 4, 0, false, true)
+QW_STEP_KERNEL(qwk_step_c8, 8, 0, false, true)
 #undef QW_STEP_KERNEL
 
 
@@ -597,7 +617,7 @@ extern "C" __global__ void __launch_bounds__(256) qwk_init(Matrix m, const doubl
     const Home x = home_item(m, it, it - (threadIdx.x & (kWave - 1)));
     if (!x.live) continue;
     const SlotRec rc = m.rec[it];
-    const Rot r = rotation(rc.val, x.j, rc.col);
+    const Rot r = rotation(rc.val, m.vim ? m.vim[it] : 0.0, x.j, rc.col);
     const double2 bj = cscale(b[x.I.jbase + x.j], x.I.inv_sqrt_s);
     double2 o0 = cmul(r.f, bj);
     double2 o1 = cscale(bj, r.g);
@@ -668,7 +688,7 @@ extern "C" __global__ void __launch_bounds__(256) qwk_measure_rows(Matrix m, Slo
           if (sw != 0.0) atomicAdd(&out[x.I.jbase + m.rec[h].col], sw);
         } else {
           const SlotRec rc = m.rec[h];
-          c = cadd(c, along(rotation(rc.val, x.j, rc.col), p0, p1));
+          c = cadd(c, along(rotation(rc.val, m.vim ? m.vim[h] : 0.0, x.j, rc.col), p0, p1));
         }
       }
       if (kind == 2) {

@@ -24,9 +24,10 @@ namespace {
 // many slots held per lane (s <= 8, 16, 32, 64), any launch shape and either
 // mode; qwk_step_g{1,2,4,8} need every instance to have at least one
 // wavefront's rows, a grid that covers the work in one pass, and the walk
-// step; qwk_step_f{S} need that and s = S for every instance.  Each has an
-// _acc twin (the solver's fused projection).  Adjoint kernels come in the
-// four widths.
+// step; qwk_step_f{S} need that and s = S for every instance;
+// qwk_step_c{1,2,4,8} are the general kernels for complex Hermitian matrices.
+// Each has an _acc twin (the solver's fused projection).  Adjoint kernels
+// (real matrices) come in the four widths.
 enum Fn {
   F_STEP_S1,
   F_STEP_S2,
@@ -43,6 +44,10 @@ enum Fn {
   F_STEP_F16,
   F_STEP_F32,
   F_STEP_F64,
+  F_STEP_C1,
+  F_STEP_C2,
+  F_STEP_C4,
+  F_STEP_C8,
   F_STEP_COUNT_,  // _acc twins follow at + F_STEP_COUNT_
   F_ADJOINT_S1 = 2 * F_STEP_COUNT_,
   F_ADJOINT_S2,
@@ -64,9 +69,11 @@ const char* const kNames[F_COUNT] = {
     "qwk_step_s1",      "qwk_step_s2",      "qwk_step_s4",      "qwk_step_s8",      "qwk_step_g1",
     "qwk_step_g2",      "qwk_step_g4",      "qwk_step_g8",      "qwk_step_f1",      "qwk_step_f2",
     "qwk_step_f4",      "qwk_step_f8",      "qwk_step_f16",     "qwk_step_f32",     "qwk_step_f64",
+    "qwk_step_c1",      "qwk_step_c2",      "qwk_step_c4",      "qwk_step_c8",
     "qwk_step_s1_acc",  "qwk_step_s2_acc",  "qwk_step_s4_acc",  "qwk_step_s8_acc",  "qwk_step_g1_acc",
     "qwk_step_g2_acc",  "qwk_step_g4_acc",  "qwk_step_g8_acc",  "qwk_step_f1_acc",  "qwk_step_f2_acc",
     "qwk_step_f4_acc",  "qwk_step_f8_acc",  "qwk_step_f16_acc", "qwk_step_f32_acc", "qwk_step_f64_acc",
+    "qwk_step_c1_acc",  "qwk_step_c2_acc",  "qwk_step_c4_acc",  "qwk_step_c8_acc",
     "qwk_adjoint_s1",   "qwk_adjoint_s2",   "qwk_adjoint_s4",   "qwk_adjoint_s8",   "qwk_qbs_table",
     "qwk_init",         "qwk_fill",         "qwk_measure",      "qwk_measure_rows", "qwk_export",
     "qwk_import",       "qwk_weight",       "qwk_grad_init"};
@@ -79,7 +86,9 @@ Fn step_kernel(const StepArgs& a, int grid, int block) {
   const bool acc = a.yacc != nullptr;
   const int64_t work = m.waves + (int64_t(a.L.cnt) + kWave - 1) / kWave;
   int f = F_STEP_S1 + width_index(m.slmax);
-  if (m.full && a.mode == kStep && int64_t(grid) * (block / kWave) >= work) {
+  if (m.vim) {
+    f = F_STEP_C1 + width_index(m.slmax);
+  } else if (m.full && a.mode == kStep && int64_t(grid) * (block / kWave) >= work) {
     f = F_STEP_G1 + width_index(m.slmax);
     if (m.suni > 0) {
       int lg = 0;
@@ -152,6 +161,7 @@ hipError_t launch_step(const StepArgs& a, int grid, int block, hipStream_t strea
 
 hipError_t launch_adjoint(const AdjArgs& a, int grid, int block, hipStream_t stream) {
   if (block < kWave || block > kMaxBlock || block % kWave) return hipErrorInvalidValue;
+  if (a.m.vim) return hipErrorInvalidValue;  // the gradient sweep is for real matrices
   AdjArgs c = a;
   c.wpb = block / kWave;
   c.pad_ = 0;

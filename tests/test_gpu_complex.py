@@ -1,0 +1,165 @@
+"""Complex Hermitian matrices on the GPU: the walk, W^dagger, measurements,
+the batched form and the solver against the oracle, and the Chebyshev
+closed form at 16384 columns."""
+import numpy as np
+import pytest
+import scipy.sparse as sp
+
+import workloads as W
+from tests.parity import compare_states
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def Q():
+    import torch
+
+    assert torch.cuda.is_available()
+    import paper_2303_06890_amd as Q
+
+    return Q
+
+
+def _b(n, seed):
+    b = W.gaussian_b(n, seed=seed) * np.exp(0.4j * np.arange(n))
+    return b / np.linalg.norm(b)
+
+
+def _pair(Q, oracle_mod, csc, b, raw=False):
+    walk = Q.Walk(csc)
+    assert walk.complex
+    st = walk.state(b, raw=raw)
+    om = oracle_mod.OracleMatrix(csc)
+    ost = oracle_mod.OracleState(om).set_b(b)
+    if not raw:
+        ost.T()
+    return walk, st, ost
+
+
+def _check(st, ost, where):
+    gk, ga = st.export()
+    ok, oa = ost.export()
+    compare_states(gk, ga, ok, oa, where=where)
+
+
+@pytest.mark.parametrize("n,c,seed", [(64, 5, 1), (200, 8, 2), (96, 3, 3), (256, 16, 4)])
+def test_complex_walk_100_steps(Q, oracle_mod, n, c, seed):
+    csc = W.hermitian_offset_matrix(n, c, seed=seed)
+    walk, st, ost = _pair(Q, oracle_mod, csc, _b(n, seed))
+    _check(st, ost, "init")
+    done = 0
+    for t in (1, 2, 10, 100):
+        st.step(t - done)
+        ost.step(t - done)
+        done = t
+        _check(st, ost, f"n={n} c={c} step {t}")
+
+
+def test_complex_raw_start_and_adjoint(Q, oracle_mod):
+    csc = W.hermitian_offset_matrix(32, 6, seed=5)
+    b = _b(32, 6)
+    walk, st, ost = _pair(Q, oracle_mod, csc, b, raw=True)
+    st.step(12)
+    ost.step(12)
+    _check(st, ost, "raw step 12")
+    st.step_adjoint(5)
+    ost.step_adjoint(5)
+    _check(st, ost, "W^dagger 5")
+
+
+def test_complex_measurements(Q, oracle_mod):
+    csc = W.hermitian_offset_matrix(256, 8, seed=7)
+    walk, st, ost = _pair(Q, oracle_mod, csc, _b(256, 8))
+    st.step(9)
+    ost.step(9)
+    assert abs(st.norm2() - 1.0) < 1e-13
+    assert np.abs(st.j_marginal() - ost.j_marginal()).max() < 1e-14
+    assert np.abs(st.project() - ost.project0()).max() < 1e-14
+
+
+def _as_complex(csc):
+    """A real symmetric matrix given to the Hermitian loader (zero imaginary parts)."""
+    return csc.n, csc.colptr, csc.rowidx, csc.vals.astype(np.complex128)
+
+
+def test_complex_batched_vs_oracle(Q, oracle_mod):
+    mats = [W.hermitian_offset_matrix(64, 5, seed=11), W.hermitian_offset_matrix(128, 12, seed=12),
+            W.Csc(*_as_complex(W.offset_matrix(32, 4, seed=13)))]
+    bs = [_b(m.n, 20 + i) for i, m in enumerate(mats)]
+    walk = Q.Walk(mats)
+    st = walk.state(bs).step(15)
+    keys, amps = st.export()
+    from tests.test_gpu_batched import _slice, unpack
+
+    F = unpack(keys, walk.nbits)
+    for i, (a, b) in enumerate(zip(mats, bs)):
+        om = oracle_mod.OracleMatrix(a)
+        ok, oa = oracle_mod.OracleState(om).set_b(b).T().step(15).export()
+        gk, ga = _slice(F, amps, i, om.nbits)
+        compare_states(gk, ga, ok, oa, where=f"complex instance {i}")
+
+
+def test_real_matrix_through_the_hermitian_path(Q, oracle_mod):
+    """Zero imaginary parts take the real rule: the complex kernels reproduce
+    the real walk."""
+    real = W.offset_matrix(128, 7, seed=31)
+    b = W.gaussian_b(128, seed=32)
+    k1, a1 = Q.Walk(real).state(b).step(25).export()
+    cw = Q.Walk(W.Csc(*_as_complex(real)))
+    assert cw.complex
+    k2, a2 = cw.state(b).step(25).export()
+    assert np.array_equal(k1, k2)
+    assert np.abs(a1 - a2).max() < 1e-14
+
+
+def test_complex_solver(Q, oracle_mod):
+    """Walk-based CKS solve on a complex Hermitian matrix: equal to the
+    oracle's classical series and close to A^-1 b."""
+    csc = W.hermitian_offset_matrix(64, 5, seed=41)
+    om = oracle_mod.OracleMatrix(csc)
+    A = csc.dense() * om.scale
+    H = A / om.s
+    kappa = 1.0 / np.abs(np.linalg.eigvalsh(H)).min()
+    b = W.gaussian_b(64, seed=42)
+    beta, j0 = oracle_mod.schedule(kappa, 1e-3)
+    coef = oracle_mod.cks_coeffs(beta, j0)
+    y_ref = om.cheb_series(b, j0, coef)
+    y, p_succ, steps = Q.Walk(csc).qls(b, kappa, eps=1e-3)
+    assert steps == 2 * j0 + 1
+    assert np.abs(y - y_ref).max() <= 1e-10 * np.abs(y_ref).max()
+    x = np.linalg.solve(H, b)
+    fid = abs(np.vdot(x, y)) ** 2 / (np.vdot(x, x).real * np.vdot(y, y).real)
+    assert fid > 1 - 1e-4
+
+
+def test_complex_gradient_not_provided(Q):
+    from paper_2303_06890_amd import QwError
+
+    csc = W.hermitian_offset_matrix(32, 4, seed=51)
+    st = Q.Walk(csc).state(W.uniform_b(32)).step(3)
+    with pytest.raises(QwError, match="real matrices"):
+        st.grad(np.ones(32), 3)
+
+
+def test_complex_chebyshev_full_size(Q):
+    """Pi_0 T~^dagger W^n T~ |b~> = T_n(A/s) b at 16384 columns, 8 entries per
+    column, complex Hermitian."""
+    csc = W.hermitian_offset_matrix(16384, 8, seed=61)
+    b = W.uniform_b(16384)
+    walk = Q.Walk(csc)
+    info = walk.info[0]
+    A = sp.csc_matrix((csc.vals * info["scale"], csc.rowidx, csc.colptr), shape=(csc.n, csc.n))
+    H = (A / info["s"]).tocsr()
+    prev, cur = b.astype(complex), H @ b.astype(complex)
+    ref = {1: cur.copy()}
+    for n in range(2, 51):
+        prev, cur = cur, 2 * (H @ cur) - prev
+        ref[n] = cur.copy()
+    st = walk.state(b)
+    done = 0
+    for t in (1, 2, 10, 50):
+        st.step(t - done)
+        done = t
+        assert np.abs(st.project() - ref[t]).max() < 1e-11, t
+        assert abs(st.norm2() - 1.0) < 1e-12

@@ -101,6 +101,43 @@ def test_rejects_row_index_out_of_range(lib):
     assert rc == -1
 
 
+def _load_hermitian(lib, csc, flags=1, with_im=True, scale=None):
+    h = ctypes.c_void_p()
+    n = np.array([csc.n], np.int32)
+    cp = np.ascontiguousarray(csc.colptr, np.int32)
+    ri = np.ascontiguousarray(csc.rowidx, np.int32)
+    re_ = np.ascontiguousarray(np.real(csc.vals), np.float64)
+    im_ = np.ascontiguousarray(np.imag(csc.vals), np.float64)
+    dp = ctypes.POINTER(ctypes.c_double)
+    ip = ctypes.POINTER(ctypes.c_int32)
+    rc = lib.qw_load_csc_hermitian(ctypes.byref(h), 1, n.ctypes.data_as(ip), None, None, cp.ctypes.data_as(ip),
+                                   ri.ctypes.data_as(ip), re_.ctypes.data_as(dp),
+                                   im_.ctypes.data_as(dp) if with_im else None,
+                                   ctypes.byref(ctypes.c_double(scale)) if scale else None, flags, None, None)
+    return rc, lib.qw_last_error().decode()
+
+
+def test_hermitian_loader_validation(lib):
+    csc = W.hermitian_offset_matrix(16, 5, seed=3)
+    # a mirrored pair that is equal instead of conjugate
+    d = csc.dense()
+    k = np.argwhere(np.abs(d.imag) > 0)[0]
+    bad = d.copy()
+    bad[k[1], k[0]] = d[k[0], k[1]]
+    rc, msg = _load_hermitian(lib, W.from_dense(bad))
+    assert rc == -1 and "Hermitian" in msg
+    # an imaginary diagonal entry
+    bad = d.copy()
+    bad[2, 2] += 0.1j
+    rc, msg = _load_hermitian(lib, W.from_dense(bad))
+    assert rc == -1 and "diagonal" in msg
+    # |a| > 1 measured as the modulus (each part alone is below 1)
+    rc, msg = _load_hermitian(lib, W.from_dense(np.array([[0.5, 0.8 + 0.8j], [0.8 - 0.8j, 0.5]])), scale=1.0)
+    assert rc == -1 and "|a| > 1" in msg
+    rc, msg = _load_hermitian(lib, csc, with_im=False)
+    assert rc == -1 and "vals_im" in msg
+
+
 def test_cks_coeffs_host(lib):
     """The library's coefficients (Stirling + ratio recurrence) agree with an
     exact rational evaluation and with the binomial tail."""

@@ -52,7 +52,8 @@ class Csc:
 def _from_triplets(n: int, rows, cols, vals) -> Csc:
     rows = np.asarray(rows, dtype=np.int64)
     cols = np.asarray(cols, dtype=np.int64)
-    vals = np.asarray(vals, dtype=np.float64)
+    vals = np.asarray(vals)
+    vals = vals.astype(np.complex128 if np.iscomplexobj(vals) else np.float64)
     order = np.lexsort((rows, cols))
     rows, cols, vals = rows[order], cols[order], vals[order]
     key = cols * n + rows
@@ -66,7 +67,8 @@ def _from_triplets(n: int, rows, cols, vals) -> Csc:
 
 def from_dense(a: np.ndarray) -> Csc:
     """CSC of the nonzero pattern of a dense square matrix."""
-    a = np.asarray(a, dtype=np.float64)
+    a = np.asarray(a)
+    a = a.astype(np.complex128 if np.iscomplexobj(a) else np.float64)
     r, c = np.nonzero(a)
     return _from_triplets(a.shape[0], r, c, a[r, c])
 
