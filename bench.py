@@ -207,6 +207,29 @@ def table1_leg(Q, W, autotune, tune: bool):
     return out
 
 
+def complex_leg(Q, W, autotune, tune: bool, steps: int = 2000):
+    """The main workload's shape with complex Hermitian values: 16384 columns,
+    8 entries per column (the off-diagonal pairs v, conj(v)), uniform b."""
+    csc = W.hermitian_offset_matrix(16384, 8, seed=2)
+    b = W.uniform_b(16384)
+    walk = Q.Walk(csc)
+    shape = autotune.tune(walk, b) if tune else None
+    st = walk.state(b)
+    if shape:
+        autotune.apply(st, shape)
+    st.step(64)
+    s0 = st.stats()
+    ms = _timed(Q, lambda: st.step(steps))
+    upd = st.stats()["total_written"] - s0["total_written"]
+    return {
+        "workload": "complex Hermitian offset matrix n = 16384, 8 entries/column, seed 2, uniform b, T~ start",
+        "branches": st.count(),
+        "us_per_step": 1e3 * ms / steps,
+        "value": upd / (ms / 1e3),
+        "launch_shape": list(shape) if shape else "default",
+    }
+
+
 def adjoint_leg(Q, W, steps: int = 20, reps: int = 5):
     """Gradient of the total probability of 32 column outcomes after 20 steps
     on G(1024, 8) w.r.t. all 8192 values and b (forward walk + reverse sweep
@@ -245,11 +268,11 @@ def main():
     ap.add_argument("--warmup", type=int, default=64)
     ap.add_argument("--cpu-steps", type=int, default=5, help="walk steps of the oracle sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-extras", action="store_true", help="skip the batched, adjoint and paper-shape legs")
+    ap.add_argument("--no-extras", action="store_true", help="skip the batched, adjoint, complex and paper-shape legs")
     ap.add_argument("--no-tune", action="store_true", help="keep the default launch shape")
     ap.add_argument("--launch", default=None, metavar="WG,GRID",
                     help="fixed launch shape of the main leg (workgroup size, workgroups)")
-    ap.add_argument("--only", choices=["batched", "adjoint", "table1"], default=None,
+    ap.add_argument("--only", choices=["batched", "adjoint", "table1", "complex"], default=None,
                     help="run one extra leg alone (for profiling) and print its JSON")
     ap.add_argument("--pmc-run", action="store_true",
                     help="counter run: a torch copy of 64 MiB (byte calibration), then 64 walk steps of "
@@ -287,6 +310,9 @@ def main():
         return
     if args.only == "adjoint":
         print(json.dumps(adjoint_leg(Q, W)), flush=True)
+        return
+    if args.only == "complex":
+        print(json.dumps(complex_leg(Q, W, autotune, not args.no_tune)), flush=True)
         return
     if args.only == "table1":
         print(json.dumps(table1_leg(Q, W, autotune, not args.no_tune)), flush=True)
@@ -362,6 +388,8 @@ def main():
         print(f"[bench] batched: {line['batched']}", file=sys.stderr, flush=True)
         line["adjoint"] = adjoint_leg(Q, W)
         print(f"[bench] adjoint: {line['adjoint']}", file=sys.stderr, flush=True)
+        line["complex"] = complex_leg(Q, W, autotune, not args.no_tune)
+        print(f"[bench] complex: {line['complex']}", file=sys.stderr, flush=True)
         line["table1_shapes"] = table1_leg(Q, W, autotune, not args.no_tune)
         print(f"[bench] table1 shapes: {line['table1_shapes']}", file=sys.stderr, flush=True)
     if not args.no_cpu_baseline:
