@@ -230,6 +230,49 @@ def complex_leg(Q, W, autotune, tune: bool, steps: int = 2000):
     }
 
 
+def max_size_leg(Q, W, steps: int = 50, oracle_steps: int = 10):
+    """Branch count of the walk versus N and s on band matrices (uniform b,
+    T~ start): the largest count at step boundaries over `steps` steps on the
+    GPU, and for n <= 256 also the oracle's largest count after any single
+    register-level operation (inside a step, as an op-by-op simulator holds
+    the state), over `oracle_steps` steps."""
+    import numpy as np
+
+    import oracle
+
+    cases = [(n, 1) for n in (64, 256, 1024, 4096, 16384)] + [(n, 3) for n in (64, 256, 1024, 4096, 16384)]
+    cases += [(4096, w) for w in (7, 15, 31)]
+    rows = []
+    for n, w in cases:
+        csc = W.band_matrix(n, w, seed=5)
+        b = W.uniform_b(n)
+        walk = Q.Walk(csc)
+        st = walk.state(b)
+        mmax = st.count()
+        for _ in range(steps):
+            st.step(1)
+            mmax = max(mmax, st.count())
+        N, s = walk.info[0]["N"], walk.info[0]["s"]
+        row = {"n": n, "s": s, "m_max_boundary": mmax, "per_Ns": mmax / (N * s)}
+        if n <= 256:
+            ost = oracle.OracleState(oracle.OracleMatrix(csc)).set_b(b).T().step(oracle_steps)
+            row["m_max_inside_step_oracle"] = ost.max_size()
+        rows.append(row)
+        st.close()
+        walk.close()
+
+    def slope(xs, ys):
+        return float(np.polyfit(np.log(xs), np.log(ys), 1)[0])
+
+    by_s = [r for r in rows if r["n"] == 4096]
+    out = {"rows": rows,
+           "loglog_slope_vs_s_at_n4096": slope([r["s"] for r in by_s], [r["m_max_boundary"] for r in by_s])}
+    for s_ in (4, 8):
+        by_n = [r for r in rows if r["s"] == s_]
+        out[f"loglog_slope_vs_n_at_s{s_}"] = slope([r["n"] for r in by_n], [r["m_max_boundary"] for r in by_n])
+    return out
+
+
 def adjoint_leg(Q, W, steps: int = 20, reps: int = 5):
     """Gradient of the total probability of 32 column outcomes after 20 steps
     on G(1024, 8) w.r.t. all 8192 values and b (forward walk + reverse sweep
@@ -268,11 +311,11 @@ def main():
     ap.add_argument("--warmup", type=int, default=64)
     ap.add_argument("--cpu-steps", type=int, default=5, help="walk steps of the oracle sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-extras", action="store_true", help="skip the batched, adjoint, complex and paper-shape legs")
+    ap.add_argument("--no-extras", action="store_true", help="skip the batched, adjoint, complex, paper-shape and branch-count legs")
     ap.add_argument("--no-tune", action="store_true", help="keep the default launch shape")
     ap.add_argument("--launch", default=None, metavar="WG,GRID",
                     help="fixed launch shape of the main leg (workgroup size, workgroups)")
-    ap.add_argument("--only", choices=["batched", "adjoint", "table1", "complex"], default=None,
+    ap.add_argument("--only", choices=["batched", "adjoint", "table1", "complex", "max_size"], default=None,
                     help="run one extra leg alone (for profiling) and print its JSON")
     ap.add_argument("--pmc-run", action="store_true",
                     help="counter run: a torch copy of 64 MiB (byte calibration), then 64 walk steps of "
@@ -310,6 +353,9 @@ def main():
         return
     if args.only == "adjoint":
         print(json.dumps(adjoint_leg(Q, W)), flush=True)
+        return
+    if args.only == "max_size":
+        print(json.dumps(max_size_leg(Q, W)), flush=True)
         return
     if args.only == "complex":
         print(json.dumps(complex_leg(Q, W, autotune, not args.no_tune)), flush=True)
@@ -392,6 +438,8 @@ def main():
         print(f"[bench] complex: {line['complex']}", file=sys.stderr, flush=True)
         line["table1_shapes"] = table1_leg(Q, W, autotune, not args.no_tune)
         print(f"[bench] table1 shapes: {line['table1_shapes']}", file=sys.stderr, flush=True)
+        line["max_size"] = max_size_leg(Q, W)
+        print(f"[bench] max size: {line['max_size']}", file=sys.stderr, flush=True)
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(csc, b, args.cpu_steps)
         print(f"[bench] oracle: {line['cpu_baseline']['value']:.3e} updates/s", file=sys.stderr, flush=True)

@@ -64,6 +64,7 @@ def _load():
         "orc_count": (i64, [P]),
         "orc_ambiguous": (i64, [P, i32]),
         "orc_pruned_mass": (dbl, [P]),
+        "orc_max_size": (ctypes.c_int64, [P]),
         "orc_export": (ctypes.c_int, [P, up, dp, dp]),
         "orc_norm2": (dbl, [P]),
         "orc_j_marginal": (None, [P, dp]),
@@ -224,6 +225,11 @@ class OracleState:
 
     def ambiguous(self, total: bool = False) -> int:
         return int(_load().orc_ambiguous(self._h, 1 if total else 0))
+
+    def max_size(self) -> int:
+        """Largest branch count after any single register-level operation so
+        far, inside walk steps included."""
+        return int(_load().orc_max_size(self._h))
 
     def pruned_mass(self) -> float:
         return float(_load().orc_pruned_mass(self._h))

@@ -391,6 +391,7 @@ struct OState {
   int64_t ambiguous = 0;       // amplitudes within +-margin of tau at the last prune
   int64_t ambiguous_total = 0;  // summed over all prunes
   double pruned_mass = 0.0;     // sum |amp|^2 removed by the last prune
+  int64_t max_size = 0;         // largest number of branches after any single operation
 };
 
 void prune(OState& o) {
@@ -411,8 +412,14 @@ void prune(OState& o) {
   o.pruned_mass = mass;
 }
 
+// Apply the operations in order, keeping the largest intermediate size (the
+// M_max of the space-complexity discussion, Sec. "The space complexity of
+// simulating the quantum walk", counts the branches inside a step).
 void run(OState& o, const std::vector<Op>& ops) {
-  for (Op op : ops) apply(o.st, *o.m, op);
+  for (Op op : ops) {
+    apply(o.st, *o.m, op);
+    o.max_size = std::max<int64_t>(o.max_size, int64_t(o.st.size()));
+  }
 }
 
 uint64_t pack(const Matrix& m, const Reg& r) {
@@ -653,6 +660,9 @@ int64_t orc_ambiguous(void* p, int32_t total) {
 }
 
 double orc_pruned_mass(void* p) { return static_cast<OState*>(p)->pruned_mass; }
+
+// Largest branch count after any single operation so far (inside steps too).
+int64_t orc_max_size(void* p) { return static_cast<OState*>(p)->max_size; }
 
 // Export sorted by packed key; fails if an ancilla (A) is not clean.
 int orc_export(void* p, uint64_t* keys, double* re, double* im) {
