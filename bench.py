@@ -319,7 +319,8 @@ def main():
                     help="run one extra leg alone (for profiling) and print its JSON")
     ap.add_argument("--pmc-run", action="store_true",
                     help="counter run: a torch copy of 64 MiB (byte calibration), then 64 walk steps of "
-                         "the main workload (default launch shape unless --launch); prints nothing else")
+                         "the main workload (default launch shape unless --launch), or of the batched leg "
+                         "with --only batched; prints nothing else")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on exactly one GPU: this build has no multi-GPU path "
@@ -340,6 +341,13 @@ def main():
         dst = torch.empty_like(src)
         dst.copy_(src)
         torch.cuda.synchronize()
+        if args.only == "batched":  # counters of the batched step kernel instead
+            inst = W.batched_instances()
+            st = Q.Walk([a for a, _ in inst]).state([b for _, b in inst])
+            st.step(64)
+            st.sync()
+            print(json.dumps({"pmc_run": True, "copy_bytes": 8 << 23, "batched_steps": 64}), flush=True)
+            return
         csc, b = W.paper_scale()
         st = Q.Walk(csc).state(b)
         if args.launch:
