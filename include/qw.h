@@ -166,7 +166,8 @@ int qw_measure(qw_state* st, int32_t kind, void* out, int64_t out_len, void* str
 int qw_export(qw_state* st, uint64_t* keys, double* re, double* im, int64_t cap, int64_t* m,
               void* stream);
 
-/* Replace the state by the given branches (equal keys are summed).  Keys must
+/* Replace the state by the given branches (equal keys are summed; branches
+ * whose |Re| and |Im| are both <= tau = 1e-13 are dropped, as after a step).  Keys must
  * follow the layout above with valid instance and register ranges, and every
  * branch must satisfy j_c < s and k_c < s (true of every state the walk
  * reaches).  Errors: QW_EINVAL, QW_ECAPACITY. */

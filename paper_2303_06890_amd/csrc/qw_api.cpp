@@ -128,6 +128,7 @@ namespace {
 struct GraphEntry {
   hipStream_t stream;
   int parity;
+  double r1s;  // sign of the R1 storage when the graph starts
   int steps;
   hipGraphExec_t exec;
 };
@@ -136,8 +137,9 @@ struct GraphEntry {
 
 struct qw_state {
   qw_ctx* ctx = nullptr;
-  Slots buf[2]{};           // amplitudes with a static home, two parities
+  Slots buf[2]{};           // R0, Q0, Q1 planes of the two parity buffers (R1 unused)
   int cur = 0;              // parity holding the state
+  double r1s = 1.0;         // buffer cur^1's Q1 plane holds r1s * (the state's R1)
   List L{};                 // branches without a static home (count on the host)
   unsigned long long* acc = nullptr;  // per-workgroup counts of branches written
   uint32_t* stepno = nullptr;         // per-wavefront solver step counters
@@ -170,11 +172,21 @@ int step_grid(const qw_state* st) {
   return int(g);
 }
 
+// The state's planes as held in buffer p (the current one for the state
+// itself): R1 is buffer p^1's Q1 plane, times r1s.
+qw::Slots view(const qw_state* st, int p, double r1s) {
+  return qw::Slots{st->buf[p].R0, st->buf[p ^ 1].Q1, st->buf[p].Q0, st->buf[p].Q1, r1s};
+}
+qw::Slots view(const qw_state* st) { return view(st, st->cur, st->r1s); }
+
+// A walk step leaves the next R1 as -Q1 of the input, the swap as +Q1.
+double r1s_after(int mode) { return mode == qw::kStep ? -1.0 : 1.0; }
+
 qw::StepArgs step_args(qw_state* st, int mode, double2* yacc, const double* coefm) {
   qw::StepArgs a;
   a.m = st->ctx->mat();
-  a.in = st->buf[st->cur];
-  a.out = st->buf[st->cur ^ 1];
+  a.in = view(st);
+  a.out = view(st, st->cur ^ 1, r1s_after(mode));
   a.L = st->L;
   a.acc = st->acc;
   a.stepno = st->stepno;
@@ -190,6 +202,7 @@ int launch_one(qw_state* st, int mode, hipStream_t stream, double2* yacc = nullp
   qw::StepArgs a = step_args(st, mode, yacc, coefm);
   QW_HIP(qw::launch_step(a, step_grid(st), st->block, stream));
   st->cur ^= 1;
+  st->r1s = r1s_after(mode);
   ++st->launches;
   return QW_OK;
 }
@@ -197,10 +210,20 @@ int launch_one(qw_state* st, int mode, hipStream_t stream, double2* yacc = nullp
 // Run `n` walk steps (with the solver's fused projection when yacc is set),
 // replaying a captured graph of kGraphSteps launches when a stream is given.
 int run_steps(qw_state* st, int64_t n, hipStream_t stream, double2* yacc = nullptr, const double* coefm = nullptr) {
-  if (stream != nullptr && n >= kGraphSteps) {
+  // A captured graph is replayed back to back, so it must start from the R1
+  // sign its own steps leave: a state fresh from preparation, import or the
+  // swap takes its first step directly.
+  if (stream != nullptr && n > kGraphSteps && st->r1s != r1s_after(qw::kStep)) {
+    int rc = launch_one(st, qw::kStep, stream, yacc, coefm);
+    if (rc) return rc;
+    --n;
+  }
+  if (stream != nullptr && n >= kGraphSteps && st->r1s == r1s_after(qw::kStep)) {
     GraphEntry* ge = nullptr;
     for (auto& g : st->graphs)
-      if (g.stream == stream && g.parity == st->cur && g.steps == kGraphSteps && yacc == nullptr) ge = &g;
+      if (g.stream == stream && g.parity == st->cur && g.r1s == st->r1s && g.steps == kGraphSteps &&
+          yacc == nullptr)
+        ge = &g;
     hipGraphExec_t exec = nullptr;
     if (ge) {
       exec = ge->exec;
@@ -208,14 +231,17 @@ int run_steps(qw_state* st, int64_t n, hipStream_t stream, double2* yacc = nullp
       hipGraph_t graph;
       QW_HIP(hipStreamBeginCapture(stream, hipStreamCaptureModeThreadLocal));
       const int cur0 = st->cur;
+      const double r1s0 = st->r1s;
       for (int i = 0; i < kGraphSteps; ++i) {
         qw::StepArgs a = step_args(st, qw::kStep, yacc, coefm);
         hipError_t e = qw::launch_step(a, step_grid(st), st->block, stream);
         st->cur ^= 1;
+        st->r1s = r1s_after(qw::kStep);
         if (e != hipSuccess) {
           hipGraph_t dummy;
           (void)hipStreamEndCapture(stream, &dummy);
           st->cur = cur0;
+          st->r1s = r1s0;
           return set_err(QW_EDEVICE, std::string("step capture: ") + hipGetErrorString(e));
         }
       }
@@ -223,11 +249,12 @@ int run_steps(qw_state* st, int64_t n, hipStream_t stream, double2* yacc = nullp
       hipError_t e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
       (void)hipGraphDestroy(graph);
       if (e != hipSuccess) return set_err(QW_EDEVICE, std::string("graph instantiate: ") + hipGetErrorString(e));
-      if (yacc == nullptr) st->graphs.push_back({stream, cur0, kGraphSteps, exec});
+      if (yacc == nullptr) st->graphs.push_back({stream, cur0, r1s0, kGraphSteps, exec});
     }
     const int64_t reps = n / kGraphSteps;
     for (int64_t r = 0; r < reps; ++r) QW_HIP(hipGraphLaunch(exec, stream));
     st->launches += reps * kGraphSteps;
+    st->r1s = r1s_after(qw::kStep);  // the parity is back where it was (kGraphSteps is even)
     if (yacc != nullptr) {
       QW_HIP(hipStreamSynchronize(stream));
       (void)hipGraphExecDestroy(exec);
@@ -521,10 +548,10 @@ int state_alloc(qw_ctx* ctx, int64_t list_cap, qw_state** out, hipStream_t strea
   ctx->refs.fetch_add(1);
   const size_t pb = sizeof(double2) * ctx->items;  // one plane
   bool ok = true;
-  for (int k = 0; k < 2; ++k) {
-    double2* p = static_cast<double2*>(state_get(st, 4 * pb));
+  for (int k = 0; k < 2; ++k) {  // R0, Q0, Q1 per parity buffer
+    double2* p = static_cast<double2*>(state_get(st, 3 * pb));
     ok = ok && p;
-    st->buf[k] = p ? qw::Slots{p, p + ctx->items, p + 2 * ctx->items, p + 3 * ctx->items} : qw::Slots{};
+    st->buf[k] = p ? qw::Slots{p, nullptr, p + ctx->items, p + 2 * ctx->items, 1.0} : qw::Slots{};
   }
   st->acc = static_cast<unsigned long long*>(state_get(st, sizeof(unsigned long long) * qw::kMaxGrid));
   st->stepno = static_cast<uint32_t*>(state_get(st, sizeof(uint32_t) * qw::kMaxWaves));
@@ -537,7 +564,7 @@ int state_alloc(qw_ctx* ctx, int64_t list_cap, qw_state** out, hipStream_t strea
     return set_err(QW_ENOMEM, "device allocation failed for the state");
   }
   hipError_t e = hipSuccess;
-  for (int k = 0; k < 2 && e == hipSuccess; ++k) e = qw::launch_fill(st->buf[k].R0, int64_t(4 * pb), stream);
+  for (int k = 0; k < 2 && e == hipSuccess; ++k) e = qw::launch_fill(st->buf[k].R0, int64_t(3 * pb), stream);
   if (e == hipSuccess) e = qw::launch_fill(st->acc, sizeof(unsigned long long) * qw::kMaxGrid, stream);
   if (e == hipSuccess) e = qw::launch_fill(st->stepno, sizeof(uint32_t) * qw::kMaxWaves, stream);
   if (e == hipSuccess) e = qw::launch_fill(st->b, sizeof(double2) * ctx->jtotal, stream);
@@ -551,9 +578,10 @@ int state_alloc(qw_ctx* ctx, int64_t list_cap, qw_state** out, hipStream_t strea
 
 // Empty the state: both parities cleared, list emptied.
 int state_clear(qw_state* st, hipStream_t stream) {
-  const int64_t sb = int64_t(sizeof(double2)) * 4 * st->ctx->items;  // the four planes, contiguous
+  const int64_t sb = int64_t(sizeof(double2)) * 3 * st->ctx->items;  // the three planes, contiguous
   for (int k = 0; k < 2; ++k) QW_HIP(qw::launch_fill(st->buf[k].R0, sb, stream));
   st->cur = 0;
+  st->r1s = 1.0;
   st->L.cnt = 0;
   return QW_OK;
 }
@@ -575,8 +603,8 @@ int import_branches(qw_state* st, const std::vector<uint64_t>& keys, const std::
   if (e == hipSuccess) e = hipMemcpyAsync(da, amps.data(), sizeof(double2) * m, hipMemcpyHostToDevice, stream);
   if (e == hipSuccess) e = qw::launch_fill(dc, 256, stream);
   if (e == hipSuccess)
-    e = qw::launch_import(ctx->mat(), static_cast<uint64_t*>(dk), static_cast<double2*>(da), m, st->buf[st->cur],
-                          st->L, static_cast<uint32_t*>(dc), stream);
+    e = qw::launch_import(ctx->mat(), static_cast<uint64_t*>(dk), static_cast<double2*>(da), m, view(st), st->L,
+                          static_cast<uint32_t*>(dc), stream);
   if (e == hipSuccess) e = hipMemcpyAsync(&lcnt, dc, sizeof(uint32_t), hipMemcpyDeviceToHost, stream);
   if (e == hipSuccess) e = hipStreamSynchronize(stream);
   ctx->alloc.put(dk);
@@ -589,7 +617,9 @@ int import_branches(qw_state* st, const std::vector<uint64_t>& keys, const std::
   return QW_OK;
 }
 
-// Validate keys against the context's layout; merge equal keys; drop zeros.
+// Validate keys against the context's layout; merge equal keys; drop the
+// branches at or below the pruning threshold, as every step does (a branch
+// stored as R1's source is not pruned again when the next step reads it).
 int canonical_branches(const qw_ctx* ctx, const uint64_t* keys, const double* re, const double* im, int64_t m,
                        std::vector<uint64_t>& ok, std::vector<double2>& oa) {
   const int n = ctx->nbits;
@@ -621,7 +651,7 @@ int canonical_branches(const qw_ctx* ctx, const uint64_t* keys, const double* re
   }
   size_t w = 0;
   for (size_t r = 0; r < ok.size(); ++r)
-    if (oa[r].x != 0.0 || oa[r].y != 0.0) {
+    if (std::fabs(oa[r].x) > qw::kTau || std::fabs(oa[r].y) > qw::kTau) {
       ok[w] = ok[r];
       oa[w] = oa[r];
       ++w;
@@ -633,7 +663,7 @@ int canonical_branches(const qw_ctx* ctx, const uint64_t* keys, const double* re
 
 int measure_partials(qw_state* st, int kind, double* result, hipStream_t stream) {
   const int grid = 256;
-  QW_HIP(qw::launch_measure(st->ctx->mat(), st->buf[st->cur], st->L, kind, st->mbuf, nullptr, grid, stream));
+  QW_HIP(qw::launch_measure(st->ctx->mat(), view(st), st->L, kind, st->mbuf, nullptr, grid, stream));
   std::vector<double> h(grid);
   QW_HIP(hipMemcpyAsync(h.data(), st->mbuf, sizeof(double) * grid, hipMemcpyDeviceToHost, stream));
   QW_HIP(hipStreamSynchronize(stream));
@@ -775,7 +805,7 @@ int qw_state_init(qw_state** out, qw_ctx* ctx, const double* b_re, const double*
       return rc;
     }
   } else {
-    e = qw::launch_init(ctx->mat(), st->b, st->buf[0], qw::kTau, stream);
+    e = qw::launch_init(ctx->mat(), st->b, view(st), qw::kTau, stream);  // a fresh state: buffer 0, r1s = +1
     if (e != hipSuccess) {
       qw_state_free(st);
       return set_err(QW_EDEVICE, std::string("init: ") + hipGetErrorString(e));
@@ -857,7 +887,7 @@ int qw_measure(qw_state* st, int32_t kind, void* out, int64_t out_len, void* str
       const int64_t need = kind == QW_J_MARGINAL ? ctx->jtotal : 2 * ctx->jtotal;
       if (out_len < need) return set_err(QW_EINVAL, "out_len too small");
       QW_HIP(qw::launch_fill(st->mbuf, (sizeof(double) * need + 15) / 16 * 16, stream));
-      QW_HIP(qw::launch_measure(ctx->mat(), st->buf[st->cur], st->L, kind == QW_J_MARGINAL ? 2 : 3, nullptr,
+      QW_HIP(qw::launch_measure(ctx->mat(), view(st), st->L, kind == QW_J_MARGINAL ? 2 : 3, nullptr,
                                 st->mbuf, 256, stream));
       QW_HIP(hipMemcpyAsync(out, st->mbuf, sizeof(double) * need, hipMemcpyDeviceToHost, stream));
       QW_HIP(hipStreamSynchronize(stream));
@@ -904,7 +934,7 @@ int qw_export(qw_state* st, uint64_t* keys, double* re, double* im, int64_t cap,
   hipError_t e = (dk && da && dc) ? hipSuccess : hipErrorOutOfMemory;
   if (e == hipSuccess) e = qw::launch_fill(dc, 256, stream);
   if (e == hipSuccess)
-    e = qw::launch_export(ctx->mat(), st->buf[st->cur], st->L, static_cast<uint64_t*>(dk),
+    e = qw::launch_export(ctx->mat(), view(st), st->L, static_cast<uint64_t*>(dk),
                           static_cast<double2*>(da), static_cast<uint32_t*>(dc), uint32_t(count), stream);
   if (e == hipSuccess) e = hipMemcpyAsync(&got, dc, sizeof(uint32_t), hipMemcpyDeviceToHost, stream);
   if (e == hipSuccess) e = hipMemcpyAsync(hk.data(), dk, sizeof(uint64_t) * count, hipMemcpyDeviceToHost, stream);
@@ -1038,17 +1068,17 @@ int qw_grad(qw_state* st, const double* w, int32_t nsteps, double* dvals, double
   if (e == hipSuccess) {
     rc = launch_one(st, qw::kSwap, stream);
     if (!rc)
-      e = qw::launch_weight(mm, st->buf[st->cur], st->L, lam->buf[0], lam->L, dw, st->mbuf, 256, stream);
+      e = qw::launch_weight(mm, view(st), st->L, view(lam), lam->L, dw, st->mbuf, 256, stream);
   }
   if (e == hipSuccess && !rc)
     e = hipMemcpyAsync(part.data(), st->mbuf, sizeof(double) * 256, hipMemcpyDeviceToHost, stream);
   for (int32_t t = nsteps; t >= 1 && e == hipSuccess && !rc; --t) {
     qw::AdjArgs a;
     a.m = mm;
-    a.in = st->buf[st->cur];
-    a.out = st->buf[st->cur ^ 1];
-    a.lin = lam->buf[lam->cur];
-    a.lout = lam->buf[lam->cur ^ 1];
+    a.in = view(st);
+    a.out = view(st, st->cur ^ 1, r1s_after(qw::kStep));
+    a.lin = view(lam);
+    a.lout = view(lam, lam->cur ^ 1, r1s_after(qw::kStep));
     a.L = st->L;
     a.LL = lam->L;
     a.acc = st->acc;
@@ -1058,12 +1088,13 @@ int qw_grad(qw_state* st, const double* w, int32_t nsteps, double* dvals, double
     e = qw::launch_adjoint(a, step_grid(st), st->block, stream);
     st->cur ^= 1;
     lam->cur ^= 1;
+    st->r1s = lam->r1s = r1s_after(qw::kStep);
     ++st->launches;
   }
   // back to the unconjugated frame: psi_0 and lambda_0
   if (e == hipSuccess && !rc) rc = launch_one(st, qw::kSwap, stream);
   if (e == hipSuccess && !rc) rc = launch_one(lam, qw::kSwap, stream);
-  if (e == hipSuccess && !rc) e = qw::launch_grad_init(mm, lam->buf[lam->cur], st->b, dv, db, stream);
+  if (e == hipSuccess && !rc) e = qw::launch_grad_init(mm, view(lam), st->b, dv, db, stream);
   if (e == hipSuccess && !rc)
     e = hipMemcpyAsync(hdv.data(), dv, sizeof(double) * ctx->items, hipMemcpyDeviceToHost, stream);
   if (e == hipSuccess && !rc)

@@ -41,12 +41,15 @@ struct Inst {
 //   Q0[h], Q1[h]: key S K(q, b2) = (0, col[q], b2, 0, j, 0)  when it is not
 //                 itself a group member (always for b2 = 1; for b2 = 0 only
 //                 when j is absent from row col[q]); Q0 stays 0 otherwise.
-// Complex double; an exact 0 means "no branch".
+// Complex double; an exact 0 means "no branch".  A state owns R0, Q0 and Q1
+// planes in each of two parity buffers; the view of the state in buffer p
+// takes R1 from buffer 1-p's Q1 plane, which holds r1s * R1 (r1s = +-1).
 struct Slots {
   double2* R0;
   double2* R1;
   double2* Q0;
   double2* Q1;
+  double r1s;  // the R1 plane holds r1s * R1
 };
 
 // Branches outside the span of those keys (imports, raw starts): the walk
@@ -116,12 +119,12 @@ struct AdjArgs {
 // The host side is compiled by the host compiler and the kernels by the GPU
 // compiler; the argument structures must have one layout on both.
 static_assert(sizeof(Inst) == 56 && offsetof(Inst, inv_sqrt_s) == 48, "Inst layout");
-static_assert(sizeof(Slots) == 32, "Slots layout");
+static_assert(sizeof(Slots) == 40 && offsetof(Slots, r1s) == 32, "Slots layout");
 static_assert(sizeof(List) == 24 && offsetof(List, cap) == 20, "List layout");
 static_assert(sizeof(SlotRec) == 16 && offsetof(SlotRec, val) == 8, "SlotRec layout");
 static_assert(sizeof(Matrix) == 152 && offsetof(Matrix, inst0) == 96, "Matrix layout");
-static_assert(sizeof(StepArgs) == 288 && offsetof(StepArgs, coefm) == 280, "StepArgs layout");
-static_assert(sizeof(AdjArgs) == 368 && offsetof(AdjArgs, wpb) == 360, "AdjArgs layout");
+static_assert(sizeof(StepArgs) == 304 && offsetof(StepArgs, coefm) == 296, "StepArgs layout");
+static_assert(sizeof(AdjArgs) == 400 && offsetof(AdjArgs, wpb) == 392, "AdjArgs layout");
 
 // Launchers (qw_launch.cpp).  All enqueue on `stream` and allocate nothing.
 hipError_t launch_step(const StepArgs& a, int grid, int block, hipStream_t stream);

@@ -30,6 +30,11 @@
 // next step:
 //   R0, R1 -> reflection -> Q1_out[h] and R0_out[h'] (or Q0_out[h])
 //   Q1, Q0 -> negation   -> R1_out[h], R0_out[h]
+// R1_out = -Q1_in is never copied: a state keeps three planes per parity
+// buffer, and its R1 is the other buffer's Q1 plane times a sign (+-1) that
+// the state carries (a walk step leaves -1, the swap +1).  So a step writes
+// three planes (R0, Q1 and the fillers' Q0) and reads R1 from the plane it
+// then overwrites with Q1.
 // Every output address receives exactly one write per step (0 when pruned),
 // so there is no atomic, no compaction and no clearing pass; the result is
 // independent of scheduling.  For matrices whose rows share their offset
@@ -325,15 +330,21 @@ __device__ __forceinline__ double block_sum(double v, double* sh) {
   return t;
 }
 
+// Logical R1 amplitude of a home (the plane holds it times r1s = +-1).
+__device__ __forceinline__ double2 r1_of(const Slots& st, int64_t h) { return cscale(st.R1[h], st.r1s); }
+
 // Outputs of one slot for the next step (step and adjoint kernels).
 // o0, o1: reflected (or swapped) group amplitudes of K(q, b2) before S;
-// n1: output of Q1_in; y0: Q0_in (read only for slots without a partner),
-// negated when `neg`.
+// y1: Q1_in, which becomes the next R1 (negated by a walk step, not by the
+// swap) without being moved: the input's Q1 plane is the output's R1
+// storage, and the sign goes with the state; y0: Q0_in (read only for slots
+// without a partner), negated when `neg`.  out.Q1 is in.R1's plane: each
+// lane reads its R1 input before it writes its Q1 output at the same home.
 __device__ __forceinline__ void write_slot(const Slots& in, const Slots& out, int64_t base, int64_t h,
-                                           const SlotRec& rc, double2 o0, double2 o1, double2 n1, bool neg,
+                                           const SlotRec& rc, double2 o0, double2 o1, double2 y1, bool neg,
                                            double tau, unsigned& cnt) {
   out.Q1[h] = prune(o1, tau, cnt);
-  out.R1[h] = prune(n1, tau, cnt);
+  cnt += nonzero(y1);  // pruned when it was written
   if (rc.part >= 0) {
     out.R0[base + rc.part] = prune(o0, tau, cnt);
   } else {
@@ -376,7 +387,7 @@ __device__ __forceinline__ unsigned step_wave(const StepArgs& a, int64_t w, int 
       rc[i] = a.m.rec[h[i]];
       if (CPLX) vi[i] = a.m.vim[h[i]];
       x0[i] = a.in.R0[h[i]];
-      x1[i] = a.in.R1[h[i]];
+      x1[i] = r1_of(a.in, h[i]);
       y1[i] = a.in.Q1[h[i]];
     }
   }
@@ -402,13 +413,12 @@ __device__ __forceinline__ unsigned step_wave(const StepArgs& a, int64_t w, int 
 #pragma unroll
   for (int i = 0; i < SLM; ++i) {
     if (i < sl) {
-      double2 o0 = x0[i], o1 = x1[i], n1 = y1[i];
+      double2 o0 = x0[i], o1 = x1[i];
       if (step) {
         o0 = csub(cmul(tc, r[i].f), x0[i]);
         o1 = csub(cscale(tc, r[i].g), x1[i]);
-        n1 = cneg(y1[i]);
       }
-      write_slot(a.in, a.out, base, h[i], rc[i], o0, o1, n1, step, a.tau, cnt);
+      write_slot(a.in, a.out, base, h[i], rc[i], o0, o1, y1[i], step, a.tau, cnt);
     }
   }
   return cnt;
@@ -537,10 +547,10 @@ __device__ __forceinline__ void adjoint_wave(const AdjArgs& a, int64_t w, int la
       h[i] = base + (int64_t(x.h * sl + i) << x.I.nlog) + x.j;
       rc[i] = a.m.rec[h[i]];
       x0[i] = a.in.R0[h[i]];
-      x1[i] = a.in.R1[h[i]];
+      x1[i] = r1_of(a.in, h[i]);
       y1[i] = a.in.Q1[h[i]];
       m0[i] = a.lin.R0[h[i]];
-      m1[i] = a.lin.R1[h[i]];
+      m1[i] = r1_of(a.lin, h[i]);
       z1[i] = a.lin.Q1[h[i]];
     }
   }
@@ -570,8 +580,8 @@ __device__ __forceinline__ void adjoint_wave(const AdjArgs& a, int64_t w, int la
       const double2 u = cadd(cmul(c, cadd(cjmul(m0[i], dr.f), make_double2(m1[i].x * dr.g, -m1[i].y * dr.g))),
                              cjmul(d, cadd(cjmul(dr.f, q0), cscale(q1, dr.g))));
       a.dv[h[i]] += 2.0 * t * u.x;
-      write_slot(a.in, a.out, base, h[i], rc[i], q0, q1, cneg(y1[i]), true, a.tau, cnt);
-      write_slot(a.lin, a.lout, base, h[i], rc[i], w0, w1, cneg(z1[i]), true, a.tau, lcnt);
+      write_slot(a.in, a.out, base, h[i], rc[i], q0, q1, y1[i], true, a.tau, cnt);
+      write_slot(a.lin, a.lout, base, h[i], rc[i], w0, w1, z1[i], true, a.tau, lcnt);
     }
   }
 }
@@ -624,7 +634,7 @@ extern "C" __global__ void __launch_bounds__(256) qwk_init(Matrix m, const doubl
     if (!kept(o0, tau)) o0 = zero2();
     if (!kept(o1, tau)) o1 = zero2();
     out.R0[it] = o0;
-    out.R1[it] = o1;
+    out.R1[it] = cscale(o1, out.r1s);
   }
 }
 
@@ -652,7 +662,7 @@ extern "C" __global__ void __launch_bounds__(256) qwk_measure(Matrix m, Slots st
       const Home x = home_item(m, it, it - (threadIdx.x & (kWave - 1)));
       if (x.live) {
         v[0] = st.R0[it];
-        v[1] = st.R1[it];
+        v[1] = r1_of(st, it);
         v[2] = st.Q0[it];
         v[3] = st.Q1[it];
       }
@@ -681,7 +691,7 @@ extern "C" __global__ void __launch_bounds__(256) qwk_measure_rows(Matrix m, Slo
       double2 c = zero2();
       for (int l = 0; l < x.I.s; ++l) {
         const int64_t h = home(x.I, x.j, l);
-        const double2 p0 = st.R0[h], p1 = st.R1[h];
+        const double2 p0 = st.R0[h], p1 = r1_of(st, h);
         if (kind == 2) {
           p += norm2(p0) + norm2(p1);
           const double sw = norm2(st.Q0[h]) + norm2(st.Q1[h]);
@@ -752,7 +762,7 @@ extern "C" __global__ void __launch_bounds__(256) qwk_export(Matrix m, Slots st,
       if (x.live) {
         const int colq = m.rec[it].col;
         v[0] = st.R0[it];
-        v[1] = st.R1[it];
+        v[1] = r1_of(st, it);
         v[2] = st.Q0[it];
         v[3] = st.Q1[it];
         for (int b2 = 0; b2 < 2; ++b2) {
@@ -817,7 +827,7 @@ extern "C" __global__ void __launch_bounds__(256) qwk_import(Matrix m, const uin
       if (h == 0)
         out.R0[idx] = v[0];
       else if (h == 1)
-        out.R1[idx] = v[0];
+        out.R1[idx] = cscale(v[0], out.r1s);
       else if (h == 2)
         out.Q0[idx] = v[0];
       else if (h == 3)
@@ -849,10 +859,10 @@ extern "C" __global__ void __launch_bounds__(256) qwk_weight(Matrix m, Slots in,
       if (x.live) {
         const double wr = w[x.I.jbase + m.rec[it].col];
         const double wq = w[x.I.jbase + x.j];
-        const double2 p0 = in.R0[it], p1 = in.R1[it], s0 = in.Q0[it], s1 = in.Q1[it];
+        const double2 p0 = in.R0[it], p1 = r1_of(in, it), s0 = in.Q0[it], s1 = in.Q1[it];
         acc += wr * (norm2(p0) + norm2(p1)) + wq * (norm2(s0) + norm2(s1));
         out.R0[it] = cscale(p0, wr);
-        out.R1[it] = cscale(p1, wr);
+        out.R1[it] = cscale(p1, wr * out.r1s);
         out.Q0[it] = cscale(s0, wq);
         out.Q1[it] = cscale(s1, wq);
       }
@@ -887,7 +897,7 @@ extern "C" __global__ void __launch_bounds__(256) qwk_grad_init(Matrix m, Slots 
     double2 c = zero2();
     for (int l = 0; l < x.I.s; ++l) {
       const int64_t h = home(x.I, x.j, l);
-      const double2 n0 = lam.R0[h], n1 = lam.R1[h];
+      const double2 n0 = lam.R0[h], n1 = r1_of(lam, h);
       const SlotRec rc = m.rec[h];
       const Rot d = rotation_deriv(rc.val, x.j, rc.col);
       const double2 u = cmul(bj, cadd(cjmul(n0, d.f), make_double2(n1.x * d.g, -n1.y * d.g)));

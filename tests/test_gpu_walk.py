@@ -235,6 +235,36 @@ def test_graph_replay_matches_direct(Q):
     assert np.array_equal(ka, kc) and np.array_equal(aa, ac)
 
 
+def test_graph_replay_after_swap_and_import(Q):
+    """A state whose R1 storage has the swap's sign (after W^dagger) or an
+    imported state enters a long graph-replayed run; both equal direct
+    launches bitwise."""
+    csc = W.offset_matrix(512, 8, seed=28)
+    b = W.gaussian_b(512, seed=29)
+    walk = Q.Walk(csc)
+    a = walk.state(b).step(5)
+    c = walk.state(b).step(5)
+    a.step_adjoint(20)
+    for _ in range(20):
+        c.step_adjoint(1)  # the swaps around each step cancel exactly
+    a.step(48)
+    for _ in range(48):
+        c.step(1)
+    ka, aa = a.export()
+    kc, ac = c.export()
+    assert np.array_equal(ka, kc) and np.array_equal(aa, ac)
+    d = walk.state(b)
+    d.import_(ka, aa)
+    d.step(48)
+    e = walk.state(b)
+    e.import_(ka, aa)
+    for _ in range(48):
+        e.step(1)
+    kd, ad = d.export()
+    ke, ae = e.export()
+    assert np.array_equal(kd, ke) and np.array_equal(ad, ae)
+
+
 @pytest.mark.parametrize("n,c", [(2048, 8), (512, 16), (256, 3)])
 def test_launch_shapes_agree(Q, oracle_mod, n, c):
     """The one-pass kernel compiled for the matrix's s (default shape) and the
