@@ -1,7 +1,8 @@
 """MI355X quantum-walk library: Python binding of libqw.so.
 
 The walk of arXiv:2303.06890 (W = S T~ P T~^dagger on the registers
-j_c, j, b1, k_c, k, b2 of a sparse symmetric matrix stored in QRAM) runs in
+j_c, j, b1, k_c, k, b2 of a sparse symmetric or complex Hermitian matrix
+stored in QRAM) runs in
 hand-written HIP kernels behind the C ABI of include/qw.h.  This module only
 marshals arguments: torch provides device memory (through the allocator
 hooks) and the current stream; every step of the walk runs in the library.
