@@ -273,6 +273,34 @@ def max_size_leg(Q, W, steps: int = 50, oracle_steps: int = 10):
     return out
 
 
+def solver_leg(Q, W):
+    """The walk-based CKS solve of the 32 x 32 five-point Laplacian + 0.1 I
+    (kappa of A/s from the matrix's spectrum, eps = 1e-3): walk steps, wall
+    time of the whole solve on the library's stream, fidelity against LU."""
+    import numpy as np
+
+    csc, b = W.solver_problem()
+    walk = Q.Walk(csc)
+    info = walk.info[0]
+    H = csc.dense() * info["scale"] / info["s"]
+    kappa = 1.0 / np.abs(np.linalg.eigvalsh(H)).min()
+    walk.qls(b, kappa, eps=1e-3)  # warm: kernels loaded, allocator primed
+    t0 = time.perf_counter()
+    y, p_succ, steps = walk.qls(b, kappa, eps=1e-3)
+    dt = time.perf_counter() - t0
+    x = np.linalg.solve(H, b)
+    fid = abs(np.vdot(x, y)) ** 2 / (np.vdot(x, x).real * np.vdot(y, y).real)
+    return {
+        "workload": "5-point Laplacian 32x32 + 0.1 I, b = normalised Gaussian (seed 0), eps = 1e-3",
+        "kappa": kappa,
+        "walk_steps": steps,
+        "solve_ms": dt * 1e3,
+        "us_per_walk_step": dt * 1e6 / steps,
+        "fidelity_vs_lu": fid,
+        "p_succ": p_succ,
+    }
+
+
 def adjoint_leg(Q, W, steps: int = 20, reps: int = 5):
     """Gradient of the total probability of 32 column outcomes after 20 steps
     on G(1024, 8) w.r.t. all 8192 values and b (forward walk + reverse sweep
@@ -311,11 +339,11 @@ def main():
     ap.add_argument("--warmup", type=int, default=64)
     ap.add_argument("--cpu-steps", type=int, default=5, help="walk steps of the oracle sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-extras", action="store_true", help="skip the batched, adjoint, complex, paper-shape and branch-count legs")
+    ap.add_argument("--no-extras", action="store_true", help="skip the batched, adjoint, solver, complex, paper-shape and branch-count legs")
     ap.add_argument("--no-tune", action="store_true", help="keep the default launch shape")
     ap.add_argument("--launch", default=None, metavar="WG,GRID",
                     help="fixed launch shape of the main leg (workgroup size, workgroups)")
-    ap.add_argument("--only", choices=["batched", "adjoint", "table1", "complex", "max_size"], default=None,
+    ap.add_argument("--only", choices=["batched", "adjoint", "table1", "complex", "max_size", "solver"], default=None,
                     help="run one extra leg alone (for profiling) and print its JSON")
     ap.add_argument("--pmc-run", action="store_true",
                     help="counter run: a torch copy of 64 MiB (byte calibration), then 64 walk steps of "
@@ -361,6 +389,9 @@ def main():
         return
     if args.only == "adjoint":
         print(json.dumps(adjoint_leg(Q, W)), flush=True)
+        return
+    if args.only == "solver":
+        print(json.dumps(solver_leg(Q, W)), flush=True)
         return
     if args.only == "max_size":
         print(json.dumps(max_size_leg(Q, W)), flush=True)
@@ -442,6 +473,8 @@ def main():
         print(f"[bench] batched: {line['batched']}", file=sys.stderr, flush=True)
         line["adjoint"] = adjoint_leg(Q, W)
         print(f"[bench] adjoint: {line['adjoint']}", file=sys.stderr, flush=True)
+        line["solver"] = solver_leg(Q, W)
+        print(f"[bench] solver: {line['solver']}", file=sys.stderr, flush=True)
         line["complex"] = complex_leg(Q, W, autotune, not args.no_tune)
         print(f"[bench] complex: {line['complex']}", file=sys.stderr, flush=True)
         line["table1_shapes"] = table1_leg(Q, W, autotune, not args.no_tune)
