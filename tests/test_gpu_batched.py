@@ -115,6 +115,26 @@ def test_batched_mixed_row_lengths(Q, oracle_mod, kind):
         compare_states(gk, ga, ok, oa, where=f"{kind} instance {i}")
 
 
+def test_batched_workload_256_sampled_vs_oracle(Q, oracle_mod):
+    """The 256-instance workload after 50 graph-replayed steps: sampled
+    instances (the two with the fewest slots and those at the first quartile
+    and the median of the slot count, which the oracle finishes in seconds)
+    match the oracle."""
+    inst = W.batched_instances()
+    walk = Q.Walk([a for a, _ in inst])
+    st = walk.state([b for _, b in inst]).step(50)
+    keys, amps = st.export()
+    F = unpack(keys, walk.nbits)
+    sizes = [d["N"] * d["s"] for d in walk.info]
+    order = sorted(range(len(inst)), key=lambda k: sizes[k])
+    for i in order[:2] + [order[len(order) // 4], order[len(order) // 2]]:
+        a, b = inst[i]
+        om = oracle_mod.OracleMatrix(a)
+        ok, oa = oracle_mod.OracleState(om).set_b(b).T().step(50).export()
+        gk, ga = _slice(F, amps, i, om.nbits)
+        compare_states(gk, ga, ok, oa, where=f"instance {i}")
+
+
 def test_batched_workload_256(Q):
     """The 256-instance workload (n in 64..4096, 4..16 entries per column,
     single-column starts, 50 graph-replayed steps): every instance keeps unit

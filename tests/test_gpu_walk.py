@@ -208,16 +208,35 @@ def test_general_list_branches(Q, oracle_mod):
     _check(st, ost, "list adjoint")
 
 
-def test_paper_scale_5_steps(Q, oracle_mod):
-    """The benchmark's workload: G(16384, 8), uniform b, 5 steps, full parity."""
+@pytest.fixture(scope="module")
+def paper_scale_oracle(oracle_mod):
+    """Oracle exports of the benchmark's workload after 0 ... 5 steps."""
     csc, b = W.paper_scale()
-    walk, st, ost = _pair(Q, oracle_mod, csc, b)
-    _check(st, ost, "16384 init")
-    for t in range(1, 6):
-        st.step(1)
+    ost = oracle_mod.OracleState(oracle_mod.OracleMatrix(csc)).set_b(b).T()
+    out = [ost.export()]
+    for _ in range(5):
         ost.step(1)
-        _check(st, ost, f"16384 step {t}")
-    assert st.count() == ost.count() <= 4 * 16384 * 8
+        assert ost.ambiguous() == 0
+        out.append(ost.export())
+    return out
+
+
+@pytest.mark.parametrize("shape", [None, (128, 1024), (64, 2048), (256, 64)])
+def test_paper_scale_5_steps(Q, paper_scale_oracle, shape):
+    """The benchmark's workload: G(16384, 8), uniform b, 5 steps, full parity,
+    at the default launch shape, the shapes the tuner picks on this part
+    (one pass) and a striding one."""
+    csc, b = W.paper_scale()
+    st = Q.Walk(csc).state(b)
+    if shape:
+        st.set_launch(*shape)
+    for t in range(6):
+        if t:
+            st.step(1)
+        gk, ga = st.export()
+        ok, oa = paper_scale_oracle[t]
+        compare_states(gk, ga, ok, oa, where=f"16384 step {t} shape {shape}")
+    assert st.count() <= 4 * 16384 * 8
 
 
 def test_graph_replay_matches_direct(Q):
