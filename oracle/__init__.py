@@ -71,7 +71,11 @@ def _load():
         "orc_project0": (ctypes.c_int, [P, dp, dp]),
         "orc_schedule": (None, [dbl, dbl, i64p, ip]),
         "orc_cks_coeffs": (None, [i64, i32, dp]),
-        "orc_cheb_series": (None, [P, dp, dp, i32, i32, dp, dp, dp]),
+        "orc_cheb_series": (ctypes.c_int, [P, dp, dp, i32, i32, dp, dp, dp]),
+        "orc_matrix_set_word": (ctypes.c_int, [P, i32]),
+        "orc_fx_sqrt": (u64, [u64, i32]),
+        "orc_fx_arccos": (u64, [u64, i32]),
+        "orc_fx_rotation": (None, [u64, i32, u64, u64, dp, dp, dp]),
         "orc_qls_walk": (ctypes.c_int, [P, dp, i32, i32, dp, dbl, dp, dp]),
         "orc_grad": (ctypes.c_int, [P, dp, dp, i32, i32, dp, dbl, dp, dp, dp, dp]),
     }
@@ -98,14 +102,34 @@ def _check(rc):
         raise RuntimeError("oracle: " + _load().orc_last_error().decode())
 
 
+def fx_sqrt(q: int, w: int) -> int:
+    """The fixed-point square-root register for the word magnitude q."""
+    return int(_load().orc_fx_sqrt(int(q), int(w)))
+
+
+def fx_arccos(r: int, w: int) -> int:
+    """The fixed-point angle register (units of (pi/2) / 2^w) for r / 2^w."""
+    return int(_load().orc_fx_arccos(int(r), int(w)))
+
+
+def fx_rotation(word: int, w: int, j: int, k: int):
+    """(f, g) of the rotation for the sign-magnitude fixed-point QRAM word."""
+    fr, fi, g = ctypes.c_double(), ctypes.c_double(), ctypes.c_double()
+    _load().orc_fx_rotation(int(word), int(w), int(j), int(k), ctypes.byref(fr), ctypes.byref(fi),
+                            ctypes.byref(g))
+    return complex(fr.value, fi.value), g.value
+
+
 # operation codes for OracleState.apply_op
 OP_H, OP_OA, OP_OS, OP_OSINV, OP_R, OP_RDAG, OP_P, OP_S = range(8)
 
 
 class OracleMatrix:
-    """Preprocessed matrix (rescale, pow2 s, zero fill, pow2 N)."""
+    """Preprocessed matrix (rescale, pow2 s, zero fill, pow2 N).  word > 0:
+    the scaled values are fixed-point numbers of that word length and the
+    rotation is computed in fixed point."""
 
-    def __init__(self, csc, scale: float = 0.0):
+    def __init__(self, csc, scale: float = 0.0, word: int = 0):
         lib = _load()
         cp, cpp = _i(csc.colptr)
         ri, rip = _i(csc.rowidx)
@@ -120,6 +144,9 @@ class OracleMatrix:
         lib.orc_matrix_info(self._h, ctypes.byref(N), ctypes.byref(s), ctypes.byref(nb), ctypes.byref(sc))
         self.N, self.s, self.nbits, self.scale = N.value, s.value, nb.value, sc.value
         self.n = csc.n
+        self.word = int(word)
+        if self.word:
+            _check(lib.orc_matrix_set_word(self._h, self.word))
 
     def __del__(self):
         if getattr(self, "_h", None) and _lib is not None:
@@ -148,7 +175,7 @@ class OracleMatrix:
         bi, bip = _d(np.imag(b) if np.iscomplexobj(b) else np.zeros(b.shape[0]))
         coef, cp = _d(coef)
         yr, yi = np.zeros(self.N), np.zeros(self.N)
-        _load().orc_cheb_series(self._h, brp, bip, br.shape[0], int(j0), cp, _d(yr)[1], _d(yi)[1])
+        _check(_load().orc_cheb_series(self._h, brp, bip, br.shape[0], int(j0), cp, _d(yr)[1], _d(yi)[1]))
         return yr + 1j * yi if (self.complex or np.iscomplexobj(b)) else yr
 
     def qls_walk(self, b, j0: int, coef, tau: float = TAU):

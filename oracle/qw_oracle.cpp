@@ -40,6 +40,13 @@
 //     the smallest row indices missing from that column, with value 0.
 //   * s = 2^ceil(log2 max nnz per column) (Table I, note b); N is padded to a
 //     power of two with empty columns; register width n = log2 N.
+//   * Fixed-point data of word length w (Sec. V.B; appendix table of basic
+//     operations): a value is +-q / 2^w with 0 <= q < 2^w; the QRAM word is
+//     sign-magnitude; the square-root register holds floor(sqrt(q / 2^w) 2^w)
+//     (truncation), the angle register the nearest integer t to
+//     arccos(r / 2^w) / (pi/2) * 2^w, and the rotation is by theta =
+//     t (pi/2) / 2^w: f = cos(theta) (with the +-i rule for a negative word),
+//     g = sin(theta).
 #include <algorithm>
 #include <cmath>
 #include <complex>
@@ -82,6 +89,10 @@ struct Matrix {
   std::vector<double> vim;    // N*s, imaginary part (all zero for a real matrix)
   std::vector<uint8_t> real;  // N*s, 1 for a stored entry, 0 for filler
   bool complex_values = false;
+  // Fixed-point data (word > 0): slot q's QRAM word is words[q], the sign in
+  // bit 63 and the magnitude q' of the value +-q' / 2^word in the low bits.
+  int32_t word = 0;
+  std::vector<uint64_t> words;
 };
 
 std::string g_err;
@@ -147,10 +158,15 @@ void per_branch(State& st, F f) {
 }
 
 // O_A' (Alg. 3): A ^= word(a_{j,l}) where register k holds the slot l (for
-// a complex value, both words: real part into A, imaginary part into A2).
+// a complex value, both words: real part into A, imaginary part into A2; for
+// fixed-point data, the sign-magnitude fixed-point word).
 void op_OA(State& st, const Matrix& m) {
   per_branch(st, [&](Reg& r, cplx&) {
     if (r.k >= uint64_t(m.s) || r.j >= uint64_t(m.N)) fail("O_A' address outside the row");
+    if (m.word > 0) {
+      r.A ^= m.words[r.j * m.s + r.k];
+      return;
+    }
     r.A ^= bits_of(m.val[r.j * m.s + r.k]);
     r.A2 ^= bits_of(m.vim[r.j * m.s + r.k]);
   });
@@ -285,6 +301,54 @@ Rot rotation_deriv(double a, uint64_t j, uint64_t k) {
   return d;
 }
 
+// ---- fixed-point rotation (Sec. V.B: values are fixed-point numbers of a
+// given word length; appendix table of basic operations: the conditional
+// rotation is computed with a fixed-point square root, a fixed-point arccos
+// and a rotation by a fixed-point angle) --------------------------------------
+
+// floor(sqrt(x)) for any 64-bit x.
+uint64_t isqrt64(uint64_t x) {
+  uint64_t r = uint64_t(std::sqrt((long double)x));
+  while (r > 0 && (unsigned __int128)r * r > x) --r;
+  while ((unsigned __int128)(r + 1) * (r + 1) <= x) ++r;
+  return r;
+}
+
+// The square-root register: sqrt(q / 2^w) truncated to w fraction bits, as an
+// integer in [0, 2^w).
+uint64_t fx_sqrt(uint64_t q, int w) { return isqrt64(q << w); }
+
+// The angle register: arccos of the fixed-point r / 2^w in units of
+// (pi/2) / 2^w, rounded to the nearest integer (0 ... 2^w).
+uint64_t fx_arccos(uint64_t r, int w) {
+  const double x = double(r) / double(uint64_t(1) << w);
+  return uint64_t(std::nearbyint(std::acos(x) * (double(uint64_t(1) << (w + 1)) / M_PI)));
+}
+
+// cos and sin of the angle t (pi/2) / 2^w, exact at 0 and pi/2 and taken
+// from the nearer end of the quarter turn otherwise.
+void quarter_cos_sin(uint64_t t, int w, double& c, double& sn) {
+  const uint64_t full = uint64_t(1) << w;
+  const auto ang = [&](uint64_t u) { return (M_PI / 2.0) * (double(u) / double(full)); };
+  c = t == full ? 0.0 : (2 * t <= full ? std::cos(ang(t)) : std::sin(ang(full - t)));
+  sn = t == 0 ? 0.0 : (2 * t >= full ? std::cos(ang(full - t)) : std::sin(ang(t)));
+}
+
+// Rotation amplitudes for the fixed-point word A (sign bit 63, magnitude in
+// the low w bits) held by row j at column k: theta = the angle register, f =
+// cos(theta) (times +-i for a negative word, by the rule of the real case),
+// g = sin(theta).
+Rot rotation_fixed(uint64_t A, int w, uint64_t j, uint64_t k) {
+  const uint64_t q = A & ((uint64_t(1) << w) - 1);
+  const bool neg = (A >> 63) != 0;
+  double c, sn;
+  quarter_cos_sin(fx_arccos(fx_sqrt(q, w), w), w, c, sn);
+  Rot r;
+  r.f = !neg ? cplx(c, 0.0) : ((j <= k) ? cplx(0.0, c) : cplx(0.0, -c));
+  r.g = sn;
+  return r;
+}
+
 // 2x2 matrix [[m00, m01], [m10, m11]] of R (dagger=false) or R^dagger.
 void rot_matrix(const Rot& r, bool dagger, cplx M[2][2]) {
   if (!dagger) {
@@ -301,7 +365,7 @@ void rot_matrix(const Rot& r, bool dagger, cplx M[2][2]) {
 }
 
 // Conditional rotation on b2 controlled by the A register (value), j and k.
-void op_CR(State& st, bool dagger) {
+void op_CR(State& st, const Matrix& m, bool dagger) {
   std::map<Reg, std::pair<cplx, cplx>> groups;
   for (auto& kv : st) {
     Reg g = kv.first;
@@ -313,7 +377,8 @@ void op_CR(State& st, bool dagger) {
   State out;
   for (auto& gv : groups) {
     const Reg& g = gv.first;
-    const Rot r = rotation(double_of(g.A), double_of(g.A2), g.j, g.k);
+    const Rot r = m.word > 0 ? rotation_fixed(g.A, m.word, g.j, g.k)
+                             : rotation(double_of(g.A), double_of(g.A2), g.j, g.k);
     cplx M[2][2];
     rot_matrix(r, dagger, M);
     const cplx v0 = gv.second.first, v1 = gv.second.second;
@@ -376,8 +441,8 @@ void apply(State& st, const Matrix& m, Op o) {
     case OA: op_OA(st, m); break;
     case OS: op_OS(st, m); break;
     case OSINV: op_OSinv(st, m); break;
-    case CR: op_CR(st, false); break;
-    case CRDAG: op_CR(st, true); break;
+    case CR: op_CR(st, m, false); break;
+    case CRDAG: op_CR(st, m, true); break;
     case P: op_P(st); break;
     case S: op_S(st); break;
   }
@@ -559,6 +624,27 @@ void* orc_matrix_new(int32_t n, const int32_t* colptr, const int32_t* rowidx, co
   return m;
 }
 
+// Switch a real matrix to fixed-point data of word length w (1 ... 32): every
+// scaled value must be +-q / 2^w with an integer 0 <= q < 2^w (the paper's
+// elements are fixed-point numbers below 1 in magnitude); its QRAM word is
+// the sign in bit 63 and q in the low w bits.
+int orc_matrix_set_word(void* p, int32_t w) {
+  Matrix* m = static_cast<Matrix*>(p);
+  return guarded([&] {
+    if (w < 1 || w > 32) fail("word length must be 1 ... 32");
+    if (m->complex_values) fail("fixed-point data is defined for real matrices only");
+    const double full = double(uint64_t(1) << w);
+    std::vector<uint64_t> words(m->val.size(), 0);
+    for (size_t q = 0; q < m->val.size(); ++q) {
+      const double x = std::fabs(m->val[q]) * full;  // exact: a power-of-two scaling
+      if (x != std::floor(x) || x >= full) fail("value is not a fixed-point number of the word length");
+      words[q] = uint64_t(x) | (std::signbit(m->val[q]) && x != 0.0 ? uint64_t(1) << 63 : 0);
+    }
+    m->word = w;
+    m->words.swap(words);
+  });
+}
+
 void orc_matrix_free(void* p) { delete static_cast<Matrix*>(p); }
 
 void orc_matrix_info(void* p, int32_t* N, int32_t* s, int32_t* nbits, double* scale) {
@@ -578,6 +664,16 @@ void orc_matrix_ell(void* p, int32_t* col, double* val, double* vim, uint8_t* re
 }
 
 uint64_t orc_qbs(const int32_t* row, int32_t s, uint64_t target) { return qbs(row, s, target); }
+
+// The fixed-point registers and rotation amplitudes, for unit tests.
+uint64_t orc_fx_sqrt(uint64_t q, int32_t w) { return fx_sqrt(q, w); }
+uint64_t orc_fx_arccos(uint64_t r, int32_t w) { return fx_arccos(r, w); }
+void orc_fx_rotation(uint64_t A, int32_t w, uint64_t j, uint64_t k, double* fre, double* fim, double* g) {
+  const Rot r = rotation_fixed(A, w, j, k);
+  *fre = r.f.real();
+  *fim = r.f.imag();
+  *g = r.g;
+}
 
 void* orc_state_new(void* mat, double tau) {
   OState* o = new OState;
@@ -730,9 +826,13 @@ void orc_cks_coeffs(int64_t beta, int32_t j0, double* out) { cks_coeffs(beta, j0
 // three-term Chebyshev recurrence on the padded, scaled matrix.  Row j of the
 // table holds column j of A (entries A_{col, j}), so A x is a scatter:
 // (A x)_{col[j,l]} += a_{j,l} x_j.
-void orc_cheb_series(void* mat, const double* bre, const double* bim, int32_t nb, int32_t j0,
-                     const double* coef, double* yre, double* yim) {
+int orc_cheb_series(void* mat, const double* bre, const double* bim, int32_t nb, int32_t j0,
+                    const double* coef, double* yre, double* yim) {
   const Matrix& m = *static_cast<Matrix*>(mat);
+  if (m.word > 0) {
+    g_err = "the classical series uses the values themselves, not fixed-point data";
+    return -1;
+  }
   const int N = m.N;
   auto apply_h = [&](const std::vector<cplx>& x, std::vector<cplx>& out) {
     std::fill(out.begin(), out.end(), cplx(0.0, 0.0));
@@ -761,6 +861,7 @@ void orc_cheb_series(void* mat, const double* bre, const double* bim, int32_t nb
     yre[r] = y[r].real();
     yim[r] = y[r].imag();
   }
+  return 0;
 }
 
 // Walk-based solver: omega = W T~ |b~>; for k = 0..j0: y += a_k Pi_0 T~^dagger
@@ -811,6 +912,7 @@ int orc_grad(void* mat, const double* bre, const double* bim, int32_t nb, int32_
   const Matrix& m = *static_cast<Matrix*>(mat);
   return guarded([&] {
     if (m.complex_values) fail("the gradient is defined for real matrices only");
+    if (m.word > 0) fail("the gradient is defined for real-valued (not fixed-point) data only");
     OState o;
     o.m = &m;
     o.tau = tau;

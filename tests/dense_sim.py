@@ -15,6 +15,8 @@ indices with value 0) so that nothing is taken from the oracle.
 """
 from __future__ import annotations
 
+import math
+
 import numpy as np
 
 
@@ -50,8 +52,31 @@ def _position(col, j, k):
     return int(hit[0]) if hit.size else 0
 
 
+def fixed_point_rotation(a, w, row, column):
+    """(f, g) for the real value a = +-q / 2^w of fixed-point data, written
+    out from the definitions: the square-root register is sqrt(q / 2^w)
+    truncated to w fraction bits, the angle register the arccos of that in
+    units of (pi/2) / 2^w rounded to the nearest integer, and the rotation is
+    by that angle (f = cos, times +-i by the order of row and column for a
+    negative value; g = sin)."""
+    q = int(round(abs(a) * 2 ** w))
+    assert q == abs(a) * 2 ** w and q < 2 ** w, "not a fixed-point value"
+    r = math.isqrt(q << w)
+    t = round(math.acos(r / 2 ** w) * 2 ** (w + 1) / math.pi)
+    if t == 2 ** w:
+        c, sn = 0.0, 1.0
+    elif t == 0:
+        c, sn = 1.0, 0.0
+    else:
+        theta = math.pi / 2 * t / 2 ** w
+        c, sn = math.cos(theta), math.sin(theta)
+    if math.copysign(1.0, a) > 0 or q == 0:
+        return complex(c, 0.0), sn
+    return (1j if row <= column else -1j) * c, sn
+
+
 class DenseWalk:
-    def __init__(self, csc, scale=None):
+    def __init__(self, csc, scale=None, word=0):
         self.N, self.n, self.s, self.scale, self.col, self.val = preprocess(csc, scale)
         N, s = self.N, self.s
         self.shape = (N, N, 2, N, N, 2)
@@ -82,6 +107,16 @@ class DenseWalk:
         f_real = np.where(ar >= 0, np.sqrt(np.abs(ar)) + 0j, np.where(j <= colk, 1j, -1j) * np.sqrt(np.abs(ar)))
         f = np.where(ai != 0, np.sqrt(a + 0j), f_real)
         g = np.sqrt(1.0 - np.abs(a))
+        if word:
+            # fixed-point data: one rotation per (value, row, column) triple
+            table = {}
+            f = np.empty(a.shape, complex)
+            g = np.empty(a.shape)
+            for idx, (av, jv, cv) in enumerate(zip(ar.tolist(), j.tolist(), colk.tolist())):
+                key = (av, jv <= cv)
+                if key not in table:
+                    table[key] = fixed_point_rotation(av, word, jv, cv)
+                f[idx], g[idx] = table[key]
         self.rot_valid = valid
         self.f, self.g = f, g
         self.b2 = b2

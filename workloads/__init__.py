@@ -173,6 +173,24 @@ def band_matrix(n: int, bandwidth: int, seed: int = 0) -> Csc:
     return _from_triplets(n, np.concatenate(rows), np.concatenate(cols), np.concatenate(vals))
 
 
+def fixed_point_band(n: int, bandwidth: int, word: int, seed: int = 0, negative: float = 0.0) -> Csc:
+    """Symmetric band matrix whose entries are fixed-point numbers of `word`
+    fraction bits in (0, 1): q / 2^word with q uniform on 1 ... 2^word - 1 (the
+    paper's matrices, Sec. V.B).  `negative`: probability that an
+    off-diagonal pair is negated (the paper's matrices are positive)."""
+    rng = np.random.default_rng(seed)
+    rows, cols, vals = [], [], []
+    for d in range(0, bandwidth + 1):
+        v = rng.integers(1, 1 << word, n - d).astype(np.float64) / float(1 << word)
+        if d and negative:
+            v = np.where(rng.uniform(size=n - d) < negative, -v, v)
+        j = np.arange(n - d)
+        rows.append(j), cols.append(j + d), vals.append(v)
+        if d:
+            rows.append(j + d), cols.append(j), vals.append(v)
+    return _from_triplets(n, np.concatenate(rows), np.concatenate(cols), np.concatenate(vals))
+
+
 def laplacian_2d(m: int = 32, shift: float = 0.1) -> Csc:
     n = m * m
     rows, cols, vals = [], [], []
@@ -225,6 +243,8 @@ TABLE1_SHAPES = {
     "D": (8192, 15, 14),   # s = 32
     "E": (16384, 31, 7),   # s = 64
 }
+# The word length of each shape's fixed-point entries in the same table.
+TABLE1_WORD = {"A": 8, "B": 8, "C": 8, "D": 16, "E": 32}
 # The paper's single-core time per walk step for each shape (context only).
 TABLE1_PAPER_SECONDS_PER_STEP = {"A": 1.1e-3, "B": 12e-3, "C": 1.2, "D": 14.0, "E": 66.0}
 
@@ -233,6 +253,14 @@ def table1_band(name: str):
     """Band matrix of the given shape of the paper's table, uniform b."""
     n, w, seed = TABLE1_SHAPES[name]
     return band_matrix(n, w, seed=seed), uniform_b(n)
+
+
+def table1_fixed_point_band(name: str):
+    """The shape's band matrix with fixed-point entries of the table's word
+    length, uniform b; returns (matrix, b, word length)."""
+    n, w, seed = TABLE1_SHAPES[name]
+    word = TABLE1_WORD[name]
+    return fixed_point_band(n, w, word, seed=seed), uniform_b(n), word
 
 
 def paper_band():
