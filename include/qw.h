@@ -68,6 +68,17 @@ typedef struct {
 
 /* flags for qw_load_csc / qw_load_csc_batched */
 #define QW_REQUIRE_SYMMETRIC 0x1u /* reject matrices that are not symmetric (Hermitian) */
+/* Fixed-point data of word length w = 1 ... 32 (bits 8-13 of flags; 0 = the
+ * values are FP64 numbers).  Sec. V.B: the elements are fixed-point numbers
+ * below 1 whose number of digits is the word length; appendix table of basic
+ * operations: the conditional rotation is computed with a fixed-point square
+ * root, a fixed-point arccos and a rotation by a fixed-point angle.  Every
+ * scaled value must be +-q / 2^w with an integer 0 <= q < 2^w; the rotation
+ * then uses r = floor(sqrt(q / 2^w) 2^w) / 2^w (truncated square root),
+ * the angle theta = t (pi/2) / 2^w with t the nearest integer to
+ * arccos(r) / (pi/2) 2^w, f = cos(theta) (times +-i for a negative value,
+ * by the rule of the real case) and g = sin(theta).  Real matrices only. */
+#define QW_WORD_LENGTH(w) (((uint32_t)(w) & 0x3fu) << 8)
 
 /* flags for qw_state_init */
 #define QW_INIT_RAW 0x1u /* start from |b~> itself instead of T~|b~> */
@@ -90,7 +101,10 @@ typedef struct {
  * Errors: QW_EINVAL for n <= 0, bad colptr, row indices out of range,
  *   unsorted or duplicate, |scale*a| > 1, a negative diagonal entry (not
  *   encodable: <j~|T~^dagger S T~|j~> = |f|^2/s >= 0), a non-symmetric matrix
- *   when QW_REQUIRE_SYMMETRIC is set; QW_ENOTSUP for s > 64 or 4n+2 > 64. */
+ *   when QW_REQUIRE_SYMMETRIC is set, a word length above 32 or a value that
+ *   is not a fixed-point number of the word length given with
+ *   QW_WORD_LENGTH; QW_ENOTSUP for s > 64 or 4n+2 > 64.  qw_grad is not
+ *   provided for fixed-point data (QW_ENOTSUP). */
 int qw_load_csc(qw_ctx** out, int32_t n, const int32_t* colptr, const int32_t* rowidx,
                 const double* vals, int64_t nnz, double scale, uint32_t flags,
                 const qw_allocator* alloc, void* stream);
@@ -114,8 +128,9 @@ int qw_load_csc_batched(qw_ctx** out, int32_t ninst, const int32_t* n, const int
  * axis, the real rule of qw_load_csc on it (entries with a zero imaginary
  * part).  QW_REQUIRE_SYMMETRIC requires A_kj = conj(A_jk) exactly.  Scaling
  * uses |a| = hypot(re, im).  Errors: as qw_load_csc, plus QW_EINVAL for a
- * diagonal entry with a nonzero imaginary part.  qw_grad is not provided for
- * such a context (QW_ENOTSUP); every other entry point is. */
+ * diagonal entry with a nonzero imaginary part, QW_ENOTSUP with
+ * QW_WORD_LENGTH.  qw_grad is not provided for such a context (QW_ENOTSUP);
+ * every other entry point is. */
 int qw_load_csc_hermitian(qw_ctx** out, int32_t ninst, const int32_t* n, const int64_t* colptr_off,
                           const int64_t* nnz_off, const int32_t* colptr, const int32_t* rowidx,
                           const double* vals_re, const double* vals_im, const double* scales, uint32_t flags,

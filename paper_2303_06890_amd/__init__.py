@@ -112,9 +112,11 @@ class Walk:
     preprocessed and resident on the GPU (a ``qw_ctx``).  ``mats``: a CSC
     object (attributes n, colptr, rowidx, vals) or a list of them (batched
     form); complex values select the Hermitian loader.  ``scale``: None
-    (automatic 1/max(1, max|a|)), a float, or one float per matrix."""
+    (automatic 1/max(1, max|a|)), a float, or one float per matrix.
+    ``word``: 0 for FP64 values, or the word length (1 ... 32) of fixed-point
+    data, whose rotation is then computed in fixed point."""
 
-    def __init__(self, mats, scale=None, symmetric: bool = True, torch_alloc: bool = True):
+    def __init__(self, mats, scale=None, symmetric: bool = True, torch_alloc: bool = True, word: int = 0):
         lib = _lib.load()
         self.mats = list(mats) if isinstance(mats, (list, tuple)) else [mats]
         self.ninst = len(self.mats)
@@ -134,7 +136,8 @@ class Walk:
             sc = np.broadcast_to(np.asarray(scale, np.float64), (self.ninst,)).copy()
         self._keep = (n, colptr, rowidx, vals, vim, coff, zoff, sc)
         h = ctypes.c_void_p()
-        flags = _lib.QW_REQUIRE_SYMMETRIC if symmetric else 0
+        flags = (_lib.QW_REQUIRE_SYMMETRIC if symmetric else 0) | _lib.word_length(word)
+        self.word = int(word)
         alloc = ctypes.byref(self._alloc.struct) if self._alloc else None
         scp = _dp(sc) if sc is not None else None
         if self.complex:

@@ -12,6 +12,11 @@ QW_REQUIRE_SYMMETRIC = 0x1
 QW_INIT_RAW = 0x1
 QW_COUNT, QW_NORM, QW_J_MARGINAL, QW_PROJECT, QW_STATS = 1, 2, 3, 4, 5
 
+
+def word_length(w: int) -> int:
+    """Load flags for fixed-point data of word length w (QW_WORD_LENGTH)."""
+    return (int(w) & 0x3F) << 8
+
 # every symbol the header declares
 SYMBOLS = [
     "qw_load_csc", "qw_load_csc_batched", "qw_ctx_info", "qw_ctx_ninst", "qw_state_init", "qw_step",

@@ -94,6 +94,7 @@ struct qw_ctx {
   qw::SlotRec* rec = nullptr;
   double* vim = nullptr;          // imaginary parts by home (complex matrices only)
   bool complex_values = false;
+  int32_t word = 0;               // fixed-point word length (0: FP64 values)
   qw::Inst* dinst = nullptr;
   int32_t* wave_inst = nullptr;
   qw::Inst inst0{};
@@ -114,6 +115,8 @@ struct qw_ctx {
     m.slmax = slmax;
     m.suni = suni;
     m.full = full;
+    m.angles = word > 0 ? 1 : 0;
+    m.pad_ = 0;
     m.inst0 = inst0;
     return m;
   }
@@ -364,6 +367,39 @@ int preprocess(int32_t n, const int32_t* colptr, const int32_t* rowidx, const do
   return QW_OK;
 }
 
+// ---- fixed-point data --------------------------------------------------------
+// A value a = +-q / 2^w of fixed-point data becomes the signed angle
+// y = +-(pi/2 - theta) / pi of its rotation, where theta is the fixed-point
+// angle: the square-root register r = floor(sqrt(q 2^w)) (integer square root,
+// w fraction bits), the angle register t = the nearest integer to
+// arccos(r / 2^w) 2^(w+1) / pi (units of (pi/2) / 2^w), theta = t (pi/2) / 2^w.
+// The kernels take f = sin(pi |y|) = cos(theta), g = cos(pi y) = sin(theta);
+// y = 0 (f = 0, g = 1) exactly when q = 0.
+
+uint64_t int_sqrt(uint64_t x) {
+  uint64_t r = uint64_t(std::sqrt(double(x)));
+  while (r > 0 && (unsigned __int128)r * r > x) --r;
+  while ((unsigned __int128)(r + 1) * (r + 1) <= x) ++r;
+  return r;
+}
+
+int fixed_point_angles(int32_t w, std::vector<double>& val) {
+  const uint64_t one = uint64_t(1) << w;
+  for (double& v : val) {
+    const double x = std::fabs(v) * double(one);  // exact (power-of-two scaling)
+    if (x != std::floor(x) || x >= double(one))
+      return set_err(QW_EINVAL, "value " + std::to_string(v) + " is not a fixed-point number of word length " +
+                                    std::to_string(w));
+    const uint64_t q = uint64_t(x);
+    const uint64_t r = int_sqrt(q << w);
+    const uint64_t t =
+        uint64_t(std::nearbyint(std::acos(double(r) / double(one)) * (double(uint64_t(1) << (w + 1)) / M_PI)));
+    const double y = double(one - t) / double(one << 1);  // exact: t <= 2^w
+    v = (v < 0.0 && q != 0) ? -y : y;
+  }
+  return QW_OK;
+}
+
 int load_impl(qw_ctx** out, int32_t ninst, const int32_t* n, const int64_t* colptr_off, const int64_t* nnz_off,
               const int32_t* colptr, const int32_t* rowidx, const double* vals, const double* vals_im,
               const double* scales, uint32_t flags, const qw_allocator* alloc, void* stream_v);
@@ -387,6 +423,9 @@ int load_impl(qw_ctx** out, int32_t ninst, const int32_t* n, const int64_t* colp
   if (!out) return set_err(QW_EINVAL, "out is NULL");
   *out = nullptr;
   if (ninst <= 0 || !n || !colptr || !rowidx || !vals) return set_err(QW_EINVAL, "missing matrix arrays");
+  const int32_t word = int32_t((flags >> 8) & 0x3fu);
+  if (word > 32) return set_err(QW_EINVAL, "word length must be 1 ... 32 (0: FP64 values)");
+  if (word > 0 && vals_im) return set_err(QW_ENOTSUP, "fixed-point data is provided for real matrices only");
   hipStream_t stream = static_cast<hipStream_t>(stream_v);
   qw_ctx* ctx = new qw_ctx;
   if (alloc) {
@@ -403,6 +442,7 @@ int load_impl(qw_ctx** out, int32_t ninst, const int32_t* n, const int64_t* colp
   std::vector<double> hval;
   std::vector<double> hvim;  // imaginary parts by home (complex input)
   ctx->complex_values = vals_im != nullptr;
+  ctx->word = word;
   int64_t items = 0, jbase = 0, nnz_base = 0, ntot = 0;
   int nbits = 1;
   for (int32_t i = 0; i < ninst; ++i) {
@@ -413,6 +453,7 @@ int load_impl(qw_ctx** out, int32_t ninst, const int32_t* n, const int64_t* colp
     std::vector<int64_t> slot_of;
     int rc = preprocess(n[i], colptr + co, rowidx + zo, vals + zo, vals_im ? vals_im + zo : nullptr,
                         scales ? scales[i] : 0.0, flags, hi, ell, slot_of);
+    if (rc == QW_OK && word > 0) rc = fixed_point_angles(word, ell.val);
     if (rc) {
       prefix_err("instance " + std::to_string(i) + ": ");
       delete ctx;
@@ -1044,6 +1085,8 @@ int qw_grad(qw_state* st, const double* w, int32_t nsteps, double* dvals, double
     return set_err(QW_EINVAL, "qw_grad needs the state made by qw_state_init (T~ start) advanced by exactly nsteps");
   if (st->ctx->complex_values)
     return set_err(QW_ENOTSUP, "the gradient is provided for real matrices only");
+  if (st->ctx->word > 0)
+    return set_err(QW_ENOTSUP, "the gradient is provided for FP64 values only, not fixed-point data");
   hipStream_t stream = static_cast<hipStream_t>(stream_v);
   qw_ctx* ctx = st->ctx;
   std::vector<double> hw(static_cast<size_t>(ctx->jtotal), 0.0);

@@ -68,6 +68,10 @@ struct SlotRec {
   double val;    // a_{j,l} after scaling
 };
 
+// Fixed-point data (angles = 1): the value of a slot is replaced by the
+// signed angle y (in units of pi, |y| <= 1/2) of its conditional rotation,
+// f = sin(pi |y|) (times +-i when y < 0), g = cos(pi y); a zero value has
+// y = 0 (f = 0, g = 1).
 struct Matrix {
   const int32_t* col;        // ELL column indices (row-major), sorted inside each row
   const double* val;         // ELL values (row-major)
@@ -84,10 +88,14 @@ struct Matrix {
   int32_t slmax;             // largest slots-per-lane over the instances
   int32_t suni;              // s of every instance when they all share it, else 0
   int32_t full;              // 1 when every instance has at least one wavefront of rows
+  int32_t angles;            // 1: fixed-point data; val holds each slot's rotation angle (below)
+  int32_t pad_;
   Inst inst0;                // copy of inst[0] (a single instance needs no table read)
 };
 
 enum Mode : int32_t { kStep = 0, kSwap = 1 };
+// What a slot's value is, for the step kernels' rotation.
+enum Enc : int32_t { kEncReal = 0, kEncComplex = 1, kEncAngle = 2 };
 
 struct StepArgs {
   Matrix m;
@@ -122,9 +130,9 @@ static_assert(sizeof(Inst) == 56 && offsetof(Inst, inv_sqrt_s) == 48, "Inst layo
 static_assert(sizeof(Slots) == 40 && offsetof(Slots, r1s) == 32, "Slots layout");
 static_assert(sizeof(List) == 24 && offsetof(List, cap) == 20, "List layout");
 static_assert(sizeof(SlotRec) == 16 && offsetof(SlotRec, val) == 8, "SlotRec layout");
-static_assert(sizeof(Matrix) == 152 && offsetof(Matrix, inst0) == 96, "Matrix layout");
-static_assert(sizeof(StepArgs) == 304 && offsetof(StepArgs, coefm) == 296, "StepArgs layout");
-static_assert(sizeof(AdjArgs) == 400 && offsetof(AdjArgs, wpb) == 392, "AdjArgs layout");
+static_assert(sizeof(Matrix) == 160 && offsetof(Matrix, inst0) == 104, "Matrix layout");
+static_assert(sizeof(StepArgs) == 312 && offsetof(StepArgs, coefm) == 304, "StepArgs layout");
+static_assert(sizeof(AdjArgs) == 408 && offsetof(AdjArgs, wpb) == 400, "AdjArgs layout");
 
 // Launchers (qw_launch.cpp).  All enqueue on `stream` and allocate nothing.
 hipError_t launch_step(const StepArgs& a, int grid, int block, hipStream_t stream);

@@ -100,6 +100,22 @@ __device__ __forceinline__ Rot rotation(double a, double b, int j, int k) {
   r.g = sqrt(1.0 - m);
   return r;
 }
+// Fixed-point data: the host has turned each value into the signed angle y
+// of its rotation (units of pi); f = sin(pi |y|), with the +-i rule of the
+// real case when y < 0, and g = cos(pi y).  sincospi is exact at y = 0.
+__device__ __forceinline__ Rot rotation_angle(double y, int j, int k) {
+  double sv, cv;
+  sincospi(fabs(y), &sv, &cv);
+  Rot r;
+  r.f = !signbit(y) ? make_double2(sv, 0.0) : make_double2(0.0, j <= k ? sv : -sv);
+  r.g = cv;
+  return r;
+}
+// Rotation of slot home h whatever the matrix holds (outside the step kernels).
+__device__ __forceinline__ Rot rotation_of(const Matrix& m, double val, int64_t h, int j, int k) {
+  if (m.angles) return rotation_angle(val, j, k);
+  return rotation(val, m.vim ? m.vim[h] : 0.0, j, k);
+}
 // d f/da and d g/da (not finite at a = 0 and |a| = 1).
 __device__ __forceinline__ Rot rotation_deriv(double a, int j, int k) {
   Rot d;
@@ -370,7 +386,7 @@ __device__ __forceinline__ unsigned list_entry(const List& L, int64_t e, int n, 
 // The data loads do not depend on each other or on the instance record
 // beyond its base, so they are issued together.  FAST: walk step (not the
 // swap) and every row of every wavefront exists.
-template <bool ACC, int SLM, int S, bool FAST, bool CPLX>
+template <bool ACC, int SLM, int S, bool FAST, int ENC>
 __device__ __forceinline__ unsigned step_wave(const StepArgs& a, int64_t w, int lane, double coef) {
   const Lanes x = lanes_of<S, FAST>(a.m, w, lane);
   const int sl = S ? Shape<S>::sl : (SLM == 1 ? 1 : x.I.sl);
@@ -385,7 +401,7 @@ __device__ __forceinline__ unsigned step_wave(const StepArgs& a, int64_t w, int 
     if (i < sl) {
       h[i] = base + (int64_t(x.h * sl + i) << x.I.nlog) + x.j;
       rc[i] = a.m.rec[h[i]];
-      if (CPLX) vi[i] = a.m.vim[h[i]];
+      if (ENC == kEncComplex) vi[i] = a.m.vim[h[i]];
       x0[i] = a.in.R0[h[i]];
       x1[i] = r1_of(a.in, h[i]);
       y1[i] = a.in.Q1[h[i]];
@@ -396,7 +412,9 @@ __device__ __forceinline__ unsigned step_wave(const StepArgs& a, int64_t w, int 
 #pragma unroll
   for (int i = 0; i < SLM; ++i) {
     if (i < sl) {
-      r[i] = CPLX ? rotation(rc[i].val, vi[i], x.j, rc[i].col) : rotation(rc[i].val, x.j, rc[i].col);
+      r[i] = ENC == kEncComplex ? rotation(rc[i].val, vi[i], x.j, rc[i].col)
+             : ENC == kEncAngle ? rotation_angle(rc[i].val, x.j, rc[i].col)
+                                : rotation(rc[i].val, x.j, rc[i].col);
       c = cadd(c, along(r[i], x0[i], x1[i]));
     }
   }
@@ -427,7 +445,7 @@ __device__ __forceinline__ unsigned step_wave(const StepArgs& a, int64_t w, int 
 // SLM: slots per lane held in registers; S: s of every instance, or 0 (read
 // per instance, slots per lane <= SLM).  FAST: one pass (the grid covers
 // every wavefront and the list), walk step only, every row exists.
-template <bool ACC, int SLM, int S, bool FAST, bool CPLX>
+template <bool ACC, int SLM, int S, bool FAST, int ENC>
 __device__ __forceinline__ void step_body(const StepArgs& a) {
   const int lane = threadIdx.x & (kWave - 1);
   const int64_t wpb = a.wpb;  // a kernel argument: reading the workgroup size costs a vector load
@@ -442,7 +460,7 @@ __device__ __forceinline__ void step_body(const StepArgs& a) {
   if (FAST) {
     const int64_t w = uniform(int(wid));
     if (w < a.m.waves)
-      cnt = step_wave<ACC, SLM, S, true, CPLX>(a, w, lane, coef);
+      cnt = step_wave<ACC, SLM, S, true, ENC>(a, w, lane, coef);
     else
       cnt = list_entry(a.L, (w - a.m.waves) * kWave + lane, a.m.nbits, true);
   } else {
@@ -450,7 +468,7 @@ __device__ __forceinline__ void step_body(const StepArgs& a) {
     const int64_t wstride = int64_t(gridDim.x) * wpb;
     for (int64_t w = uniform(int(wid)); w < total; w += wstride) {
       if (w < a.m.waves)
-        cnt += step_wave<ACC, SLM, S, false, CPLX>(a, w, lane, coef);
+        cnt += step_wave<ACC, SLM, S, false, ENC>(a, w, lane, coef);
       else
         cnt += list_entry(a.L, (w - a.m.waves) * kWave + lane, a.m.nbits, a.mode == kStep);
     }
@@ -465,33 +483,37 @@ __device__ __forceinline__ void step_body(const StepArgs& a) {
 // launch shape, walk step or swap; qwk_step_gN: the same s per instance, but
 // every instance has at least one wavefront of rows, one pass, walk step;
 // qwk_step_fS: as gN with s = S for every instance; qwk_step_cN: as sN for a
-// complex Hermitian matrix.
-#define QW_STEP_KERNEL(NAME, SLM, S, FAST, CPLX)                                                   \
+// complex Hermitian matrix; qwk_step_xN: as sN for fixed-point data.
+#define QW_STEP_KERNEL(NAME, SLM, S, FAST, ENC)                                                    \
   extern "C" __global__ void __launch_bounds__(256) NAME(qw::StepArgs a) {                         \
-    qw::step_body<false, SLM, S, FAST, CPLX>(a);                                                    \
+    qw::step_body<false, SLM, S, FAST, ENC>(a);                                                     \
   }                                                                                                 \
   extern "C" __global__ void __launch_bounds__(256) NAME##_acc(qw::StepArgs a) {                   \
-    qw::step_body<true, SLM, S, FAST, CPLX>(a);                                                     \
+    qw::step_body<true, SLM, S, FAST, ENC>(a);                                                      \
   }
-QW_STEP_KERNEL(qwk_step_s1, 1, 0, false, false)
-QW_STEP_KERNEL(qwk_step_s2, 2, 0, false, false)
-QW_STEP_KERNEL(qwk_step_s4, 4, 0, false, false)
-QW_STEP_KERNEL(qwk_step_s8, 8, 0, false, false)
-QW_STEP_KERNEL(qwk_step_g1, 1, 0, true, false)
-QW_STEP_KERNEL(qwk_step_g2, 2, 0, true, false)
-QW_STEP_KERNEL(qwk_step_g4, 4, 0, true, false)
-QW_STEP_KERNEL(qwk_step_g8, 8, 0, true, false)
-QW_STEP_KERNEL(qwk_step_f1, 1, 1, true, false)
-QW_STEP_KERNEL(qwk_step_f2, 1, 2, true, false)
-QW_STEP_KERNEL(qwk_step_f4, 1, 4, true, false)
-QW_STEP_KERNEL(qwk_step_f8, 1, 8, true, false)
-QW_STEP_KERNEL(qwk_step_f16, 2, 16, true, false)
-QW_STEP_KERNEL(qwk_step_f32, 4, 32, true, false)
-QW_STEP_KERNEL(qwk_step_f64, 8, 64, true, false)
-QW_STEP_KERNEL(qwk_step_c1, 1, 0, false, true)
-QW_STEP_KERNEL(qwk_step_c2, 2, 0, false, true)
-QW_STEP_KERNEL(qwk_step_c4, 4, 0, false, true)
-QW_STEP_KERNEL(qwk_step_c8, 8, 0, false, true)
+QW_STEP_KERNEL(qwk_step_s1, 1, 0, false, qw::kEncReal)
+QW_STEP_KERNEL(qwk_step_s2, 2, 0, false, qw::kEncReal)
+QW_STEP_KERNEL(qwk_step_s4, 4, 0, false, qw::kEncReal)
+QW_STEP_KERNEL(qwk_step_s8, 8, 0, false, qw::kEncReal)
+QW_STEP_KERNEL(qwk_step_g1, 1, 0, true, qw::kEncReal)
+QW_STEP_KERNEL(qwk_step_g2, 2, 0, true, qw::kEncReal)
+QW_STEP_KERNEL(qwk_step_g4, 4, 0, true, qw::kEncReal)
+QW_STEP_KERNEL(qwk_step_g8, 8, 0, true, qw::kEncReal)
+QW_STEP_KERNEL(qwk_step_f1, 1, 1, true, qw::kEncReal)
+QW_STEP_KERNEL(qwk_step_f2, 1, 2, true, qw::kEncReal)
+QW_STEP_KERNEL(qwk_step_f4, 1, 4, true, qw::kEncReal)
+QW_STEP_KERNEL(qwk_step_f8, 1, 8, true, qw::kEncReal)
+QW_STEP_KERNEL(qwk_step_f16, 2, 16, true, qw::kEncReal)
+QW_STEP_KERNEL(qwk_step_f32, 4, 32, true, qw::kEncReal)
+QW_STEP_KERNEL(qwk_step_f64, 8, 64, true, qw::kEncReal)
+QW_STEP_KERNEL(qwk_step_c1, 1, 0, false, qw::kEncComplex)
+QW_STEP_KERNEL(qwk_step_c2, 2, 0, false, qw::kEncComplex)
+QW_STEP_KERNEL(qwk_step_c4, 4, 0, false, qw::kEncComplex)
+QW_STEP_KERNEL(qwk_step_c8, 8, 0, false, qw::kEncComplex)
+QW_STEP_KERNEL(qwk_step_x1, 1, 0, false, qw::kEncAngle)
+QW_STEP_KERNEL(qwk_step_x2, 2, 0, false, qw::kEncAngle)
+QW_STEP_KERNEL(qwk_step_x4, 4, 0, false, qw::kEncAngle)
+QW_STEP_KERNEL(qwk_step_x8, 8, 0, false, qw::kEncAngle)
 #undef QW_STEP_KERNEL
 
 
@@ -627,7 +649,7 @@ extern "C" __global__ void __launch_bounds__(256) qwk_init(Matrix m, const doubl
     const Home x = home_item(m, it, it - (threadIdx.x & (kWave - 1)));
     if (!x.live) continue;
     const SlotRec rc = m.rec[it];
-    const Rot r = rotation(rc.val, m.vim ? m.vim[it] : 0.0, x.j, rc.col);
+    const Rot r = rotation_of(m, rc.val, it, x.j, rc.col);
     const double2 bj = cscale(b[x.I.jbase + x.j], x.I.inv_sqrt_s);
     double2 o0 = cmul(r.f, bj);
     double2 o1 = cscale(bj, r.g);
@@ -698,7 +720,7 @@ extern "C" __global__ void __launch_bounds__(256) qwk_measure_rows(Matrix m, Slo
           if (sw != 0.0) atomicAdd(&out[x.I.jbase + m.rec[h].col], sw);
         } else {
           const SlotRec rc = m.rec[h];
-          c = cadd(c, along(rotation(rc.val, m.vim ? m.vim[h] : 0.0, x.j, rc.col), p0, p1));
+          c = cadd(c, along(rotation_of(m, rc.val, h, x.j, rc.col), p0, p1));
         }
       }
       if (kind == 2) {

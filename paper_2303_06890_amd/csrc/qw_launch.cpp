@@ -25,9 +25,10 @@ namespace {
 // mode; qwk_step_g{1,2,4,8} need every instance to have at least one
 // wavefront's rows, a grid that covers the work in one pass, and the walk
 // step; qwk_step_f{S} need that and s = S for every instance;
-// qwk_step_c{1,2,4,8} are the general kernels for complex Hermitian matrices.
-// Each has an _acc twin (the solver's fused projection).  Adjoint kernels
-// (real matrices) come in the four widths.
+// qwk_step_c{1,2,4,8} are the general kernels for complex Hermitian matrices
+// and qwk_step_x{1,2,4,8} those for fixed-point data.  Each has an _acc twin
+// (the solver's fused projection).  Adjoint kernels (real FP64 matrices) come
+// in the four widths.
 enum Fn {
   F_STEP_S1,
   F_STEP_S2,
@@ -48,6 +49,10 @@ enum Fn {
   F_STEP_C2,
   F_STEP_C4,
   F_STEP_C8,
+  F_STEP_X1,
+  F_STEP_X2,
+  F_STEP_X4,
+  F_STEP_X8,
   F_STEP_COUNT_,  // _acc twins follow at + F_STEP_COUNT_
   F_ADJOINT_S1 = 2 * F_STEP_COUNT_,
   F_ADJOINT_S2,
@@ -69,11 +74,13 @@ const char* const kNames[F_COUNT] = {
     "qwk_step_s1",      "qwk_step_s2",      "qwk_step_s4",      "qwk_step_s8",      "qwk_step_g1",
     "qwk_step_g2",      "qwk_step_g4",      "qwk_step_g8",      "qwk_step_f1",      "qwk_step_f2",
     "qwk_step_f4",      "qwk_step_f8",      "qwk_step_f16",     "qwk_step_f32",     "qwk_step_f64",
-    "qwk_step_c1",      "qwk_step_c2",      "qwk_step_c4",      "qwk_step_c8",
+    "qwk_step_c1",      "qwk_step_c2",      "qwk_step_c4",      "qwk_step_c8",      "qwk_step_x1",
+    "qwk_step_x2",      "qwk_step_x4",      "qwk_step_x8",
     "qwk_step_s1_acc",  "qwk_step_s2_acc",  "qwk_step_s4_acc",  "qwk_step_s8_acc",  "qwk_step_g1_acc",
     "qwk_step_g2_acc",  "qwk_step_g4_acc",  "qwk_step_g8_acc",  "qwk_step_f1_acc",  "qwk_step_f2_acc",
     "qwk_step_f4_acc",  "qwk_step_f8_acc",  "qwk_step_f16_acc", "qwk_step_f32_acc", "qwk_step_f64_acc",
-    "qwk_step_c1_acc",  "qwk_step_c2_acc",  "qwk_step_c4_acc",  "qwk_step_c8_acc",
+    "qwk_step_c1_acc",  "qwk_step_c2_acc",  "qwk_step_c4_acc",  "qwk_step_c8_acc",  "qwk_step_x1_acc",
+    "qwk_step_x2_acc",  "qwk_step_x4_acc",  "qwk_step_x8_acc",
     "qwk_adjoint_s1",   "qwk_adjoint_s2",   "qwk_adjoint_s4",   "qwk_adjoint_s8",   "qwk_qbs_table",
     "qwk_init",         "qwk_fill",         "qwk_measure",      "qwk_measure_rows", "qwk_export",
     "qwk_import",       "qwk_weight",       "qwk_grad_init"};
@@ -88,6 +95,8 @@ Fn step_kernel(const StepArgs& a, int grid, int block) {
   int f = F_STEP_S1 + width_index(m.slmax);
   if (m.vim) {
     f = F_STEP_C1 + width_index(m.slmax);
+  } else if (m.angles) {
+    f = F_STEP_X1 + width_index(m.slmax);
   } else if (m.full && a.mode == kStep && int64_t(grid) * (block / kWave) >= work) {
     f = F_STEP_G1 + width_index(m.slmax);
     if (m.suni > 0) {
@@ -161,7 +170,7 @@ hipError_t launch_step(const StepArgs& a, int grid, int block, hipStream_t strea
 
 hipError_t launch_adjoint(const AdjArgs& a, int grid, int block, hipStream_t stream) {
   if (block < kWave || block > kMaxBlock || block % kWave) return hipErrorInvalidValue;
-  if (a.m.vim) return hipErrorInvalidValue;  // the gradient sweep is for real matrices
+  if (a.m.vim || a.m.angles) return hipErrorInvalidValue;  // the gradient sweep is for real FP64 matrices
   AdjArgs c = a;
   c.wpb = block / kWave;
   c.pad_ = 0;

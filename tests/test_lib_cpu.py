@@ -138,6 +138,23 @@ def test_hermitian_loader_validation(lib):
     assert rc == -1 and "vals_im" in msg
 
 
+def test_fixed_point_load_validation(lib):
+    """Fixed-point data (QW_WORD_LENGTH): values must be words of the given
+    length, the length at most 32, the matrix real.  All checked on the host
+    before any device work."""
+    from paper_2303_06890_amd import _lib
+
+    csc = W.fixed_point_band(16, 2, 6, seed=1)
+    rc, msg = _load(lib, csc, flags=1 | _lib.word_length(5))   # needs 6 bits
+    assert rc == -1 and "fixed-point" in msg
+    rc, msg = _load(lib, W.tiny_tridiagonal()[0], flags=1 | _lib.word_length(16))
+    assert rc == -1 and "fixed-point" in msg
+    rc, msg = _load(lib, csc, flags=1 | _lib.word_length(33))
+    assert rc == -1 and "word length" in msg
+    rc, msg = _load_hermitian(lib, W.hermitian_offset_matrix(16, 4, seed=1), flags=1 | _lib.word_length(8))
+    assert rc == -5 and "real" in msg
+
+
 def test_cks_coeffs_host(lib):
     """The library's coefficients (Stirling + ratio recurrence) agree with an
     exact rational evaluation and with the binomial tail."""
