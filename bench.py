@@ -178,10 +178,8 @@ def table1_leg(Q, W, autotune, tune: bool):
     experiments (n = 16 ... 16384, s = 8 ... 64), uniform b, T~ start; the
     paper's single-core time per step is quoted as context only (another
     machine, another code)."""
-    out = {}
-    for name in ("A", "B", "C", "D", "E"):
-        csc, b = W.table1_band(name)
-        walk = Q.Walk(csc)
+    def run(csc, b, word):
+        walk = Q.Walk(csc, word=word)
         shape = autotune.tune(walk, b) if tune else None
         st = walk.state(b)
         if shape:
@@ -191,19 +189,29 @@ def table1_leg(Q, W, autotune, tune: bool):
         s0 = st.stats()
         ms = _timed(Q, lambda: st.step(steps))
         upd = st.stats()["total_written"] - s0["total_written"]
-        us = 1e3 * ms / steps
-        paper = W.TABLE1_PAPER_SECONDS_PER_STEP[name]
-        out[name] = {
-            "n": csc.n,
+        res = {
             "s": walk.info[0]["s"],
             "branches": st.count(),
-            "us_per_step": us,
+            "us_per_step": 1e3 * ms / steps,
             "value": upd / (ms / 1e3),
             "launch_shape": list(shape) if shape else "default",
-            "paper_single_core_s_per_step": paper,
-            "time_ratio_vs_paper": paper / (us * 1e-6),
         }
         st.close()
+        return res
+
+    out = {}
+    for name in ("A", "B", "C", "D", "E"):
+        csc, b = W.table1_band(name)
+        res = run(csc, b, 0)
+        paper = W.TABLE1_PAPER_SECONDS_PER_STEP[name]
+        res.update(n=csc.n, paper_single_core_s_per_step=paper,
+                   time_ratio_vs_paper=paper / (res["us_per_step"] * 1e-6))
+        # the same shape with the table's fixed-point entries and word length
+        fcsc, fb, word = W.table1_fixed_point_band(name)
+        fx = run(fcsc, fb, word)
+        res["fixed_point"] = {"word_length": word, "us_per_step": fx["us_per_step"], "value": fx["value"],
+                              "branches": fx["branches"], "launch_shape": fx["launch_shape"]}
+        out[name] = res
     return out
 
 

@@ -22,7 +22,9 @@ def _key(walk, branches: int) -> str:
     name = torch.cuda.get_device_name()
     smax = max(d["s"] for d in walk.info)
     bucket = int(math.log2(max(1, branches)))
-    return f"{name}|N={walk.N_total}|s={smax}|inst={walk.ninst}|m2^{bucket}"
+    # the value kind selects the kernel family
+    kind = "complex" if walk.complex else (f"word{walk.word}" if walk.word else "real")
+    return f"{name}|N={walk.N_total}|s={smax}|inst={walk.ninst}|m2^{bucket}|{kind}"
 
 
 def candidates(walk):

@@ -483,7 +483,8 @@ __device__ __forceinline__ void step_body(const StepArgs& a) {
 // launch shape, walk step or swap; qwk_step_gN: the same s per instance, but
 // every instance has at least one wavefront of rows, one pass, walk step;
 // qwk_step_fS: as gN with s = S for every instance; qwk_step_cN: as sN for a
-// complex Hermitian matrix; qwk_step_xN: as sN for fixed-point data.
+// complex Hermitian matrix; qwk_step_xN: as sN for fixed-point data;
+// qwk_step_hN and qwk_step_yN: as gN for those two.
 #define QW_STEP_KERNEL(NAME, SLM, S, FAST, ENC)                                                    \
   extern "C" __global__ void __launch_bounds__(256) NAME(qw::StepArgs a) {                         \
     qw::step_body<false, SLM, S, FAST, ENC>(a);                                                     \
@@ -514,6 +515,14 @@ QW_STEP_KERNEL(qwk_step_x1, 1, 0, false, qw::kEncAngle)
 QW_STEP_KERNEL(qwk_step_x2, 2, 0, false, qw::kEncAngle)
 QW_STEP_KERNEL(qwk_step_x4, 4, 0, false, qw::kEncAngle)
 QW_STEP_KERNEL(qwk_step_x8, 8, 0, false, qw::kEncAngle)
+QW_STEP_KERNEL(qwk_step_h1, 1, 0, true, qw::kEncComplex)
+QW_STEP_KERNEL(qwk_step_h2, 2, 0, true, qw::kEncComplex)
+QW_STEP_KERNEL(qwk_step_h4, 4, 0, true, qw::kEncComplex)
+QW_STEP_KERNEL(qwk_step_h8, 8, 0, true, qw::kEncComplex)
+QW_STEP_KERNEL(qwk_step_y1, 1, 0, true, qw::kEncAngle)
+QW_STEP_KERNEL(qwk_step_y2, 2, 0, true, qw::kEncAngle)
+QW_STEP_KERNEL(qwk_step_y4, 4, 0, true, qw::kEncAngle)
+QW_STEP_KERNEL(qwk_step_y8, 8, 0, true, qw::kEncAngle)
 #undef QW_STEP_KERNEL
 
 

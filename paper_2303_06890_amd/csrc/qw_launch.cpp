@@ -26,7 +26,9 @@ namespace {
 // wavefront's rows, a grid that covers the work in one pass, and the walk
 // step; qwk_step_f{S} need that and s = S for every instance;
 // qwk_step_c{1,2,4,8} are the general kernels for complex Hermitian matrices
-// and qwk_step_x{1,2,4,8} those for fixed-point data.  Each has an _acc twin
+// and qwk_step_x{1,2,4,8} those for fixed-point data, qwk_step_h{1,2,4,8} and
+// qwk_step_y{1,2,4,8} their one-pass forms (the conditions of the g
+// kernels).  Each has an _acc twin
 // (the solver's fused projection).  Adjoint kernels (real FP64 matrices) come
 // in the four widths.
 enum Fn {
@@ -53,6 +55,14 @@ enum Fn {
   F_STEP_X2,
   F_STEP_X4,
   F_STEP_X8,
+  F_STEP_H1,
+  F_STEP_H2,
+  F_STEP_H4,
+  F_STEP_H8,
+  F_STEP_Y1,
+  F_STEP_Y2,
+  F_STEP_Y4,
+  F_STEP_Y8,
   F_STEP_COUNT_,  // _acc twins follow at + F_STEP_COUNT_
   F_ADJOINT_S1 = 2 * F_STEP_COUNT_,
   F_ADJOINT_S2,
@@ -70,20 +80,25 @@ enum Fn {
   F_COUNT
 };
 
-const char* const kNames[F_COUNT] = {
+const char* const kNames[] = {
     "qwk_step_s1",      "qwk_step_s2",      "qwk_step_s4",      "qwk_step_s8",      "qwk_step_g1",
     "qwk_step_g2",      "qwk_step_g4",      "qwk_step_g8",      "qwk_step_f1",      "qwk_step_f2",
     "qwk_step_f4",      "qwk_step_f8",      "qwk_step_f16",     "qwk_step_f32",     "qwk_step_f64",
     "qwk_step_c1",      "qwk_step_c2",      "qwk_step_c4",      "qwk_step_c8",      "qwk_step_x1",
-    "qwk_step_x2",      "qwk_step_x4",      "qwk_step_x8",
+    "qwk_step_x2",      "qwk_step_x4",      "qwk_step_x8",      "qwk_step_h1",      "qwk_step_h2",
+    "qwk_step_h4",      "qwk_step_h8",      "qwk_step_y1",      "qwk_step_y2",      "qwk_step_y4",
+    "qwk_step_y8",
     "qwk_step_s1_acc",  "qwk_step_s2_acc",  "qwk_step_s4_acc",  "qwk_step_s8_acc",  "qwk_step_g1_acc",
     "qwk_step_g2_acc",  "qwk_step_g4_acc",  "qwk_step_g8_acc",  "qwk_step_f1_acc",  "qwk_step_f2_acc",
     "qwk_step_f4_acc",  "qwk_step_f8_acc",  "qwk_step_f16_acc", "qwk_step_f32_acc", "qwk_step_f64_acc",
     "qwk_step_c1_acc",  "qwk_step_c2_acc",  "qwk_step_c4_acc",  "qwk_step_c8_acc",  "qwk_step_x1_acc",
-    "qwk_step_x2_acc",  "qwk_step_x4_acc",  "qwk_step_x8_acc",
+    "qwk_step_x2_acc",  "qwk_step_x4_acc",  "qwk_step_x8_acc",  "qwk_step_h1_acc",  "qwk_step_h2_acc",
+    "qwk_step_h4_acc",  "qwk_step_h8_acc",  "qwk_step_y1_acc",  "qwk_step_y2_acc",  "qwk_step_y4_acc",
+    "qwk_step_y8_acc",
     "qwk_adjoint_s1",   "qwk_adjoint_s2",   "qwk_adjoint_s4",   "qwk_adjoint_s8",   "qwk_qbs_table",
     "qwk_init",         "qwk_fill",         "qwk_measure",      "qwk_measure_rows", "qwk_export",
     "qwk_import",       "qwk_weight",       "qwk_grad_init"};
+static_assert(sizeof(kNames) / sizeof(kNames[0]) == F_COUNT, "one kernel name per Fn");
 
 // 0..3 for slmax = 1, 2, 4, 8
 int width_index(int32_t slmax) { return slmax <= 1 ? 0 : slmax <= 2 ? 1 : slmax <= 4 ? 2 : 3; }
@@ -92,12 +107,13 @@ Fn step_kernel(const StepArgs& a, int grid, int block) {
   const Matrix& m = a.m;
   const bool acc = a.yacc != nullptr;
   const int64_t work = m.waves + (int64_t(a.L.cnt) + kWave - 1) / kWave;
+  const bool one_pass = m.full && a.mode == kStep && int64_t(grid) * (block / kWave) >= work;
   int f = F_STEP_S1 + width_index(m.slmax);
   if (m.vim) {
-    f = F_STEP_C1 + width_index(m.slmax);
+    f = (one_pass ? F_STEP_H1 : F_STEP_C1) + width_index(m.slmax);
   } else if (m.angles) {
-    f = F_STEP_X1 + width_index(m.slmax);
-  } else if (m.full && a.mode == kStep && int64_t(grid) * (block / kWave) >= work) {
+    f = (one_pass ? F_STEP_Y1 : F_STEP_X1) + width_index(m.slmax);
+  } else if (one_pass) {
     f = F_STEP_G1 + width_index(m.slmax);
     if (m.suni > 0) {
       int lg = 0;

@@ -56,6 +56,18 @@ def test_complex_walk_100_steps(Q, oracle_mod, n, c, seed):
         _check(st, ost, f"n={n} c={c} step {t}")
 
 
+@pytest.mark.parametrize("shape", [(128, 4), (64, 1), (256, 0)])
+def test_complex_launch_shapes(Q, oracle_mod, shape):
+    """Grids too small for one pass (the grid-stride kernels) and the default
+    grid (one pass) give the oracle's state."""
+    csc = W.hermitian_offset_matrix(200, 8, seed=8)
+    walk, st, ost = _pair(Q, oracle_mod, csc, _b(200, 9))
+    st.set_launch(*shape)
+    st.step(30)
+    ost.step(30)
+    _check(st, ost, f"shape {shape} step 30")
+
+
 def test_complex_raw_start_and_adjoint(Q, oracle_mod):
     csc = W.hermitian_offset_matrix(32, 6, seed=5)
     b = _b(32, 6)

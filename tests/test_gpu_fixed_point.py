@@ -70,6 +70,18 @@ def test_fixed_point_walk(Q, oracle_mod, n, bw, word, neg, seed, steps):
         _check(st, ost, f"n={n} bw={bw} w={word} step {t}")
 
 
+@pytest.mark.parametrize("shape", [(128, 4), (64, 1), (256, 0)])
+def test_fixed_point_launch_shapes(Q, oracle_mod, shape):
+    """Grids too small for one pass (the grid-stride kernels) and the default
+    grid (one pass) give the oracle's state."""
+    csc = W.fixed_point_band(300, 6, 16, seed=9, negative=0.3)
+    walk, st, ost = _pair(Q, oracle_mod, csc, W.gaussian_b(300, seed=9), 16)
+    st.set_launch(*shape)
+    st.step(30)
+    ost.step(30)
+    _check(st, ost, f"shape {shape} step 30")
+
+
 def test_fixed_point_raw_start_adjoint_and_measurements(Q, oracle_mod):
     csc = W.fixed_point_band(128, 4, 10, seed=6, negative=0.4)
     b = W.gaussian_b(128, seed=7)

@@ -115,6 +115,47 @@ def test_measurements(Q, oracle_mod):
     assert stats["launches"] == 9 and stats["branches"] == ost.count() and stats["list_count"] == 0
 
 
+@pytest.mark.parametrize("raw", [False, True])
+def test_total_written_is_the_sum_of_branch_counts(Q, raw):
+    """stats()['total_written'], the benchmark's count of amplitude updates,
+    is the sum over launches of the output state's branch count: step by
+    step, through graph replays, after an import, and for W^dagger (a swap,
+    the steps, a swap; a swap keeps the count)."""
+    csc = W.offset_matrix(300, 8, seed=21)  # no filler slots: most raw-start keys live in the list
+    b = W.gaussian_b(300, seed=22)
+    walk = Q.Walk(csc)
+    a = walk.state(b, raw=raw)
+    counts = []
+    t0 = a.stats()["total_written"]
+    for _ in range(40):
+        a.step(1)
+        counts.append(a.count())
+    assert a.stats()["total_written"] - t0 == sum(counts)
+    if raw:
+        assert a.stats()["list_count"] > 0
+    g = walk.state(b, raw=raw)
+    g0 = g.stats()["total_written"]
+    g.step(40)  # graph replays after the first direct step
+    assert g.stats()["total_written"] - g0 == sum(counts)
+    m0, t1 = a.count(), a.stats()["total_written"]
+    a.step_adjoint(1)
+    assert a.stats()["total_written"] - t1 == m0 + 2 * a.count()
+    keys, amps = a.export()
+    c = walk.state(np.zeros(300)).import_(keys, amps)
+    c0, counts = c.stats()["total_written"], []
+    for _ in range(5):
+        c.step(1)
+        counts.append(c.count())
+    c.step(20)
+    tail = c.stats()["total_written"] - c0 - sum(counts)
+    d = walk.state(np.zeros(300)).import_(keys, amps).step(5)
+    d0, dc = d.stats()["total_written"], []
+    for _ in range(20):
+        d.step(1)
+        dc.append(d.count())
+    assert tail == sum(dc)
+
+
 def test_checkpoint_resume(Q, oracle_mod):
     csc = W.offset_matrix(256, 8, seed=15)
     b = W.uniform_b(256)
