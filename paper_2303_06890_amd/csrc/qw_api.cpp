@@ -144,7 +144,11 @@ struct qw_state {
   int cur = 0;              // parity holding the state
   double r1s = 1.0;         // buffer cur^1's Q1 plane holds r1s * (the state's R1)
   List L{};                 // branches without a static home (count on the host)
-  unsigned long long* acc = nullptr;  // per-workgroup counts of branches written
+  unsigned long long* acc = nullptr;  // per-workgroup counts of kept outputs (a Q1 output twice)
+  // Branches written before the counts were last restarted, and the Q1
+  // branches of the state at that point (see total_written).
+  int64_t written_base = 0;
+  int64_t q1_base = 0;
   uint32_t* stepno = nullptr;         // per-wavefront solver step counters
   double2* b = nullptr;     // device copy of b (N-vector layout)
   double* mbuf = nullptr;   // measurement scratch: max(kMaxGrid, 2*jtotal) doubles
@@ -714,13 +718,34 @@ int measure_partials(qw_state* st, int kind, double* result, hipStream_t stream)
   return QW_OK;
 }
 
+// Branches written by all launches so far: the sum over launches of the
+// output state's branch count.  A launch counts each kept output once and a
+// kept Q1 output twice, the second time for the R1 branch that the next
+// launch makes of it without reading it.  Over launches 1..K the counters
+// therefore hold the true sum plus (Q1 branches after launch K) minus (Q1
+// branches before launch 1).
 int total_written(qw_state* st, hipStream_t stream, int64_t* out) {
   std::vector<unsigned long long> h(qw::kMaxGrid);
   QW_HIP(hipMemcpyAsync(h.data(), st->acc, sizeof(unsigned long long) * qw::kMaxGrid, hipMemcpyDeviceToHost, stream));
   QW_HIP(hipStreamSynchronize(stream));
   unsigned long long t = 0;
   for (auto v : h) t += v;
-  *out = int64_t(t);
+  double q1 = 0.0;
+  int rc = measure_partials(st, 4, &q1, stream);
+  if (rc) return rc;
+  *out = st->written_base + int64_t(t) + st->q1_base - int64_t(std::llround(q1));
+  return QW_OK;
+}
+
+// Restart the counters after the state was changed by something other than a
+// launch of the step kernels (an import); `written` is the total before.
+int restart_counts(qw_state* st, int64_t written, hipStream_t stream) {
+  QW_HIP(qw::launch_fill(st->acc, sizeof(unsigned long long) * qw::kMaxGrid, stream));
+  double q1 = 0.0;
+  int rc = measure_partials(st, 4, &q1, stream);
+  if (rc) return rc;
+  st->written_base = written;
+  st->q1_base = int64_t(std::llround(q1));
   return QW_OK;
 }
 
@@ -841,6 +866,7 @@ int qw_state_init(qw_state** out, qw_ctx* ctx, const double* b_re, const double*
       }
     }
     rc = import_branches(st, keys, amps, stream);
+    if (rc == QW_OK) rc = restart_counts(st, 0, stream);
     if (rc) {
       qw_state_free(st);
       return rc;
@@ -1006,12 +1032,17 @@ int qw_state_import(qw_state* st, const uint64_t* keys, const double* re, const 
   std::vector<double2> a;
   int rc = canonical_branches(st->ctx, keys, re, im, m, k, a);
   if (rc) return rc;
+  int64_t written = 0;
+  rc = total_written(st, stream, &written);
+  if (rc) return rc;
   rc = state_clear(st, stream);
   if (rc) return rc;
   st->prepared = false;
   st->steps_since_init = 0;
   free_graphs(st);  // the list pointers may change
-  return import_branches(st, k, a, stream);
+  rc = import_branches(st, k, a, stream);
+  if (rc) return rc;
+  return restart_counts(st, written, stream);
 }
 
 int qw_cks_coeffs(int64_t beta, int32_t j0, double* out) {

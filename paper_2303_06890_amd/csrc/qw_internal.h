@@ -101,7 +101,7 @@ struct StepArgs {
   Matrix m;
   Slots in, out;
   List L;
-  unsigned long long* acc;  // per-workgroup running count of branches written
+  unsigned long long* acc;  // per-workgroup running count of kept outputs (a Q1 output twice)
   uint32_t* stepno;         // per-wavefront step counter (indexes coefm), kMaxWaves entries
   int32_t mode;             // kStep: W; kSwap: S only
   int32_t wpb;              // wavefronts per workgroup (set by the launcher)
@@ -141,10 +141,11 @@ hipError_t launch_adjoint(const AdjArgs& a, int grid, int block, hipStream_t str
 hipError_t launch_qbs_table(const Matrix& m, SlotRec* rec, hipStream_t stream);
 hipError_t launch_init(const Matrix& m, const double2* b, Slots out, double tau, hipStream_t stream);
 hipError_t launch_fill(void* p, int64_t bytes, hipStream_t stream);
-// Reductions over a state: kind 0 = count, 1 = norm^2 (per-block partials in
-// `partial`, length >= grid); kind 2 = j marginal into out (N-vector, must be
-// zero); kind 3 = projection <psi~_j|state> into out (interleaved complex).
-// `grid` applies to kinds 0 and 1.
+// Reductions over a state: kind 0 = count, 1 = norm^2, 4 = count of the Q1
+// plane (per-block partials in `partial`, length >= grid); kind 2 = j
+// marginal into out (N-vector, must be zero); kind 3 = projection
+// <psi~_j|state> into out (interleaved complex).  `grid` applies to kinds 0,
+// 1 and 4.
 hipError_t launch_measure(const Matrix& m, Slots st, List L, int32_t kind, double* partial, double* out, int grid,
                           hipStream_t stream);
 hipError_t launch_export(const Matrix& m, Slots st, List L, uint64_t* keys, double2* amps, uint32_t* count,

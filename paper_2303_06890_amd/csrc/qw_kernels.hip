@@ -350,17 +350,22 @@ __device__ __forceinline__ double block_sum(double v, double* sh) {
 __device__ __forceinline__ double2 r1_of(const Slots& st, int64_t h) { return cscale(st.R1[h], st.r1s); }
 
 // Outputs of one slot for the next step (step and adjoint kernels).
-// o0, o1: reflected (or swapped) group amplitudes of K(q, b2) before S;
-// y1: Q1_in, which becomes the next R1 (negated by a walk step, not by the
-// swap) without being moved: the input's Q1 plane is the output's R1
-// storage, and the sign goes with the state; y0: Q0_in (read only for slots
-// without a partner), negated when `neg`.  out.Q1 is in.R1's plane: each
-// lane reads its R1 input before it writes its Q1 output at the same home.
+// o0, o1: reflected (or swapped) group amplitudes of K(q, b2) before S; o1
+// goes to Q1 at h, o0 to R0 at the partner's home (or, without a partner, to
+// Q0 at h, with R0 at h <- Q0_in, negated when `neg`).  Q1_in becomes the
+// next R1 (negated by a walk step, not by the swap) without being moved or
+// read: the input's Q1 plane is the output's R1 storage, and the sign goes
+// with the state.  out.Q1 is in.R1's plane: each lane reads its R1 input
+// before it writes its Q1 output at the same home.
+// Counts: every kept output once, and a kept Q1 output once more for the R1
+// branch it becomes one launch later; the host corrects the sum by the Q1
+// branches of the present state.
 __device__ __forceinline__ void write_slot(const Slots& in, const Slots& out, int64_t base, int64_t h,
-                                           const SlotRec& rc, double2 o0, double2 o1, double2 y1, bool neg,
-                                           double tau, unsigned& cnt) {
-  out.Q1[h] = prune(o1, tau, cnt);
-  cnt += nonzero(y1);  // pruned when it was written
+                                           const SlotRec& rc, double2 o0, double2 o1, bool neg, double tau,
+                                           unsigned& cnt) {
+  unsigned q1 = 0;
+  out.Q1[h] = prune(o1, tau, q1);
+  cnt += 2 * q1;
   if (rc.part >= 0) {
     out.R0[base + rc.part] = prune(o0, tau, cnt);
   } else {
@@ -393,7 +398,7 @@ __device__ __forceinline__ unsigned step_wave(const StepArgs& a, int64_t w, int 
   const int64_t base = x.I.item_base;
   int64_t h[SLM];
   SlotRec rc[SLM];
-  double2 x0[SLM], x1[SLM], y1[SLM];
+  double2 x0[SLM], x1[SLM];
   double vi[SLM];
   Rot r[SLM];
 #pragma unroll
@@ -404,7 +409,6 @@ __device__ __forceinline__ unsigned step_wave(const StepArgs& a, int64_t w, int 
       if (ENC == kEncComplex) vi[i] = a.m.vim[h[i]];
       x0[i] = a.in.R0[h[i]];
       x1[i] = r1_of(a.in, h[i]);
-      y1[i] = a.in.Q1[h[i]];
     }
   }
   const bool step = FAST || a.mode == kStep;
@@ -436,7 +440,7 @@ __device__ __forceinline__ unsigned step_wave(const StepArgs& a, int64_t w, int 
         o0 = csub(cmul(tc, r[i].f), x0[i]);
         o1 = csub(cscale(tc, r[i].g), x1[i]);
       }
-      write_slot(a.in, a.out, base, h[i], rc[i], o0, o1, y1[i], step, a.tau, cnt);
+      write_slot(a.in, a.out, base, h[i], rc[i], o0, o1, step, a.tau, cnt);
     }
   }
   return cnt;
@@ -570,7 +574,7 @@ __device__ __forceinline__ void adjoint_wave(const AdjArgs& a, int64_t w, int la
   const int64_t base = x.I.item_base;
   int64_t h[SLM];
   SlotRec rc[SLM];
-  double2 x0[SLM], x1[SLM], y1[SLM], m0[SLM], m1[SLM], z1[SLM];
+  double2 x0[SLM], x1[SLM], m0[SLM], m1[SLM];
   Rot r[SLM];
 #pragma unroll
   for (int i = 0; i < SLM; ++i) {
@@ -579,10 +583,8 @@ __device__ __forceinline__ void adjoint_wave(const AdjArgs& a, int64_t w, int la
       rc[i] = a.m.rec[h[i]];
       x0[i] = a.in.R0[h[i]];
       x1[i] = r1_of(a.in, h[i]);
-      y1[i] = a.in.Q1[h[i]];
       m0[i] = a.lin.R0[h[i]];
       m1[i] = r1_of(a.lin, h[i]);
-      z1[i] = a.lin.Q1[h[i]];
     }
   }
   double2 c = zero2(), d = zero2();
@@ -611,8 +613,8 @@ __device__ __forceinline__ void adjoint_wave(const AdjArgs& a, int64_t w, int la
       const double2 u = cadd(cmul(c, cadd(cjmul(m0[i], dr.f), make_double2(m1[i].x * dr.g, -m1[i].y * dr.g))),
                              cjmul(d, cadd(cjmul(dr.f, q0), cscale(q1, dr.g))));
       a.dv[h[i]] += 2.0 * t * u.x;
-      write_slot(a.in, a.out, base, h[i], rc[i], q0, q1, y1[i], true, a.tau, cnt);
-      write_slot(a.lin, a.lout, base, h[i], rc[i], w0, w1, z1[i], true, a.tau, lcnt);
+      write_slot(a.in, a.out, base, h[i], rc[i], q0, q1, true, a.tau, cnt);
+      write_slot(a.lin, a.lout, base, h[i], rc[i], w0, w1, true, a.tau, lcnt);
     }
   }
 }
@@ -679,8 +681,8 @@ extern "C" __global__ void qwk_fill(uint4* p, int64_t n16) {
 
 // ----------------------------------------------------------------- measurements
 
-// Over homes and the list: kind 0 = branch count, 1 = norm^2, as per-block
-// partials.
+// Over homes and the list: kind 0 = branch count, 1 = norm^2, 4 = branches
+// of the Q1 plane, as per-block partials.
 extern "C" __global__ void __launch_bounds__(256) qwk_measure(Matrix m, Slots st, List L, int32_t kind,
                                                               double* partial) {
   __shared__ double sh[16];
@@ -700,7 +702,10 @@ extern "C" __global__ void __launch_bounds__(256) qwk_measure(Matrix m, Slots st
     } else if (it - m.items < int64_t(L.cnt)) {
       v[0] = L.amp[it - m.items];
     }
-    for (int i = 0; i < 4; ++i) acc += kind == 0 ? double(nonzero(v[i])) : norm2(v[i]);
+    if (kind == 4)
+      acc += it < m.items ? double(nonzero(v[3])) : 0.0;
+    else
+      for (int i = 0; i < 4; ++i) acc += kind == 0 ? double(nonzero(v[i])) : norm2(v[i]);
   }
   const double t = block_sum(acc, sh);
   if (threadIdx.x == 0) partial[blockIdx.x] = t;

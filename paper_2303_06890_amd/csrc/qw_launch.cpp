@@ -220,7 +220,7 @@ hipError_t launch_measure(const Matrix& m, Slots st, List L, int32_t kind, doubl
                           hipStream_t stream) {
   Matrix mm = m;
   int32_t k = kind;
-  if (kind <= 1) {
+  if (kind <= 1 || kind == 4) {
     void* p[] = {&mm, &st, &L, &k, &partial};
     return launch(F_MEASURE, grid, 256, stream, p);
   }
