@@ -95,6 +95,8 @@ struct qw_ctx {
   double* vim = nullptr;          // imaginary parts by home (complex matrices only)
   bool complex_values = false;
   int32_t word = 0;               // fixed-point word length (0: FP64 values)
+  // every slot of value 0 has a partner of value 0 or none (see StepArgs::zskip)
+  bool zclosed = true;
   qw::Inst* dinst = nullptr;
   int32_t* wave_inst = nullptr;
   qw::Inst inst0{};
@@ -153,6 +155,7 @@ struct qw_state {
   double2* b = nullptr;     // device copy of b (N-vector layout)
   double* mbuf = nullptr;   // measurement scratch: max(kMaxGrid, 2*jtotal) doubles
   bool prepared = false;    // created by T~ |b~>
+  bool zclean = false;      // R0 and Q0 of the slots of value 0 are 0 (true from T~ |b~> on)
   int64_t steps_since_init = 0;
   int64_t launches = 0;     // step launches (walk steps and swaps)
   int block = 256;
@@ -202,6 +205,8 @@ qw::StepArgs step_args(qw_state* st, int mode, double2* yacc, const double* coef
   a.tau = qw::kTau;
   a.yacc = yacc;
   a.coefm = coefm;
+  a.zskip = st->ctx->zclosed && st->zclean ? 1 : 0;
+  a.pad_ = 0;
   return a;
 }
 
@@ -404,6 +409,25 @@ int fixed_point_angles(int32_t w, std::vector<double>& val) {
   return QW_OK;
 }
 
+// Whether every slot of value 0 (a filler, or a stored zero) has a partner of
+// value 0 or none.  Then, from T~ |b~> on, the R0 and Q0 cells of these slots
+// stay 0: T~ puts b_j f / sqrt(s) = 0 there, and a step moves such a cell only
+// to the partner's R0 (negated) or to its own Q0 and back (o0 = (2/s) c f -
+// R0 = -R0 for f = 0), so the step kernels may skip them.
+bool zero_slots_closed(const HostInst& hi, const Ell& ell) {
+  const auto is_zero = [&](size_t q) { return ell.val[q] == 0.0 && (ell.vim.empty() || ell.vim[q] == 0.0); };
+  for (int32_t j = 0; j < hi.N; ++j)
+    for (int l = 0; l < hi.s; ++l) {
+      const size_t q = size_t(j) * hi.s + l;
+      if (!is_zero(q)) continue;
+      const int32_t c = ell.col[q];
+      const int32_t* row = ell.col.data() + size_t(c) * hi.s;
+      const int32_t* f = std::lower_bound(row, row + hi.s, j);
+      if (f != row + hi.s && *f == j && !is_zero(size_t(c) * hi.s + size_t(f - row))) return false;
+    }
+  return true;
+}
+
 int load_impl(qw_ctx** out, int32_t ninst, const int32_t* n, const int64_t* colptr_off, const int64_t* nnz_off,
               const int32_t* colptr, const int32_t* rowidx, const double* vals, const double* vals_im,
               const double* scales, uint32_t flags, const qw_allocator* alloc, void* stream_v);
@@ -458,6 +482,7 @@ int load_impl(qw_ctx** out, int32_t ninst, const int32_t* n, const int64_t* colp
     int rc = preprocess(n[i], colptr + co, rowidx + zo, vals + zo, vals_im ? vals_im + zo : nullptr,
                         scales ? scales[i] : 0.0, flags, hi, ell, slot_of);
     if (rc == QW_OK && word > 0) rc = fixed_point_angles(word, ell.val);
+    if (rc == QW_OK) ctx->zclosed = ctx->zclosed && zero_slots_closed(hi, ell);
     if (rc) {
       prefix_err("instance " + std::to_string(i) + ": ");
       delete ctx;
@@ -878,6 +903,7 @@ int qw_state_init(qw_state** out, qw_ctx* ctx, const double* b_re, const double*
       return set_err(QW_EDEVICE, std::string("init: ") + hipGetErrorString(e));
     }
     st->prepared = true;
+    st->zclean = true;
   }
   *out = st;
   return QW_OK;
@@ -1038,8 +1064,9 @@ int qw_state_import(qw_state* st, const uint64_t* keys, const double* re, const 
   rc = state_clear(st, stream);
   if (rc) return rc;
   st->prepared = false;
+  st->zclean = false;  // imported branches may sit in R0 or Q0 of slots of value 0
   st->steps_since_init = 0;
-  free_graphs(st);  // the list pointers may change
+  free_graphs(st);  // the list pointers and the kernel arguments change
   rc = import_branches(st, k, a, stream);
   if (rc) return rc;
   return restart_counts(st, written, stream);

@@ -109,6 +109,11 @@ struct StepArgs {
   // optional fused projection (linear solver): y[j] += coefm[step] <psi~_j|state>
   double2* yacc;
   const double* coefm;
+  // 1: every slot of value 0 has R0 = 0 (and Q0 = 0) in this state and its
+  // partner is a slot of value 0 too, so the grid-stride and g kernels skip
+  // those cells of such slots (they stay 0 under the step and the swap)
+  int32_t zskip;
+  int32_t pad_;
 };
 
 struct AdjArgs {
@@ -131,7 +136,7 @@ static_assert(sizeof(Slots) == 40 && offsetof(Slots, r1s) == 32, "Slots layout")
 static_assert(sizeof(List) == 24 && offsetof(List, cap) == 20, "List layout");
 static_assert(sizeof(SlotRec) == 16 && offsetof(SlotRec, val) == 8, "SlotRec layout");
 static_assert(sizeof(Matrix) == 160 && offsetof(Matrix, inst0) == 104, "Matrix layout");
-static_assert(sizeof(StepArgs) == 312 && offsetof(StepArgs, coefm) == 304, "StepArgs layout");
+static_assert(sizeof(StepArgs) == 320 && offsetof(StepArgs, zskip) == 312, "StepArgs layout");
 static_assert(sizeof(AdjArgs) == 408 && offsetof(AdjArgs, wpb) == 400, "AdjArgs layout");
 
 // Launchers (qw_launch.cpp).  All enqueue on `stream` and allocate nothing.

@@ -359,13 +359,16 @@ __device__ __forceinline__ double2 r1_of(const Slots& st, int64_t h) { return cs
 // before it writes its Q1 output at the same home.
 // Counts: every kept output once, and a kept Q1 output once more for the R1
 // branch it becomes one launch later; the host corrects the sum by the Q1
-// branches of the present state.
+// branches of the present state.  `zero`: a slot of value 0 in a state whose
+// R0 and Q0 cells of such slots are 0 (StepArgs::zskip): o0 is then 0 and
+// lands in such a cell, so the b2 = 0 path is skipped.
 __device__ __forceinline__ void write_slot(const Slots& in, const Slots& out, int64_t base, int64_t h,
                                            const SlotRec& rc, double2 o0, double2 o1, bool neg, double tau,
-                                           unsigned& cnt) {
+                                           unsigned& cnt, bool zero = false) {
   unsigned q1 = 0;
   out.Q1[h] = prune(o1, tau, q1);
   cnt += 2 * q1;
+  if (zero) return;
   if (rc.part >= 0) {
     out.R0[base + rc.part] = prune(o0, tau, cnt);
   } else {
@@ -400,6 +403,7 @@ __device__ __forceinline__ unsigned step_wave(const StepArgs& a, int64_t w, int 
   SlotRec rc[SLM];
   double2 x0[SLM], x1[SLM];
   double vi[SLM];
+  bool zero[SLM];
   Rot r[SLM];
 #pragma unroll
   for (int i = 0; i < SLM; ++i) {
@@ -407,8 +411,10 @@ __device__ __forceinline__ unsigned step_wave(const StepArgs& a, int64_t w, int 
       h[i] = base + (int64_t(x.h * sl + i) << x.I.nlog) + x.j;
       rc[i] = a.m.rec[h[i]];
       if (ENC == kEncComplex) vi[i] = a.m.vim[h[i]];
-      x0[i] = a.in.R0[h[i]];
       x1[i] = r1_of(a.in, h[i]);
+      // slots of value 0 (fillers): R0 stays 0 when the state allows it
+      zero[i] = S == 0 && a.zskip && rc[i].val == 0.0 && (ENC != kEncComplex || vi[i] == 0.0);
+      x0[i] = zero[i] ? zero2() : a.in.R0[h[i]];
     }
   }
   const bool step = FAST || a.mode == kStep;
@@ -440,7 +446,7 @@ __device__ __forceinline__ unsigned step_wave(const StepArgs& a, int64_t w, int 
         o0 = csub(cmul(tc, r[i].f), x0[i]);
         o1 = csub(cscale(tc, r[i].g), x1[i]);
       }
-      write_slot(a.in, a.out, base, h[i], rc[i], o0, o1, step, a.tau, cnt);
+      write_slot(a.in, a.out, base, h[i], rc[i], o0, o1, step, a.tau, cnt, zero[i]);
     }
   }
   return cnt;

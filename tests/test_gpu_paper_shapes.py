@@ -73,3 +73,23 @@ def test_chebyshev_closed_form_full_size(Q, name, nsteps):
         err = np.abs(y - ref[t]).max()
         assert err < 1e-11, (name, t, err)
         assert abs(st.norm2() - 1.0) < 1e-12, (name, t)
+
+
+def test_largest_dimension(Q):
+    """The largest dimension the 64-bit key holds: N = 32768 (4 log2 N + 2 =
+    62 bits), band matrix with s = 64 (2.1 M slots), against the Chebyshev
+    closed form and the branch-count bound 4 N s."""
+    csc = W.band_matrix(32768, 31, seed=91)
+    b = W.uniform_b(32768)
+    walk = Q.Walk(csc)
+    info = walk.info[0]
+    assert (info["N"], info["s"], info["nbits"]) == (32768, 64, 15)
+    ref = _chebyshev(csc, info["scale"], info["s"], b, (1, 2, 10))
+    st = walk.state(b)
+    done = 0
+    for t in (1, 2, 10):
+        st.step(t - done)
+        done = t
+        assert np.abs(st.project() - ref[t]).max() < 1e-11, t
+        assert abs(st.norm2() - 1.0) < 1e-12
+        assert st.count() <= 4 * 32768 * 64

@@ -156,6 +156,61 @@ def test_total_written_is_the_sum_of_branch_counts(Q, raw):
     assert tail == sum(dc)
 
 
+@pytest.mark.parametrize("start", ["prepared", "raw", "imported"])
+def test_zero_slots_in_grid_stride_and_mixed_kernels(Q, oracle_mod, start):
+    """Slots of value 0 (fillers): from T~|b~> the grid-stride and mixed-s
+    kernels skip their R0/Q0 cells, which stay 0; after a raw start or an
+    import those cells may hold branches and nothing is skipped.  Both must
+    match the oracle."""
+    csc = W.offset_matrix(200, 5, seed=81)  # s = 8: three filler slots per row
+    b = W.gaussian_b(200, seed=82)
+    raw = start == "raw"
+    walk, st, ost = _pair(Q, oracle_mod, csc, b, raw=raw)
+    if start == "imported":
+        ost.step(3)
+        keys, amps = ost.export()
+        st.step(3).import_(keys, amps)
+    st.set_launch(64, 8)  # too few workgroups for one pass: the grid-stride kernel
+    st.step(40)
+    ost.step(40)
+    _check(st, ost, f"{start} start, grid-stride")
+    # the same matrix beside one of another s in one context: the g kernels
+    other = W.offset_matrix(64, 12, seed=83)
+    bw = Q.Walk([csc, other])
+    bs = bw.state([b, W.uniform_b(64)], raw=raw).step(25)
+    keys, amps = bs.export()
+    from tests.test_gpu_batched import _slice, unpack
+
+    gk, ga = _slice(unpack(keys, bw.nbits), amps, 0, walk.nbits)
+    o = oracle_mod.OracleState(oracle_mod.OracleMatrix(csc)).set_b(b)
+    if not raw:
+        o.T()
+    ok, oa = o.step(25).export()
+    compare_states(gk, ga, ok, oa, where=f"{start} start, mixed-s context")
+
+
+def test_zero_slot_with_a_valued_partner(Q, oracle_mod):
+    """An unsymmetric pattern (loaded without the symmetry check) whose filler
+    slot has a partner of nonzero value: that filler's R0 fills up, so nothing
+    may be skipped."""
+    a = np.zeros((6, 6))
+    a[np.arange(6), np.arange(6)] = 0.5
+    a[1, 0] = 0.4          # column 0 holds rows 0, 1; column 1 only row 1
+    a[3, 2] = a[2, 3] = 0.3
+    a[5, 4] = 0.2
+    csc = W.from_dense(a)
+    b = W.gaussian_b(6, seed=84)
+    walk = Q.Walk(csc, symmetric=False)
+    om = oracle_mod.OracleMatrix(csc)
+    for shape in [(64, 1), (256, 0)]:
+        st = walk.state(b)
+        st.set_launch(*shape)
+        ost = oracle_mod.OracleState(om).set_b(b).T()
+        st.step(1).step(4).step(25)  # a direct step, then graph replays
+        ost.step(30)
+        _check(st, ost, f"unsymmetric pattern, shape {shape}")
+
+
 def test_checkpoint_resume(Q, oracle_mod):
     csc = W.offset_matrix(256, 8, seed=15)
     b = W.uniform_b(256)

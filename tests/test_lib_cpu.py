@@ -138,6 +138,29 @@ def test_hermitian_loader_validation(lib):
     assert rc == -1 and "vals_im" in msg
 
 
+def test_rejects_keys_wider_than_64_bits(lib):
+    """4 log2 N + 2 key bits (plus the instance bits of a batch) must fit 64:
+    N = 65536 does not (66 bits); eight instances of N = 32768 do not either
+    (3 + 62)."""
+    from paper_2303_06890_amd import _lib
+
+    big = W.Csc(65536, np.arange(65537, dtype=np.int32), np.arange(65536, dtype=np.int32), np.full(65536, 0.5))
+    rc, msg = _load(lib, big)
+    assert rc == -5 and "64 bits" in msg
+    h = ctypes.c_void_p()
+    n = np.full(8, 32768, np.int32)
+    colptr = np.concatenate([np.arange(32769, dtype=np.int32)] * 8)
+    rowidx = np.concatenate([np.arange(32768, dtype=np.int32)] * 8)
+    vals = np.full(8 * 32768, 0.5)
+    coff = (np.arange(8) * 32769).astype(np.int64)
+    zoff = (np.arange(8) * 32768).astype(np.int64)
+    ip, lp, dp = ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_double)
+    rc = lib.qw_load_csc_batched(ctypes.byref(h), 8, n.ctypes.data_as(ip), coff.ctypes.data_as(lp),
+                                 zoff.ctypes.data_as(lp), colptr.ctypes.data_as(ip), rowidx.ctypes.data_as(ip),
+                                 vals.ctypes.data_as(dp), None, 1, None, None)
+    assert rc == -5 and "64 bits" in lib.qw_last_error().decode()
+
+
 def test_fixed_point_load_validation(lib):
     """Fixed-point data (QW_WORD_LENGTH): values must be words of the given
     length, the length at most 32, the matrix real.  All checked on the host
