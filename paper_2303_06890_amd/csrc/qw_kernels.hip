@@ -80,19 +80,21 @@ struct Rot {
   double2 f;
   double g;
 };
-__device__ __forceinline__ Rot rotation(double a, int j, int k) {
+// `upper`: row j <= column k.
+__device__ __forceinline__ Rot rot_real(double a, bool upper) {
   Rot r;
   const double q = sqrt(fabs(a));  // no divergent branch
-  r.f = a >= 0.0 ? make_double2(q, 0.0) : make_double2(0.0, j <= k ? q : -q);
+  r.f = a >= 0.0 ? make_double2(q, 0.0) : make_double2(0.0, upper ? q : -q);
   r.g = sqrt(1.0 - fabs(a));
   return r;
 }
+__device__ __forceinline__ Rot rotation(double a, int j, int k) { return rot_real(a, j <= k); }
 // A complex value a + i b held by row j (the row holds A*_{jk} of a Hermitian
 // matrix): off the real axis f = the principal sqrt(a + i b), so that
 // sqrt(A*_{jk}) of psi_j appears as in Sec. IV, and g = sqrt(1 - |a + i b|);
 // on the axis the real rule above.
-__device__ __forceinline__ Rot rotation(double a, double b, int j, int k) {
-  if (b == 0.0) return rotation(a, j, k);
+__device__ __forceinline__ Rot rot_cplx(double a, double b, bool upper) {
+  if (b == 0.0) return rot_real(a, upper);
   Rot r;
   const double m = hypot(a, b);
   const double t = sqrt(0.5 * (m + fabs(a)));  // > 0 since b != 0
@@ -100,17 +102,19 @@ __device__ __forceinline__ Rot rotation(double a, double b, int j, int k) {
   r.g = sqrt(1.0 - m);
   return r;
 }
+__device__ __forceinline__ Rot rotation(double a, double b, int j, int k) { return rot_cplx(a, b, j <= k); }
 // Fixed-point data: the host has turned each value into the signed angle y
 // of its rotation (units of pi); f = sin(pi |y|), with the +-i rule of the
 // real case when y < 0, and g = cos(pi y).  sincospi is exact at y = 0.
-__device__ __forceinline__ Rot rotation_angle(double y, int j, int k) {
+__device__ __forceinline__ Rot rot_angle(double y, bool upper) {
   double sv, cv;
   sincospi(fabs(y), &sv, &cv);
   Rot r;
-  r.f = !signbit(y) ? make_double2(sv, 0.0) : make_double2(0.0, j <= k ? sv : -sv);
+  r.f = !signbit(y) ? make_double2(sv, 0.0) : make_double2(0.0, upper ? sv : -sv);
   r.g = cv;
   return r;
 }
+__device__ __forceinline__ Rot rotation_angle(double y, int j, int k) { return rot_angle(y, j <= k); }
 // Rotation of slot home h whatever the matrix holds (outside the step kernels).
 __device__ __forceinline__ Rot rotation_of(const Matrix& m, double val, int64_t h, int j, int k) {
   if (m.angles) return rotation_angle(val, j, k);
@@ -362,15 +366,15 @@ __device__ __forceinline__ double2 r1_of(const Slots& st, int64_t h) { return cs
 // branches of the present state.  `zero`: a slot of value 0 in a state whose
 // R0 and Q0 cells of such slots are 0 (StepArgs::zskip): o0 is then 0 and
 // lands in such a cell, so the b2 = 0 path is skipped.
-__device__ __forceinline__ void write_slot(const Slots& in, const Slots& out, int64_t base, int64_t h,
-                                           const SlotRec& rc, double2 o0, double2 o1, bool neg, double tau,
-                                           unsigned& cnt, bool zero = false) {
+__device__ __forceinline__ void write_slot(const Slots& in, const Slots& out, int64_t base, int64_t h, int part,
+                                           double2 o0, double2 o1, bool neg, double tau, unsigned& cnt,
+                                           bool zero = false) {
   unsigned q1 = 0;
   out.Q1[h] = prune(o1, tau, q1);
   cnt += 2 * q1;
   if (zero) return;
-  if (rc.part >= 0) {
-    out.R0[base + rc.part] = prune(o0, tau, cnt);
+  if (part >= 0) {
+    out.R0[base + part] = prune(o0, tau, cnt);
   } else {
     const double2 y0 = in.Q0[h];
     out.Q0[h] = prune(o0, tau, cnt);
@@ -390,6 +394,21 @@ __device__ __forceinline__ unsigned list_entry(const List& L, int64_t e, int n, 
 
 // ----------------------------------------------------------------- walk step
 
+// A StepRec, decoded.
+struct StepSlot {
+  int part;    // partner's home relative to the instance base, or -1
+  bool upper;  // row j <= column col[q]
+  double val;
+};
+__device__ __forceinline__ StepSlot step_rec(const StepRec* p) {
+  const StepRec v = *p;  // 12 bytes, 4-byte aligned: one three-dword load
+  StepSlot t;
+  t.part = int(v.link & 0x7fffffffu) - 1;
+  t.upper = (v.link >> 31) == 0u;
+  t.val = __hiloint2double(int(v.val_hi), int(v.val_lo));
+  return t;
+}
+
 // One wavefront of the step: up to SLM slots per lane, held in registers.
 // The data loads do not depend on each other or on the instance record
 // beyond its base, so they are issued together.  FAST: walk step (not the
@@ -400,7 +419,7 @@ __device__ __forceinline__ unsigned step_wave(const StepArgs& a, int64_t w, int 
   const int sl = S ? Shape<S>::sl : (SLM == 1 ? 1 : x.I.sl);
   const int64_t base = x.I.item_base;
   int64_t h[SLM];
-  SlotRec rc[SLM];
+  StepSlot rc[SLM];
   double2 x0[SLM], x1[SLM];
   double vi[SLM];
   bool zero[SLM];
@@ -409,7 +428,7 @@ __device__ __forceinline__ unsigned step_wave(const StepArgs& a, int64_t w, int 
   for (int i = 0; i < SLM; ++i) {
     if (i < sl) {
       h[i] = base + (int64_t(x.h * sl + i) << x.I.nlog) + x.j;
-      rc[i] = a.m.rec[h[i]];
+      rc[i] = step_rec(a.m.srec + h[i]);
       if (ENC == kEncComplex) vi[i] = a.m.vim[h[i]];
       x1[i] = r1_of(a.in, h[i]);
       // slots of value 0 (fillers): R0 stays 0 when the state allows it
@@ -422,9 +441,9 @@ __device__ __forceinline__ unsigned step_wave(const StepArgs& a, int64_t w, int 
 #pragma unroll
   for (int i = 0; i < SLM; ++i) {
     if (i < sl) {
-      r[i] = ENC == kEncComplex ? rotation(rc[i].val, vi[i], x.j, rc[i].col)
-             : ENC == kEncAngle ? rotation_angle(rc[i].val, x.j, rc[i].col)
-                                : rotation(rc[i].val, x.j, rc[i].col);
+      r[i] = ENC == kEncComplex ? rot_cplx(rc[i].val, vi[i], rc[i].upper)
+             : ENC == kEncAngle ? rot_angle(rc[i].val, rc[i].upper)
+                                : rot_real(rc[i].val, rc[i].upper);
       c = cadd(c, along(r[i], x0[i], x1[i]));
     }
   }
@@ -446,7 +465,7 @@ __device__ __forceinline__ unsigned step_wave(const StepArgs& a, int64_t w, int 
         o0 = csub(cmul(tc, r[i].f), x0[i]);
         o1 = csub(cscale(tc, r[i].g), x1[i]);
       }
-      write_slot(a.in, a.out, base, h[i], rc[i], o0, o1, step, a.tau, cnt, zero[i]);
+      write_slot(a.in, a.out, base, h[i], rc[i].part, o0, o1, step, a.tau, cnt, zero[i]);
     }
   }
   return cnt;
@@ -542,9 +561,10 @@ namespace qw {
 // rev = i_{col[q]}(j): where row j's slot q points back into its column's
 // row (-1: filler or asymmetric pattern).  The record of slot (j, l) at its
 // home holds col, the partner's home relative to the instance base
-// (rev * N + col, or -1) and the value.
+// (rev * N + col, or -1) and the value; the step kernels' record holds the
+// partner, whether j <= col, and the value.
 
-extern "C" __global__ void __launch_bounds__(256) qwk_qbs_table(Matrix m, SlotRec* rec) {
+extern "C" __global__ void __launch_bounds__(256) qwk_qbs_table(Matrix m, SlotRec* rec, StepRec* srec) {
   const int64_t stride = int64_t(gridDim.x) * blockDim.x;
   for (int64_t it = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; it < m.items; it += stride) {
     const Inst I = m.inst[find_inst<&Inst::item_base>(m, it)];
@@ -558,7 +578,14 @@ extern "C" __global__ void __launch_bounds__(256) qwk_qbs_table(Matrix m, SlotRe
     sr.col = c;
     sr.part = qbs(m.col + I.item_base + (int64_t(c) << I.hbits), I.s, j, p) ? (p << I.nlog) + c : -1;
     sr.val = m.val[it];
-    rec[home(I, j, l)] = sr;
+    const int64_t hh = home(I, j, l);
+    rec[hh] = sr;
+    const uint64_t bits = uint64_t(__double_as_longlong(sr.val));
+    StepRec t;
+    t.link = uint32_t(sr.part + 1) | (j > c ? 0x80000000u : 0u);  // part + 1 <= N s < 2^31
+    t.val_lo = uint32_t(bits);
+    t.val_hi = uint32_t(bits >> 32);
+    srec[hh] = t;
   }
 }
 
@@ -619,8 +646,8 @@ __device__ __forceinline__ void adjoint_wave(const AdjArgs& a, int64_t w, int la
       const double2 u = cadd(cmul(c, cadd(cjmul(m0[i], dr.f), make_double2(m1[i].x * dr.g, -m1[i].y * dr.g))),
                              cjmul(d, cadd(cjmul(dr.f, q0), cscale(q1, dr.g))));
       a.dv[h[i]] += 2.0 * t * u.x;
-      write_slot(a.in, a.out, base, h[i], rc[i], q0, q1, true, a.tau, cnt);
-      write_slot(a.lin, a.lout, base, h[i], rc[i], w0, w1, true, a.tau, lcnt);
+      write_slot(a.in, a.out, base, h[i], rc[i].part, q0, q1, true, a.tau, cnt);
+      write_slot(a.lin, a.lout, base, h[i], rc[i].part, w0, w1, true, a.tau, lcnt);
     }
   }
 }
