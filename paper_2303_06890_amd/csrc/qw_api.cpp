@@ -103,9 +103,11 @@ struct qw_ctx {
   int32_t* col = nullptr;
   double* val = nullptr;
   qw::SlotRec* rec = nullptr;
-  qw::StepRec* srec = nullptr;
-  void* rec_raw = nullptr;   // allocations behind rec and srec
-  void* srec_raw = nullptr;
+  uint32_t* slink = nullptr;
+  double* sval = nullptr;
+  void* rec_raw = nullptr;   // allocations behind rec, slink and sval
+  void* slink_raw = nullptr;
+  void* sval_raw = nullptr;
   double* vim = nullptr;          // imaginary parts by home (complex matrices only)
   bool complex_values = false;
   int32_t word = 0;               // fixed-point word length (0: FP64 values)
@@ -119,7 +121,8 @@ struct qw_ctx {
     m.col = col;
     m.val = val;
     m.rec = rec;
-    m.srec = srec;
+    m.slink = slink;
+    m.sval = sval;
     m.vim = vim;
     m.inst = dinst;
     m.wave_inst = wave_inst;
@@ -454,7 +457,8 @@ void ctx_release(qw_ctx* ctx) {
   ctx->alloc.put(ctx->col);
   ctx->alloc.put(ctx->val);
   ctx->alloc.put(ctx->rec_raw);
-  ctx->alloc.put(ctx->srec_raw);
+  ctx->alloc.put(ctx->slink_raw);
+  ctx->alloc.put(ctx->sval_raw);
   ctx->alloc.put(ctx->vim);
   ctx->alloc.put(ctx->dinst);
   ctx->alloc.put(ctx->wave_inst);
@@ -577,11 +581,12 @@ int load_impl(qw_ctx** out, int32_t ninst, const int32_t* n, const int64_t* colp
   ctx->col = static_cast<int32_t*>(ctx->alloc.get(sizeof(int32_t) * items));
   ctx->val = static_cast<double*>(ctx->alloc.get(sizeof(double) * items));
   ctx->rec = static_cast<qw::SlotRec*>(ctx->alloc.get_paged(sizeof(qw::SlotRec) * items, &ctx->rec_raw));
-  ctx->srec = static_cast<qw::StepRec*>(ctx->alloc.get_paged(sizeof(qw::StepRec) * items, &ctx->srec_raw));
+  ctx->slink = static_cast<uint32_t*>(ctx->alloc.get_paged(sizeof(uint32_t) * items, &ctx->slink_raw));
+  ctx->sval = static_cast<double*>(ctx->alloc.get_paged(sizeof(double) * items, &ctx->sval_raw));
   ctx->dinst = static_cast<qw::Inst*>(ctx->alloc.get(sizeof(qw::Inst) * ninst));
   ctx->wave_inst = static_cast<int32_t*>(ctx->alloc.get(sizeof(int32_t) * waves));
   if (vals_im) ctx->vim = static_cast<double*>(ctx->alloc.get(sizeof(double) * items));
-  if (!ctx->col || !ctx->val || !ctx->rec || !ctx->srec || !ctx->dinst || !ctx->wave_inst ||
+  if (!ctx->col || !ctx->val || !ctx->rec || !ctx->slink || !ctx->sval || !ctx->dinst || !ctx->wave_inst ||
       (vals_im && !ctx->vim)) {
     ctx_release(ctx);
     return set_err(QW_ENOMEM, "device allocation failed for the matrix");
@@ -597,8 +602,9 @@ int load_impl(qw_ctx** out, int32_t ninst, const int32_t* n, const int64_t* colp
     e = hipMemcpyAsync(ctx->wave_inst, hwave.data(), sizeof(int32_t) * waves, hipMemcpyHostToDevice, stream);
   // O_s'^-1 of every reflected output: the QBS of j in row col[q], once per matrix
   if (e == hipSuccess) e = qw::launch_fill(ctx->rec, int64_t(sizeof(qw::SlotRec)) * items, stream);
-  if (e == hipSuccess) e = qw::launch_fill(ctx->srec, (int64_t(sizeof(qw::StepRec)) * items + 15) / 16 * 16, stream);
-  if (e == hipSuccess) e = qw::launch_qbs_table(ctx->mat(), ctx->rec, ctx->srec, stream);
+  if (e == hipSuccess) e = qw::launch_fill(ctx->slink, int64_t(sizeof(uint32_t)) * items, stream);
+  if (e == hipSuccess) e = qw::launch_fill(ctx->sval, int64_t(sizeof(double)) * items, stream);
+  if (e == hipSuccess) e = qw::launch_qbs_table(ctx->mat(), ctx->rec, ctx->slink, ctx->sval, stream);
   if (e == hipSuccess) e = hipStreamSynchronize(stream);  // host vectors go out of scope
   if (e != hipSuccess) {
     ctx_release(ctx);

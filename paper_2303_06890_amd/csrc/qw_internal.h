@@ -72,22 +72,17 @@ struct SlotRec {
 // signed angle y (in units of pi, |y| <= 1/2) of its conditional rotation,
 // f = sin(pi |y|) (times +-i when y < 0), g = cos(pi y); a zero value has
 // y = 0 (f = 0, g = 1).
-// What the step kernels read of a slot: 12 bytes at its home, one
-// three-dword load.  link: bits 0-30 hold part + 1 (0: no partner); bit 31 is
-// set when row j > column col[q], the one fact of the column that the
-// rotation's rule for negative values needs.  val_lo, val_hi: the value's
-// 64-bit pattern.
-struct StepRec {
-  uint32_t link;
-  uint32_t val_lo;
-  uint32_t val_hi;
-};
-
 struct Matrix {
   const int32_t* col;        // ELL column indices (row-major), sorted inside each row
   const double* val;         // ELL values (row-major)
   const SlotRec* rec;        // slot records (by home)
-  const StepRec* srec;       // the step kernels' slot records (by home)
+  // What the step kernels read of a slot (12 bytes, by home, two planes so
+  // that a wavefront's eight-row runs stay sector-aligned): slink bits 0-30
+  // hold part + 1 (0: no partner) and bit 31 is set when row j > column
+  // col[q], the one fact of the column that the rule for negative values
+  // needs; sval is the value.
+  const uint32_t* slink;
+  const double* sval;
   const double* vim;         // imaginary parts of the values by home (NULL: a real matrix)
   const Inst* inst;
   const int32_t* wave_inst;  // instance of every step-kernel wavefront
@@ -147,16 +142,15 @@ static_assert(sizeof(Inst) == 56 && offsetof(Inst, inv_sqrt_s) == 48, "Inst layo
 static_assert(sizeof(Slots) == 40 && offsetof(Slots, r1s) == 32, "Slots layout");
 static_assert(sizeof(List) == 24 && offsetof(List, cap) == 20, "List layout");
 static_assert(sizeof(SlotRec) == 16 && offsetof(SlotRec, val) == 8, "SlotRec layout");
-static_assert(sizeof(StepRec) == 12, "StepRec layout");
-static_assert(sizeof(Matrix) == 168 && offsetof(Matrix, inst0) == 112, "Matrix layout");
-static_assert(sizeof(StepArgs) == 328 && offsetof(StepArgs, zskip) == 320, "StepArgs layout");
-static_assert(sizeof(AdjArgs) == 416 && offsetof(AdjArgs, wpb) == 408, "AdjArgs layout");
+static_assert(sizeof(Matrix) == 176 && offsetof(Matrix, inst0) == 120, "Matrix layout");
+static_assert(sizeof(StepArgs) == 336 && offsetof(StepArgs, zskip) == 328, "StepArgs layout");
+static_assert(sizeof(AdjArgs) == 424 && offsetof(AdjArgs, wpb) == 416, "AdjArgs layout");
 
 // Launchers (qw_launch.cpp).  All enqueue on `stream` and allocate nothing.
 hipError_t launch_step(const StepArgs& a, int grid, int block, hipStream_t stream);
 hipError_t launch_adjoint(const AdjArgs& a, int grid, int block, hipStream_t stream);
 // Slot records of both kinds (the QBS of every reflected output, once per matrix).
-hipError_t launch_qbs_table(const Matrix& m, SlotRec* rec, StepRec* srec, hipStream_t stream);
+hipError_t launch_qbs_table(const Matrix& m, SlotRec* rec, uint32_t* slink, double* sval, hipStream_t stream);
 hipError_t launch_init(const Matrix& m, const double2* b, Slots out, double tau, hipStream_t stream);
 hipError_t launch_fill(void* p, int64_t bytes, hipStream_t stream);
 // Reductions over a state: kind 0 = count, 1 = norm^2, 4 = count of the Q1

@@ -394,18 +394,18 @@ __device__ __forceinline__ unsigned list_entry(const List& L, int64_t e, int n, 
 
 // ----------------------------------------------------------------- walk step
 
-// A StepRec, decoded.
+// The step kernels' record of slot home h, decoded.
 struct StepSlot {
   int part;    // partner's home relative to the instance base, or -1
   bool upper;  // row j <= column col[q]
   double val;
 };
-__device__ __forceinline__ StepSlot step_rec(const StepRec* p) {
-  const StepRec v = *p;  // 12 bytes, 4-byte aligned: one three-dword load
+__device__ __forceinline__ StepSlot step_rec(const Matrix& m, int64_t h) {
+  const uint32_t link = m.slink[h];
   StepSlot t;
-  t.part = int(v.link & 0x7fffffffu) - 1;
-  t.upper = (v.link >> 31) == 0u;
-  t.val = __hiloint2double(int(v.val_hi), int(v.val_lo));
+  t.val = m.sval[h];
+  t.part = int(link & 0x7fffffffu) - 1;
+  t.upper = (link >> 31) == 0u;
   return t;
 }
 
@@ -428,7 +428,7 @@ __device__ __forceinline__ unsigned step_wave(const StepArgs& a, int64_t w, int 
   for (int i = 0; i < SLM; ++i) {
     if (i < sl) {
       h[i] = base + (int64_t(x.h * sl + i) << x.I.nlog) + x.j;
-      rc[i] = step_rec(a.m.srec + h[i]);
+      rc[i] = step_rec(a.m, h[i]);
       if (ENC == kEncComplex) vi[i] = a.m.vim[h[i]];
       x1[i] = r1_of(a.in, h[i]);
       // slots of value 0 (fillers): R0 stays 0 when the state allows it
@@ -564,7 +564,8 @@ namespace qw {
 // (rev * N + col, or -1) and the value; the step kernels' record holds the
 // partner, whether j <= col, and the value.
 
-extern "C" __global__ void __launch_bounds__(256) qwk_qbs_table(Matrix m, SlotRec* rec, StepRec* srec) {
+extern "C" __global__ void __launch_bounds__(256) qwk_qbs_table(Matrix m, SlotRec* rec, uint32_t* slink,
+                                                                double* sval) {
   const int64_t stride = int64_t(gridDim.x) * blockDim.x;
   for (int64_t it = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; it < m.items; it += stride) {
     const Inst I = m.inst[find_inst<&Inst::item_base>(m, it)];
@@ -580,12 +581,8 @@ extern "C" __global__ void __launch_bounds__(256) qwk_qbs_table(Matrix m, SlotRe
     sr.val = m.val[it];
     const int64_t hh = home(I, j, l);
     rec[hh] = sr;
-    const uint64_t bits = uint64_t(__double_as_longlong(sr.val));
-    StepRec t;
-    t.link = uint32_t(sr.part + 1) | (j > c ? 0x80000000u : 0u);  // part + 1 <= N s < 2^31
-    t.val_lo = uint32_t(bits);
-    t.val_hi = uint32_t(bits >> 32);
-    srec[hh] = t;
+    slink[hh] = uint32_t(sr.part + 1) | (j > c ? 0x80000000u : 0u);  // part + 1 <= N s < 2^31
+    sval[hh] = sr.val;
   }
 }
 

@@ -194,9 +194,9 @@ hipError_t launch_adjoint(const AdjArgs& a, int grid, int block, hipStream_t str
   return launch(Fn(F_ADJOINT_S1 + width_index(a.m.slmax)), grid, block, stream, p);
 }
 
-hipError_t launch_qbs_table(const Matrix& m, SlotRec* rec, StepRec* srec, hipStream_t stream) {
+hipError_t launch_qbs_table(const Matrix& m, SlotRec* rec, uint32_t* slink, double* sval, hipStream_t stream) {
   Matrix mm = m;
-  void* p[] = {&mm, &rec, &srec};
+  void* p[] = {&mm, &rec, &slink, &sval};
   return launch(F_QBS_TABLE, clamp_grid(m.items, 4096), 256, stream, p);
 }
 
