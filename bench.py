@@ -332,11 +332,18 @@ def adjoint_leg(Q, W, steps: int = 20, reps: int = 5):
     forward(), gradient()
     t_fwd = min(_timed(Q, forward) for _ in range(reps))
     t_grad = min(_timed(Q, gradient) for _ in range(reps))
+    st = walk.state(b)
+    s0 = st.stats()["total_written"]
+    st.step(steps)
+    upd = st.stats()["total_written"] - s0
     return {
         "workload": "G(1024, 8), uniform b, 20 steps, loss over 32 outcomes, 8192 values",
         "forward_ms": t_fwd,
         "forward_plus_gradient_ms": t_grad,
         "gradient_over_forward": t_grad / t_fwd,
+        "forward_updates_per_s": upd / (t_fwd / 1e3),
+        "reverse_ms_per_walk_step": (t_grad - t_fwd) / steps,
+        "note": "API calls end to end (state allocation, T~, copies and synchronisation included)",
     }
 
 
