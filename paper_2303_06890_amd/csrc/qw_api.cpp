@@ -164,7 +164,7 @@ struct qw_state {
   int cur = 0;              // parity holding the state
   double r1s = 1.0;         // buffer cur^1's Q1 plane holds r1s * (the state's R1)
   List L{};                 // branches without a static home (count on the host)
-  unsigned long long* acc = nullptr;  // per-workgroup counts of kept outputs (a Q1 output twice)
+  unsigned long long* acc = nullptr;  // counts of kept outputs (a Q1 output twice), kMaxWaves entries
   // Branches written before the counts were last restarted, and the Q1
   // branches of the state at that point (see total_written).
   int64_t written_base = 0;
@@ -655,7 +655,7 @@ int state_alloc(qw_ctx* ctx, int64_t list_cap, qw_state** out, hipStream_t strea
     ok = ok && p;
     st->buf[k] = p ? qw::Slots{p, nullptr, p + ctx->items, p + 2 * ctx->items, 1.0} : qw::Slots{};
   }
-  st->acc = static_cast<unsigned long long*>(state_get(st, sizeof(unsigned long long) * qw::kMaxGrid));
+  st->acc = static_cast<unsigned long long*>(state_get(st, sizeof(unsigned long long) * qw::kMaxWaves));
   st->stepno = static_cast<uint32_t*>(state_get(st, sizeof(uint32_t) * qw::kMaxWaves));
   st->b = static_cast<double2*>(state_get(st, sizeof(double2) * ctx->jtotal));
   st->mbuf = static_cast<double*>(state_get(st, sizeof(double) * std::max<int64_t>(qw::kMaxGrid, 2 * ctx->jtotal + 2)));
@@ -667,7 +667,7 @@ int state_alloc(qw_ctx* ctx, int64_t list_cap, qw_state** out, hipStream_t strea
   }
   hipError_t e = hipSuccess;
   for (int k = 0; k < 2 && e == hipSuccess; ++k) e = qw::launch_fill(st->buf[k].R0, int64_t(3 * pb), stream);
-  if (e == hipSuccess) e = qw::launch_fill(st->acc, sizeof(unsigned long long) * qw::kMaxGrid, stream);
+  if (e == hipSuccess) e = qw::launch_fill(st->acc, sizeof(unsigned long long) * qw::kMaxWaves, stream);
   if (e == hipSuccess) e = qw::launch_fill(st->stepno, sizeof(uint32_t) * qw::kMaxWaves, stream);
   if (e == hipSuccess) e = qw::launch_fill(st->b, sizeof(double2) * ctx->jtotal, stream);
   if (e != hipSuccess) {
@@ -782,8 +782,8 @@ int measure_partials(qw_state* st, int kind, double* result, hipStream_t stream)
 // therefore hold the true sum plus (Q1 branches after launch K) minus (Q1
 // branches before launch 1).
 int total_written(qw_state* st, hipStream_t stream, int64_t* out) {
-  std::vector<unsigned long long> h(qw::kMaxGrid);
-  QW_HIP(hipMemcpyAsync(h.data(), st->acc, sizeof(unsigned long long) * qw::kMaxGrid, hipMemcpyDeviceToHost, stream));
+  std::vector<unsigned long long> h(qw::kMaxWaves);
+  QW_HIP(hipMemcpyAsync(h.data(), st->acc, sizeof(unsigned long long) * qw::kMaxWaves, hipMemcpyDeviceToHost, stream));
   QW_HIP(hipStreamSynchronize(stream));
   unsigned long long t = 0;
   for (auto v : h) t += v;
@@ -797,7 +797,7 @@ int total_written(qw_state* st, hipStream_t stream, int64_t* out) {
 // Restart the counters after the state was changed by something other than a
 // launch of the step kernels (an import); `written` is the total before.
 int restart_counts(qw_state* st, int64_t written, hipStream_t stream) {
-  QW_HIP(qw::launch_fill(st->acc, sizeof(unsigned long long) * qw::kMaxGrid, stream));
+  QW_HIP(qw::launch_fill(st->acc, sizeof(unsigned long long) * qw::kMaxWaves, stream));
   double q1 = 0.0;
   int rc = measure_partials(st, 4, &q1, stream);
   if (rc) return rc;

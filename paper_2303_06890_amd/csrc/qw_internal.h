@@ -108,7 +108,7 @@ struct StepArgs {
   Matrix m;
   Slots in, out;
   List L;
-  unsigned long long* acc;  // per-workgroup running count of kept outputs (a Q1 output twice)
+  unsigned long long* acc;  // running counts of kept outputs (a Q1 output twice), kMaxWaves entries
   uint32_t* stepno;         // per-wavefront step counter (indexes coefm), kMaxWaves entries
   int32_t mode;             // kStep: W; kSwap: S only
   int32_t wpb;              // wavefronts per workgroup (set by the launcher)
