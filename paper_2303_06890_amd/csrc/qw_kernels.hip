@@ -336,12 +336,8 @@ __device__ __forceinline__ unsigned long long wave_sum(unsigned cnt) {
   }
   return v;
 }
-// The same, added to the workgroup's counter by one lane (adjoint kernels).
-__device__ __forceinline__ void wave_count(unsigned cnt, unsigned long long* acc) {
-  const unsigned long long v = wave_sum(cnt);
-  if ((threadIdx.x & (kWave - 1)) == 0) atomicAdd(&acc[blockIdx.x], v);
-}
-// The step kernels' running count of this wavefront (kMaxWaves counters).
+// The running count of this wavefront in the step and adjoint kernels
+// (kMaxWaves counters).
 // Workgroups are dealt to the eight XCDs in turn, so the counters are grouped
 // by XCD: the 16 counters of a cache line belong to wavefronts of one XCD,
 // and a line is never written from two XCDs' caches in one launch.  Each
@@ -672,6 +668,8 @@ __device__ __forceinline__ void adjoint_body(const AdjArgs& a) {
   const int64_t lw = (int64_t(a.L.cnt) + kWave - 1) / kWave;
   const int64_t llw = (int64_t(a.LL.cnt) + kWave - 1) / kWave;
   const int64_t total = a.m.waves + lw + llw;
+  const int64_t cidx = wave_counter(wpb);
+  const unsigned long long prev = a.acc[cidx], lprev = a.lacc[cidx];
   unsigned cnt = 0, lcnt = 0;
   const int64_t wstride = int64_t(gridDim.x) * wpb;
   for (int64_t w = uniform(int(blockIdx.x * wpb + (threadIdx.x >> 6))); w < total; w += wstride) {
@@ -682,8 +680,11 @@ __device__ __forceinline__ void adjoint_body(const AdjArgs& a) {
     else
       lcnt += list_entry(a.LL, (w - a.m.waves - lw) * kWave + lane, a.m.nbits, true);
   }
-  wave_count(cnt, a.acc);
-  wave_count(lcnt, a.lacc);
+  const unsigned long long v = wave_sum(cnt), lv = wave_sum(lcnt);
+  if (lane == 0) {
+    a.acc[cidx] = prev + v;
+    a.lacc[cidx] = lprev + lv;
+  }
 }
 
 }  // namespace qw
