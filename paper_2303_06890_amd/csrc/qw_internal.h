@@ -11,7 +11,7 @@ namespace qw {
 
 constexpr int kWave = 64;       // CDNA wavefront width
 constexpr int kMaxS = 64;       // largest QRAM row length handled (one wave per group)
-constexpr int kMaxGrid = 65536;  // largest step-kernel grid (per-workgroup counters)
+constexpr int kMaxGrid = 65536;  // largest step-kernel grid
 constexpr int kMaxBlock = 256;  // largest step-kernel workgroup
 constexpr int kMaxWaves = kMaxGrid * (kMaxBlock / kWave);  // per-wavefront counters
 constexpr double kTau = 1e-13;  // pruning threshold applied after every step

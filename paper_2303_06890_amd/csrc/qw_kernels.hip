@@ -35,9 +35,10 @@
 // the state carries (a walk step leaves -1, the swap +1).  So a step writes
 // three planes (R0, Q1 and the fillers' Q0) and reads R1 from the plane it
 // then overwrites with Q1.
-// Every output address receives exactly one write per step (0 when pruned),
-// so there is no atomic, no compaction and no clearing pass; the result is
-// independent of scheduling.  For matrices whose rows share their offset
+// Every output address receives exactly one write per step (0 when pruned;
+// the cells that provably stay 0, of slots of value 0, are skipped), so there
+// is no atomic, no compaction and no clearing pass; the result is independent
+// of scheduling.  For matrices whose rows share their offset
 // pattern (band and circulant-offset matrices) the partner writes R0_out[h']
 // of a wavefront are contiguous too.  Branches outside that span (only from
 // raw starts or imports) sit in a list that W maps in place to -S(key).
