@@ -264,6 +264,37 @@ def test_band_s64_20_steps(Q, oracle_mod):
         _check(st, ost, f"band step {t}")
 
 
+def test_degenerate_cases(Q, oracle_mod):
+    """The method's degenerate cases: a raw single-column start is one branch
+    bouncing between two keys for ever; a slot with |a| = 1 has g = 0, so
+    T~|b~> holds 2 N s - 1 branches and the steady count is 3 N s - 2; a
+    diagonal matrix (s = 1) and a 2 x 2 block."""
+    csc = W.offset_matrix(1024, 8, seed=71)
+    walk = Q.Walk(csc)
+    st = walk.state(W.basis_b(1024, 3), raw=True)
+    ost = oracle_mod.OracleState(oracle_mod.OracleMatrix(csc)).set_b(W.basis_b(1024, 3))
+    for t in range(1, 6):
+        st.step(1)
+        ost.step(1)
+        assert st.count() == 1
+        _check(st, ost, f"raw single column, step {t}")
+    csc = W.offset_matrix(256, 8, seed=61)
+    walk, st, ost = _pair(Q, oracle_mod, csc, W.uniform_b(256))
+    Ns = walk.info[0]["N"] * walk.info[0]["s"]
+    assert st.count() == ost.count() == 2 * Ns - 1
+    st.step(8)
+    ost.step(8)
+    assert st.count() == ost.count() == 3 * Ns - 2
+    _check(st, ost, "|a| = 1 slot, step 8")
+    for a in (np.diag([0.3, 1.0, 0.5, 0.0, 0.7]), np.array([[1.0, 0.0], [0.0, 1.0]])):
+        csc = W.from_dense(a)
+        b = W.gaussian_b(a.shape[0], seed=5)
+        walk, st, ost = _pair(Q, oracle_mod, csc, b)
+        st.step(7)
+        ost.step(7)
+        _check(st, ost, f"diagonal {a.shape[0]}")
+
+
 def test_empty_state(Q):
     csc = W.offset_matrix(64, 4, seed=1)
     walk = Q.Walk(csc)
