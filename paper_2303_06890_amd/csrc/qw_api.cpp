@@ -113,6 +113,8 @@ struct qw_ctx {
   int32_t word = 0;               // fixed-point word length (0: FP64 values)
   // every slot of value 0 has a partner of value 0 or none (see StepArgs::zskip)
   bool zclosed = true;
+  // no negative and no complex value: from a real b every amplitude is real
+  bool nonneg = true;
   qw::Inst* dinst = nullptr;
   int32_t* wave_inst = nullptr;
   qw::Inst inst0{};
@@ -153,6 +155,7 @@ struct GraphEntry {
   int parity;
   double r1s;  // sign of the R1 storage when the graph starts
   int steps;
+  bool real;   // launches of the real-amplitude kernels
   hipGraphExec_t exec;
 };
 
@@ -174,6 +177,12 @@ struct qw_state {
   double* mbuf = nullptr;   // measurement scratch: max(kMaxGrid, 2*jtotal) doubles
   bool prepared = false;    // created by T~ |b~>
   bool zclean = false;      // R0 and Q0 of the slots of value 0 are 0 (true from T~ |b~> on)
+  // Real amplitudes (StepArgs::real): the state may live in 8-byte planes
+  // (R0, Q0, Q1 of each parity buffer, allocated on first use) while it is
+  // only stepped; every other use moves it back to the complex planes.
+  double* rbuf[2]{};
+  bool real_ok = false;     // every amplitude is real (T~ |b~> of a real b)
+  bool in_real = false;     // the state is in rbuf
   int64_t steps_since_init = 0;
   int64_t launches = 0;     // step launches (walk steps and swaps)
   int block = 256;
@@ -224,11 +233,76 @@ qw::StepArgs step_args(qw_state* st, int mode, double2* yacc, const double* coef
   a.yacc = yacc;
   a.coefm = coefm;
   a.zskip = st->ctx->zclosed && st->zclean ? 1 : 0;
-  a.pad_ = 0;
+  a.real = 0;
   return a;
 }
 
+// The real planes of buffer p, in the layout of view().
+qw::Slots rview(const qw_state* st, int p, double r1s) {
+  const int64_t n = st->ctx->items;
+  const auto plane = [&](int k, int i) { return reinterpret_cast<double2*>(st->rbuf[k] + i * n); };
+  return qw::Slots{plane(p, 0), plane(p ^ 1, 2), plane(p, 1), plane(p, 2), r1s};
+}
+
+qw::StepArgs step_args_real(qw_state* st) {
+  qw::StepArgs a = step_args(st, qw::kStep, nullptr, nullptr);
+  a.in = rview(st, st->cur, st->r1s);
+  a.out = rview(st, st->cur ^ 1, r1s_after(qw::kStep));
+  a.zskip = 0;
+  a.real = 1;
+  return a;
+}
+
+// Whether walk steps may run on real planes: a nonnegative matrix, a state
+// of real amplitudes with an empty list, and the f kernels' conditions.
+bool real_path(const qw_state* st, const double2* yacc) {
+  const qw_ctx* c = st->ctx;
+  return yacc == nullptr && c->nonneg && st->real_ok && c->suni > 0 && c->full && st->L.cnt == 0 &&
+         int64_t(step_grid(st)) * (st->block / qw::kWave) >= c->waves;
+}
+
+void* state_get_paged(qw_state* st, size_t bytes);
+
+// Move the state into the real planes: R0, Q0, Q1 of the current buffer and
+// the other buffer's Q1 (the R1 storage).  The other buffer's R0 and Q0 are
+// outputs of the next step; what that step does not write is 0 in both forms.
+int to_real(qw_state* st, hipStream_t stream) {
+  if (st->in_real) return QW_OK;
+  const int64_t n = st->ctx->items;
+  for (int k = 0; k < 2; ++k)
+    if (!st->rbuf[k]) {
+      st->rbuf[k] = static_cast<double*>(state_get_paged(st, sizeof(double) * 3 * n));
+      if (!st->rbuf[k]) return set_err(QW_ENOMEM, "device allocation failed for the real planes");
+      QW_HIP(qw::launch_fill(st->rbuf[k], int64_t(sizeof(double)) * 3 * n, stream));
+    }
+  QW_HIP(qw::launch_to_real(st->buf[st->cur].R0, st->rbuf[st->cur], 3 * n, stream));
+  QW_HIP(qw::launch_to_real(st->buf[st->cur ^ 1].Q1, st->rbuf[st->cur ^ 1] + 2 * n, n, stream));
+  st->in_real = true;
+  return QW_OK;
+}
+
+// And back (every use other than a real walk step calls this first).
+int to_complex(qw_state* st, hipStream_t stream) {
+  if (!st->in_real) return QW_OK;
+  const int64_t n = st->ctx->items;
+  QW_HIP(qw::launch_to_complex(st->rbuf[st->cur], st->buf[st->cur].R0, 3 * n, stream));
+  QW_HIP(qw::launch_to_complex(st->rbuf[st->cur ^ 1] + 2 * n, st->buf[st->cur ^ 1].Q1, n, stream));
+  st->in_real = false;
+  return QW_OK;
+}
+
+int launch_real(qw_state* st, hipStream_t stream) {
+  qw::StepArgs a = step_args_real(st);
+  QW_HIP(qw::launch_step(a, step_grid(st), st->block, stream));
+  st->cur ^= 1;
+  st->r1s = r1s_after(qw::kStep);
+  ++st->launches;
+  return QW_OK;
+}
+
 int launch_one(qw_state* st, int mode, hipStream_t stream, double2* yacc = nullptr, const double* coefm = nullptr) {
+  int rc = to_complex(st, stream);
+  if (rc) return rc;
   qw::StepArgs a = step_args(st, mode, yacc, coefm);
   QW_HIP(qw::launch_step(a, step_grid(st), st->block, stream));
   st->cur ^= 1;
@@ -240,11 +314,16 @@ int launch_one(qw_state* st, int mode, hipStream_t stream, double2* yacc = nullp
 // Run `n` walk steps (with the solver's fused projection when yacc is set),
 // replaying a captured graph of kGraphSteps launches when a stream is given.
 int run_steps(qw_state* st, int64_t n, hipStream_t stream, double2* yacc = nullptr, const double* coefm = nullptr) {
+  if (n == 0) return QW_OK;
+  const bool real = real_path(st, yacc);
+  int rc0 = real ? to_real(st, stream) : to_complex(st, stream);
+  if (rc0) return rc0;
+  const auto one = [&]() { return real ? launch_real(st, stream) : launch_one(st, qw::kStep, stream, yacc, coefm); };
   // A captured graph is replayed back to back, so it must start from the R1
   // sign its own steps leave: a state fresh from preparation, import or the
   // swap takes its first step directly.
   if (stream != nullptr && n > kGraphSteps && st->r1s != r1s_after(qw::kStep)) {
-    int rc = launch_one(st, qw::kStep, stream, yacc, coefm);
+    int rc = one();
     if (rc) return rc;
     --n;
   }
@@ -252,7 +331,7 @@ int run_steps(qw_state* st, int64_t n, hipStream_t stream, double2* yacc = nullp
     GraphEntry* ge = nullptr;
     for (auto& g : st->graphs)
       if (g.stream == stream && g.parity == st->cur && g.r1s == st->r1s && g.steps == kGraphSteps &&
-          yacc == nullptr)
+          g.real == real && yacc == nullptr)
         ge = &g;
     hipGraphExec_t exec = nullptr;
     if (ge) {
@@ -263,7 +342,7 @@ int run_steps(qw_state* st, int64_t n, hipStream_t stream, double2* yacc = nullp
       const int cur0 = st->cur;
       const double r1s0 = st->r1s;
       for (int i = 0; i < kGraphSteps; ++i) {
-        qw::StepArgs a = step_args(st, qw::kStep, yacc, coefm);
+        qw::StepArgs a = real ? step_args_real(st) : step_args(st, qw::kStep, yacc, coefm);
         hipError_t e = qw::launch_step(a, step_grid(st), st->block, stream);
         st->cur ^= 1;
         st->r1s = r1s_after(qw::kStep);
@@ -279,7 +358,7 @@ int run_steps(qw_state* st, int64_t n, hipStream_t stream, double2* yacc = nullp
       hipError_t e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
       (void)hipGraphDestroy(graph);
       if (e != hipSuccess) return set_err(QW_EDEVICE, std::string("graph instantiate: ") + hipGetErrorString(e));
-      if (yacc == nullptr) st->graphs.push_back({stream, cur0, r1s0, kGraphSteps, exec});
+      if (yacc == nullptr) st->graphs.push_back({stream, cur0, r1s0, kGraphSteps, real, exec});
     }
     const int64_t reps = n / kGraphSteps;
     for (int64_t r = 0; r < reps; ++r) QW_HIP(hipGraphLaunch(exec, stream));
@@ -292,7 +371,7 @@ int run_steps(qw_state* st, int64_t n, hipStream_t stream, double2* yacc = nullp
     n -= reps * kGraphSteps;
   }
   for (int64_t i = 0; i < n; ++i) {
-    int rc = launch_one(st, qw::kStep, stream, yacc, coefm);
+    int rc = one();
     if (rc) return rc;
   }
   return QW_OK;
@@ -503,6 +582,8 @@ int load_impl(qw_ctx** out, int32_t ninst, const int32_t* n, const int64_t* colp
                         scales ? scales[i] : 0.0, flags, hi, ell, slot_of);
     if (rc == QW_OK && word > 0) rc = fixed_point_angles(word, ell.val);
     if (rc == QW_OK) ctx->zclosed = ctx->zclosed && zero_slots_closed(hi, ell);
+    if (rc == QW_OK)
+      for (double v : ell.val) ctx->nonneg = ctx->nonneg && !vals_im && !std::signbit(v);
     if (rc) {
       prefix_err("instance " + std::to_string(i) + ": ");
       delete ctx;
@@ -764,6 +845,8 @@ int canonical_branches(const qw_ctx* ctx, const uint64_t* keys, const double* re
 }
 
 int measure_partials(qw_state* st, int kind, double* result, hipStream_t stream) {
+  int rc = to_complex(st, stream);
+  if (rc) return rc;
   const int grid = 256;
   QW_HIP(qw::launch_measure(st->ctx->mat(), view(st), st->L, kind, st->mbuf, nullptr, grid, stream));
   std::vector<double> h(grid);
@@ -936,6 +1019,9 @@ int qw_state_init(qw_state** out, qw_ctx* ctx, const double* b_re, const double*
     }
     st->prepared = true;
     st->zclean = true;
+    st->real_ok = true;
+    if (b_im)
+      for (int64_t j = 0; j < ctx->jtotal; ++j) st->real_ok = st->real_ok && hb[size_t(j)].y == 0.0;
   }
   *out = st;
   return QW_OK;
@@ -1011,6 +1097,8 @@ int qw_measure(qw_state* st, int32_t kind, void* out, int64_t out_len, void* str
     case QW_PROJECT: {
       const int64_t need = kind == QW_J_MARGINAL ? ctx->jtotal : 2 * ctx->jtotal;
       if (out_len < need) return set_err(QW_EINVAL, "out_len too small");
+      int rc = to_complex(st, stream);
+      if (rc) return rc;
       QW_HIP(qw::launch_fill(st->mbuf, (sizeof(double) * need + 15) / 16 * 16, stream));
       QW_HIP(qw::launch_measure(ctx->mat(), view(st), st->L, kind == QW_J_MARGINAL ? 2 : 3, nullptr,
                                 st->mbuf, 256, stream));
@@ -1032,6 +1120,7 @@ int qw_measure(qw_state* st, int32_t kind, void* out, int64_t out_len, void* str
       o[2] = int64_t(st->L.cap);
       o[3] = int64_t(st->L.cnt);
       o[4] = tw;
+      if (out_len >= 6) o[5] = st->real_ok && st->ctx->nonneg ? 1 : 0;
       return QW_OK;
     }
     default:
@@ -1097,6 +1186,8 @@ int qw_state_import(qw_state* st, const uint64_t* keys, const double* re, const 
   if (rc) return rc;
   st->prepared = false;
   st->zclean = false;  // imported branches may sit in R0 or Q0 of slots of value 0
+  st->real_ok = false;
+  st->in_real = false;  // state_clear empties the complex planes, which hold the state from here
   st->steps_since_init = 0;
   free_graphs(st);  // the list pointers and the kernel arguments change
   rc = import_branches(st, k, a, stream);
@@ -1178,6 +1269,8 @@ int qw_grad(qw_state* st, const double* w, int32_t nsteps, double* dvals, double
   if (st->ctx->word > 0)
     return set_err(QW_ENOTSUP, "the gradient is provided for FP64 values only, not fixed-point data");
   hipStream_t stream = static_cast<hipStream_t>(stream_v);
+  int rc0 = to_complex(st, stream);
+  if (rc0) return rc0;
   qw_ctx* ctx = st->ctx;
   std::vector<double> hw(static_cast<size_t>(ctx->jtotal), 0.0);
   int64_t src = 0;

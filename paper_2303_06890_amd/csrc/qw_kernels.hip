@@ -567,6 +567,134 @@ QW_STEP_KERNEL(qwk_step_y4, 4, 0, true, qw::kEncAngle)
 QW_STEP_KERNEL(qwk_step_y8, 8, 0, true, qw::kEncAngle)
 #undef QW_STEP_KERNEL
 
+namespace qw {
+
+// ----------------------------------------------------------------- real amplitudes
+// With no negative and no complex value and a real b, f = sqrt(a) and
+// g = sqrt(1 - a) are real, and so is every amplitude: T~ and the reflection
+// only multiply and add reals.  The planes then hold doubles, 8 bytes per
+// cell instead of 16; StepArgs::real is set and the plane pointers of
+// StepArgs::in/out point at double arrays of the same layout.  These kernels
+// have the f kernels' conditions (one pass, one s for every instance, every
+// row exists) and take the walk step only; the list is empty (T~ starts).
+
+__device__ __forceinline__ double row_sum_r(double v, int rpw_log) {
+  if (rpw_log <= 3) v += dpp<0x128>(v);
+  if (rpw_log <= 4) v += __shfl_xor(v, 16);
+  if (rpw_log <= 5) v += __shfl_xor(v, 32);
+  return v;
+}
+__device__ __forceinline__ double prune_r(double v, double tau, unsigned& cnt) {
+  if (fabs(v) > tau) {
+    ++cnt;
+    return v;
+  }
+  return 0.0;
+}
+
+template <int SLM, int S, int ENC>
+__device__ __forceinline__ unsigned step_wave_real(const StepArgs& a, int64_t w, int lane) {
+  const Lanes x = lanes_of<S, true>(a.m, w, lane);
+  constexpr int sl = Shape<S>::sl;
+  const int64_t base = x.I.item_base;
+  const double* R0 = reinterpret_cast<const double*>(a.in.R0);
+  const double* R1 = reinterpret_cast<const double*>(a.in.R1);
+  const double* Q0 = reinterpret_cast<const double*>(a.in.Q0);
+  double* oR0 = reinterpret_cast<double*>(a.out.R0);
+  double* oQ0 = reinterpret_cast<double*>(a.out.Q0);
+  double* oQ1 = reinterpret_cast<double*>(a.out.Q1);
+  int64_t h[SLM];
+  StepSlot rc[SLM];
+  double x0[SLM], x1[SLM], f[SLM], g[SLM];
+#pragma unroll
+  for (int i = 0; i < sl; ++i) {
+    h[i] = base + (int64_t(x.h * sl + i) << x.I.nlog) + x.j;
+    rc[i] = step_rec(a.m, h[i]);
+    x0[i] = R0[h[i]];
+    x1[i] = R1[h[i]] * a.in.r1s;
+  }
+  double c = 0.0;
+#pragma unroll
+  for (int i = 0; i < sl; ++i) {
+    if (ENC == kEncAngle) {
+      sincospi(rc[i].val, &f[i], &g[i]);  // y >= 0 here
+    } else {
+      f[i] = sqrt(rc[i].val);
+      g[i] = sqrt(1.0 - rc[i].val);
+    }
+    c += f[i] * x0[i] + x1[i] * g[i];
+  }
+  c = row_sum_r(c, x.rpw_log);
+  const double tc = c * (2.0 / double(x.I.s));
+  unsigned cnt = 0;
+#pragma unroll
+  for (int i = 0; i < sl; ++i) {
+    const double o0 = tc * f[i] - x0[i];
+    const double o1 = tc * g[i] - x1[i];
+    unsigned q1 = 0;
+    oQ1[h[i]] = prune_r(o1, a.tau, q1);
+    cnt += 2 * q1;  // counted as in write_slot
+    if (rc[i].part >= 0) {
+      oR0[base + rc[i].part] = prune_r(o0, a.tau, cnt);
+    } else {
+      const double y0 = Q0[h[i]];
+      oQ0[h[i]] = prune_r(o0, a.tau, cnt);
+      oR0[h[i]] = prune_r(-y0, a.tau, cnt);
+    }
+  }
+  return cnt;
+}
+
+template <int SLM, int S, int ENC>
+__device__ __forceinline__ void step_body_real(const StepArgs& a) {
+  const int lane = threadIdx.x & (kWave - 1);
+  const int64_t wpb = a.wpb;
+  const int64_t wid = int64_t(blockIdx.x) * wpb + (threadIdx.x >> 6);
+  const int64_t cidx = wave_counter(wpb);
+  const unsigned long long prev = a.acc[cidx];
+  const int64_t w = uniform(int(wid));
+  if (w >= a.m.waves) return;  // no list: nothing to do past the slots
+  const unsigned long long v = wave_sum(step_wave_real<SLM, S, ENC>(a, w, lane));
+  if (lane == 0) a.acc[cidx] = prev + v;
+}
+
+// Plane conversions for the switch between the two representations.
+extern "C" __global__ void __launch_bounds__(256) qwk_to_real(const double2* __restrict__ src, double* dst,
+                                                              int64_t n) {
+  const int64_t stride = int64_t(gridDim.x) * blockDim.x;
+  for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += stride) dst[i] = src[i].x;
+}
+extern "C" __global__ void __launch_bounds__(256) qwk_to_complex(const double* __restrict__ src, double2* dst,
+                                                                 int64_t n) {
+  const int64_t stride = int64_t(gridDim.x) * blockDim.x;
+  for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += stride)
+    dst[i] = make_double2(src[i], 0.0);
+}
+
+}  // namespace qw
+
+// qwk_step_rS: real amplitudes, FP64 values; qwk_step_tS: real amplitudes,
+// fixed-point data (nonnegative angles).
+#define QW_REAL_KERNEL(NAME, SLM, S, ENC)                                                            \
+  extern "C" __global__ void __launch_bounds__(256) NAME(qw::StepArgs a) {                         \
+    qw::step_body_real<SLM, S, ENC>(a);                                                             \
+  }
+QW_REAL_KERNEL(qwk_step_r1, 1, 1, qw::kEncReal)
+QW_REAL_KERNEL(qwk_step_r2, 1, 2, qw::kEncReal)
+QW_REAL_KERNEL(qwk_step_r4, 1, 4, qw::kEncReal)
+QW_REAL_KERNEL(qwk_step_r8, 1, 8, qw::kEncReal)
+QW_REAL_KERNEL(qwk_step_r16, 2, 16, qw::kEncReal)
+QW_REAL_KERNEL(qwk_step_r32, 4, 32, qw::kEncReal)
+QW_REAL_KERNEL(qwk_step_r64, 8, 64, qw::kEncReal)
+QW_REAL_KERNEL(qwk_step_t1, 1, 1, qw::kEncAngle)
+QW_REAL_KERNEL(qwk_step_t2, 1, 2, qw::kEncAngle)
+QW_REAL_KERNEL(qwk_step_t4, 1, 4, qw::kEncAngle)
+QW_REAL_KERNEL(qwk_step_t8, 1, 8, qw::kEncAngle)
+QW_REAL_KERNEL(qwk_step_t16, 2, 16, qw::kEncAngle)
+QW_REAL_KERNEL(qwk_step_t32, 4, 32, qw::kEncAngle)
+QW_REAL_KERNEL(qwk_step_t64, 8, 64, qw::kEncAngle)
+#undef QW_REAL_KERNEL
+
 
 namespace qw {
 

@@ -30,7 +30,8 @@ namespace {
 // qwk_step_y{1,2,4,8} their one-pass forms (the conditions of the g
 // kernels).  Each has an _acc twin
 // (the solver's fused projection).  Adjoint kernels (real FP64 matrices) come
-// in the four widths.
+// in the four widths.  qwk_step_r{S} and qwk_step_t{S} are the f kernels for
+// real amplitudes (8-byte planes), FP64 and fixed-point values.
 enum Fn {
   F_STEP_S1,
   F_STEP_S2,
@@ -77,6 +78,10 @@ enum Fn {
   F_IMPORT,
   F_WEIGHT,
   F_GRAD_INIT,
+  F_STEP_R1,  // real amplitudes: qwk_step_r{1..64}, then qwk_step_t{1..64}
+  F_STEP_T1 = F_STEP_R1 + 7,
+  F_TO_REAL = F_STEP_T1 + 7,
+  F_TO_COMPLEX,
   F_COUNT
 };
 
@@ -97,17 +102,29 @@ const char* const kNames[] = {
     "qwk_step_y8_acc",
     "qwk_adjoint_s1",   "qwk_adjoint_s2",   "qwk_adjoint_s4",   "qwk_adjoint_s8",   "qwk_qbs_table",
     "qwk_init",         "qwk_fill",         "qwk_measure",      "qwk_measure_rows", "qwk_export",
-    "qwk_import",       "qwk_weight",       "qwk_grad_init"};
+    "qwk_import",       "qwk_weight",       "qwk_grad_init",    "qwk_step_r1",      "qwk_step_r2",
+    "qwk_step_r4",      "qwk_step_r8",      "qwk_step_r16",     "qwk_step_r32",     "qwk_step_r64",
+    "qwk_step_t1",      "qwk_step_t2",      "qwk_step_t4",      "qwk_step_t8",      "qwk_step_t16",
+    "qwk_step_t32",     "qwk_step_t64",     "qwk_to_real",      "qwk_to_complex"};
 static_assert(sizeof(kNames) / sizeof(kNames[0]) == F_COUNT, "one kernel name per Fn");
 
 // 0..3 for slmax = 1, 2, 4, 8
 int width_index(int32_t slmax) { return slmax <= 1 ? 0 : slmax <= 2 ? 1 : slmax <= 4 ? 2 : 3; }
+
+int log2_of(int32_t s) {
+  int lg = 0;
+  while ((1 << lg) < s) ++lg;
+  return lg;
+}
 
 Fn step_kernel(const StepArgs& a, int grid, int block) {
   const Matrix& m = a.m;
   const bool acc = a.yacc != nullptr;
   const int64_t work = m.waves + (int64_t(a.L.cnt) + kWave - 1) / kWave;
   const bool one_pass = m.full && a.mode == kStep && int64_t(grid) * (block / kWave) >= work;
+  if (a.real) {  // the caller checked the conditions (launch_step re-checks them)
+    return Fn((m.angles ? F_STEP_T1 : F_STEP_R1) + log2_of(m.suni));
+  }
   int f = F_STEP_S1 + width_index(m.slmax);
   if (m.vim) {
     f = (one_pass ? F_STEP_H1 : F_STEP_C1) + width_index(m.slmax);
@@ -115,11 +132,7 @@ Fn step_kernel(const StepArgs& a, int grid, int block) {
     f = (one_pass ? F_STEP_Y1 : F_STEP_X1) + width_index(m.slmax);
   } else if (one_pass) {
     f = F_STEP_G1 + width_index(m.slmax);
-    if (m.suni > 0) {
-      int lg = 0;
-      while ((1 << lg) < m.suni) ++lg;
-      f = F_STEP_F1 + lg;
-    }
+    if (m.suni > 0) f = F_STEP_F1 + log2_of(m.suni);
   }
   return Fn(f + (acc ? int(F_STEP_COUNT_) : 0));
 }
@@ -178,6 +191,9 @@ int clamp_grid(int64_t work, int64_t limit) {
 
 hipError_t launch_step(const StepArgs& a, int grid, int block, hipStream_t stream) {
   if (block < kWave || block > kMaxBlock || block % kWave) return hipErrorInvalidValue;
+  if (a.real && (a.mode != kStep || a.yacc || a.m.vim || a.L.cnt || !a.m.full || a.m.suni <= 0 ||
+                 int64_t(grid) * (block / kWave) < a.m.waves))
+    return hipErrorInvalidValue;  // the real-amplitude kernels are one-pass walk steps only
   StepArgs c = a;
   c.wpb = block / kWave;
   void* p[] = {&c};
@@ -214,6 +230,16 @@ hipError_t launch_fill(void* ptr, int64_t bytes, hipStream_t stream) {
   uint4* q = static_cast<uint4*>(ptr);
   void* p[] = {&q, &n16};
   return launch(F_FILL, clamp_grid(n16, 4096), 256, stream, p);
+}
+
+hipError_t launch_to_real(const double2* src, double* dst, int64_t n, hipStream_t stream) {
+  void* p[] = {&src, &dst, &n};
+  return launch(F_TO_REAL, clamp_grid(n, 4096), 256, stream, p);
+}
+
+hipError_t launch_to_complex(const double* src, double2* dst, int64_t n, hipStream_t stream) {
+  void* p[] = {&src, &dst, &n};
+  return launch(F_TO_COMPLEX, clamp_grid(n, 4096), 256, stream, p);
 }
 
 hipError_t launch_measure(const Matrix& m, Slots st, List L, int32_t kind, double* partial, double* out, int grid,
