@@ -91,11 +91,12 @@ typedef struct {
 #define QW_STATS 5      /* out: int64[5] {step launches so far (walk steps and
                            swaps), current branch count, general-list capacity,
                            general-list count, branches written by all launches};
-                           with out_len >= 6 also [5] = 1 when the state's
-                           amplitudes are real (a matrix with no negative or
-                           complex value and a real b, from T~ |b~>): its walk
-                           steps then run on 8-byte planes whenever the one-pass
-                           conditions of the step kernels hold */
+                           with out_len >= 6 also [5] = 1 when every cell of
+                           the state is real or imaginary by construction (a
+                           real matrix whose negative values pair up, as in a
+                           symmetric one, and a real b, from T~ |b~>): its walk
+                           steps then run on one double per cell whenever the
+                           one-pass conditions of the step kernels hold */
 
 /* Load one matrix (Sec. V.B, preprocessing list; Sec. II.C, Fig. 1):
  *   scale: > 0 multiplies every value by `scale`; 0 selects 1/max(1, max|a|).

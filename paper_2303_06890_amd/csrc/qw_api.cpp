@@ -113,8 +113,9 @@ struct qw_ctx {
   int32_t word = 0;               // fixed-point word length (0: FP64 values)
   // every slot of value 0 has a partner of value 0 or none (see StepArgs::zskip)
   bool zclosed = true;
-  // no negative and no complex value: from a real b every amplitude is real
-  bool nonneg = true;
+  // a real matrix whose slots of negative value have partners of negative
+  // value: from a real b every cell is real or imaginary (see StepArgs::real)
+  bool realsym = true;
   qw::Inst* dinst = nullptr;
   int32_t* wave_inst = nullptr;
   qw::Inst inst0{};
@@ -253,18 +254,20 @@ qw::StepArgs step_args_real(qw_state* st) {
   return a;
 }
 
-// Whether walk steps may run on real planes: a nonnegative matrix, a state
-// of real amplitudes with an empty list, and the f kernels' conditions.
+// Whether walk steps may run on one double per cell: a real matrix whose
+// negative values pair up, a state from T~ of a real b with an empty list,
+// and the f kernels' conditions.
 bool real_path(const qw_state* st, const double2* yacc) {
   const qw_ctx* c = st->ctx;
-  return yacc == nullptr && c->nonneg && st->real_ok && c->suni > 0 && c->full && st->L.cnt == 0 &&
+  return yacc == nullptr && c->realsym && st->real_ok && c->suni > 0 && c->full && st->L.cnt == 0 &&
          int64_t(step_grid(st)) * (st->block / qw::kWave) >= c->waves;
 }
 
 void* state_get_paged(qw_state* st, size_t bytes);
 
 // Move the state into the real planes: R0, Q0, Q1 of the current buffer and
-// the other buffer's Q1 (the R1 storage).  The other buffer's R0 and Q0 are
+// the other buffer's Q1 (the R1 storage); an R0 cell of a slot of negative
+// value keeps its imaginary part.  The other buffer's R0 and Q0 are
 // outputs of the next step; what that step does not write is 0 in both forms.
 int to_real(qw_state* st, hipStream_t stream) {
   if (st->in_real) return QW_OK;
@@ -275,8 +278,10 @@ int to_real(qw_state* st, hipStream_t stream) {
       if (!st->rbuf[k]) return set_err(QW_ENOMEM, "device allocation failed for the real planes");
       QW_HIP(qw::launch_fill(st->rbuf[k], int64_t(sizeof(double)) * 3 * n, stream));
     }
-  QW_HIP(qw::launch_to_real(st->buf[st->cur].R0, st->rbuf[st->cur], 3 * n, stream));
-  QW_HIP(qw::launch_to_real(st->buf[st->cur ^ 1].Q1, st->rbuf[st->cur ^ 1] + 2 * n, n, stream));
+  const double* val = st->ctx->sval;  // R0 cells of slots of negative value are imaginary
+  QW_HIP(qw::launch_to_real(st->buf[st->cur].R0, st->rbuf[st->cur], val, n, stream));
+  QW_HIP(qw::launch_to_real(st->buf[st->cur].Q0, st->rbuf[st->cur] + n, nullptr, 2 * n, stream));
+  QW_HIP(qw::launch_to_real(st->buf[st->cur ^ 1].Q1, st->rbuf[st->cur ^ 1] + 2 * n, nullptr, n, stream));
   st->in_real = true;
   return QW_OK;
 }
@@ -285,8 +290,10 @@ int to_real(qw_state* st, hipStream_t stream) {
 int to_complex(qw_state* st, hipStream_t stream) {
   if (!st->in_real) return QW_OK;
   const int64_t n = st->ctx->items;
-  QW_HIP(qw::launch_to_complex(st->rbuf[st->cur], st->buf[st->cur].R0, 3 * n, stream));
-  QW_HIP(qw::launch_to_complex(st->rbuf[st->cur ^ 1] + 2 * n, st->buf[st->cur ^ 1].Q1, n, stream));
+  const double* val = st->ctx->sval;
+  QW_HIP(qw::launch_to_complex(st->rbuf[st->cur], st->buf[st->cur].R0, val, n, stream));
+  QW_HIP(qw::launch_to_complex(st->rbuf[st->cur] + n, st->buf[st->cur].Q0, nullptr, 2 * n, stream));
+  QW_HIP(qw::launch_to_complex(st->rbuf[st->cur ^ 1] + 2 * n, st->buf[st->cur ^ 1].Q1, nullptr, n, stream));
   st->in_real = false;
   return QW_OK;
 }
@@ -506,6 +513,21 @@ int fixed_point_angles(int32_t w, std::vector<double>& val) {
   return QW_OK;
 }
 
+// Whether every slot of negative value has a partner, also of negative value
+// (true of symmetric matrices; see StepArgs::real).
+bool negative_slots_paired(const HostInst& hi, const Ell& ell) {
+  for (int32_t j = 0; j < hi.N; ++j)
+    for (int l = 0; l < hi.s; ++l) {
+      const size_t q = size_t(j) * hi.s + l;
+      if (!(ell.val[q] < 0.0)) continue;
+      const int32_t c = ell.col[q];
+      const int32_t* row = ell.col.data() + size_t(c) * hi.s;
+      const int32_t* f = std::lower_bound(row, row + hi.s, j);
+      if (f == row + hi.s || *f != j || !(ell.val[size_t(c) * hi.s + size_t(f - row)] < 0.0)) return false;
+    }
+  return true;
+}
+
 // Whether every slot of value 0 (a filler, or a stored zero) has a partner of
 // value 0 or none.  Then, from T~ |b~> on, the R0 and Q0 cells of these slots
 // stay 0: T~ puts b_j f / sqrt(s) = 0 there, and a step moves such a cell only
@@ -582,8 +604,7 @@ int load_impl(qw_ctx** out, int32_t ninst, const int32_t* n, const int64_t* colp
                         scales ? scales[i] : 0.0, flags, hi, ell, slot_of);
     if (rc == QW_OK && word > 0) rc = fixed_point_angles(word, ell.val);
     if (rc == QW_OK) ctx->zclosed = ctx->zclosed && zero_slots_closed(hi, ell);
-    if (rc == QW_OK)
-      for (double v : ell.val) ctx->nonneg = ctx->nonneg && !vals_im && !std::signbit(v);
+    if (rc == QW_OK) ctx->realsym = ctx->realsym && !vals_im && negative_slots_paired(hi, ell);
     if (rc) {
       prefix_err("instance " + std::to_string(i) + ": ");
       delete ctx;
@@ -1120,7 +1141,7 @@ int qw_measure(qw_state* st, int32_t kind, void* out, int64_t out_len, void* str
       o[2] = int64_t(st->L.cap);
       o[3] = int64_t(st->L.cnt);
       o[4] = tw;
-      if (out_len >= 6) o[5] = st->real_ok && st->ctx->nonneg ? 1 : 0;
+      if (out_len >= 6) o[5] = st->real_ok && st->ctx->realsym ? 1 : 0;
       return QW_OK;
     }
     default:

@@ -120,8 +120,9 @@ struct StepArgs {
   // partner is a slot of value 0 too, so the grid-stride and g kernels skip
   // those cells of such slots (they stay 0 under the step and the swap)
   int32_t zskip;
-  // 1: real amplitudes; the plane pointers of in/out point at double arrays
-  // (the qwk_step_r / qwk_step_t kernels)
+  // 1: one double per cell (real amplitudes, or imaginary ones in the R0
+  // cells of slots of negative value); the plane pointers of in/out point at
+  // double arrays (the qwk_step_r / qwk_step_t kernels)
   int32_t real;
 };
 
@@ -155,9 +156,10 @@ hipError_t launch_adjoint(const AdjArgs& a, int grid, int block, hipStream_t str
 hipError_t launch_qbs_table(const Matrix& m, SlotRec* rec, uint32_t* slink, double* sval, hipStream_t stream);
 hipError_t launch_init(const Matrix& m, const double2* b, Slots out, double tau, hipStream_t stream);
 hipError_t launch_fill(void* p, int64_t bytes, hipStream_t stream);
-// n complex cells to their real parts, and n reals to complex cells.
-hipError_t launch_to_real(const double2* src, double* dst, int64_t n, hipStream_t stream);
-hipError_t launch_to_complex(const double* src, double2* dst, int64_t n, hipStream_t stream);
+// n complex cells to the one double each holds, and back: the imaginary part
+// where val (by cell, or NULL) is negative, the real part elsewhere.
+hipError_t launch_to_real(const double2* src, double* dst, const double* val, int64_t n, hipStream_t stream);
+hipError_t launch_to_complex(const double* src, double2* dst, const double* val, int64_t n, hipStream_t stream);
 // Reductions over a state: kind 0 = count, 1 = norm^2, 4 = count of the Q1
 // plane (per-block partials in `partial`, length >= grid); kind 2 = j
 // marginal into out (N-vector, must be zero); kind 3 = projection

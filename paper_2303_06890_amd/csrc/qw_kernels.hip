@@ -570,13 +570,23 @@ QW_STEP_KERNEL(qwk_step_y8, 8, 0, true, qw::kEncAngle)
 namespace qw {
 
 // ----------------------------------------------------------------- real amplitudes
-// With no negative and no complex value and a real b, f = sqrt(a) and
-// g = sqrt(1 - a) are real, and so is every amplitude: T~ and the reflection
-// only multiply and add reals.  The planes then hold doubles, 8 bytes per
-// cell instead of 16; StepArgs::real is set and the plane pointers of
-// StepArgs::in/out point at double arrays of the same layout.  These kernels
-// have the f kernels' conditions (one pass, one s for every instance, every
-// row exists) and take the walk step only; the list is empty (T~ starts).
+// A real matrix whose negative values pair with negative values (a slot of
+// value a < 0 has a partner, of value < 0: true of symmetric matrices) and a
+// real b: every amplitude is then real or imaginary by its cell.  f = +-i
+// sqrt|a| for a < 0 and real otherwise, and g is real.  By induction over the
+// steps, the R0 cell of a slot of negative value holds i r and every other
+// cell a real r.  T~ puts b f / sqrt(s) into R0; the group sum
+// c = sum conj(f) x0 + g x1 is real, since conj(+-i q) (i r) = +-q r; the
+// reflected R0 output (2/s) c f - x0 lands in the partner's R0, whose value
+// is negative too; the rest is real.  So each cell keeps one double: r.  With
+// f' = +-q (the sign of the +-i rule) for a < 0 and f' = f otherwise, the
+// step reads c = sum f' r0 + g r1 and writes (2/s) c f' - r0 and
+// (2/s) c g - r1: the complex step with the i's taken out.  The planes then
+// hold doubles, 8 bytes per cell instead of 16; StepArgs::real is set and the
+// plane pointers of StepArgs::in/out point at double arrays of the same
+// layout.  These kernels have the f kernels' conditions (one pass, one s for
+// every instance, every row exists) and take the walk step only; the list is
+// empty (T~ starts).
 
 __device__ __forceinline__ double row_sum_r(double v, int rpw_log) {
   if (rpw_log <= 3) v += dpp<0x128>(v);
@@ -616,12 +626,14 @@ __device__ __forceinline__ unsigned step_wave_real(const StepArgs& a, int64_t w,
   double c = 0.0;
 #pragma unroll
   for (int i = 0; i < sl; ++i) {
+    double q;
     if (ENC == kEncAngle) {
-      sincospi(rc[i].val, &f[i], &g[i]);  // y >= 0 here
+      sincospi(fabs(rc[i].val), &q, &g[i]);
     } else {
-      f[i] = sqrt(rc[i].val);
-      g[i] = sqrt(1.0 - rc[i].val);
+      q = sqrt(fabs(rc[i].val));
+      g[i] = sqrt(1.0 - fabs(rc[i].val));
     }
+    f[i] = rc[i].val < 0.0 && !rc[i].upper ? -q : q;  // f' (the +-i rule's sign for a < 0)
     c += f[i] * x0[i] + x1[i] * g[i];
   }
   c = row_sum_r(c, x.rpw_log);
@@ -658,23 +670,26 @@ __device__ __forceinline__ void step_body_real(const StepArgs& a) {
   if (lane == 0) a.acc[cidx] = prev + v;
 }
 
-// Plane conversions for the switch between the two representations.
+// Plane conversions for the switch between the two representations.  With
+// `val` (an R0 plane: the step kernels' values by home) the cells of slots of
+// negative value are the imaginary ones; without, every cell is real.
 extern "C" __global__ void __launch_bounds__(256) qwk_to_real(const double2* __restrict__ src, double* dst,
-                                                              int64_t n) {
-  const int64_t stride = int64_t(gridDim.x) * blockDim.x;
-  for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += stride) dst[i] = src[i].x;
-}
-extern "C" __global__ void __launch_bounds__(256) qwk_to_complex(const double* __restrict__ src, double2* dst,
-                                                                 int64_t n) {
+                                                              const double* __restrict__ val, int64_t n) {
   const int64_t stride = int64_t(gridDim.x) * blockDim.x;
   for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += stride)
-    dst[i] = make_double2(src[i], 0.0);
+    dst[i] = val && val[i] < 0.0 ? src[i].y : src[i].x;
+}
+extern "C" __global__ void __launch_bounds__(256) qwk_to_complex(const double* __restrict__ src, double2* dst,
+                                                                 const double* __restrict__ val, int64_t n) {
+  const int64_t stride = int64_t(gridDim.x) * blockDim.x;
+  for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += stride)
+    dst[i] = val && val[i] < 0.0 ? make_double2(0.0, src[i]) : make_double2(src[i], 0.0);
 }
 
 }  // namespace qw
 
-// qwk_step_rS: real amplitudes, FP64 values; qwk_step_tS: real amplitudes,
-// fixed-point data (nonnegative angles).
+// qwk_step_rS: one double per cell, FP64 values; qwk_step_tS: the same for
+// fixed-point data.
 #define QW_REAL_KERNEL(NAME, SLM, S, ENC)                                                            \
   extern "C" __global__ void __launch_bounds__(256) NAME(qw::StepArgs a) {                         \
     qw::step_body_real<SLM, S, ENC>(a);                                                             \

@@ -232,13 +232,13 @@ hipError_t launch_fill(void* ptr, int64_t bytes, hipStream_t stream) {
   return launch(F_FILL, clamp_grid(n16, 4096), 256, stream, p);
 }
 
-hipError_t launch_to_real(const double2* src, double* dst, int64_t n, hipStream_t stream) {
-  void* p[] = {&src, &dst, &n};
+hipError_t launch_to_real(const double2* src, double* dst, const double* val, int64_t n, hipStream_t stream) {
+  void* p[] = {&src, &dst, &val, &n};
   return launch(F_TO_REAL, clamp_grid(n, 4096), 256, stream, p);
 }
 
-hipError_t launch_to_complex(const double* src, double2* dst, int64_t n, hipStream_t stream) {
-  void* p[] = {&src, &dst, &n};
+hipError_t launch_to_complex(const double* src, double2* dst, const double* val, int64_t n, hipStream_t stream) {
+  void* p[] = {&src, &dst, &val, &n};
   return launch(F_TO_COMPLEX, clamp_grid(n, 4096), 256, stream, p);
 }
 

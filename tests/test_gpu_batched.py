@@ -57,6 +57,9 @@ def _slice(F, amps, i, n):
 
 
 def _plain(Q, csc, b, nsteps):
+    """The same walk alone.  A single real symmetric matrix steps on one
+    double per cell (the batch has instances of several s and stays on the
+    complex planes), so amplitudes agree to rounding, keys exactly."""
     walk = Q.Walk(csc)
     keys, amps = walk.state(b).step(nsteps).export()
     return walk.nbits, keys, amps
@@ -75,7 +78,7 @@ def test_batched_equals_plain_runs(Q):
         n, rk, ra = _plain(Q, a, b, 30)
         gk, ga = _slice(F, amps, i, n)
         assert np.array_equal(gk, rk), i
-        assert np.array_equal(ga, ra), i
+        assert np.abs(ga - ra).max() < 1e-13, i
 
 
 def test_batched_vs_oracle(Q, oracle_mod):
@@ -153,4 +156,4 @@ def test_batched_workload_256(Q):
         n, rk, ra = _plain(Q, a, b, 50)
         gk, ga = _slice(F, amps, i, n)
         assert np.array_equal(gk, rk), i
-        assert np.array_equal(ga, ra), i
+        assert np.abs(ga - ra).max() < 1e-13, i

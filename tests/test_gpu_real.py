@@ -1,9 +1,11 @@
-"""Real amplitudes on the GPU: with no negative and no complex matrix value
-and a real b, every amplitude of the walk from T~|b~> is real and the walk
-steps run on 8-byte planes (the qwk_step_r / qwk_step_t kernels).  Every
-other use of the state (measurements, export, W^dagger, other launch shapes)
-moves it back to the complex planes.  Parity with the oracle across those
-switches, graph replays, the branch count and fixed-point data."""
+"""One double per cell on the GPU: for a real matrix whose negative values
+pair up (a symmetric one) and a real b, every amplitude of the walk from
+T~|b~> is real, except those of the R0 cells of slots of negative value,
+which are imaginary; the walk steps then run on 8-byte planes (the
+qwk_step_r / qwk_step_t kernels).  Every other use of the state
+(measurements, export, W^dagger, other launch shapes) moves it back to the
+complex planes.  Parity with the oracle across those switches, graph
+replays, the branch count, negative values and fixed-point data."""
 import numpy as np
 import pytest
 
@@ -34,14 +36,18 @@ def _check(st, ost, where):
     gk, ga = st.export()
     ok, oa = ost.export()
     assert ost.ambiguous() == 0
-    assert np.all(ga.imag == 0.0)
+    assert np.all((ga.real == 0.0) | (ga.imag == 0.0))  # one double per cell
     compare_states(gk, ga, ok, oa, where=where)
 
 
-@pytest.mark.parametrize("case", ["A", "B", "band300"])
+@pytest.mark.parametrize("case", ["A", "B", "band300", "offsets", "offsets_s16"])
 def test_real_amplitudes_match_the_oracle(Q, oracle_mod, case):
     if case == "band300":
         csc, b = W.band_matrix(300, 5, seed=31), W.gaussian_b(300, seed=32)  # s = 16, ragged n
+    elif case == "offsets":  # negative values: imaginary R0 cells
+        csc, b = W.offset_matrix(1024, 8, seed=4), W.gaussian_b(1024, seed=5)
+    elif case == "offsets_s16":
+        csc, b = W.offset_matrix(200, 11, seed=6), W.gaussian_b(200, seed=7)
     else:
         csc, b = W.table1_band(case)
     walk, st, ost = _pair(Q, oracle_mod, csc, b)
@@ -93,23 +99,26 @@ def test_branch_count_on_real_planes(Q):
     assert np.array_equal(k1, k2) and np.array_equal(a1, a2)
 
 
-def test_fixed_point_real_amplitudes(Q, oracle_mod):
-    csc = W.fixed_point_band(400, 6, 16, seed=36)  # nonnegative words
+@pytest.mark.parametrize("neg", [0.0, 0.4])
+def test_fixed_point_real_amplitudes(Q, oracle_mod, neg):
+    csc = W.fixed_point_band(400, 6, 16, seed=36, negative=neg)
     walk, st, ost = _pair(Q, oracle_mod, csc, W.gaussian_b(400, seed=37), word=16)
     assert st.stats()["real_amplitudes"]
     st.step(30)
     ost.step(30)
-    _check(st, ost, "fixed point, step 30")
+    _check(st, ost, f"fixed point, negative fraction {neg}, step 30")
 
 
-def test_when_amplitudes_are_not_real(Q, oracle_mod):
-    """A negative entry, or a complex b, keeps the complex planes."""
-    csc = W.band_matrix(128, 3, seed=38)
-    d = csc.dense()
-    d[5, 6] = d[6, 5] = -0.25
-    neg = W.from_dense(d)
-    st = Q.Walk(neg).state(W.uniform_b(128))
+def test_when_cells_are_not_real(Q, oracle_mod):
+    """A negative value whose partner is positive (an unsymmetric pattern), or
+    a complex b, keeps the complex planes."""
+    a = np.diag(np.full(64, 0.5))
+    for j in range(63):
+        a[j + 1, j] = a[j, j + 1] = 0.2
+    a[7, 8] = -0.2  # its mirror a[8, 7] stays positive
+    st = Q.Walk(W.from_dense(a), symmetric=False).state(W.uniform_b(64))
     assert not st.stats()["real_amplitudes"]
+    csc = W.band_matrix(128, 3, seed=38)
     b = W.gaussian_b(128, seed=39) * np.exp(0.3j * np.arange(128))
     walk, st, ost = _pair(Q, oracle_mod, csc, b)
     assert not st.stats()["real_amplitudes"]
