@@ -249,17 +249,16 @@ qw::StepArgs step_args_real(qw_state* st) {
   qw::StepArgs a = step_args(st, qw::kStep, nullptr, nullptr);
   a.in = rview(st, st->cur, st->r1s);
   a.out = rview(st, st->cur ^ 1, r1s_after(qw::kStep));
-  a.zskip = 0;
   a.real = 1;
   return a;
 }
 
 // Whether walk steps may run on one double per cell: a real matrix whose
 // negative values pair up, a state from T~ of a real b with an empty list,
-// and the f kernels' conditions.
+// and the one-pass kernels' conditions.
 bool real_path(const qw_state* st, const double2* yacc) {
   const qw_ctx* c = st->ctx;
-  return yacc == nullptr && c->realsym && st->real_ok && c->suni > 0 && c->full && st->L.cnt == 0 &&
+  return yacc == nullptr && c->realsym && st->real_ok && c->full && st->L.cnt == 0 &&
          int64_t(step_grid(st)) * (st->block / qw::kWave) >= c->waves;
 }
 

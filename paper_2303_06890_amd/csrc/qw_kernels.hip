@@ -584,9 +584,9 @@ namespace qw {
 // (2/s) c g - r1: the complex step with the i's taken out.  The planes then
 // hold doubles, 8 bytes per cell instead of 16; StepArgs::real is set and the
 // plane pointers of StepArgs::in/out point at double arrays of the same
-// layout.  These kernels have the f kernels' conditions (one pass, one s for
-// every instance, every row exists) and take the walk step only; the list is
-// empty (T~ starts).
+// layout.  These kernels have the f kernels' conditions (one s for every
+// instance) or the g kernels' (mixed s): one pass, every row exists, the
+// walk step only, and an empty list (T~ starts).
 
 __device__ __forceinline__ double row_sum_r(double v, int rpw_log) {
   if (rpw_log <= 3) v += dpp<0x128>(v);
@@ -602,10 +602,12 @@ __device__ __forceinline__ double prune_r(double v, double tau, unsigned& cnt) {
   return 0.0;
 }
 
+// S: s of every instance, or 0 (read per instance, slots per lane <= SLM;
+// slots of value 0 are skipped as in step_wave when StepArgs::zskip is set).
 template <int SLM, int S, int ENC>
 __device__ __forceinline__ unsigned step_wave_real(const StepArgs& a, int64_t w, int lane) {
   const Lanes x = lanes_of<S, true>(a.m, w, lane);
-  constexpr int sl = Shape<S>::sl;
+  const int sl = S ? Shape<S>::sl : (SLM == 1 ? 1 : x.I.sl);
   const int64_t base = x.I.item_base;
   const double* R0 = reinterpret_cast<const double*>(a.in.R0);
   const double* R1 = reinterpret_cast<const double*>(a.in.R1);
@@ -616,42 +618,51 @@ __device__ __forceinline__ unsigned step_wave_real(const StepArgs& a, int64_t w,
   int64_t h[SLM];
   StepSlot rc[SLM];
   double x0[SLM], x1[SLM], f[SLM], g[SLM];
+  bool zero[SLM];
 #pragma unroll
-  for (int i = 0; i < sl; ++i) {
-    h[i] = base + (int64_t(x.h * sl + i) << x.I.nlog) + x.j;
-    rc[i] = step_rec(a.m, h[i]);
-    x0[i] = R0[h[i]];
-    x1[i] = R1[h[i]] * a.in.r1s;
+  for (int i = 0; i < SLM; ++i) {
+    if (i < sl) {
+      h[i] = base + (int64_t(x.h * sl + i) << x.I.nlog) + x.j;
+      rc[i] = step_rec(a.m, h[i]);
+      x1[i] = R1[h[i]] * a.in.r1s;
+      zero[i] = S == 0 && a.zskip && rc[i].val == 0.0;
+      x0[i] = zero[i] ? 0.0 : R0[h[i]];
+    }
   }
   double c = 0.0;
 #pragma unroll
-  for (int i = 0; i < sl; ++i) {
-    double q;
-    if (ENC == kEncAngle) {
-      sincospi(fabs(rc[i].val), &q, &g[i]);
-    } else {
-      q = sqrt(fabs(rc[i].val));
-      g[i] = sqrt(1.0 - fabs(rc[i].val));
+  for (int i = 0; i < SLM; ++i) {
+    if (i < sl) {
+      double q;
+      if (ENC == kEncAngle) {
+        sincospi(fabs(rc[i].val), &q, &g[i]);
+      } else {
+        q = sqrt(fabs(rc[i].val));
+        g[i] = sqrt(1.0 - fabs(rc[i].val));
+      }
+      f[i] = rc[i].val < 0.0 && !rc[i].upper ? -q : q;  // f' (the +-i rule's sign for a < 0)
+      c += f[i] * x0[i] + x1[i] * g[i];
     }
-    f[i] = rc[i].val < 0.0 && !rc[i].upper ? -q : q;  // f' (the +-i rule's sign for a < 0)
-    c += f[i] * x0[i] + x1[i] * g[i];
   }
   c = row_sum_r(c, x.rpw_log);
   const double tc = c * (2.0 / double(x.I.s));
   unsigned cnt = 0;
 #pragma unroll
-  for (int i = 0; i < sl; ++i) {
-    const double o0 = tc * f[i] - x0[i];
-    const double o1 = tc * g[i] - x1[i];
-    unsigned q1 = 0;
-    oQ1[h[i]] = prune_r(o1, a.tau, q1);
-    cnt += 2 * q1;  // counted as in write_slot
-    if (rc[i].part >= 0) {
-      oR0[base + rc[i].part] = prune_r(o0, a.tau, cnt);
-    } else {
-      const double y0 = Q0[h[i]];
-      oQ0[h[i]] = prune_r(o0, a.tau, cnt);
-      oR0[h[i]] = prune_r(-y0, a.tau, cnt);
+  for (int i = 0; i < SLM; ++i) {
+    if (i < sl) {
+      const double o0 = tc * f[i] - x0[i];
+      const double o1 = tc * g[i] - x1[i];
+      unsigned q1 = 0;
+      oQ1[h[i]] = prune_r(o1, a.tau, q1);
+      cnt += 2 * q1;  // counted as in write_slot
+      if (zero[i]) continue;
+      if (rc[i].part >= 0) {
+        oR0[base + rc[i].part] = prune_r(o0, a.tau, cnt);
+      } else {
+        const double y0 = Q0[h[i]];
+        oQ0[h[i]] = prune_r(o0, a.tau, cnt);
+        oR0[h[i]] = prune_r(-y0, a.tau, cnt);
+      }
     }
   }
   return cnt;
@@ -688,8 +699,9 @@ extern "C" __global__ void __launch_bounds__(256) qwk_to_complex(const double* _
 
 }  // namespace qw
 
-// qwk_step_rS: one double per cell, FP64 values; qwk_step_tS: the same for
-// fixed-point data.
+// qwk_step_rS: one double per cell, FP64 values, s = S for every instance;
+// qwk_step_tS: the same for fixed-point data; qwk_step_rgN / qwk_step_tgN:
+// mixed s, up to N slots per lane (the g kernels' shapes).
 #define QW_REAL_KERNEL(NAME, SLM, S, ENC)                                                            \
   extern "C" __global__ void __launch_bounds__(256) NAME(qw::StepArgs a) {                         \
     qw::step_body_real<SLM, S, ENC>(a);                                                             \
@@ -708,6 +720,14 @@ QW_REAL_KERNEL(qwk_step_t8, 1, 8, qw::kEncAngle)
 QW_REAL_KERNEL(qwk_step_t16, 2, 16, qw::kEncAngle)
 QW_REAL_KERNEL(qwk_step_t32, 4, 32, qw::kEncAngle)
 QW_REAL_KERNEL(qwk_step_t64, 8, 64, qw::kEncAngle)
+QW_REAL_KERNEL(qwk_step_rg1, 1, 0, qw::kEncReal)
+QW_REAL_KERNEL(qwk_step_rg2, 2, 0, qw::kEncReal)
+QW_REAL_KERNEL(qwk_step_rg4, 4, 0, qw::kEncReal)
+QW_REAL_KERNEL(qwk_step_rg8, 8, 0, qw::kEncReal)
+QW_REAL_KERNEL(qwk_step_tg1, 1, 0, qw::kEncAngle)
+QW_REAL_KERNEL(qwk_step_tg2, 2, 0, qw::kEncAngle)
+QW_REAL_KERNEL(qwk_step_tg4, 4, 0, qw::kEncAngle)
+QW_REAL_KERNEL(qwk_step_tg8, 8, 0, qw::kEncAngle)
 #undef QW_REAL_KERNEL
 
 

@@ -82,7 +82,9 @@ enum Fn {
   F_STEP_T1 = F_STEP_R1 + 7,
   F_TO_REAL = F_STEP_T1 + 7,
   F_TO_COMPLEX,
-  F_COUNT
+  F_STEP_RG1,  // real amplitudes, mixed s: qwk_step_rg{1,2,4,8}, then qwk_step_tg{1,2,4,8}
+  F_STEP_TG1 = F_STEP_RG1 + 4,
+  F_COUNT = F_STEP_TG1 + 4
 };
 
 const char* const kNames[] = {
@@ -105,7 +107,9 @@ const char* const kNames[] = {
     "qwk_import",       "qwk_weight",       "qwk_grad_init",    "qwk_step_r1",      "qwk_step_r2",
     "qwk_step_r4",      "qwk_step_r8",      "qwk_step_r16",     "qwk_step_r32",     "qwk_step_r64",
     "qwk_step_t1",      "qwk_step_t2",      "qwk_step_t4",      "qwk_step_t8",      "qwk_step_t16",
-    "qwk_step_t32",     "qwk_step_t64",     "qwk_to_real",      "qwk_to_complex"};
+    "qwk_step_t32",     "qwk_step_t64",     "qwk_to_real",      "qwk_to_complex",
+    "qwk_step_rg1",     "qwk_step_rg2",     "qwk_step_rg4",     "qwk_step_rg8",     "qwk_step_tg1",
+    "qwk_step_tg2",     "qwk_step_tg4",     "qwk_step_tg8"};
 static_assert(sizeof(kNames) / sizeof(kNames[0]) == F_COUNT, "one kernel name per Fn");
 
 // 0..3 for slmax = 1, 2, 4, 8
@@ -123,7 +127,8 @@ Fn step_kernel(const StepArgs& a, int grid, int block) {
   const int64_t work = m.waves + (int64_t(a.L.cnt) + kWave - 1) / kWave;
   const bool one_pass = m.full && a.mode == kStep && int64_t(grid) * (block / kWave) >= work;
   if (a.real) {  // the caller checked the conditions (launch_step re-checks them)
-    return Fn((m.angles ? F_STEP_T1 : F_STEP_R1) + log2_of(m.suni));
+    if (m.suni > 0) return Fn((m.angles ? F_STEP_T1 : F_STEP_R1) + log2_of(m.suni));
+    return Fn((m.angles ? F_STEP_TG1 : F_STEP_RG1) + width_index(m.slmax));
   }
   int f = F_STEP_S1 + width_index(m.slmax);
   if (m.vim) {
@@ -191,7 +196,7 @@ int clamp_grid(int64_t work, int64_t limit) {
 
 hipError_t launch_step(const StepArgs& a, int grid, int block, hipStream_t stream) {
   if (block < kWave || block > kMaxBlock || block % kWave) return hipErrorInvalidValue;
-  if (a.real && (a.mode != kStep || a.yacc || a.m.vim || a.L.cnt || !a.m.full || a.m.suni <= 0 ||
+  if (a.real && (a.mode != kStep || a.yacc || a.m.vim || a.L.cnt || !a.m.full ||
                  int64_t(grid) * (block / kWave) < a.m.waves))
     return hipErrorInvalidValue;  // the real-amplitude kernels are one-pass walk steps only
   StepArgs c = a;

@@ -57,9 +57,9 @@ def _slice(F, amps, i, n):
 
 
 def _plain(Q, csc, b, nsteps):
-    """The same walk alone.  A single real symmetric matrix steps on one
-    double per cell (the batch has instances of several s and stays on the
-    complex planes), so amplitudes agree to rounding, keys exactly."""
+    """The same walk alone.  The batch and the single walk may run different
+    kernels (one double per cell or complex planes, other lane shapes), so
+    amplitudes agree to rounding, keys exactly."""
     walk = Q.Walk(csc)
     keys, amps = walk.state(b).step(nsteps).export()
     return walk.nbits, keys, amps

@@ -2,7 +2,8 @@
 pair up (a symmetric one) and a real b, every amplitude of the walk from
 T~|b~> is real, except those of the R0 cells of slots of negative value,
 which are imaginary; the walk steps then run on 8-byte planes (the
-qwk_step_r / qwk_step_t kernels).  Every other use of the state
+qwk_step_r / qwk_step_t kernels; qwk_step_rg / qwk_step_tg for instances of
+mixed s).  Every other use of the state
 (measurements, export, W^dagger, other launch shapes) moves it back to the
 complex planes.  Parity with the oracle across those switches, graph
 replays, the branch count, negative values and fixed-point data."""
@@ -58,6 +59,43 @@ def test_real_amplitudes_match_the_oracle(Q, oracle_mod, case):
         ost.step(t - done)
         done = t
         _check(st, ost, f"{case} step {t}")
+
+
+@pytest.mark.parametrize("kind", ["offsets", "fixed_point"])
+def test_mixed_s_batch_on_real_planes(Q, oracle_mod, kind):
+    """Instances of s = 4, 8 and 16 in one context (the one-pass kernels of
+    mixed s on one double per cell): negative values, fillers of value 0
+    where the column count is not a power of two (skipped in place), a ragged
+    dimension; each instance against its own oracle walk."""
+    from tests.test_gpu_batched import _slice, unpack
+
+    word = 0
+    if kind == "offsets":
+        mats = [W.offset_matrix(64, 3, seed=81), W.offset_matrix(128, 6, seed=82),
+                W.offset_matrix(256, 11, seed=83), W.band_matrix(300, 2, seed=84)]
+    else:
+        word = 12
+        mats = [W.fixed_point_band(64, 1, word, seed=85, negative=0.5),
+                W.fixed_point_band(200, 3, word, seed=86, negative=0.3),
+                W.fixed_point_band(128, 6, word, seed=87, negative=0.5)]
+    bs = [W.gaussian_b(m.n, seed=90 + i) for i, m in enumerate(mats)]
+    walk = Q.Walk(mats, word=word)
+    assert len({d["s"] for d in walk.info}) == 3
+    st = walk.state(bs)
+    assert st.stats()["real_amplitudes"]
+    osts = [oracle_mod.OracleState(oracle_mod.OracleMatrix(m, word=word)).set_b(b).T() for m, b in zip(mats, bs)]
+    done = 0
+    for t in (1, 2, 19, 40):  # single launches and graph replays
+        st.step(t - done)
+        keys, amps = st.export()
+        assert np.all((amps.real == 0.0) | (amps.imag == 0.0))  # one double per cell
+        F = unpack(keys, walk.nbits)
+        for i, ost in enumerate(osts):
+            ost.step(t - done)
+            ok, oa = ost.export()
+            gk, ga = _slice(F, amps, i, ost.mat.nbits)
+            compare_states(gk, ga, ok, oa, where=f"{kind} instance {i} step {t}")
+        done = t
 
 
 def test_switches_between_the_representations(Q, oracle_mod):
