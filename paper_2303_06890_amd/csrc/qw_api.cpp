@@ -245,20 +245,21 @@ qw::Slots rview(const qw_state* st, int p, double r1s) {
   return qw::Slots{plane(p, 0), plane(p ^ 1, 2), plane(p, 1), plane(p, 2), r1s};
 }
 
-qw::StepArgs step_args_real(qw_state* st) {
-  qw::StepArgs a = step_args(st, qw::kStep, nullptr, nullptr);
+qw::StepArgs step_args_real(qw_state* st, double2* yacc, const double* coefm) {
+  qw::StepArgs a = step_args(st, qw::kStep, yacc, coefm);
   a.in = rview(st, st->cur, st->r1s);
   a.out = rview(st, st->cur ^ 1, r1s_after(qw::kStep));
   a.real = 1;
   return a;
 }
 
-// Whether walk steps may run on one double per cell: a real matrix whose
-// negative values pair up, a state from T~ of a real b with an empty list,
-// and the one-pass kernels' conditions.
-bool real_path(const qw_state* st, const double2* yacc) {
+// Whether walk steps (with or without the solver's fused projection) may run
+// on one double per cell: a real matrix whose negative values pair up, a
+// state from T~ of a real b with an empty list, and the one-pass kernels'
+// conditions.
+bool real_path(const qw_state* st) {
   const qw_ctx* c = st->ctx;
-  return yacc == nullptr && c->realsym && st->real_ok && c->full && st->L.cnt == 0 &&
+  return c->realsym && st->real_ok && c->full && st->L.cnt == 0 &&
          int64_t(step_grid(st)) * (st->block / qw::kWave) >= c->waves;
 }
 
@@ -297,8 +298,8 @@ int to_complex(qw_state* st, hipStream_t stream) {
   return QW_OK;
 }
 
-int launch_real(qw_state* st, hipStream_t stream) {
-  qw::StepArgs a = step_args_real(st);
+int launch_real(qw_state* st, hipStream_t stream, double2* yacc, const double* coefm) {
+  qw::StepArgs a = step_args_real(st, yacc, coefm);
   QW_HIP(qw::launch_step(a, step_grid(st), st->block, stream));
   st->cur ^= 1;
   st->r1s = r1s_after(qw::kStep);
@@ -321,10 +322,12 @@ int launch_one(qw_state* st, int mode, hipStream_t stream, double2* yacc = nullp
 // replaying a captured graph of kGraphSteps launches when a stream is given.
 int run_steps(qw_state* st, int64_t n, hipStream_t stream, double2* yacc = nullptr, const double* coefm = nullptr) {
   if (n == 0) return QW_OK;
-  const bool real = real_path(st, yacc);
+  const bool real = real_path(st);
   int rc0 = real ? to_real(st, stream) : to_complex(st, stream);
   if (rc0) return rc0;
-  const auto one = [&]() { return real ? launch_real(st, stream) : launch_one(st, qw::kStep, stream, yacc, coefm); };
+  const auto one = [&]() {
+    return real ? launch_real(st, stream, yacc, coefm) : launch_one(st, qw::kStep, stream, yacc, coefm);
+  };
   // A captured graph is replayed back to back, so it must start from the R1
   // sign its own steps leave: a state fresh from preparation, import or the
   // swap takes its first step directly.
@@ -348,7 +351,7 @@ int run_steps(qw_state* st, int64_t n, hipStream_t stream, double2* yacc = nullp
       const int cur0 = st->cur;
       const double r1s0 = st->r1s;
       for (int i = 0; i < kGraphSteps; ++i) {
-        qw::StepArgs a = real ? step_args_real(st) : step_args(st, qw::kStep, yacc, coefm);
+        qw::StepArgs a = real ? step_args_real(st, yacc, coefm) : step_args(st, qw::kStep, yacc, coefm);
         hipError_t e = qw::launch_step(a, step_grid(st), st->block, stream);
         st->cur ^= 1;
         st->r1s = r1s_after(qw::kStep);

@@ -604,8 +604,8 @@ __device__ __forceinline__ double prune_r(double v, double tau, unsigned& cnt) {
 
 // S: s of every instance, or 0 (read per instance, slots per lane <= SLM;
 // slots of value 0 are skipped as in step_wave when StepArgs::zskip is set).
-template <int SLM, int S, int ENC>
-__device__ __forceinline__ unsigned step_wave_real(const StepArgs& a, int64_t w, int lane) {
+template <bool ACC, int SLM, int S, int ENC>
+__device__ __forceinline__ unsigned step_wave_real(const StepArgs& a, int64_t w, int lane, double coef) {
   const Lanes x = lanes_of<S, true>(a.m, w, lane);
   const int sl = S ? Shape<S>::sl : (SLM == 1 ? 1 : x.I.sl);
   const int64_t base = x.I.item_base;
@@ -645,6 +645,10 @@ __device__ __forceinline__ unsigned step_wave_real(const StepArgs& a, int64_t w,
     }
   }
   c = row_sum_r(c, x.rpw_log);
+  if (ACC && x.h == 0) {  // the group sum is real: only the real part of y_j moves
+    double* y = reinterpret_cast<double*>(a.yacc + x.I.jbase + x.j);
+    *y += coef * (c * x.I.inv_sqrt_s);
+  }
   const double tc = c * (2.0 / double(x.I.s));
   unsigned cnt = 0;
 #pragma unroll
@@ -668,17 +672,25 @@ __device__ __forceinline__ unsigned step_wave_real(const StepArgs& a, int64_t w,
   return cnt;
 }
 
-template <int SLM, int S, int ENC>
+template <bool ACC, int SLM, int S, int ENC>
 __device__ __forceinline__ void step_body_real(const StepArgs& a) {
   const int lane = threadIdx.x & (kWave - 1);
   const int64_t wpb = a.wpb;
   const int64_t wid = int64_t(blockIdx.x) * wpb + (threadIdx.x >> 6);
-  const int64_t cidx = wave_counter(wpb);
-  const unsigned long long prev = a.acc[cidx];
+  double coef = 0.0;
+  uint32_t stepno = 0;
+  if (ACC) {
+    stepno = a.stepno[wid];
+    coef = a.coefm[stepno];
+  }
   const int64_t w = uniform(int(wid));
-  if (w >= a.m.waves) return;  // no list: nothing to do past the slots
-  const unsigned long long v = wave_sum(step_wave_real<SLM, S, ENC>(a, w, lane));
-  if (lane == 0) a.acc[cidx] = prev + v;
+  if (w < a.m.waves) {  // no list: nothing to do past the slots
+    const int64_t cidx = wave_counter(wpb);
+    const unsigned long long prev = a.acc[cidx];
+    const unsigned long long v = wave_sum(step_wave_real<ACC, SLM, S, ENC>(a, w, lane, coef));
+    if (lane == 0) a.acc[cidx] = prev + v;
+  }
+  if (ACC && lane == 0) a.stepno[wid] = stepno + 1;  // every wavefront of the grid, as in step_body
 }
 
 // Plane conversions for the switch between the two representations.  With
@@ -701,10 +713,14 @@ extern "C" __global__ void __launch_bounds__(256) qwk_to_complex(const double* _
 
 // qwk_step_rS: one double per cell, FP64 values, s = S for every instance;
 // qwk_step_tS: the same for fixed-point data; qwk_step_rgN / qwk_step_tgN:
-// mixed s, up to N slots per lane (the g kernels' shapes).
+// mixed s, up to N slots per lane (the g kernels' shapes).  The _acc twins
+// fuse the solver's projection, as the other families' do.
 #define QW_REAL_KERNEL(NAME, SLM, S, ENC)                                                            \
   extern "C" __global__ void __launch_bounds__(256) NAME(qw::StepArgs a) {                         \
-    qw::step_body_real<SLM, S, ENC>(a);                                                             \
+    qw::step_body_real<false, SLM, S, ENC>(a);                                                      \
+  }                                                                                                 \
+  extern "C" __global__ void __launch_bounds__(256) NAME##_acc(qw::StepArgs a) {                   \
+    qw::step_body_real<true, SLM, S, ENC>(a);                                                       \
   }
 QW_REAL_KERNEL(qwk_step_r1, 1, 1, qw::kEncReal)
 QW_REAL_KERNEL(qwk_step_r2, 1, 2, qw::kEncReal)

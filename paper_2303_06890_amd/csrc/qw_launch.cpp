@@ -30,8 +30,10 @@ namespace {
 // qwk_step_y{1,2,4,8} their one-pass forms (the conditions of the g
 // kernels).  Each has an _acc twin
 // (the solver's fused projection).  Adjoint kernels (real FP64 matrices) come
-// in the four widths.  qwk_step_r{S} and qwk_step_t{S} are the f kernels for
-// real amplitudes (8-byte planes), FP64 and fixed-point values.
+// in the four widths.  qwk_step_r{S} and qwk_step_t{S} are the f kernels on
+// one double per cell (8-byte planes), FP64 and fixed-point values, and
+// qwk_step_rg{N} and qwk_step_tg{N} the g kernels on them; each has an _acc
+// twin too.
 enum Fn {
   F_STEP_S1,
   F_STEP_S2,
@@ -78,13 +80,14 @@ enum Fn {
   F_IMPORT,
   F_WEIGHT,
   F_GRAD_INIT,
-  F_STEP_R1,  // real amplitudes: qwk_step_r{1..64}, then qwk_step_t{1..64}
-  F_STEP_T1 = F_STEP_R1 + 7,
-  F_TO_REAL = F_STEP_T1 + 7,
-  F_TO_COMPLEX,
-  F_STEP_RG1,  // real amplitudes, mixed s: qwk_step_rg{1,2,4,8}, then qwk_step_tg{1,2,4,8}
+  F_STEP_R1,  // one double per cell: qwk_step_r{1..64}, qwk_step_t{1..64}, then mixed s:
+  F_STEP_T1 = F_STEP_R1 + 7,    // qwk_step_rg{1,2,4,8}, qwk_step_tg{1,2,4,8}; their _acc
+  F_STEP_RG1 = F_STEP_T1 + 7,   // twins follow at + F_REAL_COUNT_
   F_STEP_TG1 = F_STEP_RG1 + 4,
-  F_COUNT = F_STEP_TG1 + 4
+  F_REAL_COUNT_ = F_STEP_TG1 + 4 - F_STEP_R1,
+  F_TO_REAL = F_STEP_R1 + 2 * F_REAL_COUNT_,
+  F_TO_COMPLEX,
+  F_COUNT
 };
 
 const char* const kNames[] = {
@@ -107,9 +110,13 @@ const char* const kNames[] = {
     "qwk_import",       "qwk_weight",       "qwk_grad_init",    "qwk_step_r1",      "qwk_step_r2",
     "qwk_step_r4",      "qwk_step_r8",      "qwk_step_r16",     "qwk_step_r32",     "qwk_step_r64",
     "qwk_step_t1",      "qwk_step_t2",      "qwk_step_t4",      "qwk_step_t8",      "qwk_step_t16",
-    "qwk_step_t32",     "qwk_step_t64",     "qwk_to_real",      "qwk_to_complex",
-    "qwk_step_rg1",     "qwk_step_rg2",     "qwk_step_rg4",     "qwk_step_rg8",     "qwk_step_tg1",
-    "qwk_step_tg2",     "qwk_step_tg4",     "qwk_step_tg8"};
+    "qwk_step_t32",     "qwk_step_t64",     "qwk_step_rg1",     "qwk_step_rg2",     "qwk_step_rg4",
+    "qwk_step_rg8",     "qwk_step_tg1",     "qwk_step_tg2",     "qwk_step_tg4",     "qwk_step_tg8",
+    "qwk_step_r1_acc",  "qwk_step_r2_acc",  "qwk_step_r4_acc",  "qwk_step_r8_acc",  "qwk_step_r16_acc",
+    "qwk_step_r32_acc", "qwk_step_r64_acc", "qwk_step_t1_acc",  "qwk_step_t2_acc",  "qwk_step_t4_acc",
+    "qwk_step_t8_acc",  "qwk_step_t16_acc", "qwk_step_t32_acc", "qwk_step_t64_acc", "qwk_step_rg1_acc",
+    "qwk_step_rg2_acc", "qwk_step_rg4_acc", "qwk_step_rg8_acc", "qwk_step_tg1_acc", "qwk_step_tg2_acc",
+    "qwk_step_tg4_acc", "qwk_step_tg8_acc", "qwk_to_real",      "qwk_to_complex"};
 static_assert(sizeof(kNames) / sizeof(kNames[0]) == F_COUNT, "one kernel name per Fn");
 
 // 0..3 for slmax = 1, 2, 4, 8
@@ -127,8 +134,9 @@ Fn step_kernel(const StepArgs& a, int grid, int block) {
   const int64_t work = m.waves + (int64_t(a.L.cnt) + kWave - 1) / kWave;
   const bool one_pass = m.full && a.mode == kStep && int64_t(grid) * (block / kWave) >= work;
   if (a.real) {  // the caller checked the conditions (launch_step re-checks them)
-    if (m.suni > 0) return Fn((m.angles ? F_STEP_T1 : F_STEP_R1) + log2_of(m.suni));
-    return Fn((m.angles ? F_STEP_TG1 : F_STEP_RG1) + width_index(m.slmax));
+    const int f = m.suni > 0 ? (m.angles ? F_STEP_T1 : F_STEP_R1) + log2_of(m.suni)
+                             : (m.angles ? F_STEP_TG1 : F_STEP_RG1) + width_index(m.slmax);
+    return Fn(f + (acc ? int(F_REAL_COUNT_) : 0));
   }
   int f = F_STEP_S1 + width_index(m.slmax);
   if (m.vim) {
@@ -196,7 +204,7 @@ int clamp_grid(int64_t work, int64_t limit) {
 
 hipError_t launch_step(const StepArgs& a, int grid, int block, hipStream_t stream) {
   if (block < kWave || block > kMaxBlock || block % kWave) return hipErrorInvalidValue;
-  if (a.real && (a.mode != kStep || a.yacc || a.m.vim || a.L.cnt || !a.m.full ||
+  if (a.real && (a.mode != kStep || a.m.vim || a.L.cnt || !a.m.full ||
                  int64_t(grid) * (block / kWave) < a.m.waves))
     return hipErrorInvalidValue;  // the real-amplitude kernels are one-pass walk steps only
   StepArgs c = a;

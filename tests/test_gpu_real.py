@@ -98,6 +98,28 @@ def test_mixed_s_batch_on_real_planes(Q, oracle_mod, kind):
         done = t
 
 
+@pytest.mark.parametrize("word", [0, 10])
+def test_solver_projection_on_real_planes(Q, oracle_mod, word):
+    """The solver's fused projection on one double per cell, in a context of
+    instances of mixed s (the solve works on instance 0): equal to the
+    oracle's walk-based solve of instance 0."""
+    if word:
+        a = W.fixed_point_band(128, 3, word, seed=95, negative=0.4)
+        other = W.fixed_point_band(64, 6, word, seed=96)
+    else:
+        a, other = W.offset_matrix(128, 6, seed=95), W.offset_matrix(64, 11, seed=96)
+    b = W.gaussian_b(128, seed=97)
+    kappa, j0 = 40.0, 30
+    om = oracle_mod.OracleMatrix(a, word=word)
+    beta, _ = oracle_mod.schedule(kappa, 1e-3)
+    y_ref = om.qls_walk(b, j0, oracle_mod.cks_coeffs(beta, j0))
+    for mats in ([a], [a, other]):
+        walk = Q.Walk(mats, word=word)
+        y, p_succ, steps = walk.qls(b, kappa=kappa, eps=1e-3, j0=j0)
+        assert steps == 2 * j0 + 1
+        assert np.abs(y - y_ref).max() <= 1e-12 * np.abs(y_ref).max(), len(mats)
+
+
 def test_switches_between_the_representations(Q, oracle_mod):
     csc, b = W.band_matrix(300, 5, seed=33), W.gaussian_b(300, seed=34)
     walk, st, ost = _pair(Q, oracle_mod, csc, b)
