@@ -173,7 +173,9 @@ struct qw_state {
   // branches of the state at that point (see total_written).
   int64_t written_base = 0;
   int64_t q1_base = 0;
-  uint32_t* stepno = nullptr;         // per-wavefront solver step counters
+  // The solver's coefficient window inside a captured graph: kSolverGraphSteps
+  // coefficients, then the index of the next replay's first one.
+  double* cwin = nullptr;
   double2* b = nullptr;     // device copy of b (N-vector layout)
   double* mbuf = nullptr;   // measurement scratch: max(kMaxGrid, 2*jtotal) doubles
   bool prepared = false;    // created by T~ |b~>
@@ -195,6 +197,7 @@ struct qw_state {
 namespace {
 
 constexpr int kGraphSteps = 16;  // steps per captured graph (even: the parity is preserved)
+constexpr int kSolverGraphSteps = 64;  // the same for the solver's graph (<= one wavefront's lanes: the window)
 
 void free_graphs(qw_state* st) {
   for (auto& g : st->graphs) (void)hipGraphExecDestroy(g.exec);
@@ -220,19 +223,18 @@ qw::Slots view(const qw_state* st) { return view(st, st->cur, st->r1s); }
 // A walk step leaves the next R1 as -Q1 of the input, the swap as +Q1.
 double r1s_after(int mode) { return mode == qw::kStep ? -1.0 : 1.0; }
 
-qw::StepArgs step_args(qw_state* st, int mode, double2* yacc, const double* coefm) {
+qw::StepArgs step_args(qw_state* st, int mode, double2* yacc, const double* coef) {
   qw::StepArgs a;
   a.m = st->ctx->mat();
   a.in = view(st);
   a.out = view(st, st->cur ^ 1, r1s_after(mode));
   a.L = st->L;
   a.acc = st->acc;
-  a.stepno = st->stepno;
   a.mode = mode;
   a.wpb = 0;  // set by the launcher
   a.tau = qw::kTau;
   a.yacc = yacc;
-  a.coefm = coefm;
+  a.coef = coef;
   a.zskip = st->ctx->zclosed && st->zclean ? 1 : 0;
   a.real = 0;
   return a;
@@ -245,8 +247,8 @@ qw::Slots rview(const qw_state* st, int p, double r1s) {
   return qw::Slots{plane(p, 0), plane(p ^ 1, 2), plane(p, 1), plane(p, 2), r1s};
 }
 
-qw::StepArgs step_args_real(qw_state* st, double2* yacc, const double* coefm) {
-  qw::StepArgs a = step_args(st, qw::kStep, yacc, coefm);
+qw::StepArgs step_args_real(qw_state* st, double2* yacc, const double* coef) {
+  qw::StepArgs a = step_args(st, qw::kStep, yacc, coef);
   a.in = rview(st, st->cur, st->r1s);
   a.out = rview(st, st->cur ^ 1, r1s_after(qw::kStep));
   a.real = 1;
@@ -298,8 +300,8 @@ int to_complex(qw_state* st, hipStream_t stream) {
   return QW_OK;
 }
 
-int launch_real(qw_state* st, hipStream_t stream, double2* yacc, const double* coefm) {
-  qw::StepArgs a = step_args_real(st, yacc, coefm);
+int launch_real(qw_state* st, hipStream_t stream, double2* yacc, const double* coef) {
+  qw::StepArgs a = step_args_real(st, yacc, coef);
   QW_HIP(qw::launch_step(a, step_grid(st), st->block, stream));
   st->cur ^= 1;
   st->r1s = r1s_after(qw::kStep);
@@ -307,10 +309,10 @@ int launch_real(qw_state* st, hipStream_t stream, double2* yacc, const double* c
   return QW_OK;
 }
 
-int launch_one(qw_state* st, int mode, hipStream_t stream, double2* yacc = nullptr, const double* coefm = nullptr) {
+int launch_one(qw_state* st, int mode, hipStream_t stream, double2* yacc = nullptr, const double* coef = nullptr) {
   int rc = to_complex(st, stream);
   if (rc) return rc;
-  qw::StepArgs a = step_args(st, mode, yacc, coefm);
+  qw::StepArgs a = step_args(st, mode, yacc, coef);
   QW_HIP(qw::launch_step(a, step_grid(st), st->block, stream));
   st->cur ^= 1;
   st->r1s = r1s_after(mode);
@@ -318,25 +320,36 @@ int launch_one(qw_state* st, int mode, hipStream_t stream, double2* yacc = nullp
   return QW_OK;
 }
 
-// Run `n` walk steps (with the solver's fused projection when yacc is set),
-// replaying a captured graph of kGraphSteps launches when a stream is given.
+// Run `n` walk steps (with the solver's fused projection when yacc is set:
+// the k-th launch of the call adds coefm[k] times the projection), replaying
+// a captured graph of kGraphSteps launches (kSolverGraphSteps for the
+// solver) when a stream is given.  Inside
+// the solver's graph a window node ahead of the steps copies the replay's
+// coefficients into st->cwin, so no step looks its coefficient up through a
+// device-side counter (a dependent load on every wavefront's path).
 int run_steps(qw_state* st, int64_t n, hipStream_t stream, double2* yacc = nullptr, const double* coefm = nullptr) {
   if (n == 0) return QW_OK;
   const bool real = real_path(st);
   int rc0 = real ? to_real(st, stream) : to_complex(st, stream);
   if (rc0) return rc0;
+  int64_t k = 0;  // launches of this call so far
   const auto one = [&]() {
-    return real ? launch_real(st, stream, yacc, coefm) : launch_one(st, qw::kStep, stream, yacc, coefm);
+    const double* coef = yacc ? coefm + k : nullptr;
+    ++k;
+    return real ? launch_real(st, stream, yacc, coef) : launch_one(st, qw::kStep, stream, yacc, coef);
   };
+  // graph length: the solver's window node is amortised over more steps
+  const int gsteps = yacc ? kSolverGraphSteps : kGraphSteps;
+  int64_t* cbase = reinterpret_cast<int64_t*>(st->cwin + kSolverGraphSteps);
   // A captured graph is replayed back to back, so it must start from the R1
   // sign its own steps leave: a state fresh from preparation, import or the
   // swap takes its first step directly.
-  if (stream != nullptr && n > kGraphSteps && st->r1s != r1s_after(qw::kStep)) {
+  if (stream != nullptr && n > gsteps && st->r1s != r1s_after(qw::kStep)) {
     int rc = one();
     if (rc) return rc;
     --n;
   }
-  if (stream != nullptr && n >= kGraphSteps && st->r1s == r1s_after(qw::kStep)) {
+  if (stream != nullptr && n >= gsteps && st->r1s == r1s_after(qw::kStep)) {
     GraphEntry* ge = nullptr;
     for (auto& g : st->graphs)
       if (g.stream == stream && g.parity == st->cur && g.r1s == st->r1s && g.steps == kGraphSteps &&
@@ -350,9 +363,12 @@ int run_steps(qw_state* st, int64_t n, hipStream_t stream, double2* yacc = nullp
       QW_HIP(hipStreamBeginCapture(stream, hipStreamCaptureModeThreadLocal));
       const int cur0 = st->cur;
       const double r1s0 = st->r1s;
-      for (int i = 0; i < kGraphSteps; ++i) {
-        qw::StepArgs a = real ? step_args_real(st, yacc, coefm) : step_args(st, qw::kStep, yacc, coefm);
-        hipError_t e = qw::launch_step(a, step_grid(st), st->block, stream);
+      for (int i = 0; i < gsteps; ++i) {
+        hipError_t e = hipSuccess;
+        if (yacc && i == 0) e = qw::launch_coef_window(coefm, cbase, st->cwin, gsteps, -1, stream);
+        const double* coef = yacc ? st->cwin + i : nullptr;
+        qw::StepArgs a = real ? step_args_real(st, yacc, coef) : step_args(st, qw::kStep, yacc, coef);
+        if (e == hipSuccess) e = qw::launch_step(a, step_grid(st), st->block, stream);
         st->cur ^= 1;
         st->r1s = r1s_after(qw::kStep);
         if (e != hipSuccess) {
@@ -369,15 +385,17 @@ int run_steps(qw_state* st, int64_t n, hipStream_t stream, double2* yacc = nullp
       if (e != hipSuccess) return set_err(QW_EDEVICE, std::string("graph instantiate: ") + hipGetErrorString(e));
       if (yacc == nullptr) st->graphs.push_back({stream, cur0, r1s0, kGraphSteps, real, exec});
     }
-    const int64_t reps = n / kGraphSteps;
+    const int64_t reps = n / gsteps;
+    if (yacc) QW_HIP(qw::launch_coef_window(coefm, cbase, st->cwin, gsteps, k, stream));
     for (int64_t r = 0; r < reps; ++r) QW_HIP(hipGraphLaunch(exec, stream));
-    st->launches += reps * kGraphSteps;
-    st->r1s = r1s_after(qw::kStep);  // the parity is back where it was (kGraphSteps is even)
+    st->launches += reps * gsteps;
+    k += reps * gsteps;
+    st->r1s = r1s_after(qw::kStep);  // the parity is back where it was (gsteps is even)
     if (yacc != nullptr) {
       QW_HIP(hipStreamSynchronize(stream));
       (void)hipGraphExecDestroy(exec);
     }
-    n -= reps * kGraphSteps;
+    n -= reps * gsteps;
   }
   for (int64_t i = 0; i < n; ++i) {
     int rc = one();
@@ -760,10 +778,10 @@ int state_alloc(qw_ctx* ctx, int64_t list_cap, qw_state** out, hipStream_t strea
     st->buf[k] = p ? qw::Slots{p, nullptr, p + ctx->items, p + 2 * ctx->items, 1.0} : qw::Slots{};
   }
   st->acc = static_cast<unsigned long long*>(state_get(st, sizeof(unsigned long long) * qw::kMaxWaves));
-  st->stepno = static_cast<uint32_t*>(state_get(st, sizeof(uint32_t) * qw::kMaxWaves));
+  st->cwin = static_cast<double*>(state_get(st, sizeof(double) * (kSolverGraphSteps + 1)));
   st->b = static_cast<double2*>(state_get(st, sizeof(double2) * ctx->jtotal));
   st->mbuf = static_cast<double*>(state_get(st, sizeof(double) * std::max<int64_t>(qw::kMaxGrid, 2 * ctx->jtotal + 2)));
-  ok = ok && st->acc && st->stepno && st->b && st->mbuf;
+  ok = ok && st->acc && st->cwin && st->b && st->mbuf;
   if (ok && list_cap > 0) ok = list_alloc(st, uint32_t(list_cap)) == QW_OK;
   if (!ok) {
     qw_state_free(st);
@@ -772,7 +790,6 @@ int state_alloc(qw_ctx* ctx, int64_t list_cap, qw_state** out, hipStream_t strea
   hipError_t e = hipSuccess;
   for (int k = 0; k < 2 && e == hipSuccess; ++k) e = qw::launch_fill(st->buf[k].R0, int64_t(3 * pb), stream);
   if (e == hipSuccess) e = qw::launch_fill(st->acc, sizeof(unsigned long long) * qw::kMaxWaves, stream);
-  if (e == hipSuccess) e = qw::launch_fill(st->stepno, sizeof(uint32_t) * qw::kMaxWaves, stream);
   if (e == hipSuccess) e = qw::launch_fill(st->b, sizeof(double2) * ctx->jtotal, stream);
   if (e != hipSuccess) {
     qw_state_free(st);

@@ -109,13 +109,15 @@ struct StepArgs {
   Slots in, out;
   List L;
   unsigned long long* acc;  // running counts of kept outputs (a Q1 output twice), kMaxWaves entries
-  uint32_t* stepno;         // per-wavefront step counter (indexes coefm), kMaxWaves entries
   int32_t mode;             // kStep: W; kSwap: S only
   int32_t wpb;              // wavefronts per workgroup (set by the launcher)
   double tau;
-  // optional fused projection (linear solver): y[j] += coefm[step] <psi~_j|state>
+  // optional fused projection (linear solver): y[j] += coef[0] <psi~_j|state>,
+  // coef pointing at this launch's coefficient (its entry of the host's table,
+  // or inside a graph an entry of a window that a node ahead of the steps
+  // refreshes on every replay: qwk_coef_window)
   double2* yacc;
-  const double* coefm;
+  const double* coef;
   // 1: every slot of value 0 has R0 = 0 (and Q0 = 0) in this state and its
   // partner is a slot of value 0 too, so the grid-stride and g kernels skip
   // those cells of such slots (they stay 0 under the step and the swap)
@@ -146,7 +148,7 @@ static_assert(sizeof(Slots) == 40 && offsetof(Slots, r1s) == 32, "Slots layout")
 static_assert(sizeof(List) == 24 && offsetof(List, cap) == 20, "List layout");
 static_assert(sizeof(SlotRec) == 16 && offsetof(SlotRec, val) == 8, "SlotRec layout");
 static_assert(sizeof(Matrix) == 176 && offsetof(Matrix, inst0) == 120, "Matrix layout");
-static_assert(sizeof(StepArgs) == 336 && offsetof(StepArgs, zskip) == 328, "StepArgs layout");
+static_assert(sizeof(StepArgs) == 328 && offsetof(StepArgs, zskip) == 320, "StepArgs layout");
 static_assert(sizeof(AdjArgs) == 424 && offsetof(AdjArgs, wpb) == 416, "AdjArgs layout");
 
 // Launchers (qw_launch.cpp).  All enqueue on `stream` and allocate nothing.
@@ -156,6 +158,10 @@ hipError_t launch_adjoint(const AdjArgs& a, int grid, int block, hipStream_t str
 hipError_t launch_qbs_table(const Matrix& m, SlotRec* rec, uint32_t* slink, double* sval, hipStream_t stream);
 hipError_t launch_init(const Matrix& m, const double2* b, Slots out, double tau, hipStream_t stream);
 hipError_t launch_fill(void* p, int64_t bytes, hipStream_t stream);
+// window[i] = table[*base + i] for i < count, then *base += count; with
+// set >= 0 only *base = set.
+hipError_t launch_coef_window(const double* table, int64_t* base, double* window, int32_t count, int64_t set,
+                              hipStream_t stream);
 // n complex cells to the one double each holds, and back: the imaginary part
 // where val (by cell, or NULL) is negative, the real part elsewhere.
 hipError_t launch_to_real(const double2* src, double* dst, const double* val, int64_t n, hipStream_t stream);

@@ -488,13 +488,8 @@ template <bool ACC, int SLM, int S, bool FAST, int ENC>
 __device__ __forceinline__ void step_body(const StepArgs& a) {
   const int lane = threadIdx.x & (kWave - 1);
   const int64_t wpb = a.wpb;  // a kernel argument: reading the workgroup size costs a vector load
-  const int64_t wid = int64_t(blockIdx.x) * wpb + (threadIdx.x >> 6);  // this wavefront's counter
-  double coef = 0.0;
-  uint32_t stepno = 0;
-  if (ACC) {
-    stepno = a.stepno[wid];
-    coef = a.coefm[stepno];
-  }
+  const int64_t wid = int64_t(blockIdx.x) * wpb + (threadIdx.x >> 6);  // this wavefront's index
+  const double coef = ACC ? *a.coef : 0.0;  // no dependent load: the pointer is this launch's
   const int64_t cidx = wave_counter(wpb);
   const unsigned long long prev = a.acc[cidx];
   unsigned cnt = 0;
@@ -516,7 +511,6 @@ __device__ __forceinline__ void step_body(const StepArgs& a) {
   }
   const unsigned long long v = wave_sum(cnt);
   if (lane == 0) a.acc[cidx] = prev + v;
-  if (ACC && lane == 0) a.stepno[wid] = stepno + 1;
 }
 
 }  // namespace qw
@@ -629,6 +623,14 @@ __device__ __forceinline__ unsigned step_wave_real(const StepArgs& a, int64_t w,
       x0[i] = zero[i] ? 0.0 : R0[h[i]];
     }
   }
+  // The solver's y_j, loaded with the data: it is not needed before the
+  // group sum.
+  double* yp = nullptr;
+  double yv = 0.0;
+  if (ACC && x.h == 0) {
+    yp = reinterpret_cast<double*>(a.yacc + x.I.jbase + x.j);
+    yv = *yp;
+  }
   double c = 0.0;
 #pragma unroll
   for (int i = 0; i < SLM; ++i) {
@@ -645,10 +647,7 @@ __device__ __forceinline__ unsigned step_wave_real(const StepArgs& a, int64_t w,
     }
   }
   c = row_sum_r(c, x.rpw_log);
-  if (ACC && x.h == 0) {  // the group sum is real: only the real part of y_j moves
-    double* y = reinterpret_cast<double*>(a.yacc + x.I.jbase + x.j);
-    *y += coef * (c * x.I.inv_sqrt_s);
-  }
+  if (ACC && x.h == 0) *yp = yv + coef * (c * x.I.inv_sqrt_s);  // the group sum is real: only Re y_j moves
   const double tc = c * (2.0 / double(x.I.s));
   unsigned cnt = 0;
 #pragma unroll
@@ -677,20 +676,13 @@ __device__ __forceinline__ void step_body_real(const StepArgs& a) {
   const int lane = threadIdx.x & (kWave - 1);
   const int64_t wpb = a.wpb;
   const int64_t wid = int64_t(blockIdx.x) * wpb + (threadIdx.x >> 6);
-  double coef = 0.0;
-  uint32_t stepno = 0;
-  if (ACC) {
-    stepno = a.stepno[wid];
-    coef = a.coefm[stepno];
-  }
   const int64_t w = uniform(int(wid));
-  if (w < a.m.waves) {  // no list: nothing to do past the slots
-    const int64_t cidx = wave_counter(wpb);
-    const unsigned long long prev = a.acc[cidx];
-    const unsigned long long v = wave_sum(step_wave_real<ACC, SLM, S, ENC>(a, w, lane, coef));
-    if (lane == 0) a.acc[cidx] = prev + v;
-  }
-  if (ACC && lane == 0) a.stepno[wid] = stepno + 1;  // every wavefront of the grid, as in step_body
+  if (w >= a.m.waves) return;  // no list: nothing to do past the slots
+  const double coef = ACC ? *a.coef : 0.0;
+  const int64_t cidx = wave_counter(wpb);
+  const unsigned long long prev = a.acc[cidx];
+  const unsigned long long v = wave_sum(step_wave_real<ACC, SLM, S, ENC>(a, w, lane, coef));
+  if (lane == 0) a.acc[cidx] = prev + v;
 }
 
 // Plane conversions for the switch between the two representations.  With
@@ -904,6 +896,22 @@ extern "C" __global__ void qwk_fill(uint4* p, int64_t n16) {
   const int64_t stride = int64_t(gridDim.x) * blockDim.x;
   for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n16; i += stride)
     p[i] = make_uint4(0u, 0u, 0u, 0u);
+}
+
+// The solver's coefficient window for a graph of `count` steps (one
+// wavefront, count <= 64): window[i] = table[*base + i], then *base += count.
+// Every lane reads *base in the one load ahead of lane 0's store, so the
+// update cannot overtake the reads.  With set >= 0 only *base = set.
+extern "C" __global__ void __launch_bounds__(64) qwk_coef_window(const double* __restrict__ table, int64_t* base,
+                                                                  double* window, int32_t count, int64_t set) {
+  const int lane = threadIdx.x;
+  if (set >= 0) {
+    if (lane == 0) *base = set;
+    return;
+  }
+  const int64_t b = *base;
+  if (lane < count) window[lane] = table[b + lane];
+  if (lane == 0) *base = b + count;
 }
 
 // ----------------------------------------------------------------- measurements

@@ -87,6 +87,7 @@ enum Fn {
   F_REAL_COUNT_ = F_STEP_TG1 + 4 - F_STEP_R1,
   F_TO_REAL = F_STEP_R1 + 2 * F_REAL_COUNT_,
   F_TO_COMPLEX,
+  F_COEF_WINDOW,
   F_COUNT
 };
 
@@ -116,7 +117,8 @@ const char* const kNames[] = {
     "qwk_step_r32_acc", "qwk_step_r64_acc", "qwk_step_t1_acc",  "qwk_step_t2_acc",  "qwk_step_t4_acc",
     "qwk_step_t8_acc",  "qwk_step_t16_acc", "qwk_step_t32_acc", "qwk_step_t64_acc", "qwk_step_rg1_acc",
     "qwk_step_rg2_acc", "qwk_step_rg4_acc", "qwk_step_rg8_acc", "qwk_step_tg1_acc", "qwk_step_tg2_acc",
-    "qwk_step_tg4_acc", "qwk_step_tg8_acc", "qwk_to_real",      "qwk_to_complex"};
+    "qwk_step_tg4_acc", "qwk_step_tg8_acc", "qwk_to_real",      "qwk_to_complex",
+    "qwk_coef_window"};
 static_assert(sizeof(kNames) / sizeof(kNames[0]) == F_COUNT, "one kernel name per Fn");
 
 // 0..3 for slmax = 1, 2, 4, 8
@@ -243,6 +245,13 @@ hipError_t launch_fill(void* ptr, int64_t bytes, hipStream_t stream) {
   uint4* q = static_cast<uint4*>(ptr);
   void* p[] = {&q, &n16};
   return launch(F_FILL, clamp_grid(n16, 4096), 256, stream, p);
+}
+
+hipError_t launch_coef_window(const double* table, int64_t* base, double* window, int32_t count, int64_t set,
+                              hipStream_t stream) {
+  if (count < 0 || count > kWave) return hipErrorInvalidValue;  // one wavefront fills the window
+  void* p[] = {&table, &base, &window, &count, &set};
+  return launch(F_COEF_WINDOW, 1, kWave, stream, p);
 }
 
 hipError_t launch_to_real(const double2* src, double* dst, const double* val, int64_t n, hipStream_t stream) {
