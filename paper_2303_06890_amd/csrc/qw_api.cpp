@@ -196,8 +196,10 @@ struct qw_state {
 
 namespace {
 
-constexpr int kGraphSteps = 16;  // steps per captured graph (even: the parity is preserved)
-constexpr int kSolverGraphSteps = 64;  // the same for the solver's graph (<= one wavefront's lanes: the window)
+// Steps per captured graph (even: the parity is preserved).
+constexpr int kLongGraphSteps = 256;
+constexpr int kGraphSteps = 16;
+constexpr int kSolverGraphSteps = 64;  // the solver's graph (<= one wavefront's lanes: the window)
 
 void free_graphs(qw_state* st) {
   for (auto& g : st->graphs) (void)hipGraphExecDestroy(g.exec);
@@ -322,11 +324,13 @@ int launch_one(qw_state* st, int mode, hipStream_t stream, double2* yacc = nullp
 
 // Run `n` walk steps (with the solver's fused projection when yacc is set:
 // the k-th launch of the call adds coefm[k] times the projection), replaying
-// a captured graph of kGraphSteps launches (kSolverGraphSteps for the
-// solver) when a stream is given.  Inside
-// the solver's graph a window node ahead of the steps copies the replay's
-// coefficients into st->cwin, so no step looks its coefficient up through a
-// device-side counter (a dependent load on every wavefront's path).
+// captured graphs when a stream is given: as many kLongGraphSteps-step
+// replays as fit, then kGraphSteps-step ones, then single launches (the
+// solver: kSolverGraphSteps-step replays).  A replay boundary costs about
+// as much as two launches, hence the long graph.  Inside the solver's graph
+// a window node ahead of the steps copies the replay's coefficients into
+// st->cwin, so no step looks its coefficient up through a device-side
+// counter (a dependent load on every wavefront's path).
 int run_steps(qw_state* st, int64_t n, hipStream_t stream, double2* yacc = nullptr, const double* coefm = nullptr) {
   if (n == 0) return QW_OK;
   const bool real = real_path(st);
@@ -336,25 +340,45 @@ int run_steps(qw_state* st, int64_t n, hipStream_t stream, double2* yacc = nullp
   const auto one = [&]() {
     const double* coef = yacc ? coefm + k : nullptr;
     ++k;
+    --n;
     return real ? launch_real(st, stream, yacc, coef) : launch_one(st, qw::kStep, stream, yacc, coef);
   };
-  // graph length: the solver's window node is amortised over more steps
-  const int gsteps = yacc ? kSolverGraphSteps : kGraphSteps;
-  int64_t* cbase = reinterpret_cast<int64_t*>(st->cwin + kSolverGraphSteps);
+  if (stream == nullptr) {
+    while (n > 0) {
+      int rc = one();
+      if (rc) return rc;
+    }
+    return QW_OK;
+  }
+  const int lens_plain[] = {kLongGraphSteps, kGraphSteps};
+  const int lens_solver[] = {kSolverGraphSteps};
+  const int* lens = yacc ? lens_solver : lens_plain;
+  const int nlens = yacc ? 1 : 2;
+  const auto cached = [&](int len, int parity) -> GraphEntry* {
+    if (yacc) return nullptr;  // the solver's graphs are not kept (y and the table change per solve)
+    for (auto& g : st->graphs)
+      if (g.stream == stream && g.parity == parity && g.r1s == r1s_after(qw::kStep) && g.steps == len &&
+          g.real == real)
+        return &g;
+    return nullptr;
+  };
   // A captured graph is replayed back to back, so it must start from the R1
   // sign its own steps leave: a state fresh from preparation, import or the
-  // swap takes its first step directly.
-  if (stream != nullptr && n > gsteps && st->r1s != r1s_after(qw::kStep)) {
+  // swap takes its first step directly.  So does a state whose graphs were
+  // captured at the other parity (one launch instead of a new capture).
+  int first = 0;  // the longest graph this call replays
+  for (int li = nlens - 1; li >= 0; --li)
+    if (n > lens[li]) first = lens[li];
+  if (first > 0 && (st->r1s != r1s_after(qw::kStep) || (!cached(first, st->cur) && cached(first, st->cur ^ 1)))) {
     int rc = one();
     if (rc) return rc;
-    --n;
   }
-  if (stream != nullptr && n >= gsteps && st->r1s == r1s_after(qw::kStep)) {
-    GraphEntry* ge = nullptr;
-    for (auto& g : st->graphs)
-      if (g.stream == stream && g.parity == st->cur && g.r1s == st->r1s && g.steps == kGraphSteps &&
-          g.real == real && yacc == nullptr)
-        ge = &g;
+  int64_t* cbase = reinterpret_cast<int64_t*>(st->cwin + kSolverGraphSteps);
+  for (int li = 0; li < nlens; ++li) {
+    const int len = lens[li];  // even: a replay leaves the parity where it was
+    const int64_t reps = n / len;
+    if (reps == 0 || st->r1s != r1s_after(qw::kStep)) continue;
+    GraphEntry* ge = cached(len, st->cur);
     hipGraphExec_t exec = nullptr;
     if (ge) {
       exec = ge->exec;
@@ -363,9 +387,9 @@ int run_steps(qw_state* st, int64_t n, hipStream_t stream, double2* yacc = nullp
       QW_HIP(hipStreamBeginCapture(stream, hipStreamCaptureModeThreadLocal));
       const int cur0 = st->cur;
       const double r1s0 = st->r1s;
-      for (int i = 0; i < gsteps; ++i) {
+      for (int i = 0; i < len; ++i) {
         hipError_t e = hipSuccess;
-        if (yacc && i == 0) e = qw::launch_coef_window(coefm, cbase, st->cwin, gsteps, -1, stream);
+        if (yacc && i == 0) e = qw::launch_coef_window(coefm, cbase, st->cwin, len, -1, stream);
         const double* coef = yacc ? st->cwin + i : nullptr;
         qw::StepArgs a = real ? step_args_real(st, yacc, coef) : step_args(st, qw::kStep, yacc, coef);
         if (e == hipSuccess) e = qw::launch_step(a, step_grid(st), st->block, stream);
@@ -383,21 +407,19 @@ int run_steps(qw_state* st, int64_t n, hipStream_t stream, double2* yacc = nullp
       hipError_t e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
       (void)hipGraphDestroy(graph);
       if (e != hipSuccess) return set_err(QW_EDEVICE, std::string("graph instantiate: ") + hipGetErrorString(e));
-      if (yacc == nullptr) st->graphs.push_back({stream, cur0, r1s0, kGraphSteps, real, exec});
+      if (yacc == nullptr) st->graphs.push_back({stream, cur0, r1s0, len, real, exec});
     }
-    const int64_t reps = n / gsteps;
-    if (yacc) QW_HIP(qw::launch_coef_window(coefm, cbase, st->cwin, gsteps, k, stream));
+    if (yacc) QW_HIP(qw::launch_coef_window(coefm, cbase, st->cwin, len, k, stream));
     for (int64_t r = 0; r < reps; ++r) QW_HIP(hipGraphLaunch(exec, stream));
-    st->launches += reps * gsteps;
-    k += reps * gsteps;
-    st->r1s = r1s_after(qw::kStep);  // the parity is back where it was (gsteps is even)
+    st->launches += reps * len;
+    k += reps * len;
+    n -= reps * len;
     if (yacc != nullptr) {
       QW_HIP(hipStreamSynchronize(stream));
       (void)hipGraphExecDestroy(exec);
     }
-    n -= reps * gsteps;
   }
-  for (int64_t i = 0; i < n; ++i) {
+  while (n > 0) {
     int rc = one();
     if (rc) return rc;
   }

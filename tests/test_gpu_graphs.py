@@ -1,0 +1,62 @@
+"""Long runs through the captured step graphs, against the oracle: 256-step
+and 16-step replays with the single launches around them, the one launch
+that moves a state onto the parity its graphs were captured at, each
+representation (one double per cell, complex planes, a grid-stride launch
+shape), and the solver's 64-step graph with its coefficient window."""
+import numpy as np
+import pytest
+
+import workloads as W
+from tests.parity import compare_states
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def Q():
+    import torch
+
+    assert torch.cuda.is_available()
+    import paper_2303_06890_amd as Q
+
+    return Q
+
+
+@pytest.mark.parametrize("kind", ["real", "complex", "grid_stride"])
+def test_long_runs_match_the_oracle(Q, oracle_mod, kind):
+    if kind == "complex":
+        csc = W.hermitian_offset_matrix(64, 4, seed=41)
+        b = W.gaussian_b(64, seed=42) * np.exp(0.2j * np.arange(64))
+    else:
+        csc, b = W.offset_matrix(64, 4, seed=43), W.gaussian_b(64, seed=44)
+    st = Q.Walk(csc).state(b)
+    if kind == "grid_stride":
+        st.set_launch(64, 1)
+    ost = oracle_mod.OracleState(oracle_mod.OracleMatrix(csc)).set_b(b).T()
+    assert st.stats()["real_amplitudes"] == (kind != "complex")
+    total = 0
+    # 600 from the T~ start: one launch, two 256-step replays, five 16-step
+    # replays, seven launches; 300 from the other parity: one launch to reach
+    # the graphs' parity, then replays; then counts around the graph lengths
+    for n in (600, 300, 17, 256, 513, 16, 2):
+        st.step(n)
+        ost.step(n)
+        total += n
+        gk, ga = st.export()
+        ok, oa = ost.export()
+        compare_states(gk, ga, ok, oa, where=f"{kind}, {total} steps")
+        assert st.stats()["launches"] == total
+
+
+def test_solver_graph_window(Q, oracle_mod):
+    """A solve of 2 j0 + 1 = 301 launches: one launch, four 64-step replays
+    with the window node ahead of each, 44 launches; equal to the oracle's
+    walk-based solve."""
+    csc, b = W.offset_matrix(64, 4, seed=45), W.gaussian_b(64, seed=46)
+    kappa, j0 = 60.0, 150
+    om = oracle_mod.OracleMatrix(csc)
+    beta, _ = oracle_mod.schedule(kappa, 1e-3)
+    y_ref = om.qls_walk(b, j0, oracle_mod.cks_coeffs(beta, j0))
+    y, _, steps = Q.Walk(csc).qls(b, kappa=kappa, eps=1e-3, j0=j0)
+    assert steps == 301
+    assert np.abs(y - y_ref).max() <= 1e-12 * np.abs(y_ref).max()
