@@ -33,15 +33,16 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "step_kernel_G16384x8_traffic.md")
+BATCHED_TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "batched_256_instances_traffic.md")
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_2303_06890_amd", "csrc", f) for f in ("qw_kernels.hip", "qw_internal.h")]
 
 
-def measured_traffic():
-    """HBM bytes per step launch from the committed counter summary (calibrated
+def measured_traffic(path: str = TRAFFIC_PROFILE):
+    """HBM bytes per step launch from a committed counter summary (calibrated
     FETCH_SIZE + WRITE_SIZE), or None when the summary is missing or was taken
     on other kernel sources than the ones in this tree."""
     try:
-        with open(TRAFFIC_PROFILE) as f:
+        with open(path) as f:
             text = f.read()
         digest = hashlib.sha256(b"".join(open(p, "rb").read() for p in KERNEL_SOURCES)).hexdigest()
     except OSError:
@@ -152,7 +153,12 @@ def batched_leg(Q, W, autotune, tune: bool, steps: int = 50, cpu: bool = True):
     st.step(steps)  # the same call untimed: captures the step graphs outside the timed region
     s0 = st.stats()
     ms = _timed(Q, lambda: st.step(steps))
-    upd = st.stats()["total_written"] - s0["total_written"]
+    s1 = st.stats()
+    upd = s1["total_written"] - s0["total_written"]
+    upd_in = upd - s1["branches"] + s0["branches"]
+    slots = int(sum(d["N"] * d["s"] for d in walk.info))
+    traffic = measured_traffic(BATCHED_TRAFFIC_PROFILE)
+    step_s = ms / 1e3 / steps
     singles = []
     for a, b in inst:
         w1 = Q.Walk(a)
@@ -163,13 +169,27 @@ def batched_leg(Q, W, autotune, tune: bool, steps: int = 50, cpu: bool = True):
     assert upd_plain == upd, (upd_plain, upd)
     return {
         "workload": "256 instances, n = 2^U{6..12}, 4..16 entries/column, single-column T~ starts, 50 steps",
-        "slots": int(sum(d["N"] * d["s"] for d in walk.info)),
+        "slots": slots,
         "steps": steps,
         "ms": ms,
         "value": upd / (ms / 1e3),
         "plain_ms": ms_plain,
         "plain_value": upd_plain / (ms_plain / 1e3),
         "speedup_vs_plain": ms_plain / ms,
+        # against HBM: the counters' bytes per launch (the state, ~150 MB in
+        # doubles, does not fit the caches); the algorithmic bytes (24 B per
+        # branch in and out + 12 B per slot) count keys and complex values
+        # this layout does not move, so they exceed what the kernel reads
+        "roofline": {
+            "bound": "hbm",
+            "kernel": "batched step kernel",
+            "traffic": traffic,
+            "achieved": traffic / step_s / 1e9 if traffic else None,
+            "peak": HBM_PEAK_GBS,
+            "unit": "GB/s",
+            "frac": traffic / step_s / 1e9 / HBM_PEAK_GBS if traffic else None,
+            "alg_bytes_per_launch": (24.0 * (upd + upd_in) + 12.0 * slots * steps) / steps,
+        },
         "launch_shape": list(shape) if shape else "default",
         "cpu_baseline": batched_cpu_baseline(inst) if cpu else None,
     }
@@ -448,6 +468,11 @@ def main():
     s1 = st.stats()
     out_total = s1["total_written"] - s0["total_written"]
     in_total = out_total - s1["branches"] + m_in0
+    # four more timed loops of the same count, after the reported one, for
+    # the spread (the reported figures are the first loop's)
+    repeats = [1e3 * ms / args.steps]
+    for _ in range(4):
+        repeats.append(1e3 * _timed(Q, lambda: st.step(args.steps)) / args.steps)
     alg_bytes = 24.0 * (in_total + out_total) + 12.0 * N * s * args.steps
     launch_s = ms / 1e3 / args.steps
     achieved = alg_bytes / args.steps / launch_s / 1e9
@@ -487,6 +512,8 @@ def main():
             "alg_bytes_per_launch": alg_bytes / args.steps,
             "avg_launch_us": launch_s * 1e6,
         },
+        "us_per_step_repeats": repeats,
+        "us_per_step_median_of_5": sorted(repeats)[2],
     }
     print(f"[bench] {args.steps} steps in {ms:.2f} ms ({launch_s * 1e6:.2f} us/step), "
           f"{value:.3e} updates/s, {achieved:.0f} GB/s algorithmic", file=sys.stderr, flush=True)
