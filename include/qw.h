@@ -165,10 +165,14 @@ int qw_state_init(qw_state** out, qw_ctx* ctx, const double* b_re, const double*
 
 /* Apply W^nsteps (Alg. 6: W = S T~ P T~^dagger), branches with |Re| and |Im|
  * both <= tau (1e-13) removed after every step.  One kernel launch per step;
- * asynchronous; the step loop is replayed from a captured HIP graph (16 steps
- * per graph, built on first use for the stream and kept with the state) when
- * `stream` is not NULL.  The state's amplitude planes are double-buffered
- * inside the state; nothing is allocated once the graph exists.
+ * asynchronous.  When `stream` is not NULL the step loop is replayed from
+ * captured HIP graphs of 256 and of 16 steps (as many long replays as fit,
+ * then short ones, then single launches), each built on first use for the
+ * stream, the state's parity and its representation, and kept with the
+ * state; a state at the other parity from its graphs takes one single step
+ * first.  The state's amplitude planes are double-buffered inside the state
+ * (the 8-byte planes of one double per cell are allocated at the first step
+ * that uses them); nothing is allocated once the graphs exist.
  * Errors: QW_EINVAL (NULL state, nsteps < 0), QW_EDEVICE (launch or graph
  * failure). */
 int qw_step(qw_state* st, int32_t nsteps, void* stream);
