@@ -520,7 +520,8 @@ __device__ __forceinline__ void step_body(const StepArgs& a) {
 // every instance has at least one wavefront of rows, one pass, walk step;
 // qwk_step_fS: as gN with s = S for every instance; qwk_step_cN: as sN for a
 // complex Hermitian matrix; qwk_step_xN: as sN for fixed-point data;
-// qwk_step_hN and qwk_step_yN: as gN for those two.
+// qwk_step_hN and qwk_step_yN: as gN for those two; qwk_step_kS: as fS for
+// a complex Hermitian matrix.
 #define QW_STEP_KERNEL(NAME, SLM, S, FAST, ENC)                                                    \
   extern "C" __global__ void __launch_bounds__(256) NAME(qw::StepArgs a) {                         \
     qw::step_body<false, SLM, S, FAST, ENC>(a);                                                     \
@@ -559,6 +560,13 @@ QW_STEP_KERNEL(qwk_step_y1, 1, 0, true, qw::kEncAngle)
 QW_STEP_KERNEL(qwk_step_y2, 2, 0, true, qw::kEncAngle)
 QW_STEP_KERNEL(qwk_step_y4, 4, 0, true, qw::kEncAngle)
 QW_STEP_KERNEL(qwk_step_y8, 8, 0, true, qw::kEncAngle)
+QW_STEP_KERNEL(qwk_step_k1, 1, 1, true, qw::kEncComplex)
+QW_STEP_KERNEL(qwk_step_k2, 1, 2, true, qw::kEncComplex)
+QW_STEP_KERNEL(qwk_step_k4, 1, 4, true, qw::kEncComplex)
+QW_STEP_KERNEL(qwk_step_k8, 1, 8, true, qw::kEncComplex)
+QW_STEP_KERNEL(qwk_step_k16, 2, 16, true, qw::kEncComplex)
+QW_STEP_KERNEL(qwk_step_k32, 4, 32, true, qw::kEncComplex)
+QW_STEP_KERNEL(qwk_step_k64, 8, 64, true, qw::kEncComplex)
 #undef QW_STEP_KERNEL
 
 namespace qw {

@@ -28,7 +28,7 @@ namespace {
 // qwk_step_c{1,2,4,8} are the general kernels for complex Hermitian matrices
 // and qwk_step_x{1,2,4,8} those for fixed-point data, qwk_step_h{1,2,4,8} and
 // qwk_step_y{1,2,4,8} their one-pass forms (the conditions of the g
-// kernels).  Each has an _acc twin
+// kernels); qwk_step_k{S} is the complex form of the f kernels.  Each has an _acc twin
 // (the solver's fused projection).  Adjoint kernels (real FP64 matrices) come
 // in the four widths.  qwk_step_r{S} and qwk_step_t{S} are the f kernels on
 // one double per cell (8-byte planes), FP64 and fixed-point values, and
@@ -66,7 +66,8 @@ enum Fn {
   F_STEP_Y2,
   F_STEP_Y4,
   F_STEP_Y8,
-  F_STEP_COUNT_,  // _acc twins follow at + F_STEP_COUNT_
+  F_STEP_K1,  // complex values, s = 1 ... 64 for every instance: qwk_step_k{1..64}
+  F_STEP_COUNT_ = F_STEP_K1 + 7,  // _acc twins follow at + F_STEP_COUNT_
   F_ADJOINT_S1 = 2 * F_STEP_COUNT_,
   F_ADJOINT_S2,
   F_ADJOINT_S4,
@@ -98,14 +99,16 @@ const char* const kNames[] = {
     "qwk_step_c1",      "qwk_step_c2",      "qwk_step_c4",      "qwk_step_c8",      "qwk_step_x1",
     "qwk_step_x2",      "qwk_step_x4",      "qwk_step_x8",      "qwk_step_h1",      "qwk_step_h2",
     "qwk_step_h4",      "qwk_step_h8",      "qwk_step_y1",      "qwk_step_y2",      "qwk_step_y4",
-    "qwk_step_y8",
+    "qwk_step_y8",      "qwk_step_k1",      "qwk_step_k2",      "qwk_step_k4",      "qwk_step_k8",
+    "qwk_step_k16",     "qwk_step_k32",     "qwk_step_k64",
     "qwk_step_s1_acc",  "qwk_step_s2_acc",  "qwk_step_s4_acc",  "qwk_step_s8_acc",  "qwk_step_g1_acc",
     "qwk_step_g2_acc",  "qwk_step_g4_acc",  "qwk_step_g8_acc",  "qwk_step_f1_acc",  "qwk_step_f2_acc",
     "qwk_step_f4_acc",  "qwk_step_f8_acc",  "qwk_step_f16_acc", "qwk_step_f32_acc", "qwk_step_f64_acc",
     "qwk_step_c1_acc",  "qwk_step_c2_acc",  "qwk_step_c4_acc",  "qwk_step_c8_acc",  "qwk_step_x1_acc",
     "qwk_step_x2_acc",  "qwk_step_x4_acc",  "qwk_step_x8_acc",  "qwk_step_h1_acc",  "qwk_step_h2_acc",
     "qwk_step_h4_acc",  "qwk_step_h8_acc",  "qwk_step_y1_acc",  "qwk_step_y2_acc",  "qwk_step_y4_acc",
-    "qwk_step_y8_acc",
+    "qwk_step_y8_acc",  "qwk_step_k1_acc",  "qwk_step_k2_acc",  "qwk_step_k4_acc",  "qwk_step_k8_acc",
+    "qwk_step_k16_acc", "qwk_step_k32_acc", "qwk_step_k64_acc",
     "qwk_adjoint_s1",   "qwk_adjoint_s2",   "qwk_adjoint_s4",   "qwk_adjoint_s8",   "qwk_qbs_table",
     "qwk_init",         "qwk_fill",         "qwk_measure",      "qwk_measure_rows", "qwk_export",
     "qwk_import",       "qwk_weight",       "qwk_grad_init",    "qwk_step_r1",      "qwk_step_r2",
@@ -143,6 +146,7 @@ Fn step_kernel(const StepArgs& a, int grid, int block) {
   int f = F_STEP_S1 + width_index(m.slmax);
   if (m.vim) {
     f = (one_pass ? F_STEP_H1 : F_STEP_C1) + width_index(m.slmax);
+    if (one_pass && m.suni > 0) f = F_STEP_K1 + log2_of(m.suni);
   } else if (m.angles) {
     f = (one_pass ? F_STEP_Y1 : F_STEP_X1) + width_index(m.slmax);
   } else if (one_pass) {
