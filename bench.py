@@ -374,7 +374,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=2000)
     ap.add_argument("--warmup", type=int, default=64)
-    ap.add_argument("--cpu-steps", type=int, default=5, help="walk steps of the oracle sample")
+    ap.add_argument("--cpu-steps", type=int, default=8, help="walk steps of the oracle sample (about 15 s)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true", help="skip the batched, adjoint, solver, complex, paper-shape and branch-count legs")
     ap.add_argument("--no-tune", action="store_true", help="keep the default launch shape")
