@@ -169,6 +169,7 @@ struct qw_state {
   double r1s = 1.0;         // buffer cur^1's Q1 plane holds r1s * (the state's R1)
   List L{};                 // branches without a static home (count on the host)
   unsigned long long* acc = nullptr;  // counts of kept outputs (a Q1 output twice), kMaxWaves entries
+  bool counts = true;       // false: the step kernels keep no counts (the solver's private walk)
   // Branches written before the counts were last restarted, and the Q1
   // branches of the state at that point (see total_written).
   int64_t written_base = 0;
@@ -231,7 +232,7 @@ qw::StepArgs step_args(qw_state* st, int mode, double2* yacc, const double* coef
   a.in = view(st);
   a.out = view(st, st->cur ^ 1, r1s_after(mode));
   a.L = st->L;
-  a.acc = st->acc;
+  a.acc = st->counts ? st->acc : nullptr;
   a.mode = mode;
   a.wpb = 0;  // set by the launcher
   a.tau = qw::kTau;
@@ -1285,6 +1286,7 @@ int qls_run(qw_ctx* ctx, const double* b, double kappa, double eps, int32_t j0_o
   qw_state* st = nullptr;
   int rc = qw_state_init(&st, ctx, bfull.data(), nullptr, 0, 0, stream_v);
   if (rc) return rc;
+  st->counts = false;  // nobody reads this walk's branch counts
   const int64_t N = ctx->inst[0].N;
   double* dcoef = static_cast<double*>(ctx->alloc.get(sizeof(double) * coefm.size()));
   double2* y = static_cast<double2*>(ctx->alloc.get(sizeof(double2) * ctx->jtotal));

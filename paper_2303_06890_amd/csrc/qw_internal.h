@@ -108,7 +108,8 @@ struct StepArgs {
   Matrix m;
   Slots in, out;
   List L;
-  unsigned long long* acc;  // running counts of kept outputs (a Q1 output twice), kMaxWaves entries
+  unsigned long long* acc;  // running counts of kept outputs (a Q1 output twice), kMaxWaves entries,
+                            // or NULL: no counts (a walk whose counts nobody reads)
   int32_t mode;             // kStep: W; kSwap: S only
   int32_t wpb;              // wavefronts per workgroup (set by the launcher)
   double tau;

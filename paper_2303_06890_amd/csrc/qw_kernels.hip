@@ -491,7 +491,8 @@ __device__ __forceinline__ void step_body(const StepArgs& a) {
   const int64_t wid = int64_t(blockIdx.x) * wpb + (threadIdx.x >> 6);  // this wavefront's index
   const double coef = ACC ? *a.coef : 0.0;  // no dependent load: the pointer is this launch's
   const int64_t cidx = wave_counter(wpb);
-  const unsigned long long prev = a.acc[cidx];
+  const bool counting = a.acc != nullptr;  // the solver's private walk keeps no counts
+  const unsigned long long prev = counting ? a.acc[cidx] : 0ull;
   unsigned cnt = 0;
   if (FAST) {
     const int64_t w = uniform(int(wid));
@@ -509,8 +510,10 @@ __device__ __forceinline__ void step_body(const StepArgs& a) {
         cnt += list_entry(a.L, (w - a.m.waves) * kWave + lane, a.m.nbits, a.mode == kStep);
     }
   }
-  const unsigned long long v = wave_sum(cnt);
-  if (lane == 0) a.acc[cidx] = prev + v;
+  if (counting) {
+    const unsigned long long v = wave_sum(cnt);
+    if (lane == 0) a.acc[cidx] = prev + v;
+  }
 }
 
 }  // namespace qw
@@ -688,6 +691,10 @@ __device__ __forceinline__ void step_body_real(const StepArgs& a) {
   if (w >= a.m.waves) return;  // no list: nothing to do past the slots
   const double coef = ACC ? *a.coef : 0.0;
   const int64_t cidx = wave_counter(wpb);
+  if (a.acc == nullptr) {  // the solver's private walk keeps no counts
+    (void)step_wave_real<ACC, SLM, S, ENC>(a, w, lane, coef);
+    return;
+  }
   const unsigned long long prev = a.acc[cidx];
   const unsigned long long v = wave_sum(step_wave_real<ACC, SLM, S, ENC>(a, w, lane, coef));
   if (lane == 0) a.acc[cidx] = prev + v;
