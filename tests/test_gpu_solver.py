@@ -64,3 +64,27 @@ def test_qls_laplacian_32x32(Q, oracle_mod):
     fid = abs(np.vdot(x, y)) ** 2 / (np.vdot(x, x).real * np.vdot(y, y).real)
     assert fid > 1 - 1e-9
     assert 1e-4 < p_succ < 1e-3
+
+
+@pytest.mark.parametrize("mixed", [False, True])
+def test_qls_on_the_complex_planes(Q, oracle_mod, mixed):
+    """A real matrix whose negative value has a positive partner keeps the
+    complex planes (the f and g kernels' fused projection, one s and mixed
+    s): equal to the oracle's walk-based solve, through a 64-step graph."""
+    a = np.diag(np.full(64, 0.5))
+    for j in range(63):
+        a[j + 1, j] = a[j, j + 1] = 0.2
+    a[7, 8] = -0.2  # its mirror a[8, 7] stays positive
+    csc = W.from_dense(a)
+    b = W.gaussian_b(64, seed=47)
+    kappa, j0 = 30.0, 40
+    om = oracle_mod.OracleMatrix(csc)
+    beta, _ = oracle_mod.schedule(kappa, 1e-3)
+    y_ref = om.qls_walk(b, j0, oracle_mod.cks_coeffs(beta, j0))
+    mats = [csc, W.offset_matrix(64, 11, seed=48)] if mixed else [csc]
+    walk = Q.Walk(mats, symmetric=False)
+    st = walk.state([b] + [W.uniform_b(64)] * (len(mats) - 1) if mixed else b)
+    assert not st.stats()["real_amplitudes"]
+    y, _, steps = walk.qls(b, kappa=kappa, eps=1e-3, j0=j0)
+    assert steps == 2 * j0 + 1
+    assert np.abs(y - y_ref).max() <= 1e-12 * np.abs(y_ref).max()
