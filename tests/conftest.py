@@ -1,3 +1,4 @@
+import json
 import os
 import sys
 
@@ -19,3 +20,10 @@ def oracle_mod():
 
     oracle._load()
     return oracle
+
+
+def load_golden(name):
+    """A fixture file under tests/golden/ (values the paper prints, each file
+    with its citation)."""
+    with open(os.path.join(ROOT, "tests", "golden", name)) as f:
+        return json.load(f)

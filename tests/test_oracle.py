@@ -10,6 +10,7 @@ import numpy as np
 import pytest
 
 import workloads as W
+from tests.conftest import load_golden
 from tests.dense_sim import DenseWalk, preprocess
 
 
@@ -54,17 +55,20 @@ def _matrix_with_row(oracle_mod, row_cols, N=16):
 
 def test_os_inverse_worked_example(oracle_mod):
     # O_s'^dagger on k = 0, k_c = 0 in a row {2, 5, 8, 10}: QBS misses, the
-    # QRAM read at slot 0 gives column 2, so (l, z) = (0, 2)  (Sec. III.B)
-    csc = _matrix_with_row(oracle_mod, [2, 5, 8, 10])
+    # QRAM read at slot 0 gives column 2, so (l, z) = (0, 2)  (the appendix's
+    # worked example; tests/golden/os_inverse_worked_example.json)
+    g = load_golden("os_inverse_worked_example.json")
+    csc = _matrix_with_row(oracle_mod, g["row"])
     m = oracle_mod.OracleMatrix(csc)
     col, _, _ = m.ell()
-    assert list(col[0]) == [2, 5, 8, 10]
+    assert list(col[0]) == g["row"]
     st = oracle_mod.OracleState(m, tau=0.0)
-    key = oracle_mod.pack_key(m.nbits, 0, 0, 0, 0, 0, 0)
+    key = oracle_mod.pack_key(m.nbits, 0, 0, 0, g["input"]["k_c"], g["input"]["k"], 0)
     st.import_(np.array([key], np.uint64), np.array([1.0 + 0j]))
     st.apply_op(oracle_mod.OP_OSINV)
     keys, _ = st.export()
-    assert int(keys[0]) == oracle_mod.pack_key(m.nbits, 0, 0, 0, 2, 0, 0)  # k_c holds z=2, k holds l=0
+    # k_c holds z, k holds l
+    assert int(keys[0]) == oracle_mod.pack_key(m.nbits, 0, 0, 0, g["output"]["k_c"], g["output"]["k"], 0)
     # a valid input: k = 8 is slot 2 of row 0 -> (l, z) = (2, 0), the plain O_s
     st.import_(np.array([oracle_mod.pack_key(m.nbits, 0, 0, 0, 0, 8, 0)], np.uint64), np.array([1.0 + 0j]))
     st.apply_op(oracle_mod.OP_OSINV)

@@ -6,6 +6,7 @@ import numpy as np
 import pytest
 
 import workloads as W
+from tests.conftest import load_golden
 from tests.dense_sim import preprocess, torch_loss
 
 
@@ -60,11 +61,16 @@ def test_schedule_laplacian(oracle_mod):
     assert beta == int(np.ceil((1 / lam) ** 2 * np.log(1 / lam / 1e-3)))
 
 
-@pytest.mark.parametrize("kappa_printed,j0_printed", [(1.0e2, 1532), (6.6e2, 11824), (5.0e3, 106122)])
+_SETTINGS = load_golden("experimental_settings.json")
+
+
+@pytest.mark.parametrize("kappa_printed,j0_printed",
+                         [(r["kappa"], r["j0"]) for r in _SETTINGS["rows"] if r["j0"] is not None])
 def test_schedule_reproduces_table1(oracle_mod, kappa_printed, j0_printed):
-    """Table I prints kappa to two significant digits; some kappa in
-    [printed, printed + one unit of the second digit) gives the printed j0
-    with natural logarithms and eps = 1e-3."""
+    """The table of experimental settings prints kappa to two significant
+    digits; some kappa in [printed, printed + one unit of the second digit)
+    gives the printed j0 with natural logarithms and eps = 1e-3
+    (tests/golden/experimental_settings.json)."""
     unit = 10 ** (np.floor(np.log10(kappa_printed)) - 1)
     lo, hi = kappa_printed, kappa_printed + unit
     assert oracle_mod.schedule(lo, 1e-3)[1] <= j0_printed <= oracle_mod.schedule(hi, 1e-3)[1]
@@ -76,6 +82,27 @@ def test_schedule_reproduces_table1(oracle_mod, kappa_printed, j0_printed):
         else:
             hi = mid
     assert oracle_mod.schedule(hi, 1e-3)[1] == j0_printed
+
+
+def test_walk_steps_of_matrix_c():
+    """The text gives 212245 = 2 j0 + 1 walk steps for the 1024 matrix."""
+    c = next(r for r in _SETTINGS["rows"] if r["name"] == "C")
+    assert _SETTINGS["walk_steps_C"] == 2 * c["j0"] + 1
+
+
+@pytest.mark.parametrize("row", _SETTINGS["rows"], ids=lambda r: r["name"])
+def test_workload_shapes_match_the_table(oracle_mod, row):
+    """The band workloads of the five experiments have the table's row size,
+    sparsity (footnote b: s = 2^ceil(log2(2 * bandwidth + 1))) and word
+    length."""
+    csc, _ = W.table1_band(row["name"])
+    m = oracle_mod.OracleMatrix(csc)
+    assert (csc.n, m.N, m.s) == (row["row_size"], row["row_size"], row["s"])
+    r, c = np.nonzero(csc.dense())
+    bw = int(np.abs(r - c).max())
+    assert 2 ** int(np.ceil(np.log2(2 * bw + 1))) == row["s"]
+    assert W.TABLE1_WORD[row["name"]] == row["word_length"]
+    assert W.TABLE1_PAPER_SECONDS_PER_STEP[row["name"]] == pytest.approx(row["seconds_per_step"])
 
 
 # ---------------------------------------------------------------- series and walk solver
