@@ -913,6 +913,23 @@ extern "C" __global__ void qwk_fill(uint4* p, int64_t n16) {
     p[i] = make_uint4(0u, 0u, 0u, 0u);
 }
 
+// Sum of the per-wavefront counters (one workgroup of 1024 threads): *out =
+// a[0] + ... + a[n-1].
+extern "C" __global__ void __launch_bounds__(1024) qwk_sum_counts(const unsigned long long* __restrict__ a, int64_t n,
+                                                                   unsigned long long* out) {
+  __shared__ unsigned long long part[1024 / 64];
+  unsigned long long v = 0;
+  for (int64_t i = threadIdx.x; i < n; i += blockDim.x) v += a[i];
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+  if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = v;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    unsigned long long t = 0;
+    for (int i = 0; i < int(blockDim.x >> 6); ++i) t += part[i];
+    *out = t;
+  }
+}
+
 // The solver's coefficient window for a graph of `count` steps (one
 // wavefront, count <= 64): window[i] = table[*base + i], then *base += count.
 // Every lane reads *base in the one load ahead of lane 0's store, so the

@@ -89,6 +89,7 @@ enum Fn {
   F_TO_REAL = F_STEP_R1 + 2 * F_REAL_COUNT_,
   F_TO_COMPLEX,
   F_COEF_WINDOW,
+  F_SUM_COUNTS,
   F_COUNT
 };
 
@@ -121,7 +122,7 @@ const char* const kNames[] = {
     "qwk_step_t8_acc",  "qwk_step_t16_acc", "qwk_step_t32_acc", "qwk_step_t64_acc", "qwk_step_rg1_acc",
     "qwk_step_rg2_acc", "qwk_step_rg4_acc", "qwk_step_rg8_acc", "qwk_step_tg1_acc", "qwk_step_tg2_acc",
     "qwk_step_tg4_acc", "qwk_step_tg8_acc", "qwk_to_real",      "qwk_to_complex",
-    "qwk_coef_window"};
+    "qwk_coef_window",  "qwk_sum_counts"};
 static_assert(sizeof(kNames) / sizeof(kNames[0]) == F_COUNT, "one kernel name per Fn");
 
 // 0..3 for slmax = 1, 2, 4, 8
@@ -249,6 +250,11 @@ hipError_t launch_fill(void* ptr, int64_t bytes, hipStream_t stream) {
   uint4* q = static_cast<uint4*>(ptr);
   void* p[] = {&q, &n16};
   return launch(F_FILL, clamp_grid(n16, 4096), 256, stream, p);
+}
+
+hipError_t launch_sum_counts(const unsigned long long* a, int64_t n, unsigned long long* out, hipStream_t stream) {
+  void* p[] = {&a, &n, &out};
+  return launch(F_SUM_COUNTS, 1, 1024, stream, p);
 }
 
 hipError_t launch_coef_window(const double* table, int64_t* base, double* window, int32_t count, int64_t set,
