@@ -11,8 +11,10 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <numeric>
 #include <string>
+#include <utility>
 #include <vector>
 
 using qw::List;
@@ -91,6 +93,14 @@ struct qw_ctx {
   // order the caller frees them in
   std::atomic<int> refs{1};
   Alloc alloc;
+  // Device buffers of freed states, kept for the next states of this context
+  // (one allocation through a caller's allocator can cost several us; a
+  // state has eight): at most kPoolPerSize buffers of one size and
+  // kPoolBytes in all, released with the context.  A state is freed after a
+  // device synchronisation, so no launch still uses a pooled buffer.
+  std::mutex pool_mu;
+  std::vector<std::pair<size_t, void*>> pool;
+  size_t pool_bytes = 0;
   int32_t ninst = 0;
   int32_t nbits = 0;  // key register width
   int64_t items = 0;  // ELL slots incl. alignment padding
@@ -192,7 +202,7 @@ struct qw_state {
   int block = 256;
   int grid = 0;             // 0 = automatic
   std::vector<GraphEntry> graphs;
-  std::vector<void*> owned;
+  std::vector<std::pair<void*, size_t>> owned;  // device buffers and their requested sizes
 };
 
 namespace {
@@ -606,6 +616,7 @@ void ctx_release(qw_ctx* ctx) {
   ctx->alloc.put(ctx->vim);
   ctx->alloc.put(ctx->dinst);
   ctx->alloc.put(ctx->wave_inst);
+  for (const auto& e : ctx->pool) ctx->alloc.put(e.second);
   delete ctx;
 }
 
@@ -761,17 +772,51 @@ int load_impl(qw_ctx** out, int32_t ninst, const int32_t* n, const int64_t* colp
 
 // ---- states ---------------------------------------------------------------------
 
+constexpr int kPoolPerSize = 4;
+constexpr size_t kPoolBytes = size_t(4) << 30;
+
+// A buffer of `bytes` from the context's pool, else from its allocator.
+void* ctx_take(qw_ctx* ctx, size_t bytes) {
+  {
+    std::lock_guard<std::mutex> lock(ctx->pool_mu);
+    for (size_t i = 0; i < ctx->pool.size(); ++i)
+      if (ctx->pool[i].first == bytes) {
+        void* p = ctx->pool[i].second;
+        ctx->pool[i] = ctx->pool.back();
+        ctx->pool.pop_back();
+        ctx->pool_bytes -= bytes;
+        return p;
+      }
+  }
+  return ctx->alloc.get(bytes);
+}
+// Back to the pool, or to the allocator when the pool is full.
+void ctx_give(qw_ctx* ctx, void* p, size_t bytes) {
+  {
+    std::lock_guard<std::mutex> lock(ctx->pool_mu);
+    int same = 0;
+    for (const auto& e : ctx->pool) same += e.first == bytes;
+    if (same < kPoolPerSize && ctx->pool_bytes + bytes <= kPoolBytes) {
+      ctx->pool.push_back({bytes, p});
+      ctx->pool_bytes += bytes;
+      return;
+    }
+  }
+  ctx->alloc.put(p);
+}
+
 void* state_get(qw_state* st, size_t bytes) {
-  void* p = st->ctx->alloc.get(bytes);
-  if (p) st->owned.push_back(p);
+  void* p = ctx_take(st->ctx, bytes);
+  if (p) st->owned.push_back({p, bytes});
   return p;
 }
 // The same, starting on a 2 MiB boundary when 2 MiB or larger.
 void* state_get_paged(qw_state* st, size_t bytes) {
-  void* raw = nullptr;
-  void* p = st->ctx->alloc.get_paged(bytes, &raw);
-  if (raw) st->owned.push_back(raw);
-  return p;
+  constexpr uintptr_t kPage = uintptr_t(2) << 20;
+  if (bytes < kPage) return state_get(st, bytes);
+  char* raw = static_cast<char*>(state_get(st, bytes + kPage));
+  if (!raw) return nullptr;
+  return reinterpret_cast<void*>((reinterpret_cast<uintptr_t>(raw) + kPage - 1) & ~(kPage - 1));
 }
 
 // Allocate the general list for `cap` branches (previous contents dropped).
@@ -1096,7 +1141,7 @@ void qw_state_free(qw_state* st) {
   (void)hipDeviceSynchronize();
   free_graphs(st);
   qw_ctx* ctx = st->ctx;
-  for (void* p : st->owned) ctx->alloc.put(p);
+  for (const auto& o : st->owned) ctx_give(ctx, o.first, o.second);
   delete st;
   ctx_release(ctx);
 }
@@ -1345,9 +1390,9 @@ int qw_grad(qw_state* st, const double* w, int32_t nsteps, double* dvals, double
   int rc = state_alloc(ctx, st->L.cap, &lam, stream);
   if (rc) return rc;
   lam->L.cnt = st->L.cnt;
-  double* dw = static_cast<double*>(ctx->alloc.get(sizeof(double) * ctx->jtotal));
-  double* dv = static_cast<double*>(ctx->alloc.get(sizeof(double) * ctx->items));
-  double2* db = static_cast<double2*>(ctx->alloc.get(sizeof(double2) * ctx->jtotal));
+  double* dw = static_cast<double*>(ctx_take(ctx, sizeof(double) * ctx->jtotal));
+  double* dv = static_cast<double*>(ctx_take(ctx, sizeof(double) * ctx->items));
+  double2* db = static_cast<double2*>(ctx_take(ctx, sizeof(double2) * ctx->jtotal));
   std::vector<double> hdv(static_cast<size_t>(ctx->items));
   std::vector<double2> hdb(static_cast<size_t>(ctx->jtotal));
   std::vector<double> part(256);
@@ -1391,9 +1436,10 @@ int qw_grad(qw_state* st, const double* w, int32_t nsteps, double* dvals, double
   if (e == hipSuccess && !rc)
     e = hipMemcpyAsync(hdb.data(), db, sizeof(double2) * ctx->jtotal, hipMemcpyDeviceToHost, stream);
   if (e == hipSuccess && !rc) e = hipStreamSynchronize(stream);
-  ctx->alloc.put(dw);
-  ctx->alloc.put(dv);
-  ctx->alloc.put(db);
+  (void)hipStreamSynchronize(stream);  // after an error too: nothing may still use the buffers
+  if (dw) ctx_give(ctx, dw, sizeof(double) * ctx->jtotal);
+  if (dv) ctx_give(ctx, dv, sizeof(double) * ctx->items);
+  if (db) ctx_give(ctx, db, sizeof(double2) * ctx->jtotal);
   qw_state_free(lam);
   st->steps_since_init = 0;
   if (e != hipSuccess)
