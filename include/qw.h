@@ -16,8 +16,11 @@
  *   - Host arrays are borrowed for the duration of the call only.
  *   - Device memory comes from the caller's allocator (qw_allocator; NULL
  *     means hipMalloc/hipFree) and belongs to the qw_ctx or qw_state that
- *     allocated it until it is freed.  Nothing is allocated inside qw_step,
- *     qw_step_adjoint or qls_run's step loop.
+ *     allocated it until it is freed.  A freed state's buffers stay with its
+ *     context, for the next states made from it (at most four of one size,
+ *     4 GiB in all), and return to the allocator when the context goes.
+ *     Nothing is allocated inside qw_step, qw_step_adjoint or qls_run's step
+ *     loop once a state's graphs and 8-byte planes exist.
  *   - `stream` is a hipStream_t passed as void* (NULL = the null stream).
  *     qw_load_csc*, qw_state_init, qw_state_import, qw_step and
  *     qw_step_adjoint only enqueue work; qw_measure, qw_export, qls_run,
@@ -236,7 +239,8 @@ int qw_cks_coeffs(int64_t beta, int32_t j0, double* out);
 int qw_grad(qw_state* st, const double* w, int32_t nsteps, double* dvals, double* db_re, double* db_im,
             double* loss, void* stream);
 
-/* Free a state (waits for the device).  NULL is ignored. */
+/* Free a state (waits for the device; its buffers go to the context's
+ * pool).  NULL is ignored. */
 void qw_state_free(qw_state* st);
 /* Release the caller's reference to a context.  Each state holds its own
  * reference, so a context and its states may be freed in any order; the
