@@ -1,8 +1,8 @@
 """Launch-shape autotuner of the step kernel.
 
 The step kernel strides over wavefronts (each covers 64 / min(s, 8) rows,
-min(s, 8) lanes per row), so its launch shape is free: workgroup size and
-number of workgroups.  `tune` times candidate shapes on a scratch state
+min(s, 8) lanes per row; 16 lanes for s >= 16 in small contexts), so its
+launch shape is free: workgroup size and number of workgroups.  `tune` times candidate shapes on a scratch state
 of the given workload (HIP events on the library's stream), keeps the fastest,
 and remembers it under (device name, padded dimensions, largest s, instance
 count, branch-count bucket), in memory and optionally in a JSON file.
@@ -27,11 +27,21 @@ def _key(walk, branches: int) -> str:
     return f"{name}|N={walk.N_total}|s={smax}|inst={walk.ninst}|m2^{bucket}|{kind}"
 
 
+def _waves(walk) -> int:
+    """Wavefronts of one step-kernel pass, by the library's lane mapping:
+    min(s, 8) lanes per row, or 16 for s >= 16 when that keeps the context
+    at 2048 wavefronts or fewer."""
+    def count(lanes_of):
+        return sum(-(-d["N"] // (64 // lanes_of(d["s"]))) for d in walk.info)
+
+    waves8 = count(lambda s: min(s, 8))
+    if 2 * waves8 <= 2048:
+        return count(lambda s: 16 if s >= 16 else min(s, 8))
+    return waves8
+
+
 def candidates(walk):
-    waves = 0
-    for d in walk.info:
-        rows_per_wave = 64 // min(d["s"], 8)
-        waves += -(-d["N"] // rows_per_wave)
+    waves = _waves(walk)
     lanes = 64 * waves
     out = []
     for wg in (64, 128, 256):

@@ -149,7 +149,7 @@ struct qw_ctx {
     m.suni = suni;
     m.full = full;
     m.angles = word > 0 ? 1 : 0;
-    m.pad_ = 0;
+    m.wide = wide;
     m.inst0 = inst0;
     return m;
   }
@@ -157,6 +157,7 @@ struct qw_ctx {
   int32_t slmax = 1;
   int32_t suni = 0;  // s shared by every instance, else 0
   int32_t full = 0;  // every instance has at least one step-kernel wavefront of rows
+  int32_t wide = 0;  // 16 lanes per row for instances with s >= 16 (Matrix::wide)
 };
 
 namespace {
@@ -700,12 +701,22 @@ int load_impl(qw_ctx** out, int32_t ninst, const int32_t* n, const int64_t* colp
   ctx->ntotal = ntot;
   ctx->nnz_total = nnz_base;
   // Step-kernel wavefronts: min(s, 8) lanes share a row and hold s / min(s, 8)
-  // slots each, so a wavefront covers 64 / min(s, 8) rows.
+  // slots each, so a wavefront covers 64 / min(s, 8) rows.  A context with
+  // at most kWideWaves / 2 wavefronts that way gives instances with s >= 16
+  // 16 lanes per row instead (at most twice the wavefronts, half the slots
+  // per lane): the shapes of 1024 to 8192 rows with s = 16 or 32 step 7-25 %
+  // faster so, while 16384 rows with s = 64 (2048 wavefronts) step slower.
+  int64_t waves8 = 0;
+  for (int32_t i = 0; i < ninst; ++i) {
+    const int rpw_log = 6 - std::min(ctx->inst[i].hbits, 3);
+    waves8 += (int64_t(ctx->inst[i].N) + (int64_t(1) << rpw_log) - 1) >> rpw_log;
+  }
+  ctx->wide = 2 * waves8 <= qw::kWideWaves ? 1 : 0;
   std::vector<qw::Inst> dinst(ninst);
   int64_t waves = 0;
   for (int32_t i = 0; i < ninst; ++i) {
     const HostInst& hi = ctx->inst[i];
-    const int lpr_log = std::min(hi.hbits, 3);
+    const int lpr_log = std::min(hi.hbits, ctx->wide ? 4 : 3);
     const int rpw_log = 6 - lpr_log;
     dinst[i].item_base = hi.item_base;
     dinst[i].jbase = hi.jbase;

@@ -14,6 +14,10 @@ constexpr int kMaxS = 64;       // largest QRAM row length handled (one wave per
 constexpr int kMaxGrid = 65536;  // largest step-kernel grid
 constexpr int kMaxBlock = 256;  // largest step-kernel workgroup
 constexpr int kMaxWaves = kMaxGrid * (kMaxBlock / kWave);  // per-wavefront counters
+// Lanes per row of the step kernels: min(s, 8), or 16 for s >= 16 when the
+// context then has at most kWideWaves wavefronts (Matrix::wide): more,
+// shorter lanes for a launch that would not fill the chip.
+constexpr int kWideWaves = 2048;
 constexpr double kTau = 1e-13;  // pruning threshold applied after every step
 
 // Per-instance facts, resident on the device.  The slots of instance i are
@@ -96,7 +100,7 @@ struct Matrix {
   int32_t suni;              // s of every instance when they all share it, else 0
   int32_t full;              // 1 when every instance has at least one wavefront of rows
   int32_t angles;            // 1: fixed-point data; val holds each slot's rotation angle (below)
-  int32_t pad_;
+  int32_t wide;              // 1: instances with s >= 16 use 16 lanes per row (kWideWaves)
   Inst inst0;                // copy of inst[0] (a single instance needs no table read)
 };
 

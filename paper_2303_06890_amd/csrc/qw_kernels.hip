@@ -167,9 +167,10 @@ __device__ __forceinline__ double2 xor_add(double2 v, int off) {
   return make_double2(v.x + __shfl_xor(v.x, off), v.y + __shfl_xor(v.y, off));
 }
 // Sum over the lanes that hold one row in the step kernels: lanes
-// jj + h * 2^rpw_log, h < 2^(6 - rpw_log), rpw_log >= 3.  Every lane of a
+// jj + h * 2^rpw_log, h < 2^(6 - rpw_log), rpw_log >= 2.  Every lane of a
 // row ends with the bitwise-identical sum (each stage adds a commuted pair).
 __device__ __forceinline__ double2 row_sum(double2 v, int rpw_log) {
+  if (rpw_log <= 2) v = xor_add(v, 4);
   if (rpw_log <= 3) v = xor_add_8(v);
   if (rpw_log <= 4) v = xor_add(v, 16);
   if (rpw_log <= 5) v = xor_add(v, 32);
@@ -295,10 +296,10 @@ __device__ __forceinline__ Row row_item(const Matrix& m, int64_t r) {
 }
 
 // Lane mapping of the step kernels for s = S: min(S, 8) lanes share a row,
-// each holding S / min(S, 8) slots.
-template <int S>
+// each holding S / min(S, 8) slots; W (Matrix::wide): 16 lanes for S >= 16.
+template <int S, int W = 0>
 struct Shape {
-  static constexpr int lpr_log = S >= 8 ? 3 : (S == 4 ? 2 : (S == 2 ? 1 : 0));
+  static constexpr int lpr_log = W && S >= 16 ? 4 : S >= 8 ? 3 : (S == 4 ? 2 : (S == 2 ? 1 : 0));
   static constexpr int rpw_log = 6 - lpr_log;
   static constexpr int sl = S >> lpr_log;
 };
@@ -313,12 +314,12 @@ struct Lanes {
   int j, h, rpw_log;
   bool live;
 };
-template <int S, bool FULL = false>
+template <int S, bool FULL = false, int W = 0>
 __device__ __forceinline__ Lanes lanes_of(const Matrix& m, int64_t w, int lane) {
   Lanes x;
   x.inst = m.ninst == 1 ? 0 : uload(m.wave_inst + w);
   x.I = inst_uniform(m, x.inst);
-  x.rpw_log = S ? Shape<S>::rpw_log : 6 - x.I.lpr_log;
+  x.rpw_log = S ? Shape<S, W>::rpw_log : 6 - x.I.lpr_log;
   x.h = lane >> x.rpw_log;
   const int64_t j = ((w - x.I.wave_base) << x.rpw_log) + (lane & ((1 << x.rpw_log) - 1));
   x.live = FULL || j < x.I.N;  // FULL: every N is a multiple of 2^rpw_log
@@ -423,10 +424,10 @@ __device__ __forceinline__ StepSlot step_rec(const Matrix& m, int64_t h) {
 // The data loads do not depend on each other or on the instance record
 // beyond its base, so they are issued together.  FAST: walk step (not the
 // swap) and every row of every wavefront exists.
-template <bool ACC, int SLM, int S, bool FAST, int ENC>
+template <bool ACC, int SLM, int S, bool FAST, int ENC, int W = 0>
 __device__ __forceinline__ unsigned step_wave(const StepArgs& a, int64_t w, int lane, double coef) {
-  const Lanes x = lanes_of<S, FAST>(a.m, w, lane);
-  const int sl = S ? Shape<S>::sl : (SLM == 1 ? 1 : x.I.sl);
+  const Lanes x = lanes_of<S, FAST, W>(a.m, w, lane);
+  const int sl = S ? Shape<S, W>::sl : (SLM == 1 ? 1 : x.I.sl);
   const int64_t base = x.I.item_base;
   int64_t h[SLM];
   StepSlot rc[SLM];
@@ -484,7 +485,7 @@ __device__ __forceinline__ unsigned step_wave(const StepArgs& a, int64_t w, int 
 // SLM: slots per lane held in registers; S: s of every instance, or 0 (read
 // per instance, slots per lane <= SLM).  FAST: one pass (the grid covers
 // every wavefront and the list), walk step only, every row exists.
-template <bool ACC, int SLM, int S, bool FAST, int ENC>
+template <bool ACC, int SLM, int S, bool FAST, int ENC, int W = 0>
 __device__ __forceinline__ void step_body(const StepArgs& a) {
   const int lane = threadIdx.x & (kWave - 1);
   const int64_t wpb = a.wpb;  // a kernel argument: reading the workgroup size costs a vector load
@@ -497,7 +498,7 @@ __device__ __forceinline__ void step_body(const StepArgs& a) {
   if (FAST) {
     const int64_t w = uniform(int(wid));
     if (w < a.m.waves)
-      cnt = step_wave<ACC, SLM, S, true, ENC>(a, w, lane, coef);
+      cnt = step_wave<ACC, SLM, S, true, ENC, W>(a, w, lane, coef);
     else
       cnt = list_entry(a.L, (w - a.m.waves) * kWave + lane, a.m.nbits, true);
   } else {
@@ -531,6 +532,14 @@ __device__ __forceinline__ void step_body(const StepArgs& a) {
   }                                                                                                 \
   extern "C" __global__ void __launch_bounds__(256) NAME##_acc(qw::StepArgs a) {                   \
     qw::step_body<true, SLM, S, FAST, ENC>(a);                                                      \
+  }
+// The one-pass compile-time kernels with 16 lanes per row (Matrix::wide).
+#define QW_STEP_KERNEL_W(NAME, SLM, S, ENC)                                                        \
+  extern "C" __global__ void __launch_bounds__(256) NAME(qw::StepArgs a) {                         \
+    qw::step_body<false, SLM, S, true, ENC, 1>(a);                                                  \
+  }                                                                                                 \
+  extern "C" __global__ void __launch_bounds__(256) NAME##_acc(qw::StepArgs a) {                   \
+    qw::step_body<true, SLM, S, true, ENC, 1>(a);                                                   \
   }
 QW_STEP_KERNEL(qwk_step_s1, 1, 0, false, qw::kEncReal)
 QW_STEP_KERNEL(qwk_step_s2, 2, 0, false, qw::kEncReal)
@@ -570,7 +579,14 @@ QW_STEP_KERNEL(qwk_step_k8, 1, 8, true, qw::kEncComplex)
 QW_STEP_KERNEL(qwk_step_k16, 2, 16, true, qw::kEncComplex)
 QW_STEP_KERNEL(qwk_step_k32, 4, 32, true, qw::kEncComplex)
 QW_STEP_KERNEL(qwk_step_k64, 8, 64, true, qw::kEncComplex)
+QW_STEP_KERNEL_W(qwk_step_f16w, 1, 16, qw::kEncReal)
+QW_STEP_KERNEL_W(qwk_step_f32w, 2, 32, qw::kEncReal)
+QW_STEP_KERNEL_W(qwk_step_f64w, 4, 64, qw::kEncReal)
+QW_STEP_KERNEL_W(qwk_step_k16w, 1, 16, qw::kEncComplex)
+QW_STEP_KERNEL_W(qwk_step_k32w, 2, 32, qw::kEncComplex)
+QW_STEP_KERNEL_W(qwk_step_k64w, 4, 64, qw::kEncComplex)
 #undef QW_STEP_KERNEL
+#undef QW_STEP_KERNEL_W
 
 namespace qw {
 
@@ -594,6 +610,7 @@ namespace qw {
 // walk step only, and an empty list (T~ starts).
 
 __device__ __forceinline__ double row_sum_r(double v, int rpw_log) {
+  if (rpw_log <= 2) v += __shfl_xor(v, 4);
   if (rpw_log <= 3) v += dpp<0x128>(v);
   if (rpw_log <= 4) v += __shfl_xor(v, 16);
   if (rpw_log <= 5) v += __shfl_xor(v, 32);
@@ -609,10 +626,10 @@ __device__ __forceinline__ double prune_r(double v, double tau, unsigned& cnt) {
 
 // S: s of every instance, or 0 (read per instance, slots per lane <= SLM;
 // slots of value 0 are skipped as in step_wave when StepArgs::zskip is set).
-template <bool ACC, int SLM, int S, int ENC>
+template <bool ACC, int SLM, int S, int ENC, int W = 0>
 __device__ __forceinline__ unsigned step_wave_real(const StepArgs& a, int64_t w, int lane, double coef) {
-  const Lanes x = lanes_of<S, true>(a.m, w, lane);
-  const int sl = S ? Shape<S>::sl : (SLM == 1 ? 1 : x.I.sl);
+  const Lanes x = lanes_of<S, true, W>(a.m, w, lane);
+  const int sl = S ? Shape<S, W>::sl : (SLM == 1 ? 1 : x.I.sl);
   const int64_t base = x.I.item_base;
   const double* R0 = reinterpret_cast<const double*>(a.in.R0);
   const double* R1 = reinterpret_cast<const double*>(a.in.R1);
@@ -682,7 +699,7 @@ __device__ __forceinline__ unsigned step_wave_real(const StepArgs& a, int64_t w,
   return cnt;
 }
 
-template <bool ACC, int SLM, int S, int ENC>
+template <bool ACC, int SLM, int S, int ENC, int W = 0>
 __device__ __forceinline__ void step_body_real(const StepArgs& a) {
   const int lane = threadIdx.x & (kWave - 1);
   const int64_t wpb = a.wpb;
@@ -692,11 +709,11 @@ __device__ __forceinline__ void step_body_real(const StepArgs& a) {
   const double coef = ACC ? *a.coef : 0.0;
   const int64_t cidx = wave_counter(wpb);
   if (a.acc == nullptr) {  // the solver's private walk keeps no counts
-    (void)step_wave_real<ACC, SLM, S, ENC>(a, w, lane, coef);
+    (void)step_wave_real<ACC, SLM, S, ENC, W>(a, w, lane, coef);
     return;
   }
   const unsigned long long prev = a.acc[cidx];
-  const unsigned long long v = wave_sum(step_wave_real<ACC, SLM, S, ENC>(a, w, lane, coef));
+  const unsigned long long v = wave_sum(step_wave_real<ACC, SLM, S, ENC, W>(a, w, lane, coef));
   if (lane == 0) a.acc[cidx] = prev + v;
 }
 
@@ -729,6 +746,13 @@ extern "C" __global__ void __launch_bounds__(256) qwk_to_complex(const double* _
   extern "C" __global__ void __launch_bounds__(256) NAME##_acc(qw::StepArgs a) {                   \
     qw::step_body_real<true, SLM, S, ENC>(a);                                                       \
   }
+#define QW_REAL_KERNEL_W(NAME, SLM, S, ENC)                                                          \
+  extern "C" __global__ void __launch_bounds__(256) NAME(qw::StepArgs a) {                         \
+    qw::step_body_real<false, SLM, S, ENC, 1>(a);                                                   \
+  }                                                                                                 \
+  extern "C" __global__ void __launch_bounds__(256) NAME##_acc(qw::StepArgs a) {                   \
+    qw::step_body_real<true, SLM, S, ENC, 1>(a);                                                    \
+  }
 QW_REAL_KERNEL(qwk_step_r1, 1, 1, qw::kEncReal)
 QW_REAL_KERNEL(qwk_step_r2, 1, 2, qw::kEncReal)
 QW_REAL_KERNEL(qwk_step_r4, 1, 4, qw::kEncReal)
@@ -751,7 +775,14 @@ QW_REAL_KERNEL(qwk_step_tg1, 1, 0, qw::kEncAngle)
 QW_REAL_KERNEL(qwk_step_tg2, 2, 0, qw::kEncAngle)
 QW_REAL_KERNEL(qwk_step_tg4, 4, 0, qw::kEncAngle)
 QW_REAL_KERNEL(qwk_step_tg8, 8, 0, qw::kEncAngle)
+QW_REAL_KERNEL_W(qwk_step_r16w, 1, 16, qw::kEncReal)
+QW_REAL_KERNEL_W(qwk_step_r32w, 2, 32, qw::kEncReal)
+QW_REAL_KERNEL_W(qwk_step_r64w, 4, 64, qw::kEncReal)
+QW_REAL_KERNEL_W(qwk_step_t16w, 1, 16, qw::kEncAngle)
+QW_REAL_KERNEL_W(qwk_step_t32w, 2, 32, qw::kEncAngle)
+QW_REAL_KERNEL_W(qwk_step_t64w, 4, 64, qw::kEncAngle)
 #undef QW_REAL_KERNEL
+#undef QW_REAL_KERNEL_W
 
 
 namespace qw {

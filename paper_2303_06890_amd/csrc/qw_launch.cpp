@@ -67,7 +67,9 @@ enum Fn {
   F_STEP_Y4,
   F_STEP_Y8,
   F_STEP_K1,  // complex values, s = 1 ... 64 for every instance: qwk_step_k{1..64}
-  F_STEP_COUNT_ = F_STEP_K1 + 7,  // _acc twins follow at + F_STEP_COUNT_
+  F_STEP_FW16 = F_STEP_K1 + 7,  // 16 lanes per row (Matrix::wide): qwk_step_f{16,32,64}w,
+  F_STEP_KW16 = F_STEP_FW16 + 3,  // then qwk_step_k{16,32,64}w
+  F_STEP_COUNT_ = F_STEP_KW16 + 3,  // _acc twins follow at + F_STEP_COUNT_
   F_ADJOINT_S1 = 2 * F_STEP_COUNT_,
   F_ADJOINT_S2,
   F_ADJOINT_S4,
@@ -85,7 +87,9 @@ enum Fn {
   F_STEP_T1 = F_STEP_R1 + 7,    // qwk_step_rg{1,2,4,8}, qwk_step_tg{1,2,4,8}; their _acc
   F_STEP_RG1 = F_STEP_T1 + 7,   // twins follow at + F_REAL_COUNT_
   F_STEP_TG1 = F_STEP_RG1 + 4,
-  F_REAL_COUNT_ = F_STEP_TG1 + 4 - F_STEP_R1,
+  F_STEP_RW16 = F_STEP_TG1 + 4,  // 16 lanes per row: qwk_step_r{16,32,64}w, qwk_step_t{16,32,64}w
+  F_STEP_TW16 = F_STEP_RW16 + 3,
+  F_REAL_COUNT_ = F_STEP_TW16 + 3 - F_STEP_R1,
   F_TO_REAL = F_STEP_R1 + 2 * F_REAL_COUNT_,
   F_TO_COMPLEX,
   F_COEF_WINDOW,
@@ -101,7 +105,8 @@ const char* const kNames[] = {
     "qwk_step_x2",      "qwk_step_x4",      "qwk_step_x8",      "qwk_step_h1",      "qwk_step_h2",
     "qwk_step_h4",      "qwk_step_h8",      "qwk_step_y1",      "qwk_step_y2",      "qwk_step_y4",
     "qwk_step_y8",      "qwk_step_k1",      "qwk_step_k2",      "qwk_step_k4",      "qwk_step_k8",
-    "qwk_step_k16",     "qwk_step_k32",     "qwk_step_k64",
+    "qwk_step_k16",     "qwk_step_k32",     "qwk_step_k64",     "qwk_step_f16w",    "qwk_step_f32w",
+    "qwk_step_f64w",    "qwk_step_k16w",    "qwk_step_k32w",    "qwk_step_k64w",
     "qwk_step_s1_acc",  "qwk_step_s2_acc",  "qwk_step_s4_acc",  "qwk_step_s8_acc",  "qwk_step_g1_acc",
     "qwk_step_g2_acc",  "qwk_step_g4_acc",  "qwk_step_g8_acc",  "qwk_step_f1_acc",  "qwk_step_f2_acc",
     "qwk_step_f4_acc",  "qwk_step_f8_acc",  "qwk_step_f16_acc", "qwk_step_f32_acc", "qwk_step_f64_acc",
@@ -109,7 +114,8 @@ const char* const kNames[] = {
     "qwk_step_x2_acc",  "qwk_step_x4_acc",  "qwk_step_x8_acc",  "qwk_step_h1_acc",  "qwk_step_h2_acc",
     "qwk_step_h4_acc",  "qwk_step_h8_acc",  "qwk_step_y1_acc",  "qwk_step_y2_acc",  "qwk_step_y4_acc",
     "qwk_step_y8_acc",  "qwk_step_k1_acc",  "qwk_step_k2_acc",  "qwk_step_k4_acc",  "qwk_step_k8_acc",
-    "qwk_step_k16_acc", "qwk_step_k32_acc", "qwk_step_k64_acc",
+    "qwk_step_k16_acc", "qwk_step_k32_acc", "qwk_step_k64_acc", "qwk_step_f16w_acc", "qwk_step_f32w_acc",
+    "qwk_step_f64w_acc", "qwk_step_k16w_acc", "qwk_step_k32w_acc", "qwk_step_k64w_acc",
     "qwk_adjoint_s1",   "qwk_adjoint_s2",   "qwk_adjoint_s4",   "qwk_adjoint_s8",   "qwk_qbs_table",
     "qwk_init",         "qwk_fill",         "qwk_measure",      "qwk_measure_rows", "qwk_export",
     "qwk_import",       "qwk_weight",       "qwk_grad_init",    "qwk_step_r1",      "qwk_step_r2",
@@ -117,11 +123,14 @@ const char* const kNames[] = {
     "qwk_step_t1",      "qwk_step_t2",      "qwk_step_t4",      "qwk_step_t8",      "qwk_step_t16",
     "qwk_step_t32",     "qwk_step_t64",     "qwk_step_rg1",     "qwk_step_rg2",     "qwk_step_rg4",
     "qwk_step_rg8",     "qwk_step_tg1",     "qwk_step_tg2",     "qwk_step_tg4",     "qwk_step_tg8",
+    "qwk_step_r16w",    "qwk_step_r32w",    "qwk_step_r64w",    "qwk_step_t16w",    "qwk_step_t32w",
+    "qwk_step_t64w",
     "qwk_step_r1_acc",  "qwk_step_r2_acc",  "qwk_step_r4_acc",  "qwk_step_r8_acc",  "qwk_step_r16_acc",
     "qwk_step_r32_acc", "qwk_step_r64_acc", "qwk_step_t1_acc",  "qwk_step_t2_acc",  "qwk_step_t4_acc",
     "qwk_step_t8_acc",  "qwk_step_t16_acc", "qwk_step_t32_acc", "qwk_step_t64_acc", "qwk_step_rg1_acc",
     "qwk_step_rg2_acc", "qwk_step_rg4_acc", "qwk_step_rg8_acc", "qwk_step_tg1_acc", "qwk_step_tg2_acc",
-    "qwk_step_tg4_acc", "qwk_step_tg8_acc", "qwk_to_real",      "qwk_to_complex",
+    "qwk_step_tg4_acc", "qwk_step_tg8_acc", "qwk_step_r16w_acc", "qwk_step_r32w_acc", "qwk_step_r64w_acc",
+    "qwk_step_t16w_acc", "qwk_step_t32w_acc", "qwk_step_t64w_acc", "qwk_to_real",      "qwk_to_complex",
     "qwk_coef_window",  "qwk_sum_counts"};
 static_assert(sizeof(kNames) / sizeof(kNames[0]) == F_COUNT, "one kernel name per Fn");
 
@@ -139,20 +148,22 @@ Fn step_kernel(const StepArgs& a, int grid, int block) {
   const bool acc = a.yacc != nullptr;
   const int64_t work = m.waves + (int64_t(a.L.cnt) + kWave - 1) / kWave;
   const bool one_pass = m.full && a.mode == kStep && int64_t(grid) * (block / kWave) >= work;
+  const bool wide = m.wide && m.suni >= 16;  // compile-time kernels with 16 lanes per row
   if (a.real) {  // the caller checked the conditions (launch_step re-checks them)
-    const int f = m.suni > 0 ? (m.angles ? F_STEP_T1 : F_STEP_R1) + log2_of(m.suni)
-                             : (m.angles ? F_STEP_TG1 : F_STEP_RG1) + width_index(m.slmax);
+    const int f = m.suni > 0 && wide ? (m.angles ? F_STEP_TW16 : F_STEP_RW16) + log2_of(m.suni) - 4
+                  : m.suni > 0       ? (m.angles ? F_STEP_T1 : F_STEP_R1) + log2_of(m.suni)
+                                     : (m.angles ? F_STEP_TG1 : F_STEP_RG1) + width_index(m.slmax);
     return Fn(f + (acc ? int(F_REAL_COUNT_) : 0));
   }
   int f = F_STEP_S1 + width_index(m.slmax);
   if (m.vim) {
     f = (one_pass ? F_STEP_H1 : F_STEP_C1) + width_index(m.slmax);
-    if (one_pass && m.suni > 0) f = F_STEP_K1 + log2_of(m.suni);
+    if (one_pass && m.suni > 0) f = wide ? F_STEP_KW16 + log2_of(m.suni) - 4 : F_STEP_K1 + log2_of(m.suni);
   } else if (m.angles) {
     f = (one_pass ? F_STEP_Y1 : F_STEP_X1) + width_index(m.slmax);
   } else if (one_pass) {
     f = F_STEP_G1 + width_index(m.slmax);
-    if (m.suni > 0) f = F_STEP_F1 + log2_of(m.suni);
+    if (m.suni > 0) f = wide ? F_STEP_FW16 + log2_of(m.suni) - 4 : F_STEP_F1 + log2_of(m.suni);
   }
   return Fn(f + (acc ? int(F_STEP_COUNT_) : 0));
 }

@@ -1,0 +1,81 @@
+"""Sixteen lanes per row: a context that would have at most 1024 step-kernel
+wavefronts with eight lanes per row gives its instances with s >= 16 sixteen
+(two, four slots per lane for s = 32, 64).  Parity with the oracle for every
+kernel family that then runs with that mapping: one double per cell (FP64
+and fixed-point words), the complex planes (a complex b), complex Hermitian
+values, a grid-stride launch shape and W^dagger."""
+import numpy as np
+import pytest
+
+import workloads as W
+from tests.parity import compare_states
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def Q():
+    import torch
+
+    assert torch.cuda.is_available()
+    import paper_2303_06890_amd as Q
+
+    return Q
+
+
+def _run(Q, oracle_mod, csc, b, word=0, shape=None, steps=(1, 2, 17, 40), adjoint=0):
+    walk = Q.Walk(csc, word=word)
+    assert walk.info[0]["s"] >= 16
+    st = walk.state(b)
+    if shape:
+        st.set_launch(*shape)
+    ost = oracle_mod.OracleState(oracle_mod.OracleMatrix(csc, word=word)).set_b(b).T()
+    done = 0
+    for t in steps:
+        st.step(t - done)
+        ost.step(t - done)
+        done = t
+        gk, ga = st.export()
+        ok, oa = ost.export()
+        assert ost.ambiguous() == 0
+        compare_states(gk, ga, ok, oa, where=f"s={walk.info[0]['s']} step {t}")
+    if adjoint:
+        st.step_adjoint(adjoint)
+        ost.step_adjoint(adjoint)
+        gk, ga = st.export()
+        ok, oa = ost.export()
+        compare_states(gk, ga, ok, oa, where=f"s={walk.info[0]['s']} W^dagger {adjoint}")
+    return st
+
+
+@pytest.mark.parametrize("c", [11, 21, 40])
+def test_real_planes(Q, oracle_mod, c):
+    csc, b = W.offset_matrix(64, c, seed=100 + c), W.gaussian_b(64, seed=200 + c)
+    st = _run(Q, oracle_mod, csc, b, adjoint=5)
+    assert st.stats()["real_amplitudes"]
+
+
+@pytest.mark.parametrize("c", [11, 21, 40])
+def test_complex_b(Q, oracle_mod, c):
+    csc = W.offset_matrix(64, c, seed=110 + c)
+    b = W.gaussian_b(64, seed=210 + c) * np.exp(0.3j * np.arange(64))
+    _run(Q, oracle_mod, csc, b)
+
+
+@pytest.mark.parametrize("c", [11, 21, 40])
+def test_hermitian(Q, oracle_mod, c):
+    csc = W.hermitian_offset_matrix(64, c, seed=120 + c)
+    b = W.gaussian_b(64, seed=220 + c)
+    _run(Q, oracle_mod, csc, b)
+
+
+@pytest.mark.parametrize("bw", [5, 12, 25])
+def test_fixed_point_words(Q, oracle_mod, bw):
+    csc = W.fixed_point_band(96, bw, 12, seed=130 + bw, negative=0.4)
+    _run(Q, oracle_mod, csc, W.gaussian_b(96, seed=230 + bw), word=12)
+
+
+@pytest.mark.parametrize("c", [11, 40])
+def test_grid_stride_shape(Q, oracle_mod, c):
+    csc, b = W.offset_matrix(64, c, seed=140 + c), W.gaussian_b(64, seed=240 + c)
+    _run(Q, oracle_mod, csc, b, shape=(64, 1))
