@@ -984,12 +984,14 @@ int measure_partials(qw_state* st, int kind, double* result, hipStream_t stream)
 // therefore hold the true sum plus (Q1 branches after launch K) minus (Q1
 // branches before launch 1).
 int total_written(qw_state* st, hipStream_t stream, int64_t* out) {
-  // summed on the device: one 8-byte copy instead of the whole counter array
+  // partial sums on the device: 2 KB to copy instead of the whole counter array
   unsigned long long* dsum = reinterpret_cast<unsigned long long*>(st->mbuf);
-  unsigned long long t = 0;
+  unsigned long long part[qw::kSumBlocks];
   QW_HIP(qw::launch_sum_counts(st->acc, qw::kMaxWaves, dsum, stream));
-  QW_HIP(hipMemcpyAsync(&t, dsum, sizeof(t), hipMemcpyDeviceToHost, stream));
+  QW_HIP(hipMemcpyAsync(part, dsum, sizeof(part), hipMemcpyDeviceToHost, stream));
   QW_HIP(hipStreamSynchronize(stream));
+  unsigned long long t = 0;
+  for (unsigned long long v : part) t += v;
   double q1 = 0.0;
   int rc = measure_partials(st, 4, &q1, stream);
   if (rc) return rc;

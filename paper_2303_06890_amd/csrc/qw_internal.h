@@ -163,7 +163,8 @@ hipError_t launch_adjoint(const AdjArgs& a, int grid, int block, hipStream_t str
 hipError_t launch_qbs_table(const Matrix& m, SlotRec* rec, uint32_t* slink, double* sval, hipStream_t stream);
 hipError_t launch_init(const Matrix& m, const double2* b, Slots out, double tau, hipStream_t stream);
 hipError_t launch_fill(void* p, int64_t bytes, hipStream_t stream);
-// *out = a[0] + ... + a[n-1] (the per-wavefront counters).
+// out[0 .. kSumBlocks) = partial sums of a[0 .. n) (the per-wavefront counters).
+constexpr int kSumBlocks = 256;
 hipError_t launch_sum_counts(const unsigned long long* a, int64_t n, unsigned long long* out, hipStream_t stream);
 // window[i] = table[*base + i] for i < count, then *base += count; with
 // set >= 0 only *base = set.

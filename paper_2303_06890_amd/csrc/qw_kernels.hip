@@ -944,21 +944,18 @@ extern "C" __global__ void qwk_fill(uint4* p, int64_t n16) {
     p[i] = make_uint4(0u, 0u, 0u, 0u);
 }
 
-// Sum of the per-wavefront counters (one workgroup of 1024 threads): *out =
-// a[0] + ... + a[n-1].
-extern "C" __global__ void __launch_bounds__(1024) qwk_sum_counts(const unsigned long long* __restrict__ a, int64_t n,
-                                                                   unsigned long long* out) {
-  __shared__ unsigned long long part[1024 / 64];
+// Partial sums of the per-wavefront counters: out[b] = the sum of
+// a[i] over the grid-stride share of workgroup b (256 threads each).
+extern "C" __global__ void __launch_bounds__(256) qwk_sum_counts(const unsigned long long* __restrict__ a, int64_t n,
+                                                                  unsigned long long* out) {
+  __shared__ unsigned long long part[256 / 64];
   unsigned long long v = 0;
-  for (int64_t i = threadIdx.x; i < n; i += blockDim.x) v += a[i];
+  const int64_t stride = int64_t(gridDim.x) * blockDim.x;
+  for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += stride) v += a[i];
   for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
   if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = v;
   __syncthreads();
-  if (threadIdx.x == 0) {
-    unsigned long long t = 0;
-    for (int i = 0; i < int(blockDim.x >> 6); ++i) t += part[i];
-    *out = t;
-  }
+  if (threadIdx.x == 0) out[blockIdx.x] = part[0] + part[1] + part[2] + part[3];
 }
 
 // The solver's coefficient window for a graph of `count` steps (one

@@ -265,7 +265,7 @@ hipError_t launch_fill(void* ptr, int64_t bytes, hipStream_t stream) {
 
 hipError_t launch_sum_counts(const unsigned long long* a, int64_t n, unsigned long long* out, hipStream_t stream) {
   void* p[] = {&a, &n, &out};
-  return launch(F_SUM_COUNTS, 1, 1024, stream, p);
+  return launch(F_SUM_COUNTS, kSumBlocks, 256, stream, p);
 }
 
 hipError_t launch_coef_window(const double* table, int64_t* base, double* window, int32_t count, int64_t set,
