@@ -388,7 +388,7 @@ def main():
                          "with --only batched; prints nothing else")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py runs on exactly one GPU: this build has no multi-GPU path "
+        print("bench.py runs on exactly one GPU: the library has no multi-GPU path "
               "(a single walk instance would shard by row owner with one all-to-all per step)",
               file=sys.stderr)
         sys.exit(2)

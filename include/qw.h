@@ -55,7 +55,7 @@ typedef enum {
   QW_ENOMEM = -2,    /* allocation failed */
   QW_ECAPACITY = -3, /* general branch list capacity exceeded */
   QW_EDEVICE = -4,   /* HIP runtime error */
-  QW_ENOTSUP = -5    /* valid request outside what this build supports */
+  QW_ENOTSUP = -5    /* valid request outside what the library supports */
 } qw_status;
 
 typedef struct qw_ctx qw_ctx;     /* preprocessed matrices resident on the GPU */
