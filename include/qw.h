@@ -99,7 +99,10 @@ typedef struct {
                            real matrix whose negative values pair up, as in a
                            symmetric one, and a real b, from T~ |b~>): its walk
                            steps then run on one double per cell whenever the
-                           one-pass conditions of the step kernels hold */
+                           one-pass conditions of the step kernels hold; with
+                           out_len >= 7 also [6] = the lanes of a step-kernel
+                           wavefront that share a row of s >= 16 slots (8, or
+                           16 in a context of at most 1024 wavefronts with 8) */
 
 /* Load one matrix (Sec. V.B, preprocessing list; Sec. II.C, Fig. 1):
  *   scale: > 0 multiplies every value by `scale`; 0 selects 1/max(1, max|a|).

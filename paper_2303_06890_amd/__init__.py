@@ -253,9 +253,9 @@ class State:
         return out[0::2] + 1j * out[1::2]
 
     def stats(self) -> dict:
-        o = self._measure(_lib.QW_STATS, np.zeros(6, np.int64))
+        o = self._measure(_lib.QW_STATS, np.zeros(7, np.int64))
         return dict(launches=int(o[0]), branches=int(o[1]), list_capacity=int(o[2]), list_count=int(o[3]),
-                    total_written=int(o[4]), real_amplitudes=bool(o[5]))
+                    total_written=int(o[4]), real_amplitudes=bool(o[5]), lanes_per_row_s16=int(o[6]))
 
     def export(self):
         """(keys uint64 sorted, amplitudes complex128)."""

@@ -1243,6 +1243,7 @@ int qw_measure(qw_state* st, int32_t kind, void* out, int64_t out_len, void* str
       o[3] = int64_t(st->L.cnt);
       o[4] = tw;
       if (out_len >= 6) o[5] = st->real_ok && st->ctx->realsym ? 1 : 0;
+      if (out_len >= 7) o[6] = st->ctx->wide ? 16 : 8;
       return QW_OK;
     }
     default:

@@ -27,6 +27,7 @@ def _run(Q, oracle_mod, csc, b, word=0, shape=None, steps=(1, 2, 17, 40), adjoin
     walk = Q.Walk(csc, word=word)
     assert walk.info[0]["s"] >= 16
     st = walk.state(b)
+    assert st.stats()["lanes_per_row_s16"] == 16
     if shape:
         st.set_launch(*shape)
     ost = oracle_mod.OracleState(oracle_mod.OracleMatrix(csc, word=word)).set_b(b).T()
@@ -79,3 +80,14 @@ def test_fixed_point_words(Q, oracle_mod, bw):
 def test_grid_stride_shape(Q, oracle_mod, c):
     csc, b = W.offset_matrix(64, c, seed=140 + c), W.gaussian_b(64, seed=240 + c)
     _run(Q, oracle_mod, csc, b, shape=(64, 1))
+
+
+def test_large_contexts_keep_eight_lanes(Q):
+    """Shape E (16384 rows, s = 64: 2048 wavefronts with eight lanes) and a
+    batch of 256 instances keep eight lanes per row; shape D (8192 rows,
+    s = 32: 1024 wavefronts) takes sixteen."""
+    assert Q.Walk(W.table1_band("E")[0]).state(W.uniform_b(16384)).stats()["lanes_per_row_s16"] == 8
+    assert Q.Walk(W.table1_band("D")[0]).state(W.uniform_b(8192)).stats()["lanes_per_row_s16"] == 16
+    inst = W.batched_instances(count=256)
+    st = Q.Walk([a for a, _ in inst]).state([b for _, b in inst])
+    assert st.stats()["lanes_per_row_s16"] == 8
