@@ -338,6 +338,21 @@ __device__ __forceinline__ unsigned long long wave_sum(unsigned cnt) {
   }
   return v;
 }
+// The same for counts below 2^BITS: one ballot per bit and no branch (the
+// loop's early exit cost 0.09 us per launch at 16384 x 8).
+template <int BITS>
+__device__ __forceinline__ unsigned long long wave_sum_bits(unsigned cnt) {
+  unsigned long long v = 0;
+#pragma unroll
+  for (int b = 0; b < BITS; ++b) v += static_cast<unsigned long long>(__popcll(__ballot((cnt >> b) & 1u))) << b;
+  return v;
+}
+// Bits of a one-pass lane's count: at most 4 per slot (a kept Q1 output
+// twice, then R0, or Q0 and R0), SLM slots.
+template <int SLM>
+struct CountBits {
+  static constexpr int value = SLM == 1 ? 3 : SLM == 2 ? 4 : SLM == 4 ? 5 : 6;
+};
 // The running count of this wavefront in the step and adjoint kernels
 // (kMaxWaves counters).
 // Workgroups are dealt to the eight XCDs in turn, so the counters are grouped
@@ -512,7 +527,7 @@ __device__ __forceinline__ void step_body(const StepArgs& a) {
     }
   }
   if (counting) {
-    const unsigned long long v = wave_sum(cnt);
+    const unsigned long long v = FAST ? wave_sum_bits<CountBits<SLM>::value>(cnt) : wave_sum(cnt);
     if (lane == 0) a.acc[cidx] = prev + v;
   }
 }
@@ -713,7 +728,7 @@ __device__ __forceinline__ void step_body_real(const StepArgs& a) {
     return;
   }
   const unsigned long long prev = a.acc[cidx];
-  const unsigned long long v = wave_sum(step_wave_real<ACC, SLM, S, ENC, W>(a, w, lane, coef));
+  const unsigned long long v = wave_sum_bits<CountBits<SLM>::value>(step_wave_real<ACC, SLM, S, ENC, W>(a, w, lane, coef));
   if (lane == 0) a.acc[cidx] = prev + v;
 }
 
