@@ -512,6 +512,11 @@ __device__ __forceinline__ void step_body(const StepArgs& a) {
   unsigned cnt = 0;
   if (FAST) {
     const int64_t w = uniform(int(wid));
+    // the arguments in one scalar-load round trip, as in step_body_real
+    asm volatile("" ::"s"(a.m.inst0.item_base), "s"(a.m.inst0.nlog), "s"(a.m.slink), "s"(a.m.sval), "s"(a.in.R0),
+                 "s"(a.in.R1), "s"(a.out.R0), "s"(a.out.Q1), "s"(a.in.r1s), "s"(a.tau), "s"(a.m.vim));
+    asm volatile("" ::"s"(a.m.ninst), "s"(a.m.inst0.wave_base), "s"(a.m.inst0.s), "s"(a.m.inst0.N), "s"(a.in.Q0),
+                 "s"(a.out.Q0), "s"(a.m.inst0.inv_sqrt_s), "s"(a.m.inst0.jbase), "s"(a.m.inst), "s"(a.m.wave_inst));
     if (w < a.m.waves)
       cnt = step_wave<ACC, SLM, S, true, ENC, W>(a, w, lane, coef);
     else
