@@ -497,7 +497,7 @@ def main():
             "nnz_per_col": 8,
             "s": s,
             "branches": s1["branches"],
-            "graph_steps_per_replay": 16,
+            "graph_steps_per_replay": "256, then 16, then single launches",
             "launch_shape": list(shape) if shape else "default",
         },
         "roofline": {
