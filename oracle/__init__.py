@@ -32,12 +32,15 @@ def build() -> str:
 
 
 def _load():
+    """Load the oracle library; QW_ORACLE_LIB names another build of it (the
+    tests' planted-mistake copies)."""
     global _lib
     if _lib is not None:
         return _lib
-    if not os.path.exists(_LIB):
+    path = os.environ.get("QW_ORACLE_LIB") or _LIB
+    if path == _LIB and not os.path.exists(_LIB):
         build()
-    lib = ctypes.CDLL(_LIB)
+    lib = ctypes.CDLL(path)
     P = ctypes.c_void_p
     i32, i64, u64, dbl = ctypes.c_int32, ctypes.c_int64, ctypes.c_uint64, ctypes.c_double
     dp = ctypes.POINTER(ctypes.c_double)

@@ -76,10 +76,19 @@ def fixed_point_rotation(a, w, row, column):
 
 
 class DenseWalk:
-    def __init__(self, csc, scale=None, word=0):
+    """``jc_dim``: number of values of register j_c held (default N).  Every
+    state reachable from |b~> or T~|b~> has j_c < s at all times and k_c < s
+    at step boundaries (k_c holds z < N only inside T~^dagger ... T~), so
+    jc_dim = s keeps the whole walk while cutting the vector by N/s; j_c is
+    the most significant register, so the flat index still equals the packed
+    key.  S then moves only entries with k_c < jc_dim and asserts that the
+    others are zero."""
+
+    def __init__(self, csc, scale=None, word=0, jc_dim=None):
         self.N, self.n, self.s, self.scale, self.col, self.val = preprocess(csc, scale)
         N, s = self.N, self.s
-        self.shape = (N, N, 2, N, N, 2)
+        self.jc_dim = N if jc_dim is None else int(jc_dim)
+        self.shape = (self.jc_dim, N, 2, N, N, 2)
         self.size = int(np.prod(self.shape))
         c = np.indices(self.shape).reshape(6, -1)
         jc, j, b1, kc, k, b2 = c
@@ -95,7 +104,14 @@ class DenseWalk:
         kcnew = np.where(valid, k ^ pos[j, knew], k)
         self.os_perm = flat(jc, j, b1, kcnew, knew, b2)
         assert np.unique(self.os_perm).size == self.size
-        self.s_perm = flat(kc, k, b2, jc, j, b1)
+        s_ok = kc < self.jc_dim
+        self.s_full = bool(s_ok.all())
+        if self.s_full:
+            self.s_perm = flat(kc, k, b2, jc, j, b1)
+        else:
+            self.s_src = np.nonzero(s_ok)[0]
+            self.s_dst = flat(kc[s_ok], k[s_ok], b2[s_ok], jc[s_ok], j[s_ok], b1[s_ok])
+            self.s_drop = np.nonzero(~s_ok)[0]
         self.p_sign = np.where((jc == 0) & (b1 == 0) & (kc == 0) & (k == 0) & (b2 == 0), 1.0, -1.0)
         # rotation in the (l, z) frame: controlled by j, l = k register, z = k_c register
         ll = np.minimum(k, s - 1)
@@ -119,6 +135,8 @@ class DenseWalk:
                 f[idx], g[idx] = table[key]
         self.rot_valid = valid
         self.f, self.g = f, g
+        # per amplitude pair (f, g and the slot range do not depend on b2)
+        self.f2, self.g2, self.valid2 = f[0::2], g[0::2], valid[0::2]
         self.b2 = b2
         self.partner = flat(jc, j, b1, kc, k, 1 - b2)
         hs = np.array([[1.0]])
@@ -137,30 +155,46 @@ class DenseWalk:
 
     def S(self, psi):
         out = np.zeros_like(psi)
-        out[self.s_perm] = psi
+        if self.s_full:
+            out[self.s_perm] = psi
+        else:
+            if np.any(psi[self.s_drop] != 0):
+                raise AssertionError("k_c >= jc_dim at S: the restricted register range does not hold the walk")
+            out[self.s_dst] = psi[self.s_src]
         return out
 
     def P(self, psi):
         return psi * self.p_sign
 
     def H(self, psi):
-        N, s = self.N, self.s
-        v = psi.reshape(N, N, 2, N, N // s, s, 2)
-        return np.einsum("xy,abcdeyg->abcdexg", self.hmat, v).reshape(-1)
+        # H on each of the low log2(s) bits of k in turn: (v0, v1) -> (v0 + v1,
+        # v0 - v1) on the pairs that differ in that bit, then 1/sqrt(s) once
+        s = self.s
+        out = psi * (1.0 / np.sqrt(s))
+        h = 1
+        while h < s:
+            # (registers above, higher bits of k, this bit, lower bits of k, b2)
+            v = out.reshape(-1, s // (2 * h), 2, h, 2)
+            d = v[:, :, 0] - v[:, :, 1]
+            v[:, :, 0] += v[:, :, 1]
+            v[:, :, 1] = d
+            h *= 2
+        return out
 
     def R(self, psi, dagger=False):
-        v = psi
-        w = v[self.partner]
-        f, g = self.f, self.g
+        # b2 is the lowest register: amplitude pairs (b2 = 0, b2 = 1)
+        x = psi.reshape(-1, 2)
+        v0, v1 = x[:, 0], x[:, 1]
+        f, g = self.f2, self.g2
         if not dagger:
             # [[f, -g], [g, conj f]]
-            new = np.where(self.b2 == 0, f * v - g * w, g * w + np.conj(f) * v)
+            o0, o1 = f * v0 - g * v1, g * v0 + np.conj(f) * v1
         else:
             # [[conj f, g], [-g, f]]
-            new = np.where(self.b2 == 0, np.conj(f) * v + g * w, -g * w + f * v)
-        if np.any(~self.rot_valid & (np.abs(psi) > 0)):
+            o0, o1 = np.conj(f) * v0 + g * v1, -g * v0 + f * v1
+        if np.any(~self.valid2[:, None] & (x != 0)):
             raise AssertionError("amplitude outside the slot range at a rotation")
-        return np.where(self.rot_valid, new, psi)
+        return np.where(self.valid2[:, None], np.stack((o0, o1), axis=1), x).reshape(-1)
 
     def T(self, psi):
         return self.OS(self.R(self.H(psi)))
