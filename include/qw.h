@@ -11,7 +11,9 @@
  *
  * Conventions shared by every entry point
  *   - Return value: QW_OK (0) or a negative qw_status.  Functions never throw
- *     and never abort; qw_last_error() returns the text of the last error of
+ *     and never abort: every entry point catches what the host code may
+ *     throw (host memory exhaustion is reported as QW_ENOMEM, anything else
+ *     as QW_EINVAL); qw_last_error() returns the text of the last error of
  *     the calling thread.
  *   - Host arrays are borrowed for the duration of the call only.
  *   - Device memory comes from the caller's allocator (qw_allocator; NULL
@@ -149,11 +151,27 @@ int qw_load_csc_hermitian(qw_ctx** out, int32_t ninst, const int32_t* n, const i
                           const qw_allocator* alloc, void* stream);
 
 /* Per-instance facts: padded dimension N, slots per row s, register width n
- * of the key layout (common to all instances), scale applied.  Any output
- * pointer may be NULL.  Errors: QW_EINVAL for a NULL context or an instance
- * index out of range. */
+ * of the key layout (common to all instances), scale applied, and the
+ * condition number kappa of A/s once qw_kappa (or qls_run with kappa <= 0)
+ * has computed it, NaN before.  Any output pointer may be NULL.  Errors:
+ * QW_EINVAL for a NULL context or an instance index out of range. */
 int qw_ctx_info(const qw_ctx* ctx, int32_t inst, int32_t* n_padded, int32_t* s, int32_t* nbits,
-                double* scale);
+                double* scale, double* kappa);
+
+/* Condition number kappa = 1 / min |lambda(A/s)| of instance `inst`, the
+ * quantity the solver's schedule takes (Sec. V.B, preprocessing list: A is
+ * rescaled and the walk encodes A/s; Table I, note a; A is the n x n matrix
+ * given, without the padding to N).  Computed on the host once and kept with
+ * the context: for n <= 2048 (2n for complex values) exactly, by Householder
+ * reduction to tridiagonal form and bisection on Sturm counts; beyond that
+ * estimated by Lanczos on (A/s)^2 with full reorthogonalisation, accepted
+ * when the residual bound of the smallest Ritz value is below 1e-9 of it.
+ * Fixed-point data uses the matrix the rotations encode, sign(a) cos^2(theta)
+ * per entry.  Synchronous, host only (about 1 s at n = 1024).
+ * Errors: QW_EINVAL (NULL arguments, instance out of range, a singular
+ * matrix), QW_ENOTSUP (a matrix that is not symmetric or Hermitian; a
+ * Lanczos estimate that did not converge in 600 steps). */
+int qw_kappa(qw_ctx* ctx, int32_t inst, double* kappa);
 /* Number of instances of a context (0 for NULL). */
 int32_t qw_ctx_ninst(const qw_ctx* ctx);
 
@@ -188,12 +206,21 @@ int qw_step(qw_state* st, int32_t nsteps, void* stream);
 int qw_step_adjoint(qw_state* st, int32_t nsteps, void* stream);
 
 /* Measurements (kinds above).  out_len is the number of elements of `out`.
+ * QW_J_MARGINAL is the probability of each value of the column register j,
+ * the p_j of the solver's readout (Sec. V.B: the probability of measuring
+ * each column index); QW_PROJECT is <psi~_j|state> = <j~|T~^dagger|state>,
+ * the amplitude of |0, j, 0, 0, 0, 0> after T~^dagger, which Pi_0 T~^dagger
+ * of the iteration of Sec. V.B reads (psi~_j = T~|j~>, Sec. IV);
+ * QW_COUNT and QW_NORM are the number of stored branches and sum |amp|^2 of
+ * the sparse state (Sec. V.A: the state array and amplitude vector).
  * Synchronises the stream.  Errors: QW_EINVAL (unknown kind, NULL pointers,
  * out_len too small), QW_EDEVICE. */
 int qw_measure(qw_state* st, int32_t kind, void* out, int64_t out_len, void* stream);
 
-/* Copy the state to the host, sorted by key.  cap = size of the host arrays;
- * *m receives the branch count (QW_EINVAL with *m set if cap < count). */
+/* Copy the state to the host, sorted by key: the sparse representation of
+ * Sec. V.A (every stored register tuple and its amplitude), with keys in the
+ * layout above.  cap = size of the host arrays; *m receives the branch count
+ * (QW_EINVAL with *m set if cap < count).  Synchronises the stream. */
 int qw_export(qw_state* st, uint64_t* keys, double* re, double* im, int64_t cap, int64_t* m,
               void* stream);
 
@@ -214,13 +241,18 @@ int qw_sync(qw_state* st, void* stream);
  *   (j0_override >= 0 replaces j0), a_k the coefficients of Eq. "fx";
  *   omega = W T~ |b~>; for k = 0..j0: y += a_k Pi_0 T~^dagger omega; then
  *   omega = W^2 omega (k < j0).  2 j0 + 1 walk steps in total.
- * kappa: condition number of A/s (1 / smallest |eigenvalue|), > 1.
- * y_re/y_im (N values, host): the unnormalised post-selected output
- * sum_k a_k tau_k; the solution estimate is y/|y|.  p_succ = |y|^2 /
- * (sum_k |a_k|)^2.  walk_steps receives 2 j0 + 1.  Either output pointer may
- * be NULL.  Errors: QW_EINVAL (kappa <= 1, eps outside (0,1), b NULL). */
+ * b: n values (host, real).  kappa: condition number of A/s (1 / smallest
+ * |eigenvalue|), > 1; kappa <= 0 takes the library's own (qw_kappa, computed
+ * once per context).
+ * x_re/x_im (n values, host): the post-selected, normalised solution
+ * x = y / |y| with y = sum_k a_k tau_k; y_norm receives |y|, so that y itself
+ * is y_norm * x.  p_succ = |y|^2 / (sum_k |a_k|)^2 (the LCU's success
+ * probability).  walk_steps receives 2 j0 + 1.  Any output pointer may be
+ * NULL.  Synchronises the stream.
+ * Errors: QW_EINVAL (1 >= kappa > 0, eps outside (0,1), b NULL, y = 0),
+ * and qw_kappa's errors when kappa <= 0. */
 int qls_run(qw_ctx* ctx, const double* b, double kappa, double eps, int32_t j0_override,
-            double* y_re, double* y_im, double* p_succ, int64_t* walk_steps, void* stream);
+            double* x_re, double* x_im, double* y_norm, double* p_succ, int64_t* walk_steps, void* stream);
 
 /* Chebyshev coefficients a_0..a_j0 of Eq. "fx" for the given beta, computed
  * on the host into out[j0 + 1]: a_j = 4 (-1)^j sum_{i > j} C(2 beta, beta + i)

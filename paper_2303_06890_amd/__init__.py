@@ -19,7 +19,7 @@ import torch  # noqa: F401  (imported before the atexit hook below is registered
 from . import _lib
 from ._lib import QwError, check  # noqa: F401
 
-__all__ = ["Walk", "State", "QwError", "WalkObservable", "cks_coeffs", "schedule", "pack_key", "stream"]
+__all__ = ["Walk", "State", "QwError", "WalkObservable", "cks_coeffs", "pack_key", "stream"]
 
 
 # At interpreter exit, library objects still alive are freed and the kernels
@@ -152,7 +152,7 @@ class Walk:
         for i in range(self.ninst):
             N, s, nb = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
             scv = ctypes.c_double()
-            check(lib.qw_ctx_info(h, i, ctypes.byref(N), ctypes.byref(s), ctypes.byref(nb), ctypes.byref(scv)))
+            check(lib.qw_ctx_info(h, i, ctypes.byref(N), ctypes.byref(s), ctypes.byref(nb), ctypes.byref(scv), None))
             self.info.append(dict(N=N.value, s=s.value, nbits=nb.value, scale=scv.value))
         self.nbits = self.info[0]["nbits"]
         self.N_total = sum(d["N"] for d in self.info)
@@ -187,17 +187,33 @@ class Walk:
                                          _lib.QW_INIT_RAW if raw else 0, int(capacity), _stream()))
         return State(self, h)
 
-    def qls(self, b, kappa: float, eps: float = 1e-3, j0: int | None = None):
-        """Walk-based CKS solve on instance 0: returns (y, p_succ, walk_steps)
-        with y the unnormalised post-selected output (solution ~ y/|y|)."""
+    def kappa(self, inst: int = 0) -> float:
+        """Condition number 1 / min |lambda(A/s)| of one instance (qw_kappa:
+        computed by the library once, then kept)."""
+        k = ctypes.c_double()
+        check(_lib.load().qw_kappa(self._h, int(inst), ctypes.byref(k)))
+        return k.value
+
+    def kappa_known(self, inst: int = 0) -> float:
+        """The condition number if the library has computed it, else NaN."""
+        k = ctypes.c_double()
+        check(_lib.load().qw_ctx_info(self._h, int(inst), None, None, None, None, ctypes.byref(k)))
+        return k.value
+
+    def qls(self, b, kappa: float | None = None, eps: float = 1e-3, j0: int | None = None):
+        """Walk-based CKS solve on instance 0: returns (x, p_succ, walk_steps,
+        y_norm) with x = y / |y| the post-selected, normalised solution and
+        y_norm = |y| (y = y_norm * x is the unnormalised LCU output).
+        kappa None: the library's own condition number."""
         b = np.ascontiguousarray(b, dtype=np.float64)
         n0 = self.mats[0].n
-        yr, yi = np.zeros(n0), np.zeros(n0)
-        p = ctypes.c_double()
+        xr, xi = np.zeros(n0), np.zeros(n0)
+        p, yn = ctypes.c_double(), ctypes.c_double()
         steps = ctypes.c_int64()
-        check(_lib.load().qls_run(self._h, _dp(b), float(kappa), float(eps), -1 if j0 is None else int(j0),
-                                  _dp(yr), _dp(yi), ctypes.byref(p), ctypes.byref(steps), _stream()))
-        return yr + 1j * yi, p.value, steps.value
+        check(_lib.load().qls_run(self._h, _dp(b), 0.0 if kappa is None else float(kappa), float(eps),
+                                  -1 if j0 is None else int(j0), _dp(xr), _dp(xi), ctypes.byref(yn),
+                                  ctypes.byref(p), ctypes.byref(steps), _stream()))
+        return xr + 1j * xi, p.value, steps.value, yn.value
 
 
 class State:
@@ -349,10 +365,3 @@ class _Lazy:
 
 
 WalkObservable = _Lazy()
-
-
-def schedule(kappa: float, eps: float = 1e-3):
-    """(beta, j0) of the CKS series: beta = ceil(kappa^2 ln(kappa/eps)),
-    j0 = ceil(sqrt(beta ln(4 beta/eps)))."""
-    b = float(np.ceil(kappa * kappa * np.log(kappa / eps)))
-    return int(b), int(np.ceil(np.sqrt(b * np.log(4.0 * b / eps))))

@@ -22,7 +22,7 @@ SYMBOLS = [
     "qw_load_csc", "qw_load_csc_batched", "qw_ctx_info", "qw_ctx_ninst", "qw_state_init", "qw_step",
     "qw_step_adjoint", "qw_measure", "qw_export", "qw_state_import", "qw_sync", "qls_run",
     "qw_cks_coeffs", "qw_grad", "qw_state_free", "qw_ctx_free", "qw_last_error", "qw_set_launch",
-    "qw_shutdown", "qw_load_csc_hermitian",
+    "qw_shutdown", "qw_load_csc_hermitian", "qw_kappa",
 ]
 
 ALLOC_T = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p)
@@ -64,7 +64,8 @@ def load() -> ctypes.CDLL:
         "qw_load_csc": (c_int, [PP, i32, ip, ip, dp, i64, dbl, u32, ap, P]),
         "qw_load_csc_batched": (c_int, [PP, i32, ip, lp, lp, ip, ip, dp, dp, u32, ap, P]),
         "qw_load_csc_hermitian": (c_int, [PP, i32, ip, lp, lp, ip, ip, dp, dp, dp, u32, ap, P]),
-        "qw_ctx_info": (c_int, [P, i32, ip, ip, ip, dp]),
+        "qw_ctx_info": (c_int, [P, i32, ip, ip, ip, dp, dp]),
+        "qw_kappa": (c_int, [P, i32, dp]),
         "qw_ctx_ninst": (i32, [P]),
         "qw_state_init": (c_int, [PP, P, dp, dp, u32, i64, P]),
         "qw_step": (c_int, [P, i32, P]),
@@ -73,7 +74,7 @@ def load() -> ctypes.CDLL:
         "qw_export": (c_int, [P, up, dp, dp, i64, lp, P]),
         "qw_state_import": (c_int, [P, up, dp, dp, i64, P]),
         "qw_sync": (c_int, [P, P]),
-        "qls_run": (c_int, [P, dp, dbl, dbl, i32, dp, dp, dp, lp, P]),
+        "qls_run": (c_int, [P, dp, dbl, dbl, i32, dp, dp, dp, dp, lp, P]),
         "qw_cks_coeffs": (c_int, [i64, i32, dp]),
         "qw_grad": (c_int, [P, dp, i32, dp, dp, dp, dp, P]),
         "qw_state_free": (None, [P]),

@@ -3,6 +3,7 @@
 // the C ABI declared in include/qw.h.
 #include "../../include/qw.h"
 #include "qw_internal.h"
+#include "qw_kappa.h"
 
 #include <hip/hip_runtime.h>
 
@@ -11,7 +12,9 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <limits>
 #include <mutex>
+#include <new>
 #include <numeric>
 #include <string>
 #include <utility>
@@ -29,6 +32,34 @@ thread_local char g_err[1024];
 int set_err(int code, const std::string& msg) {
   std::snprintf(g_err, sizeof(g_err), "%s", msg.c_str());
   return code;
+}
+// The same without a std::string (usable where host memory has run out).
+int set_err_text(int code, const char* msg) {
+  std::snprintf(g_err, sizeof(g_err), "%s", msg);
+  return code;
+}
+
+// Body of an entry point of the C ABI: no C++ exception leaves the library.
+// Host memory exhaustion becomes QW_ENOMEM, anything else QW_EINVAL.
+template <class F>
+int guarded(F&& f) noexcept {
+  try {
+    return f();
+  } catch (const std::bad_alloc&) {
+    return set_err_text(QW_ENOMEM, "host memory allocation failed");
+  } catch (const std::exception& e) {
+    return set_err_text(QW_EINVAL, e.what());
+  } catch (...) {
+    return set_err_text(QW_EINVAL, "unexpected internal error");
+  }
+}
+// The same for entry points without a status (errors are dropped).
+template <class F>
+void guarded_void(F&& f) noexcept {
+  try {
+    f();
+  } catch (...) {
+  }
 }
 
 void prefix_err(const std::string& prefix) {
@@ -110,6 +141,14 @@ struct qw_ctx {
   int64_t nnz_total = 0;
   std::vector<HostInst> inst;
   std::vector<int64_t> csc_home;  // home of every CSC entry's slot
+  // Host copy of the QRAM table (row-major col/val as on the device, the
+  // imaginary parts by home), kept for the condition number.
+  std::vector<int32_t> hcol;
+  std::vector<double> hval;
+  std::vector<double> hvim;
+  // 1 / min |lambda(A/s)| per instance once computed (NaN before).
+  mutable std::mutex kappa_mu;
+  std::vector<double> kappa;
   int32_t* col = nullptr;
   double* val = nullptr;
   qw::SlotRec* rec = nullptr;
@@ -777,7 +816,30 @@ int load_impl(qw_ctx** out, int32_t ninst, const int32_t* n, const int64_t* colp
     ctx_release(ctx);
     return set_err(QW_EDEVICE, std::string("matrix upload: ") + hipGetErrorString(e));
   }
+  ctx->hcol.swap(hcol);
+  ctx->hval.swap(hval);
+  ctx->hvim.swap(hvim);
+  ctx->kappa.assign(size_t(ninst), std::numeric_limits<double>::quiet_NaN());
   *out = ctx;
+  return QW_OK;
+}
+
+// 1 / min |lambda(A/s)| of one instance, computed once and kept.
+int ctx_kappa(qw_ctx* ctx, int32_t inst, double* out) {
+  std::lock_guard<std::mutex> lock(ctx->kappa_mu);
+  double& k = ctx->kappa[size_t(inst)];
+  if (std::isnan(k)) {
+    const HostInst& hi = ctx->inst[size_t(inst)];
+    std::string err;
+    double lam = 0.0;
+    const int rc = qw::min_abs_eigenvalue(hi.n, hi.s, hi.nbits, ctx->hcol.data() + hi.item_base,
+                                          ctx->hval.data() + hi.item_base,
+                                          ctx->hvim.empty() ? nullptr : ctx->hvim.data() + hi.item_base,
+                                          ctx->word > 0, &lam, err);
+    if (rc) return set_err(rc, "kappa: " + err);
+    k = 1.0 / lam;
+  }
+  *out = k;
   return QW_OK;
 }
 
@@ -1050,430 +1112,492 @@ const char* qw_last_error(void) { return g_err; }
 
 int qw_load_csc(qw_ctx** out, int32_t n, const int32_t* colptr, const int32_t* rowidx, const double* vals,
                 int64_t nnz, double scale, uint32_t flags, const qw_allocator* alloc, void* stream) {
-  if (colptr && n > 0 && colptr[n] != nnz) return set_err(QW_EINVAL, "colptr[n] != nnz");
-  const int64_t zero = 0;
-  return load_impl(out, 1, &n, &zero, &zero, colptr, rowidx, vals, nullptr, scale > 0.0 ? &scale : nullptr, flags,
-                   alloc, stream);
+  return guarded([&]() -> int {
+    if (colptr && n > 0 && colptr[n] != nnz) return set_err(QW_EINVAL, "colptr[n] != nnz");
+    const int64_t zero = 0;
+    return load_impl(out, 1, &n, &zero, &zero, colptr, rowidx, vals, nullptr, scale > 0.0 ? &scale : nullptr, flags,
+                     alloc, stream);
+  });
 }
 
 int qw_load_csc_batched(qw_ctx** out, int32_t ninst, const int32_t* n, const int64_t* colptr_off,
                         const int64_t* nnz_off, const int32_t* colptr, const int32_t* rowidx, const double* vals,
                         const double* scales, uint32_t flags, const qw_allocator* alloc, void* stream) {
-  if (!colptr_off || !nnz_off) return set_err(QW_EINVAL, "offset arrays are required");
-  return load_impl(out, ninst, n, colptr_off, nnz_off, colptr, rowidx, vals, nullptr, scales, flags, alloc, stream);
+  return guarded([&]() -> int {
+    if (!colptr_off || !nnz_off) return set_err(QW_EINVAL, "offset arrays are required");
+    return load_impl(out, ninst, n, colptr_off, nnz_off, colptr, rowidx, vals, nullptr, scales, flags, alloc, stream);
+  });
 }
 
 int qw_load_csc_hermitian(qw_ctx** out, int32_t ninst, const int32_t* n, const int64_t* colptr_off,
                           const int64_t* nnz_off, const int32_t* colptr, const int32_t* rowidx, const double* vals_re,
                           const double* vals_im, const double* scales, uint32_t flags, const qw_allocator* alloc,
                           void* stream) {
-  if (!vals_im) return set_err(QW_EINVAL, "vals_im is required (use qw_load_csc for real matrices)");
-  if (ninst > 1 && (!colptr_off || !nnz_off)) return set_err(QW_EINVAL, "offset arrays are required");
-  return load_impl(out, ninst, n, colptr_off, nnz_off, colptr, rowidx, vals_re, vals_im, scales, flags, alloc,
-                   stream);
+  return guarded([&]() -> int {
+    if (!vals_im) return set_err(QW_EINVAL, "vals_im is required (use qw_load_csc for real matrices)");
+    if (ninst > 1 && (!colptr_off || !nnz_off)) return set_err(QW_EINVAL, "offset arrays are required");
+    return load_impl(out, ninst, n, colptr_off, nnz_off, colptr, rowidx, vals_re, vals_im, scales, flags, alloc,
+                     stream);
+  });
 }
 
 int32_t qw_ctx_ninst(const qw_ctx* ctx) { return ctx ? ctx->ninst : 0; }
 
-int qw_ctx_info(const qw_ctx* ctx, int32_t inst, int32_t* n_padded, int32_t* s, int32_t* nbits, double* scale) {
-  if (!ctx || inst < 0 || inst >= ctx->ninst) return set_err(QW_EINVAL, "bad context or instance");
-  const HostInst& hi = ctx->inst[inst];
-  if (n_padded) *n_padded = hi.N;
-  if (s) *s = hi.s;
-  if (nbits) *nbits = ctx->nbits;
-  if (scale) *scale = hi.scale;
-  return QW_OK;
+int qw_ctx_info(const qw_ctx* ctx, int32_t inst, int32_t* n_padded, int32_t* s, int32_t* nbits, double* scale,
+                double* kappa) {
+  return guarded([&]() -> int {
+    if (!ctx || inst < 0 || inst >= ctx->ninst) return set_err(QW_EINVAL, "bad context or instance");
+    const HostInst& hi = ctx->inst[inst];
+    if (n_padded) *n_padded = hi.N;
+    if (s) *s = hi.s;
+    if (nbits) *nbits = ctx->nbits;
+    if (scale) *scale = hi.scale;
+    if (kappa) {
+      std::lock_guard<std::mutex> lock(ctx->kappa_mu);
+      *kappa = ctx->kappa[size_t(inst)];
+    }
+    return QW_OK;
+  });
+}
+
+int qw_kappa(qw_ctx* ctx, int32_t inst, double* kappa) {
+  return guarded([&]() -> int {
+    if (!ctx || inst < 0 || inst >= ctx->ninst || !kappa) return set_err(QW_EINVAL, "bad context, instance or output");
+    return ctx_kappa(ctx, inst, kappa);
+  });
 }
 
 void qw_ctx_free(qw_ctx* ctx) {
-  if (ctx) ctx_release(ctx);
+  guarded_void([&]() {
+    if (ctx) ctx_release(ctx);
+  });
 }
 
 int qw_state_init(qw_state** out, qw_ctx* ctx, const double* b_re, const double* b_im, uint32_t flags,
                   int64_t capacity, void* stream_v) {
-  if (!out || !ctx || !b_re) return set_err(QW_EINVAL, "missing argument");
-  *out = nullptr;
-  hipStream_t stream = static_cast<hipStream_t>(stream_v);
-  std::vector<double2> hb(static_cast<size_t>(ctx->jtotal), make_double2(0.0, 0.0));
-  int64_t src = 0;
-  for (int32_t i = 0; i < ctx->ninst; ++i) {
-    const HostInst& hi = ctx->inst[i];
-    for (int32_t j = 0; j < hi.n; ++j, ++src) {
-      const double2 v = make_double2(b_re[src], b_im ? b_im[src] : 0.0);
-      if (!std::isfinite(v.x) || !std::isfinite(v.y)) return set_err(QW_EINVAL, "non-finite b");
-      hb[size_t(hi.jbase + j)] = v;
-    }
-  }
-  if (capacity < 0) return set_err(QW_EINVAL, "capacity must be >= 0");
-  qw_state* st;
-  int rc = state_alloc(ctx, capacity, &st, stream);
-  if (rc) return rc;
-  hipError_t e = hipMemcpyAsync(st->b, hb.data(), sizeof(double2) * ctx->jtotal, hipMemcpyHostToDevice, stream);
-  if (e == hipSuccess) e = hipStreamSynchronize(stream);
-  if (e != hipSuccess) {
-    qw_state_free(st);
-    return set_err(QW_EDEVICE, std::string("b upload: ") + hipGetErrorString(e));
-  }
-  if (flags & QW_INIT_RAW) {
-    std::vector<uint64_t> keys;
-    std::vector<double2> amps;
-    const int n = ctx->nbits;
+  return guarded([&]() -> int {
+    if (!out || !ctx || !b_re) return set_err(QW_EINVAL, "missing argument");
+    *out = nullptr;
+    hipStream_t stream = static_cast<hipStream_t>(stream_v);
+    std::vector<double2> hb(static_cast<size_t>(ctx->jtotal), make_double2(0.0, 0.0));
+    int64_t src = 0;
     for (int32_t i = 0; i < ctx->ninst; ++i) {
       const HostInst& hi = ctx->inst[i];
-      for (int32_t j = 0; j < hi.N; ++j) {
-        const double2 v = hb[size_t(hi.jbase + j)];
-        if (v.x == 0.0 && v.y == 0.0) continue;
-        keys.push_back((uint64_t(i) << (4 * n + 2)) | (uint64_t(j) << (2 * n + 2)));
-        amps.push_back(v);
+      for (int32_t j = 0; j < hi.n; ++j, ++src) {
+        const double2 v = make_double2(b_re[src], b_im ? b_im[src] : 0.0);
+        if (!std::isfinite(v.x) || !std::isfinite(v.y)) return set_err(QW_EINVAL, "non-finite b");
+        hb[size_t(hi.jbase + j)] = v;
       }
     }
-    rc = import_branches(st, keys, amps, stream);
-    if (rc == QW_OK) rc = restart_counts(st, 0, stream);
-    if (rc) {
-      qw_state_free(st);
-      return rc;
-    }
-  } else {
-    e = qw::launch_init(ctx->mat(), st->b, view(st), qw::kTau, stream);  // a fresh state: buffer 0, r1s = +1
+    if (capacity < 0) return set_err(QW_EINVAL, "capacity must be >= 0");
+    qw_state* st;
+    int rc = state_alloc(ctx, capacity, &st, stream);
+    if (rc) return rc;
+    hipError_t e = hipMemcpyAsync(st->b, hb.data(), sizeof(double2) * ctx->jtotal, hipMemcpyHostToDevice, stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(stream);
     if (e != hipSuccess) {
       qw_state_free(st);
-      return set_err(QW_EDEVICE, std::string("init: ") + hipGetErrorString(e));
+      return set_err(QW_EDEVICE, std::string("b upload: ") + hipGetErrorString(e));
     }
-    st->prepared = true;
-    st->zclean = true;
-    st->real_ok = true;
-    if (b_im)
-      for (int64_t j = 0; j < ctx->jtotal; ++j) st->real_ok = st->real_ok && hb[size_t(j)].y == 0.0;
-  }
-  *out = st;
-  return QW_OK;
+    if (flags & QW_INIT_RAW) {
+      std::vector<uint64_t> keys;
+      std::vector<double2> amps;
+      const int n = ctx->nbits;
+      for (int32_t i = 0; i < ctx->ninst; ++i) {
+        const HostInst& hi = ctx->inst[i];
+        for (int32_t j = 0; j < hi.N; ++j) {
+          const double2 v = hb[size_t(hi.jbase + j)];
+          if (v.x == 0.0 && v.y == 0.0) continue;
+          keys.push_back((uint64_t(i) << (4 * n + 2)) | (uint64_t(j) << (2 * n + 2)));
+          amps.push_back(v);
+        }
+      }
+      rc = import_branches(st, keys, amps, stream);
+      if (rc == QW_OK) rc = restart_counts(st, 0, stream);
+      if (rc) {
+        qw_state_free(st);
+        return rc;
+      }
+    } else {
+      e = qw::launch_init(ctx->mat(), st->b, view(st), qw::kTau, stream);  // a fresh state: buffer 0, r1s = +1
+      if (e != hipSuccess) {
+        qw_state_free(st);
+        return set_err(QW_EDEVICE, std::string("init: ") + hipGetErrorString(e));
+      }
+      st->prepared = true;
+      st->zclean = true;
+      st->real_ok = true;
+      if (b_im)
+        for (int64_t j = 0; j < ctx->jtotal; ++j) st->real_ok = st->real_ok && hb[size_t(j)].y == 0.0;
+    }
+    *out = st;
+    return QW_OK;
+  });
 }
 
 void qw_state_free(qw_state* st) {
-  if (!st) return;
-  (void)hipDeviceSynchronize();
-  free_graphs(st);
-  qw_ctx* ctx = st->ctx;
-  for (const auto& o : st->owned) ctx_give(ctx, o.first, o.second);
-  delete st;
-  ctx_release(ctx);
+  guarded_void([&]() {
+    if (!st) return;
+    (void)hipDeviceSynchronize();
+    free_graphs(st);
+    qw_ctx* ctx = st->ctx;
+    for (const auto& o : st->owned) ctx_give(ctx, o.first, o.second);
+    delete st;
+    ctx_release(ctx);
+  });
 }
 
 int qw_set_launch(qw_state* st, int32_t wg_size, int32_t grid) {
-  if (!st) return set_err(QW_EINVAL, "state is NULL");
-  if (wg_size) {
-    if (wg_size < 64 || wg_size > 256 || wg_size % 64)
-      return set_err(QW_EINVAL, "workgroup size must be 64..256, a multiple of 64");
-    st->block = wg_size;
-  }
-  if (grid) {
-    if (grid < 1 || grid > qw::kMaxGrid) return set_err(QW_EINVAL, "grid out of range (1..65536)");
-    st->grid = grid;
-  }
-  free_graphs(st);
-  return QW_OK;
+  return guarded([&]() -> int {
+    if (!st) return set_err(QW_EINVAL, "state is NULL");
+    if (wg_size) {
+      if (wg_size < 64 || wg_size > 256 || wg_size % 64)
+        return set_err(QW_EINVAL, "workgroup size must be 64..256, a multiple of 64");
+      st->block = wg_size;
+    }
+    if (grid) {
+      if (grid < 1 || grid > qw::kMaxGrid) return set_err(QW_EINVAL, "grid out of range (1..65536)");
+      st->grid = grid;
+    }
+    free_graphs(st);
+    return QW_OK;
+  });
 }
 
 int qw_step(qw_state* st, int32_t nsteps, void* stream) {
-  if (!st || nsteps < 0) return set_err(QW_EINVAL, "bad state or step count");
-  int rc = run_steps(st, nsteps, static_cast<hipStream_t>(stream));
-  if (rc == QW_OK) st->steps_since_init += nsteps;
-  return rc;
+  return guarded([&]() -> int {
+    if (!st || nsteps < 0) return set_err(QW_EINVAL, "bad state or step count");
+    int rc = run_steps(st, nsteps, static_cast<hipStream_t>(stream));
+    if (rc == QW_OK) st->steps_since_init += nsteps;
+    return rc;
+  });
 }
 
 int qw_step_adjoint(qw_state* st, int32_t nsteps, void* stream_v) {
-  if (!st || nsteps < 0) return set_err(QW_EINVAL, "bad state or step count");
-  if (nsteps == 0) return QW_OK;
-  hipStream_t stream = static_cast<hipStream_t>(stream_v);
-  // W^dagger = S W S: swap, walk, swap
-  int rc = launch_one(st, qw::kSwap, stream);
-  if (!rc) rc = run_steps(st, nsteps, stream);
-  if (!rc) rc = launch_one(st, qw::kSwap, stream);
-  if (rc == QW_OK) st->steps_since_init -= nsteps;
-  return rc;
+  return guarded([&]() -> int {
+    if (!st || nsteps < 0) return set_err(QW_EINVAL, "bad state or step count");
+    if (nsteps == 0) return QW_OK;
+    hipStream_t stream = static_cast<hipStream_t>(stream_v);
+    // W^dagger = S W S: swap, walk, swap
+    int rc = launch_one(st, qw::kSwap, stream);
+    if (!rc) rc = run_steps(st, nsteps, stream);
+    if (!rc) rc = launch_one(st, qw::kSwap, stream);
+    if (rc == QW_OK) st->steps_since_init -= nsteps;
+    return rc;
+  });
 }
 
 int qw_sync(qw_state* st, void* stream) {
-  if (!st) return set_err(QW_EINVAL, "state is NULL");
-  QW_HIP(hipStreamSynchronize(static_cast<hipStream_t>(stream)));
-  return QW_OK;
+  return guarded([&]() -> int {
+    if (!st) return set_err(QW_EINVAL, "state is NULL");
+    QW_HIP(hipStreamSynchronize(static_cast<hipStream_t>(stream)));
+    return QW_OK;
+  });
 }
 
 int qw_measure(qw_state* st, int32_t kind, void* out, int64_t out_len, void* stream_v) {
-  if (!st || !out) return set_err(QW_EINVAL, "missing argument");
-  hipStream_t stream = static_cast<hipStream_t>(stream_v);
-  qw_ctx* ctx = st->ctx;
-  switch (kind) {
-    case QW_COUNT: {
-      if (out_len < 1) return set_err(QW_EINVAL, "out_len too small");
-      double c;
-      int rc = measure_partials(st, 0, &c, stream);
-      if (!rc) static_cast<int64_t*>(out)[0] = int64_t(std::llround(c));
-      return rc;
+  return guarded([&]() -> int {
+    if (!st || !out) return set_err(QW_EINVAL, "missing argument");
+    hipStream_t stream = static_cast<hipStream_t>(stream_v);
+    qw_ctx* ctx = st->ctx;
+    switch (kind) {
+      case QW_COUNT: {
+        if (out_len < 1) return set_err(QW_EINVAL, "out_len too small");
+        double c;
+        int rc = measure_partials(st, 0, &c, stream);
+        if (!rc) static_cast<int64_t*>(out)[0] = int64_t(std::llround(c));
+        return rc;
+      }
+      case QW_NORM: {
+        if (out_len < 1) return set_err(QW_EINVAL, "out_len too small");
+        return measure_partials(st, 1, static_cast<double*>(out), stream);
+      }
+      case QW_J_MARGINAL:
+      case QW_PROJECT: {
+        const int64_t need = kind == QW_J_MARGINAL ? ctx->jtotal : 2 * ctx->jtotal;
+        if (out_len < need) return set_err(QW_EINVAL, "out_len too small");
+        int rc = to_complex(st, stream);
+        if (rc) return rc;
+        QW_HIP(qw::launch_fill(st->mbuf, (sizeof(double) * need + 15) / 16 * 16, stream));
+        QW_HIP(qw::launch_measure(ctx->mat(), view(st), st->L, kind == QW_J_MARGINAL ? 2 : 3, nullptr,
+                                  st->mbuf, 256, stream));
+        QW_HIP(hipMemcpyAsync(out, st->mbuf, sizeof(double) * need, hipMemcpyDeviceToHost, stream));
+        QW_HIP(hipStreamSynchronize(stream));
+        return QW_OK;
+      }
+      case QW_STATS: {
+        if (out_len < 5) return set_err(QW_EINVAL, "out_len too small");
+        int64_t* o = static_cast<int64_t*>(out);
+        double c;
+        int rc = measure_partials(st, 0, &c, stream);
+        if (rc) return rc;
+        int64_t tw;
+        rc = total_written(st, stream, &tw);
+        if (rc) return rc;
+        o[0] = st->launches;
+        o[1] = int64_t(std::llround(c));
+        o[2] = int64_t(st->L.cap);
+        o[3] = int64_t(st->L.cnt);
+        o[4] = tw;
+        if (out_len >= 6) o[5] = st->real_ok && st->ctx->realsym ? 1 : 0;
+        if (out_len >= 7) o[6] = st->ctx->wide ? 16 : 8;
+        return QW_OK;
+      }
+      default:
+        return set_err(QW_EINVAL, "unknown measurement kind");
     }
-    case QW_NORM: {
-      if (out_len < 1) return set_err(QW_EINVAL, "out_len too small");
-      return measure_partials(st, 1, static_cast<double*>(out), stream);
-    }
-    case QW_J_MARGINAL:
-    case QW_PROJECT: {
-      const int64_t need = kind == QW_J_MARGINAL ? ctx->jtotal : 2 * ctx->jtotal;
-      if (out_len < need) return set_err(QW_EINVAL, "out_len too small");
-      int rc = to_complex(st, stream);
-      if (rc) return rc;
-      QW_HIP(qw::launch_fill(st->mbuf, (sizeof(double) * need + 15) / 16 * 16, stream));
-      QW_HIP(qw::launch_measure(ctx->mat(), view(st), st->L, kind == QW_J_MARGINAL ? 2 : 3, nullptr,
-                                st->mbuf, 256, stream));
-      QW_HIP(hipMemcpyAsync(out, st->mbuf, sizeof(double) * need, hipMemcpyDeviceToHost, stream));
-      QW_HIP(hipStreamSynchronize(stream));
-      return QW_OK;
-    }
-    case QW_STATS: {
-      if (out_len < 5) return set_err(QW_EINVAL, "out_len too small");
-      int64_t* o = static_cast<int64_t*>(out);
-      double c;
-      int rc = measure_partials(st, 0, &c, stream);
-      if (rc) return rc;
-      int64_t tw;
-      rc = total_written(st, stream, &tw);
-      if (rc) return rc;
-      o[0] = st->launches;
-      o[1] = int64_t(std::llround(c));
-      o[2] = int64_t(st->L.cap);
-      o[3] = int64_t(st->L.cnt);
-      o[4] = tw;
-      if (out_len >= 6) o[5] = st->real_ok && st->ctx->realsym ? 1 : 0;
-      if (out_len >= 7) o[6] = st->ctx->wide ? 16 : 8;
-      return QW_OK;
-    }
-    default:
-      return set_err(QW_EINVAL, "unknown measurement kind");
-  }
+  });
 }
 
 int qw_export(qw_state* st, uint64_t* keys, double* re, double* im, int64_t cap, int64_t* m, void* stream_v) {
-  if (!st || !m) return set_err(QW_EINVAL, "missing argument");
-  hipStream_t stream = static_cast<hipStream_t>(stream_v);
-  int64_t count = 0;
-  int rc = qw_measure(st, QW_COUNT, &count, 1, stream_v);
-  if (rc) return rc;
-  *m = count;
-  if (cap < count) return set_err(QW_EINVAL, "output arrays too small: " + std::to_string(count) + " branches");
-  if (count == 0) return QW_OK;
-  if (!keys) return set_err(QW_EINVAL, "keys is NULL");
-  qw_ctx* ctx = st->ctx;
-  void* dk = ctx->alloc.get(sizeof(uint64_t) * count);
-  void* da = ctx->alloc.get(sizeof(double2) * count);
-  void* dc = ctx->alloc.get(256);
-  std::vector<uint64_t> hk(static_cast<size_t>(count));
-  std::vector<double2> ha(static_cast<size_t>(count));
-  uint32_t got = 0;
-  hipError_t e = (dk && da && dc) ? hipSuccess : hipErrorOutOfMemory;
-  if (e == hipSuccess) e = qw::launch_fill(dc, 256, stream);
-  if (e == hipSuccess)
-    e = qw::launch_export(ctx->mat(), view(st), st->L, static_cast<uint64_t*>(dk),
-                          static_cast<double2*>(da), static_cast<uint32_t*>(dc), uint32_t(count), stream);
-  if (e == hipSuccess) e = hipMemcpyAsync(&got, dc, sizeof(uint32_t), hipMemcpyDeviceToHost, stream);
-  if (e == hipSuccess) e = hipMemcpyAsync(hk.data(), dk, sizeof(uint64_t) * count, hipMemcpyDeviceToHost, stream);
-  if (e == hipSuccess) e = hipMemcpyAsync(ha.data(), da, sizeof(double2) * count, hipMemcpyDeviceToHost, stream);
-  if (e == hipSuccess) e = hipStreamSynchronize(stream);
-  ctx->alloc.put(dk);
-  ctx->alloc.put(da);
-  ctx->alloc.put(dc);
-  if (e != hipSuccess)
-    return set_err(e == hipErrorOutOfMemory ? QW_ENOMEM : QW_EDEVICE, std::string("export: ") + hipGetErrorString(e));
-  if (int64_t(got) != count) return set_err(QW_EDEVICE, "export count mismatch");
-  std::vector<int64_t> idx(static_cast<size_t>(count));
-  std::iota(idx.begin(), idx.end(), 0);
-  std::sort(idx.begin(), idx.end(), [&](int64_t a, int64_t b) { return hk[size_t(a)] < hk[size_t(b)]; });
-  for (int64_t t = 0; t < count; ++t) {
-    keys[t] = hk[size_t(idx[size_t(t)])];
-    if (re) re[t] = ha[size_t(idx[size_t(t)])].x;
-    if (im) im[t] = ha[size_t(idx[size_t(t)])].y;
-  }
-  return QW_OK;
+  return guarded([&]() -> int {
+    if (!st || !m) return set_err(QW_EINVAL, "missing argument");
+    hipStream_t stream = static_cast<hipStream_t>(stream_v);
+    int64_t count = 0;
+    int rc = qw_measure(st, QW_COUNT, &count, 1, stream_v);
+    if (rc) return rc;
+    *m = count;
+    if (cap < count) return set_err(QW_EINVAL, "output arrays too small: " + std::to_string(count) + " branches");
+    if (count == 0) return QW_OK;
+    if (!keys) return set_err(QW_EINVAL, "keys is NULL");
+    qw_ctx* ctx = st->ctx;
+    void* dk = ctx->alloc.get(sizeof(uint64_t) * count);
+    void* da = ctx->alloc.get(sizeof(double2) * count);
+    void* dc = ctx->alloc.get(256);
+    std::vector<uint64_t> hk(static_cast<size_t>(count));
+    std::vector<double2> ha(static_cast<size_t>(count));
+    uint32_t got = 0;
+    hipError_t e = (dk && da && dc) ? hipSuccess : hipErrorOutOfMemory;
+    if (e == hipSuccess) e = qw::launch_fill(dc, 256, stream);
+    if (e == hipSuccess)
+      e = qw::launch_export(ctx->mat(), view(st), st->L, static_cast<uint64_t*>(dk),
+                            static_cast<double2*>(da), static_cast<uint32_t*>(dc), uint32_t(count), stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(&got, dc, sizeof(uint32_t), hipMemcpyDeviceToHost, stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(hk.data(), dk, sizeof(uint64_t) * count, hipMemcpyDeviceToHost, stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(ha.data(), da, sizeof(double2) * count, hipMemcpyDeviceToHost, stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(stream);
+    ctx->alloc.put(dk);
+    ctx->alloc.put(da);
+    ctx->alloc.put(dc);
+    if (e != hipSuccess)
+      return set_err(e == hipErrorOutOfMemory ? QW_ENOMEM : QW_EDEVICE, std::string("export: ") + hipGetErrorString(e));
+    if (int64_t(got) != count) return set_err(QW_EDEVICE, "export count mismatch");
+    std::vector<int64_t> idx(static_cast<size_t>(count));
+    std::iota(idx.begin(), idx.end(), 0);
+    std::sort(idx.begin(), idx.end(), [&](int64_t a, int64_t b) { return hk[size_t(a)] < hk[size_t(b)]; });
+    for (int64_t t = 0; t < count; ++t) {
+      keys[t] = hk[size_t(idx[size_t(t)])];
+      if (re) re[t] = ha[size_t(idx[size_t(t)])].x;
+      if (im) im[t] = ha[size_t(idx[size_t(t)])].y;
+    }
+    return QW_OK;
+  });
 }
 
 int qw_state_import(qw_state* st, const uint64_t* keys, const double* re, const double* im, int64_t m,
                     void* stream_v) {
-  if (!st || m < 0 || (m > 0 && (!keys || !re))) return set_err(QW_EINVAL, "missing argument");
-  hipStream_t stream = static_cast<hipStream_t>(stream_v);
-  std::vector<uint64_t> k;
-  std::vector<double2> a;
-  int rc = canonical_branches(st->ctx, keys, re, im, m, k, a);
-  if (rc) return rc;
-  int64_t written = 0;
-  rc = total_written(st, stream, &written);
-  if (rc) return rc;
-  rc = state_clear(st, stream);
-  if (rc) return rc;
-  st->prepared = false;
-  st->zclean = false;  // imported branches may sit in R0 or Q0 of slots of value 0
-  st->real_ok = false;
-  st->in_real = false;  // state_clear empties the complex planes, which hold the state from here
-  st->steps_since_init = 0;
-  free_graphs(st);  // the list pointers and the kernel arguments change
-  rc = import_branches(st, k, a, stream);
-  if (rc) return rc;
-  return restart_counts(st, written, stream);
+  return guarded([&]() -> int {
+    if (!st || m < 0 || (m > 0 && (!keys || !re))) return set_err(QW_EINVAL, "missing argument");
+    hipStream_t stream = static_cast<hipStream_t>(stream_v);
+    std::vector<uint64_t> k;
+    std::vector<double2> a;
+    int rc = canonical_branches(st->ctx, keys, re, im, m, k, a);
+    if (rc) return rc;
+    int64_t written = 0;
+    rc = total_written(st, stream, &written);
+    if (rc) return rc;
+    rc = state_clear(st, stream);
+    if (rc) return rc;
+    st->prepared = false;
+    st->zclean = false;  // imported branches may sit in R0 or Q0 of slots of value 0
+    st->real_ok = false;
+    st->in_real = false;  // state_clear empties the complex planes, which hold the state from here
+    st->steps_since_init = 0;
+    free_graphs(st);  // the list pointers and the kernel arguments change
+    rc = import_branches(st, k, a, stream);
+    if (rc) return rc;
+    return restart_counts(st, written, stream);
+  });
 }
 
 int qw_cks_coeffs(int64_t beta, int32_t j0, double* out) {
-  if (beta < 1 || j0 < 0 || !out) return set_err(QW_EINVAL, "bad arguments");
-  cks_coefficients(beta, j0, out);
-  return QW_OK;
+  return guarded([&]() -> int {
+    if (beta < 1 || j0 < 0 || !out) return set_err(QW_EINVAL, "bad arguments");
+    cks_coefficients(beta, j0, out);
+    return QW_OK;
+  });
 }
 
-int qls_run(qw_ctx* ctx, const double* b, double kappa, double eps, int32_t j0_override, double* y_re,
-            double* y_im, double* p_succ, int64_t* walk_steps, void* stream_v) {
-  if (!ctx || !b) return set_err(QW_EINVAL, "missing argument");
-  if (!(kappa > 1.0) || !std::isfinite(kappa)) return set_err(QW_EINVAL, "kappa must be > 1");
-  if (!(eps > 0.0 && eps < 1.0)) return set_err(QW_EINVAL, "eps must lie in (0, 1)");
-  hipStream_t stream = static_cast<hipStream_t>(stream_v);
-  const double bb = std::ceil(kappa * kappa * std::log(kappa / eps));
-  const int64_t beta = int64_t(bb);
-  int32_t j0 = int32_t(std::ceil(std::sqrt(bb * std::log(4.0 * bb / eps))));
-  if (j0_override >= 0) j0 = j0_override;
-  std::vector<double> a(static_cast<size_t>(j0) + 1);
-  cks_coefficients(beta, j0, a.data());
-  const int64_t nsteps = 2 * int64_t(j0) + 1;
-  // coefficient per input step number m: a_{(m-1)/2} for odd m
-  std::vector<double> coefm(static_cast<size_t>(nsteps) + 1, 0.0);
-  for (int64_t mm = 1; mm <= nsteps; mm += 2) coefm[size_t(mm)] = a[size_t((mm - 1) / 2)];
-  // the solver works on instance 0 only
-  std::vector<double> bfull(static_cast<size_t>(ctx->ntotal), 0.0);
-  for (int32_t j = 0; j < ctx->inst[0].n; ++j) bfull[size_t(j)] = b[j];
-  qw_state* st = nullptr;
-  int rc = qw_state_init(&st, ctx, bfull.data(), nullptr, 0, 0, stream_v);
-  if (rc) return rc;
-  st->counts = false;  // nobody reads this walk's branch counts
-  const int64_t N = ctx->inst[0].N;
-  double* dcoef = static_cast<double*>(ctx->alloc.get(sizeof(double) * coefm.size()));
-  double2* y = static_cast<double2*>(ctx->alloc.get(sizeof(double2) * ctx->jtotal));
-  std::vector<double2> hy(static_cast<size_t>(ctx->jtotal));
-  std::vector<double> proj(2 * static_cast<size_t>(ctx->jtotal));
-  hipError_t e = (dcoef && y) ? hipSuccess : hipErrorOutOfMemory;
-  if (e == hipSuccess)
-    e = hipMemcpyAsync(dcoef, coefm.data(), sizeof(double) * coefm.size(), hipMemcpyHostToDevice, stream);
-  if (e == hipSuccess) e = qw::launch_fill(y, sizeof(double2) * ctx->jtotal, stream);
-  if (e == hipSuccess) {
-    rc = run_steps(st, nsteps, stream, y, dcoef);
-    if (!rc) rc = qw_measure(st, QW_PROJECT, proj.data(), int64_t(proj.size()), stream_v);
-    if (!rc) {
-      e = hipMemcpyAsync(hy.data(), y, sizeof(double2) * ctx->jtotal, hipMemcpyDeviceToHost, stream);
-      if (e == hipSuccess) e = hipStreamSynchronize(stream);
+int qls_run(qw_ctx* ctx, const double* b, double kappa, double eps, int32_t j0_override, double* x_re,
+            double* x_im, double* y_norm, double* p_succ, int64_t* walk_steps, void* stream_v) {
+  return guarded([&]() -> int {
+    if (!ctx || !b) return set_err(QW_EINVAL, "missing argument");
+    if (!(eps > 0.0 && eps < 1.0)) return set_err(QW_EINVAL, "eps must lie in (0, 1)");
+    if (kappa <= 0.0) {  // the library's own condition number of A/s
+      int rck = ctx_kappa(ctx, 0, &kappa);
+      if (rck) return rck;
+      if (!(kappa >= 1.0)) return set_err(QW_EINVAL, "computed kappa below 1");
+    } else if (!(kappa > 1.0) || !std::isfinite(kappa)) {
+      return set_err(QW_EINVAL, "kappa must be > 1 (or <= 0 for the library's own)");
     }
-  }
-  ctx->alloc.put(dcoef);
-  ctx->alloc.put(y);
-  qw_state_free(st);
-  if (e != hipSuccess) return set_err(e == hipErrorOutOfMemory ? QW_ENOMEM : QW_EDEVICE, "linear solver failed");
-  if (rc) return rc;
-  double norm2 = 0.0, asum = 0.0;
-  for (double v : a) asum += std::fabs(v);
-  for (int64_t j = 0; j < N; ++j) {
-    const double yr = hy[size_t(j)].x + a[size_t(j0)] * proj[2 * size_t(j)];
-    const double yi = hy[size_t(j)].y + a[size_t(j0)] * proj[2 * size_t(j) + 1];
-    if (y_re && j < ctx->inst[0].n) y_re[j] = yr;
-    if (y_im && j < ctx->inst[0].n) y_im[j] = yi;
-    norm2 += yr * yr + yi * yi;
-  }
-  if (p_succ) *p_succ = norm2 / (asum * asum);
-  if (walk_steps) *walk_steps = nsteps;
-  return QW_OK;
+    hipStream_t stream = static_cast<hipStream_t>(stream_v);
+    const double bb = std::ceil(kappa * kappa * std::log(kappa / eps));
+    const double j0d = std::ceil(std::sqrt(bb * std::log(4.0 * bb / eps)));
+    if (!(bb < 1e15) || !(j0d < 1e9))
+      return set_err(QW_EINVAL, "kappa " + std::to_string(kappa) + " needs a schedule of more than 2e9 walk steps");
+    const int64_t beta = int64_t(bb);
+    int32_t j0 = int32_t(j0d);
+    if (j0_override >= 0) j0 = j0_override;
+    std::vector<double> a(static_cast<size_t>(j0) + 1);
+    cks_coefficients(beta, j0, a.data());
+    const int64_t nsteps = 2 * int64_t(j0) + 1;
+    // coefficient per input step number m: a_{(m-1)/2} for odd m
+    std::vector<double> coefm(static_cast<size_t>(nsteps) + 1, 0.0);
+    for (int64_t mm = 1; mm <= nsteps; mm += 2) coefm[size_t(mm)] = a[size_t((mm - 1) / 2)];
+    // the solver works on instance 0 only
+    std::vector<double> bfull(static_cast<size_t>(ctx->ntotal), 0.0);
+    for (int32_t j = 0; j < ctx->inst[0].n; ++j) bfull[size_t(j)] = b[j];
+    qw_state* st = nullptr;
+    int rc = qw_state_init(&st, ctx, bfull.data(), nullptr, 0, 0, stream_v);
+    if (rc) return rc;
+    st->counts = false;  // nobody reads this walk's branch counts
+    const int64_t N = ctx->inst[0].N;
+    double* dcoef = static_cast<double*>(ctx->alloc.get(sizeof(double) * coefm.size()));
+    double2* y = static_cast<double2*>(ctx->alloc.get(sizeof(double2) * ctx->jtotal));
+    std::vector<double2> hy(static_cast<size_t>(ctx->jtotal));
+    std::vector<double> proj(2 * static_cast<size_t>(ctx->jtotal));
+    hipError_t e = (dcoef && y) ? hipSuccess : hipErrorOutOfMemory;
+    if (e == hipSuccess)
+      e = hipMemcpyAsync(dcoef, coefm.data(), sizeof(double) * coefm.size(), hipMemcpyHostToDevice, stream);
+    if (e == hipSuccess) e = qw::launch_fill(y, sizeof(double2) * ctx->jtotal, stream);
+    if (e == hipSuccess) {
+      rc = run_steps(st, nsteps, stream, y, dcoef);
+      if (!rc) rc = qw_measure(st, QW_PROJECT, proj.data(), int64_t(proj.size()), stream_v);
+      if (!rc) {
+        e = hipMemcpyAsync(hy.data(), y, sizeof(double2) * ctx->jtotal, hipMemcpyDeviceToHost, stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(stream);
+      }
+    }
+    ctx->alloc.put(dcoef);
+    ctx->alloc.put(y);
+    qw_state_free(st);
+    if (e != hipSuccess) return set_err(e == hipErrorOutOfMemory ? QW_ENOMEM : QW_EDEVICE, "linear solver failed");
+    if (rc) return rc;
+    // y = sum_k a_k tau_k; the post-selected state is y / |y| (the success
+    // probability of the LCU is |y|^2 / (sum_k |a_k|)^2)
+    double norm2 = 0.0, asum = 0.0;
+    for (double v : a) asum += std::fabs(v);
+    for (int64_t j = 0; j < N; ++j) {
+      hy[size_t(j)].x += a[size_t(j0)] * proj[2 * size_t(j)];
+      hy[size_t(j)].y += a[size_t(j0)] * proj[2 * size_t(j) + 1];
+      norm2 += hy[size_t(j)].x * hy[size_t(j)].x + hy[size_t(j)].y * hy[size_t(j)].y;
+    }
+    const double yn = std::sqrt(norm2);
+    if (!(yn > 0.0)) return set_err(QW_EINVAL, "the solver's output vanishes (b = 0?)");
+    for (int32_t j = 0; j < ctx->inst[0].n; ++j) {
+      if (x_re) x_re[j] = hy[size_t(j)].x / yn;
+      if (x_im) x_im[j] = hy[size_t(j)].y / yn;
+    }
+    if (y_norm) *y_norm = yn;
+    if (p_succ) *p_succ = norm2 / (asum * asum);
+    if (walk_steps) *walk_steps = nsteps;
+    return QW_OK;
+  });
 }
 
 int qw_grad(qw_state* st, const double* w, int32_t nsteps, double* dvals, double* db_re, double* db_im,
             double* loss, void* stream_v) {
-  if (!st || !w) return set_err(QW_EINVAL, "missing argument");
-  if (!st->prepared || st->steps_since_init != nsteps)
-    return set_err(QW_EINVAL, "qw_grad needs the state made by qw_state_init (T~ start) advanced by exactly nsteps");
-  if (st->ctx->complex_values)
-    return set_err(QW_ENOTSUP, "the gradient is provided for real matrices only");
-  if (st->ctx->word > 0)
-    return set_err(QW_ENOTSUP, "the gradient is provided for FP64 values only, not fixed-point data");
-  hipStream_t stream = static_cast<hipStream_t>(stream_v);
-  int rc0 = to_complex(st, stream);
-  if (rc0) return rc0;
-  qw_ctx* ctx = st->ctx;
-  std::vector<double> hw(static_cast<size_t>(ctx->jtotal), 0.0);
-  int64_t src = 0;
-  for (int32_t i = 0; i < ctx->ninst; ++i)
-    for (int32_t j = 0; j < ctx->inst[i].n; ++j, ++src) hw[size_t(ctx->inst[i].jbase + j)] = w[src];
-  qw_state* lam = nullptr;
-  int rc = state_alloc(ctx, st->L.cap, &lam, stream);
-  if (rc) return rc;
-  lam->L.cnt = st->L.cnt;
-  double* dw = static_cast<double*>(ctx_take(ctx, sizeof(double) * ctx->jtotal));
-  double* dv = static_cast<double*>(ctx_take(ctx, sizeof(double) * ctx->items));
-  double2* db = static_cast<double2*>(ctx_take(ctx, sizeof(double2) * ctx->jtotal));
-  std::vector<double> hdv(static_cast<size_t>(ctx->items));
-  std::vector<double2> hdb(static_cast<size_t>(ctx->jtotal));
-  std::vector<double> part(256);
-  hipError_t e = (dw && dv && db) ? hipSuccess : hipErrorOutOfMemory;
-  const qw::Matrix mm = ctx->mat();
-  if (e == hipSuccess) e = hipMemcpyAsync(dw, hw.data(), sizeof(double) * ctx->jtotal, hipMemcpyHostToDevice, stream);
-  if (e == hipSuccess) e = qw::launch_fill(dv, (sizeof(double) * ctx->items + 15) / 16 * 16, stream);
-  // Psi_n = S psi_n, Lambda_n = diag(w[k]) Psi_n
-  if (e == hipSuccess) {
-    rc = launch_one(st, qw::kSwap, stream);
-    if (!rc)
-      e = qw::launch_weight(mm, view(st), st->L, view(lam), lam->L, dw, st->mbuf, 256, stream);
-  }
-  if (e == hipSuccess && !rc)
-    e = hipMemcpyAsync(part.data(), st->mbuf, sizeof(double) * 256, hipMemcpyDeviceToHost, stream);
-  for (int32_t t = nsteps; t >= 1 && e == hipSuccess && !rc; --t) {
-    qw::AdjArgs a;
-    a.m = mm;
-    a.in = view(st);
-    a.out = view(st, st->cur ^ 1, r1s_after(qw::kStep));
-    a.lin = view(lam);
-    a.lout = view(lam, lam->cur ^ 1, r1s_after(qw::kStep));
-    a.L = st->L;
-    a.LL = lam->L;
-    a.acc = st->acc;
-    a.lacc = lam->acc;
-    a.tau = qw::kTau;
-    a.dv = dv;
-    e = qw::launch_adjoint(a, step_grid(st), st->block, stream);
-    st->cur ^= 1;
-    lam->cur ^= 1;
-    st->r1s = lam->r1s = r1s_after(qw::kStep);
-    ++st->launches;
-  }
-  // back to the unconjugated frame: psi_0 and lambda_0
-  if (e == hipSuccess && !rc) rc = launch_one(st, qw::kSwap, stream);
-  if (e == hipSuccess && !rc) rc = launch_one(lam, qw::kSwap, stream);
-  if (e == hipSuccess && !rc) e = qw::launch_grad_init(mm, view(lam), st->b, dv, db, stream);
-  if (e == hipSuccess && !rc)
-    e = hipMemcpyAsync(hdv.data(), dv, sizeof(double) * ctx->items, hipMemcpyDeviceToHost, stream);
-  if (e == hipSuccess && !rc)
-    e = hipMemcpyAsync(hdb.data(), db, sizeof(double2) * ctx->jtotal, hipMemcpyDeviceToHost, stream);
-  if (e == hipSuccess && !rc) e = hipStreamSynchronize(stream);
-  (void)hipStreamSynchronize(stream);  // after an error too: nothing may still use the buffers
-  if (dw) ctx_give(ctx, dw, sizeof(double) * ctx->jtotal);
-  if (dv) ctx_give(ctx, dv, sizeof(double) * ctx->items);
-  if (db) ctx_give(ctx, db, sizeof(double2) * ctx->jtotal);
-  qw_state_free(lam);
-  st->steps_since_init = 0;
-  if (e != hipSuccess)
-    return set_err(e == hipErrorOutOfMemory ? QW_ENOMEM : QW_EDEVICE, std::string("gradient: ") + hipGetErrorString(e));
-  if (rc) return rc;
-  if (loss) {
-    double L = 0.0;
-    for (double v : part) L += v;
-    *loss = L;
-  }
-  if (dvals)
-    for (size_t p = 0; p < ctx->csc_home.size(); ++p) dvals[p] = hdv[size_t(ctx->csc_home[p])];
-  src = 0;
-  for (int32_t i = 0; i < ctx->ninst; ++i)
-    for (int32_t j = 0; j < ctx->inst[i].n; ++j, ++src) {
-      const double2 g = hdb[size_t(ctx->inst[i].jbase + j)];
-      if (db_re) db_re[src] = g.x;
-      if (db_im) db_im[src] = g.y;
+  return guarded([&]() -> int {
+    if (!st || !w) return set_err(QW_EINVAL, "missing argument");
+    if (!st->prepared || st->steps_since_init != nsteps)
+      return set_err(QW_EINVAL, "qw_grad needs the state made by qw_state_init (T~ start) advanced by exactly nsteps");
+    if (st->ctx->complex_values)
+      return set_err(QW_ENOTSUP, "the gradient is provided for real matrices only");
+    if (st->ctx->word > 0)
+      return set_err(QW_ENOTSUP, "the gradient is provided for FP64 values only, not fixed-point data");
+    hipStream_t stream = static_cast<hipStream_t>(stream_v);
+    int rc0 = to_complex(st, stream);
+    if (rc0) return rc0;
+    qw_ctx* ctx = st->ctx;
+    std::vector<double> hw(static_cast<size_t>(ctx->jtotal), 0.0);
+    int64_t src = 0;
+    for (int32_t i = 0; i < ctx->ninst; ++i)
+      for (int32_t j = 0; j < ctx->inst[i].n; ++j, ++src) hw[size_t(ctx->inst[i].jbase + j)] = w[src];
+    qw_state* lam = nullptr;
+    int rc = state_alloc(ctx, st->L.cap, &lam, stream);
+    if (rc) return rc;
+    lam->L.cnt = st->L.cnt;
+    double* dw = static_cast<double*>(ctx_take(ctx, sizeof(double) * ctx->jtotal));
+    double* dv = static_cast<double*>(ctx_take(ctx, sizeof(double) * ctx->items));
+    double2* db = static_cast<double2*>(ctx_take(ctx, sizeof(double2) * ctx->jtotal));
+    std::vector<double> hdv(static_cast<size_t>(ctx->items));
+    std::vector<double2> hdb(static_cast<size_t>(ctx->jtotal));
+    std::vector<double> part(256);
+    hipError_t e = (dw && dv && db) ? hipSuccess : hipErrorOutOfMemory;
+    const qw::Matrix mm = ctx->mat();
+    if (e == hipSuccess) e = hipMemcpyAsync(dw, hw.data(), sizeof(double) * ctx->jtotal, hipMemcpyHostToDevice, stream);
+    if (e == hipSuccess) e = qw::launch_fill(dv, (sizeof(double) * ctx->items + 15) / 16 * 16, stream);
+    // Psi_n = S psi_n, Lambda_n = diag(w[k]) Psi_n
+    if (e == hipSuccess) {
+      rc = launch_one(st, qw::kSwap, stream);
+      if (!rc)
+        e = qw::launch_weight(mm, view(st), st->L, view(lam), lam->L, dw, st->mbuf, 256, stream);
     }
-  return QW_OK;
+    if (e == hipSuccess && !rc)
+      e = hipMemcpyAsync(part.data(), st->mbuf, sizeof(double) * 256, hipMemcpyDeviceToHost, stream);
+    for (int32_t t = nsteps; t >= 1 && e == hipSuccess && !rc; --t) {
+      qw::AdjArgs a;
+      a.m = mm;
+      a.in = view(st);
+      a.out = view(st, st->cur ^ 1, r1s_after(qw::kStep));
+      a.lin = view(lam);
+      a.lout = view(lam, lam->cur ^ 1, r1s_after(qw::kStep));
+      a.L = st->L;
+      a.LL = lam->L;
+      a.acc = st->acc;
+      a.lacc = lam->acc;
+      a.tau = qw::kTau;
+      a.dv = dv;
+      e = qw::launch_adjoint(a, step_grid(st), st->block, stream);
+      st->cur ^= 1;
+      lam->cur ^= 1;
+      st->r1s = lam->r1s = r1s_after(qw::kStep);
+      ++st->launches;
+    }
+    // back to the unconjugated frame: psi_0 and lambda_0
+    if (e == hipSuccess && !rc) rc = launch_one(st, qw::kSwap, stream);
+    if (e == hipSuccess && !rc) rc = launch_one(lam, qw::kSwap, stream);
+    if (e == hipSuccess && !rc) e = qw::launch_grad_init(mm, view(lam), st->b, dv, db, stream);
+    if (e == hipSuccess && !rc)
+      e = hipMemcpyAsync(hdv.data(), dv, sizeof(double) * ctx->items, hipMemcpyDeviceToHost, stream);
+    if (e == hipSuccess && !rc)
+      e = hipMemcpyAsync(hdb.data(), db, sizeof(double2) * ctx->jtotal, hipMemcpyDeviceToHost, stream);
+    if (e == hipSuccess && !rc) e = hipStreamSynchronize(stream);
+    (void)hipStreamSynchronize(stream);  // after an error too: nothing may still use the buffers
+    if (dw) ctx_give(ctx, dw, sizeof(double) * ctx->jtotal);
+    if (dv) ctx_give(ctx, dv, sizeof(double) * ctx->items);
+    if (db) ctx_give(ctx, db, sizeof(double2) * ctx->jtotal);
+    qw_state_free(lam);
+    st->steps_since_init = 0;
+    if (e != hipSuccess)
+      return set_err(e == hipErrorOutOfMemory ? QW_ENOMEM : QW_EDEVICE, std::string("gradient: ") + hipGetErrorString(e));
+    if (rc) return rc;
+    if (loss) {
+      double L = 0.0;
+      for (double v : part) L += v;
+      *loss = L;
+    }
+    if (dvals)
+      for (size_t p = 0; p < ctx->csc_home.size(); ++p) dvals[p] = hdv[size_t(ctx->csc_home[p])];
+    src = 0;
+    for (int32_t i = 0; i < ctx->ninst; ++i)
+      for (int32_t j = 0; j < ctx->inst[i].n; ++j, ++src) {
+        const double2 g = hdb[size_t(ctx->inst[i].jbase + j)];
+        if (db_re) db_re[src] = g.x;
+        if (db_im) db_im[src] = g.y;
+      }
+    return QW_OK;
+  });
 }
 
 }  // extern "C"

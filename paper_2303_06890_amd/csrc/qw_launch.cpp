@@ -333,13 +333,16 @@ hipError_t launch_grad_init(const Matrix& m, Slots lam, const double2* b, double
 }  // namespace qw
 
 extern "C" void qw_shutdown(void) {
-  std::lock_guard<std::mutex> lock(qw::g_mu);
-  int cur = 0;
-  const bool have_dev = hipGetDevice(&cur) == hipSuccess;
-  for (int d = 0; d < qw::kMaxDevices; ++d) {
-    if (!qw::g_dev[d].loaded) continue;
-    if (hipSetDevice(d) == hipSuccess) (void)hipModuleUnload(qw::g_dev[d].mod);
-    qw::g_dev[d].loaded = false;
+  try {  // no C++ exception leaves the library (std::mutex::lock may throw)
+    std::lock_guard<std::mutex> lock(qw::g_mu);
+    int cur = 0;
+    const bool have_dev = hipGetDevice(&cur) == hipSuccess;
+    for (int d = 0; d < qw::kMaxDevices; ++d) {
+      if (!qw::g_dev[d].loaded) continue;
+      if (hipSetDevice(d) == hipSuccess) (void)hipModuleUnload(qw::g_dev[d].mod);
+      qw::g_dev[d].loaded = false;
+    }
+    if (have_dev) (void)hipSetDevice(cur);
+  } catch (...) {
   }
-  if (have_dev) (void)hipSetDevice(cur);
 }

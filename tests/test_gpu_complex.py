@@ -137,8 +137,11 @@ def test_complex_solver(Q, oracle_mod):
     beta, j0 = oracle_mod.schedule(kappa, 1e-3)
     coef = oracle_mod.cks_coeffs(beta, j0)
     y_ref = om.cheb_series(b, j0, coef)
-    y, p_succ, steps = Q.Walk(csc).qls(b, kappa, eps=1e-3)
+    walk = Q.Walk(csc)
+    x, p_succ, steps, yn = walk.qls(b, eps=1e-3)  # the library's kappa (complex: the real 2n form)
+    assert walk.kappa_known() == pytest.approx(kappa, rel=1e-11)
     assert steps == 2 * j0 + 1
+    y = yn * x
     assert np.abs(y - y_ref).max() <= 1e-10 * np.abs(y_ref).max()
     x = np.linalg.solve(H, b)
     fid = abs(np.vdot(x, y)) ** 2 / (np.vdot(x, x).real * np.vdot(y, y).real)

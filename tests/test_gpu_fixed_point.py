@@ -129,8 +129,9 @@ def test_fixed_point_solver(Q, oracle_mod):
     beta, _ = oracle_mod.schedule(kappa, 1e-3)
     coef = oracle_mod.cks_coeffs(beta, j0)
     y_ref = om.qls_walk(b, j0, coef)
-    y, p_succ, steps = Q.Walk(csc, word=word).qls(b, kappa=kappa, eps=1e-3, j0=j0)
+    x, p_succ, steps, yn = Q.Walk(csc, word=word).qls(b, kappa=kappa, eps=1e-3, j0=j0)
     assert steps == 2 * j0 + 1
+    y = yn * x
     assert np.abs(y - y_ref).max() <= 1e-10 * np.abs(y_ref).max()
 
 

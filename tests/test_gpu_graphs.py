@@ -57,6 +57,7 @@ def test_solver_graph_window(Q, oracle_mod):
     om = oracle_mod.OracleMatrix(csc)
     beta, _ = oracle_mod.schedule(kappa, 1e-3)
     y_ref = om.qls_walk(b, j0, oracle_mod.cks_coeffs(beta, j0))
-    y, _, steps = Q.Walk(csc).qls(b, kappa=kappa, eps=1e-3, j0=j0)
+    x, _, steps, yn = Q.Walk(csc).qls(b, kappa=kappa, eps=1e-3, j0=j0)
     assert steps == 301
+    y = yn * x
     assert np.abs(y - y_ref).max() <= 1e-12 * np.abs(y_ref).max()

@@ -115,8 +115,9 @@ def test_solver_projection_on_real_planes(Q, oracle_mod, word):
     y_ref = om.qls_walk(b, j0, oracle_mod.cks_coeffs(beta, j0))
     for mats in ([a], [a, other]):
         walk = Q.Walk(mats, word=word)
-        y, p_succ, steps = walk.qls(b, kappa=kappa, eps=1e-3, j0=j0)
+        x, p_succ, steps, yn = walk.qls(b, kappa=kappa, eps=1e-3, j0=j0)
         assert steps == 2 * j0 + 1
+        y = yn * x
         assert np.abs(y - y_ref).max() <= 1e-12 * np.abs(y_ref).max(), len(mats)
 
 

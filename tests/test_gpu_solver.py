@@ -25,6 +25,8 @@ def _kappa(csc):
 
 
 def test_qls_tiny_matches_oracle_walk_and_series(Q, oracle_mod):
+    """kappa from the library (qw_kappa inside qls_run), checked against
+    numpy's eigenvalues; the post-selected x and |y| against the oracle."""
     csc, _ = W.tiny_tridiagonal()
     b = W.gaussian_b(16, seed=3)
     kappa, H = _kappa(csc)
@@ -34,8 +36,12 @@ def test_qls_tiny_matches_oracle_walk_and_series(Q, oracle_mod):
     y_series = m.cheb_series(b, j0, coef)
     y_walk = m.qls_walk(b, j0, coef)
     walk = Q.Walk(csc)
-    y, p_succ, steps = walk.qls(b, kappa, eps=1e-2)
+    assert np.isnan(walk.kappa_known())
+    x, p_succ, steps, yn = walk.qls(b, eps=1e-2)
+    assert walk.kappa_known() == pytest.approx(kappa, rel=1e-11)
     assert steps == 2 * j0 + 1
+    assert np.linalg.norm(x) == pytest.approx(1.0, abs=1e-14)
+    y = yn * x
     scale = np.abs(y_series).max()
     assert np.abs(y - y_walk).max() < 1e-12 * scale
     assert np.abs(y - y_series).max() < 1e-11 * scale
@@ -56,8 +62,10 @@ def test_qls_laplacian_32x32(Q, oracle_mod):
     coef = oracle_mod.cks_coeffs(beta, j0)
     y_ref = oracle_mod.OracleMatrix(csc).cheb_series(b, j0, coef)
     walk = Q.Walk(csc)
-    y, p_succ, steps = walk.qls(b, kappa, eps=1e-3)
+    assert walk.kappa(0) == pytest.approx(kappa, rel=1e-11)  # the library's own, then kept
+    x, p_succ, steps, yn = walk.qls(b, eps=1e-3)
     assert steps == 9241
+    y = yn * x
     assert np.abs(y.imag).max() < 1e-10
     assert np.abs(y - y_ref).max() <= 1e-10 * np.abs(y_ref).max()
     x = np.linalg.solve(H, b)
@@ -85,6 +93,7 @@ def test_qls_on_the_complex_planes(Q, oracle_mod, mixed):
     walk = Q.Walk(mats, symmetric=False)
     st = walk.state([b] + [W.uniform_b(64)] * (len(mats) - 1) if mixed else b)
     assert not st.stats()["real_amplitudes"]
-    y, _, steps = walk.qls(b, kappa=kappa, eps=1e-3, j0=j0)
+    x, _, steps, yn = walk.qls(b, kappa=kappa, eps=1e-3, j0=j0)
     assert steps == 2 * j0 + 1
+    y = yn * x
     assert np.abs(y - y_ref).max() <= 1e-12 * np.abs(y_ref).max()

@@ -208,3 +208,44 @@ def test_missing_library_fails_loudly(monkeypatch, tmp_path):
     monkeypatch.setattr(_lib, "LIB_PATH", str(tmp_path / "libqw.so"))
     with pytest.raises(ImportError, match="no CPU fallback"):
         _lib.load()
+
+
+def test_failing_allocator_reports_enomem(lib):
+    """A caller's allocator that returns NULL: qw_load_csc reports QW_ENOMEM
+    (after validating the matrix on the host) and leaks nothing it could
+    free; the call neither throws nor aborts."""
+    from paper_2303_06890_amd import _lib
+
+    calls = []
+
+    def alloc(nbytes, user):
+        calls.append(int(nbytes))
+        return None
+
+    def free(p, user):
+        raise AssertionError("nothing was allocated, nothing may be freed")
+
+    a = _lib.QwAllocator(_lib.ALLOC_T(alloc), _lib.FREE_T(free), None)
+    csc = W.offset_matrix(64, 5, seed=1)
+    h = ctypes.c_void_p()
+    cp = np.ascontiguousarray(csc.colptr, np.int32)
+    ri = np.ascontiguousarray(csc.rowidx, np.int32)
+    va = np.ascontiguousarray(csc.vals, np.float64)
+    rc = lib.qw_load_csc(ctypes.byref(h), csc.n, cp.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
+                         ri.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
+                         va.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), csc.nnz, 0.0, 1, ctypes.byref(a), None)
+    assert rc == _lib.QW_ENOMEM, lib.qw_last_error().decode()
+    assert "allocation failed" in lib.qw_last_error().decode()
+    assert h.value is None and len(calls) >= 1
+
+
+def test_solver_and_kappa_argument_checks(lib):
+    """qls_run / qw_kappa reject bad arguments before touching a context."""
+    from paper_2303_06890_amd import _lib
+
+    k = ctypes.c_double()
+    assert lib.qw_kappa(None, 0, ctypes.byref(k)) == _lib.QW_EINVAL
+    b = np.ones(4)
+    bp = b.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+    assert lib.qls_run(None, bp, 10.0, 1e-3, -1, None, None, None, None, None, None) == _lib.QW_EINVAL
+    assert lib.qw_ctx_info(None, 0, None, None, None, None, ctypes.byref(k)) == _lib.QW_EINVAL
