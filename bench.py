@@ -125,18 +125,83 @@ def batched_cpu_baseline(inst, steps: int = 10, count: int = 64):
     }
 
 
-def _timed(Q, fn):
-    """GPU time (ms) of fn() on the library's stream, by HIP events."""
-    import torch
+def launch_floors(torch, launches: int = 256):
+    """Per-launch time of an empty kernel and of one coalesced kernel moving
+    about the step's bytes (4.5 MB read, 2.25 MB written; the counters
+    measure 4.25 and 2.25 MB for one step on one double per cell), each back
+    to back in a graph of `launches` launches: the floors of the step kernel
+    at 16384 x 8."""
+    out = {}
+    tiny = torch.zeros(1, device="cuda")
+    n = 2_250_000 // 8
+    src = torch.ones(2 * n, dtype=torch.float64, device="cuda")
+    dst = torch.zeros(n, dtype=torch.float64, device="cuda")
+    s = torch.cuda.Stream()
+    for name, op in (("empty_kernel_us", lambda: tiny.zero_()),
+                     ("copy_floor_us", lambda: torch.add(src[:n], src[n:], out=dst))):
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.stream(s):  # capture and replay on s, where the events are recorded
+            op()
+            torch.cuda.synchronize()
+            with torch.cuda.graph(g, stream=s):
+                for _ in range(launches):
+                    op()
+            g.replay()
+            torch.cuda.synchronize()
+            best = None
+            for _ in range(3):
+                t = _timed_on(torch, s, g.replay) * 1e3 / launches
+                best = t if best is None else min(best, t)
+        out[name] = best
+    return out
 
+
+SPACER_CYCLES = 250_000  # about 0.1 ms of GPU clock
+
+
+def _timed_on(torch, stream, fn):
+    """GPU time (ms) of the work fn() enqueues on `stream`, by HIP events on
+    that stream.  The device is synchronised first; then torch's
+    clock-counting wait kernel (a fixed number of GPU cycles, about 0.1 ms;
+    it touches no memory, so the caches keep the state) is enqueued ahead of
+    the start event, so that the host has queued fn()'s work before the GPU
+    reaches the start event: the interval between the events holds that work
+    alone, run back to back, and not the host's time to submit it."""
     e0 = torch.cuda.Event(enable_timing=True)
     e1 = torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
-    e0.record(Q.stream())
+    with torch.cuda.stream(stream):
+        torch.cuda._sleep(SPACER_CYCLES)
+    e0.record(stream)
+    t0 = time.perf_counter()
     fn()
-    e1.record(Q.stream())
+    HOST_MS.append((time.perf_counter() - t0) * 1e3)
+    e1.record(stream)
     torch.cuda.synchronize()
     return e0.elapsed_time(e1)
+
+
+HOST_MS = []  # host time of each timed call (ms), to compare with the spacer
+
+
+def spacer_ms(torch, stream):
+    """GPU time of the spacer alone (ms)."""
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record(stream)
+    with torch.cuda.stream(stream):
+        torch.cuda._sleep(SPACER_CYCLES)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1)
+
+
+def _timed(Q, fn):
+    """GPU time (ms) of fn() on the library's stream (see _timed_on)."""
+    import torch
+
+    return _timed_on(torch, Q.stream(), fn)
 
 
 def batched_leg(Q, W, autotune, tune: bool, steps: int = 50, cpu: bool = True):
@@ -456,31 +521,28 @@ def main():
         autotune.apply(st, shape)
     st.step(args.warmup)
     # One more untimed call of exactly the timed count: it captures the step
-    # graphs that the timed call replays (a replay needs its graph for the
-    # state's parity; the library steps once to reach it if needed).
+    # graph that the timed calls replay (the library keeps a graph of exactly
+    # the remainder of a call after its 256-step replays).
     st.step(args.steps)
     torch.cuda.synchronize()
-    m_in0 = st.count()
-    s0 = st.stats()
-    ev0 = torch.cuda.Event(enable_timing=True)
-    ev1 = torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
-    ev0.record(Q.stream())  # the stream the step kernels are launched on
-    st.step(args.steps)
-    ev1.record(Q.stream())
-    torch.cuda.synchronize()
-    ms = ev0.elapsed_time(ev1)
-    s1 = st.stats()
-    out_total = s1["total_written"] - s0["total_written"]
-    in_total = out_total - s1["branches"] + m_in0
-    # four more timed loops of the same count, after the reported one, for
-    # the spread (the reported figures are the first loop's)
-    repeats = [1e3 * ms / args.steps]
-    for _ in range(4):
-        repeats.append(1e3 * _timed(Q, lambda: st.step(args.steps)) / args.steps)
+    # Five timed loops of exactly K steps, each bracketed by synchronisation;
+    # the value is their median.
+    loops = []
+    del HOST_MS[:]
+    for _ in range(5):
+        m_in0 = st.count()
+        s0 = st.stats()
+        ms = _timed(Q, lambda: st.step(args.steps))
+        s1 = st.stats()
+        out_total = s1["total_written"] - s0["total_written"]
+        loops.append((ms, out_total, out_total - s1["branches"] + m_in0))
+    ms, out_total, in_total = sorted(loops)[2]
+    repeats = [1e3 * x[0] / args.steps for x in loops]
     alg_bytes = 24.0 * (in_total + out_total) + 12.0 * N * s * args.steps
     launch_s = ms / 1e3 / args.steps
     achieved = alg_bytes / args.steps / launch_s / 1e9
+    traffic = measured_traffic()
+    floors = launch_floors(torch)
     value = out_total / (ms / 1e3)
     line = {
         "metric": "walk-step amplitude updates/s (16384-dim, 8 nnz/col)",
@@ -501,26 +563,37 @@ def main():
             "N": N,
             "nnz_per_col": 8,
             "s": s,
-            "branches": s1["branches"],
-            "graph_steps_per_replay": "256, then 16, then single launches",
+            "branches": st.count(),
+            "graph_steps_per_replay": "256, then one graph of the remaining count",
             "launch_shape": list(shape) if shape else "default",
+            "timing": "median of 5 loops of exactly `steps` steps, HIP events on the kernels' stream",
+            "host_ms_per_call": HOST_MS[:5],
+            "spacer_gpu_ms": spacer_ms(torch, Q.stream()),
         },
+        # The step kernel at this size is bound by latency, not by bandwidth:
+        # the whole state sits in the 256 MB Infinity Cache and one launch
+        # costs the launch floor plus the longest chain of dependent loads,
+        # row sum and stores (`floors`: an empty kernel and a copy of the
+        # step's bytes, each back to back in a 256-launch graph).  `frac` is
+        # the algorithmic bytes of the 24 B/branch model over 8 TB/s;
+        # `counter_frac` is the bytes the counters measure over 8 TB/s.
         "roofline": {
-            "bound": "hbm",
+            "bound": "latency",
             "kernel": "step_kernel",
             "achieved": achieved,
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS,
-            "traffic": measured_traffic(),
+            "traffic": traffic,
             "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
+            "counter_frac": traffic / launch_s / 1e9 / HBM_PEAK_GBS if traffic else None,
             "alg_bytes_per_launch": alg_bytes / args.steps,
             "avg_launch_us": launch_s * 1e6,
+            "floors": floors,
         },
         "us_per_step_repeats": repeats,
-        "us_per_step_median_of_5": sorted(repeats)[2],
     }
-    print(f"[bench] {args.steps} steps in {ms:.2f} ms ({launch_s * 1e6:.2f} us/step), "
+    print(f"[bench] {args.steps} steps in {ms:.3f} ms (median of 5; {launch_s * 1e6:.2f} us/step), "
           f"{value:.3e} updates/s, {achieved:.0f} GB/s algorithmic", file=sys.stderr, flush=True)
     if not args.no_extras:
         line["batched"] = batched_leg(Q, W, autotune, not args.no_tune, cpu=not args.no_cpu_baseline)

@@ -247,9 +247,11 @@ struct qw_state {
 
 namespace {
 
-// Steps per captured graph (even: the parity is preserved).
+// Steps per captured graph of the bulk of a call (even: the parity is kept),
+// the most graphs one state keeps, and the length of the solver's graph.
 constexpr int kLongGraphSteps = 256;
-constexpr int kGraphSteps = 16;
+constexpr int kSingleMax = 32;  // calls (and remainders) of at most this many steps: single launches
+constexpr size_t kMaxGraphs = 16;
 constexpr int kSolverGraphSteps = 64;  // the solver's graph (<= one wavefront's lanes: the window)
 
 void free_graphs(qw_state* st) {
@@ -373,107 +375,156 @@ int launch_one(qw_state* st, int mode, hipStream_t stream, double2* yacc = nullp
   return QW_OK;
 }
 
-// Run `n` walk steps (with the solver's fused projection when yacc is set:
-// the k-th launch of the call adds coefm[k] times the projection), replaying
-// captured graphs when a stream is given: as many kLongGraphSteps-step
-// replays as fit, then kGraphSteps-step ones, then single launches (the
-// solver: kSolverGraphSteps-step replays).  A replay boundary costs about
-// as much as two launches, hence the long graph.  Inside the solver's graph
-// a window node ahead of the steps copies the replay's coefficients into
+// Capture `len` walk steps from the state's present parity and sign into an
+// instantiated graph (with the solver's fused projection when yacc is set: a
+// window node ahead of the steps copies the replay's coefficients into
 // st->cwin, so no step looks its coefficient up through a device-side
-// counter (a dependent load on every wavefront's path).
-int run_steps(qw_state* st, int64_t n, hipStream_t stream, double2* yacc = nullptr, const double* coefm = nullptr) {
+// counter).  Capturing runs nothing: the state is left as it was, and each
+// replay advances it by `len` steps.
+int capture_steps(qw_state* st, int len, hipStream_t stream, bool real, double2* yacc, const double* coefm,
+                  hipGraphExec_t* out) {
+  int64_t* cbase = reinterpret_cast<int64_t*>(st->cwin + kSolverGraphSteps);
+  const int cur0 = st->cur;
+  const double r1s0 = st->r1s;
+  QW_HIP(hipStreamBeginCapture(stream, hipStreamCaptureModeThreadLocal));
+  hipError_t e = hipSuccess;
+  for (int i = 0; i < len && e == hipSuccess; ++i) {
+    if (yacc && i == 0) e = qw::launch_coef_window(coefm, cbase, st->cwin, len, -1, stream);
+    const double* coef = yacc ? st->cwin + i : nullptr;
+    qw::StepArgs a = real ? step_args_real(st, yacc, coef) : step_args(st, qw::kStep, yacc, coef);
+    if (e == hipSuccess) e = qw::launch_step(a, step_grid(st), st->block, stream);
+    st->cur ^= 1;
+    st->r1s = r1s_after(qw::kStep);
+  }
+  st->cur = cur0;
+  st->r1s = r1s0;
+  hipGraph_t graph = nullptr;
+  const hipError_t ee = hipStreamEndCapture(stream, &graph);
+  if (e == hipSuccess) e = ee;
+  if (e == hipSuccess) e = hipGraphInstantiate(out, graph, nullptr, nullptr, 0);
+  if (graph) (void)hipGraphDestroy(graph);
+  if (e != hipSuccess) return set_err(QW_EDEVICE, std::string("step graph capture: ") + hipGetErrorString(e));
+  (void)hipGraphUpload(*out, stream);  // the first replay then starts as fast as the later ones
+  return QW_OK;
+}
+
+// Replay `reps` times the state's graph of `len` walk steps for its present
+// stream, parity, sign and representation, capturing it first if needed.
+// A state keeps at most kMaxGraphs graphs (the oldest goes first).
+int replay_steps(qw_state* st, int len, int64_t reps, hipStream_t stream, bool real) {
+  GraphEntry* ge = nullptr;
+  for (auto& g : st->graphs)
+    if (g.stream == stream && g.parity == st->cur && g.r1s == st->r1s && g.steps == len && g.real == real) ge = &g;
+  if (!ge) {
+    if (st->graphs.size() >= kMaxGraphs) {
+      QW_HIP(hipStreamSynchronize(stream));  // no replay of the evicted graph is still running
+      (void)hipGraphExecDestroy(st->graphs.front().exec);
+      st->graphs.erase(st->graphs.begin());
+    }
+    hipGraphExec_t exec;
+    int rc = capture_steps(st, len, stream, real, nullptr, nullptr, &exec);
+    if (rc) return rc;
+    st->graphs.push_back({stream, st->cur, st->r1s, len, real, exec});
+    ge = &st->graphs.back();
+  }
+  for (int64_t r = 0; r < reps; ++r) QW_HIP(hipGraphLaunch(ge->exec, stream));
+  st->cur ^= int((int64_t(len) * reps) & 1);
+  st->r1s = r1s_after(qw::kStep);
+  st->launches += reps * len;
+  return QW_OK;
+}
+
+// Run `n` walk steps.  On a stream, a call of more than kSingleMax steps is
+// replayed from captured graphs: as many kLongGraphSteps-step replays as
+// fit, then one graph of exactly the remaining count (single launches when
+// that is kSingleMax or fewer), each captured on first use and kept with the
+// state.  Inside a long graph a kernel follows the previous one about 0.2 us
+// sooner than a single launch does, but the start of a replay costs the GPU
+// about 10-20 us more than a launch (measured with empty kernels and with
+// the step), so short calls are single launches: as fast as a short graph
+// when the GPU idles, faster when the launches queue behind other work.  A
+// captured graph is replayed back to back, so it starts from the sign a walk
+// step leaves: a state fresh from preparation, import or the swap takes its
+// first step as a single launch, and so does a state whose long graph exists
+// only for the other parity (one launch instead of a second capture).
+int run_steps(qw_state* st, int64_t n, hipStream_t stream) {
   if (n == 0) return QW_OK;
   const bool real = real_path(st);
-  int rc0 = real ? to_real(st, stream) : to_complex(st, stream);
-  if (rc0) return rc0;
+  int rc = real ? to_real(st, stream) : to_complex(st, stream);
+  if (rc) return rc;
+  const auto one = [&]() {
+    --n;
+    return real ? launch_real(st, stream, nullptr, nullptr) : launch_one(st, qw::kStep, stream);
+  };
+  if (stream == nullptr || n <= kSingleMax) {
+    while (n > 0)
+      if ((rc = one())) return rc;
+    return QW_OK;
+  }
+  const auto have = [&](int len, int parity) {
+    for (const auto& g : st->graphs)
+      if (g.stream == stream && g.parity == parity && g.r1s == r1s_after(qw::kStep) && g.steps == len &&
+          g.real == real)
+        return true;
+    return false;
+  };
+  if (n >= 2 && st->r1s != r1s_after(qw::kStep) && (rc = one())) return rc;
+  if (n >= kLongGraphSteps) {
+    if (n > kLongGraphSteps && !have(kLongGraphSteps, st->cur) && have(kLongGraphSteps, st->cur ^ 1) &&
+        (rc = one()))
+      return rc;
+    const int64_t reps = n / kLongGraphSteps;
+    if (reps > 0) {
+      if ((rc = replay_steps(st, kLongGraphSteps, reps, stream, real))) return rc;
+      n -= reps * kLongGraphSteps;
+    }
+  }
+  if (n > kSingleMax) {
+    if ((rc = replay_steps(st, int(n), 1, stream, real))) return rc;
+    n = 0;
+  }
+  while (n > 0)
+    if ((rc = one())) return rc;
+  return QW_OK;
+}
+
+// The solver's walk: `n` steps, the k-th launch of the call adding coefm[k]
+// times the projection into yacc; kSolverGraphSteps-step graph replays
+// (captured for this call and not kept: y and the table change per solve)
+// between single launches.
+int run_solver_steps(qw_state* st, int64_t n, hipStream_t stream, double2* yacc, const double* coefm) {
+  if (n == 0) return QW_OK;
+  const bool real = real_path(st);
+  int rc = real ? to_real(st, stream) : to_complex(st, stream);
+  if (rc) return rc;
   int64_t k = 0;  // launches of this call so far
   const auto one = [&]() {
-    const double* coef = yacc ? coefm + k : nullptr;
+    const double* coef = coefm + k;
     ++k;
     --n;
     return real ? launch_real(st, stream, yacc, coef) : launch_one(st, qw::kStep, stream, yacc, coef);
   };
-  if (stream == nullptr) {
-    while (n > 0) {
-      int rc = one();
-      if (rc) return rc;
-    }
-    return QW_OK;
-  }
-  const int lens_plain[] = {kLongGraphSteps, kGraphSteps};
-  const int lens_solver[] = {kSolverGraphSteps};
-  const int* lens = yacc ? lens_solver : lens_plain;
-  const int nlens = yacc ? 1 : 2;
-  const auto cached = [&](int len, int parity) -> GraphEntry* {
-    if (yacc) return nullptr;  // the solver's graphs are not kept (y and the table change per solve)
-    for (auto& g : st->graphs)
-      if (g.stream == stream && g.parity == parity && g.r1s == r1s_after(qw::kStep) && g.steps == len &&
-          g.real == real)
-        return &g;
-    return nullptr;
-  };
-  // A captured graph is replayed back to back, so it must start from the R1
-  // sign its own steps leave: a state fresh from preparation, import or the
-  // swap takes its first step directly.  So does a state whose graphs were
-  // captured at the other parity (one launch instead of a new capture).
-  int first = 0;  // the longest graph this call replays
-  for (int li = nlens - 1; li >= 0; --li)
-    if (n > lens[li]) first = lens[li];
-  if (first > 0 && (st->r1s != r1s_after(qw::kStep) || (!cached(first, st->cur) && cached(first, st->cur ^ 1)))) {
-    int rc = one();
-    if (rc) return rc;
-  }
-  int64_t* cbase = reinterpret_cast<int64_t*>(st->cwin + kSolverGraphSteps);
-  for (int li = 0; li < nlens; ++li) {
-    const int len = lens[li];  // even: a replay leaves the parity where it was
-    const int64_t reps = n / len;
-    if (reps == 0 || st->r1s != r1s_after(qw::kStep)) continue;
-    GraphEntry* ge = cached(len, st->cur);
-    hipGraphExec_t exec = nullptr;
-    if (ge) {
-      exec = ge->exec;
-    } else {
-      hipGraph_t graph;
-      QW_HIP(hipStreamBeginCapture(stream, hipStreamCaptureModeThreadLocal));
-      const int cur0 = st->cur;
-      const double r1s0 = st->r1s;
-      for (int i = 0; i < len; ++i) {
-        hipError_t e = hipSuccess;
-        if (yacc && i == 0) e = qw::launch_coef_window(coefm, cbase, st->cwin, len, -1, stream);
-        const double* coef = yacc ? st->cwin + i : nullptr;
-        qw::StepArgs a = real ? step_args_real(st, yacc, coef) : step_args(st, qw::kStep, yacc, coef);
-        if (e == hipSuccess) e = qw::launch_step(a, step_grid(st), st->block, stream);
-        st->cur ^= 1;
-        st->r1s = r1s_after(qw::kStep);
-        if (e != hipSuccess) {
-          hipGraph_t dummy;
-          (void)hipStreamEndCapture(stream, &dummy);
-          st->cur = cur0;
-          st->r1s = r1s0;
-          return set_err(QW_EDEVICE, std::string("step capture: ") + hipGetErrorString(e));
-        }
-      }
-      QW_HIP(hipStreamEndCapture(stream, &graph));
-      hipError_t e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
-      (void)hipGraphDestroy(graph);
-      if (e != hipSuccess) return set_err(QW_EDEVICE, std::string("graph instantiate: ") + hipGetErrorString(e));
-      if (yacc == nullptr) st->graphs.push_back({stream, cur0, r1s0, len, real, exec});
-    }
-    if (yacc) QW_HIP(qw::launch_coef_window(coefm, cbase, st->cwin, len, k, stream));
-    for (int64_t r = 0; r < reps; ++r) QW_HIP(hipGraphLaunch(exec, stream));
-    st->launches += reps * len;
-    k += reps * len;
-    n -= reps * len;
-    if (yacc != nullptr) {
-      QW_HIP(hipStreamSynchronize(stream));
+  if (stream != nullptr && n > kSolverGraphSteps) {
+    if (st->r1s != r1s_after(qw::kStep) && (rc = one())) return rc;
+    const int64_t reps = n / kSolverGraphSteps;
+    if (reps > 0) {
+      hipGraphExec_t exec;
+      if ((rc = capture_steps(st, kSolverGraphSteps, stream, real, yacc, coefm, &exec))) return rc;
+      int64_t* cbase = reinterpret_cast<int64_t*>(st->cwin + kSolverGraphSteps);
+      hipError_t e = qw::launch_coef_window(coefm, cbase, st->cwin, kSolverGraphSteps, k, stream);
+      for (int64_t r = 0; r < reps && e == hipSuccess; ++r) e = hipGraphLaunch(exec, stream);
+      const hipError_t es = hipStreamSynchronize(stream);  // before the graph goes
       (void)hipGraphExecDestroy(exec);
+      if (e == hipSuccess) e = es;
+      if (e != hipSuccess) return set_err(QW_EDEVICE, std::string("solver graph: ") + hipGetErrorString(e));
+      st->launches += reps * kSolverGraphSteps;  // even: the parity is kept
+      st->r1s = r1s_after(qw::kStep);
+      k += reps * kSolverGraphSteps;
+      n -= reps * kSolverGraphSteps;
     }
   }
-  while (n > 0) {
-    int rc = one();
-    if (rc) return rc;
-  }
+  while (n > 0)
+    if ((rc = one())) return rc;
   return QW_OK;
 }
 
@@ -1471,7 +1522,7 @@ int qls_run(qw_ctx* ctx, const double* b, double kappa, double eps, int32_t j0_o
       e = hipMemcpyAsync(dcoef, coefm.data(), sizeof(double) * coefm.size(), hipMemcpyHostToDevice, stream);
     if (e == hipSuccess) e = qw::launch_fill(y, sizeof(double2) * ctx->jtotal, stream);
     if (e == hipSuccess) {
-      rc = run_steps(st, nsteps, stream, y, dcoef);
+      rc = run_solver_steps(st, nsteps, stream, y, dcoef);
       if (!rc) rc = qw_measure(st, QW_PROJECT, proj.data(), int64_t(proj.size()), stream_v);
       if (!rc) {
         e = hipMemcpyAsync(hy.data(), y, sizeof(double2) * ctx->jtotal, hipMemcpyDeviceToHost, stream);

@@ -12,6 +12,20 @@ if ROOT not in sys.path:
 def pytest_configure(config):
     config.addinivalue_line("markers", "gpu: needs an MI355X (runs through the HIP library)")
     config.addinivalue_line("markers", "slow: CPU test that takes more than a few seconds")
+    config.addinivalue_line("markers", "oracle_job(*names): needs the named background oracle runs "
+                                       "(tests/oracle_jobs.py), started once collection is done")
+
+
+def pytest_collection_finish(session):
+    """Start the oracle runs that the selected tests need, in the background."""
+    names = set()
+    for item in session.items:
+        for m in item.iter_markers("oracle_job"):
+            names.update(m.args)
+    if names:
+        from tests import oracle_jobs
+
+        oracle_jobs.start(names)
 
 
 @pytest.fixture(scope="session")

@@ -1,8 +1,9 @@
 """Long runs through the captured step graphs, against the oracle: 256-step
-and 16-step replays with the single launches around them, the one launch
-that moves a state onto the parity its graphs were captured at, each
-representation (one double per cell, complex planes, a grid-stride launch
-shape), and the solver's 64-step graph with its coefficient window."""
+replays and graphs of exactly the remaining count, with the single launches
+around them, the one launch that moves a state onto the parity its long
+graph was captured at, each representation (one double per cell, complex
+planes, a grid-stride launch shape), the bound on the graphs a state keeps,
+and the solver's 64-step graph with its coefficient window."""
 import numpy as np
 import pytest
 
@@ -35,10 +36,11 @@ def test_long_runs_match_the_oracle(Q, oracle_mod, kind):
     ost = oracle_mod.OracleState(oracle_mod.OracleMatrix(csc)).set_b(b).T()
     assert st.stats()["real_amplitudes"] == (kind != "complex")
     total = 0
-    # 600 from the T~ start: one launch, two 256-step replays, five 16-step
-    # replays, seven launches; 300 from the other parity: one launch to reach
-    # the graphs' parity, then replays; then counts around the graph lengths
-    for n in (600, 300, 17, 256, 513, 16, 2):
+    # 600 from the T~ start: one launch, two 256-step replays, one 87-step
+    # graph; 300 from the other parity: one launch to reach the long graph's
+    # parity, then a replay and a 43-step graph; then counts around the graph
+    # lengths and the single-launch limit (odd ones leave the other parity)
+    for n in (600, 300, 17, 256, 513, 16, 2, 1, 257, 33, 290):
         st.step(n)
         ost.step(n)
         total += n
@@ -61,3 +63,25 @@ def test_solver_graph_window(Q, oracle_mod):
     assert steps == 301
     y = yn * x
     assert np.abs(y - y_ref).max() <= 1e-12 * np.abs(y_ref).max()
+
+
+def test_many_step_counts_keep_a_bounded_graph_cache(Q, oracle_mod):
+    """Twenty distinct step counts above the single-launch limit, odd and
+    even, on one state (more graphs than the state keeps, so the oldest are
+    released between calls), then repeats of earlier counts (captured again
+    where released) and short calls: equal to the oracle throughout."""
+    csc, b = W.offset_matrix(128, 6, seed=61), W.gaussian_b(128, seed=62)
+    st = Q.Walk(csc).state(b)
+    ost = oracle_mod.OracleState(oracle_mod.OracleMatrix(csc)).set_b(b).T()
+    total = 0
+    # calls of more than 32 steps replay a graph of exactly their count
+    counts = list(range(34, 74, 2)) + [33, 35, 37, 39, 41] + [34, 36, 72, 33, 33, 70, 5, 1]
+    for i, n in enumerate(counts):
+        st.step(n)
+        ost.step(n)
+        total += n
+        if i % 5 == 4 or i == len(counts) - 1:
+            gk, ga = st.export()
+            ok, oa = ost.export()
+            compare_states(gk, ga, ok, oa, where=f"after {total} steps (count {n})")
+    assert st.stats()["launches"] == total
