@@ -210,8 +210,7 @@ def batched_leg(Q, W, autotune, tune: bool, steps: int = 50, cpu: bool = True):
     walk at a time on the same GPU."""
     inst = W.batched_instances()
     mats, bs = [a for a, _ in inst], [b for _, b in inst]
-    walk = Q.Walk(mats)
-    shape = autotune.tune(walk, bs) if tune else None
+    walk, shape, tune_log = autotune.tune_walk(mats, bs) if tune else (Q.Walk(mats), None, None)
     st = walk.state(bs)
     if shape:
         autotune.apply(st, shape)
@@ -256,6 +255,7 @@ def batched_leg(Q, W, autotune, tune: bool, steps: int = 50, cpu: bool = True):
             "alg_bytes_per_launch": (24.0 * (upd + upd_in) + 12.0 * slots * steps) / steps,
         },
         "launch_shape": list(shape) if shape else "default",
+        "autotune": tune_log,
         "cpu_baseline": batched_cpu_baseline(inst) if cpu else None,
     }
 
@@ -266,8 +266,7 @@ def table1_leg(Q, W, autotune, tune: bool):
     paper's single-core time per step is quoted as context only (another
     machine, another code)."""
     def run(csc, b, word):
-        walk = Q.Walk(csc, word=word)
-        shape = autotune.tune(walk, b) if tune else None
+        walk, shape, tune_log = autotune.tune_walk(csc, b, word=word) if tune else (Q.Walk(csc, word=word), None, None)
         st = walk.state(b)
         if shape:
             autotune.apply(st, shape)
@@ -282,6 +281,8 @@ def table1_leg(Q, W, autotune, tune: bool):
             "us_per_step": 1e3 * ms / steps,
             "value": upd / (ms / 1e3),
             "launch_shape": list(shape) if shape else "default",
+            "lanes_per_row": tune_log["chosen_lanes_per_row"] if tune_log else "default",
+            "autotune_tiles": tune_log["tile_choices"] if tune_log else None,
         }
         st.close()
         return res
@@ -307,8 +308,7 @@ def complex_leg(Q, W, autotune, tune: bool, steps: int = 2000):
     8 entries per column (the off-diagonal pairs v, conj(v)), uniform b."""
     csc = W.hermitian_offset_matrix(16384, 8, seed=2)
     b = W.uniform_b(16384)
-    walk = Q.Walk(csc)
-    shape = autotune.tune(walk, b) if tune else None
+    walk, shape, _ = autotune.tune_walk(csc, b) if tune else (Q.Walk(csc), None, None)
     st = walk.state(b)
     if shape:
         autotune.apply(st, shape)
@@ -403,40 +403,49 @@ def solver_leg(Q, W):
 
 def adjoint_leg(Q, W, steps: int = 20, reps: int = 5):
     """Gradient of the total probability of 32 column outcomes after 20 steps
-    on G(1024, 8) w.r.t. all 8192 values and b (forward walk + reverse sweep
-    with recomputation), against the forward walk alone."""
+    w.r.t. all stored values and b (forward walk + reverse sweep with
+    recomputation), against the forward walk alone: on G(1024, 8) (8192
+    values) and on the benchmark's G(16384, 8) (131072 values)."""
     import numpy as np
 
-    a, b, w = W.adjoint_problem()
-    sc = 1.0 / np.abs(a.vals).max()
-    a = W.Csc(a.n, a.colptr, a.rowidx, a.vals * sc)
-    walk = Q.Walk(a, scale=1.0)
+    out = {}
+    for n in (1024, 16384):
+        a, b, w = W.adjoint_problem(n)
+        sc = 1.0 / np.abs(a.vals).max()
+        a = W.Csc(a.n, a.colptr, a.rowidx, a.vals * sc)
+        walk = Q.Walk(a, scale=1.0)
 
-    def forward():
-        st = walk.state(b).step(steps)
-        st.sync()
-        return st
+        def forward():
+            st = walk.state(b).step(steps)
+            st.sync()
+            return st
 
-    def gradient():
-        st = walk.state(b).step(steps)
-        st.grad(w, steps)
+        def gradient():
+            st = walk.state(b).step(steps)
+            st.grad(w, steps)
 
-    forward(), gradient()
-    t_fwd = min(_timed(Q, forward) for _ in range(reps))
-    t_grad = min(_timed(Q, gradient) for _ in range(reps))
-    st = walk.state(b)
-    s0 = st.stats()["total_written"]
-    st.step(steps)
-    upd = st.stats()["total_written"] - s0
-    return {
-        "workload": "G(1024, 8), uniform b, 20 steps, loss over 32 outcomes, 8192 values",
-        "forward_ms": t_fwd,
-        "forward_plus_gradient_ms": t_grad,
-        "gradient_over_forward": t_grad / t_fwd,
-        "forward_updates_per_s": upd / (t_fwd / 1e3),
-        "reverse_ms_per_walk_step": (t_grad - t_fwd) / steps,
-        "note": "API calls end to end (state allocation, T~, copies and synchronisation included)",
-    }
+        forward(), gradient()
+        t_fwd = sorted(_timed(Q, forward) for _ in range(reps))[reps // 2]
+        t_grad = sorted(_timed(Q, gradient) for _ in range(reps))[reps // 2]
+        st = walk.state(b)
+        s0 = st.stats()
+        st.step(steps)
+        s1 = st.stats()
+        upd = s1["total_written"] - s0["total_written"]
+        out[f"G({n}, 8)"] = {
+            "workload": f"G({n}, 8), uniform b, {steps} steps, loss over 32 outcomes, {a.nnz} values",
+            "forward_ms": t_fwd,
+            "forward_plus_gradient_ms": t_grad,
+            "gradient_over_forward": t_grad / t_fwd,
+            "forward_updates_per_s": upd / (t_fwd / 1e3),
+            "forward_us_per_walk_step": 1e3 * t_fwd / steps,
+            "reverse_us_per_walk_step": 1e3 * (t_grad - t_fwd) / steps,
+            "reverse_over_forward_per_step": (t_grad - t_fwd) / t_fwd,
+            "real_planes": bool(s1["real_amplitudes"]),
+        }
+    out["note"] = ("API calls end to end (state allocation, T~, copies and synchronisation included; "
+                   "median of 5); reverse = (forward + gradient) - forward")
+    return out
 
 
 def main():
@@ -452,10 +461,13 @@ def main():
                     help="fixed launch shape of the main leg (workgroup size, workgroups)")
     ap.add_argument("--only", choices=["batched", "adjoint", "table1", "complex", "max_size", "solver"], default=None,
                     help="run one extra leg alone (for profiling) and print its JSON")
+    ap.add_argument("--lanes", default="0", choices=["0", "8", "16"],
+                    help="lanes per row of s >= 16 slots for the counter run of --only table1 (0: the library's rule)")
     ap.add_argument("--pmc-run", action="store_true",
                     help="counter run: a torch copy of 64 MiB (byte calibration), then 64 walk steps of "
-                         "the main workload (default launch shape unless --launch), or of the batched leg "
-                         "with --only batched; prints nothing else")
+                         "the main workload (default launch shape unless --launch), of the batched leg "
+                         "with --only batched, or of the paper's shape E with --only table1; prints "
+                         "nothing else")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on exactly one GPU: the library has no multi-GPU path "
@@ -482,6 +494,13 @@ def main():
             st.step(64)
             st.sync()
             print(json.dumps({"pmc_run": True, "copy_bytes": 8 << 23, "batched_steps": 64}), flush=True)
+            return
+        if args.only == "table1":  # counters of the paper's shape E (16384 rows, s = 64)
+            csc, b = W.table1_band("E")
+            st = Q.Walk(csc, lanes=int(args.lanes)).state(b)
+            st.step(64)
+            st.sync()
+            print(json.dumps({"pmc_run": True, "copy_bytes": 8 << 23, "shape": "E", "steps": 64}), flush=True)
             return
         csc, b = W.paper_scale()
         st = Q.Walk(csc).state(b)
@@ -510,12 +529,14 @@ def main():
         print(json.dumps(table1_leg(Q, W, autotune, not args.no_tune)), flush=True)
         return
     csc, b = W.paper_scale()
-    walk = Q.Walk(csc)
-    N, s = walk.info[0]["N"], walk.info[0]["s"]
+    tune_log = None
     if args.launch:
-        shape = tuple(int(v) for v in args.launch.split(","))
+        walk, shape = Q.Walk(csc), tuple(int(v) for v in args.launch.split(","))
+    elif args.no_tune:
+        walk, shape = Q.Walk(csc), None
     else:
-        shape = None if args.no_tune else autotune.tune(walk, b)
+        walk, shape, tune_log = autotune.tune_walk(csc, b)
+    N, s = walk.info[0]["N"], walk.info[0]["s"]
     st = walk.state(b)
     if shape:
         autotune.apply(st, shape)
@@ -566,6 +587,7 @@ def main():
             "branches": st.count(),
             "graph_steps_per_replay": "256, then one graph of the remaining count",
             "launch_shape": list(shape) if shape else "default",
+            "autotune": tune_log,
             "timing": "median of 5 loops of exactly `steps` steps, HIP events on the kernels' stream",
             "host_ms_per_call": HOST_MS[:5],
             "spacer_gpu_ms": spacer_ms(torch, Q.stream()),

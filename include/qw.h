@@ -85,6 +85,14 @@ typedef struct {
  * by the rule of the real case) and g = sin(theta).  Real matrices only. */
 #define QW_WORD_LENGTH(w) (((uint32_t)(w) & 0x3fu) << 8)
 
+/* Lanes of a step-kernel wavefront that share a row of s >= 16 slots
+ * (bits 16-17 of flags; neither: 16 when the context would have at most
+ * 1024 wavefronts with 8, else 8).  A tuning choice: results are identical,
+ * only the lane mapping of the step, adjoint and measurement kernels
+ * changes (the autotuner times both). */
+#define QW_LANES_8 (1u << 16)
+#define QW_LANES_16 (2u << 16)
+
 /* flags for qw_state_init */
 #define QW_INIT_RAW 0x1u /* start from |b~> itself instead of T~|b~> */
 
@@ -103,8 +111,9 @@ typedef struct {
                            steps then run on one double per cell whenever the
                            one-pass conditions of the step kernels hold; with
                            out_len >= 7 also [6] = the lanes of a step-kernel
-                           wavefront that share a row of s >= 16 slots (8, or
-                           16 in a context of at most 1024 wavefronts with 8) */
+                           wavefront that share a row of s >= 16 slots (8 or
+                           16: QW_LANES_8 / QW_LANES_16, or by default 16 in a
+                           context of at most 1024 wavefronts with 8) */
 
 /* Load one matrix (Sec. V.B, preprocessing list; Sec. II.C, Fig. 1):
  *   scale: > 0 multiplies every value by `scale`; 0 selects 1/max(1, max|a|).

@@ -114,9 +114,12 @@ class Walk:
     form); complex values select the Hermitian loader.  ``scale``: None
     (automatic 1/max(1, max|a|)), a float, or one float per matrix.
     ``word``: 0 for FP64 values, or the word length (1 ... 32) of fixed-point
-    data, whose rotation is then computed in fixed point."""
+    data, whose rotation is then computed in fixed point.  ``lanes``: 0 for
+    the library's rule, or 8 / 16 lanes of a step-kernel wavefront per row of
+    s >= 16 slots (a tuning choice; see autotune)."""
 
-    def __init__(self, mats, scale=None, symmetric: bool = True, torch_alloc: bool = True, word: int = 0):
+    def __init__(self, mats, scale=None, symmetric: bool = True, torch_alloc: bool = True, word: int = 0,
+                 lanes: int = 0):
         lib = _lib.load()
         self.mats = list(mats) if isinstance(mats, (list, tuple)) else [mats]
         self.ninst = len(self.mats)
@@ -136,8 +139,10 @@ class Walk:
             sc = np.broadcast_to(np.asarray(scale, np.float64), (self.ninst,)).copy()
         self._keep = (n, colptr, rowidx, vals, vim, coff, zoff, sc)
         h = ctypes.c_void_p()
-        flags = (_lib.QW_REQUIRE_SYMMETRIC if symmetric else 0) | _lib.word_length(word)
+        flags = (_lib.QW_REQUIRE_SYMMETRIC if symmetric else 0) | _lib.word_length(word) | _lib.lanes_flag(lanes)
         self.word = int(word)
+        self.lanes = int(lanes)
+        self.load_args = dict(scale=scale, symmetric=symmetric, torch_alloc=torch_alloc, word=word)
         alloc = ctypes.byref(self._alloc.struct) if self._alloc else None
         scp = _dp(sc) if sc is not None else None
         if self.complex:
@@ -291,16 +296,23 @@ class State:
 
     def grad(self, w, nsteps: int):
         """Reverse-mode gradient of sum_j w_j p_j after ``nsteps`` steps from
-        T~|b~>: returns (loss, dvals in CSC order, db complex)."""
+        T~|b~>: returns (loss, dvals in CSC order, db complex).  The library
+        copies the results into pinned host buffers (torch's pinned
+        allocator), which dvals then shares."""
+        torch = _torch()
         w = np.ascontiguousarray(w, dtype=np.float64)
         if w.shape[0] != self.walk.n_total:
             raise ValueError("w must have one weight per column of every instance")
-        dv = np.zeros(self.walk.nnz_total)
-        dbr, dbi = np.zeros(self.walk.n_total), np.zeros(self.walk.n_total)
+        dv = torch.empty(self.walk.nnz_total, dtype=torch.float64, pin_memory=True)
+        dbb = torch.empty(2 * self.walk.n_total, dtype=torch.float64, pin_memory=True)
+        dp = ctypes.POINTER(ctypes.c_double)
         loss = ctypes.c_double()
-        check(_lib.load().qw_grad(self._h, _dp(w), int(nsteps), _dp(dv), _dp(dbr), _dp(dbi), ctypes.byref(loss),
+        check(_lib.load().qw_grad(self._h, _dp(w), int(nsteps), ctypes.cast(dv.data_ptr(), dp),
+                                  ctypes.cast(dbb.data_ptr(), dp),
+                                  ctypes.cast(dbb.data_ptr() + 8 * self.walk.n_total, dp), ctypes.byref(loss),
                                   _stream()))
-        return loss.value, dv, dbr + 1j * dbi
+        db = dbb.numpy()
+        return loss.value, dv.numpy(), db[: self.walk.n_total] + 1j * db[self.walk.n_total:]
 
 
 def cks_coeffs(beta: int, j0: int) -> np.ndarray:

@@ -13,6 +13,15 @@ QW_INIT_RAW = 0x1
 QW_COUNT, QW_NORM, QW_J_MARGINAL, QW_PROJECT, QW_STATS = 1, 2, 3, 4, 5
 
 
+QW_LANES_8, QW_LANES_16 = 1 << 16, 2 << 16
+
+
+def lanes_flag(lanes: int) -> int:
+    """Load flags for the lanes that share a row of s >= 16 slots (0: the
+    library's rule)."""
+    return {0: 0, 8: QW_LANES_8, 16: QW_LANES_16}[int(lanes)]
+
+
 def word_length(w: int) -> int:
     """Load flags for fixed-point data of word length w (QW_WORD_LENGTH)."""
     return (int(w) & 0x3F) << 8

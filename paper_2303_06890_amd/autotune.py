@@ -1,11 +1,23 @@
-"""Launch-shape autotuner of the step kernel.
+"""Autotuner of the step kernel's tile and launch shape.
 
-The step kernel strides over wavefronts (each covers 64 / min(s, 8) rows,
-min(s, 8) lanes per row; 16 lanes for s >= 16 in small contexts), so its
-launch shape is free: workgroup size and number of workgroups.  `tune` times candidate shapes on a scratch state
-of the given workload (HIP events on the library's stream), keeps the fastest,
-and remembers it under (device name, padded dimensions, largest s, instance
-count, branch-count bucket), in memory and optionally in a JSON file.
+Two choices change how fast a walk step runs and never what it computes:
+
+* the tile: how many lanes of a wavefront share a row of the QRAM table
+  (8, or 16 for rows of s >= 16 slots: the QW_LANES_8 / QW_LANES_16 load
+  flags), which fixes the slots each lane holds (s / lanes) and the
+  wavefronts of a pass.  It is a property of the loaded matrix, so each
+  choice is a separate load.  (Four lanes per row, two to sixteen slots per
+  lane, measured slower than eight for every workload here: G(16384, 8),
+  the 256-instance batch and the paper's band shapes.)
+* the launch shape: workgroup size and number of workgroups.
+
+`tune_walk` loads the matrices once per tile choice that applies, times the
+launch-shape candidates of each on a scratch state (HIP events on the
+library's stream, graph-replayed steps), and returns the fastest walk, its
+launch shape and the log of every candidate.  `tune` tunes the launch shape
+of a walk already loaded.  Results are remembered under (device, padded
+dimensions, largest s, instance count, branch-count bucket, value kind,
+tile), in memory and optionally in a JSON file.
 """
 from __future__ import annotations
 
@@ -14,6 +26,8 @@ import math
 import os
 
 _cache: dict = {}
+
+TIMED_STEPS = 64  # more than a call replays as single launches: the graph path
 
 
 def _key(walk, branches: int) -> str:
@@ -24,20 +38,25 @@ def _key(walk, branches: int) -> str:
     bucket = int(math.log2(max(1, branches)))
     # the value kind selects the kernel family
     kind = "complex" if walk.complex else (f"word{walk.word}" if walk.word else "real")
-    return f"{name}|N={walk.N_total}|s={smax}|inst={walk.ninst}|m2^{bucket}|{kind}"
+    return f"{name}|N={walk.N_total}|s={smax}|inst={walk.ninst}|m2^{bucket}|{kind}|lanes={walk.lanes}"
+
+
+def lanes_per_row(walk, s: int) -> int:
+    """The lanes that share a row of s slots in the library's lane mapping:
+    min(s, 8), or 16 for s >= 16 when the walk was loaded with lanes=16, or
+    by the library's rule (lanes=0: 16 when the context has at most 1024
+    wavefronts with 8)."""
+    if s < 16:
+        return min(s, 8)
+    if walk.lanes:
+        return walk.lanes
+    waves8 = sum(-(-d["N"] // (64 // min(d["s"], 8))) for d in walk.info)
+    return 16 if 2 * waves8 <= 2048 else 8
 
 
 def _waves(walk) -> int:
-    """Wavefronts of one step-kernel pass, by the library's lane mapping:
-    min(s, 8) lanes per row, or 16 for s >= 16 when that keeps the context
-    at 2048 wavefronts or fewer."""
-    def count(lanes_of):
-        return sum(-(-d["N"] // (64 // lanes_of(d["s"]))) for d in walk.info)
-
-    waves8 = count(lambda s: min(s, 8))
-    if 2 * waves8 <= 2048:
-        return count(lambda s: 16 if s >= 16 else min(s, 8))
-    return waves8
+    """Wavefronts of one step-kernel pass under the walk's lane mapping."""
+    return sum(-(-d["N"] // (64 // lanes_per_row(walk, d["s"]))) for d in walk.info)
 
 
 def candidates(walk):
@@ -52,45 +71,100 @@ def candidates(walk):
     return out
 
 
-def tune(walk, b, steps: int = 32, warm: int = 16, cache_path: str | None = None, verbose: bool = False):
-    """Return the fastest (wg_size, grid) for stepping `walk` from T~|b~>."""
+def _time_shapes(walk, b, warm: int = 16, steps: int = TIMED_STEPS, verbose: bool = False):
+    """[(us per step, (wg, grid))] for every candidate launch shape, and the
+    branch count of the scratch state."""
     import torch
 
     from . import stream
 
     st = walk.state(b).step(warm)
-    key = _key(walk, st.count())
-    if key not in _cache and cache_path and os.path.exists(cache_path):
-        with open(cache_path) as f:
-            _cache.update(json.load(f))
-    if key in _cache:
-        st.close()
-        return tuple(_cache[key])
-    best, best_t = None, math.inf
+    branches = st.count()
+    out = []
     for wg, grid in candidates(walk):
         st.set_launch(wg, grid)
-        st.step(steps)  # warm the captured graph for this shape
+        st.step(steps)  # captures the graph for this shape
         e0 = torch.cuda.Event(enable_timing=True)
         e1 = torch.cuda.Event(enable_timing=True)
         e0.record(stream())
         st.step(steps)
         e1.record(stream())
         e1.synchronize()
-        t = e0.elapsed_time(e1) / steps
+        t = e0.elapsed_time(e1) * 1e3 / steps
         if verbose:
-            print(f"[autotune] wg={wg:4d} grid={grid:5d}: {t * 1e3:8.2f} us/step")
-        if t < best_t:
-            best, best_t = (wg, grid), t
+            print(f"[autotune] lanes={walk.lanes} wg={wg:4d} grid={grid:5d}: {t:8.3f} us/step")
+        out.append((t, (wg, grid)))
     st.close()
-    _cache[key] = list(best)
+    return out, branches
+
+
+def _load_cache(cache_path):
+    if cache_path and os.path.exists(cache_path):
+        with open(cache_path) as f:
+            _cache.update(json.load(f))
+
+
+def _save_cache(cache_path):
     if cache_path:
         with open(cache_path, "w") as f:
             json.dump(_cache, f, indent=1)
-    return best
+
+
+def tune(walk, b, cache_path: str | None = None, verbose: bool = False):
+    """Return the fastest (wg_size, grid) for stepping `walk` from T~|b~>."""
+    _load_cache(cache_path)
+    st = walk.state(b).step(16)
+    key = _key(walk, st.count())
+    st.close()
+    if key not in _cache:
+        times, _ = _time_shapes(walk, b, verbose=verbose)
+        _cache[key] = [list(min(times)[1]), min(times)[0]]
+        _save_cache(cache_path)
+    return tuple(_cache[key][0])
+
+
+def _smax(mats) -> int:
+    """Largest QRAM row length s over the matrices (the power of two at or
+    above the largest column count)."""
+    import numpy as np
+
+    mats = list(mats) if isinstance(mats, (list, tuple)) else [mats]
+    return max(1 << int(math.ceil(math.log2(max(1, int(np.diff(np.asarray(m.colptr)).max()))))) for m in mats)
+
+
+def tune_walk(mats, b, verbose: bool = False, **walk_kwargs):
+    """Load `mats` with each tile choice that applies (8 and 16 lanes per row
+    when some row has s >= 16 slots, else the one mapping there is), tune the
+    launch shape of each, and return (walk, (wg, grid), log): the fastest
+    walk (the others are released), its launch shape, and a log of every
+    candidate timed, for the record of the run."""
+    from . import Walk
+
+    choices = [8, 16] if _smax(mats) >= 16 else [0]
+    log = {"tile_choices": [], "launch_candidates": []}
+    best = None
+    for lanes in choices:
+        walk = Walk(mats, lanes=lanes, **walk_kwargs)
+        times, _ = _time_shapes(walk, b, verbose=verbose)
+        t, shape = min(times)
+        lpr = sorted({lanes_per_row(walk, d["s"]) for d in walk.info})
+        log["tile_choices"].append({"lanes_per_row": lpr, "wavefronts": _waves(walk), "best_us_per_step": t,
+                                    "best_launch": list(shape)})
+        log["launch_candidates"] += [{"lanes_per_row": lpr, "wg": s[0], "grid": s[1], "us_per_step": u}
+                                     for u, s in times]
+        if best is None or t < best[0]:
+            if best is not None:
+                best[1].close()
+            best = (t, walk, shape, lpr)
+        else:
+            walk.close()
+    t, walk, shape, lpr = best
+    log.update(chosen_lanes_per_row=lpr, chosen_launch=list(shape), chosen_us_per_step=t)
+    return walk, shape, log
 
 
 def apply(state, shape) -> None:
     state.set_launch(int(shape[0]), int(shape[1]))
 
 
-__all__ = ["tune", "apply", "candidates"]
+__all__ = ["tune", "tune_walk", "apply", "candidates", "lanes_per_row"]

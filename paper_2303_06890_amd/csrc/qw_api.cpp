@@ -141,6 +141,10 @@ struct qw_ctx {
   int64_t nnz_total = 0;
   std::vector<HostInst> inst;
   std::vector<int64_t> csc_home;  // home of every CSC entry's slot
+  // The same on the device (int32: homes < 2^31), and the N-vector index of
+  // every unpadded column, for the gradient's gathers into CSC order.
+  int32_t* dcsc_home = nullptr;
+  int32_t* dcol_row = nullptr;
   // Host copy of the QRAM table (row-major col/val as on the device, the
   // imaginary parts by home), kept for the condition number.
   std::vector<int32_t> hcol;
@@ -162,6 +166,8 @@ struct qw_ctx {
   int32_t word = 0;               // fixed-point word length (0: FP64 values)
   // every slot of value 0 has a partner of value 0 or none (see StepArgs::zskip)
   bool zclosed = true;
+  // some slot has no partner (its S K(q, 0) branch lives in a Q0 cell; see StepArgs::q0)
+  bool q0 = false;
   // a real matrix whose slots of negative value have partners of negative
   // value: from a real b every cell is real or imaginary (see StepArgs::real)
   bool realsym = true;
@@ -292,6 +298,7 @@ qw::StepArgs step_args(qw_state* st, int mode, double2* yacc, const double* coef
   a.coef = coef;
   a.zskip = st->ctx->zclosed && st->zclean ? 1 : 0;
   a.real = 0;
+  a.q0 = st->ctx->q0 ? 1 : 0;
   return a;
 }
 
@@ -672,6 +679,18 @@ bool negative_slots_paired(const HostInst& hi, const Ell& ell) {
   return true;
 }
 
+// Whether every slot (j, l) has a partner: j appears in row col[j, l].
+bool every_slot_paired(const HostInst& hi, const Ell& ell) {
+  for (int32_t j = 0; j < hi.N; ++j)
+    for (int l = 0; l < hi.s; ++l) {
+      const int32_t c = ell.col[size_t(j) * hi.s + l];
+      const int32_t* row = ell.col.data() + size_t(c) * hi.s;
+      const int32_t* f = std::lower_bound(row, row + hi.s, j);
+      if (f == row + hi.s || *f != j) return false;
+    }
+  return true;
+}
+
 // Whether every slot of value 0 (a filler, or a stored zero) has a partner of
 // value 0 or none.  Then, from T~ |b~> on, the R0 and Q0 cells of these slots
 // stay 0: T~ puts b_j f / sqrt(s) = 0 there, and a step moves such a cell only
@@ -707,6 +726,8 @@ void ctx_release(qw_ctx* ctx) {
   ctx->alloc.put(ctx->vim);
   ctx->alloc.put(ctx->dinst);
   ctx->alloc.put(ctx->wave_inst);
+  ctx->alloc.put(ctx->dcsc_home);
+  ctx->alloc.put(ctx->dcol_row);
   for (const auto& e : ctx->pool) ctx->alloc.put(e.second);
   delete ctx;
 }
@@ -718,6 +739,8 @@ int load_impl(qw_ctx** out, int32_t ninst, const int32_t* n, const int64_t* colp
   *out = nullptr;
   if (ninst <= 0 || !n || !colptr || !rowidx || !vals) return set_err(QW_EINVAL, "missing matrix arrays");
   const int32_t word = int32_t((flags >> 8) & 0x3fu);
+  const uint32_t lanes = (flags >> 16) & 0x3u;  // 0: the rule below; 1: 8 lanes per row; 2: 16
+  if (lanes == 3) return set_err(QW_EINVAL, "lanes per row: QW_LANES_8 or QW_LANES_16, not both");
   if (word > 32) return set_err(QW_EINVAL, "word length must be 1 ... 32 (0: FP64 values)");
   if (word > 0 && vals_im) return set_err(QW_ENOTSUP, "fixed-point data is provided for real matrices only");
   hipStream_t stream = static_cast<hipStream_t>(stream_v);
@@ -749,6 +772,7 @@ int load_impl(qw_ctx** out, int32_t ninst, const int32_t* n, const int64_t* colp
                         scales ? scales[i] : 0.0, flags, hi, ell, slot_of);
     if (rc == QW_OK && word > 0) rc = fixed_point_angles(word, ell.val);
     if (rc == QW_OK) ctx->zclosed = ctx->zclosed && zero_slots_closed(hi, ell);
+    if (rc == QW_OK) ctx->q0 = ctx->q0 || !every_slot_paired(hi, ell);
     if (rc == QW_OK) ctx->realsym = ctx->realsym && !vals_im && negative_slots_paired(hi, ell);
     if (rc) {
       prefix_err("instance " + std::to_string(i) + ": ");
@@ -796,12 +820,14 @@ int load_impl(qw_ctx** out, int32_t ninst, const int32_t* n, const int64_t* colp
   // 16 lanes per row instead (at most twice the wavefronts, half the slots
   // per lane): the shapes of 1024 to 8192 rows with s = 16 or 32 step 7-25 %
   // faster so, while 16384 rows with s = 64 (2048 wavefronts) step slower.
+  // The load flags QW_LANES_8 / QW_LANES_16 replace the rule (the autotuner
+  // times both).
   int64_t waves8 = 0;
   for (int32_t i = 0; i < ninst; ++i) {
     const int rpw_log = 6 - std::min(ctx->inst[i].hbits, 3);
     waves8 += (int64_t(ctx->inst[i].N) + (int64_t(1) << rpw_log) - 1) >> rpw_log;
   }
-  ctx->wide = 2 * waves8 <= qw::kWideWaves ? 1 : 0;
+  ctx->wide = lanes == 2 ? 1 : lanes == 1 ? 0 : (2 * waves8 <= qw::kWideWaves ? 1 : 0);
   std::vector<qw::Inst> dinst(ninst);
   int64_t waves = 0;
   for (int32_t i = 0; i < ninst; ++i) {
@@ -857,6 +883,17 @@ int load_impl(qw_ctx** out, int32_t ninst, const int32_t* n, const int64_t* colp
     e = hipMemcpyAsync(ctx->vim, hvim.data(), sizeof(double) * items, hipMemcpyHostToDevice, stream);
   if (e == hipSuccess)
     e = hipMemcpyAsync(ctx->wave_inst, hwave.data(), sizeof(int32_t) * waves, hipMemcpyHostToDevice, stream);
+  std::vector<int32_t> hhome(ctx->csc_home.begin(), ctx->csc_home.end());
+  std::vector<int32_t> hrow;
+  for (int32_t i = 0; i < ninst; ++i)
+    for (int32_t j = 0; j < ctx->inst[i].n; ++j) hrow.push_back(int32_t(ctx->inst[i].jbase + j));
+  ctx->dcsc_home = static_cast<int32_t*>(ctx->alloc.get(sizeof(int32_t) * std::max<size_t>(1, hhome.size())));
+  ctx->dcol_row = static_cast<int32_t*>(ctx->alloc.get(sizeof(int32_t) * std::max<size_t>(1, hrow.size())));
+  if (e == hipSuccess && (!ctx->dcsc_home || !ctx->dcol_row)) e = hipErrorOutOfMemory;
+  if (e == hipSuccess && !hhome.empty())
+    e = hipMemcpyAsync(ctx->dcsc_home, hhome.data(), sizeof(int32_t) * hhome.size(), hipMemcpyHostToDevice, stream);
+  if (e == hipSuccess && !hrow.empty())
+    e = hipMemcpyAsync(ctx->dcol_row, hrow.data(), sizeof(int32_t) * hrow.size(), hipMemcpyHostToDevice, stream);
   // O_s'^-1 of every reflected output: the QBS of j in row col[q], once per matrix
   if (e == hipSuccess) e = qw::launch_fill(ctx->rec, int64_t(sizeof(qw::SlotRec)) * items, stream);
   if (e == hipSuccess) e = qw::launch_fill(ctx->slink, int64_t(sizeof(uint32_t)) * items, stream);
@@ -865,7 +902,8 @@ int load_impl(qw_ctx** out, int32_t ninst, const int32_t* n, const int64_t* colp
   if (e == hipSuccess) e = hipStreamSynchronize(stream);  // host vectors go out of scope
   if (e != hipSuccess) {
     ctx_release(ctx);
-    return set_err(QW_EDEVICE, std::string("matrix upload: ") + hipGetErrorString(e));
+    return set_err(e == hipErrorOutOfMemory ? QW_ENOMEM : QW_EDEVICE,
+                   std::string("matrix upload: ") + hipGetErrorString(e));
   }
   ctx->hcol.swap(hcol);
   ctx->hval.swap(hval);
@@ -998,6 +1036,38 @@ int state_clear(qw_state* st, hipStream_t stream) {
   st->cur = 0;
   st->r1s = 1.0;
   st->L.cnt = 0;
+  return QW_OK;
+}
+
+// A state of the 8-byte planes only (the gradient's adjoint state on its
+// real path): both parity buffers cleared, no counts, no list.
+int state_alloc_real(qw_ctx* ctx, qw_state** out, hipStream_t stream) {
+  qw_state* st = new qw_state;
+  st->ctx = ctx;
+  ctx->refs.fetch_add(1);
+  st->counts = false;
+  st->real_ok = true;
+  st->in_real = true;
+  const int64_t bytes = int64_t(sizeof(double)) * 3 * ctx->items;
+  for (int k = 0; k < 2; ++k) {
+    st->rbuf[k] = static_cast<double*>(state_get_paged(st, size_t(bytes)));
+    hipError_t e = st->rbuf[k] ? qw::launch_fill(st->rbuf[k], bytes, stream) : hipErrorOutOfMemory;
+    if (e != hipSuccess) {
+      qw_state_free(st);
+      return set_err(e == hipErrorOutOfMemory ? QW_ENOMEM : QW_EDEVICE, "device allocation failed for the real planes");
+    }
+  }
+  *out = st;
+  return QW_OK;
+}
+
+// The swap S of a state on the 8-byte planes.
+int swap_real(qw_state* st, hipStream_t stream) {
+  QW_HIP(qw::launch_swap_real(st->ctx->mat(), rview(st, st->cur, st->r1s), rview(st, st->cur ^ 1, r1s_after(qw::kSwap)),
+                              st->counts ? st->acc : nullptr, stream));
+  st->cur ^= 1;
+  st->r1s = r1s_after(qw::kSwap);
+  ++st->launches;
   return QW_OK;
 }
 
@@ -1152,6 +1222,118 @@ void cks_coefficients(int64_t beta, int32_t j0, double* out) {
     const long double tail = (k + 1 <= imax) ? suf[k + 1] : 0.0L;
     out[k] = double(((k & 1) ? -4.0L : 4.0L) * tail);
   }
+}
+
+// Argument checks of qw_grad.
+int grad_check(qw_state* st, const double* w, int32_t nsteps) {
+  if (!st || !w) return set_err(QW_EINVAL, "missing argument");
+  if (!st->prepared || st->steps_since_init != nsteps)
+    return set_err(QW_EINVAL, "qw_grad needs the state made by qw_state_init (T~ start) advanced by exactly nsteps");
+  if (st->ctx->complex_values) return set_err(QW_ENOTSUP, "the gradient is provided for real matrices only");
+  if (st->ctx->word > 0)
+    return set_err(QW_ENOTSUP, "the gradient is provided for FP64 values only, not fixed-point data");
+  return QW_OK;
+}
+
+// Device buffers of one gradient sweep: the weights (N-vector layout, padding
+// rows 0), dL/dv by home, dL/db, and the results in the caller's order.
+struct GradBufs {
+  double* dw = nullptr;
+  double* dv = nullptr;
+  double2* db = nullptr;
+  double* dg = nullptr;
+};
+
+// The reverse sweep of the gradient, on the state st (advanced by nsteps from
+// T~|b~>) and the adjoint state lam (its planes cleared; on the 8-byte planes
+// when `real`, where st is too), with dw holding the weights:
+//   Psi_n = S psi_n and Lambda_n = diag(w[k]) Psi_n; nsteps reverse steps
+//   (the recomputed state and the adjoint state advance together, dL/dv
+//   accumulates); back through S; the gradient through the initial T~;
+//   the results gathered into the caller's order and copied out.
+// Synchronises the stream; the state is left holding the recomputed T~|b~>.
+int grad_sweep(qw_state* st, qw_state* lam, bool real, const GradBufs& gb, int32_t nsteps, double* dvals,
+               double* db_re, double* db_im, double* loss, hipStream_t stream) {
+  qw_ctx* ctx = st->ctx;
+  const qw::Matrix mm = ctx->mat();
+  double part[256];
+  int rc = QW_OK;
+  hipError_t e = qw::launch_fill(gb.dv, (sizeof(double) * ctx->items + 15) / 16 * 16, stream);
+  if (e == hipSuccess && real) {
+    rc = swap_real(st, stream);
+    if (!rc)
+      e = qw::launch_weight_real(mm, rview(st, st->cur, st->r1s), rview(lam, lam->cur, lam->r1s), gb.dw, st->mbuf,
+                                 256, stream);
+  } else if (e == hipSuccess) {
+    rc = launch_one(st, qw::kSwap, stream);
+    if (!rc) e = qw::launch_weight(mm, view(st), st->L, view(lam), lam->L, gb.dw, st->mbuf, 256, stream);
+  }
+  if (e == hipSuccess && !rc) e = hipMemcpyAsync(part, st->mbuf, sizeof(part), hipMemcpyDeviceToHost, stream);
+  for (int32_t t = nsteps; t >= 1 && e == hipSuccess && !rc; --t) {
+    qw::AdjArgs a;
+    a.m = mm;
+    if (real) {
+      a.in = rview(st, st->cur, st->r1s);
+      a.out = rview(st, st->cur ^ 1, r1s_after(qw::kStep));
+      a.lin = rview(lam, lam->cur, lam->r1s);
+      a.lout = rview(lam, lam->cur ^ 1, r1s_after(qw::kStep));
+    } else {
+      a.in = view(st);
+      a.out = view(st, st->cur ^ 1, r1s_after(qw::kStep));
+      a.lin = view(lam);
+      a.lout = view(lam, lam->cur ^ 1, r1s_after(qw::kStep));
+    }
+    a.L = st->L;
+    a.LL = lam->L;
+    a.acc = st->counts ? st->acc : nullptr;
+    a.lacc = lam->acc;
+    a.tau = qw::kTau;
+    a.dv = gb.dv;
+    a.wpb = 0;  // set by the launcher
+    a.real = real ? 1 : 0;
+    a.q0 = ctx->q0 ? 1 : 0;
+    e = qw::launch_adjoint(a, step_grid(st), st->block, stream);
+    st->cur ^= 1;
+    lam->cur ^= 1;
+    st->r1s = lam->r1s = r1s_after(qw::kStep);
+    ++st->launches;
+  }
+  // back to the unconjugated frame: psi_0 and lambda_0, then the finish
+  if (e == hipSuccess && !rc && real) {
+    rc = swap_real(st, stream);
+    if (!rc) rc = swap_real(lam, stream);
+    if (!rc) e = qw::launch_grad_init_real(mm, rview(lam, lam->cur, lam->r1s), st->b, gb.dv, gb.db, stream);
+  } else if (e == hipSuccess && !rc) {
+    rc = launch_one(st, qw::kSwap, stream);
+    if (!rc) rc = launch_one(lam, qw::kSwap, stream);
+    if (!rc) e = qw::launch_grad_init(mm, view(lam), st->b, gb.dv, gb.db, stream);
+  }
+  // the results in the caller's order (CSC entries; b's columns, real and
+  // imaginary parts), gathered on the device and copied straight out
+  double* gv = gb.dg;
+  double* gbr = gb.dg + ctx->nnz_total;
+  double* gbi = gbr + ctx->ntotal;
+  if (e == hipSuccess && !rc)
+    e = qw::launch_gather_grad(gb.dv, ctx->dcsc_home, ctx->nnz_total, gb.db, ctx->dcol_row, ctx->ntotal, gv, gbr, gbi,
+                               stream);
+  if (e == hipSuccess && !rc && dvals)
+    e = hipMemcpyAsync(dvals, gv, sizeof(double) * ctx->nnz_total, hipMemcpyDeviceToHost, stream);
+  if (e == hipSuccess && !rc && db_re)
+    e = hipMemcpyAsync(db_re, gbr, sizeof(double) * ctx->ntotal, hipMemcpyDeviceToHost, stream);
+  if (e == hipSuccess && !rc && db_im)
+    e = hipMemcpyAsync(db_im, gbi, sizeof(double) * ctx->ntotal, hipMemcpyDeviceToHost, stream);
+  if (e == hipSuccess && !rc) e = hipStreamSynchronize(stream);
+  (void)hipStreamSynchronize(stream);
+  st->steps_since_init = 0;
+  if (e != hipSuccess)
+    return set_err(e == hipErrorOutOfMemory ? QW_ENOMEM : QW_EDEVICE, std::string("gradient: ") + hipGetErrorString(e));
+  if (rc) return rc;
+  if (loss) {
+    double L = 0.0;
+    for (double v : part) L += v;
+    *loss = L;
+  }
+  return QW_OK;
 }
 
 }  // namespace
@@ -1559,95 +1741,41 @@ int qls_run(qw_ctx* ctx, const double* b, double kappa, double eps, int32_t j0_o
 int qw_grad(qw_state* st, const double* w, int32_t nsteps, double* dvals, double* db_re, double* db_im,
             double* loss, void* stream_v) {
   return guarded([&]() -> int {
-    if (!st || !w) return set_err(QW_EINVAL, "missing argument");
-    if (!st->prepared || st->steps_since_init != nsteps)
-      return set_err(QW_EINVAL, "qw_grad needs the state made by qw_state_init (T~ start) advanced by exactly nsteps");
-    if (st->ctx->complex_values)
-      return set_err(QW_ENOTSUP, "the gradient is provided for real matrices only");
-    if (st->ctx->word > 0)
-      return set_err(QW_ENOTSUP, "the gradient is provided for FP64 values only, not fixed-point data");
+    int rc = grad_check(st, w, nsteps);
+    if (rc) return rc;
     hipStream_t stream = static_cast<hipStream_t>(stream_v);
-    int rc0 = to_complex(st, stream);
-    if (rc0) return rc0;
+    const bool real = real_path(st);
+    rc = real ? to_real(st, stream) : to_complex(st, stream);
+    if (rc) return rc;
     qw_ctx* ctx = st->ctx;
     std::vector<double> hw(static_cast<size_t>(ctx->jtotal), 0.0);
     int64_t src = 0;
     for (int32_t i = 0; i < ctx->ninst; ++i)
       for (int32_t j = 0; j < ctx->inst[i].n; ++j, ++src) hw[size_t(ctx->inst[i].jbase + j)] = w[src];
     qw_state* lam = nullptr;
-    int rc = state_alloc(ctx, st->L.cap, &lam, stream);
+    rc = real ? state_alloc_real(ctx, &lam, stream) : state_alloc(ctx, st->L.cap, &lam, stream);
     if (rc) return rc;
     lam->L.cnt = st->L.cnt;
-    double* dw = static_cast<double*>(ctx_take(ctx, sizeof(double) * ctx->jtotal));
-    double* dv = static_cast<double*>(ctx_take(ctx, sizeof(double) * ctx->items));
-    double2* db = static_cast<double2*>(ctx_take(ctx, sizeof(double2) * ctx->jtotal));
-    std::vector<double> hdv(static_cast<size_t>(ctx->items));
-    std::vector<double2> hdb(static_cast<size_t>(ctx->jtotal));
-    std::vector<double> part(256);
-    hipError_t e = (dw && dv && db) ? hipSuccess : hipErrorOutOfMemory;
-    const qw::Matrix mm = ctx->mat();
-    if (e == hipSuccess) e = hipMemcpyAsync(dw, hw.data(), sizeof(double) * ctx->jtotal, hipMemcpyHostToDevice, stream);
-    if (e == hipSuccess) e = qw::launch_fill(dv, (sizeof(double) * ctx->items + 15) / 16 * 16, stream);
-    // Psi_n = S psi_n, Lambda_n = diag(w[k]) Psi_n
-    if (e == hipSuccess) {
-      rc = launch_one(st, qw::kSwap, stream);
-      if (!rc)
-        e = qw::launch_weight(mm, view(st), st->L, view(lam), lam->L, dw, st->mbuf, 256, stream);
-    }
-    if (e == hipSuccess && !rc)
-      e = hipMemcpyAsync(part.data(), st->mbuf, sizeof(double) * 256, hipMemcpyDeviceToHost, stream);
-    for (int32_t t = nsteps; t >= 1 && e == hipSuccess && !rc; --t) {
-      qw::AdjArgs a;
-      a.m = mm;
-      a.in = view(st);
-      a.out = view(st, st->cur ^ 1, r1s_after(qw::kStep));
-      a.lin = view(lam);
-      a.lout = view(lam, lam->cur ^ 1, r1s_after(qw::kStep));
-      a.L = st->L;
-      a.LL = lam->L;
-      a.acc = st->acc;
-      a.lacc = lam->acc;
-      a.tau = qw::kTau;
-      a.dv = dv;
-      e = qw::launch_adjoint(a, step_grid(st), st->block, stream);
-      st->cur ^= 1;
-      lam->cur ^= 1;
-      st->r1s = lam->r1s = r1s_after(qw::kStep);
-      ++st->launches;
-    }
-    // back to the unconjugated frame: psi_0 and lambda_0
-    if (e == hipSuccess && !rc) rc = launch_one(st, qw::kSwap, stream);
-    if (e == hipSuccess && !rc) rc = launch_one(lam, qw::kSwap, stream);
-    if (e == hipSuccess && !rc) e = qw::launch_grad_init(mm, view(lam), st->b, dv, db, stream);
-    if (e == hipSuccess && !rc)
-      e = hipMemcpyAsync(hdv.data(), dv, sizeof(double) * ctx->items, hipMemcpyDeviceToHost, stream);
-    if (e == hipSuccess && !rc)
-      e = hipMemcpyAsync(hdb.data(), db, sizeof(double2) * ctx->jtotal, hipMemcpyDeviceToHost, stream);
-    if (e == hipSuccess && !rc) e = hipStreamSynchronize(stream);
+    GradBufs gb;
+    gb.dw = static_cast<double*>(ctx_take(ctx, sizeof(double) * ctx->jtotal));
+    gb.dv = static_cast<double*>(ctx_take(ctx, sizeof(double) * ctx->items));
+    gb.db = static_cast<double2*>(ctx_take(ctx, sizeof(double2) * ctx->jtotal));
+    const size_t gbytes = sizeof(double) * size_t(ctx->nnz_total + 2 * ctx->ntotal);
+    gb.dg = static_cast<double*>(ctx_take(ctx, gbytes));
+    hipError_t e = (gb.dw && gb.dv && gb.db && gb.dg) ? hipSuccess : hipErrorOutOfMemory;
+    if (e == hipSuccess)
+      e = hipMemcpyAsync(gb.dw, hw.data(), sizeof(double) * ctx->jtotal, hipMemcpyHostToDevice, stream);
+    if (e == hipSuccess)
+      rc = grad_sweep(st, lam, real, gb, nsteps, dvals, db_re, db_im, loss, stream);
     (void)hipStreamSynchronize(stream);  // after an error too: nothing may still use the buffers
-    if (dw) ctx_give(ctx, dw, sizeof(double) * ctx->jtotal);
-    if (dv) ctx_give(ctx, dv, sizeof(double) * ctx->items);
-    if (db) ctx_give(ctx, db, sizeof(double2) * ctx->jtotal);
+    if (gb.dw) ctx_give(ctx, gb.dw, sizeof(double) * ctx->jtotal);
+    if (gb.dv) ctx_give(ctx, gb.dv, sizeof(double) * ctx->items);
+    if (gb.db) ctx_give(ctx, gb.db, sizeof(double2) * ctx->jtotal);
+    if (gb.dg) ctx_give(ctx, gb.dg, gbytes);
     qw_state_free(lam);
-    st->steps_since_init = 0;
     if (e != hipSuccess)
       return set_err(e == hipErrorOutOfMemory ? QW_ENOMEM : QW_EDEVICE, std::string("gradient: ") + hipGetErrorString(e));
-    if (rc) return rc;
-    if (loss) {
-      double L = 0.0;
-      for (double v : part) L += v;
-      *loss = L;
-    }
-    if (dvals)
-      for (size_t p = 0; p < ctx->csc_home.size(); ++p) dvals[p] = hdv[size_t(ctx->csc_home[p])];
-    src = 0;
-    for (int32_t i = 0; i < ctx->ninst; ++i)
-      for (int32_t j = 0; j < ctx->inst[i].n; ++j, ++src) {
-        const double2 g = hdb[size_t(ctx->inst[i].jbase + j)];
-        if (db_re) db_re[src] = g.x;
-        if (db_im) db_im[src] = g.y;
-      }
-    return QW_OK;
+    return rc;
   });
 }
 

@@ -131,6 +131,10 @@ struct StepArgs {
   // cells of slots of negative value); the plane pointers of in/out point at
   // double arrays (the qwk_step_r / qwk_step_t kernels)
   int32_t real;
+  // 1: some slot has no partner (Matrix::q0): the launcher takes the real
+  // kernels' _q forms, which read Q0 of such slots with the other loads
+  // (step_wave_real's EQ0); the kernels do not read it
+  int32_t q0;
 };
 
 struct AdjArgs {
@@ -143,7 +147,10 @@ struct AdjArgs {
   double tau;
   double* dv;       // gradient per slot (by home), accumulated
   int32_t wpb;      // wavefronts per workgroup (set by the launcher)
-  int32_t pad_;
+  // 1: both states on one double per cell (the plane pointers point at
+  // double arrays; the qwk_adjoint_r kernels: one pass, empty lists)
+  int32_t real;
+  int32_t q0;  // as StepArgs::q0
 };
 
 // The host side is compiled by the host compiler and the kernels by the GPU
@@ -153,8 +160,10 @@ static_assert(sizeof(Slots) == 40 && offsetof(Slots, r1s) == 32, "Slots layout")
 static_assert(sizeof(List) == 24 && offsetof(List, cap) == 20, "List layout");
 static_assert(sizeof(SlotRec) == 16 && offsetof(SlotRec, val) == 8, "SlotRec layout");
 static_assert(sizeof(Matrix) == 176 && offsetof(Matrix, inst0) == 120, "Matrix layout");
-static_assert(sizeof(StepArgs) == 328 && offsetof(StepArgs, zskip) == 320, "StepArgs layout");
-static_assert(sizeof(AdjArgs) == 424 && offsetof(AdjArgs, wpb) == 416, "AdjArgs layout");
+static_assert(sizeof(StepArgs) == 336 && offsetof(StepArgs, zskip) == 320 && offsetof(StepArgs, q0) == 328,
+              "StepArgs layout");
+static_assert(sizeof(AdjArgs) == 432 && offsetof(AdjArgs, wpb) == 416 && offsetof(AdjArgs, q0) == 424,
+              "AdjArgs layout");
 
 // Launchers (qw_launch.cpp).  All enqueue on `stream` and allocate nothing.
 hipError_t launch_step(const StepArgs& a, int grid, int block, hipStream_t stream);
@@ -191,5 +200,17 @@ hipError_t launch_weight(const Matrix& m, Slots in, List L, Slots out, List LL, 
                          int grid, hipStream_t stream);
 hipError_t launch_grad_init(const Matrix& m, Slots lam, const double2* b, double* dv, double2* db,
                             hipStream_t stream);
+// The same three on one double per cell (the plane pointers point at double
+// arrays): the swap S (counted into acc unless NULL), the weighting, and the
+// gradient through the initial T~ for a real b.
+hipError_t launch_swap_real(const Matrix& m, Slots in, Slots out, unsigned long long* acc, hipStream_t stream);
+hipError_t launch_weight_real(const Matrix& m, Slots in, Slots out, const double* w, double* partial, int grid,
+                              hipStream_t stream);
+hipError_t launch_grad_init_real(const Matrix& m, Slots lam, const double2* b, double* dv, double2* db,
+                                 hipStream_t stream);
+// gv[p] = dv[home[p]] (p < nnz) and br/bi[p] = db[row[p]] (p < n).
+hipError_t launch_gather_grad(const double* dv, const int32_t* home, int64_t nnz, const double2* db,
+                              const int32_t* row, int64_t n, double* gv, double* br, double* bi,
+                              hipStream_t stream);
 
 }  // namespace qw

@@ -179,6 +179,14 @@ __device__ __forceinline__ double2 row_sum(double2 v, int rpw_log) {
 
 __device__ __forceinline__ int uniform(int v) { return __builtin_amdgcn_readfirstlane(v); }
 
+// 2/s of the reflection 2 |phi><phi| - 1 (phi carries 1/sqrt(s) per entry):
+// a constant for a compile-time s, else one ldexp (s = 2^hbits, so both are
+// exact); a division here sat on every wavefront's path after the row sum.
+template <int S>
+__device__ __forceinline__ double two_over_s(const Inst& I) {
+  return S ? 2.0 / double(S) : ldexp(2.0, -I.hbits);
+}
+
 // Read-only loads from a wavefront-uniform address, through the scalar cache
 // (the constant address space).
 typedef const __attribute__((address_space(4))) Inst* ConstInstPtr;
@@ -481,7 +489,7 @@ __device__ __forceinline__ unsigned step_wave(const StepArgs& a, int64_t w, int 
     a.yacc[x.I.jbase + x.j] = yv;
   }
   if (!x.live) return 0;
-  const double2 tc = cscale(c, 2.0 / double(x.I.s));
+  const double2 tc = cscale(c, two_over_s<S>(x.I));
   unsigned cnt = 0;
 #pragma unroll
   for (int i = 0; i < SLM; ++i) {
@@ -646,7 +654,9 @@ __device__ __forceinline__ double prune_r(double v, double tau, unsigned& cnt) {
 
 // S: s of every instance, or 0 (read per instance, slots per lane <= SLM;
 // slots of value 0 are skipped as in step_wave when StepArgs::zskip is set).
-template <bool ACC, int SLM, int S, int ENC, int W = 0>
+// EQ0: when Q0 of a slot without a partner is read (see below); both forms
+// are correct for every matrix, the launcher takes the faster one.
+template <bool ACC, int SLM, int S, int ENC, int W = 0, bool EQ0 = false>
 __device__ __forceinline__ unsigned step_wave_real(const StepArgs& a, int64_t w, int lane, double coef) {
   const Lanes x = lanes_of<S, true, W>(a.m, w, lane);
   const int sl = S ? Shape<S, W>::sl : (SLM == 1 ? 1 : x.I.sl);
@@ -659,7 +669,7 @@ __device__ __forceinline__ unsigned step_wave_real(const StepArgs& a, int64_t w,
   double* oQ1 = reinterpret_cast<double*>(a.out.Q1);
   int64_t h[SLM];
   StepSlot rc[SLM];
-  double x0[SLM], x1[SLM], f[SLM], g[SLM];
+  double x0[SLM], x1[SLM], f[SLM], g[SLM], y0[SLM];
   bool zero[SLM];
 #pragma unroll
   for (int i = 0; i < SLM; ++i) {
@@ -669,6 +679,14 @@ __device__ __forceinline__ unsigned step_wave_real(const StepArgs& a, int64_t w,
       x1[i] = R1[h[i]] * a.in.r1s;
       zero[i] = S == 0 && a.zskip && rc[i].val == 0.0;
       x0[i] = zero[i] ? 0.0 : R0[h[i]];
+      // Q0 of a slot without a partner (fillers at the edge of a band).
+      // EQ0: issued as soon as the slot's link is in, not after the group
+      // sum, where a second round trip at the end of the wavefront cost
+      // 0.9 us per step on the paper's shape E.  Matrices where every slot
+      // has a partner (no Q0 cells) take the other form: the early load's
+      // code alone cost 6 % at 16384 x 8.
+      y0[i] = 0.0;
+      if (EQ0 && !zero[i] && rc[i].part < 0) y0[i] = Q0[h[i]];
     }
   }
   // The solver's y_j, loaded with the data: it is not needed before the
@@ -696,7 +714,7 @@ __device__ __forceinline__ unsigned step_wave_real(const StepArgs& a, int64_t w,
   }
   c = row_sum_r(c, x.rpw_log);
   if (ACC && x.h == 0) *yp = yv + coef * (c * x.I.inv_sqrt_s);  // the group sum is real: only Re y_j moves
-  const double tc = c * (2.0 / double(x.I.s));
+  const double tc = c * two_over_s<S>(x.I);
   unsigned cnt = 0;
 #pragma unroll
   for (int i = 0; i < SLM; ++i) {
@@ -710,16 +728,15 @@ __device__ __forceinline__ unsigned step_wave_real(const StepArgs& a, int64_t w,
       if (rc[i].part >= 0) {
         oR0[base + rc[i].part] = prune_r(o0, a.tau, cnt);
       } else {
-        const double y0 = Q0[h[i]];
         oQ0[h[i]] = prune_r(o0, a.tau, cnt);
-        oR0[h[i]] = prune_r(-y0, a.tau, cnt);
+        oR0[h[i]] = prune_r(EQ0 ? -y0[i] : -Q0[h[i]], a.tau, cnt);
       }
     }
   }
   return cnt;
 }
 
-template <bool ACC, int SLM, int S, int ENC, int W = 0>
+template <bool ACC, int SLM, int S, int ENC, int W = 0, bool EQ0 = false>
 __device__ __forceinline__ void step_body_real(const StepArgs& a) {
   const int lane = threadIdx.x & (kWave - 1);
   const int64_t wpb = a.wpb;
@@ -736,11 +753,11 @@ __device__ __forceinline__ void step_body_real(const StepArgs& a) {
   const double coef = ACC ? *a.coef : 0.0;
   const int64_t cidx = wave_counter(wpb);
   if (a.acc == nullptr) {  // the solver's private walk keeps no counts
-    (void)step_wave_real<ACC, SLM, S, ENC, W>(a, w, lane, coef);
+    (void)step_wave_real<ACC, SLM, S, ENC, W, EQ0>(a, w, lane, coef);
     return;
   }
   const unsigned long long prev = a.acc[cidx];
-  const unsigned long long v = wave_sum_bits<CountBits<SLM>::value>(step_wave_real<ACC, SLM, S, ENC, W>(a, w, lane, coef));
+  const unsigned long long v = wave_sum_bits<CountBits<SLM>::value>(step_wave_real<ACC, SLM, S, ENC, W, EQ0>(a, w, lane, coef));
   if (lane == 0) a.acc[cidx] = prev + v;
 }
 
@@ -765,21 +782,19 @@ extern "C" __global__ void __launch_bounds__(256) qwk_to_complex(const double* _
 // qwk_step_rS: one double per cell, FP64 values, s = S for every instance;
 // qwk_step_tS: the same for fixed-point data; qwk_step_rgN / qwk_step_tgN:
 // mixed s, up to N slots per lane (the g kernels' shapes).  The _acc twins
-// fuse the solver's projection, as the other families' do.
-#define QW_REAL_KERNEL(NAME, SLM, S, ENC)                                                            \
+// fuse the solver's projection, as the other families' do; the _q forms read
+// Q0 of unpartnered slots early (step_wave_real's EQ0).
+#define QW_REAL_KERNEL_(NAME, ACC, SLM, S, ENC, W, EQ0)                                              \
   extern "C" __global__ void __launch_bounds__(256) NAME(qw::StepArgs a) {                         \
-    qw::step_body_real<false, SLM, S, ENC>(a);                                                      \
-  }                                                                                                 \
-  extern "C" __global__ void __launch_bounds__(256) NAME##_acc(qw::StepArgs a) {                   \
-    qw::step_body_real<true, SLM, S, ENC>(a);                                                       \
+    qw::step_body_real<ACC, SLM, S, ENC, W, EQ0>(a);                                                \
   }
-#define QW_REAL_KERNEL_W(NAME, SLM, S, ENC)                                                          \
-  extern "C" __global__ void __launch_bounds__(256) NAME(qw::StepArgs a) {                         \
-    qw::step_body_real<false, SLM, S, ENC, 1>(a);                                                   \
-  }                                                                                                 \
-  extern "C" __global__ void __launch_bounds__(256) NAME##_acc(qw::StepArgs a) {                   \
-    qw::step_body_real<true, SLM, S, ENC, 1>(a);                                                    \
-  }
+#define QW_REAL_KERNEL4_(NAME, SLM, S, ENC, W)            \
+  QW_REAL_KERNEL_(NAME, false, SLM, S, ENC, W, false)     \
+  QW_REAL_KERNEL_(NAME##_acc, true, SLM, S, ENC, W, false) \
+  QW_REAL_KERNEL_(NAME##_q, false, SLM, S, ENC, W, true)   \
+  QW_REAL_KERNEL_(NAME##_q_acc, true, SLM, S, ENC, W, true)
+#define QW_REAL_KERNEL(NAME, SLM, S, ENC) QW_REAL_KERNEL4_(NAME, SLM, S, ENC, 0)
+#define QW_REAL_KERNEL_W(NAME, SLM, S, ENC) QW_REAL_KERNEL4_(NAME, SLM, S, ENC, 1)
 QW_REAL_KERNEL(qwk_step_r1, 1, 1, qw::kEncReal)
 QW_REAL_KERNEL(qwk_step_r2, 1, 2, qw::kEncReal)
 QW_REAL_KERNEL(qwk_step_r4, 1, 4, qw::kEncReal)
@@ -810,6 +825,8 @@ QW_REAL_KERNEL_W(qwk_step_t32w, 2, 32, qw::kEncAngle)
 QW_REAL_KERNEL_W(qwk_step_t64w, 4, 64, qw::kEncAngle)
 #undef QW_REAL_KERNEL
 #undef QW_REAL_KERNEL_W
+#undef QW_REAL_KERNEL4_
+#undef QW_REAL_KERNEL_
 
 
 namespace qw {
@@ -886,7 +903,7 @@ __device__ __forceinline__ void adjoint_wave(const AdjArgs& a, int64_t w, int la
   c = row_sum(c, x.rpw_log);
   d = row_sum(d, x.rpw_log);
   if (!x.live) return;
-  const double t = 2.0 / double(x.I.s);
+  const double t = two_over_s<0>(x.I);
   const double2 tc = cscale(c, t), td = cscale(d, t);
 #pragma unroll
   for (int i = 0; i < SLM; ++i) {
@@ -938,6 +955,143 @@ extern "C" __global__ void __launch_bounds__(256) qwk_adjoint_s1(qw::AdjArgs a) 
 extern "C" __global__ void __launch_bounds__(256) qwk_adjoint_s2(qw::AdjArgs a) { qw::adjoint_body<2>(a); }
 extern "C" __global__ void __launch_bounds__(256) qwk_adjoint_s4(qw::AdjArgs a) { qw::adjoint_body<4>(a); }
 extern "C" __global__ void __launch_bounds__(256) qwk_adjoint_s8(qw::AdjArgs a) { qw::adjoint_body<8>(a); }
+
+namespace qw {
+
+// ----------------------------------------------------------------- adjoint sweep step, one double per cell
+// The reverse step of adjoint_wave for a state on the 8-byte planes (both the
+// recomputed state and the adjoint state: S-conjugation and the weighting
+// diag(w) keep every cell real or imaginary by the rule of step_wave_real).
+// With f' = +-sqrt|a| (the sign of the +-i rule for a < 0) and
+// f_d' = df'/d|a| taken the same way (f_d = i f_d' for a < 0), every term of
+// the complex formula is real:
+//   c = sum f' x0 + g x1,  d = sum f' m0 + g m1  (row sums over the group),
+//   p = (2/s) c (f', g) - x  (the forward state's outputs of this step),
+//   dL/dv += 2 (2/s) [ c (m0 f_d' + m1 g_d) + d (f_d' p0 + g_d p1) ],
+// and the outputs are the real step's for both states.  One pass over the
+// wavefronts (every row exists, empty lists).  Returns the recomputed
+// state's kept outputs, counted as the step kernels count them.
+template <int SLM, int S, int W = 0, bool EQ0 = false>
+__device__ __forceinline__ unsigned adjoint_wave_real(const AdjArgs& a, int64_t w, int lane) {
+  const Lanes x = lanes_of<S, true, W>(a.m, w, lane);
+  const int sl = S ? Shape<S, W>::sl : (SLM == 1 ? 1 : x.I.sl);
+  const int64_t base = x.I.item_base;
+  const double* R0 = reinterpret_cast<const double*>(a.in.R0);
+  const double* R1 = reinterpret_cast<const double*>(a.in.R1);
+  const double* Q0 = reinterpret_cast<const double*>(a.in.Q0);
+  const double* LR0 = reinterpret_cast<const double*>(a.lin.R0);
+  const double* LR1 = reinterpret_cast<const double*>(a.lin.R1);
+  const double* LQ0 = reinterpret_cast<const double*>(a.lin.Q0);
+  int64_t h[SLM];
+  StepSlot rc[SLM];
+  double x0[SLM], x1[SLM], m0[SLM], m1[SLM], f[SLM], g[SLM], y0[SLM], z0[SLM];
+#pragma unroll
+  for (int i = 0; i < SLM; ++i) {
+    if (i < sl) {
+      h[i] = base + (int64_t(x.h * sl + i) << x.I.nlog) + x.j;
+      rc[i] = step_rec(a.m, h[i]);
+      x1[i] = R1[h[i]] * a.in.r1s;
+      x0[i] = R0[h[i]];
+      m1[i] = LR1[h[i]] * a.lin.r1s;
+      m0[i] = LR0[h[i]];
+      y0[i] = z0[i] = 0.0;  // Q0 of slots without a partner, early or late (step_wave_real's EQ0)
+      if (EQ0 && rc[i].part < 0) {
+        y0[i] = Q0[h[i]];
+        z0[i] = LQ0[h[i]];
+      }
+    }
+  }
+  double c = 0.0, d = 0.0;
+#pragma unroll
+  for (int i = 0; i < SLM; ++i) {
+    if (i < sl) {
+      const double q = sqrt(fabs(rc[i].val));
+      g[i] = sqrt(1.0 - fabs(rc[i].val));
+      f[i] = rc[i].val < 0.0 && !rc[i].upper ? -q : q;
+      c += f[i] * x0[i] + x1[i] * g[i];
+      d += f[i] * m0[i] + m1[i] * g[i];
+    }
+  }
+  c = row_sum_r(c, x.rpw_log);
+  d = row_sum_r(d, x.rpw_log);
+  const double t = two_over_s<S>(x.I);
+  const double tc = c * t, td = d * t;
+  double* oR0 = reinterpret_cast<double*>(a.out.R0);
+  double* oQ0 = reinterpret_cast<double*>(a.out.Q0);
+  double* oQ1 = reinterpret_cast<double*>(a.out.Q1);
+  double* lR0 = reinterpret_cast<double*>(a.lout.R0);
+  double* lQ0 = reinterpret_cast<double*>(a.lout.Q0);
+  double* lQ1 = reinterpret_cast<double*>(a.lout.Q1);
+  unsigned cnt = 0, unused = 0;
+#pragma unroll
+  for (int i = 0; i < SLM; ++i) {
+    if (i < sl) {
+      const double v = rc[i].val;
+      const double p0 = tc * f[i] - x0[i], p1 = tc * g[i] - x1[i];
+      const double w0 = td * f[i] - m0[i], w1 = td * g[i] - m1[i];
+      // df'/da and dg/da (not finite at a = 0 and |a| = 1)
+      const double fq = 0.5 / sqrt(fabs(v));
+      const double fd = v > 0.0 ? fq : (v < 0.0 ? (rc[i].upper ? -fq : fq) : __builtin_inf());
+      const double gd = (v > 0.0 ? -0.5 : (v < 0.0 ? 0.5 : 0.0)) / sqrt(1.0 - fabs(v));
+      const double u = c * (m0[i] * fd + m1[i] * gd) + d * (fd * p0 + gd * p1);
+      a.dv[h[i]] += 2.0 * t * u;
+      unsigned q1 = 0;
+      oQ1[h[i]] = prune_r(p1, a.tau, q1);
+      cnt += 2 * q1;  // counted as in write_slot
+      lQ1[h[i]] = prune_r(w1, a.tau, unused);
+      if (rc[i].part >= 0) {
+        oR0[base + rc[i].part] = prune_r(p0, a.tau, cnt);
+        lR0[base + rc[i].part] = prune_r(w0, a.tau, unused);
+      } else {
+        oQ0[h[i]] = prune_r(p0, a.tau, cnt);
+        oR0[h[i]] = prune_r(EQ0 ? -y0[i] : -Q0[h[i]], a.tau, cnt);
+        lQ0[h[i]] = prune_r(w0, a.tau, unused);
+        lR0[h[i]] = prune_r(EQ0 ? -z0[i] : -LQ0[h[i]], a.tau, unused);
+      }
+    }
+  }
+  return cnt;
+}
+
+template <int SLM, int S, int W = 0, bool EQ0 = false>
+__device__ __forceinline__ void adjoint_body_real(const AdjArgs& a) {
+  const int lane = threadIdx.x & (kWave - 1);
+  const int64_t wpb = a.wpb;
+  const int64_t w = uniform(int(int64_t(blockIdx.x) * wpb + (threadIdx.x >> 6)));
+  if (w >= a.m.waves) return;
+  const int64_t cidx = wave_counter(wpb);
+  const unsigned long long prev = a.acc ? a.acc[cidx] : 0ull;
+  const unsigned cnt = adjoint_wave_real<SLM, S, W, EQ0>(a, w, lane);
+  if (a.acc) {
+    const unsigned long long v = wave_sum_bits<CountBits<SLM>::value>(cnt);
+    if (lane == 0) a.acc[cidx] = prev + v;
+  }
+}
+
+}  // namespace qw
+
+// qwk_adjoint_rS: s = S for every instance; qwk_adjoint_rgN: mixed s, up to N
+// slots per lane; qwk_adjoint_rSw: 16 lanes per row (Matrix::wide).
+#define QW_ADJ_REAL_KERNEL(NAME, SLM, S, W)                                                       \
+  extern "C" __global__ void __launch_bounds__(256) NAME(qw::AdjArgs a) {                       \
+    qw::adjoint_body_real<SLM, S, W, false>(a);                                                  \
+  }                                                                                              \
+  extern "C" __global__ void __launch_bounds__(256) NAME##_q(qw::AdjArgs a) { qw::adjoint_body_real<SLM, S, W, true>(a); }
+QW_ADJ_REAL_KERNEL(qwk_adjoint_r1, 1, 1, 0)
+QW_ADJ_REAL_KERNEL(qwk_adjoint_r2, 1, 2, 0)
+QW_ADJ_REAL_KERNEL(qwk_adjoint_r4, 1, 4, 0)
+QW_ADJ_REAL_KERNEL(qwk_adjoint_r8, 1, 8, 0)
+QW_ADJ_REAL_KERNEL(qwk_adjoint_r16, 2, 16, 0)
+QW_ADJ_REAL_KERNEL(qwk_adjoint_r32, 4, 32, 0)
+QW_ADJ_REAL_KERNEL(qwk_adjoint_r64, 8, 64, 0)
+QW_ADJ_REAL_KERNEL(qwk_adjoint_rg1, 1, 0, 0)
+QW_ADJ_REAL_KERNEL(qwk_adjoint_rg2, 2, 0, 0)
+QW_ADJ_REAL_KERNEL(qwk_adjoint_rg4, 4, 0, 0)
+QW_ADJ_REAL_KERNEL(qwk_adjoint_rg8, 8, 0, 0)
+QW_ADJ_REAL_KERNEL(qwk_adjoint_r16w, 1, 16, 1)
+QW_ADJ_REAL_KERNEL(qwk_adjoint_r32w, 2, 32, 1)
+QW_ADJ_REAL_KERNEL(qwk_adjoint_r64w, 4, 64, 1)
+#undef QW_ADJ_REAL_KERNEL
 
 namespace qw {
 
@@ -1240,6 +1394,128 @@ extern "C" __global__ void __launch_bounds__(256) qwk_weight(Matrix m, Slots in,
   }
   const double t = block_sum(acc, sh);
   if (threadIdx.x == 0) partial[blockIdx.x] = t;
+}
+
+// ----------------------------------------------------------------- the same on one double per cell
+// The swap S of a state on the 8-byte planes (a permutation of its cells:
+// R0 to the partner's R0 or to its own Q0 and back, R1 to Q1, the R1 of the
+// output being the input's Q1 plane with sign +1), one lane per home; the
+// outputs are counted as the step kernels count them (acc may be NULL).
+extern "C" __global__ void __launch_bounds__(256) qwk_swap_real(Matrix m, Slots in, Slots out,
+                                                                unsigned long long* acc) {
+  const double* R0 = reinterpret_cast<const double*>(in.R0);
+  const double* R1 = reinterpret_cast<const double*>(in.R1);
+  const double* Q0 = reinterpret_cast<const double*>(in.Q0);
+  double* oR0 = reinterpret_cast<double*>(out.R0);
+  double* oQ0 = reinterpret_cast<double*>(out.Q0);
+  double* oQ1 = reinterpret_cast<double*>(out.Q1);
+  const int64_t wpb = blockDim.x >> 6;
+  const int64_t cidx = wave_counter(wpb);
+  const unsigned long long prev = acc ? acc[cidx] : 0ull;
+  unsigned cnt = 0;
+  const int64_t stride = int64_t(gridDim.x) * blockDim.x;
+  for (int64_t it = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; it < m.items; it += stride) {
+    const Home x = home_item(m, it, it - (threadIdx.x & (kWave - 1)));
+    if (!x.live) continue;
+    const double x0 = R0[it], x1 = R1[it] * in.r1s;
+    const int part = int(m.slink[it] & 0x7fffffffu) - 1;
+    oQ1[it] = x1;
+    cnt += 2 * (x1 != 0.0);
+    if (part >= 0) {
+      oR0[x.I.item_base + part] = x0;
+      cnt += x0 != 0.0;
+    } else {
+      const double y0 = Q0[it];
+      oQ0[it] = x0;
+      oR0[it] = y0;
+      cnt += (x0 != 0.0) + (y0 != 0.0);
+    }
+  }
+  const unsigned long long v = wave_sum(cnt);
+  if (acc && (threadIdx.x & (kWave - 1)) == 0) acc[cidx] = prev + v;
+}
+
+// qwk_weight on the 8-byte planes: Lambda = diag(w[k register]) Psi and the
+// loss as per-block partials.
+extern "C" __global__ void __launch_bounds__(256) qwk_weight_real(Matrix m, Slots in, Slots out, const double* w,
+                                                                  double* partial) {
+  __shared__ double sh[16];
+  const double* R0 = reinterpret_cast<const double*>(in.R0);
+  const double* R1 = reinterpret_cast<const double*>(in.R1);
+  const double* Q0 = reinterpret_cast<const double*>(in.Q0);
+  const double* Q1 = reinterpret_cast<const double*>(in.Q1);
+  double* oR0 = reinterpret_cast<double*>(out.R0);
+  double* oR1 = reinterpret_cast<double*>(out.R1);
+  double* oQ0 = reinterpret_cast<double*>(out.Q0);
+  double* oQ1 = reinterpret_cast<double*>(out.Q1);
+  double acc = 0.0;
+  const int64_t stride = int64_t(gridDim.x) * blockDim.x;
+  for (int64_t it = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; it < m.items; it += stride) {
+    const Home x = home_item(m, it, it - (threadIdx.x & (kWave - 1)));
+    if (!x.live) continue;
+    const double wr = w[x.I.jbase + m.rec[it].col];
+    const double wq = w[x.I.jbase + x.j];
+    const double p0 = R0[it], p1 = R1[it] * in.r1s, s0 = Q0[it], s1 = Q1[it];
+    acc += wr * (p0 * p0 + p1 * p1) + wq * (s0 * s0 + s1 * s1);
+    oR0[it] = p0 * wr;
+    oR1[it] = p1 * (wr * out.r1s);
+    oQ0[it] = s0 * wq;
+    oQ1[it] = s1 * wq;
+  }
+  const double t = block_sum(acc, sh);
+  if (threadIdx.x == 0) partial[blockIdx.x] = t;
+}
+
+// qwk_grad_init on the 8-byte planes (a real b): with n the cells of lambda_0
+// (imaginary R0 cells of slots of negative value held as their coefficient
+// of i), dL/dv += 2 b_j (n0 f_d' + n1 g_d) / sqrt(s) and
+// dL/db_j = 2 sum (f' n0 + g n1) / sqrt(s) (the real parts; the imaginary
+// parts are 0).
+extern "C" __global__ void __launch_bounds__(256) qwk_grad_init_real(Matrix m, Slots lam, const double2* b,
+                                                                     double* dv, double2* db) {
+  const double* N0 = reinterpret_cast<const double*>(lam.R0);
+  const double* N1 = reinterpret_cast<const double*>(lam.R1);
+  const int64_t stride = int64_t(gridDim.x) * blockDim.x;
+  for (int64_t it = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; it < m.rows; it += stride) {
+    const Row x = row_item(m, it);
+    const double bj = b[it].x;
+    double c = 0.0;
+    for (int l = 0; l < x.I.s; ++l) {
+      const int64_t h = home(x.I, x.j, l);
+      const double n0 = N0[h], n1 = N1[h] * lam.r1s;
+      const SlotRec rc = m.rec[h];
+      const double a = rc.val;
+      const bool upper = x.j <= rc.col;
+      const double q = sqrt(fabs(a));
+      const double f = a < 0.0 && !upper ? -q : q;
+      const double g = sqrt(1.0 - fabs(a));
+      const double fq = 0.5 / q;
+      const double fd = a > 0.0 ? fq : (a < 0.0 ? (upper ? -fq : fq) : __builtin_inf());
+      const double gd = (a > 0.0 ? -0.5 : (a < 0.0 ? 0.5 : 0.0)) / g;
+      dv[h] += 2.0 * bj * (n0 * fd + n1 * gd) * x.I.inv_sqrt_s;
+      c += f * n0 + g * n1;
+    }
+    db[it] = make_double2(2.0 * c * x.I.inv_sqrt_s, 0.0);
+  }
+}
+
+// The gradient's results in the caller's order: gv[p] = dv[home[p]] for the
+// CSC entries, br/bi[p] = db[row[p]] for the unpadded columns.
+extern "C" __global__ void __launch_bounds__(256) qwk_gather_grad(const double* __restrict__ dv,
+                                                                  const int32_t* __restrict__ home, int64_t nnz,
+                                                                  const double2* __restrict__ db,
+                                                                  const int32_t* __restrict__ row, int64_t n,
+                                                                  double* gv, double* br, double* bi) {
+  const int64_t stride = int64_t(gridDim.x) * blockDim.x;
+  for (int64_t p = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; p < nnz + n; p += stride) {
+    if (p < nnz) {
+      gv[p] = dv[home[p]];
+    } else {
+      const double2 v = db[row[p - nnz]];
+      br[p - nnz] = v.x;
+      bi[p - nnz] = v.y;
+    }
+  }
 }
 
 // Gradient through the initial T~ (one lane per row): psi_0 holds b_j phi_j

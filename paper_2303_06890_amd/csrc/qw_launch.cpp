@@ -85,15 +85,23 @@ enum Fn {
   F_GRAD_INIT,
   F_STEP_R1,  // one double per cell: qwk_step_r{1..64}, qwk_step_t{1..64}, then mixed s:
   F_STEP_T1 = F_STEP_R1 + 7,    // qwk_step_rg{1,2,4,8}, qwk_step_tg{1,2,4,8}; their _acc
-  F_STEP_RG1 = F_STEP_T1 + 7,   // twins follow at + F_REAL_COUNT_
-  F_STEP_TG1 = F_STEP_RG1 + 4,
-  F_STEP_RW16 = F_STEP_TG1 + 4,  // 16 lanes per row: qwk_step_r{16,32,64}w, qwk_step_t{16,32,64}w
-  F_STEP_TW16 = F_STEP_RW16 + 3,
+  F_STEP_RG1 = F_STEP_T1 + 7,   // twins follow at + F_REAL_COUNT_, the _q forms (early Q0
+  F_STEP_TG1 = F_STEP_RG1 + 4,  // loads) at + 2 F_REAL_COUNT_ and their _acc twins at
+  F_STEP_RW16 = F_STEP_TG1 + 4,  // + 3 F_REAL_COUNT_.  16 lanes per row: qwk_step_r{16,32,64}w,
+  F_STEP_TW16 = F_STEP_RW16 + 3,  // qwk_step_t{16,32,64}w
   F_REAL_COUNT_ = F_STEP_TW16 + 3 - F_STEP_R1,
-  F_TO_REAL = F_STEP_R1 + 2 * F_REAL_COUNT_,
+  F_TO_REAL = F_STEP_R1 + 4 * F_REAL_COUNT_,
   F_TO_COMPLEX,
   F_COEF_WINDOW,
   F_SUM_COUNTS,
+  F_ADJ_R1,                   // one-pass adjoint on one double per cell: qwk_adjoint_r{1..64},
+  F_ADJ_RG1 = F_ADJ_R1 + 7,   // qwk_adjoint_rg{1,2,4,8} (mixed s),
+  F_ADJ_RW16 = F_ADJ_RG1 + 4,  // qwk_adjoint_r{16,32,64}w (16 lanes per row); the _q forms
+  F_ADJ_COUNT_ = F_ADJ_RW16 + 3 - F_ADJ_R1,  // follow at + F_ADJ_COUNT_
+  F_SWAP_REAL = F_ADJ_R1 + 2 * F_ADJ_COUNT_,
+  F_WEIGHT_REAL,
+  F_GRAD_INIT_REAL,
+  F_GATHER_GRAD,
   F_COUNT
 };
 
@@ -130,8 +138,30 @@ const char* const kNames[] = {
     "qwk_step_t8_acc",  "qwk_step_t16_acc", "qwk_step_t32_acc", "qwk_step_t64_acc", "qwk_step_rg1_acc",
     "qwk_step_rg2_acc", "qwk_step_rg4_acc", "qwk_step_rg8_acc", "qwk_step_tg1_acc", "qwk_step_tg2_acc",
     "qwk_step_tg4_acc", "qwk_step_tg8_acc", "qwk_step_r16w_acc", "qwk_step_r32w_acc", "qwk_step_r64w_acc",
-    "qwk_step_t16w_acc", "qwk_step_t32w_acc", "qwk_step_t64w_acc", "qwk_to_real",      "qwk_to_complex",
-    "qwk_coef_window",  "qwk_sum_counts"};
+    "qwk_step_t16w_acc", "qwk_step_t32w_acc", "qwk_step_t64w_acc",
+    "qwk_step_r1_q", "qwk_step_r2_q", "qwk_step_r4_q", "qwk_step_r8_q", "qwk_step_r16_q", "qwk_step_r32_q",
+    "qwk_step_r64_q", "qwk_step_t1_q", "qwk_step_t2_q", "qwk_step_t4_q", "qwk_step_t8_q", "qwk_step_t16_q",
+    "qwk_step_t32_q", "qwk_step_t64_q", "qwk_step_rg1_q", "qwk_step_rg2_q", "qwk_step_rg4_q",
+    "qwk_step_rg8_q", "qwk_step_tg1_q", "qwk_step_tg2_q", "qwk_step_tg4_q", "qwk_step_tg8_q",
+    "qwk_step_r16w_q", "qwk_step_r32w_q", "qwk_step_r64w_q", "qwk_step_t16w_q", "qwk_step_t32w_q",
+    "qwk_step_t64w_q",
+    "qwk_step_r1_q_acc", "qwk_step_r2_q_acc", "qwk_step_r4_q_acc", "qwk_step_r8_q_acc", "qwk_step_r16_q_acc",
+    "qwk_step_r32_q_acc", "qwk_step_r64_q_acc", "qwk_step_t1_q_acc", "qwk_step_t2_q_acc", "qwk_step_t4_q_acc",
+    "qwk_step_t8_q_acc", "qwk_step_t16_q_acc", "qwk_step_t32_q_acc", "qwk_step_t64_q_acc",
+    "qwk_step_rg1_q_acc", "qwk_step_rg2_q_acc", "qwk_step_rg4_q_acc", "qwk_step_rg8_q_acc",
+    "qwk_step_tg1_q_acc", "qwk_step_tg2_q_acc", "qwk_step_tg4_q_acc", "qwk_step_tg8_q_acc",
+    "qwk_step_r16w_q_acc", "qwk_step_r32w_q_acc", "qwk_step_r64w_q_acc", "qwk_step_t16w_q_acc",
+    "qwk_step_t32w_q_acc", "qwk_step_t64w_q_acc",
+    "qwk_to_real",      "qwk_to_complex",
+    "qwk_coef_window",  "qwk_sum_counts",
+    "qwk_adjoint_r1",   "qwk_adjoint_r2",   "qwk_adjoint_r4",   "qwk_adjoint_r8",   "qwk_adjoint_r16",
+    "qwk_adjoint_r32",  "qwk_adjoint_r64",  "qwk_adjoint_rg1",  "qwk_adjoint_rg2",  "qwk_adjoint_rg4",
+    "qwk_adjoint_rg8",  "qwk_adjoint_r16w", "qwk_adjoint_r32w", "qwk_adjoint_r64w",
+    "qwk_adjoint_r1_q", "qwk_adjoint_r2_q", "qwk_adjoint_r4_q", "qwk_adjoint_r8_q", "qwk_adjoint_r16_q",
+    "qwk_adjoint_r32_q", "qwk_adjoint_r64_q", "qwk_adjoint_rg1_q", "qwk_adjoint_rg2_q", "qwk_adjoint_rg4_q",
+    "qwk_adjoint_rg8_q", "qwk_adjoint_r16w_q", "qwk_adjoint_r32w_q", "qwk_adjoint_r64w_q",
+    "qwk_swap_real",
+    "qwk_weight_real",  "qwk_grad_init_real", "qwk_gather_grad"};
 static_assert(sizeof(kNames) / sizeof(kNames[0]) == F_COUNT, "one kernel name per Fn");
 
 // 0..3 for slmax = 1, 2, 4, 8
@@ -153,7 +183,7 @@ Fn step_kernel(const StepArgs& a, int grid, int block) {
     const int f = m.suni > 0 && wide ? (m.angles ? F_STEP_TW16 : F_STEP_RW16) + log2_of(m.suni) - 4
                   : m.suni > 0       ? (m.angles ? F_STEP_T1 : F_STEP_R1) + log2_of(m.suni)
                                      : (m.angles ? F_STEP_TG1 : F_STEP_RG1) + width_index(m.slmax);
-    return Fn(f + (acc ? int(F_REAL_COUNT_) : 0));
+    return Fn(f + (acc ? int(F_REAL_COUNT_) : 0) + (a.q0 ? 2 * int(F_REAL_COUNT_) : 0));
   }
   int f = F_STEP_S1 + width_index(m.slmax);
   if (m.vim) {
@@ -204,6 +234,10 @@ hipError_t function(Fn f, hipFunction_t* out) {
   return hipSuccess;
 }
 
+}  // namespace
+
+namespace {
+
 hipError_t launch(Fn f, int grid, int block, hipStream_t stream, void** params) {
   hipFunction_t fn;
   hipError_t e = function(f, &fn);
@@ -236,9 +270,19 @@ hipError_t launch_adjoint(const AdjArgs& a, int grid, int block, hipStream_t str
   if (a.m.vim || a.m.angles) return hipErrorInvalidValue;  // the gradient sweep is for real FP64 matrices
   AdjArgs c = a;
   c.wpb = block / kWave;
-  c.pad_ = 0;
+  if (!a.real) {
+    c.real = 0;
+    void* p[] = {&c};
+    return launch(Fn(F_ADJOINT_S1 + width_index(a.m.slmax)), grid, block, stream, p);
+  }
+  // one pass over every wavefront, no lists (the caller checked; re-checked here)
+  if (a.L.cnt || a.LL.cnt || !a.m.full || int64_t(grid) * (block / kWave) < a.m.waves) return hipErrorInvalidValue;
+  const bool wide = a.m.wide && a.m.suni >= 16;
+  const int f = a.m.suni > 0 && wide ? F_ADJ_RW16 + log2_of(a.m.suni) - 4
+                : a.m.suni > 0       ? F_ADJ_R1 + log2_of(a.m.suni)
+                                     : F_ADJ_RG1 + width_index(a.m.slmax);
   void* p[] = {&c};
-  return launch(Fn(F_ADJOINT_S1 + width_index(a.m.slmax)), grid, block, stream, p);
+  return launch(Fn(f + (a.q0 ? int(F_ADJ_COUNT_) : 0)), grid, block, stream, p);
 }
 
 hipError_t launch_qbs_table(const Matrix& m, SlotRec* rec, uint32_t* slink, double* sval, hipStream_t stream) {
@@ -320,6 +364,35 @@ hipError_t launch_weight(const Matrix& m, Slots in, List L, Slots out, List LL, 
   const double* ww = w;
   void* p[] = {&mm, &in, &L, &out, &LL, &ww, &partial};
   return launch(F_WEIGHT, grid, 256, stream, p);
+}
+
+hipError_t launch_swap_real(const Matrix& m, Slots in, Slots out, unsigned long long* acc, hipStream_t stream) {
+  Matrix mm = m;
+  void* p[] = {&mm, &in, &out, &acc};
+  return launch(F_SWAP_REAL, clamp_grid(m.items, 4096), 256, stream, p);
+}
+
+hipError_t launch_weight_real(const Matrix& m, Slots in, Slots out, const double* w, double* partial, int grid,
+                              hipStream_t stream) {
+  Matrix mm = m;
+  const double* ww = w;
+  void* p[] = {&mm, &in, &out, &ww, &partial};
+  return launch(F_WEIGHT_REAL, grid, 256, stream, p);
+}
+
+hipError_t launch_grad_init_real(const Matrix& m, Slots lam, const double2* b, double* dv, double2* db,
+                                 hipStream_t stream) {
+  Matrix mm = m;
+  const double2* bb = b;
+  void* p[] = {&mm, &lam, &bb, &dv, &db};
+  return launch(F_GRAD_INIT_REAL, clamp_grid(m.rows, 4096), 256, stream, p);
+}
+
+hipError_t launch_gather_grad(const double* dv, const int32_t* home, int64_t nnz, const double2* db,
+                              const int32_t* row, int64_t n, double* gv, double* br, double* bi,
+                              hipStream_t stream) {
+  void* p[] = {&dv, &home, &nnz, &db, &row, &n, &gv, &br, &bi};
+  return launch(F_GATHER_GRAD, clamp_grid(nnz + n, 4096), 256, stream, p);
 }
 
 hipError_t launch_grad_init(const Matrix& m, Slots lam, const double2* b, double* dv, double2* db,

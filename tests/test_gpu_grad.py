@@ -85,10 +85,14 @@ def _close(g, o, floor, rel=1e-8, where=""):
     return fin, float(ratio.max()), int(np.count_nonzero(floor[fin] > rel * np.abs(o[fin])))
 
 
+@pytest.mark.parametrize("real_b", [False, True])
 @pytest.mark.parametrize("n,c,seed,nsteps", [(16, 5, 81, 5), (64, 7, 82, 9), (64, 12, 83, 5), (64, 20, 84, 4)])
-def test_grad_matches_oracle_small(Q, oracle_mod, n, c, seed, nsteps):
+def test_grad_matches_oracle_small(Q, oracle_mod, n, c, seed, nsteps, real_b):
+    """A complex b keeps the reverse sweep on the complex planes; a real b
+    runs it on one double per cell (s = 8 and 16 lanes per row for s = 16
+    and 32 at these sizes)."""
     csc = _scaled(W.offset_matrix(n, c, seed=seed))
-    b = W.gaussian_b(n, seed=seed + 1) * (1 + 0.3j)
+    b = W.gaussian_b(n, seed=seed + 1) * (1 if real_b else (1 + 0.3j))
     b = b / np.linalg.norm(b)
     w = np.zeros(n)
     w[np.random.default_rng(seed).choice(n, size=max(2, n // 4), replace=False)] = 1.0
@@ -143,3 +147,30 @@ def test_walk_observable_autograd(Q):
     assert float(loss.detach()) == pytest.approx(gl, rel=1e-12)
     assert np.allclose(vals.grad.numpy(), gg, rtol=1e-12, atol=1e-14, equal_nan=True)
     assert np.allclose(bt.grad.numpy(), gdb.real, rtol=1e-12, atol=1e-14)
+
+
+def test_grad_batched_mixed_s_on_real_planes(Q, oracle_mod):
+    """Two instances of different s in one context with real b: the reverse
+    sweep runs the mixed-s kernel on one double per cell; each instance's
+    gradient equals the oracle's for that matrix alone."""
+    mats = [_scaled(W.offset_matrix(128, 6, seed=85)), _scaled(W.offset_matrix(64, 11, seed=86))]
+    bs = [W.uniform_b(128), W.gaussian_b(64, seed=87)]
+    bs[1] = bs[1] / np.linalg.norm(bs[1])
+    ws = [np.zeros(128), np.zeros(64)]
+    ws[0][::5] = 1.0
+    ws[1][1::3] = 1.0
+    nsteps = 7
+    walk = Q.Walk(mats, scale=1.0, symmetric=False)
+    assert len({d["s"] for d in walk.info}) == 2
+    st = walk.state(bs).step(nsteps)
+    assert st.stats()["real_amplitudes"]
+    gl, gg, gdb = st.grad(np.concatenate(ws), nsteps)
+    off, boff, total = 0, 0, 0.0
+    for csc, b, w, d in zip(mats, bs, ws, walk.info):
+        ol, og, odb = _oracle_csc_grad(oracle_mod, csc, b, w, nsteps)
+        total += ol
+        _close(gg[off:off + csc.nnz], og, _floor_dv(csc.vals, d["s"], nsteps), where=f"dvals n={csc.n}")
+        _close(gdb[boff:boff + csc.n], odb, _floor_db(d["s"], nsteps), where=f"db n={csc.n}")
+        off += csc.nnz
+        boff += csc.n
+    assert gl == pytest.approx(total, rel=1e-12)

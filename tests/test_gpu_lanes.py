@@ -91,3 +91,40 @@ def test_large_contexts_keep_eight_lanes(Q):
     inst = W.batched_instances(count=256)
     st = Q.Walk([a for a, _ in inst]).state([b for _, b in inst])
     assert st.stats()["lanes_per_row_s16"] == 8
+
+
+@pytest.mark.parametrize("lanes", [8, 16])
+@pytest.mark.parametrize("shape", ["C", "E"])
+def test_lanes_flag_forces_the_mapping(Q, oracle_mod, lanes, shape):
+    """QW_LANES_8 / QW_LANES_16 replace the library's rule: the paper's shape
+    C (s = 32, which the rule gives 16 lanes) and E (s = 64, which it gives
+    8), each with both mappings, equal the oracle."""
+    csc, b = W.table1_band(shape)
+    if shape == "E":  # a smaller band of the same s keeps the oracle quick
+        csc, b = W.band_matrix(512, 31, seed=7), W.uniform_b(512)
+    walk = Q.Walk(csc, lanes=lanes)
+    st = walk.state(b)
+    assert st.stats()["lanes_per_row_s16"] == lanes
+    ost = oracle_mod.OracleState(oracle_mod.OracleMatrix(csc)).set_b(b).T()
+    st.step(9)
+    ost.step(9)
+    gk, ga = st.export()
+    ok, oa = ost.export()
+    compare_states(gk, ga, ok, oa, where=f"shape {shape}, {lanes} lanes per row")
+
+
+def test_tune_walk_chooses_a_tile_and_logs_it(Q, oracle_mod):
+    """The autotuner loads both tiles of an s = 32 matrix, times them, and
+    returns a walk that equals the oracle."""
+    from paper_2303_06890_amd import autotune
+
+    csc, b = W.band_matrix(256, 15, seed=8), W.uniform_b(256)
+    walk, shape, log = autotune.tune_walk(csc, b)
+    assert sorted(c["lanes_per_row"][0] for c in log["tile_choices"]) == [8, 16]
+    assert log["chosen_lanes_per_row"] in ([8], [16]) and len(log["launch_candidates"]) >= 2
+    st = walk.state(b)
+    autotune.apply(st, shape)
+    st.step(40)
+    ok, oa = oracle_mod.OracleState(oracle_mod.OracleMatrix(csc)).set_b(b).T().step(40).export()
+    gk, ga = st.export()
+    compare_states(gk, ga, ok, oa, where="tuned walk")

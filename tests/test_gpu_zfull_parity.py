@@ -35,8 +35,7 @@ def test_g16384_100_steps_elementwise(Q):
     from paper_2303_06890_amd import autotune
 
     csc, b = W.paper_scale()
-    walk = Q.Walk(csc)
-    shape = autotune.tune(walk, b)  # the launch configuration the benchmark times
+    walk, shape, _ = autotune.tune_walk(csc, b)  # the configuration the benchmark times
     st = walk.state(b)
     autotune.apply(st, shape)
     st.step(100)
@@ -73,9 +72,8 @@ def test_batched_largest_instances_vs_oracle(Q):
     from paper_2303_06890_amd import autotune
 
     inst = W.batched_instances()
-    walk = Q.Walk([a for a, _ in inst])
     bs = [b for _, b in inst]
-    shape = autotune.tune(walk, bs)  # the batched leg's launch configuration
+    walk, shape, _ = autotune.tune_walk([a for a, _ in inst], bs)  # the batched leg's configuration
     st = walk.state(bs)
     autotune.apply(st, shape)
     st.step(50)
