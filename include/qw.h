@@ -283,6 +283,22 @@ int qw_cks_coeffs(int64_t beta, int32_t j0, double* out);
 int qw_grad(qw_state* st, const double* w, int32_t nsteps, double* dvals, double* db_re, double* db_im,
             double* loss, void* stream);
 
+/* qw_grad without allocating anything: for callers that cannot allocate
+ * device memory (tight serving loops, harnesses that forbid allocation).
+ * Same arguments, results and errors as qw_grad, for a state whose walk
+ * steps run on one double per cell and have run at least once (a real
+ * matrix whose negative values pair up, a real b, a one-pass launch shape);
+ * other states: QW_ENOTSUP.  Every buffer of the sweep (the adjoint state's
+ * planes, the weights, dL/dv, dL/db and the results in CSC order) is carved
+ * from one device array of the library, 32 MiB on each GPU it runs on, held
+ * from the first call on that GPU to qw_shutdown; a context that needs more
+ * (about 56 bytes per QRAM slot plus 40 per column; G(16384, 8) needs 9 MB)
+ * is rejected with QW_EINVAL and the size in qw_last_error.  Calls share
+ * that array: calls that overlap on one GPU (other threads or streams) race,
+ * so serialise them.  Each call clears what must start at 0. */
+int qw_grad_noalloc(qw_state* st, const double* w, int32_t nsteps, double* dvals, double* db_re,
+                    double* db_im, double* loss, void* stream);
+
 /* Free a state (waits for the device; its buffers go to the context's
  * pool).  NULL is ignored. */
 void qw_state_free(qw_state* st);

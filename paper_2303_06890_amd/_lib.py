@@ -31,7 +31,7 @@ SYMBOLS = [
     "qw_load_csc", "qw_load_csc_batched", "qw_ctx_info", "qw_ctx_ninst", "qw_state_init", "qw_step",
     "qw_step_adjoint", "qw_measure", "qw_export", "qw_state_import", "qw_sync", "qls_run",
     "qw_cks_coeffs", "qw_grad", "qw_state_free", "qw_ctx_free", "qw_last_error", "qw_set_launch",
-    "qw_shutdown", "qw_load_csc_hermitian", "qw_kappa",
+    "qw_shutdown", "qw_load_csc_hermitian", "qw_kappa", "qw_grad_noalloc",
 ]
 
 ALLOC_T = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p)
@@ -86,6 +86,7 @@ def load() -> ctypes.CDLL:
         "qls_run": (c_int, [P, dp, dbl, dbl, i32, dp, dp, dp, dp, lp, P]),
         "qw_cks_coeffs": (c_int, [i64, i32, dp]),
         "qw_grad": (c_int, [P, dp, i32, dp, dp, dp, dp, P]),
+        "qw_grad_noalloc": (c_int, [P, dp, i32, dp, dp, dp, dp, P]),
         "qw_state_free": (None, [P]),
         "qw_ctx_free": (None, [P]),
         "qw_last_error": (ctypes.c_char_p, []),

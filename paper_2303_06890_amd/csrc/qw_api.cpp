@@ -1224,7 +1224,7 @@ void cks_coefficients(int64_t beta, int32_t j0, double* out) {
   }
 }
 
-// Argument checks of qw_grad.
+// Argument checks shared by qw_grad and qw_grad_noalloc.
 int grad_check(qw_state* st, const double* w, int32_t nsteps) {
   if (!st || !w) return set_err(QW_EINVAL, "missing argument");
   if (!st->prepared || st->steps_since_init != nsteps)
@@ -1775,6 +1775,75 @@ int qw_grad(qw_state* st, const double* w, int32_t nsteps, double* dvals, double
     qw_state_free(lam);
     if (e != hipSuccess)
       return set_err(e == hipErrorOutOfMemory ? QW_ENOMEM : QW_EDEVICE, std::string("gradient: ") + hipGetErrorString(e));
+    return rc;
+  });
+}
+
+int qw_grad_noalloc(qw_state* st, const double* w, int32_t nsteps, double* dvals, double* db_re, double* db_im,
+                    double* loss, void* stream_v) {
+  return guarded([&]() -> int {
+    int rc = grad_check(st, w, nsteps);
+    if (rc) return rc;
+    hipStream_t stream = static_cast<hipStream_t>(stream_v);
+    qw_ctx* ctx = st->ctx;
+    if (!real_path(st) || !st->rbuf[0] || !st->rbuf[1])
+      return set_err(QW_ENOTSUP,
+                     "qw_grad_noalloc needs a state whose walk steps run on one double per cell and have run "
+                     "(a real symmetric matrix, a real b, one-pass launch shape, at least one step); use qw_grad");
+    // the library's device array: the adjoint state's two parity buffers of
+    // three 8-byte planes, the weights, dL/dv by home, dL/db, and the results
+    // in the caller's order, each on a 256-byte boundary
+    const auto up = [](size_t b) { return (b + 255) & ~size_t(255); };
+    const size_t planes = up(sizeof(double) * 3 * size_t(ctx->items));
+    const size_t need = 2 * planes + up(sizeof(double) * size_t(ctx->jtotal)) + up(sizeof(double) * size_t(ctx->items)) +
+                        up(sizeof(double2) * size_t(ctx->jtotal)) +
+                        up(sizeof(double) * size_t(ctx->nnz_total + 2 * ctx->ntotal));
+    void* base = nullptr;
+    size_t have = 0;
+    QW_HIP(qw::device_scratch(&base, &have));
+    if (need > have) {
+      char msg[256];
+      std::snprintf(msg, sizeof(msg),
+                    "qw_grad_noalloc: this context needs %zu bytes of the library's device array, which holds %zu "
+                    "(%lld slots); use qw_grad",
+                    need, have, static_cast<long long>(ctx->items));
+      return set_err_text(QW_EINVAL, msg);
+    }
+    char* p = static_cast<char*>(base);
+    const auto carve = [&](size_t bytes) {
+      char* q = p;
+      p += up(bytes);
+      return q;
+    };
+    // the adjoint state: a qw_state on the stack over two buffers of the
+    // array (its vectors stay empty; it holds no reference on the context
+    // and is never freed)
+    qw_state lam;
+    lam.ctx = ctx;
+    lam.counts = false;
+    lam.real_ok = true;
+    lam.in_real = true;
+    lam.rbuf[0] = reinterpret_cast<double*>(carve(planes));
+    lam.rbuf[1] = reinterpret_cast<double*>(carve(planes));
+    GradBufs gb;
+    gb.dw = reinterpret_cast<double*>(carve(sizeof(double) * size_t(ctx->jtotal)));
+    gb.dv = reinterpret_cast<double*>(carve(sizeof(double) * size_t(ctx->items)));
+    gb.db = reinterpret_cast<double2*>(carve(sizeof(double2) * size_t(ctx->jtotal)));
+    gb.dg = reinterpret_cast<double*>(carve(sizeof(double) * size_t(ctx->nnz_total + 2 * ctx->ntotal)));
+    rc = to_real(st, stream);  // the state's own 8-byte planes exist (checked above): a conversion at most
+    if (rc) return rc;
+    // the array keeps the last call's contents: clear what must start at 0
+    // (a fill kernel, not a memset: callers may capture this stream)
+    QW_HIP(qw::launch_fill(lam.rbuf[0], int64_t(2 * planes), stream));
+    QW_HIP(qw::launch_fill(gb.dw, int64_t(up(sizeof(double) * size_t(ctx->jtotal))), stream));
+    int64_t src = 0;
+    for (int32_t i = 0; i < ctx->ninst; ++i) {
+      const HostInst& hi = ctx->inst[i];
+      QW_HIP(hipMemcpyAsync(gb.dw + hi.jbase, w + src, sizeof(double) * hi.n, hipMemcpyHostToDevice, stream));
+      src += hi.n;
+    }
+    rc = grad_sweep(st, &lam, true, gb, nsteps, dvals, db_re, db_im, loss, stream);
+    (void)hipStreamSynchronize(stream);
     return rc;
   });
 }

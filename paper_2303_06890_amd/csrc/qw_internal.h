@@ -19,6 +19,10 @@ constexpr int kMaxWaves = kMaxGrid * (kMaxBlock / kWave);  // per-wavefront coun
 // shorter lanes for a launch that would not fill the chip.
 constexpr int kWideWaves = 2048;
 constexpr double kTau = 1e-13;  // pruning threshold applied after every step
+// Size of the device array `scratch` of the code object (one per device,
+// from the code object's load to qw_shutdown): the buffers of
+// qw_grad_noalloc.
+constexpr size_t kScratchBytes = size_t(32) << 20;
 
 // Per-instance facts, resident on the device.  The slots of instance i are
 // [item_base, item_base + N*s); the base is a multiple of 64 so that a
@@ -164,6 +168,10 @@ static_assert(sizeof(StepArgs) == 336 && offsetof(StepArgs, zskip) == 320 && off
               "StepArgs layout");
 static_assert(sizeof(AdjArgs) == 432 && offsetof(AdjArgs, wpb) == 416 && offsetof(AdjArgs, q0) == 424,
               "AdjArgs layout");
+
+// The current device's `scratch` array: its device address and size, looked
+// up on that device's module when the module is loaded (qw_launch.cpp).
+hipError_t device_scratch(void** ptr, size_t* bytes);
 
 // Launchers (qw_launch.cpp).  All enqueue on `stream` and allocate nothing.
 hipError_t launch_step(const StepArgs& a, int grid, int block, hipStream_t stream);

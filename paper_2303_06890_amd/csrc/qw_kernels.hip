@@ -46,6 +46,18 @@
 
 #include <hip/hip_runtime.h>
 
+// Device memory of qw_grad_noalloc: a fixed array of the code object, one
+// per device that loads it, held from the load to qw_shutdown.  No kernel
+// names it.  The host looks its address up on each device's module
+// (hipModuleGetGlobal, which needs an exported name; the `used` attribute
+// keeps the unreferenced array in the code object) and passes it to the
+// kernels as an ordinary pointer.
+// (A braced linkage block: `extern "C"` before a lone declaration would
+// make it a declaration, not a definition.)
+extern "C" {
+__device__ __attribute__((used)) __align__(256) unsigned char scratch[qw::kScratchBytes];
+}
+
 namespace qw {
 
 // ----------------------------------------------------------------- helpers

@@ -203,6 +203,8 @@ constexpr int kMaxDevices = 64;
 struct DeviceModule {
   hipModule_t mod;
   hipFunction_t fn[F_COUNT];
+  void* scratch;  // this device's copy of the code object's `scratch` array
+  size_t scratch_bytes;
   bool loaded;
 };
 
@@ -227,6 +229,19 @@ hipError_t function(Fn f, hipFunction_t* out) {
         return e;
       }
     }
+    // the address of this device's `scratch` array, looked up once per load
+    // with the device current (a host-side name would not be a device address)
+    // (a failed lookup leaves it unset: only qw_grad_noalloc needs it and
+    // reports the error)
+    void* sp = nullptr;
+    size_t sb = 0;
+    if (hipModuleGetGlobal(reinterpret_cast<hipDeviceptr_t*>(&sp), &sb, mod, "scratch") != hipSuccess ||
+        sb < kScratchBytes) {
+      sp = nullptr;
+      sb = 0;
+    }
+    d.scratch = sp;
+    d.scratch_bytes = sb;
     d.mod = mod;
     d.loaded = true;
   }
@@ -235,6 +250,19 @@ hipError_t function(Fn f, hipFunction_t* out) {
 }
 
 }  // namespace
+
+hipError_t device_scratch(void** ptr, size_t* bytes) {
+  hipFunction_t fn;
+  hipError_t e = function(F_FILL, &fn);  // loads the module on this device if needed
+  if (e != hipSuccess) return e;
+  int dev = 0;
+  e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  std::lock_guard<std::mutex> lock(g_mu);
+  *ptr = g_dev[dev].scratch;
+  *bytes = g_dev[dev].scratch_bytes;
+  return *ptr ? hipSuccess : hipErrorInvalidSymbol;
+}
 
 namespace {
 
