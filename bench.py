@@ -34,6 +34,7 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0
 TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "step_kernel_G16384x8_traffic.md")
 BATCHED_TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "batched_256_instances_traffic.md")
+E_TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "step_kernel_E_traffic.md")
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_2303_06890_amd", "csrc", f) for f in ("qw_kernels.hip", "qw_internal.h")]
 
 
@@ -299,6 +300,11 @@ def table1_leg(Q, W, autotune, tune: bool):
         fx = run(fcsc, fb, word)
         res["fixed_point"] = {"word_length": word, "us_per_step": fx["us_per_step"], "value": fx["value"],
                               "branches": fx["branches"], "launch_shape": fx["launch_shape"]}
+        if name == "E" and res["lanes_per_row"] == [8]:
+            # the counters were taken with eight lanes per row (one slot per lane in eight)
+            traffic = measured_traffic(E_TRAFFIC_PROFILE)
+            res["traffic"] = traffic
+            res["counter_gbs"] = traffic / (res["us_per_step"] * 1e-6) / 1e9 if traffic else None
         out[name] = res
     return out
 

@@ -239,10 +239,12 @@ struct qw_state {
   bool zclean = false;      // R0 and Q0 of the slots of value 0 are 0 (true from T~ |b~> on)
   // Real amplitudes (StepArgs::real): the state may live in 8-byte planes
   // (R0, Q0, Q1 of each parity buffer, allocated on first use) while it is
-  // only stepped; every other use moves it back to the complex planes.
+  // only stepped; every use that changes it otherwise moves it back to the
+  // complex planes, and a measurement reads a copy there (complex_copy).
   double* rbuf[2]{};
   bool real_ok = false;     // every amplitude is real (T~ |b~> of a real b)
   bool in_real = false;     // the state is in rbuf
+  bool cview = false;       // in_real, and the complex planes hold a copy of it
   int64_t steps_since_init = 0;
   int64_t launches = 0;     // step launches (walk steps and swaps)
   int block = 256;
@@ -350,15 +352,28 @@ int to_real(qw_state* st, hipStream_t stream) {
   return QW_OK;
 }
 
-// And back (every use other than a real walk step calls this first).
-int to_complex(qw_state* st, hipStream_t stream) {
-  if (!st->in_real) return QW_OK;
+// A copy of a state on the real planes in the complex planes, for uses that
+// only read it (measurements, the export): the state stays on the real
+// planes, so the next real walk step needs no conversion back.  The copy
+// stands until the real planes change (walk steps, the gradient sweep).
+int complex_copy(qw_state* st, hipStream_t stream) {
+  if (!st->in_real || st->cview) return QW_OK;
   const int64_t n = st->ctx->items;
   const double* val = st->ctx->sval;
   QW_HIP(qw::launch_to_complex(st->rbuf[st->cur], st->buf[st->cur].R0, val, n, stream));
   QW_HIP(qw::launch_to_complex(st->rbuf[st->cur] + n, st->buf[st->cur].Q0, nullptr, 2 * n, stream));
   QW_HIP(qw::launch_to_complex(st->rbuf[st->cur ^ 1] + 2 * n, st->buf[st->cur ^ 1].Q1, nullptr, n, stream));
+  st->cview = true;
+  return QW_OK;
+}
+
+// And back for good (every use that changes the state other than a real walk
+// step calls this first).
+int to_complex(qw_state* st, hipStream_t stream) {
+  int rc = complex_copy(st, stream);
+  if (rc) return rc;
   st->in_real = false;
+  st->cview = false;
   return QW_OK;
 }
 
@@ -459,6 +474,7 @@ int run_steps(qw_state* st, int64_t n, hipStream_t stream) {
   const bool real = real_path(st);
   int rc = real ? to_real(st, stream) : to_complex(st, stream);
   if (rc) return rc;
+  st->cview = false;
   const auto one = [&]() {
     --n;
     return real ? launch_real(st, stream, nullptr, nullptr) : launch_one(st, qw::kStep, stream);
@@ -504,6 +520,7 @@ int run_solver_steps(qw_state* st, int64_t n, hipStream_t stream, double2* yacc,
   const bool real = real_path(st);
   int rc = real ? to_real(st, stream) : to_complex(st, stream);
   if (rc) return rc;
+  st->cview = false;
   int64_t k = 0;  // launches of this call so far
   const auto one = [&]() {
     const double* coef = coefm + k;
@@ -1147,7 +1164,7 @@ int canonical_branches(const qw_ctx* ctx, const uint64_t* keys, const double* re
 }
 
 int measure_partials(qw_state* st, int kind, double* result, hipStream_t stream) {
-  int rc = to_complex(st, stream);
+  int rc = complex_copy(st, stream);
   if (rc) return rc;
   const int grid = 256;
   QW_HIP(qw::launch_measure(st->ctx->mat(), view(st), st->L, kind, st->mbuf, nullptr, grid, stream));
@@ -1258,6 +1275,7 @@ int grad_sweep(qw_state* st, qw_state* lam, bool real, const GradBufs& gb, int32
   const qw::Matrix mm = ctx->mat();
   double part[256];
   int rc = QW_OK;
+  st->cview = false;  // the sweep moves the real planes
   hipError_t e = qw::launch_fill(gb.dv, (sizeof(double) * ctx->items + 15) / 16 * 16, stream);
   if (e == hipSuccess && real) {
     rc = swap_real(st, stream);
@@ -1549,7 +1567,7 @@ int qw_measure(qw_state* st, int32_t kind, void* out, int64_t out_len, void* str
       case QW_PROJECT: {
         const int64_t need = kind == QW_J_MARGINAL ? ctx->jtotal : 2 * ctx->jtotal;
         if (out_len < need) return set_err(QW_EINVAL, "out_len too small");
-        int rc = to_complex(st, stream);
+        int rc = complex_copy(st, stream);
         if (rc) return rc;
         QW_HIP(qw::launch_fill(st->mbuf, (sizeof(double) * need + 15) / 16 * 16, stream));
         QW_HIP(qw::launch_measure(ctx->mat(), view(st), st->L, kind == QW_J_MARGINAL ? 2 : 3, nullptr,
@@ -1645,6 +1663,7 @@ int qw_state_import(qw_state* st, const uint64_t* keys, const double* re, const 
     st->zclean = false;  // imported branches may sit in R0 or Q0 of slots of value 0
     st->real_ok = false;
     st->in_real = false;  // state_clear empties the complex planes, which hold the state from here
+    st->cview = false;
     st->steps_since_init = 0;
     free_graphs(st);  // the list pointers and the kernel arguments change
     rc = import_branches(st, k, a, stream);

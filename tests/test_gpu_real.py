@@ -142,6 +142,33 @@ def test_switches_between_the_representations(Q, oracle_mod):
     assert st.stats()["real_amplitudes"]
 
 
+def test_measurements_leave_the_state_on_the_real_planes(Q):
+    """A measurement reads a copy of the real planes and leaves the state on
+    them: graph-replayed calls with measurements in between, a swap pass (on
+    the complex planes) right after a measurement, then more steps; the state
+    equals, bit for bit, one that was never measured."""
+    csc, b = W.offset_matrix(512, 6, seed=36), W.uniform_b(512)
+    walk = Q.Walk(csc)
+    a, g = walk.state(b), walk.state(b)
+    for n in (40, 1, 300, 33):
+        a.step(n)
+        a.count()
+        a.j_marginal()
+        assert a.stats()["real_amplitudes"]
+        a.project()
+        g.step(n)
+    a.step_adjoint(5)
+    g.step_adjoint(5)
+    a.count()
+    a.step(50)
+    g.step(50)
+    k1, a1 = a.export()
+    k2, a2 = g.export()
+    assert np.array_equal(k1, k2) and np.array_equal(a1, a2)
+    # the marginal is summed with atomics: equal up to the order of the sum
+    assert np.allclose(a.j_marginal(), g.j_marginal(), rtol=1e-13, atol=0)
+
+
 def test_branch_count_on_real_planes(Q):
     csc, b = W.band_matrix(256, 3, seed=35), W.uniform_b(256)
     walk = Q.Walk(csc)
