@@ -173,8 +173,10 @@ int qw_ctx_info(const qw_ctx* ctx, int32_t inst, int32_t* n_padded, int32_t* s, 
  * given, without the padding to N).  Computed on the host once and kept with
  * the context: for n <= 2048 (2n for complex values) exactly, by Householder
  * reduction to tridiagonal form and bisection on Sturm counts; beyond that
- * estimated by Lanczos on (A/s)^2 with full reorthogonalisation, accepted
- * when the residual bound of the smallest Ritz value is below 1e-9 of it.
+ * estimated by Lanczos with full reorthogonalisation, on A/s when its
+ * extreme Ritz values show it definite (the end of the spectrum nearest 0)
+ * and on (A/s)^2 otherwise (its smallest eigenvalue), accepted when the
+ * residual bound of that Ritz value is below 1e-9 of it.
  * Fixed-point data uses the matrix the rotations encode, sign(a) cos^2(theta)
  * per entry.  Synchronous, host only (about 1 s at n = 1024).
  * Errors: QW_EINVAL (NULL arguments, instance out of range, a singular

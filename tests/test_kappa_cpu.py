@@ -120,8 +120,8 @@ def test_fixed_point_angles_encode_cos_squared(shim):
 
 
 def test_lanczos_path(shim):
-    """n = 4096 > 2048: the Lanczos estimate on (A/s)^2 (5-point Laplacian on
-    64 x 64 + 0.1 I)."""
+    """n = 4096 > 2048: the Lanczos estimate (5-point Laplacian on 64 x 64 +
+    0.1 I, a definite matrix, so the iteration runs on A/s itself)."""
     csc = W.laplacian_2d(64, 0.1)
     rc, lam, err, _ = _kappa(shim, csc)
     assert rc == 0, err
