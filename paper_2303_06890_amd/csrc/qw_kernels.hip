@@ -683,22 +683,59 @@ __device__ __forceinline__ unsigned step_wave_real(const StepArgs& a, int64_t w,
   StepSlot rc[SLM];
   double x0[SLM], x1[SLM], f[SLM], g[SLM], y0[SLM];
   bool zero[SLM];
+  // Q0 of a slot without a partner (fillers at the edge of a band).  EQ0:
+  // issued with the other loads, not after the group sum, where a second
+  // round trip at the end of the wavefront cost 0.9 us per step on the
+  // paper's shape E.  Matrices where every slot has a partner (no Q0 cells)
+  // take the other form: the early load's code alone cost 6 % at 16384 x 8.
+  const bool skip0 = S == 0 && a.zskip;
+  if constexpr (S != 0) {
+    // One s for every instance: the loads come in two rounds.  First those
+    // of every slot that depend on nothing loaded (the record, R1, R0), all
+    // issued before any is used; then the Q0 loads, which depend on a record
+    // just read.  In one loop the compiler waited for each slot's record
+    // before issuing the next slot's loads: a memory round trip per slot
+    // held by the lane instead of two in all (shape E: 9.9 -> 9.4 us per
+    // step; B 2.27 -> 2.20, D 3.97 -> 3.87).  The first round keeps the words
+    // as loaded; they are decoded and scaled in the second.
+    uint32_t link[SLM];
 #pragma unroll
-  for (int i = 0; i < SLM; ++i) {
-    if (i < sl) {
-      h[i] = base + (int64_t(x.h * sl + i) << x.I.nlog) + x.j;
-      rc[i] = step_rec(a.m, h[i]);
-      x1[i] = R1[h[i]] * a.in.r1s;
-      zero[i] = S == 0 && a.zskip && rc[i].val == 0.0;
-      x0[i] = zero[i] ? 0.0 : R0[h[i]];
-      // Q0 of a slot without a partner (fillers at the edge of a band).
-      // EQ0: issued as soon as the slot's link is in, not after the group
-      // sum, where a second round trip at the end of the wavefront cost
-      // 0.9 us per step on the paper's shape E.  Matrices where every slot
-      // has a partner (no Q0 cells) take the other form: the early load's
-      // code alone cost 6 % at 16384 x 8.
-      y0[i] = 0.0;
-      if (EQ0 && !zero[i] && rc[i].part < 0) y0[i] = Q0[h[i]];
+    for (int i = 0; i < SLM; ++i) {
+      if (i < sl) {
+        h[i] = base + (int64_t(x.h * sl + i) << x.I.nlog) + x.j;
+        link[i] = a.m.slink[h[i]];
+        rc[i].val = a.m.sval[h[i]];
+        x1[i] = R1[h[i]];
+        x0[i] = R0[h[i]];
+      }
+    }
+    asm volatile("" ::: "memory");  // the second round's loads stay behind all of the first's
+#pragma unroll
+    for (int i = 0; i < SLM; ++i) {
+      if (i < sl) {
+        rc[i].part = int(link[i] & 0x7fffffffu) - 1;  // as step_rec
+        rc[i].upper = (link[i] >> 31) == 0u;
+        x1[i] *= a.in.r1s;
+        zero[i] = false;
+        y0[i] = 0.0;
+        if (EQ0 && rc[i].part < 0) y0[i] = Q0[h[i]];
+      }
+    }
+  } else {
+    // Mixed s (the batch): one loop, slot after slot.  The two rounds above
+    // made the HBM-bound 256-instance batch 0.5-1.7 % slower (26.6 against
+    // 26.1-26.4 us per step, A/B on one box).
+#pragma unroll
+    for (int i = 0; i < SLM; ++i) {
+      if (i < sl) {
+        h[i] = base + (int64_t(x.h * sl + i) << x.I.nlog) + x.j;
+        rc[i] = step_rec(a.m, h[i]);
+        x1[i] = R1[h[i]] * a.in.r1s;
+        zero[i] = skip0 && rc[i].val == 0.0;
+        x0[i] = zero[i] ? 0.0 : R0[h[i]];
+        y0[i] = 0.0;
+        if (EQ0 && !zero[i] && rc[i].part < 0) y0[i] = Q0[h[i]];
+      }
     }
   }
   // The solver's y_j, loaded with the data: it is not needed before the
@@ -997,15 +1034,27 @@ __device__ __forceinline__ unsigned adjoint_wave_real(const AdjArgs& a, int64_t 
   int64_t h[SLM];
   StepSlot rc[SLM];
   double x0[SLM], x1[SLM], m0[SLM], m1[SLM], f[SLM], g[SLM], y0[SLM], z0[SLM];
+  uint32_t link[SLM];
 #pragma unroll
-  for (int i = 0; i < SLM; ++i) {
+  for (int i = 0; i < SLM; ++i) {  // words as loaded, in two rounds (as in step_wave_real)
     if (i < sl) {
       h[i] = base + (int64_t(x.h * sl + i) << x.I.nlog) + x.j;
-      rc[i] = step_rec(a.m, h[i]);
-      x1[i] = R1[h[i]] * a.in.r1s;
+      link[i] = a.m.slink[h[i]];
+      rc[i].val = a.m.sval[h[i]];
+      x1[i] = R1[h[i]];
       x0[i] = R0[h[i]];
-      m1[i] = LR1[h[i]] * a.lin.r1s;
+      m1[i] = LR1[h[i]];
       m0[i] = LR0[h[i]];
+    }
+  }
+  asm volatile("" ::: "memory");
+#pragma unroll
+  for (int i = 0; i < SLM; ++i) {  // the loads that depend on a record, after all others
+    if (i < sl) {
+      rc[i].part = int(link[i] & 0x7fffffffu) - 1;  // as step_rec
+      rc[i].upper = (link[i] >> 31) == 0u;
+      x1[i] *= a.in.r1s;
+      m1[i] *= a.lin.r1s;
       y0[i] = z0[i] = 0.0;  // Q0 of slots without a partner, early or late (step_wave_real's EQ0)
       if (EQ0 && rc[i].part < 0) {
         y0[i] = Q0[h[i]];
