@@ -319,8 +319,10 @@ void qw_shutdown(void);
 /* Launch shape of the step kernel: workgroup size (64..256, a multiple of
  * 64) and number of workgroups, 1..65536 (a grid smaller than one pass over
  * the work makes the kernel stride); 0 keeps the current value (default: 256
- * and one pass, at most 65536).  Captured graphs are discarded.  Used by the
- * autotuner.  Errors: QW_EINVAL for sizes out of range. */
+ * and one pass, at most 65536).  Captured graphs are discarded, after the
+ * device has finished all work enqueued so far (a replay may still be
+ * running).  Used by the autotuner.  Errors: QW_EINVAL for sizes out of
+ * range. */
 int qw_set_launch(qw_state* st, int32_t wg_size, int32_t grid_limit);
 
 #ifdef __cplusplus

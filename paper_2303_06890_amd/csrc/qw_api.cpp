@@ -262,7 +262,12 @@ constexpr int kSingleMax = 32;  // calls (and remainders) of at most this many s
 constexpr size_t kMaxGraphs = 16;
 constexpr int kSolverGraphSteps = 64;  // the solver's graph (<= one wavefront's lanes: the window)
 
+// Destroy the state's graphs.  A replay may still be running on any of the
+// streams they were made for, and such a stream may since have been
+// destroyed by its owner, so the wait is for the whole device, not per stream.
 void free_graphs(qw_state* st) {
+  if (st->graphs.empty()) return;
+  (void)hipDeviceSynchronize();
   for (auto& g : st->graphs) (void)hipGraphExecDestroy(g.exec);
   st->graphs.clear();
 }
@@ -439,7 +444,8 @@ int replay_steps(qw_state* st, int len, int64_t reps, hipStream_t stream, bool r
     if (g.stream == stream && g.parity == st->cur && g.r1s == st->r1s && g.steps == len && g.real == real) ge = &g;
   if (!ge) {
     if (st->graphs.size() >= kMaxGraphs) {
-      QW_HIP(hipStreamSynchronize(stream));  // no replay of the evicted graph is still running
+      // no replay of the evicted graph may still run, on whichever stream it was made for
+      QW_HIP(hipDeviceSynchronize());
       (void)hipGraphExecDestroy(st->graphs.front().exec);
       st->graphs.erase(st->graphs.begin());
     }

@@ -85,3 +85,21 @@ def test_many_step_counts_keep_a_bounded_graph_cache(Q, oracle_mod):
             ok, oa = ost.export()
             compare_states(gk, ga, ok, oa, where=f"after {total} steps (count {n})")
     assert st.stats()["launches"] == total
+
+
+def test_launch_shape_change_behind_a_running_replay(Q):
+    """qw_set_launch discards the graphs while a replay may still run: it
+    waits for the device first.  A shape change right behind an enqueued
+    600-step call (no synchronisation), then more steps, equals the same
+    walk run straight through, bit for bit."""
+    csc, b = W.offset_matrix(2048, 8, seed=71), W.uniform_b(2048)
+    walk = Q.Walk(csc)
+    a, g = walk.state(b), walk.state(b)
+    a.set_launch(128, 0).step(600)
+    a.set_launch(256, 0)  # the one-pass kernels: the same arithmetic in another launch shape
+    a.step(300)
+    g.step(900)
+    k1, a1 = a.export()
+    k2, a2 = g.export()
+    assert np.array_equal(k1, k2) and np.array_equal(a1, a2)
+
