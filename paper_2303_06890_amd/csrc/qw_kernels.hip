@@ -172,21 +172,49 @@ __device__ __forceinline__ double dpp(double v) {
   return __hiloint2double(__builtin_amdgcn_update_dpp(0, hi, CTRL, 0xF, 0xF, false),
                           __builtin_amdgcn_update_dpp(0, lo, CTRL, 0xF, 0xF, false));
 }
-__device__ __forceinline__ double2 xor_add_8(double2 v) {  // lane ^ 8: rotate each row of 16 lanes by 8
-  return make_double2(v.x + dpp<0x128>(v.x), v.y + dpp<0x128>(v.y));
+// v plus its value in lane ^ 16 (lane ^ 32): gfx950's cross-row swaps
+// (v_permlane16_swap, v_permlane32_swap) exchange the two halves of each
+// pair of 16-lane rows (of the wavefront) in the vector ALU, where a lane
+// shuffle is an LDS round trip.  Both lanes of a pair add the same two
+// values in the same order, so their sums are bitwise identical.
+__device__ __forceinline__ double swap_add_16(double v) {
+  const unsigned lo = __double2loint(v), hi = __double2hiint(v);
+  const auto l = __builtin_amdgcn_permlane16_swap(lo, lo, false, false);
+  const auto h = __builtin_amdgcn_permlane16_swap(hi, hi, false, false);
+  return __hiloint2double(h[0], l[0]) + __hiloint2double(h[1], l[1]);
 }
-__device__ __forceinline__ double2 xor_add(double2 v, int off) {
-  return make_double2(v.x + __shfl_xor(v.x, off), v.y + __shfl_xor(v.y, off));
+__device__ __forceinline__ double swap_add_32(double v) {
+  const unsigned lo = __double2loint(v), hi = __double2hiint(v);
+  const auto l = __builtin_amdgcn_permlane32_swap(lo, lo, false, false);
+  const auto h = __builtin_amdgcn_permlane32_swap(hi, hi, false, false);
+  return __hiloint2double(h[0], l[0]) + __hiloint2double(h[1], l[1]);
 }
 // Sum over the lanes that hold one row in the step kernels: lanes
-// jj + h * 2^rpw_log, h < 2^(6 - rpw_log), rpw_log >= 2.  Every lane of a
-// row ends with the bitwise-identical sum (each stage adds a commuted pair).
-__device__ __forceinline__ double2 row_sum(double2 v, int rpw_log) {
-  if (rpw_log <= 2) v = xor_add(v, 4);
-  if (rpw_log <= 3) v = xor_add_8(v);
-  if (rpw_log <= 4) v = xor_add(v, 16);
-  if (rpw_log <= 5) v = xor_add(v, 32);
+// jj + h * 2^rpw_log, h < 2^(6 - rpw_log), rpw_log >= 2.  Within a row of
+// 16 lanes: + lane ^ 8 (a rotation by 8), then, for 16 lanes per row, + the
+// lane 4 further on (its sum of {l + 4, l + 12} against {l, l + 8}).  Across
+// rows: the swaps above when a lane holds at most two slots; with more, the
+// vector ALU is busy with the slots' square roots, and lane shuffles through
+// the LDS, another unit, are faster (per step: shapes B and C 6 % and 5 %
+// faster with the swaps, G(16384, 8) 1.5 %, the batch 1 %; shape E, eight
+// slots per lane, 2 % slower).  Every lane of a row ends with the
+// bitwise-identical sum (each stage adds a commuted pair).
+template <int SLM>
+__device__ __forceinline__ double row_sum_r(double v, int rpw_log) {
+  if (rpw_log <= 3) v += dpp<0x128>(v);
+  if (rpw_log <= 2) v += dpp<0x124>(v);
+  if constexpr (SLM <= 2) {
+    if (rpw_log <= 4) v = swap_add_16(v);
+    if (rpw_log <= 5) v = swap_add_32(v);
+  } else {
+    if (rpw_log <= 4) v += __shfl_xor(v, 16);
+    if (rpw_log <= 5) v += __shfl_xor(v, 32);
+  }
   return v;
+}
+template <int SLM>
+__device__ __forceinline__ double2 row_sum(double2 v, int rpw_log) {
+  return make_double2(row_sum_r<SLM>(v.x, rpw_log), row_sum_r<SLM>(v.y, rpw_log));
 }
 
 __device__ __forceinline__ int uniform(int v) { return __builtin_amdgcn_readfirstlane(v); }
@@ -493,7 +521,7 @@ __device__ __forceinline__ unsigned step_wave(const StepArgs& a, int64_t w, int 
       c = cadd(c, along(r[i], x0[i], x1[i]));
     }
   }
-  if (step) c = row_sum(c, x.rpw_log);
+  if (step) c = row_sum<SLM>(c, x.rpw_log);
   if (ACC && x.live && x.h == 0) {
     double2 yv = a.yacc[x.I.jbase + x.j];
     yv.x += coef * (c.x * x.I.inv_sqrt_s);
@@ -649,13 +677,6 @@ namespace qw {
 // instance) or the g kernels' (mixed s): one pass, every row exists, the
 // walk step only, and an empty list (T~ starts).
 
-__device__ __forceinline__ double row_sum_r(double v, int rpw_log) {
-  if (rpw_log <= 2) v += __shfl_xor(v, 4);
-  if (rpw_log <= 3) v += dpp<0x128>(v);
-  if (rpw_log <= 4) v += __shfl_xor(v, 16);
-  if (rpw_log <= 5) v += __shfl_xor(v, 32);
-  return v;
-}
 __device__ __forceinline__ double prune_r(double v, double tau, unsigned& cnt) {
   if (fabs(v) > tau) {
     ++cnt;
@@ -761,7 +782,7 @@ __device__ __forceinline__ unsigned step_wave_real(const StepArgs& a, int64_t w,
       c += f[i] * x0[i] + x1[i] * g[i];
     }
   }
-  c = row_sum_r(c, x.rpw_log);
+  c = row_sum_r<SLM>(c, x.rpw_log);
   if (ACC && x.h == 0) *yp = yv + coef * (c * x.I.inv_sqrt_s);  // the group sum is real: only Re y_j moves
   const double tc = c * two_over_s<S>(x.I);
   unsigned cnt = 0;
@@ -949,8 +970,8 @@ __device__ __forceinline__ void adjoint_wave(const AdjArgs& a, int64_t w, int la
       d = cadd(d, along(r[i], m0[i], m1[i]));
     }
   }
-  c = row_sum(c, x.rpw_log);
-  d = row_sum(d, x.rpw_log);
+  c = row_sum<SLM>(c, x.rpw_log);
+  d = row_sum<SLM>(d, x.rpw_log);
   if (!x.live) return;
   const double t = two_over_s<0>(x.I);
   const double2 tc = cscale(c, t), td = cscale(d, t);
@@ -1073,8 +1094,8 @@ __device__ __forceinline__ unsigned adjoint_wave_real(const AdjArgs& a, int64_t 
       d += f[i] * m0[i] + m1[i] * g[i];
     }
   }
-  c = row_sum_r(c, x.rpw_log);
-  d = row_sum_r(d, x.rpw_log);
+  c = row_sum_r<SLM>(c, x.rpw_log);
+  d = row_sum_r<SLM>(d, x.rpw_log);
   const double t = two_over_s<S>(x.I);
   const double tc = c * t, td = d * t;
   double* oR0 = reinterpret_cast<double*>(a.out.R0);
