@@ -158,9 +158,11 @@ struct qw_ctx {
   qw::SlotRec* rec = nullptr;
   uint32_t* slink = nullptr;
   double* sval = nullptr;
-  void* rec_raw = nullptr;   // allocations behind rec, slink and sval
+  double* sfg = nullptr;     // rotation table (Matrix::sfg), real matrices only
+  void* rec_raw = nullptr;   // allocations behind rec, slink, sval and sfg
   void* slink_raw = nullptr;
   void* sval_raw = nullptr;
+  void* sfg_raw = nullptr;
   double* vim = nullptr;          // imaginary parts by home (complex matrices only)
   bool complex_values = false;
   int32_t word = 0;               // fixed-point word length (0: FP64 values)
@@ -181,6 +183,7 @@ struct qw_ctx {
     m.rec = rec;
     m.slink = slink;
     m.sval = sval;
+    m.sfg = sfg;
     m.vim = vim;
     m.inst = dinst;
     m.wave_inst = wave_inst;
@@ -746,6 +749,7 @@ void ctx_release(qw_ctx* ctx) {
   ctx->alloc.put(ctx->rec_raw);
   ctx->alloc.put(ctx->slink_raw);
   ctx->alloc.put(ctx->sval_raw);
+  if (ctx->sfg_raw) ctx->alloc.put(ctx->sfg_raw);
   ctx->alloc.put(ctx->vim);
   ctx->alloc.put(ctx->dinst);
   ctx->alloc.put(ctx->wave_inst);
@@ -889,11 +893,13 @@ int load_impl(qw_ctx** out, int32_t ninst, const int32_t* n, const int64_t* colp
   ctx->rec = static_cast<qw::SlotRec*>(ctx->alloc.get_paged(sizeof(qw::SlotRec) * items, &ctx->rec_raw));
   ctx->slink = static_cast<uint32_t*>(ctx->alloc.get_paged(sizeof(uint32_t) * items, &ctx->slink_raw));
   ctx->sval = static_cast<double*>(ctx->alloc.get_paged(sizeof(double) * items, &ctx->sval_raw));
+  if (ctx->realsym)
+    ctx->sfg = static_cast<double*>(ctx->alloc.get_paged(2 * sizeof(double) * items, &ctx->sfg_raw));
   ctx->dinst = static_cast<qw::Inst*>(ctx->alloc.get(sizeof(qw::Inst) * ninst));
   ctx->wave_inst = static_cast<int32_t*>(ctx->alloc.get(sizeof(int32_t) * waves));
   if (vals_im) ctx->vim = static_cast<double*>(ctx->alloc.get(sizeof(double) * items));
   if (!ctx->col || !ctx->val || !ctx->rec || !ctx->slink || !ctx->sval || !ctx->dinst || !ctx->wave_inst ||
-      (vals_im && !ctx->vim)) {
+      (vals_im && !ctx->vim) || (ctx->realsym && !ctx->sfg)) {
     ctx_release(ctx);
     return set_err(QW_ENOMEM, "device allocation failed for the matrix");
   }
@@ -922,6 +928,7 @@ int load_impl(qw_ctx** out, int32_t ninst, const int32_t* n, const int64_t* colp
   if (e == hipSuccess) e = qw::launch_fill(ctx->slink, int64_t(sizeof(uint32_t)) * items, stream);
   if (e == hipSuccess) e = qw::launch_fill(ctx->sval, int64_t(sizeof(double)) * items, stream);
   if (e == hipSuccess) e = qw::launch_qbs_table(ctx->mat(), ctx->rec, ctx->slink, ctx->sval, stream);
+  if (e == hipSuccess && ctx->sfg) e = qw::launch_rot_table(ctx->mat(), ctx->sfg, stream);
   if (e == hipSuccess) e = hipStreamSynchronize(stream);  // host vectors go out of scope
   if (e != hipSuccess) {
     ctx_release(ctx);

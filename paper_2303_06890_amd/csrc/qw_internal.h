@@ -91,6 +91,12 @@ struct Matrix {
   // needs; sval is the value.
   const uint32_t* slink;
   const double* sval;
+  // The rotation of every slot of a real matrix, two doubles by home: f'
+  // (the +-i rule's sign taken into f for a negative value) and g, computed
+  // once at load exactly as the step kernels compute them (qwk_rot_table).
+  // Read by the one-double-per-cell kernels of one s with at most two slots
+  // per lane, in place of sval and two square roots.  NULL for complex values.
+  const double* sfg;
   const double* vim;         // imaginary parts of the values by home (NULL: a real matrix)
   const Inst* inst;
   const int32_t* wave_inst;  // instance of every step-kernel wavefront
@@ -163,10 +169,10 @@ static_assert(sizeof(Inst) == 56 && offsetof(Inst, inv_sqrt_s) == 48, "Inst layo
 static_assert(sizeof(Slots) == 40 && offsetof(Slots, r1s) == 32, "Slots layout");
 static_assert(sizeof(List) == 24 && offsetof(List, cap) == 20, "List layout");
 static_assert(sizeof(SlotRec) == 16 && offsetof(SlotRec, val) == 8, "SlotRec layout");
-static_assert(sizeof(Matrix) == 176 && offsetof(Matrix, inst0) == 120, "Matrix layout");
-static_assert(sizeof(StepArgs) == 336 && offsetof(StepArgs, zskip) == 320 && offsetof(StepArgs, q0) == 328,
+static_assert(sizeof(Matrix) == 184 && offsetof(Matrix, inst0) == 128, "Matrix layout");
+static_assert(sizeof(StepArgs) == 344 && offsetof(StepArgs, zskip) == 328 && offsetof(StepArgs, q0) == 336,
               "StepArgs layout");
-static_assert(sizeof(AdjArgs) == 432 && offsetof(AdjArgs, wpb) == 416 && offsetof(AdjArgs, q0) == 424,
+static_assert(sizeof(AdjArgs) == 440 && offsetof(AdjArgs, wpb) == 424 && offsetof(AdjArgs, q0) == 432,
               "AdjArgs layout");
 
 // The current device's `scratch` array: its device address and size, looked
@@ -178,6 +184,8 @@ hipError_t launch_step(const StepArgs& a, int grid, int block, hipStream_t strea
 hipError_t launch_adjoint(const AdjArgs& a, int grid, int block, hipStream_t stream);
 // Slot records of both kinds (the QBS of every reflected output, once per matrix).
 hipError_t launch_qbs_table(const Matrix& m, SlotRec* rec, uint32_t* slink, double* sval, hipStream_t stream);
+// Fill Matrix::sfg (2 doubles per slot) from slink and sval (after launch_qbs_table).
+hipError_t launch_rot_table(const Matrix& m, double* sfg, hipStream_t stream);
 hipError_t launch_init(const Matrix& m, const double2* b, Slots out, double tau, hipStream_t stream);
 hipError_t launch_fill(void* p, int64_t bytes, hipStream_t stream);
 // out[0 .. kSumBlocks) = partial sums of a[0 .. n) (the per-wavefront counters).

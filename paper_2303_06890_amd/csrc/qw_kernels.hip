@@ -704,6 +704,15 @@ __device__ __forceinline__ unsigned step_wave_real(const StepArgs& a, int64_t w,
   StepSlot rc[SLM];
   double x0[SLM], x1[SLM], f[SLM], g[SLM], y0[SLM];
   bool zero[SLM];
+  // Kernels of one s with at most two slots per lane read f' and g from the
+  // rotation table (Matrix::sfg, 16 bytes per slot) instead of the value
+  // (8 bytes) and two square roots: the cache-resident steps are bound by
+  // their chain of dependent operations (per step, A/B on one box:
+  // G(16384, 8) 2.58 -> 2.45 us, C -6 %, D with sixteen lanes -4 %).  With
+  // more slots per lane, or mixed s, the step is bound by bandwidth and the
+  // extra bytes cost more (shape E +7 %, the 256-instance batch +9 %).
+  constexpr bool kTab = S != 0 && SLM <= 2;
+  double2 fgv[SLM];
   // Q0 of a slot without a partner (fillers at the edge of a band).  EQ0:
   // issued with the other loads, not after the group sum, where a second
   // round trip at the end of the wavefront cost 0.9 us per step on the
@@ -725,7 +734,12 @@ __device__ __forceinline__ unsigned step_wave_real(const StepArgs& a, int64_t w,
       if (i < sl) {
         h[i] = base + (int64_t(x.h * sl + i) << x.I.nlog) + x.j;
         link[i] = a.m.slink[h[i]];
-        rc[i].val = a.m.sval[h[i]];
+        if constexpr (kTab) {
+          fgv[i] = reinterpret_cast<const double2*>(a.m.sfg)[h[i]];
+          rc[i].val = 0.0;  // not read: the table holds the rotation
+        } else {
+          rc[i].val = a.m.sval[h[i]];
+        }
         x1[i] = R1[h[i]];
         x0[i] = R0[h[i]];
       }
@@ -771,14 +785,19 @@ __device__ __forceinline__ unsigned step_wave_real(const StepArgs& a, int64_t w,
 #pragma unroll
   for (int i = 0; i < SLM; ++i) {
     if (i < sl) {
-      double q;
-      if (ENC == kEncAngle) {
-        sincospi(fabs(rc[i].val), &q, &g[i]);
+      if constexpr (kTab) {
+        f[i] = fgv[i].x;
+        g[i] = fgv[i].y;
       } else {
-        q = sqrt(fabs(rc[i].val));
-        g[i] = sqrt(1.0 - fabs(rc[i].val));
+        double q;
+        if (ENC == kEncAngle) {
+          sincospi(fabs(rc[i].val), &q, &g[i]);
+        } else {
+          q = sqrt(fabs(rc[i].val));
+          g[i] = sqrt(1.0 - fabs(rc[i].val));
+        }
+        f[i] = rc[i].val < 0.0 && !rc[i].upper ? -q : q;  // f' (the +-i rule's sign for a < 0)
       }
-      f[i] = rc[i].val < 0.0 && !rc[i].upper ? -q : q;  // f' (the +-i rule's sign for a < 0)
       c += f[i] * x0[i] + x1[i] * g[i];
     }
   }
@@ -927,6 +946,25 @@ extern "C" __global__ void __launch_bounds__(256) qwk_qbs_table(Matrix m, SlotRe
     rec[hh] = sr;
     slink[hh] = uint32_t(sr.part + 1) | (j > c ? 0x80000000u : 0u);  // part + 1 <= N s < 2^31
     sval[hh] = sr.val;
+  }
+}
+
+// Matrix::sfg: f' and g of every slot (by home, padding included), computed
+// from slink and sval exactly as step_wave_real computes them, so a kernel
+// that reads the table takes the same values bit for bit.
+extern "C" __global__ void __launch_bounds__(256) qwk_rot_table(Matrix m, double* sfg) {
+  const int64_t stride = int64_t(gridDim.x) * blockDim.x;
+  for (int64_t h = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; h < m.items; h += stride) {
+    const StepSlot rc = step_rec(m, h);
+    double q, g;
+    if (m.angles) {
+      sincospi(fabs(rc.val), &q, &g);
+    } else {
+      q = sqrt(fabs(rc.val));
+      g = sqrt(1.0 - fabs(rc.val));
+    }
+    sfg[2 * h] = rc.val < 0.0 && !rc.upper ? -q : q;
+    sfg[2 * h + 1] = g;
   }
 }
 

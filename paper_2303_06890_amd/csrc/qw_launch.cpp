@@ -102,6 +102,7 @@ enum Fn {
   F_WEIGHT_REAL,
   F_GRAD_INIT_REAL,
   F_GATHER_GRAD,
+  F_ROT_TABLE,
   F_COUNT
 };
 
@@ -161,7 +162,7 @@ const char* const kNames[] = {
     "qwk_adjoint_r32_q", "qwk_adjoint_r64_q", "qwk_adjoint_rg1_q", "qwk_adjoint_rg2_q", "qwk_adjoint_rg4_q",
     "qwk_adjoint_rg8_q", "qwk_adjoint_r16w_q", "qwk_adjoint_r32w_q", "qwk_adjoint_r64w_q",
     "qwk_swap_real",
-    "qwk_weight_real",  "qwk_grad_init_real", "qwk_gather_grad"};
+    "qwk_weight_real",  "qwk_grad_init_real", "qwk_gather_grad", "qwk_rot_table"};
 static_assert(sizeof(kNames) / sizeof(kNames[0]) == F_COUNT, "one kernel name per Fn");
 
 // 0..3 for slmax = 1, 2, 4, 8
@@ -311,6 +312,12 @@ hipError_t launch_adjoint(const AdjArgs& a, int grid, int block, hipStream_t str
                                      : F_ADJ_RG1 + width_index(a.m.slmax);
   void* p[] = {&c};
   return launch(Fn(f + (a.q0 ? int(F_ADJ_COUNT_) : 0)), grid, block, stream, p);
+}
+
+hipError_t launch_rot_table(const Matrix& m, double* sfg, hipStream_t stream) {
+  Matrix mm = m;
+  void* p[] = {&mm, &sfg};
+  return launch(F_ROT_TABLE, clamp_grid(m.items, 4096), 256, stream, p);
 }
 
 hipError_t launch_qbs_table(const Matrix& m, SlotRec* rec, uint32_t* slink, double* sval, hipStream_t stream) {
