@@ -158,7 +158,7 @@ struct qw_ctx {
   qw::SlotRec* rec = nullptr;
   uint32_t* slink = nullptr;
   double* sval = nullptr;
-  double* sfg = nullptr;     // rotation table (Matrix::sfg), real matrices only
+  double* sfg = nullptr;     // rotation table (Matrix::sfg): realsym or complex matrices
   void* rec_raw = nullptr;   // allocations behind rec, slink, sval and sfg
   void* slink_raw = nullptr;
   void* sval_raw = nullptr;
@@ -893,13 +893,14 @@ int load_impl(qw_ctx** out, int32_t ninst, const int32_t* n, const int64_t* colp
   ctx->rec = static_cast<qw::SlotRec*>(ctx->alloc.get_paged(sizeof(qw::SlotRec) * items, &ctx->rec_raw));
   ctx->slink = static_cast<uint32_t*>(ctx->alloc.get_paged(sizeof(uint32_t) * items, &ctx->slink_raw));
   ctx->sval = static_cast<double*>(ctx->alloc.get_paged(sizeof(double) * items, &ctx->sval_raw));
-  if (ctx->realsym)
-    ctx->sfg = static_cast<double*>(ctx->alloc.get_paged(2 * sizeof(double) * items, &ctx->sfg_raw));
+  const int64_t table_doubles = vals_im ? 4 : (ctx->realsym ? 2 : 0);  // per slot (Matrix::sfg)
+  if (table_doubles)
+    ctx->sfg = static_cast<double*>(ctx->alloc.get_paged(sizeof(double) * table_doubles * items, &ctx->sfg_raw));
   ctx->dinst = static_cast<qw::Inst*>(ctx->alloc.get(sizeof(qw::Inst) * ninst));
   ctx->wave_inst = static_cast<int32_t*>(ctx->alloc.get(sizeof(int32_t) * waves));
   if (vals_im) ctx->vim = static_cast<double*>(ctx->alloc.get(sizeof(double) * items));
   if (!ctx->col || !ctx->val || !ctx->rec || !ctx->slink || !ctx->sval || !ctx->dinst || !ctx->wave_inst ||
-      (vals_im && !ctx->vim) || (ctx->realsym && !ctx->sfg)) {
+      (vals_im && !ctx->vim) || (table_doubles && !ctx->sfg)) {
     ctx_release(ctx);
     return set_err(QW_ENOMEM, "device allocation failed for the matrix");
   }

@@ -91,11 +91,14 @@ struct Matrix {
   // needs; sval is the value.
   const uint32_t* slink;
   const double* sval;
-  // The rotation of every slot of a real matrix, two doubles by home: f'
-  // (the +-i rule's sign taken into f for a negative value) and g, computed
-  // once at load exactly as the step kernels compute them (qwk_rot_table).
-  // Read by the one-double-per-cell kernels of one s with at most two slots
-  // per lane, in place of sval and two square roots.  NULL for complex values.
+  // The rotation of every slot, computed once at load exactly as the step
+  // kernels compute it (qwk_rot_table), by home.  Real matrices (realsym):
+  // two doubles, f' (the +-i rule's sign taken into f for a negative value)
+  // and g, read by the one-double-per-cell kernels of one s with at most two
+  // slots per lane in place of sval and two square roots.  Complex values:
+  // four doubles, f (real, imaginary), g and 0, read by the complex kernels
+  // of one s with at most two slots per lane in place of sval, vim and the
+  // principal square root.  NULL otherwise.
   const double* sfg;
   const double* vim;         // imaginary parts of the values by home (NULL: a real matrix)
   const Inst* inst;

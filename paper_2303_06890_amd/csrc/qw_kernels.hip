@@ -498,12 +498,30 @@ __device__ __forceinline__ unsigned step_wave(const StepArgs& a, int64_t w, int 
   double vi[SLM];
   bool zero[SLM];
   Rot r[SLM];
+  // Complex values, one s, at most two slots per lane: the rotation comes
+  // from the table (Matrix::sfg, four doubles per slot) instead of the two
+  // value planes and the principal square root (as the real kernels'
+  // rotation table does, for the same reason: these steps are bound by
+  // their chain of dependent operations).
+  constexpr bool kTab = ENC == kEncComplex && S != 0 && SLM <= 2;
+  double2 tf[SLM], tg[SLM];
 #pragma unroll
   for (int i = 0; i < SLM; ++i) {
     if (i < sl) {
       h[i] = base + (int64_t(x.h * sl + i) << x.I.nlog) + x.j;
-      rc[i] = step_rec(a.m, h[i]);
-      if (ENC == kEncComplex) vi[i] = a.m.vim[h[i]];
+      if constexpr (kTab) {
+        const uint32_t link = a.m.slink[h[i]];
+        rc[i].part = int(link & 0x7fffffffu) - 1;  // as step_rec
+        rc[i].upper = (link >> 31) == 0u;
+        rc[i].val = 0.0;  // not read: the table holds the rotation
+        vi[i] = 0.0;
+        const double2* t = reinterpret_cast<const double2*>(a.m.sfg) + 2 * h[i];
+        tf[i] = t[0];
+        tg[i] = t[1];
+      } else {
+        rc[i] = step_rec(a.m, h[i]);
+        if (ENC == kEncComplex) vi[i] = a.m.vim[h[i]];
+      }
       x1[i] = r1_of(a.in, h[i]);
       // slots of value 0 (fillers): R0 stays 0 when the state allows it
       zero[i] = S == 0 && a.zskip && rc[i].val == 0.0 && (ENC != kEncComplex || vi[i] == 0.0);
@@ -515,9 +533,14 @@ __device__ __forceinline__ unsigned step_wave(const StepArgs& a, int64_t w, int 
 #pragma unroll
   for (int i = 0; i < SLM; ++i) {
     if (i < sl) {
-      r[i] = ENC == kEncComplex ? rot_cplx(rc[i].val, vi[i], rc[i].upper)
-             : ENC == kEncAngle ? rot_angle(rc[i].val, rc[i].upper)
-                                : rot_real(rc[i].val, rc[i].upper);
+      if constexpr (kTab) {
+        r[i].f = tf[i];
+        r[i].g = tg[i].x;
+      } else {
+        r[i] = ENC == kEncComplex ? rot_cplx(rc[i].val, vi[i], rc[i].upper)
+               : ENC == kEncAngle ? rot_angle(rc[i].val, rc[i].upper)
+                                  : rot_real(rc[i].val, rc[i].upper);
+      }
       c = cadd(c, along(r[i], x0[i], x1[i]));
     }
   }
@@ -949,13 +972,22 @@ extern "C" __global__ void __launch_bounds__(256) qwk_qbs_table(Matrix m, SlotRe
   }
 }
 
-// Matrix::sfg: f' and g of every slot (by home, padding included), computed
-// from slink and sval exactly as step_wave_real computes them, so a kernel
-// that reads the table takes the same values bit for bit.
+// Matrix::sfg: the rotation of every slot (by home, padding included),
+// computed from slink, sval and vim exactly as the step kernels compute it
+// (step_wave_real; rot_cplx in step_wave), so a kernel that reads the table
+// takes the same values bit for bit.
 extern "C" __global__ void __launch_bounds__(256) qwk_rot_table(Matrix m, double* sfg) {
   const int64_t stride = int64_t(gridDim.x) * blockDim.x;
   for (int64_t h = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; h < m.items; h += stride) {
     const StepSlot rc = step_rec(m, h);
+    if (m.vim) {
+      const Rot r = rot_cplx(rc.val, m.vim[h], rc.upper);
+      sfg[4 * h] = r.f.x;
+      sfg[4 * h + 1] = r.f.y;
+      sfg[4 * h + 2] = r.g;
+      sfg[4 * h + 3] = 0.0;
+      continue;
+    }
     double q, g;
     if (m.angles) {
       sincospi(fabs(rc.val), &q, &g);
