@@ -618,6 +618,10 @@ def main():
             "alg_bytes_per_launch": alg_bytes / args.steps,
             "avg_launch_us": launch_s * 1e6,
             "floors": floors,
+            "note": ("frac prices every branch read and written at 24 bytes (key and complex amplitude); "
+                     "this layout keeps one 8-byte double per branch with an implicit key, so frac can pass 1. "
+                     "counter_frac uses the bytes the counters measure; the step is bound by latency "
+                     "(floors: an empty kernel and a step-sized copy per launch in 256-launch graphs)"),
         },
         "us_per_step_repeats": repeats,
     }
