@@ -730,7 +730,8 @@ __device__ __forceinline__ unsigned step_wave_real(const StepArgs& a, int64_t w,
   // Kernels of one s with at most two slots per lane read f' and g from the
   // rotation table (Matrix::sfg, 16 bytes per slot) instead of the value
   // (8 bytes) and two square roots: the cache-resident steps are bound by
-  // their chain of dependent operations (per step, A/B on one box:
+  // their chain of dependent operations (per step, each pair of builds timed
+  // back to back on one GPU:
   // G(16384, 8) 2.58 -> 2.45 us, C -6 %, D with sixteen lanes -4 %).  With
   // more slots per lane, or mixed s, the step is bound by bandwidth and the
   // extra bytes cost more (shape E +7 %, the 256-instance batch +9 %).
@@ -782,7 +783,7 @@ __device__ __forceinline__ unsigned step_wave_real(const StepArgs& a, int64_t w,
   } else {
     // Mixed s (the batch): one loop, slot after slot.  The two rounds above
     // made the HBM-bound 256-instance batch 0.5-1.7 % slower (26.6 against
-    // 26.1-26.4 us per step, A/B on one box).
+    // 26.1-26.4 us per step, both builds timed back to back on one GPU).
 #pragma unroll
     for (int i = 0; i < SLM; ++i) {
       if (i < sl) {

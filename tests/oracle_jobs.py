@@ -2,8 +2,8 @@
 as soon as pytest has collected a test that needs one (tests/conftest.py),
 so that they overlap the GPU tests collected ahead of it.  The oracle's C
 calls release the interpreter lock.  Each job logs one line per walk step to
-oracle_jobs.log under the repository's gpurun_out/ (or the system's temporary
-directory), so that a long run shows progress."""
+oracle_jobs.log in the directory named by QW_TEST_LOG_DIR (else the system's
+temporary directory), so that a long run shows progress."""
 import os
 import tempfile
 import threading
@@ -18,8 +18,7 @@ _lock = threading.Lock()
 
 
 def _log_path():
-    root = os.environ.get("GRAFT_REPO_ROOT")
-    d = os.path.join(root, "gpurun_out") if root else tempfile.gettempdir()
+    d = os.environ.get("QW_TEST_LOG_DIR") or tempfile.gettempdir()
     os.makedirs(d, exist_ok=True)
     return os.path.join(d, "oracle_jobs.log")
 
