@@ -1723,6 +1723,9 @@ int qls_run(qw_ctx* ctx, const double* b, double kappa, double eps, int32_t j0_o
     // the solver works on instance 0 only
     std::vector<double> bfull(static_cast<size_t>(ctx->ntotal), 0.0);
     for (int32_t j = 0; j < ctx->inst[0].n; ++j) bfull[size_t(j)] = b[j];
+    // host buffers first: nothing below may throw while device resources are held
+    std::vector<double2> hy(static_cast<size_t>(ctx->jtotal));
+    std::vector<double> proj(2 * static_cast<size_t>(ctx->jtotal));
     qw_state* st = nullptr;
     int rc = qw_state_init(&st, ctx, bfull.data(), nullptr, 0, 0, stream_v);
     if (rc) return rc;
@@ -1730,8 +1733,6 @@ int qls_run(qw_ctx* ctx, const double* b, double kappa, double eps, int32_t j0_o
     const int64_t N = ctx->inst[0].N;
     double* dcoef = static_cast<double*>(ctx->alloc.get(sizeof(double) * coefm.size()));
     double2* y = static_cast<double2*>(ctx->alloc.get(sizeof(double2) * ctx->jtotal));
-    std::vector<double2> hy(static_cast<size_t>(ctx->jtotal));
-    std::vector<double> proj(2 * static_cast<size_t>(ctx->jtotal));
     hipError_t e = (dcoef && y) ? hipSuccess : hipErrorOutOfMemory;
     if (e == hipSuccess)
       e = hipMemcpyAsync(dcoef, coefm.data(), sizeof(double) * coefm.size(), hipMemcpyHostToDevice, stream);
