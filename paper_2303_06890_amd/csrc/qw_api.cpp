@@ -263,7 +263,7 @@ namespace {
 constexpr int kLongGraphSteps = 256;
 constexpr int kSingleMax = 32;  // calls (and remainders) of at most this many steps: single launches
 constexpr size_t kMaxGraphs = 16;
-constexpr int kSolverGraphSteps = 64;  // the solver's graph (<= one wavefront's lanes: the window)
+constexpr int kSolverGraphSteps = 256;  // the solver's graph (and the length of its coefficient window)
 
 // Destroy the state's graphs.  A replay may still be running on any of the
 // streams they were made for, and such a stream may since have been

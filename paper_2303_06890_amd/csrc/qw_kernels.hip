@@ -1293,9 +1293,9 @@ extern "C" __global__ void __launch_bounds__(256) qwk_sum_counts(const unsigned 
 }
 
 // The solver's coefficient window for a graph of `count` steps (one
-// wavefront, count <= 64): window[i] = table[*base + i], then *base += count.
-// Every lane reads *base in the one load ahead of lane 0's store, so the
-// update cannot overtake the reads.  With set >= 0 only *base = set.
+// wavefront): window[i] = table[*base + i], then *base += count.  Every lane
+// reads *base in the one load ahead of lane 0's store, so the update cannot
+// overtake the reads.  With set >= 0 only *base = set.
 extern "C" __global__ void __launch_bounds__(64) qwk_coef_window(const double* __restrict__ table, int64_t* base,
                                                                   double* window, int32_t count, int64_t set) {
   const int lane = threadIdx.x;
@@ -1304,7 +1304,7 @@ extern "C" __global__ void __launch_bounds__(64) qwk_coef_window(const double* _
     return;
   }
   const int64_t b = *base;
-  if (lane < count) window[lane] = table[b + lane];
+  for (int i = lane; i < count; i += kWave) window[i] = table[b + i];
   if (lane == 0) *base = b + count;
 }
 

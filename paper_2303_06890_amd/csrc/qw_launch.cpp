@@ -349,7 +349,7 @@ hipError_t launch_sum_counts(const unsigned long long* a, int64_t n, unsigned lo
 
 hipError_t launch_coef_window(const double* table, int64_t* base, double* window, int32_t count, int64_t set,
                               hipStream_t stream) {
-  if (count < 0 || count > kWave) return hipErrorInvalidValue;  // one wavefront fills the window
+  if (count < 0) return hipErrorInvalidValue;  // one wavefront fills the window, kWave entries at a time
   void* p[] = {&table, &base, &window, &count, &set};
   return launch(F_COEF_WINDOW, 1, kWave, stream, p);
 }

@@ -51,16 +51,16 @@ def test_long_runs_match_the_oracle(Q, oracle_mod, kind):
 
 
 def test_solver_graph_window(Q, oracle_mod):
-    """A solve of 2 j0 + 1 = 301 launches: one launch, four 64-step replays
-    with the window node ahead of each, 44 launches; equal to the oracle's
-    walk-based solve."""
+    """A solve of 2 j0 + 1 = 801 launches: one launch, three 256-step
+    replays with the window node ahead of each, 32 launches; equal to the
+    oracle's walk-based solve."""
     csc, b = W.offset_matrix(64, 4, seed=45), W.gaussian_b(64, seed=46)
-    kappa, j0 = 60.0, 150
+    kappa, j0 = 60.0, 400
     om = oracle_mod.OracleMatrix(csc)
     beta, _ = oracle_mod.schedule(kappa, 1e-3)
     y_ref = om.qls_walk(b, j0, oracle_mod.cks_coeffs(beta, j0))
     x, _, steps, yn = Q.Walk(csc).qls(b, kappa=kappa, eps=1e-3, j0=j0)
-    assert steps == 301
+    assert steps == 801
     y = yn * x
     assert np.abs(y - y_ref).max() <= 1e-12 * np.abs(y_ref).max()
 

@@ -109,7 +109,7 @@ def test_solver_projection_on_real_planes(Q, oracle_mod, word):
     else:
         a, other = W.offset_matrix(128, 6, seed=95), W.offset_matrix(64, 11, seed=96)
     b = W.gaussian_b(128, seed=97)
-    kappa, j0 = 40.0, 40  # 81 launches: one, a 64-step graph replay, 16 more
+    kappa, j0 = 40.0, 150  # 301 launches: one, a 256-step graph replay, 44 more
     om = oracle_mod.OracleMatrix(a, word=word)
     beta, _ = oracle_mod.schedule(kappa, 1e-3)
     y_ref = om.qls_walk(b, j0, oracle_mod.cks_coeffs(beta, j0))
