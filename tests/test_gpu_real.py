@@ -3,9 +3,9 @@ pair up (a symmetric one) and a real b, every amplitude of the walk from
 T~|b~> is real, except those of the R0 cells of slots of negative value,
 which are imaginary; the walk steps then run on 8-byte planes (the
 qwk_step_r / qwk_step_t kernels; qwk_step_rg / qwk_step_tg for instances of
-mixed s).  Every other use of the state
-(measurements, export, W^dagger, other launch shapes) moves it back to the
-complex planes.  Parity with the oracle across those switches, graph
+mixed s).  Uses that change the state otherwise (W^dagger, other launch
+shapes) move it back to the complex planes; measurements and the export read
+a copy there.  Parity with the oracle across those switches, graph
 replays, the branch count, negative values and fixed-point data."""
 import numpy as np
 import pytest
