@@ -205,6 +205,54 @@ def _timed(Q, fn):
     return _timed_on(torch, Q.stream(), fn)
 
 
+def host_inclusive_leg(Q, csc, b, lanes: int, shape, steps: int, updates_per_step: float, reps: int = 5):
+    """The same walk from host memory to host memory: the matrix loaded from
+    host CSC arrays (preprocessing and tables included), then, per job, the
+    state made from the host vector b, `steps` walk steps and the export of
+    every branch (packed keys and complex amplitudes) into host arrays.  Host
+    wall clock, median of `reps` jobs; a second pass with a synchronisation
+    after each part gives the split."""
+    import torch
+
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    walk = Q.Walk(csc, lanes=lanes)
+    torch.cuda.synchronize()
+    load_ms = (time.perf_counter() - t0) * 1e3
+
+    def job(split):
+        t = [time.perf_counter()]
+        st = walk.state(b)
+        if shape:
+            st.set_launch(*shape)
+        if split:
+            torch.cuda.synchronize()
+            t.append(time.perf_counter())
+        st.step(steps)
+        if split:
+            torch.cuda.synchronize()
+            t.append(time.perf_counter())
+        keys, amps = st.export()
+        t.append(time.perf_counter())
+        st.close()
+        return [1e3 * (y - x) for x, y in zip(t, t[1:])], keys.nbytes + amps.nbytes
+
+    job(False)  # captures the graph of this step count
+    jobs = sorted(job(False)[0][0] for _ in range(reps))
+    split, export_bytes = job(True)
+    ms = jobs[reps // 2]
+    walk.close()
+    return {
+        "what": "host b in, walk steps, every branch exported to host (keys + amplitudes); host wall clock",
+        "steps": steps,
+        "ms_per_job": ms,
+        "updates_per_s": updates_per_step * steps / (ms / 1e3),
+        "split_ms": {"state_from_host_b": split[0], "steps": split[1], "export_to_host": split[2]},
+        "export_bytes": export_bytes,
+        "matrix_load_ms": load_ms,
+    }
+
+
 def batched_leg(Q, W, autotune, tune: bool, steps: int = 50, cpu: bool = True):
     """256 instances (n = 2^U{6..12}, 4..16 entries per column, single-column
     starts) in one launch per step, against the same instances advanced one
@@ -570,6 +618,11 @@ def main():
     achieved = alg_bytes / args.steps / launch_s / 1e9
     traffic = measured_traffic()
     floors = launch_floors(torch)
+    if args.steps != 256:
+        # The same floors in graphs of the timed call's length: a short graph
+        # costs more per launch, and the timed call is one such graph.
+        floors.update({f"{k[:-3]}_{args.steps}_launch_graph_us": v
+                       for k, v in launch_floors(torch, args.steps).items()})
     value = out_total / (ms / 1e3)
     line = {
         "metric": "walk-step amplitude updates/s (16384-dim, 8 nnz/col)",
@@ -621,12 +674,15 @@ def main():
             "note": ("frac prices every branch read and written at 24 bytes (key and complex amplitude); "
                      "this layout keeps one 8-byte double per branch with an implicit key, so frac can pass 1. "
                      "counter_frac uses the bytes the counters measure; the step is bound by latency "
-                     "(floors: an empty kernel and a step-sized copy per launch in 256-launch graphs)"),
+                     "(floors: an empty kernel and a step-sized copy per launch in 256-launch graphs, "
+                     "and in graphs of the timed step count)"),
         },
         "us_per_step_repeats": repeats,
     }
     print(f"[bench] {args.steps} steps in {ms:.3f} ms (median of 5; {launch_s * 1e6:.2f} us/step), "
           f"{value:.3e} updates/s, {achieved:.0f} GB/s algorithmic", file=sys.stderr, flush=True)
+    line["host_inclusive"] = host_inclusive_leg(Q, csc, b, walk.lanes, shape, args.steps, out_total / args.steps)
+    print(f"[bench] host inclusive: {line['host_inclusive']}", file=sys.stderr, flush=True)
     if not args.no_extras:
         line["batched"] = batched_leg(Q, W, autotune, not args.no_tune, cpu=not args.no_cpu_baseline)
         print(f"[bench] batched: {line['batched']}", file=sys.stderr, flush=True)
