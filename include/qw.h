@@ -230,10 +230,19 @@ int qw_measure(qw_state* st, int32_t kind, void* out, int64_t out_len, void* str
 
 /* Copy the state to the host, sorted by key: the sparse representation of
  * Sec. V.A (every stored register tuple and its amplitude), with keys in the
- * layout above.  cap = size of the host arrays; *m receives the branch count
- * (QW_EINVAL with *m set if cap < count).  Synchronises the stream. */
+ * layout above.  The branches are compacted and sorted on the GPU (a radix
+ * sort; it takes about 48 bytes of device memory per branch for the call),
+ * then copied.  cap = size of the host arrays; *m receives the branch count
+ * (QW_EINVAL with *m set if cap < count).  re or im may be NULL.
+ * Synchronises the stream.  Errors: QW_EINVAL, QW_ENOMEM, QW_EDEVICE. */
 int qw_export(qw_state* st, uint64_t* keys, double* re, double* im, int64_t cap, int64_t* m,
               void* stream);
+
+/* qw_export with the amplitudes interleaved: amps[2 t] and amps[2 t + 1] are
+ * the real and imaginary parts of branch t (the layout of a C99 double
+ * complex or std::complex<double> array of cap elements), copied from the
+ * device without a split.  Same order, synchronisation and errors. */
+int qw_export_complex(qw_state* st, uint64_t* keys, double* amps, int64_t cap, int64_t* m, void* stream);
 
 /* Replace the state by the given branches (equal keys are summed; branches
  * whose |Re| and |Im| are both <= tau = 1e-13 are dropped, as after a step).  Keys must

@@ -279,13 +279,15 @@ class State:
                     total_written=int(o[4]), real_amplitudes=bool(o[5]), lanes_per_row_s16=int(o[6]))
 
     def export(self):
-        """(keys uint64 sorted, amplitudes complex128)."""
+        """(keys uint64 sorted, amplitudes complex128).  The library copies
+        keys and amplitudes into one pinned host buffer (torch's pinned
+        allocator), which both returned arrays share."""
         m = self.count()
-        keys = np.zeros(m, np.uint64)
-        re, im = np.zeros(m), np.zeros(m)
+        buf = _torch().empty(max(1, 3 * m), dtype=_torch().float64, pin_memory=True).numpy()
+        keys, amps = buf[:m].view(np.uint64), buf[m:3 * m]
         got = ctypes.c_int64()
-        check(_lib.load().qw_export(self._h, _up(keys), _dp(re), _dp(im), m, ctypes.byref(got), _stream()))
-        return keys[:got.value], (re + 1j * im)[:got.value]
+        check(_lib.load().qw_export_complex(self._h, _up(keys), _dp(amps), m, ctypes.byref(got), _stream()))
+        return keys[:got.value], amps.view(np.complex128)[:got.value]
 
     def import_(self, keys, amps) -> "State":
         keys = np.ascontiguousarray(keys, dtype=np.uint64)

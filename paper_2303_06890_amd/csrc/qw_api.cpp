@@ -1614,7 +1614,11 @@ int qw_measure(qw_state* st, int32_t kind, void* out, int64_t out_len, void* str
   });
 }
 
-int qw_export(qw_state* st, uint64_t* keys, double* re, double* im, int64_t cap, int64_t* m, void* stream_v) {
+namespace {
+
+// qw_export (re, im) and qw_export_complex (amps: re/im interleaved).
+int export_sorted(qw_state* st, uint64_t* keys, double* re, double* im, double* amps, int64_t cap, int64_t* m,
+                  void* stream_v) {
   return guarded([&]() -> int {
     if (!st || !m) return set_err(QW_EINVAL, "missing argument");
     hipStream_t stream = static_cast<hipStream_t>(stream_v);
@@ -1626,37 +1630,75 @@ int qw_export(qw_state* st, uint64_t* keys, double* re, double* im, int64_t cap,
     if (count == 0) return QW_OK;
     if (!keys) return set_err(QW_EINVAL, "keys is NULL");
     qw_ctx* ctx = st->ctx;
-    void* dk = ctx->alloc.get(sizeof(uint64_t) * count);
-    void* da = ctx->alloc.get(sizeof(double2) * count);
-    void* dc = ctx->alloc.get(256);
-    std::vector<uint64_t> hk(static_cast<size_t>(count));
-    std::vector<double2> ha(static_cast<size_t>(count));
-    uint32_t got = 0;
-    hipError_t e = (dk && da && dc) ? hipSuccess : hipErrorOutOfMemory;
+    // Branches are compacted on the GPU (in no fixed order), then sorted by
+    // key there: an LSD radix sort over the 8-bit digit windows that hold a
+    // bit on which the keys differ (qwk_key_bits), ping-ponging between two
+    // key/amplitude buffers.
+    const int64_t tiles = (count + qw::kSortTile - 1) / qw::kSortTile;
+    void* dk[2] = {ctx->alloc.get(sizeof(uint64_t) * count), ctx->alloc.get(sizeof(uint64_t) * count)};
+    void* da[2] = {ctx->alloc.get(sizeof(double2) * count), ctx->alloc.get(sizeof(double2) * count)};
+    void* dh = ctx->alloc.get(sizeof(uint32_t) * 256 * (tiles + 1));
+    void* dc = ctx->alloc.get(256);  // the append counter at 0, the key bits at 8 and 16
+    struct {
+      uint32_t got, pad;
+      unsigned long long bits[2];
+    } hc = {};
+    hipError_t e = (dk[0] && dk[1] && da[0] && da[1] && dh && dc) ? hipSuccess : hipErrorOutOfMemory;
     if (e == hipSuccess) e = qw::launch_fill(dc, 256, stream);
     if (e == hipSuccess)
-      e = qw::launch_export(ctx->mat(), view(st), st->L, static_cast<uint64_t*>(dk),
-                            static_cast<double2*>(da), static_cast<uint32_t*>(dc), uint32_t(count), stream);
-    if (e == hipSuccess) e = hipMemcpyAsync(&got, dc, sizeof(uint32_t), hipMemcpyDeviceToHost, stream);
-    if (e == hipSuccess) e = hipMemcpyAsync(hk.data(), dk, sizeof(uint64_t) * count, hipMemcpyDeviceToHost, stream);
-    if (e == hipSuccess) e = hipMemcpyAsync(ha.data(), da, sizeof(double2) * count, hipMemcpyDeviceToHost, stream);
+      e = qw::launch_export(ctx->mat(), view(st), st->L, static_cast<uint64_t*>(dk[0]),
+                            static_cast<double2*>(da[0]), static_cast<uint32_t*>(dc), uint32_t(count), stream);
+    unsigned long long* dbits = reinterpret_cast<unsigned long long*>(static_cast<char*>(dc) + 8);
+    if (e == hipSuccess) e = qw::launch_key_bits(static_cast<uint64_t*>(dk[0]), count, dbits, stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(&hc, dc, sizeof(hc), hipMemcpyDeviceToHost, stream);
     if (e == hipSuccess) e = hipStreamSynchronize(stream);
-    ctx->alloc.put(dk);
-    ctx->alloc.put(da);
-    ctx->alloc.put(dc);
+    int cur = 0;
+    if (e == hipSuccess && int64_t(hc.got) == count) {
+      const unsigned long long differ = hc.bits[0] & hc.bits[1];
+      uint32_t* hist = static_cast<uint32_t*>(dh);
+      for (int shift = 0; shift < 64 && e == hipSuccess;) {
+        if (!((differ >> shift) & 1ull)) {
+          ++shift;
+          continue;
+        }
+        e = qw::launch_radix_pass(static_cast<uint64_t*>(dk[cur]), static_cast<double2*>(da[cur]), count, shift,
+                                  hist + 256, hist, static_cast<uint64_t*>(dk[1 - cur]),
+                                  static_cast<double2*>(da[1 - cur]), stream);
+        cur = 1 - cur;
+        shift += 8;
+      }
+      if (e == hipSuccess) e = hipMemcpyAsync(keys, dk[cur], sizeof(uint64_t) * count, hipMemcpyDeviceToHost, stream);
+      if (amps) {
+        if (e == hipSuccess) e = hipMemcpyAsync(amps, da[cur], sizeof(double2) * count, hipMemcpyDeviceToHost, stream);
+      } else if (re || im) {
+        // Split into re and im planes in the other buffer, then each goes
+        // straight to the caller's array.
+        double* dre = static_cast<double*>(da[1 - cur]);
+        double* dim = dre + count;
+        if (e == hipSuccess) e = qw::launch_split_amps(static_cast<double2*>(da[cur]), count, dre, dim, stream);
+        if (e == hipSuccess && re) e = hipMemcpyAsync(re, dre, sizeof(double) * count, hipMemcpyDeviceToHost, stream);
+        if (e == hipSuccess && im) e = hipMemcpyAsync(im, dim, sizeof(double) * count, hipMemcpyDeviceToHost, stream);
+      }
+      if (e == hipSuccess) e = hipStreamSynchronize(stream);
+    }
+    for (void* p : {dk[0], dk[1], da[0], da[1], dh, dc}) ctx->alloc.put(p);
     if (e != hipSuccess)
       return set_err(e == hipErrorOutOfMemory ? QW_ENOMEM : QW_EDEVICE, std::string("export: ") + hipGetErrorString(e));
-    if (int64_t(got) != count) return set_err(QW_EDEVICE, "export count mismatch");
-    std::vector<int64_t> idx(static_cast<size_t>(count));
-    std::iota(idx.begin(), idx.end(), 0);
-    std::sort(idx.begin(), idx.end(), [&](int64_t a, int64_t b) { return hk[size_t(a)] < hk[size_t(b)]; });
-    for (int64_t t = 0; t < count; ++t) {
-      keys[t] = hk[size_t(idx[size_t(t)])];
-      if (re) re[t] = ha[size_t(idx[size_t(t)])].x;
-      if (im) im[t] = ha[size_t(idx[size_t(t)])].y;
-    }
+    if (int64_t(hc.got) != count) return set_err(QW_EDEVICE, "export count mismatch");
+    for (int64_t t = 1; t < count; ++t)  // every key is unique: strictly increasing
+      if (!(keys[t - 1] < keys[t])) return set_err(QW_EDEVICE, "export: keys out of order");
     return QW_OK;
   });
+}
+
+}  // namespace
+
+int qw_export(qw_state* st, uint64_t* keys, double* re, double* im, int64_t cap, int64_t* m, void* stream_v) {
+  return export_sorted(st, keys, re, im, nullptr, cap, m, stream_v);
+}
+
+int qw_export_complex(qw_state* st, uint64_t* keys, double* amps, int64_t cap, int64_t* m, void* stream_v) {
+  return export_sorted(st, keys, nullptr, nullptr, amps, cap, m, stream_v);
 }
 
 int qw_state_import(qw_state* st, const uint64_t* keys, const double* re, const double* im, int64_t m,

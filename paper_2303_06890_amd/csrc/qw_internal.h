@@ -23,6 +23,8 @@ constexpr double kTau = 1e-13;  // pruning threshold applied after every step
 // from the code object's load to qw_shutdown): the buffers of
 // qw_grad_noalloc.
 constexpr size_t kScratchBytes = size_t(32) << 20;
+// Keys per workgroup of the export's radix-sort passes (256 threads, 8 keys each).
+constexpr int kSortTile = 256 * 8;
 
 // Per-instance facts, resident on the device.  The slots of instance i are
 // [item_base, item_base + N*s); the base is a multiple of 64 so that a
@@ -211,6 +213,16 @@ hipError_t launch_measure(const Matrix& m, Slots st, List L, int32_t kind, doubl
                           hipStream_t stream);
 hipError_t launch_export(const Matrix& m, Slots st, List L, uint64_t* keys, double2* amps, uint32_t* count,
                          uint32_t cap, hipStream_t stream);
+// The export's key order.  launch_key_bits: bits[0] |= OR of keys[0 .. count),
+// bits[1] |= OR of their complements (bits[] zeroed by the caller).
+// launch_radix_pass: one stable counting-sort pass on the 8-bit digit at
+// `shift` moving (kin, vin) to (kout, vout); hist holds 256 counters per tile
+// of kSortTile keys, digit_base 256.
+hipError_t launch_key_bits(const uint64_t* keys, int64_t count, unsigned long long* bits, hipStream_t stream);
+hipError_t launch_radix_pass(const uint64_t* kin, const double2* vin, int64_t count, int shift, uint32_t* hist,
+                             uint32_t* digit_base, uint64_t* kout, double2* vout, hipStream_t stream);
+// re[i], im[i] = a[i] for i < n.
+hipError_t launch_split_amps(const double2* a, int64_t n, double* re, double* im, hipStream_t stream);
 // Place unique branches at their homes; keys with no static home are appended
 // to the list (count in *lcnt, which must start at 0).
 hipError_t launch_import(const Matrix& m, const uint64_t* keys, const double2* amps, int64_t n, Slots out, List L,

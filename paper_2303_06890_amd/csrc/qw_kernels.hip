@@ -1504,6 +1504,143 @@ extern "C" __global__ void __launch_bounds__(256) qwk_import(Matrix m, const uin
   }
 }
 
+// ----------------------------------------------------------------- export order
+//
+// The export hands branches over in key order; the compacted append leaves
+// them in the order the wavefronts finished.  A least-significant-digit radix
+// sort puts them in order on the GPU: 8-bit digits, one pass for each digit
+// window that holds a bit on which some keys differ (bits every key shares
+// cannot change the order, so those windows are skipped), each pass a stable
+// counting sort over tiles of kSortTile keys: per-tile digit counts, their
+// offsets, then a scatter that ranks equal digits in input order.
+
+// bits[0] |= OR of the keys, bits[1] |= OR of their complements (so the
+// bits on which the keys differ are bits[0] & bits[1]).  bits[] start at 0.
+extern "C" __global__ void __launch_bounds__(256) qwk_key_bits(const uint64_t* keys, int64_t count,
+                                                               unsigned long long* bits) {
+  unsigned long long o = 0, z = 0;
+  const int64_t stride = int64_t(gridDim.x) * blockDim.x;
+  for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < count; i += stride) {
+    o |= keys[i];
+    z |= ~keys[i];
+  }
+  for (int d = 1; d < kWave; d <<= 1) {
+    o |= __shfl_xor(o, d);
+    z |= __shfl_xor(z, d);
+  }
+  if ((threadIdx.x & (kWave - 1)) == 0) {
+    atomicOr(&bits[0], o);
+    atomicOr(&bits[1], z);
+  }
+}
+
+// hist[tile * 256 + d] = keys of the tile whose digit (key >> shift) & 255 is d.
+// One workgroup of 256 per tile.
+extern "C" __global__ void __launch_bounds__(256) qwk_radix_hist(const uint64_t* keys, int64_t count, int shift,
+                                                                 uint32_t* hist) {
+  __shared__ uint32_t h[256];
+  h[threadIdx.x] = 0;
+  __syncthreads();
+  const int64_t base = int64_t(blockIdx.x) * kSortTile;
+  for (int t = 0; t < kSortTile / 256; ++t) {
+    const int64_t i = base + t * 256 + threadIdx.x;
+    if (i < count) atomicAdd(&h[(keys[i] >> shift) & 255u], 1u);
+  }
+  __syncthreads();
+  hist[int64_t(blockIdx.x) * 256 + threadIdx.x] = h[threadIdx.x];
+}
+
+// One workgroup of 256 (thread d owns digit d): hist[tile * 256 + d] becomes
+// the number of keys of digit d in the tiles before it, and digit_base[d] the
+// number of keys of a smaller digit.
+extern "C" __global__ void __launch_bounds__(256) qwk_radix_offsets(uint32_t* hist, int64_t tiles,
+                                                                    uint32_t* digit_base) {
+  __shared__ uint32_t s[256];
+  const int d = threadIdx.x;
+  uint32_t run = 0;
+  for (int64_t b = 0; b < tiles; ++b) {
+    const uint32_t c = hist[b * 256 + d];
+    hist[b * 256 + d] = run;
+    run += c;
+  }
+  s[d] = run;
+  __syncthreads();
+  for (int off = 1; off < 256; off <<= 1) {  // inclusive scan over the digits
+    const uint32_t v = d >= off ? s[d - off] : 0u;
+    __syncthreads();
+    s[d] += v;
+    __syncthreads();
+  }
+  digit_base[d] = s[d] - run;
+}
+
+// Scatter of one pass.  Keys are taken in input order: tile, then 256-key
+// row t, then wavefront, then lane.  A lane's rank among the lanes of its
+// wavefront with the same digit comes from eight ballots (one per digit
+// bit); the counts of the wavefronts before it and of the rows before t
+// (run[]) are kept in LDS.  Equal digits thus keep their input order, which
+// makes each pass stable.
+extern "C" __global__ void __launch_bounds__(256) qwk_radix_scatter(const uint64_t* kin, const double2* vin,
+                                                                    int64_t count, int shift, const uint32_t* hist,
+                                                                    const uint32_t* digit_base, uint64_t* kout,
+                                                                    double2* vout) {
+  __shared__ uint32_t run[256];
+  __shared__ uint32_t wc[256 / kWave][256];
+  const int tid = threadIdx.x;
+  const int lane = tid & (kWave - 1);
+  const int wave = tid >> 6;
+  const uint64_t below = (uint64_t(1) << lane) - 1;
+  run[tid] = hist[int64_t(blockIdx.x) * 256 + tid] + digit_base[tid];
+  const int64_t base = int64_t(blockIdx.x) * kSortTile;
+  for (int t = 0; t < kSortTile / 256; ++t) {
+#pragma unroll
+    for (int w = 0; w < 256 / kWave; ++w) wc[w][tid] = 0;
+    __syncthreads();
+    const int64_t i = base + t * 256 + tid;
+    const bool ok = i < count;
+    uint64_t k = 0;
+    double2 v = zero2();
+    int d = 0;
+    if (ok) {
+      k = kin[i];
+      v = vin[i];
+      d = int((k >> shift) & 255u);
+    }
+    uint64_t peer = __ballot(ok);
+#pragma unroll
+    for (int bit = 0; bit < 8; ++bit) {
+      const uint64_t set = __ballot((d >> bit) & 1);
+      peer &= ((d >> bit) & 1) ? set : ~set;
+    }
+    const uint32_t rank = __popcll(peer & below);
+    if (ok && rank == 0) wc[wave][d] = __popcll(peer);
+    __syncthreads();
+    if (ok) {
+      uint32_t dst = run[d] + rank;
+      for (int w = 0; w < wave; ++w) dst += wc[w][d];
+      if (int64_t(dst) < count) {
+        kout[dst] = k;
+        vout[dst] = v;
+      }
+    }
+    __syncthreads();
+    uint32_t add = 0;
+#pragma unroll
+    for (int w = 0; w < 256 / kWave; ++w) add += wc[w][tid];
+    run[tid] += add;
+  }
+}
+
+// re[i], im[i] = a[i] (the export's amplitudes into the caller's two arrays).
+extern "C" __global__ void __launch_bounds__(256) qwk_split_amps(const double2* a, int64_t n, double* re, double* im) {
+  const int64_t stride = int64_t(gridDim.x) * blockDim.x;
+  for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += stride) {
+    const double2 v = a[i];
+    re[i] = v.x;
+    im[i] = v.y;
+  }
+}
+
 // ----------------------------------------------------------------- gradient set-up and finish
 
 // Lambda = diag(w[k register]) Psi for a state kept S-conjugated (the j

@@ -103,6 +103,11 @@ enum Fn {
   F_GRAD_INIT_REAL,
   F_GATHER_GRAD,
   F_ROT_TABLE,
+  F_KEY_BITS,
+  F_RADIX_HIST,
+  F_RADIX_OFFSETS,
+  F_RADIX_SCATTER,
+  F_SPLIT_AMPS,
   F_COUNT
 };
 
@@ -162,7 +167,9 @@ const char* const kNames[] = {
     "qwk_adjoint_r32_q", "qwk_adjoint_r64_q", "qwk_adjoint_rg1_q", "qwk_adjoint_rg2_q", "qwk_adjoint_rg4_q",
     "qwk_adjoint_rg8_q", "qwk_adjoint_r16w_q", "qwk_adjoint_r32w_q", "qwk_adjoint_r64w_q",
     "qwk_swap_real",
-    "qwk_weight_real",  "qwk_grad_init_real", "qwk_gather_grad", "qwk_rot_table"};
+    "qwk_weight_real",  "qwk_grad_init_real", "qwk_gather_grad", "qwk_rot_table",
+    "qwk_key_bits",     "qwk_radix_hist",   "qwk_radix_offsets", "qwk_radix_scatter",
+    "qwk_split_amps"};
 static_assert(sizeof(kNames) / sizeof(kNames[0]) == F_COUNT, "one kernel name per Fn");
 
 // 0..3 for slmax = 1, 2, 4, 8
@@ -381,6 +388,41 @@ hipError_t launch_export(const Matrix& m, Slots st, List L, uint64_t* keys, doub
   Matrix mm = m;
   void* p[] = {&mm, &st, &L, &keys, &amps, &count, &cap};
   return launch(F_EXPORT, 1024, 256, stream, p);
+}
+
+hipError_t launch_key_bits(const uint64_t* keys, int64_t count, unsigned long long* bits, hipStream_t stream) {
+  const uint64_t* k = keys;
+  int64_t n = count;
+  void* p[] = {&k, &n, &bits};
+  return launch(F_KEY_BITS, clamp_grid(n, 1024), 256, stream, p);
+}
+
+hipError_t launch_radix_pass(const uint64_t* kin, const double2* vin, int64_t count, int shift, uint32_t* hist,
+                             uint32_t* digit_base, uint64_t* kout, double2* vout, hipStream_t stream) {
+  if (count <= 0) return hipSuccess;
+  int64_t tiles = (count + kSortTile - 1) / kSortTile;
+  if (tiles > int64_t(INT32_MAX)) return hipErrorInvalidValue;
+  const uint64_t* ki = kin;
+  const double2* vi = vin;
+  int64_t n = count;
+  int sh = shift;
+  void* ph[] = {&ki, &n, &sh, &hist};
+  hipError_t e = launch(F_RADIX_HIST, int(tiles), 256, stream, ph);
+  if (e != hipSuccess) return e;
+  void* po[] = {&hist, &tiles, &digit_base};
+  e = launch(F_RADIX_OFFSETS, 1, 256, stream, po);
+  if (e != hipSuccess) return e;
+  const uint32_t* h = hist;
+  const uint32_t* db = digit_base;
+  void* ps[] = {&ki, &vi, &n, &sh, &h, &db, &kout, &vout};
+  return launch(F_RADIX_SCATTER, int(tiles), 256, stream, ps);
+}
+
+hipError_t launch_split_amps(const double2* a, int64_t n, double* re, double* im, hipStream_t stream) {
+  const double2* aa = a;
+  int64_t nn = n;
+  void* p[] = {&aa, &nn, &re, &im};
+  return launch(F_SPLIT_AMPS, clamp_grid(n, 2048), 256, stream, p);
 }
 
 hipError_t launch_import(const Matrix& m, const uint64_t* keys, const double2* amps, int64_t n, Slots out, List L,
