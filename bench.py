@@ -212,6 +212,7 @@ def host_inclusive_leg(Q, csc, b, lanes: int, shape, steps: int, updates_per_ste
     every branch (packed keys and complex amplitudes) into host arrays.  Host
     wall clock, median of `reps` jobs; a second pass with a synchronisation
     after each part gives the split."""
+    import numpy as np
     import torch
 
     torch.cuda.synchronize()
@@ -241,6 +242,17 @@ def host_inclusive_leg(Q, csc, b, lanes: int, shape, steps: int, updates_per_ste
     jobs = sorted(job(False)[0][0] for _ in range(reps))
     split, export_bytes = job(True)
     ms = jobs[reps // 2]
+    # The way back: the exported branches imported into a fresh state.
+    st = walk.state(b)
+    keys, amps = st.step(steps).export()
+    st.close()
+    imp = walk.state(np.zeros(len(b)))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    imp.import_(keys, amps)
+    torch.cuda.synchronize()
+    import_ms = (time.perf_counter() - t0) * 1e3
+    imp.close()
     walk.close()
     return {
         "what": "host b in, walk steps, every branch exported to host (keys + amplitudes); host wall clock",
@@ -249,6 +261,7 @@ def host_inclusive_leg(Q, csc, b, lanes: int, shape, steps: int, updates_per_ste
         "updates_per_s": updates_per_step * steps / (ms / 1e3),
         "split_ms": {"state_from_host_b": split[0], "steps": split[1], "export_to_host": split[2]},
         "export_bytes": export_bytes,
+        "import_of_export_ms": import_ms,
         "matrix_load_ms": load_ms,
     }
 

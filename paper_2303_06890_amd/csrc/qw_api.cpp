@@ -1140,13 +1140,22 @@ int canonical_branches(const qw_ctx* ctx, const uint64_t* keys, const double* re
                        std::vector<uint64_t>& ok, std::vector<double2>& oa) {
   const int n = ctx->nbits;
   const uint64_t nm = (uint64_t(1) << n) - 1;
-  std::vector<int64_t> idx(static_cast<size_t>(m));
-  std::iota(idx.begin(), idx.end(), 0);
-  std::sort(idx.begin(), idx.end(), [&](int64_t a, int64_t b) { return keys[a] < keys[b]; });
+  // Keys in strictly increasing order (an exported state) need no sort:
+  // they are already unique and in order.
+  bool in_order = true;
+  for (int64_t t = 1; t < m && in_order; ++t) in_order = keys[t - 1] < keys[t];
+  std::vector<int64_t> idx;
+  if (!in_order) {
+    idx.resize(static_cast<size_t>(m));
+    std::iota(idx.begin(), idx.end(), 0);
+    std::sort(idx.begin(), idx.end(), [&](int64_t a, int64_t b) { return keys[a] < keys[b]; });
+  }
   ok.clear();
   oa.clear();
+  ok.reserve(static_cast<size_t>(m));
+  oa.reserve(static_cast<size_t>(m));
   for (int64_t t = 0; t < m; ++t) {
-    const int64_t i = idx[size_t(t)];
+    const int64_t i = in_order ? t : idx[size_t(t)];
     const uint64_t key = keys[i];
     const uint64_t inst = key >> (4 * n + 2);
     if (inst >= uint64_t(ctx->ninst)) return set_err(QW_EINVAL, "key with an instance index out of range");
