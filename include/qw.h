@@ -233,7 +233,8 @@ int qw_measure(qw_state* st, int32_t kind, void* out, int64_t out_len, void* str
  * layout above.  The branches are compacted and sorted on the GPU (a radix
  * sort; it takes about 48 bytes of device memory per branch for the call),
  * then copied.  cap = size of the host arrays; *m receives the branch count
- * (QW_EINVAL with *m set if cap < count).  re or im may be NULL.
+ * (QW_EINVAL with *m set if cap < count, or if count > 2^32 - 1).  re or im
+ * may be NULL.
  * Synchronises the stream.  Errors: QW_EINVAL, QW_ENOMEM, QW_EDEVICE. */
 int qw_export(qw_state* st, uint64_t* keys, double* re, double* im, int64_t cap, int64_t* m,
               void* stream);

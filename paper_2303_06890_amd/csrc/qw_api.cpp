@@ -1638,6 +1638,8 @@ int export_sorted(qw_state* st, uint64_t* keys, double* re, double* im, double* 
     if (cap < count) return set_err(QW_EINVAL, "output arrays too small: " + std::to_string(count) + " branches");
     if (count == 0) return QW_OK;
     if (!keys) return set_err(QW_EINVAL, "keys is NULL");
+    if (count > int64_t(UINT32_MAX))  // the compaction and the sort count in 32 bits
+      return set_err(QW_EINVAL, "export of more than 2^32 - 1 branches");
     qw_ctx* ctx = st->ctx;
     // Branches are compacted on the GPU (in no fixed order), then sorted by
     // key there: an LSD radix sort over the 8-bit digit windows that hold a
