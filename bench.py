@@ -74,19 +74,26 @@ def cpu_baseline(csc, b, steps: int):
 
     om = oracle.OracleMatrix(csc)
     ost = oracle.OracleState(om).set_b(b).T()
-    written = 0
-    t0 = time.perf_counter()
-    for _ in range(steps):
-        ost.step(1)
-        written += ost.count()
-    dt = time.perf_counter() - t0
+    # The oracle runs on the calling thread: pin it to one core while timed.
+    saved = os.sched_getaffinity(0)
+    core = min(saved)
+    os.sched_setaffinity(0, {core})
+    try:
+        written = 0
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            ost.step(1)
+            written += ost.count()
+        dt = time.perf_counter() - t0
+    finally:
+        os.sched_setaffinity(0, saved)
     return {
         "value": written / dt,
         "unit": "amplitude updates/s",
         "cores": 1,
         "kind": "oracle",
         "sample": f"T~|b~> then {steps} walk steps of the same 16384-dim workload "
-                  f"({written} branch updates in {dt:.1f} s), one thread on {cpu_model()} "
+                  f"({written} branch updates in {dt:.1f} s), one thread pinned to core {core} of {cpu_model()} "
                   f"(nproc={os.cpu_count()})",
     }
 
