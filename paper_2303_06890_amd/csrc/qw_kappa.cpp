@@ -5,7 +5,9 @@
 //
 // Two methods, chosen by size:
 //   * dimension <= kDenseMax: the dense matrix is reduced to tridiagonal form
-//     by Householder reflections (Golub & Van Loan, Sec. 8.3.1) and the
+//     by Householder reflections (Golub & Van Loan, Sec. 8.3.1; on the lower
+//     triangle, the rows shared by a team of host threads in fixed chunks, so
+//     that the result does not depend on the thread count) and the
 //     eigenvalue of least magnitude is located by bisection on Sturm counts
 //     (the number of negative pivots of T - x I is the number of eigenvalues
 //     below x; Golub & Van Loan, Sec. 8.4.1).  Exact up to rounding.
@@ -20,12 +22,16 @@
 // [[X, -Y], [Y, X]], whose spectrum is that of A with every eigenvalue twice.
 #include "qw_kappa.h"
 
+#include <sched.h>
+
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <cstdint>
 #include <limits>
 #include <map>
 #include <string>
+#include <thread>
 #include <utility>
 #include <vector>
 
@@ -34,6 +40,10 @@ namespace {
 
 constexpr int64_t kDenseMax = 2048;
 constexpr int kLanczosMax = 600;
+// The dense reduction splits the rows of each trailing block into kChunks
+// fixed chunks; from kThreadedMin rows on, a team of host threads shares them.
+constexpr int kChunks = 16;
+constexpr int64_t kThreadedMin = 256;
 
 // Sparse real symmetric matrix of dimension m as coordinate triplets.
 struct Coo {
@@ -117,51 +127,164 @@ double tridiag_min(const std::vector<double>& d, const std::vector<double>& e) {
   return hi;
 }
 
-// Householder reduction of the dense symmetric a (m x m, row-major, full
-// storage, overwritten) to the tridiagonal (d, e).
+// Threads of the dense reduction: the CPUs this process may run on, at most
+// kChunks.
+int host_threads() {
+  cpu_set_t set;
+  CPU_ZERO(&set);
+  const int n = sched_getaffinity(0, sizeof(set), &set) == 0 ? CPU_COUNT(&set) : 1;
+  return std::max(1, std::min(n, kChunks));
+}
+
+// A barrier for the threads of one reduction (they spin, then yield).
+class SpinBarrier {
+ public:
+  explicit SpinBarrier(int n) : n_(n) {}
+  void wait() {
+    const int g = gen_.load(std::memory_order_acquire);
+    if (count_.fetch_add(1, std::memory_order_acq_rel) == n_ - 1) {
+      count_.store(0, std::memory_order_relaxed);
+      gen_.fetch_add(1, std::memory_order_acq_rel);
+      return;
+    }
+    for (int spin = 0; gen_.load(std::memory_order_acquire) == g; ++spin)
+      if (spin > 2048) std::this_thread::yield();
+  }
+
+ private:
+  const int n_;
+  std::atomic<int> count_{0};
+  std::atomic<int> gen_{0};
+};
+
+// Householder reduction of the dense symmetric a (m x m, row-major; the lower
+// triangle is read and overwritten) to the tridiagonal (d, e), as LAPACK's
+// unblocked symmetric reduction does it: for column k, the reflector
+// H = I - 2 v v^T that zeroes a[k+2.., k], then p = B v over the lower
+// triangle of the trailing block B, q = p - (v^T p) v, and the rank-2 update
+// B <- B - 2 (v q^T + q v^T) of the lower triangle (Golub & Van Loan,
+// Sec. 8.3.1).  The rows of B are split into kChunks fixed chunks of equal
+// area; each chunk's part of p is summed on its own and the parts are added in
+// chunk order, so the result does not depend on how many threads ran.
 void householder_tridiagonal(std::vector<double>& a, int64_t m, std::vector<double>& d, std::vector<double>& e) {
   d.assign(size_t(m), 0.0);
   e.assign(size_t(std::max<int64_t>(m - 1, 0)), 0.0);
-  std::vector<double> v(static_cast<size_t>(m)), p(static_cast<size_t>(m));
-  for (int64_t k = 0; k + 2 < m; ++k) {
-    // x = a[k+1 .. m-1, k]
-    const int64_t len = m - k - 1;
-    double xn = 0.0;
-    for (int64_t i = 0; i < len; ++i) {
-      v[size_t(i)] = a[size_t((k + 1 + i) * m + k)];
-      xn += v[size_t(i)] * v[size_t(i)];
+  std::vector<double> v(static_cast<size_t>(m)), p(static_cast<size_t>(m)), q(static_cast<size_t>(m));
+  std::vector<std::vector<double>> part(kChunks, std::vector<double>(static_cast<size_t>(m)));
+  std::vector<char> skip(static_cast<size_t>(m), 0);
+  std::vector<double> kpart(kChunks);
+
+  auto bounds = [](int64_t len, int c) {  // rows [bounds(c), bounds(c + 1)) of chunk c: equal areas
+    return c >= kChunks ? len : int64_t(std::floor(double(len) * std::sqrt(double(c) / kChunks)));
+  };
+  // Thread tid of nt (the chunks c = tid, tid + nt, ...); thread 0 also forms
+  // the reflectors.
+  auto work = [&](int tid, int nt, SpinBarrier& bar) {
+    for (int64_t k = 0; k + 2 < m; ++k) {
+      const int64_t len = m - k - 1;
+      double* const B = &a[size_t((k + 1) * m + k + 1)];  // B[i * m + j], j <= i
+      if (tid == 0) {
+        double xn = 0.0;
+        for (int64_t i = 0; i < len; ++i) {
+          v[size_t(i)] = a[size_t((k + 1 + i) * m + k)];
+          xn += v[size_t(i)] * v[size_t(i)];
+        }
+        xn = std::sqrt(xn);
+        d[size_t(k)] = a[size_t(k * m + k)];
+        skip[size_t(k)] = 1;
+        if (xn != 0.0) {
+          const double alpha = v[0] > 0.0 ? -xn : xn;
+          v[0] -= alpha;
+          double vn = 0.0;
+          for (int64_t i = 0; i < len; ++i) vn += v[size_t(i)] * v[size_t(i)];
+          vn = std::sqrt(vn);
+          e[size_t(k)] = alpha;
+          if (vn != 0.0) {
+            for (int64_t i = 0; i < len; ++i) v[size_t(i)] /= vn;
+            skip[size_t(k)] = 0;
+          }
+        }
+      }
+      bar.wait();
+      if (skip[size_t(k)]) continue;  // thread 0 writes the next column's entry only
+      // p = B v from the lower triangle, one partial sum per chunk
+      for (int c = tid; c < kChunks; c += nt) {
+        const int64_t r0 = bounds(len, c), r1 = bounds(len, c + 1);
+        double* pc = part[size_t(c)].data();
+        std::fill(pc, pc + r1, 0.0);
+        for (int64_t i = r0; i < r1; ++i) {
+          const double* row = B + i * m;
+          const double vi = v[size_t(i)];
+          double t = row[i] * vi;
+          for (int64_t j = 0; j < i; ++j) {
+            t += row[j] * v[size_t(j)];
+            pc[j] += row[j] * vi;
+          }
+          pc[i] += t;
+        }
+      }
+      bar.wait();
+      // p by index slices (the chunks' parts added in chunk order), and v^T p
+      for (int c = tid; c < kChunks; c += nt) {
+        const int64_t i0 = len * c / kChunks, i1 = len * (c + 1) / kChunks;
+        double kp = 0.0;
+        for (int64_t i = i0; i < i1; ++i) {
+          double t = 0.0;
+          for (int h = 0; h < kChunks; ++h)
+            if (i < bounds(len, h + 1)) t += part[size_t(h)][size_t(i)];
+          p[size_t(i)] = t;
+          kp += v[size_t(i)] * t;
+        }
+        kpart[size_t(c)] = kp;
+      }
+      bar.wait();
+      double K = 0.0;
+      for (int c = 0; c < kChunks; ++c) K += kpart[size_t(c)];
+      for (int c = tid; c < kChunks; c += nt) {
+        const int64_t i0 = len * c / kChunks, i1 = len * (c + 1) / kChunks;
+        for (int64_t i = i0; i < i1; ++i) q[size_t(i)] = p[size_t(i)] - K * v[size_t(i)];
+      }
+      bar.wait();
+      // B <- B - 2 (v q^T + q v^T) on the lower triangle
+      for (int c = tid; c < kChunks; c += nt) {
+        const int64_t r0 = bounds(len, c), r1 = bounds(len, c + 1);
+        for (int64_t i = r0; i < r1; ++i) {
+          double* row = B + i * m;
+          const double vi = 2.0 * v[size_t(i)], qi = 2.0 * q[size_t(i)];
+          for (int64_t j = 0; j <= i; ++j) row[j] -= vi * q[size_t(j)] + qi * v[size_t(j)];
+        }
+      }
+      bar.wait();
     }
-    xn = std::sqrt(xn);
-    d[size_t(k)] = a[size_t(k * m + k)];
-    if (xn == 0.0) {
-      e[size_t(k)] = 0.0;
-      continue;
-    }
-    const double alpha = v[0] > 0.0 ? -xn : xn;
-    v[0] -= alpha;
-    double vn = 0.0;
-    for (int64_t i = 0; i < len; ++i) vn += v[size_t(i)] * v[size_t(i)];
-    vn = std::sqrt(vn);
-    e[size_t(k)] = alpha;
-    if (vn == 0.0) continue;
-    for (int64_t i = 0; i < len; ++i) v[size_t(i)] /= vn;
-    // B = a[k+1.., k+1..];  B <- (I - 2 v v^T) B (I - 2 v v^T) = B - 2 (v q^T + q v^T)
-    // with p = B v, K = v^T p, q = p - K v
-    double K = 0.0;
-    for (int64_t i = 0; i < len; ++i) {
-      const double* row = &a[size_t((k + 1 + i) * m + k + 1)];
-      double t = 0.0;
-      for (int64_t j = 0; j < len; ++j) t += row[j] * v[size_t(j)];
-      p[size_t(i)] = t;
-      K += v[size_t(i)] * t;
-    }
-    for (int64_t i = 0; i < len; ++i) p[size_t(i)] -= K * v[size_t(i)];
-    for (int64_t i = 0; i < len; ++i) {
-      double* row = &a[size_t((k + 1 + i) * m + k + 1)];
-      const double vi = 2.0 * v[size_t(i)], qi = 2.0 * p[size_t(i)];
-      for (int64_t j = 0; j < len; ++j) row[j] -= vi * p[size_t(j)] + qi * v[size_t(j)];
+  };
+
+  int nt = m >= kThreadedMin ? host_threads() : 1;
+  std::vector<std::thread> team;
+  std::atomic<int> go{0};  // 1: run; 2: not every thread could be started, leave
+  SpinBarrier bar(nt);
+  if (nt > 1) {
+    try {
+      team.reserve(size_t(nt - 1));
+      for (int t = 1; t < nt; ++t)
+        team.emplace_back([&, t] {
+          while (go.load(std::memory_order_acquire) == 0) std::this_thread::yield();
+          if (go.load(std::memory_order_acquire) == 1) work(t, nt, bar);
+        });
+      go.store(1, std::memory_order_release);
+    } catch (...) {
+      go.store(2, std::memory_order_release);
+      for (auto& t : team) t.join();
+      team.clear();
+      nt = 1;
     }
   }
+  if (nt > 1) {
+    work(0, nt, bar);
+  } else {
+    SpinBarrier alone(1);
+    work(0, 1, alone);
+  }
+  for (auto& t : team) t.join();
   if (m >= 2) {
     d[size_t(m - 2)] = a[size_t((m - 2) * m + m - 2)];
     e[size_t(m - 2)] = a[size_t((m - 1) * m + m - 2)];

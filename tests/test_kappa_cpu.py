@@ -34,7 +34,7 @@ def shim(tmp_path_factory):
     d = tmp_path_factory.mktemp("kappa")
     (d / "shim.cpp").write_text(SHIM)
     lib = d / "libkappa.so"
-    subprocess.run(["g++", "-O2", "-std=c++17", "-shared", "-fPIC", "-I", CSRC, "-o", str(lib),
+    subprocess.run(["g++", "-O2", "-std=c++17", "-shared", "-fPIC", "-pthread", "-I", CSRC, "-o", str(lib),
                     str(d / "shim.cpp"), os.path.join(CSRC, "qw_kappa.cpp")], check=True)
     f = ctypes.CDLL(str(lib)).kappa_shim
     f.restype = ctypes.c_int
@@ -139,3 +139,20 @@ def test_rejects_unsymmetric_and_singular(shim):
     b = np.array([[1.0, 1.0], [1.0, 1.0]])
     rc, _, err, _ = _kappa(shim, W.from_dense(b))
     assert rc == -1 and "singular" in err
+
+
+def test_dense_path_does_not_depend_on_the_thread_count(shim):
+    """The dense reduction shares its rows among as many threads as the
+    calling thread may run on, in fixed chunks summed in a fixed order: one
+    CPU or all of them give the same bits."""
+    csc = W.offset_matrix(512, 6, seed=9)  # 512 rows: the threaded reduction
+    saved = os.sched_getaffinity(0)
+    try:
+        os.sched_setaffinity(0, {min(saved)})
+        rc1, lam1, err1, _ = _kappa(shim, csc)
+    finally:
+        os.sched_setaffinity(0, saved)
+    rc2, lam2, err2, _ = _kappa(shim, csc)
+    assert rc1 == 0 and rc2 == 0, (err1, err2)
+    assert lam1 == lam2
+    assert lam1 == pytest.approx(_numpy_min_abs(csc), rel=1e-11)
