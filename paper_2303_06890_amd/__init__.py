@@ -314,7 +314,11 @@ class State:
                                   ctypes.cast(dbb.data_ptr() + 8 * self.walk.n_total, dp), ctypes.byref(loss),
                                   _stream()))
         db = dbb.numpy()
-        return loss.value, dv.numpy(), db[: self.walk.n_total] + 1j * db[self.walk.n_total:]
+        n = self.walk.n_total
+        dbc = np.empty(n, np.complex128)
+        dbc.real = db[:n]
+        dbc.imag = db[n:]
+        return loss.value, dv.numpy(), dbc
 
 
 def cks_coeffs(beta: int, j0: int) -> np.ndarray:

@@ -1309,7 +1309,9 @@ int grad_sweep(qw_state* st, qw_state* lam, bool real, const GradBufs& gb, int32
     rc = launch_one(st, qw::kSwap, stream);
     if (!rc) e = qw::launch_weight(mm, view(st), st->L, view(lam), lam->L, gb.dw, st->mbuf, 256, stream);
   }
-  if (e == hipSuccess && !rc) e = hipMemcpyAsync(part, st->mbuf, sizeof(part), hipMemcpyDeviceToHost, stream);
+  // The loss partials stay in st->mbuf (no kernel of the sweep uses it) and
+  // come back with the results: a copy to host memory here would hold the
+  // host until the GPU got to it, and the sweep's launches behind it.
   for (int32_t t = nsteps; t >= 1 && e == hipSuccess && !rc; --t) {
     qw::AdjArgs a;
     a.m = mm;
@@ -1363,6 +1365,7 @@ int grad_sweep(qw_state* st, qw_state* lam, bool real, const GradBufs& gb, int32
     e = hipMemcpyAsync(db_re, gbr, sizeof(double) * ctx->ntotal, hipMemcpyDeviceToHost, stream);
   if (e == hipSuccess && !rc && db_im)
     e = hipMemcpyAsync(db_im, gbi, sizeof(double) * ctx->ntotal, hipMemcpyDeviceToHost, stream);
+  if (e == hipSuccess && !rc) e = hipMemcpyAsync(part, st->mbuf, sizeof(part), hipMemcpyDeviceToHost, stream);
   if (e == hipSuccess && !rc) e = hipStreamSynchronize(stream);
   (void)hipStreamSynchronize(stream);
   st->steps_since_init = 0;
