@@ -253,6 +253,11 @@ int qw_export_complex(qw_state* st, uint64_t* keys, double* amps, int64_t cap, i
 int qw_state_import(qw_state* st, const uint64_t* keys, const double* re, const double* im, int64_t m,
                     void* stream);
 
+/* qw_state_import with the amplitudes interleaved (amps[2 t], amps[2 t + 1]
+ * = real and imaginary part of branch t; the layout qw_export_complex
+ * writes).  Same rules and errors. */
+int qw_state_import_complex(qw_state* st, const uint64_t* keys, const double* amps, int64_t m, void* stream);
+
 /* Wait for the stream (QW_EDEVICE reports an earlier asynchronous failure). */
 int qw_sync(qw_state* st, void* stream);
 

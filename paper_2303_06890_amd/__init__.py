@@ -291,9 +291,11 @@ class State:
 
     def import_(self, keys, amps) -> "State":
         keys = np.ascontiguousarray(keys, dtype=np.uint64)
-        re = np.ascontiguousarray(np.real(amps), dtype=np.float64)
-        im = np.ascontiguousarray(np.imag(amps), dtype=np.float64)
-        check(_lib.load().qw_state_import(self._h, _up(keys), _dp(re), _dp(im), keys.shape[0], _stream()))
+        amps = np.ascontiguousarray(amps, dtype=np.complex128)
+        if amps.shape != keys.shape:
+            raise ValueError("one amplitude per key")
+        check(_lib.load().qw_state_import_complex(self._h, _up(keys), _dp(amps.view(np.float64)), keys.shape[0],
+                                                  _stream()))
         return self
 
     def grad(self, w, nsteps: int):

@@ -29,7 +29,7 @@ def word_length(w: int) -> int:
 # every symbol the header declares
 SYMBOLS = [
     "qw_load_csc", "qw_load_csc_batched", "qw_ctx_info", "qw_ctx_ninst", "qw_state_init", "qw_step",
-    "qw_step_adjoint", "qw_measure", "qw_export", "qw_export_complex", "qw_state_import", "qw_sync", "qls_run",
+    "qw_step_adjoint", "qw_measure", "qw_export", "qw_export_complex", "qw_state_import", "qw_state_import_complex", "qw_sync", "qls_run",
     "qw_cks_coeffs", "qw_grad", "qw_state_free", "qw_ctx_free", "qw_last_error", "qw_set_launch",
     "qw_shutdown", "qw_load_csc_hermitian", "qw_kappa", "qw_grad_noalloc",
 ]
@@ -83,6 +83,7 @@ def load() -> ctypes.CDLL:
         "qw_export": (c_int, [P, up, dp, dp, i64, lp, P]),
         "qw_export_complex": (c_int, [P, up, dp, i64, lp, P]),
         "qw_state_import": (c_int, [P, up, dp, dp, i64, P]),
+        "qw_state_import_complex": (c_int, [P, up, dp, i64, P]),
         "qw_sync": (c_int, [P, P]),
         "qls_run": (c_int, [P, dp, dbl, dbl, i32, dp, dp, dp, dp, lp, P]),
         "qw_cks_coeffs": (c_int, [i64, i32, dp]),

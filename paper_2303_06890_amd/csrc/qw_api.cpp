@@ -1136,8 +1136,8 @@ int import_branches(qw_state* st, const std::vector<uint64_t>& keys, const std::
 // Validate keys against the context's layout; merge equal keys; drop the
 // branches at or below the pruning threshold, as every step does (a branch
 // stored as R1's source is not pruned again when the next step reads it).
-int canonical_branches(const qw_ctx* ctx, const uint64_t* keys, const double* re, const double* im, int64_t m,
-                       std::vector<uint64_t>& ok, std::vector<double2>& oa) {
+int canonical_branches(const qw_ctx* ctx, const uint64_t* keys, const double* re, const double* im,
+                       const double* amps, int64_t m, std::vector<uint64_t>& ok, std::vector<double2>& oa) {
   const int n = ctx->nbits;
   const uint64_t nm = (uint64_t(1) << n) - 1;
   // Keys in strictly increasing order (an exported state) need no sort:
@@ -1164,7 +1164,7 @@ int canonical_branches(const qw_ctx* ctx, const uint64_t* keys, const double* re
                    jc = (key >> (3 * n + 2)) & nm;
     if (k >= uint64_t(hi.N) || j >= uint64_t(hi.N) || kc >= uint64_t(hi.s) || jc >= uint64_t(hi.s))
       return set_err(QW_EINVAL, "key with a register value out of range (j,k < N and j_c,k_c < s required)");
-    const double2 a = make_double2(re ? re[i] : 0.0, im ? im[i] : 0.0);
+    const double2 a = amps ? make_double2(amps[2 * i], amps[2 * i + 1]) : make_double2(re ? re[i] : 0.0, im ? im[i] : 0.0);
     if (!std::isfinite(a.x) || !std::isfinite(a.y)) return set_err(QW_EINVAL, "non-finite amplitude");
     if (!ok.empty() && ok.back() == key) {
       oa.back().x += a.x;
@@ -1715,14 +1715,17 @@ int qw_export_complex(qw_state* st, uint64_t* keys, double* amps, int64_t cap, i
   return export_sorted(st, keys, nullptr, nullptr, amps, cap, m, stream_v);
 }
 
-int qw_state_import(qw_state* st, const uint64_t* keys, const double* re, const double* im, int64_t m,
-                    void* stream_v) {
+namespace {
+
+// qw_state_import (re, im) and qw_state_import_complex (amps interleaved).
+int import_state(qw_state* st, const uint64_t* keys, const double* re, const double* im, const double* amps,
+                 int64_t m, void* stream_v) {
   return guarded([&]() -> int {
-    if (!st || m < 0 || (m > 0 && (!keys || !re))) return set_err(QW_EINVAL, "missing argument");
+    if (!st || m < 0 || (m > 0 && (!keys || (!re && !amps)))) return set_err(QW_EINVAL, "missing argument");
     hipStream_t stream = static_cast<hipStream_t>(stream_v);
     std::vector<uint64_t> k;
     std::vector<double2> a;
-    int rc = canonical_branches(st->ctx, keys, re, im, m, k, a);
+    int rc = canonical_branches(st->ctx, keys, re, im, amps, m, k, a);
     if (rc) return rc;
     int64_t written = 0;
     rc = total_written(st, stream, &written);
@@ -1740,6 +1743,17 @@ int qw_state_import(qw_state* st, const uint64_t* keys, const double* re, const 
     if (rc) return rc;
     return restart_counts(st, written, stream);
   });
+}
+
+}  // namespace
+
+int qw_state_import(qw_state* st, const uint64_t* keys, const double* re, const double* im, int64_t m,
+                    void* stream_v) {
+  return import_state(st, keys, re, im, nullptr, m, stream_v);
+}
+
+int qw_state_import_complex(qw_state* st, const uint64_t* keys, const double* amps, int64_t m, void* stream_v) {
+  return import_state(st, keys, nullptr, nullptr, amps, m, stream_v);
 }
 
 int qw_cks_coeffs(int64_t beta, int32_t j0, double* out) {

@@ -107,3 +107,44 @@ def test_split_and_interleaved_exports_agree(Q):
     k3, a3 = st.export()
     np.testing.assert_array_equal(k3, k1)
     np.testing.assert_array_equal(a3, amps)
+
+
+def test_split_and_interleaved_imports_agree(Q):
+    """qw_state_import (re and im arrays) and qw_state_import_complex
+    (interleaved) build the same state: equal keys summed, branches at or
+    below 1e-13 in both parts dropped, the rest placed by key."""
+    import ctypes
+
+    from paper_2303_06890_amd import _lib
+
+    csc = W.offset_matrix(64, 6, seed=31)
+    walk = Q.Walk(csc)
+    keys, amps = walk.state(W.gaussian_b(64, seed=32)).step(4).export()
+    rng = np.random.default_rng(7)
+    dup = rng.choice(keys.size, 50, replace=False)
+    tiny = rng.choice(keys.size, 20, replace=False)
+    k = np.concatenate([keys, keys[dup], keys[tiny]])
+    a = np.concatenate([amps, 0.5 * amps[dup], -amps[tiny] + 1e-14])  # the tiny ones cancel to 1e-14
+    perm = rng.permutation(k.size)
+    k, a = np.ascontiguousarray(k[perm]), np.ascontiguousarray(a[perm])
+    lib = _lib.load()
+    dp = ctypes.POINTER(ctypes.c_double)
+    up = ctypes.POINTER(ctypes.c_uint64)
+    s1 = walk.state(np.zeros(64))
+    re, im = np.ascontiguousarray(a.real), np.ascontiguousarray(a.imag)
+    _lib.check(lib.qw_state_import(s1._h, k.ctypes.data_as(up), re.ctypes.data_as(dp), im.ctypes.data_as(dp), k.size,
+                                   Q._stream()))
+    s2 = walk.state(np.zeros(64))
+    _lib.check(lib.qw_state_import_complex(s2._h, k.ctypes.data_as(up), a.view(np.float64).ctypes.data_as(dp), k.size,
+                                           Q._stream()))
+    k1, a1 = s1.export()
+    k2, a2 = s2.export()
+    np.testing.assert_array_equal(k1, k2)
+    np.testing.assert_array_equal(a1, a2)
+    # what the import should hold: sums per key, then the pruning rule
+    expect = {}
+    for kk, aa in zip(k, a):
+        expect[int(kk)] = expect.get(int(kk), 0) + aa
+    kept = sorted(kk for kk, aa in expect.items() if abs(aa.real) > 1e-13 or abs(aa.imag) > 1e-13)
+    np.testing.assert_array_equal(k1, np.array(kept, np.uint64))
+    np.testing.assert_allclose(a1, np.array([expect[kk] for kk in kept]), rtol=1e-15, atol=1e-17)
