@@ -351,6 +351,7 @@ def table1_leg(Q, W, autotune, tune: bool):
             "value": upd / (ms / 1e3),
             "launch_shape": list(shape) if shape else "default",
             "lanes_per_row": tune_log["chosen_lanes_per_row"] if tune_log else "default",
+            "xcd_rows": tune_log["chosen_xcd_rows"] if tune_log else False,
             "autotune_tiles": tune_log["tile_choices"] if tune_log else None,
         }
         st.close()
@@ -535,6 +536,8 @@ def main():
                     help="fixed launch shape of the main leg (workgroup size, workgroups)")
     ap.add_argument("--only", choices=["batched", "adjoint", "table1", "complex", "max_size", "solver"], default=None,
                     help="run one extra leg alone (for profiling) and print its JSON")
+    ap.add_argument("--xcd", action="store_true",
+                    help="--pmc-run: load with the XCD numbering of row blocks (QW_XCD_ROWS)")
     ap.add_argument("--lanes", default="0", choices=["0", "8", "16"],
                     help="lanes per row of s >= 16 slots for the counter run of --only table1 (0: the library's rule)")
     ap.add_argument("--pmc-run", action="store_true",
@@ -564,25 +567,27 @@ def main():
         torch.cuda.synchronize()
         if args.only == "batched":  # counters of the batched step kernel instead
             inst = W.batched_instances()
-            st = Q.Walk([a for a, _ in inst]).state([b for _, b in inst])
+            st = Q.Walk([a for a, _ in inst], xcd=args.xcd).state([b for _, b in inst])
             st.step(64)
             st.sync()
-            print(json.dumps({"pmc_run": True, "copy_bytes": 8 << 23, "batched_steps": 64}), flush=True)
+            print(json.dumps({"pmc_run": True, "copy_bytes": 8 << 23, "batched_steps": 64, "xcd": args.xcd}),
+                  flush=True)
             return
         if args.only == "table1":  # counters of the paper's shape E (16384 rows, s = 64)
             csc, b = W.table1_band("E")
-            st = Q.Walk(csc, lanes=int(args.lanes)).state(b)
+            st = Q.Walk(csc, lanes=int(args.lanes), xcd=args.xcd).state(b)
             st.step(64)
             st.sync()
-            print(json.dumps({"pmc_run": True, "copy_bytes": 8 << 23, "shape": "E", "steps": 64}), flush=True)
+            print(json.dumps({"pmc_run": True, "copy_bytes": 8 << 23, "shape": "E", "steps": 64, "xcd": args.xcd}),
+                  flush=True)
             return
         csc, b = W.paper_scale()
-        st = Q.Walk(csc).state(b)
+        st = Q.Walk(csc, xcd=args.xcd).state(b)
         if args.launch:
             st.set_launch(*(int(v) for v in args.launch.split(",")))
         st.step(64)
         st.sync()
-        print(json.dumps({"pmc_run": True, "copy_bytes": 8 << 23, "steps": 64}), flush=True)
+        print(json.dumps({"pmc_run": True, "copy_bytes": 8 << 23, "steps": 64, "xcd": args.xcd}), flush=True)
         return
     if args.only == "batched":
         print(json.dumps(batched_leg(Q, W, autotune, not args.no_tune, cpu=not args.no_cpu_baseline)), flush=True)

@@ -93,6 +93,14 @@ typedef struct {
 #define QW_LANES_8 (1u << 16)
 #define QW_LANES_16 (2u << 16)
 
+/* Row blocks of the one-pass walk-step kernels numbered by XCD: the
+ * GPU deals workgroups to its eight XCDs in turn, each XCD with its own L2,
+ * and neighbouring row blocks share cache lines of the state and slot
+ * planes; with this flag they run on one XCD.  A tuning choice like the lanes
+ * per row: results are identical, and which is faster depends on the matrix
+ * (the autotuner times both). */
+#define QW_XCD_ROWS (1u << 18)
+
 /* flags for qw_state_init */
 #define QW_INIT_RAW 0x1u /* start from |b~> itself instead of T~|b~> */
 
@@ -113,7 +121,9 @@ typedef struct {
                            out_len >= 7 also [6] = the lanes of a step-kernel
                            wavefront that share a row of s >= 16 slots (8 or
                            16: QW_LANES_8 / QW_LANES_16, or by default 16 in a
-                           context of at most 1024 wavefronts with 8) */
+                           context of at most 1024 wavefronts with 8); with
+                           out_len >= 8 also [7] = 1 when the context was
+                           loaded with QW_XCD_ROWS */
 
 /* Load one matrix (Sec. V.B, preprocessing list; Sec. II.C, Fig. 1):
  *   scale: > 0 multiplies every value by `scale`; 0 selects 1/max(1, max|a|).

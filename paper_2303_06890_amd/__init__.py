@@ -116,10 +116,12 @@ class Walk:
     ``word``: 0 for FP64 values, or the word length (1 ... 32) of fixed-point
     data, whose rotation is then computed in fixed point.  ``lanes``: 0 for
     the library's rule, or 8 / 16 lanes of a step-kernel wavefront per row of
-    s >= 16 slots (a tuning choice; see autotune)."""
+    s >= 16 slots; ``xcd``: number the one-pass step kernels' row blocks by XCD
+    (QW_XCD_ROWS).  Both are tuning choices that leave results unchanged (see
+    autotune)."""
 
     def __init__(self, mats, scale=None, symmetric: bool = True, torch_alloc: bool = True, word: int = 0,
-                 lanes: int = 0):
+                 lanes: int = 0, xcd: bool = False):
         lib = _lib.load()
         self.mats = list(mats) if isinstance(mats, (list, tuple)) else [mats]
         self.ninst = len(self.mats)
@@ -140,8 +142,11 @@ class Walk:
         self._keep = (n, colptr, rowidx, vals, vim, coff, zoff, sc)
         h = ctypes.c_void_p()
         flags = (_lib.QW_REQUIRE_SYMMETRIC if symmetric else 0) | _lib.word_length(word) | _lib.lanes_flag(lanes)
+        if xcd:
+            flags |= _lib.QW_XCD_ROWS
         self.word = int(word)
         self.lanes = int(lanes)
+        self.xcd = bool(xcd)
         self.load_args = dict(scale=scale, symmetric=symmetric, torch_alloc=torch_alloc, word=word)
         alloc = ctypes.byref(self._alloc.struct) if self._alloc else None
         scp = _dp(sc) if sc is not None else None
@@ -274,9 +279,10 @@ class State:
         return out[0::2] + 1j * out[1::2]
 
     def stats(self) -> dict:
-        o = self._measure(_lib.QW_STATS, np.zeros(7, np.int64))
+        o = self._measure(_lib.QW_STATS, np.zeros(8, np.int64))
         return dict(launches=int(o[0]), branches=int(o[1]), list_capacity=int(o[2]), list_count=int(o[3]),
-                    total_written=int(o[4]), real_amplitudes=bool(o[5]), lanes_per_row_s16=int(o[6]))
+                    total_written=int(o[4]), real_amplitudes=bool(o[5]), lanes_per_row_s16=int(o[6]),
+                    xcd_rows=bool(o[7]))
 
     def export(self):
         """(keys uint64 sorted, amplitudes complex128).  The library copies

@@ -14,6 +14,7 @@ QW_COUNT, QW_NORM, QW_J_MARGINAL, QW_PROJECT, QW_STATS = 1, 2, 3, 4, 5
 
 
 QW_LANES_8, QW_LANES_16 = 1 << 16, 2 << 16
+QW_XCD_ROWS = 1 << 18
 
 
 def lanes_flag(lanes: int) -> int:

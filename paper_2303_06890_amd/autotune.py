@@ -8,13 +8,17 @@ Two choices change how fast a walk step runs and never what it computes:
   wavefronts of a pass.  It is a property of the loaded matrix, so each
   choice is a separate load.  (Four lanes per row, two to sixteen slots per
   lane, measured slower than eight for every workload here: G(16384, 8),
-  the 256-instance batch and the paper's band shapes.)
+  the 256-instance batch and the paper's band shapes.)  The tile also says
+  whether the one-pass kernels number their row blocks by XCD (QW_XCD_ROWS:
+  neighbouring rows, which share cache lines, then run on one XCD's L2);
+  which is faster depends on the matrix.
 * the launch shape: workgroup size and number of workgroups.
 
 `tune_walk` loads the matrices once per tile choice that applies, times the
 launch-shape candidates of each on a scratch state (HIP events on the
-library's stream, graph-replayed steps), and returns the fastest walk, its
-launch shape and the log of every candidate.  `tune` tunes the launch shape
+library's stream, graph-replayed steps), re-times the best shape of each tile
+(median of three loops) to choose between tiles, and returns the fastest
+walk, its launch shape and the log of every candidate.  `tune` tunes the launch shape
 of a walk already loaded.  Results are remembered under (device, padded
 dimensions, largest s, instance count, branch-count bucket, value kind,
 tile), in memory and optionally in a JSON file.
@@ -38,7 +42,8 @@ def _key(walk, branches: int) -> str:
     bucket = int(math.log2(max(1, branches)))
     # the value kind selects the kernel family
     kind = "complex" if walk.complex else (f"word{walk.word}" if walk.word else "real")
-    return f"{name}|N={walk.N_total}|s={smax}|inst={walk.ninst}|m2^{bucket}|{kind}|lanes={walk.lanes}"
+    return (f"{name}|N={walk.N_total}|s={smax}|inst={walk.ninst}|m2^{bucket}|{kind}|lanes={walk.lanes}"
+            f"|xcd={int(walk.xcd)}")
 
 
 def lanes_per_row(walk, s: int) -> int:
@@ -92,7 +97,7 @@ def _time_shapes(walk, b, warm: int = 16, steps: int = TIMED_STEPS, verbose: boo
         e1.synchronize()
         t = e0.elapsed_time(e1) * 1e3 / steps
         if verbose:
-            print(f"[autotune] lanes={walk.lanes} wg={wg:4d} grid={grid:5d}: {t:8.3f} us/step")
+            print(f"[autotune] lanes={walk.lanes} xcd={int(walk.xcd)} wg={wg:4d} grid={grid:5d}: {t:8.3f} us/step")
         out.append((t, (wg, grid)))
     st.close()
     return out, branches
@@ -132,34 +137,60 @@ def _smax(mats) -> int:
     return max(1 << int(math.ceil(math.log2(max(1, int(np.diff(np.asarray(m.colptr)).max()))))) for m in mats)
 
 
+def _retime(walk, b, shape, reps: int = 3, warm: int = 16, steps: int = TIMED_STEPS) -> float:
+    """Median over `reps` graph-replayed loops of the time per step at one
+    launch shape (us)."""
+    import torch
+
+    from . import stream
+
+    st = walk.state(b).step(warm)
+    st.set_launch(*shape)
+    st.step(steps)
+    ts = []
+    for _ in range(reps):
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream())
+        st.step(steps)
+        e1.record(stream())
+        e1.synchronize()
+        ts.append(e0.elapsed_time(e1) * 1e3 / steps)
+    st.close()
+    return sorted(ts)[reps // 2]
+
+
 def tune_walk(mats, b, verbose: bool = False, **walk_kwargs):
     """Load `mats` with each tile choice that applies (8 and 16 lanes per row
-    when some row has s >= 16 slots, else the one mapping there is), tune the
-    launch shape of each, and return (walk, (wg, grid), log): the fastest
-    walk (the others are released), its launch shape, and a log of every
-    candidate timed, for the record of the run."""
+    when some row has s >= 16 slots, else the one mapping there is; each with
+    and without the XCD numbering of row blocks), tune the launch shape of
+    each, and return (walk, (wg, grid), log): the fastest walk (the others
+    are released), its launch shape, and a log of every candidate timed, for
+    the record of the run."""
     from . import Walk
 
-    choices = [8, 16] if _smax(mats) >= 16 else [0]
+    lanes_choices = [8, 16] if _smax(mats) >= 16 else [0]
     log = {"tile_choices": [], "launch_candidates": []}
     best = None
-    for lanes in choices:
-        walk = Walk(mats, lanes=lanes, **walk_kwargs)
-        times, _ = _time_shapes(walk, b, verbose=verbose)
-        t, shape = min(times)
-        lpr = sorted({lanes_per_row(walk, d["s"]) for d in walk.info})
-        log["tile_choices"].append({"lanes_per_row": lpr, "wavefronts": _waves(walk), "best_us_per_step": t,
-                                    "best_launch": list(shape)})
-        log["launch_candidates"] += [{"lanes_per_row": lpr, "wg": s[0], "grid": s[1], "us_per_step": u}
-                                     for u, s in times]
-        if best is None or t < best[0]:
-            if best is not None:
-                best[1].close()
-            best = (t, walk, shape, lpr)
-        else:
-            walk.close()
-    t, walk, shape, lpr = best
-    log.update(chosen_lanes_per_row=lpr, chosen_launch=list(shape), chosen_us_per_step=t)
+    for lanes in lanes_choices:
+        for xcd in (False, True):
+            walk = Walk(mats, lanes=lanes, xcd=xcd, **walk_kwargs)
+            times, _ = _time_shapes(walk, b, verbose=verbose)
+            shape = min(times)[1]
+            t = _retime(walk, b, shape)
+            lpr = sorted({lanes_per_row(walk, d["s"]) for d in walk.info})
+            log["tile_choices"].append({"lanes_per_row": lpr, "xcd_rows": xcd, "wavefronts": _waves(walk),
+                                        "best_us_per_step": t, "best_launch": list(shape)})
+            log["launch_candidates"] += [{"lanes_per_row": lpr, "xcd_rows": xcd, "wg": s[0], "grid": s[1],
+                                          "us_per_step": u} for u, s in times]
+            if best is None or t < best[0]:
+                if best is not None:
+                    best[1].close()
+                best = (t, walk, shape, lpr, xcd)
+            else:
+                walk.close()
+    t, walk, shape, lpr, xcd = best
+    log.update(chosen_lanes_per_row=lpr, chosen_xcd_rows=xcd, chosen_launch=list(shape), chosen_us_per_step=t)
     return walk, shape, log
 
 

@@ -195,9 +195,10 @@ struct qw_ctx {
     m.smax = smax;
     m.slmax = slmax;
     m.suni = suni;
-    m.full = full;
+    m.full = int16_t(full);
     m.angles = word > 0 ? 1 : 0;
     m.wide = wide;
+    m.xcd = int16_t(xcd ? -1 : 0);  // the launchers fill in the workgroups per XCD
     m.inst0 = inst0;
     return m;
   }
@@ -206,6 +207,7 @@ struct qw_ctx {
   int32_t suni = 0;  // s shared by every instance, else 0
   int32_t full = 0;  // every instance has at least one step-kernel wavefront of rows
   int32_t wide = 0;  // 16 lanes per row for instances with s >= 16 (Matrix::wide)
+  int32_t xcd = 0;   // row blocks numbered by XCD in the one-pass kernels (Matrix::xcd)
 };
 
 namespace {
@@ -855,6 +857,7 @@ int load_impl(qw_ctx** out, int32_t ninst, const int32_t* n, const int64_t* colp
     waves8 += (int64_t(ctx->inst[i].N) + (int64_t(1) << rpw_log) - 1) >> rpw_log;
   }
   ctx->wide = lanes == 2 ? 1 : lanes == 1 ? 0 : (2 * waves8 <= qw::kWideWaves ? 1 : 0);
+  ctx->xcd = (flags & QW_XCD_ROWS) ? 1 : 0;
   std::vector<qw::Inst> dinst(ninst);
   int64_t waves = 0;
   for (int32_t i = 0; i < ninst; ++i) {
@@ -1618,6 +1621,7 @@ int qw_measure(qw_state* st, int32_t kind, void* out, int64_t out_len, void* str
         o[4] = tw;
         if (out_len >= 6) o[5] = st->real_ok && st->ctx->realsym ? 1 : 0;
         if (out_len >= 7) o[6] = st->ctx->wide ? 16 : 8;
+        if (out_len >= 8) o[7] = st->ctx->xcd;
         return QW_OK;
       }
       default:

@@ -409,6 +409,22 @@ struct CountBits {
 // counter has one writer, so a plain load at the start and a store at the
 // end replace an atomic (the count store ends the wavefront's work; on a
 // shared line it cost 0.17 us per launch at 16384 x 8).
+// Row block of this workgroup in the one-pass step kernels' _x forms.
+// Workgroups are dealt to the eight XCDs in turn (workgroup p runs on XCD
+// p % 8), each with its own L2.  Neighbouring row blocks share cache lines of
+// the 4- and 8-byte planes (a 128-byte line of the link plane spans 32 rows),
+// so with Matrix::xcd = G / 8 > 0 (set by the launcher for a grid G that is a
+// multiple of 8; it then launches the _x forms) the blocks are renumbered to
+// keep neighbours on one XCD:
+// workgroup p takes block (p % 8) * (G / 8) + p / 8.  A tuning choice: which
+// workgroup runs which rows changes, nothing else.  (The grid comes from the
+// arguments, not from gridDim, which costs one more scalar load of the
+// dispatch packet ahead of the data: 3 % per step at 16384 x 8.)
+__device__ __forceinline__ int64_t row_block(const Matrix& m) {
+  const int64_t p = blockIdx.x;
+  return m.xcd > 0 ? (p & 7) * int64_t(m.xcd) + (p >> 3) : p;
+}
+
 __device__ __forceinline__ int64_t wave_counter(int64_t wpb) {
   return int64_t(blockIdx.x & 7) * (kMaxWaves / 8) + int64_t(blockIdx.x >> 3) * wpb + (threadIdx.x >> 6);
 }
@@ -849,12 +865,16 @@ __device__ __forceinline__ unsigned step_wave_real(const StepArgs& a, int64_t w,
   return cnt;
 }
 
-template <bool ACC, int SLM, int S, int ENC, int W = 0, bool EQ0 = false>
+// XB: the row blocks numbered by XCD (row_block; the _x kernels, which the
+// launcher takes when Matrix::xcd > 0).  A run-time choice in one kernel cost
+// the plain numbering 1-3 % per step (its arguments and arithmetic reordered
+// the loads of the prologue), so each numbering has kernels of its own.
+template <bool ACC, int SLM, int S, int ENC, int W = 0, bool EQ0 = false, bool XB = false>
 __device__ __forceinline__ void step_body_real(const StepArgs& a) {
   const int lane = threadIdx.x & (kWave - 1);
   const int64_t wpb = a.wpb;
-  const int64_t wid = int64_t(blockIdx.x) * wpb + (threadIdx.x >> 6);
-  const int64_t w = uniform(int(wid));
+  int64_t w = 0;
+  if constexpr (!XB) w = uniform(int(int64_t(blockIdx.x) * wpb + (threadIdx.x >> 6)));
   // The arguments the wavefront needs, in registers before the branch below:
   // otherwise they are loaded after it, one more scalar-load round trip
   // ahead of the data loads (2.67 against 2.60 us per step at 16384 x 8).
@@ -862,6 +882,12 @@ __device__ __forceinline__ void step_body_real(const StepArgs& a) {
                "s"(a.in.R1), "s"(a.out.R0), "s"(a.out.Q1), "s"(a.in.r1s), "s"(a.tau), "s"(a.acc));
   asm volatile("" ::"s"(a.m.ninst), "s"(a.m.inst0.wave_base), "s"(a.m.inst0.s), "s"(a.m.inst0.N), "s"(a.in.Q0),
                "s"(a.out.Q0), "s"(a.m.inst0.inv_sqrt_s), "s"(a.m.inst0.jbase), "s"(a.m.inst), "s"(a.m.wave_inst));
+  if constexpr (XB) {
+    // after the others: computed first, its argument was loaded and waited
+    // for ahead of them, a round trip of its own
+    asm volatile("" ::"s"(a.m.xcd), "s"(a.m.waves), "s"(wpb));
+    w = uniform(int(row_block(a.m) * wpb + (threadIdx.x >> 6)));
+  }
   if (w >= a.m.waves) return;  // no list: nothing to do past the slots
   const double coef = ACC ? *a.coef : 0.0;
   const int64_t cidx = wave_counter(wpb);
@@ -897,15 +923,19 @@ extern "C" __global__ void __launch_bounds__(256) qwk_to_complex(const double* _
 // mixed s, up to N slots per lane (the g kernels' shapes).  The _acc twins
 // fuse the solver's projection, as the other families' do; the _q forms read
 // Q0 of unpartnered slots early (step_wave_real's EQ0).
-#define QW_REAL_KERNEL_(NAME, ACC, SLM, S, ENC, W, EQ0)                                              \
+#define QW_REAL_KERNEL_(NAME, ACC, SLM, S, ENC, W, EQ0, XB)                                          \
   extern "C" __global__ void __launch_bounds__(256) NAME(qw::StepArgs a) {                         \
-    qw::step_body_real<ACC, SLM, S, ENC, W, EQ0>(a);                                                \
+    qw::step_body_real<ACC, SLM, S, ENC, W, EQ0, XB>(a);                                            \
   }
-#define QW_REAL_KERNEL4_(NAME, SLM, S, ENC, W)            \
-  QW_REAL_KERNEL_(NAME, false, SLM, S, ENC, W, false)     \
-  QW_REAL_KERNEL_(NAME##_acc, true, SLM, S, ENC, W, false) \
-  QW_REAL_KERNEL_(NAME##_q, false, SLM, S, ENC, W, true)   \
-  QW_REAL_KERNEL_(NAME##_q_acc, true, SLM, S, ENC, W, true)
+#define QW_REAL_KERNEL4_(NAME, SLM, S, ENC, W)                     \
+  QW_REAL_KERNEL_(NAME, false, SLM, S, ENC, W, false, false)       \
+  QW_REAL_KERNEL_(NAME##_acc, true, SLM, S, ENC, W, false, false)  \
+  QW_REAL_KERNEL_(NAME##_q, false, SLM, S, ENC, W, true, false)    \
+  QW_REAL_KERNEL_(NAME##_q_acc, true, SLM, S, ENC, W, true, false) \
+  QW_REAL_KERNEL_(NAME##_x, false, SLM, S, ENC, W, false, true)    \
+  QW_REAL_KERNEL_(NAME##_x_acc, true, SLM, S, ENC, W, false, true) \
+  QW_REAL_KERNEL_(NAME##_x_q, false, SLM, S, ENC, W, true, true)   \
+  QW_REAL_KERNEL_(NAME##_x_q_acc, true, SLM, S, ENC, W, true, true)
 #define QW_REAL_KERNEL(NAME, SLM, S, ENC) QW_REAL_KERNEL4_(NAME, SLM, S, ENC, 0)
 #define QW_REAL_KERNEL_W(NAME, SLM, S, ENC) QW_REAL_KERNEL4_(NAME, SLM, S, ENC, 1)
 QW_REAL_KERNEL(qwk_step_r1, 1, 1, qw::kEncReal)

@@ -90,7 +90,7 @@ enum Fn {
   F_STEP_RW16 = F_STEP_TG1 + 4,  // + 3 F_REAL_COUNT_.  16 lanes per row: qwk_step_r{16,32,64}w,
   F_STEP_TW16 = F_STEP_RW16 + 3,  // qwk_step_t{16,32,64}w
   F_REAL_COUNT_ = F_STEP_TW16 + 3 - F_STEP_R1,
-  F_TO_REAL = F_STEP_R1 + 4 * F_REAL_COUNT_,
+  F_TO_REAL = F_STEP_R1 + 8 * F_REAL_COUNT_,  // + 4 F_REAL_COUNT_: the _x forms (row blocks by XCD)
   F_TO_COMPLEX,
   F_COEF_WINDOW,
   F_SUM_COUNTS,
@@ -158,6 +158,34 @@ const char* const kNames[] = {
     "qwk_step_tg1_q_acc", "qwk_step_tg2_q_acc", "qwk_step_tg4_q_acc", "qwk_step_tg8_q_acc",
     "qwk_step_r16w_q_acc", "qwk_step_r32w_q_acc", "qwk_step_r64w_q_acc", "qwk_step_t16w_q_acc",
     "qwk_step_t32w_q_acc", "qwk_step_t64w_q_acc",
+    "qwk_step_r1_x", "qwk_step_r2_x", "qwk_step_r4_x", "qwk_step_r8_x",
+    "qwk_step_r16_x", "qwk_step_r32_x", "qwk_step_r64_x", "qwk_step_t1_x",
+    "qwk_step_t2_x", "qwk_step_t4_x", "qwk_step_t8_x", "qwk_step_t16_x",
+    "qwk_step_t32_x", "qwk_step_t64_x", "qwk_step_rg1_x", "qwk_step_rg2_x",
+    "qwk_step_rg4_x", "qwk_step_rg8_x", "qwk_step_tg1_x", "qwk_step_tg2_x",
+    "qwk_step_tg4_x", "qwk_step_tg8_x", "qwk_step_r16w_x", "qwk_step_r32w_x",
+    "qwk_step_r64w_x", "qwk_step_t16w_x", "qwk_step_t32w_x", "qwk_step_t64w_x",
+    "qwk_step_r1_x_acc", "qwk_step_r2_x_acc", "qwk_step_r4_x_acc", "qwk_step_r8_x_acc",
+    "qwk_step_r16_x_acc", "qwk_step_r32_x_acc", "qwk_step_r64_x_acc", "qwk_step_t1_x_acc",
+    "qwk_step_t2_x_acc", "qwk_step_t4_x_acc", "qwk_step_t8_x_acc", "qwk_step_t16_x_acc",
+    "qwk_step_t32_x_acc", "qwk_step_t64_x_acc", "qwk_step_rg1_x_acc", "qwk_step_rg2_x_acc",
+    "qwk_step_rg4_x_acc", "qwk_step_rg8_x_acc", "qwk_step_tg1_x_acc", "qwk_step_tg2_x_acc",
+    "qwk_step_tg4_x_acc", "qwk_step_tg8_x_acc", "qwk_step_r16w_x_acc", "qwk_step_r32w_x_acc",
+    "qwk_step_r64w_x_acc", "qwk_step_t16w_x_acc", "qwk_step_t32w_x_acc", "qwk_step_t64w_x_acc",
+    "qwk_step_r1_x_q", "qwk_step_r2_x_q", "qwk_step_r4_x_q", "qwk_step_r8_x_q",
+    "qwk_step_r16_x_q", "qwk_step_r32_x_q", "qwk_step_r64_x_q", "qwk_step_t1_x_q",
+    "qwk_step_t2_x_q", "qwk_step_t4_x_q", "qwk_step_t8_x_q", "qwk_step_t16_x_q",
+    "qwk_step_t32_x_q", "qwk_step_t64_x_q", "qwk_step_rg1_x_q", "qwk_step_rg2_x_q",
+    "qwk_step_rg4_x_q", "qwk_step_rg8_x_q", "qwk_step_tg1_x_q", "qwk_step_tg2_x_q",
+    "qwk_step_tg4_x_q", "qwk_step_tg8_x_q", "qwk_step_r16w_x_q", "qwk_step_r32w_x_q",
+    "qwk_step_r64w_x_q", "qwk_step_t16w_x_q", "qwk_step_t32w_x_q", "qwk_step_t64w_x_q",
+    "qwk_step_r1_x_q_acc", "qwk_step_r2_x_q_acc", "qwk_step_r4_x_q_acc", "qwk_step_r8_x_q_acc",
+    "qwk_step_r16_x_q_acc", "qwk_step_r32_x_q_acc", "qwk_step_r64_x_q_acc", "qwk_step_t1_x_q_acc",
+    "qwk_step_t2_x_q_acc", "qwk_step_t4_x_q_acc", "qwk_step_t8_x_q_acc", "qwk_step_t16_x_q_acc",
+    "qwk_step_t32_x_q_acc", "qwk_step_t64_x_q_acc", "qwk_step_rg1_x_q_acc", "qwk_step_rg2_x_q_acc",
+    "qwk_step_rg4_x_q_acc", "qwk_step_rg8_x_q_acc", "qwk_step_tg1_x_q_acc", "qwk_step_tg2_x_q_acc",
+    "qwk_step_tg4_x_q_acc", "qwk_step_tg8_x_q_acc", "qwk_step_r16w_x_q_acc", "qwk_step_r32w_x_q_acc",
+    "qwk_step_r64w_x_q_acc", "qwk_step_t16w_x_q_acc", "qwk_step_t32w_x_q_acc", "qwk_step_t64w_x_q_acc",
     "qwk_to_real",      "qwk_to_complex",
     "qwk_coef_window",  "qwk_sum_counts",
     "qwk_adjoint_r1",   "qwk_adjoint_r2",   "qwk_adjoint_r4",   "qwk_adjoint_r8",   "qwk_adjoint_r16",
@@ -181,6 +209,13 @@ int log2_of(int32_t s) {
   return lg;
 }
 
+// Matrix::xcd for one launch of the one-pass step kernels: the
+// workgroups per XCD when the context asks for the XCD numbering (-1) and the
+// grid is a multiple of 8, else 0 (the plain numbering).
+int16_t xcd_blocks(const Matrix& m, int grid) {
+  return m.xcd < 0 && grid % 8 == 0 && grid / 8 <= INT16_MAX ? int16_t(grid / 8) : int16_t(0);
+}
+
 Fn step_kernel(const StepArgs& a, int grid, int block) {
   const Matrix& m = a.m;
   const bool acc = a.yacc != nullptr;
@@ -191,7 +226,8 @@ Fn step_kernel(const StepArgs& a, int grid, int block) {
     const int f = m.suni > 0 && wide ? (m.angles ? F_STEP_TW16 : F_STEP_RW16) + log2_of(m.suni) - 4
                   : m.suni > 0       ? (m.angles ? F_STEP_T1 : F_STEP_R1) + log2_of(m.suni)
                                      : (m.angles ? F_STEP_TG1 : F_STEP_RG1) + width_index(m.slmax);
-    return Fn(f + (acc ? int(F_REAL_COUNT_) : 0) + (a.q0 ? 2 * int(F_REAL_COUNT_) : 0));
+    return Fn(f + (acc ? int(F_REAL_COUNT_) : 0) + (a.q0 ? 2 * int(F_REAL_COUNT_) : 0) +
+              (m.xcd > 0 ? 4 * int(F_REAL_COUNT_) : 0));
   }
   int f = F_STEP_S1 + width_index(m.slmax);
   if (m.vim) {
@@ -297,6 +333,7 @@ hipError_t launch_step(const StepArgs& a, int grid, int block, hipStream_t strea
     return hipErrorInvalidValue;  // the real-amplitude kernels are one-pass walk steps only
   StepArgs c = a;
   c.wpb = block / kWave;
+  c.m.xcd = xcd_blocks(a.m, grid);
   void* p[] = {&c};
   return launch(step_kernel(c, grid, block), grid, block, stream, p);
 }

@@ -114,17 +114,62 @@ def test_lanes_flag_forces_the_mapping(Q, oracle_mod, lanes, shape):
 
 
 def test_tune_walk_chooses_a_tile_and_logs_it(Q, oracle_mod):
-    """The autotuner loads both tiles of an s = 32 matrix, times them, and
-    returns a walk that equals the oracle."""
+    """The autotuner loads the four tiles of an s = 32 matrix (8 or 16 lanes
+    per row, with and without the XCD numbering of row blocks), times them,
+    and returns a walk that equals the oracle."""
     from paper_2303_06890_amd import autotune
 
     csc, b = W.band_matrix(256, 15, seed=8), W.uniform_b(256)
     walk, shape, log = autotune.tune_walk(csc, b)
-    assert sorted(c["lanes_per_row"][0] for c in log["tile_choices"]) == [8, 16]
-    assert log["chosen_lanes_per_row"] in ([8], [16]) and len(log["launch_candidates"]) >= 2
+    tiles = sorted((c["lanes_per_row"][0], c["xcd_rows"]) for c in log["tile_choices"])
+    assert tiles == [(8, False), (8, True), (16, False), (16, True)]
+    assert log["chosen_lanes_per_row"] in ([8], [16]) and len(log["launch_candidates"]) >= 4
+    assert walk.xcd == log["chosen_xcd_rows"]
     st = walk.state(b)
     autotune.apply(st, shape)
     st.step(40)
     ok, oa = oracle_mod.OracleState(oracle_mod.OracleMatrix(csc)).set_b(b).T().step(40).export()
     gk, ga = st.export()
     compare_states(gk, ga, ok, oa, where="tuned walk")
+
+
+_XCD_CASES = {
+    "G1024x8": lambda: (W.offset_matrix(1024, 8, seed=41), W.gaussian_b(1024, seed=42), 0, 0),
+    "band_s32_16lanes": lambda: (W.band_matrix(2048, 15, seed=43), W.uniform_b(2048), 16, 0),
+    "band_s64_8lanes": lambda: (W.band_matrix(1024, 31, seed=44), W.gaussian_b(1024, seed=45), 8, 0),
+    "fixed_point_w16": lambda: (W.fixed_point_band(1024, 15, 16, seed=46), W.uniform_b(1024), 16, 16),
+    "batch_mixed_s": lambda: ([a for a, _ in W.batched_instances(count=24, seed=47)],
+                              [b for _, b in W.batched_instances(count=24, seed=47)], 0, 0),
+}
+
+
+@pytest.mark.parametrize("case", list(_XCD_CASES))
+def test_xcd_rows_change_nothing(Q, case):
+    """QW_XCD_ROWS renumbers the row blocks of the one-pass step and adjoint
+    kernels by XCD.  Only which workgroup runs which rows changes, so the
+    states, branch counts and gradients equal those of the plain numbering bit
+    for bit.  Grids are multiples of 8, where the numbering applies."""
+    from paper_2303_06890_amd import autotune
+
+    mats, b, lanes, word = _XCD_CASES[case]()
+    out = []
+    for xcd in (False, True):
+        walk = Q.Walk(mats, lanes=lanes, word=word, xcd=xcd)
+        shape = (64, -(-autotune._waves(walk) // 8) * 8)  # one pass; blocks past the rows return at once
+        st = walk.state(b)
+        st.set_launch(*shape)
+        assert st.stats()["xcd_rows"] == xcd
+        st.step(3).step(37)  # single launches, then a graph
+        k, a = st.export()
+        adj = st.step_adjoint(5).export()
+        res = [k, a, adj[0], adj[1], st.stats()["total_written"]]
+        if word == 0:
+            g = walk.state(b)
+            g.set_launch(*shape)
+            w = np.random.default_rng(48).random(walk.n_total)
+            loss, dv, db = g.step(12).grad(w, 12)
+            res += [loss, dv.copy(), db.copy()]
+        out.append(res)
+        walk.close()
+    for x, y in zip(out[0], out[1]):
+        np.testing.assert_array_equal(x, y, err_msg=case)
