@@ -38,17 +38,19 @@ E_TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "step_kernel_E_traffic.md")
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_2303_06890_amd", "csrc", f) for f in ("qw_kernels.hip", "qw_internal.h")]
 
 
-def measured_traffic(path: str = TRAFFIC_PROFILE):
+def measured_traffic(path: str = TRAFFIC_PROFILE, xcd: bool = False):
     """HBM bytes per step launch from a committed counter summary (calibrated
-    FETCH_SIZE + WRITE_SIZE), or None when the summary is missing or was taken
-    on other kernel sources than the ones in this tree."""
+    FETCH_SIZE + WRITE_SIZE) for the plain numbering of row blocks, or with
+    xcd for the numbering by XCD (QW_XCD_ROWS), or None when the summary is
+    missing, lacks that figure or was taken on other kernel sources than the
+    ones in this tree."""
     try:
         with open(path) as f:
             text = f.read()
         digest = hashlib.sha256(b"".join(open(p, "rb").read() for p in KERNEL_SOURCES)).hexdigest()
     except OSError:
         return None
-    m = re.search(r"traffic_bytes_per_launch: (\d+)", text)
+    m = re.search(r"traffic_bytes_per_launch%s: (\d+)" % ("_xcd" if xcd else ""), text)
     h = re.search(r"sha256 ([0-9a-f]{64})", text)
     if not m or not h or h.group(1) != digest:
         return None
@@ -290,7 +292,7 @@ def batched_leg(Q, W, autotune, tune: bool, steps: int = 50, cpu: bool = True):
     upd = s1["total_written"] - s0["total_written"]
     upd_in = upd - s1["branches"] + s0["branches"]
     slots = int(sum(d["N"] * d["s"] for d in walk.info))
-    traffic = measured_traffic(BATCHED_TRAFFIC_PROFILE)
+    traffic = measured_traffic(BATCHED_TRAFFIC_PROFILE, xcd=walk.xcd)
     step_s = ms / 1e3 / steps
     singles = []
     for a, b in inst:
@@ -371,7 +373,7 @@ def table1_leg(Q, W, autotune, tune: bool):
                               "branches": fx["branches"], "launch_shape": fx["launch_shape"]}
         if name == "E" and res["lanes_per_row"] == [8]:
             # the counters were taken with eight lanes per row (one slot per lane in eight)
-            traffic = measured_traffic(E_TRAFFIC_PROFILE)
+            traffic = measured_traffic(E_TRAFFIC_PROFILE, xcd=res["xcd_rows"])
             res["traffic"] = traffic
             res["counter_gbs"] = traffic / (res["us_per_step"] * 1e-6) / 1e9 if traffic else None
         out[name] = res
@@ -641,7 +643,7 @@ def main():
     alg_bytes = 24.0 * (in_total + out_total) + 12.0 * N * s * args.steps
     launch_s = ms / 1e3 / args.steps
     achieved = alg_bytes / args.steps / launch_s / 1e9
-    traffic = measured_traffic()
+    traffic = measured_traffic(xcd=walk.xcd)
     floors = launch_floors(torch)
     if args.steps != 256:
         # The same floors in graphs of the timed call's length: a short graph

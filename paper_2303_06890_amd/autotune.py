@@ -65,13 +65,20 @@ def _waves(walk) -> int:
 
 
 def candidates(walk):
+    """(workgroup size, workgroups) to time: the one-pass grid and a few
+    grid-stride ones.  A walk loaded with the XCD numbering of row blocks also
+    gets the one-pass grid rounded up to a multiple of 8 (the numbering needs
+    one; the workgroups past the rows return at once)."""
     waves = _waves(walk)
     lanes = 64 * waves
     out = []
     for wg in (64, 128, 256):
         one_pass = max(1, -(-lanes // wg))
-        for grid in sorted({min(one_pass, 65536), 1024, 2048, 4096, 8192}):
-            if grid <= one_pass:
+        grids = {min(one_pass, 65536), 1024, 2048, 4096, 8192}
+        if walk.xcd and -(-one_pass // 8) * 8 <= 65536:
+            grids.add(-(-one_pass // 8) * 8)
+        for grid in sorted(grids):
+            if grid <= one_pass or grid == -(-one_pass // 8) * 8:
                 out.append((wg, grid))
     return out
 

@@ -28,8 +28,14 @@ def test_traffic_is_read_only_for_the_recorded_sources(tmp_path):
     stale = tmp_path / "stale.md"
     stale.write_text(f"traffic_bytes_per_launch: 123456\nkernel sources sha256 {'0' * 64}\n")
     assert bench.measured_traffic(str(good)) == 123456.0
+    assert bench.measured_traffic(str(good), xcd=True) is None  # no figure for the XCD numbering
     assert bench.measured_traffic(str(stale)) is None
     assert bench.measured_traffic(str(tmp_path / "missing.md")) is None
+    both = tmp_path / "both.md"
+    both.write_text(f"traffic_bytes_per_launch: 123456\ntraffic_bytes_per_launch_xcd: 120000\n"
+                    f"kernel sources sha256 {digest}\n")
+    assert bench.measured_traffic(str(both)) == 123456.0
+    assert bench.measured_traffic(str(both), xcd=True) == 120000.0
 
 
 def test_oracle_baseline_fields():
