@@ -38,23 +38,32 @@ E_TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "step_kernel_E_traffic.md")
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_2303_06890_amd", "csrc", f) for f in ("qw_kernels.hip", "qw_internal.h")]
 
 
-def measured_traffic(path: str = TRAFFIC_PROFILE, xcd: bool = False):
+def measured_traffic(path: str = TRAFFIC_PROFILE, xcd: bool = False, lanes16: bool = False):
     """HBM bytes per step launch from a committed counter summary (calibrated
-    FETCH_SIZE + WRITE_SIZE) for the plain numbering of row blocks, or with
-    xcd for the numbering by XCD (QW_XCD_ROWS), or None when the summary is
-    missing, lacks that figure or was taken on other kernel sources than the
-    ones in this tree."""
+    FETCH_SIZE + WRITE_SIZE) for one tile: the library's lane mapping or
+    sixteen lanes per row (lanes16), row blocks in the plain numbering or by
+    XCD (xcd, QW_XCD_ROWS).  None when the summary is missing, lacks that
+    tile's figure or was taken on other kernel sources than the ones in this
+    tree."""
     try:
         with open(path) as f:
             text = f.read()
         digest = hashlib.sha256(b"".join(open(p, "rb").read() for p in KERNEL_SOURCES)).hexdigest()
     except OSError:
         return None
-    m = re.search(r"traffic_bytes_per_launch%s: (\d+)" % ("_xcd" if xcd else ""), text)
+    key = "traffic_bytes_per_launch" + ("_lanes16" if lanes16 else "") + ("_xcd" if xcd else "")
+    m = re.search(key + r": (\d+)", text)
     h = re.search(r"sha256 ([0-9a-f]{64})", text)
     if not m or not h or h.group(1) != digest:
         return None
     return float(m.group(1))
+
+
+def xcd_active(walk, shape) -> bool:
+    """Whether the step kernels of `walk` at launch `shape` number their row
+    blocks by XCD: the walk was loaded with the numbering and the grid is a
+    multiple of 8 (other grids run the plain numbering)."""
+    return bool(walk.xcd and shape and int(shape[1]) % 8 == 0)
 
 
 def cpu_model() -> str:
@@ -292,7 +301,7 @@ def batched_leg(Q, W, autotune, tune: bool, steps: int = 50, cpu: bool = True):
     upd = s1["total_written"] - s0["total_written"]
     upd_in = upd - s1["branches"] + s0["branches"]
     slots = int(sum(d["N"] * d["s"] for d in walk.info))
-    traffic = measured_traffic(BATCHED_TRAFFIC_PROFILE, xcd=walk.xcd)
+    traffic = measured_traffic(BATCHED_TRAFFIC_PROFILE, xcd=xcd_active(walk, shape), lanes16=walk.lanes == 16)
     step_s = ms / 1e3 / steps
     singles = []
     for a, b in inst:
@@ -354,6 +363,7 @@ def table1_leg(Q, W, autotune, tune: bool):
             "launch_shape": list(shape) if shape else "default",
             "lanes_per_row": tune_log["chosen_lanes_per_row"] if tune_log else "default",
             "xcd_rows": tune_log["chosen_xcd_rows"] if tune_log else False,
+            "xcd_rows_active": xcd_active(walk, shape),
             "autotune_tiles": tune_log["tile_choices"] if tune_log else None,
         }
         st.close()
@@ -371,9 +381,9 @@ def table1_leg(Q, W, autotune, tune: bool):
         fx = run(fcsc, fb, word)
         res["fixed_point"] = {"word_length": word, "us_per_step": fx["us_per_step"], "value": fx["value"],
                               "branches": fx["branches"], "launch_shape": fx["launch_shape"]}
-        if name == "E" and res["lanes_per_row"] == [8]:
-            # the counters were taken with eight lanes per row (one slot per lane in eight)
-            traffic = measured_traffic(E_TRAFFIC_PROFILE, xcd=res["xcd_rows"])
+        if name == "E" and res["lanes_per_row"] in ([8], [16]):
+            # counters of each tile the tuner can choose for this shape
+            traffic = measured_traffic(E_TRAFFIC_PROFILE, xcd=res["xcd_rows_active"], lanes16=res["lanes_per_row"] == [16])
             res["traffic"] = traffic
             res["counter_gbs"] = traffic / (res["us_per_step"] * 1e-6) / 1e9 if traffic else None
         out[name] = res
@@ -569,7 +579,9 @@ def main():
         torch.cuda.synchronize()
         if args.only == "batched":  # counters of the batched step kernel instead
             inst = W.batched_instances()
-            st = Q.Walk([a for a, _ in inst], xcd=args.xcd).state([b for _, b in inst])
+            st = Q.Walk([a for a, _ in inst], lanes=int(args.lanes), xcd=args.xcd).state([b for _, b in inst])
+            if args.launch:
+                st.set_launch(*(int(v) for v in args.launch.split(",")))
             st.step(64)
             st.sync()
             print(json.dumps({"pmc_run": True, "copy_bytes": 8 << 23, "batched_steps": 64, "xcd": args.xcd}),
@@ -578,6 +590,8 @@ def main():
         if args.only == "table1":  # counters of the paper's shape E (16384 rows, s = 64)
             csc, b = W.table1_band("E")
             st = Q.Walk(csc, lanes=int(args.lanes), xcd=args.xcd).state(b)
+            if args.launch:
+                st.set_launch(*(int(v) for v in args.launch.split(",")))
             st.step(64)
             st.sync()
             print(json.dumps({"pmc_run": True, "copy_bytes": 8 << 23, "shape": "E", "steps": 64, "xcd": args.xcd}),
@@ -643,7 +657,7 @@ def main():
     alg_bytes = 24.0 * (in_total + out_total) + 12.0 * N * s * args.steps
     launch_s = ms / 1e3 / args.steps
     achieved = alg_bytes / args.steps / launch_s / 1e9
-    traffic = measured_traffic(xcd=walk.xcd)
+    traffic = measured_traffic(xcd=xcd_active(walk, shape))
     floors = launch_floors(torch)
     if args.steps != 256:
         # The same floors in graphs of the timed call's length: a short graph

@@ -36,6 +36,7 @@ def test_traffic_is_read_only_for_the_recorded_sources(tmp_path):
                     f"kernel sources sha256 {digest}\n")
     assert bench.measured_traffic(str(both)) == 123456.0
     assert bench.measured_traffic(str(both), xcd=True) == 120000.0
+    assert bench.measured_traffic(str(both), lanes16=True) is None
 
 
 def test_oracle_baseline_fields():
