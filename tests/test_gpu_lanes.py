@@ -173,3 +173,14 @@ def test_xcd_rows_change_nothing(Q, case):
         walk.close()
     for x, y in zip(out[0], out[1]):
         np.testing.assert_array_equal(x, y, err_msg=case)
+
+
+def test_xcd_rows_change_nothing_in_the_solver(Q):
+    """The solver's steps run the _acc forms, which have XCD-numbered
+    versions too: the same solve with and without the numbering gives the same
+    bits (x, success probability, walk steps, |y|)."""
+    A, b = W.solver_problem(32)  # 1024 rows, s = 8: 128 wavefronts, 32 or more workgroups (a multiple of 8)
+    plain = Q.Walk(A).qls(b, eps=1e-2)
+    xcd = Q.Walk(A, xcd=True).qls(b, eps=1e-2)
+    np.testing.assert_array_equal(plain[0], xcd[0])
+    assert plain[1:] == xcd[1:]
