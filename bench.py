@@ -32,6 +32,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+VERBOSE = False  # --verbose: the autotuner prints every candidate it times (progress of long runs)
 TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "step_kernel_G16384x8_traffic.md")
 BATCHED_TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "batched_256_instances_traffic.md")
 E_TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "step_kernel_E_traffic.md")
@@ -290,7 +291,7 @@ def batched_leg(Q, W, autotune, tune: bool, steps: int = 50, cpu: bool = True):
     walk at a time on the same GPU."""
     inst = W.batched_instances()
     mats, bs = [a for a, _ in inst], [b for _, b in inst]
-    walk, shape, tune_log = autotune.tune_walk(mats, bs) if tune else (Q.Walk(mats), None, None)
+    walk, shape, tune_log = autotune.tune_walk(mats, bs, verbose=VERBOSE) if tune else (Q.Walk(mats), None, None)
     st = walk.state(bs)
     if shape:
         autotune.apply(st, shape)
@@ -346,7 +347,7 @@ def table1_leg(Q, W, autotune, tune: bool):
     paper's single-core time per step is quoted as context only (another
     machine, another code)."""
     def run(csc, b, word):
-        walk, shape, tune_log = autotune.tune_walk(csc, b, word=word) if tune else (Q.Walk(csc, word=word), None, None)
+        walk, shape, tune_log = autotune.tune_walk(csc, b, word=word, verbose=VERBOSE) if tune else (Q.Walk(csc, word=word), None, None)
         st = walk.state(b)
         if shape:
             autotune.apply(st, shape)
@@ -395,7 +396,7 @@ def complex_leg(Q, W, autotune, tune: bool, steps: int = 2000):
     8 entries per column (the off-diagonal pairs v, conj(v)), uniform b."""
     csc = W.hermitian_offset_matrix(16384, 8, seed=2)
     b = W.uniform_b(16384)
-    walk, shape, _ = autotune.tune_walk(csc, b) if tune else (Q.Walk(csc), None, None)
+    walk, shape, _ = autotune.tune_walk(csc, b, verbose=VERBOSE) if tune else (Q.Walk(csc), None, None)
     st = walk.state(b)
     if shape:
         autotune.apply(st, shape)
@@ -548,6 +549,7 @@ def main():
                     help="fixed launch shape of the main leg (workgroup size, workgroups)")
     ap.add_argument("--only", choices=["batched", "adjoint", "table1", "complex", "max_size", "solver"], default=None,
                     help="run one extra leg alone (for profiling) and print its JSON")
+    ap.add_argument("--verbose", action="store_true", help="print every autotuner candidate as it is timed")
     ap.add_argument("--xcd", action="store_true",
                     help="--pmc-run: load with the XCD numbering of row blocks (QW_XCD_ROWS)")
     ap.add_argument("--lanes", default="0", choices=["0", "8", "16"],
@@ -558,6 +560,8 @@ def main():
                          "with --only batched, or of the paper's shape E with --only table1; prints "
                          "nothing else")
     args = ap.parse_args()
+    global VERBOSE
+    VERBOSE = args.verbose
     if args.gpus != 1:
         print("bench.py runs on exactly one GPU: the library has no multi-GPU path "
               "(a single walk instance would shard by row owner with one all-to-all per step)",
@@ -630,7 +634,7 @@ def main():
     elif args.no_tune:
         walk, shape = Q.Walk(csc), None
     else:
-        walk, shape, tune_log = autotune.tune_walk(csc, b)
+        walk, shape, tune_log = autotune.tune_walk(csc, b, verbose=VERBOSE)
     N, s = walk.info[0]["N"], walk.info[0]["s"]
     st = walk.state(b)
     if shape:

@@ -28,6 +28,7 @@ from __future__ import annotations
 import json
 import math
 import os
+import sys
 
 _cache: dict = {}
 
@@ -104,7 +105,8 @@ def _time_shapes(walk, b, warm: int = 16, steps: int = TIMED_STEPS, verbose: boo
         e1.synchronize()
         t = e0.elapsed_time(e1) * 1e3 / steps
         if verbose:
-            print(f"[autotune] lanes={walk.lanes} xcd={int(walk.xcd)} wg={wg:4d} grid={grid:5d}: {t:8.3f} us/step")
+            print(f"[autotune] lanes={walk.lanes} xcd={int(walk.xcd)} wg={wg:4d} grid={grid:5d}: {t:8.3f} us/step",
+                  file=sys.stderr, flush=True)
         out.append((t, (wg, grid)))
     st.close()
     return out, branches
