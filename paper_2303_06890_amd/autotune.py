@@ -171,18 +171,24 @@ def _retime(walk, b, shape, reps: int = 3, warm: int = 16, steps: int = TIMED_ST
 
 def tune_walk(mats, b, verbose: bool = False, **walk_kwargs):
     """Load `mats` with each tile choice that applies (8 and 16 lanes per row
-    when some row has s >= 16 slots, else the one mapping there is; each with
-    and without the XCD numbering of row blocks), tune the launch shape of
-    each, and return (walk, (wg, grid), log): the fastest walk (the others
-    are released), its launch shape, and a log of every candidate timed, for
-    the record of the run."""
+    when some row has s >= 16 slots, else the one mapping there is; for real
+    values each with and without the XCD numbering of row blocks), tune the
+    launch shape of each, and return (walk, (wg, grid), log): the fastest
+    walk (the others are released), its launch shape, and a log of every
+    candidate timed, for the record of the run."""
+    import numpy as np
+
     from . import Walk
 
     lanes_choices = [8, 16] if _smax(mats) >= 16 else [0]
+    # the numbering by XCD exists for the one-double-per-cell kernels (real
+    # values); complex values would time the same kernels twice
+    mlist = list(mats) if isinstance(mats, (list, tuple)) else [mats]
+    xcd_choices = (False,) if any(np.iscomplexobj(m.vals) for m in mlist) else (False, True)
     log = {"tile_choices": [], "launch_candidates": []}
     best = None
     for lanes in lanes_choices:
-        for xcd in (False, True):
+        for xcd in xcd_choices:
             walk = Walk(mats, lanes=lanes, xcd=xcd, **walk_kwargs)
             times, _ = _time_shapes(walk, b, verbose=verbose)
             shape = min(times)[1]
