@@ -93,7 +93,7 @@ typedef struct {
 #define QW_LANES_8 (1u << 16)
 #define QW_LANES_16 (2u << 16)
 
-/* Row blocks of the one-pass walk-step kernels numbered by XCD: the
+/* Row blocks of the one-pass walk-step and adjoint kernels numbered by XCD: the
  * GPU deals workgroups to its eight XCDs in turn, each XCD with its own L2,
  * and neighbouring row blocks share cache lines of the state and slot
  * planes; with this flag they run on one XCD.  A tuning choice like the lanes

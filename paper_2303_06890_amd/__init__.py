@@ -116,7 +116,7 @@ class Walk:
     ``word``: 0 for FP64 values, or the word length (1 ... 32) of fixed-point
     data, whose rotation is then computed in fixed point.  ``lanes``: 0 for
     the library's rule, or 8 / 16 lanes of a step-kernel wavefront per row of
-    s >= 16 slots; ``xcd``: number the one-pass step kernels' row blocks by XCD
+    s >= 16 slots; ``xcd``: number the one-pass step and adjoint kernels' row blocks by XCD
     (QW_XCD_ROWS).  Both are tuning choices that leave results unchanged (see
     autotune)."""
 

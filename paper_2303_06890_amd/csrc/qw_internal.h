@@ -114,10 +114,11 @@ struct Matrix {
   int32_t slmax;             // largest slots-per-lane over the instances
   int32_t suni;              // s of every instance when they all share it, else 0
   int16_t full;  // 1 when every instance has at least one wavefront of rows
-  // Row blocks of the one-pass step kernels numbered by XCD (row_block, the
-  // _x kernels): -1 in the context's matrix when it was loaded with
-  // QW_XCD_ROWS; launch_step replaces it by the launch's workgroups per XCD
-  // (grid / 8; 0, the plain numbering, for a grid that is not a multiple of 8).
+  // Row blocks of the one-pass step and adjoint kernels numbered by XCD
+  // (row_block, the _x kernels): -1 in the context's matrix when it was loaded
+  // with QW_XCD_ROWS; launch_step and launch_adjoint replace it by the
+  // launch's workgroups per XCD (grid / 8; 0, the plain numbering, for a grid
+  // that is not a multiple of 8).
   int16_t xcd;
   int32_t angles;            // 1: fixed-point data; val holds each slot's rotation angle (below)
   int32_t wide;              // 1: instances with s >= 16 use 16 lanes per row (kWideWaves)

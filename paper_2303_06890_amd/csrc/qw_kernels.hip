@@ -409,7 +409,7 @@ struct CountBits {
 // counter has one writer, so a plain load at the start and a store at the
 // end replace an atomic (the count store ends the wavefront's work; on a
 // shared line it cost 0.17 us per launch at 16384 x 8).
-// Row block of this workgroup in the one-pass step kernels' _x forms.
+// Row block of this workgroup in the one-pass step and adjoint kernels' _x forms.
 // Workgroups are dealt to the eight XCDs in turn (workgroup p runs on XCD
 // p % 8), each with its own L2.  Neighbouring row blocks share cache lines of
 // the 4- and 8-byte planes (a 128-byte line of the link plane spans 32 rows),
@@ -1236,11 +1236,13 @@ __device__ __forceinline__ unsigned adjoint_wave_real(const AdjArgs& a, int64_t 
   return cnt;
 }
 
-template <int SLM, int S, int W = 0, bool EQ0 = false>
+// XB: the row blocks numbered by XCD (the _x kernels; see step_body_real).
+template <int SLM, int S, int W = 0, bool EQ0 = false, bool XB = false>
 __device__ __forceinline__ void adjoint_body_real(const AdjArgs& a) {
   const int lane = threadIdx.x & (kWave - 1);
   const int64_t wpb = a.wpb;
-  const int64_t w = uniform(int(int64_t(blockIdx.x) * wpb + (threadIdx.x >> 6)));
+  const int64_t blk = XB ? row_block(a.m) : int64_t(blockIdx.x);
+  const int64_t w = uniform(int(blk * wpb + (threadIdx.x >> 6)));
   if (w >= a.m.waves) return;
   const int64_t cidx = wave_counter(wpb);
   const unsigned long long prev = a.acc ? a.acc[cidx] : 0ull;
@@ -1259,7 +1261,13 @@ __device__ __forceinline__ void adjoint_body_real(const AdjArgs& a) {
   extern "C" __global__ void __launch_bounds__(256) NAME(qw::AdjArgs a) {                       \
     qw::adjoint_body_real<SLM, S, W, false>(a);                                                  \
   }                                                                                              \
-  extern "C" __global__ void __launch_bounds__(256) NAME##_q(qw::AdjArgs a) { qw::adjoint_body_real<SLM, S, W, true>(a); }
+  extern "C" __global__ void __launch_bounds__(256) NAME##_q(qw::AdjArgs a) { qw::adjoint_body_real<SLM, S, W, true>(a); } \
+  extern "C" __global__ void __launch_bounds__(256) NAME##_x(qw::AdjArgs a) {                   \
+    qw::adjoint_body_real<SLM, S, W, false, true>(a);                                            \
+  }                                                                                              \
+  extern "C" __global__ void __launch_bounds__(256) NAME##_x_q(qw::AdjArgs a) {                 \
+    qw::adjoint_body_real<SLM, S, W, true, true>(a);                                             \
+  }
 QW_ADJ_REAL_KERNEL(qwk_adjoint_r1, 1, 1, 0)
 QW_ADJ_REAL_KERNEL(qwk_adjoint_r2, 1, 2, 0)
 QW_ADJ_REAL_KERNEL(qwk_adjoint_r4, 1, 4, 0)

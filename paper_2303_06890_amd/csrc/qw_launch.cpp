@@ -97,8 +97,9 @@ enum Fn {
   F_ADJ_R1,                   // one-pass adjoint on one double per cell: qwk_adjoint_r{1..64},
   F_ADJ_RG1 = F_ADJ_R1 + 7,   // qwk_adjoint_rg{1,2,4,8} (mixed s),
   F_ADJ_RW16 = F_ADJ_RG1 + 4,  // qwk_adjoint_r{16,32,64}w (16 lanes per row); the _q forms
-  F_ADJ_COUNT_ = F_ADJ_RW16 + 3 - F_ADJ_R1,  // follow at + F_ADJ_COUNT_
-  F_SWAP_REAL = F_ADJ_R1 + 2 * F_ADJ_COUNT_,
+  F_ADJ_COUNT_ = F_ADJ_RW16 + 3 - F_ADJ_R1,  // follow at + F_ADJ_COUNT_, the _x forms (row blocks by
+                                             // XCD) at + 2 F_ADJ_COUNT_ and their _q forms at + 3
+  F_SWAP_REAL = F_ADJ_R1 + 4 * F_ADJ_COUNT_,
   F_WEIGHT_REAL,
   F_GRAD_INIT_REAL,
   F_GATHER_GRAD,
@@ -194,6 +195,13 @@ const char* const kNames[] = {
     "qwk_adjoint_r1_q", "qwk_adjoint_r2_q", "qwk_adjoint_r4_q", "qwk_adjoint_r8_q", "qwk_adjoint_r16_q",
     "qwk_adjoint_r32_q", "qwk_adjoint_r64_q", "qwk_adjoint_rg1_q", "qwk_adjoint_rg2_q", "qwk_adjoint_rg4_q",
     "qwk_adjoint_rg8_q", "qwk_adjoint_r16w_q", "qwk_adjoint_r32w_q", "qwk_adjoint_r64w_q",
+    "qwk_adjoint_r1_x", "qwk_adjoint_r2_x", "qwk_adjoint_r4_x", "qwk_adjoint_r8_x",
+    "qwk_adjoint_r16_x", "qwk_adjoint_r32_x", "qwk_adjoint_r64_x", "qwk_adjoint_rg1_x",
+    "qwk_adjoint_rg2_x", "qwk_adjoint_rg4_x", "qwk_adjoint_rg8_x", "qwk_adjoint_r16w_x",
+    "qwk_adjoint_r32w_x", "qwk_adjoint_r64w_x", "qwk_adjoint_r1_x_q", "qwk_adjoint_r2_x_q",
+    "qwk_adjoint_r4_x_q", "qwk_adjoint_r8_x_q", "qwk_adjoint_r16_x_q", "qwk_adjoint_r32_x_q",
+    "qwk_adjoint_r64_x_q", "qwk_adjoint_rg1_x_q", "qwk_adjoint_rg2_x_q", "qwk_adjoint_rg4_x_q",
+    "qwk_adjoint_rg8_x_q", "qwk_adjoint_r16w_x_q", "qwk_adjoint_r32w_x_q", "qwk_adjoint_r64w_x_q",
     "qwk_swap_real",
     "qwk_weight_real",  "qwk_grad_init_real", "qwk_gather_grad", "qwk_rot_table",
     "qwk_key_bits",     "qwk_radix_hist",   "qwk_radix_offsets", "qwk_radix_scatter",
@@ -209,7 +217,7 @@ int log2_of(int32_t s) {
   return lg;
 }
 
-// Matrix::xcd for one launch of the one-pass step kernels: the
+// Matrix::xcd for one launch of the one-pass step and adjoint kernels: the
 // workgroups per XCD when the context asks for the XCD numbering (-1) and the
 // grid is a multiple of 8, else 0 (the plain numbering).
 int16_t xcd_blocks(const Matrix& m, int grid) {
@@ -343,6 +351,7 @@ hipError_t launch_adjoint(const AdjArgs& a, int grid, int block, hipStream_t str
   if (a.m.vim || a.m.angles) return hipErrorInvalidValue;  // the gradient sweep is for real FP64 matrices
   AdjArgs c = a;
   c.wpb = block / kWave;
+  c.m.xcd = xcd_blocks(a.m, grid);
   if (!a.real) {
     c.real = 0;
     void* p[] = {&c};
@@ -355,7 +364,8 @@ hipError_t launch_adjoint(const AdjArgs& a, int grid, int block, hipStream_t str
                 : a.m.suni > 0       ? F_ADJ_R1 + log2_of(a.m.suni)
                                      : F_ADJ_RG1 + width_index(a.m.slmax);
   void* p[] = {&c};
-  return launch(Fn(f + (a.q0 ? int(F_ADJ_COUNT_) : 0)), grid, block, stream, p);
+  return launch(Fn(f + (a.q0 ? int(F_ADJ_COUNT_) : 0) + (c.m.xcd > 0 ? 2 * int(F_ADJ_COUNT_) : 0)), grid, block, stream,
+                p);
 }
 
 hipError_t launch_rot_table(const Matrix& m, double* sfg, hipStream_t stream) {
