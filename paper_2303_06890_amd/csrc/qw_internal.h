@@ -115,10 +115,11 @@ struct Matrix {
   int32_t suni;              // s of every instance when they all share it, else 0
   int16_t full;  // 1 when every instance has at least one wavefront of rows
   // Row blocks of the one-pass step and adjoint kernels numbered by XCD
-  // (row_block, the _x kernels): -1 in the context's matrix when it was loaded
-  // with QW_XCD_ROWS; launch_step and launch_adjoint replace it by the
+  // (xcd_row_block, the _x kernels): -1 in the context's matrix when it was
+  // loaded with QW_XCD_ROWS; launch_step and launch_adjoint replace it by the
   // launch's workgroups per XCD (grid / 8; 0, the plain numbering, for a grid
-  // that is not a multiple of 8).
+  // that is not a multiple of 8), pick the _x kernels when it is positive and
+  // pass it to them in the upper bits of wpb.
   int16_t xcd;
   int32_t angles;            // 1: fixed-point data; val holds each slot's rotation angle (below)
   int32_t wide;              // 1: instances with s >= 16 use 16 lanes per row (kWideWaves)
@@ -136,7 +137,8 @@ struct StepArgs {
   unsigned long long* acc;  // running counts of kept outputs (a Q1 output twice), kMaxWaves entries,
                             // or NULL: no counts (a walk whose counts nobody reads)
   int32_t mode;             // kStep: W; kSwap: S only
-  int32_t wpb;              // wavefronts per workgroup (set by the launcher)
+  int32_t wpb;              // wavefronts per workgroup (set by the launcher); for the _x kernels
+                            // bits 8 and up hold the workgroups per XCD (xcd_row_block)
   double tau;
   // optional fused projection (linear solver): y[j] += coef[0] <psi~_j|state>,
   // coef pointing at this launch's coefficient (its entry of the host's table,
@@ -167,7 +169,7 @@ struct AdjArgs {
   unsigned long long* lacc;
   double tau;
   double* dv;       // gradient per slot (by home), accumulated
-  int32_t wpb;      // wavefronts per workgroup (set by the launcher)
+  int32_t wpb;      // wavefronts per workgroup (set by the launcher; bits 8 and up as StepArgs::wpb)
   // 1: both states on one double per cell (the plane pointers point at
   // double arrays; the qwk_adjoint_r kernels: one pass, empty lists)
   int32_t real;

@@ -409,21 +409,19 @@ struct CountBits {
 // counter has one writer, so a plain load at the start and a store at the
 // end replace an atomic (the count store ends the wavefront's work; on a
 // shared line it cost 0.17 us per launch at 16384 x 8).
-// Row block of this workgroup in the one-pass step and adjoint kernels' _x forms.
+// Row block of workgroup p in the one-pass step and adjoint kernels' _x forms.
 // Workgroups are dealt to the eight XCDs in turn (workgroup p runs on XCD
 // p % 8), each with its own L2.  Neighbouring row blocks share cache lines of
 // the 4- and 8-byte planes (a 128-byte line of the link plane spans 32 rows),
-// so with Matrix::xcd = G / 8 > 0 (set by the launcher for a grid G that is a
-// multiple of 8; it then launches the _x forms) the blocks are renumbered to
-// keep neighbours on one XCD:
-// workgroup p takes block (p % 8) * (G / 8) + p / 8.  A tuning choice: which
-// workgroup runs which rows changes, nothing else.  (The grid comes from the
-// arguments, not from gridDim, which costs one more scalar load of the
-// dispatch packet ahead of the data: 3 % per step at 16384 x 8.)
-__device__ __forceinline__ int64_t row_block(const Matrix& m) {
-  const int64_t p = blockIdx.x;
-  return m.xcd > 0 ? (p & 7) * int64_t(m.xcd) + (p >> 3) : p;
-}
+// so the _x forms renumber the blocks to keep neighbours on one XCD: with xb =
+// G / 8 workgroups per XCD (G a multiple of 8), workgroup p takes block
+// (p % 8) * xb + p / 8.  A tuning choice: which workgroup runs which rows
+// changes, nothing else.  The launcher passes xb in bits 8 and up of
+// StepArgs::wpb / AdjArgs::wpb, the argument the prologue loads first anyway:
+// a separate argument, or the grid read from the dispatch packet, put one
+// more scalar load ahead of the data (2.52 against 2.47 us per step at
+// 16384 x 8).
+__device__ __forceinline__ int64_t xcd_row_block(int64_t p, int64_t xb) { return (p & 7) * xb + (p >> 3); }
 
 __device__ __forceinline__ int64_t wave_counter(int64_t wpb) {
   return int64_t(blockIdx.x & 7) * (kMaxWaves / 8) + int64_t(blockIdx.x >> 3) * wpb + (threadIdx.x >> 6);
@@ -865,16 +863,17 @@ __device__ __forceinline__ unsigned step_wave_real(const StepArgs& a, int64_t w,
   return cnt;
 }
 
-// XB: the row blocks numbered by XCD (row_block; the _x kernels, which the
-// launcher takes when Matrix::xcd > 0).  A run-time choice in one kernel cost
-// the plain numbering 1-3 % per step (its arguments and arithmetic reordered
-// the loads of the prologue), so each numbering has kernels of its own.
+// XB: the row blocks numbered by XCD (xcd_row_block; the _x kernels, which
+// the launcher takes when Matrix::xcd > 0).  A run-time choice in one kernel
+// cost the plain numbering 1-3 % per step (its arguments and arithmetic
+// reordered the loads of the prologue), so each numbering has kernels of its
+// own.
 template <bool ACC, int SLM, int S, int ENC, int W = 0, bool EQ0 = false, bool XB = false>
 __device__ __forceinline__ void step_body_real(const StepArgs& a) {
   const int lane = threadIdx.x & (kWave - 1);
-  const int64_t wpb = a.wpb;
-  int64_t w = 0;
-  if constexpr (!XB) w = uniform(int(int64_t(blockIdx.x) * wpb + (threadIdx.x >> 6)));
+  const int64_t wpb = XB ? int64_t(a.wpb & 0xff) : int64_t(a.wpb);
+  const int64_t blk = XB ? xcd_row_block(blockIdx.x, int64_t(a.wpb >> 8)) : int64_t(blockIdx.x);
+  const int64_t w = uniform(int(blk * wpb + (threadIdx.x >> 6)));
   // The arguments the wavefront needs, in registers before the branch below:
   // otherwise they are loaded after it, one more scalar-load round trip
   // ahead of the data loads (2.67 against 2.60 us per step at 16384 x 8).
@@ -882,12 +881,6 @@ __device__ __forceinline__ void step_body_real(const StepArgs& a) {
                "s"(a.in.R1), "s"(a.out.R0), "s"(a.out.Q1), "s"(a.in.r1s), "s"(a.tau), "s"(a.acc));
   asm volatile("" ::"s"(a.m.ninst), "s"(a.m.inst0.wave_base), "s"(a.m.inst0.s), "s"(a.m.inst0.N), "s"(a.in.Q0),
                "s"(a.out.Q0), "s"(a.m.inst0.inv_sqrt_s), "s"(a.m.inst0.jbase), "s"(a.m.inst), "s"(a.m.wave_inst));
-  if constexpr (XB) {
-    // after the others: computed first, its argument was loaded and waited
-    // for ahead of them, a round trip of its own
-    asm volatile("" ::"s"(a.m.xcd), "s"(a.m.waves), "s"(wpb));
-    w = uniform(int(row_block(a.m) * wpb + (threadIdx.x >> 6)));
-  }
   if (w >= a.m.waves) return;  // no list: nothing to do past the slots
   const double coef = ACC ? *a.coef : 0.0;
   const int64_t cidx = wave_counter(wpb);
@@ -1240,8 +1233,8 @@ __device__ __forceinline__ unsigned adjoint_wave_real(const AdjArgs& a, int64_t 
 template <int SLM, int S, int W = 0, bool EQ0 = false, bool XB = false>
 __device__ __forceinline__ void adjoint_body_real(const AdjArgs& a) {
   const int lane = threadIdx.x & (kWave - 1);
-  const int64_t wpb = a.wpb;
-  const int64_t blk = XB ? row_block(a.m) : int64_t(blockIdx.x);
+  const int64_t wpb = XB ? int64_t(a.wpb & 0xff) : int64_t(a.wpb);
+  const int64_t blk = XB ? xcd_row_block(blockIdx.x, int64_t(a.wpb >> 8)) : int64_t(blockIdx.x);
   const int64_t w = uniform(int(blk * wpb + (threadIdx.x >> 6)));
   if (w >= a.m.waves) return;
   const int64_t cidx = wave_counter(wpb);

@@ -342,6 +342,7 @@ hipError_t launch_step(const StepArgs& a, int grid, int block, hipStream_t strea
   StepArgs c = a;
   c.wpb = block / kWave;
   c.m.xcd = xcd_blocks(a.m, grid);
+  if (c.m.xcd > 0 && a.real) c.wpb |= int32_t(c.m.xcd) << 8;  // the _x kernels' workgroups per XCD
   void* p[] = {&c};
   return launch(step_kernel(c, grid, block), grid, block, stream, p);
 }
@@ -352,6 +353,7 @@ hipError_t launch_adjoint(const AdjArgs& a, int grid, int block, hipStream_t str
   AdjArgs c = a;
   c.wpb = block / kWave;
   c.m.xcd = xcd_blocks(a.m, grid);
+  if (c.m.xcd > 0 && a.real) c.wpb |= int32_t(c.m.xcd) << 8;  // the _x kernels' workgroups per XCD
   if (!a.real) {
     c.real = 0;
     void* p[] = {&c};
