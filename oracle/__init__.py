@@ -81,6 +81,7 @@ def _load():
         "orc_fx_rotation": (None, [u64, i32, u64, u64, dp, dp, dp]),
         "orc_qls_walk": (ctypes.c_int, [P, dp, i32, i32, dp, dbl, dp, dp]),
         "orc_grad": (ctypes.c_int, [P, dp, dp, i32, i32, dp, dbl, dp, dp, dp, dp]),
+        "orc_grad_complex": (ctypes.c_int, [P, dp, dp, i32, i32, dp, dbl, dp, dp, dp, dp, dp]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -189,7 +190,8 @@ class OracleMatrix:
         return yr + 1j * yi
 
     def grad(self, b, w, nsteps: int, tau: float = TAU):
-        """Reverse mode with stored states: returns (loss, dv[N,s], db complex)."""
+        """Reverse mode with stored states: returns (loss, dv[N,s], db complex).
+        For a complex matrix dv is complex: dL/dRe v + i dL/dIm v per slot."""
         b = np.asarray(b)
         br, brp = _d(b.real)
         bi, bip = _d(np.imag(b) if np.iscomplexobj(b) else np.zeros(b.shape[0]))
@@ -197,6 +199,13 @@ class OracleMatrix:
         dv = np.zeros(self.N * self.s)
         dbr, dbi = np.zeros(self.N), np.zeros(self.N)
         loss = ctypes.c_double()
+        if self.complex:
+            dvi = np.zeros(self.N * self.s)
+            _check(_load().orc_grad_complex(self._h, brp, bip, br.shape[0], int(nsteps), wp, tau,
+                                            _d(dv)[1], _d(dvi)[1], _d(dbr)[1], _d(dbi)[1], ctypes.byref(loss)))
+            g = np.empty(self.N * self.s, np.complex128)
+            g.real, g.imag = dv, dvi  # not dv + 1j * dvi: 1j * nan is nan + nan i
+            return loss.value, g.reshape(self.N, self.s), dbr + 1j * dbi
         _check(_load().orc_grad(self._h, brp, bip, br.shape[0], int(nsteps), wp, tau,
                                 _d(dv)[1], _d(dbr)[1], _d(dbi)[1], ctypes.byref(loss)))
         return loss.value, dv.reshape(self.N, self.s), dbr + 1j * dbi

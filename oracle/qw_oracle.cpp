@@ -898,6 +898,34 @@ int orc_qls_walk(void* mat, const double* b, int32_t nb, int32_t j0, const doubl
   });
 }
 
+// d f / d Re v and d g / d Re v (im = false), or the same with respect to
+// Im v (im = true), for a complex value v = a + i b.  Off the real axis f is
+// the principal sqrt(v), holomorphic there, so df/da = 1/(2f) and
+// df/db = i/(2f); g = sqrt(1 - |v|) with d|v|/da = a/|v| and d|v|/db = b/|v|.
+// On the axis the real rule of rotation() holds: with respect to a it is
+// rotation_deriv; with respect to b the principal root is analytic only for
+// a > 0 (df/db = i/(2 sqrt a), dg/db = 0), and for a <= 0 the derivative does
+// not exist (NaN: the real rule's +-i branch is one side of the cut).
+Rot rotation_deriv_c(double a, double b, uint64_t j, uint64_t k, bool im) {
+  if (b == 0.0 && !im) return rotation_deriv(a, j, k);
+  Rot d;
+  if (b == 0.0) {
+    if (a > 0.0) {
+      d.f = cplx(0.0, 0.5 / std::sqrt(a));
+      d.g = 0.0;
+    } else {
+      d.f = cplx(NAN, NAN);
+      d.g = NAN;
+    }
+    return d;
+  }
+  const cplx f = std::sqrt(cplx(a, b));
+  const double mod = std::abs(cplx(a, b));
+  d.f = (im ? cplx(0.0, 1.0) : cplx(1.0, 0.0)) / (2.0 * f);
+  d.g = -(im ? b : a) / (2.0 * mod * std::sqrt(1.0 - mod));
+  return d;
+}
+
 // ---- reverse-mode gradient with stored states ---------------------------------
 // Loss L = sum_j w_j p_j(psi_n), psi_n = W^n T~ |b~>.  Forward: every operation
 // of T~ and of the n walk steps is applied in order, and the input state of
@@ -906,12 +934,15 @@ int orc_qls_walk(void* mat, const double* b, int32_t nb, int32_t j0, const doubl
 // reverse, a rotation site adds 2 Re <lambda_out | dU/da | x_in> to the value
 // the site's A register holds (slot l = k_c ^ i_j(k) of row j), and lambda is
 // mapped through the inverse operation.  At the start, dL/db_j = 2 lambda(j~).
-// dv is indexed by ELL slot (j*s + l).
-int orc_grad(void* mat, const double* bre, const double* bim, int32_t nb, int32_t nsteps,
-             const double* w, double tau, double* dv, double* dbre, double* dbim, double* loss) {
+// dv is indexed by ELL slot (j*s + l).  For a complex matrix dv holds
+// dL/dRe v and dvi dL/dIm v, each entry taken as an independent parameter
+// (the Hermitian mirror of an entry has its own derivative).
+static int grad_impl(void* mat, const double* bre, const double* bim, int32_t nb, int32_t nsteps,
+                     const double* w, double tau, double* dv, double* dvi, double* dbre, double* dbim, double* loss) {
   const Matrix& m = *static_cast<Matrix*>(mat);
   return guarded([&] {
-    if (m.complex_values) fail("the gradient is defined for real matrices only");
+    if (m.complex_values && !dvi) fail("a complex matrix takes the complex gradient (orc_grad_complex)");
+    if (!m.complex_values && dvi) fail("a real matrix takes orc_grad");
     if (m.word > 0) fail("the gradient is defined for real-valued (not fixed-point) data only");
     OState o;
     o.m = &m;
@@ -947,6 +978,7 @@ int orc_grad(void* mat, const double* bre, const double* bim, int32_t nb, int32_
     }
     *loss = L;
     std::fill(dv, dv + size_t(m.N) * m.s, 0.0);
+    if (dvi) std::fill(dvi, dvi + size_t(m.N) * m.s, 0.0);
     for (size_t ii = prog.size(); ii-- > 0;) {
       const Op op = prog[ii];
       if (op == CR || op == CRDAG) {
@@ -969,20 +1001,28 @@ int orc_grad(void* mat, const double* bre, const double* bim, int32_t nb, int32_
           auto it = lout.find(gv.first);
           if (it == lout.end()) continue;
           const Reg& g = gv.first;
-          const double a = double_of(g.A);
-          const Rot d = rotation_deriv(a, g.j, g.k);  // real matrices: A2 = 0
-          cplx D[2][2];
-          rot_matrix(d, dag, D);  // derivative of R or of R^dagger (a is real)
+          const double a = double_of(g.A), ai = double_of(g.A2);  // A2 = 0 for real matrices
           const cplx x0 = gv.second.first, x1 = gv.second.second;
           const cplx l0 = it->second.first, l1 = it->second.second;
-          const cplx y0 = D[0][0] * x0 + D[0][1] * x1;
-          const cplx y1 = D[1][0] * x0 + D[1][1] * x1;
-          const double contrib = 2.0 * (std::conj(l0) * y0 + std::conj(l1) * y1).real();
+          // 2 Re <lambda_out| dU/dp |x_in> for a real parameter p of the value
+          const auto contrib = [&](const Rot& d) {
+            cplx D[2][2];
+            rot_matrix(d, dag, D);  // derivative of R or of R^dagger (p is real)
+            const cplx y0 = D[0][0] * x0 + D[0][1] * x1;
+            const cplx y1 = D[1][0] * x0 + D[1][1] * x1;
+            return 2.0 * (std::conj(l0) * y0 + std::conj(l1) * y1).real();
+          };
           const int32_t* row = &m.col[g.j * m.s];
           const uint64_t l = g.kc ^ qbs(row, m.s, g.k);
           if (l >= uint64_t(m.s)) fail("rotation site with slot >= s");
           if (bits_of(m.val[g.j * m.s + l]) != g.A) fail("A register does not hold a_{j,l}");
-          dv[g.j * m.s + l] += contrib;
+          if (!dvi) {
+            dv[g.j * m.s + l] += contrib(rotation_deriv(a, g.j, g.k));
+          } else {
+            if (bits_of(m.vim[g.j * m.s + l]) != g.A2) fail("A2 register does not hold Im a_{j,l}");
+            dv[g.j * m.s + l] += contrib(rotation_deriv_c(a, ai, g.j, g.k, false));
+            dvi[g.j * m.s + l] += contrib(rotation_deriv_c(a, ai, g.j, g.k, true));
+          }
         }
       }
       apply(lam, m, inverse(op));
@@ -997,6 +1037,18 @@ int orc_grad(void* mat, const double* bre, const double* bim, int32_t nb, int32_
       }
     }
   });
+}
+
+int orc_grad(void* mat, const double* bre, const double* bim, int32_t nb, int32_t nsteps, const double* w,
+             double tau, double* dv, double* dbre, double* dbim, double* loss) {
+  return grad_impl(mat, bre, bim, nb, nsteps, w, tau, dv, nullptr, dbre, dbim, loss);
+}
+
+// The complex matrices' form: dv = dL/dRe v, dvi = dL/dIm v by ELL slot.
+int orc_grad_complex(void* mat, const double* bre, const double* bim, int32_t nb, int32_t nsteps, const double* w,
+                     double tau, double* dv, double* dvi, double* dbre, double* dbim, double* loss) {
+  if (!dvi) return guarded([] { fail("orc_grad_complex needs dvi"); });
+  return grad_impl(mat, bre, bim, nb, nsteps, w, tau, dv, dvi, dbre, dbim, loss);
 }
 
 }  // extern "C"

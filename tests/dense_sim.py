@@ -214,14 +214,16 @@ class DenseWalk:
 
 def torch_loss(csc, vals_scaled, b, w, nsteps, scale=1.0):
     """Same dense walk written with torch ops, differentiable in the stored
-    (already scaled) CSC values and in b.  Returns (loss, vals tensor, b tensor).
+    (already scaled) CSC values (real, or complex for a complex matrix) and in b.  Returns (loss, vals tensor, b tensor).
     Loss = sum_j w_j p_j with p the marginal of register j after
     W^nsteps T~ |b~>."""
     import torch
 
     dw = DenseWalk(csc, scale=scale)
     N, s = dw.N, dw.s
-    v = torch.tensor(np.asarray(vals_scaled, dtype=np.float64), requires_grad=True)
+    cplx = np.iscomplexobj(vals_scaled)
+    vdt = torch.complex128 if cplx else torch.float64
+    v = torch.tensor(np.asarray(vals_scaled, dtype=np.complex128 if cplx else np.float64), requires_grad=True)
     bt = torch.tensor(np.asarray(b, dtype=np.complex128), requires_grad=True)
     # ELL value table as a differentiable gather of the CSC values
     slot_of = np.full((N, s), -1, np.int64)
@@ -229,7 +231,7 @@ def torch_loss(csc, vals_scaled, b, w, nsteps, scale=1.0):
         for p in range(csc.colptr[c], csc.colptr[c + 1]):
             l = int(np.nonzero(dw.col[c] == csc.rowidx[p])[0][0])
             slot_of[c, l] = p
-    ell = torch.zeros(N * s, dtype=torch.float64)
+    ell = torch.zeros(N * s, dtype=vdt)
     idx = np.nonzero(slot_of.reshape(-1) >= 0)[0]
     ell = ell.index_put((torch.tensor(idx),), v[torch.tensor(slot_of.reshape(-1)[idx])])
     ell = ell.reshape(N, s)
@@ -239,9 +241,15 @@ def torch_loss(csc, vals_scaled, b, w, nsteps, scale=1.0):
     a = ell[torch.tensor(j), torch.tensor(ll)]
     colk = kc ^ dw.col[j, ll]
     neg_phase = np.where(j <= colk, 1j, -1j)
-    phase = torch.where(a >= 0, torch.ones_like(a, dtype=torch.complex128),
-                        torch.tensor(neg_phase, dtype=torch.complex128))
-    f = torch.sqrt(torch.abs(a)) * phase
+    if cplx:
+        # the principal sqrt(a) off the negative real axis, the +-i rule on it
+        cut = (a.imag == 0) & (a.real < 0)
+        f_rule = torch.sqrt(torch.abs(a)) * torch.tensor(neg_phase, dtype=torch.complex128)
+        f = torch.where(cut, f_rule, torch.sqrt(torch.where(cut, torch.ones_like(a), a)))
+    else:
+        phase = torch.where(a >= 0, torch.ones_like(a, dtype=torch.complex128),
+                            torch.tensor(neg_phase, dtype=torch.complex128))
+        f = torch.sqrt(torch.abs(a)) * phase
     g = torch.sqrt(1.0 - torch.abs(a)).to(torch.complex128)
     valid = torch.tensor(dw.rot_valid)
     b2t = torch.tensor(dw.b2)
