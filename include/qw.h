@@ -162,8 +162,8 @@ int qw_load_csc_batched(qw_ctx** out, int32_t ninst, const int32_t* n, const int
  * part).  QW_REQUIRE_SYMMETRIC requires A_kj = conj(A_jk) exactly.  Scaling
  * uses |a| = hypot(re, im).  Errors: as qw_load_csc, plus QW_EINVAL for a
  * diagonal entry with a nonzero imaginary part, QW_ENOTSUP with
- * QW_WORD_LENGTH.  qw_grad is not provided for such a context (QW_ENOTSUP);
- * every other entry point is. */
+ * QW_WORD_LENGTH.  Such a context takes qw_grad_complex instead of qw_grad
+ * (QW_ENOTSUP there). */
 int qw_load_csc_hermitian(qw_ctx** out, int32_t ninst, const int32_t* n, const int64_t* colptr_off,
                           const int64_t* nnz_off, const int32_t* colptr, const int32_t* rowidx,
                           const double* vals_re, const double* vals_im, const double* scales, uint32_t flags,
@@ -309,6 +309,20 @@ int qw_cks_coeffs(int64_t beta, int32_t j0, double* out);
  * NULL.  The state is consumed (left holding the recomputed T~|b~>). */
 int qw_grad(qw_state* st, const double* w, int32_t nsteps, double* dvals, double* db_re, double* db_im,
             double* loss, void* stream);
+
+/* qw_grad for a context of complex Hermitian values (qw_load_csc_hermitian;
+ * a real context: QW_ENOTSUP, use qw_grad).  The rotation of a value
+ * v = a + i b is f = sqrt(v) (the principal root off the real axis, the +-i
+ * rule of real values on it) and g = sqrt(1 - |v|) (Sec. IV); reverse mode
+ * differentiates it by a and by b, each stored entry an independent
+ * parameter (the mirror conj(v) of an entry has derivatives of its own).
+ * dvals_re[p] = dL/da and dvals_im[p] = dL/db of CSC entry p after scaling
+ * (CSC order, instance after instance).  Not differentiable, non-finite:
+ * both parts at v = 0 and |v| = 1, and dL/db on the negative real axis,
+ * where the +-i rule is one side of the principal root's cut.  Other
+ * arguments, results and errors as qw_grad. */
+int qw_grad_complex(qw_state* st, const double* w, int32_t nsteps, double* dvals_re, double* dvals_im,
+                    double* db_re, double* db_im, double* loss, void* stream);
 
 /* qw_grad without allocating anything: for callers that cannot allocate
  * device memory (tight serving loops, harnesses that forbid allocation).

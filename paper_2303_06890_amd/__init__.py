@@ -306,27 +306,38 @@ class State:
 
     def grad(self, w, nsteps: int):
         """Reverse-mode gradient of sum_j w_j p_j after ``nsteps`` steps from
-        T~|b~>: returns (loss, dvals in CSC order, db complex).  The library
+        T~|b~>: returns (loss, dvals in CSC order, db complex).  For complex
+        Hermitian values dvals is complex, dL/dRe v + i dL/dIm v
+        (qw_grad_complex); for real values it is real (qw_grad).  The library
         copies the results into pinned host buffers (torch's pinned
-        allocator), which dvals then shares."""
+        allocator), which a real dvals then shares."""
         torch = _torch()
         w = np.ascontiguousarray(w, dtype=np.float64)
         if w.shape[0] != self.walk.n_total:
             raise ValueError("w must have one weight per column of every instance")
-        dv = torch.empty(self.walk.nnz_total, dtype=torch.float64, pin_memory=True)
+        nnz = self.walk.nnz_total
+        dv = torch.empty((2 if self.walk.complex else 1) * nnz, dtype=torch.float64, pin_memory=True)
         dbb = torch.empty(2 * self.walk.n_total, dtype=torch.float64, pin_memory=True)
         dp = ctypes.POINTER(ctypes.c_double)
         loss = ctypes.c_double()
-        check(_lib.load().qw_grad(self._h, _dp(w), int(nsteps), ctypes.cast(dv.data_ptr(), dp),
-                                  ctypes.cast(dbb.data_ptr(), dp),
-                                  ctypes.cast(dbb.data_ptr() + 8 * self.walk.n_total, dp), ctypes.byref(loss),
-                                  _stream()))
-        db = dbb.numpy()
+        ptr = lambda t, off=0: ctypes.cast(t.data_ptr() + 8 * off, dp)  # noqa: E731
         n = self.walk.n_total
+        if self.walk.complex:
+            check(_lib.load().qw_grad_complex(self._h, _dp(w), int(nsteps), ptr(dv), ptr(dv, nnz), ptr(dbb),
+                                              ptr(dbb, n), ctypes.byref(loss), _stream()))
+            g = dv.numpy()
+            dvals = np.empty(nnz, np.complex128)
+            dvals.real = g[:nnz]  # not re + 1j * im: 1j * nan is nan + nan i
+            dvals.imag = g[nnz:]
+        else:
+            check(_lib.load().qw_grad(self._h, _dp(w), int(nsteps), ptr(dv), ptr(dbb), ptr(dbb, n),
+                                      ctypes.byref(loss), _stream()))
+            dvals = dv.numpy()
+        db = dbb.numpy()
         dbc = np.empty(n, np.complex128)
         dbc.real = db[:n]
         dbc.imag = db[n:]
-        return loss.value, dv.numpy(), dbc
+        return loss.value, dvals, dbc
 
 
 def cks_coeffs(beta: int, j0: int) -> np.ndarray:
@@ -353,13 +364,16 @@ def _make_walk_observable():
 
     class WalkObservable(torch.autograd.Function):
         """p = j-register marginal of W^nsteps T~|b~> for the matrix with the
-        given CSC pattern and (already scaled) values; differentiable in the
-        values and in b.  The backward pass is the library's reverse sweep
-        (qw_grad): earlier states are recomputed with W^dagger."""
+        given CSC pattern and (already scaled) values, real or complex
+        Hermitian; differentiable in the values and in b (torch's convention
+        for complex inputs: dL/dRe + i dL/dIm).  The backward pass is the
+        library's reverse sweep (qw_grad, qw_grad_complex): earlier states
+        are recomputed with W^dagger."""
 
         @staticmethod
         def forward(ctx, vals, b, pattern, nsteps):
-            v = vals.detach().cpu().numpy().astype(np.float64)
+            v = vals.detach().cpu().numpy()
+            v = v.astype(np.complex128 if np.iscomplexobj(v) else np.float64)
             mat = _CscArrays(pattern.n, np.asarray(pattern.colptr, np.int32), np.asarray(pattern.rowidx, np.int32), v)
             walk = Walk(mat, scale=1.0, symmetric=False)  # entries are independent parameters
             st = walk.state(b.detach().cpu().numpy())

@@ -32,7 +32,7 @@ SYMBOLS = [
     "qw_load_csc", "qw_load_csc_batched", "qw_ctx_info", "qw_ctx_ninst", "qw_state_init", "qw_step",
     "qw_step_adjoint", "qw_measure", "qw_export", "qw_export_complex", "qw_state_import", "qw_state_import_complex", "qw_sync", "qls_run",
     "qw_cks_coeffs", "qw_grad", "qw_state_free", "qw_ctx_free", "qw_last_error", "qw_set_launch",
-    "qw_shutdown", "qw_load_csc_hermitian", "qw_kappa", "qw_grad_noalloc",
+    "qw_shutdown", "qw_load_csc_hermitian", "qw_kappa", "qw_grad_noalloc", "qw_grad_complex",
 ]
 
 ALLOC_T = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p)
@@ -90,6 +90,7 @@ def load() -> ctypes.CDLL:
         "qw_cks_coeffs": (c_int, [i64, i32, dp]),
         "qw_grad": (c_int, [P, dp, i32, dp, dp, dp, dp, P]),
         "qw_grad_noalloc": (c_int, [P, dp, i32, dp, dp, dp, dp, P]),
+        "qw_grad_complex": (c_int, [P, dp, i32, dp, dp, dp, dp, dp, P]),
         "qw_state_free": (None, [P]),
         "qw_ctx_free": (None, [P]),
         "qw_last_error": (ctypes.c_char_p, []),

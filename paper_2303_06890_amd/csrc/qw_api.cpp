@@ -1267,12 +1267,15 @@ void cks_coefficients(int64_t beta, int32_t j0, double* out) {
   }
 }
 
-// Argument checks shared by qw_grad and qw_grad_noalloc.
-int grad_check(qw_state* st, const double* w, int32_t nsteps) {
+// Argument checks shared by qw_grad, qw_grad_noalloc (real values) and
+// qw_grad_complex (complex values).
+int grad_check(qw_state* st, const double* w, int32_t nsteps, bool complex_form = false) {
   if (!st || !w) return set_err(QW_EINVAL, "missing argument");
   if (!st->prepared || st->steps_since_init != nsteps)
     return set_err(QW_EINVAL, "qw_grad needs the state made by qw_state_init (T~ start) advanced by exactly nsteps");
-  if (st->ctx->complex_values) return set_err(QW_ENOTSUP, "the gradient is provided for real matrices only");
+  if (st->ctx->complex_values && !complex_form)
+    return set_err(QW_ENOTSUP, "a complex Hermitian matrix takes qw_grad_complex");
+  if (!st->ctx->complex_values && complex_form) return set_err(QW_ENOTSUP, "a real matrix takes qw_grad");
   if (st->ctx->word > 0)
     return set_err(QW_ENOTSUP, "the gradient is provided for FP64 values only, not fixed-point data");
   return QW_OK;
@@ -1285,6 +1288,7 @@ struct GradBufs {
   double* dv = nullptr;
   double2* db = nullptr;
   double* dg = nullptr;
+  double* dvi = nullptr;  // dL/d(Im v) by home: complex values only (dg then holds nnz more results)
 };
 
 // The reverse sweep of the gradient, on the state st (advanced by nsteps from
@@ -1296,13 +1300,14 @@ struct GradBufs {
 //   the results gathered into the caller's order and copied out.
 // Synchronises the stream; the state is left holding the recomputed T~|b~>.
 int grad_sweep(qw_state* st, qw_state* lam, bool real, const GradBufs& gb, int32_t nsteps, double* dvals,
-               double* db_re, double* db_im, double* loss, hipStream_t stream) {
+               double* dvals_im, double* db_re, double* db_im, double* loss, hipStream_t stream) {
   qw_ctx* ctx = st->ctx;
   const qw::Matrix mm = ctx->mat();
   double part[256];
   int rc = QW_OK;
   st->cview = false;  // the sweep moves the real planes
   hipError_t e = qw::launch_fill(gb.dv, (sizeof(double) * ctx->items + 15) / 16 * 16, stream);
+  if (e == hipSuccess && gb.dvi) e = qw::launch_fill(gb.dvi, (sizeof(double) * ctx->items + 15) / 16 * 16, stream);
   if (e == hipSuccess && real) {
     rc = swap_real(st, stream);
     if (!rc)
@@ -1335,6 +1340,7 @@ int grad_sweep(qw_state* st, qw_state* lam, bool real, const GradBufs& gb, int32
     a.lacc = lam->acc;
     a.tau = qw::kTau;
     a.dv = gb.dv;
+    a.dvi = gb.dvi;
     a.wpb = 0;  // set by the launcher
     a.real = real ? 1 : 0;
     a.q0 = ctx->q0 ? 1 : 0;
@@ -1352,18 +1358,21 @@ int grad_sweep(qw_state* st, qw_state* lam, bool real, const GradBufs& gb, int32
   } else if (e == hipSuccess && !rc) {
     rc = launch_one(st, qw::kSwap, stream);
     if (!rc) rc = launch_one(lam, qw::kSwap, stream);
-    if (!rc) e = qw::launch_grad_init(mm, view(lam), st->b, gb.dv, gb.db, stream);
+    if (!rc) e = qw::launch_grad_init(mm, view(lam), st->b, gb.dv, gb.db, gb.dvi, stream);
   }
   // the results in the caller's order (CSC entries; b's columns, real and
   // imaginary parts), gathered on the device and copied straight out
   double* gv = gb.dg;
   double* gbr = gb.dg + ctx->nnz_total;
   double* gbi = gbr + ctx->ntotal;
+  double* gvi = gb.dvi ? gbi + ctx->ntotal : nullptr;
   if (e == hipSuccess && !rc)
     e = qw::launch_gather_grad(gb.dv, ctx->dcsc_home, ctx->nnz_total, gb.db, ctx->dcol_row, ctx->ntotal, gv, gbr, gbi,
-                               stream);
+                               gb.dvi, gvi, stream);
   if (e == hipSuccess && !rc && dvals)
     e = hipMemcpyAsync(dvals, gv, sizeof(double) * ctx->nnz_total, hipMemcpyDeviceToHost, stream);
+  if (e == hipSuccess && !rc && dvals_im && gvi)
+    e = hipMemcpyAsync(dvals_im, gvi, sizeof(double) * ctx->nnz_total, hipMemcpyDeviceToHost, stream);
   if (e == hipSuccess && !rc && db_re)
     e = hipMemcpyAsync(db_re, gbr, sizeof(double) * ctx->ntotal, hipMemcpyDeviceToHost, stream);
   if (e == hipSuccess && !rc && db_im)
@@ -1846,13 +1855,19 @@ int qls_run(qw_ctx* ctx, const double* b, double kappa, double eps, int32_t j0_o
   });
 }
 
-int qw_grad(qw_state* st, const double* w, int32_t nsteps, double* dvals, double* db_re, double* db_im,
-            double* loss, void* stream_v) {
+}  // extern "C"
+
+namespace {
+
+// qw_grad and qw_grad_complex: the sweep on buffers of the context's pool;
+// dvals_im is used for complex values only.
+int grad_impl(qw_state* st, const double* w, int32_t nsteps, double* dvals, double* dvals_im, double* db_re,
+              double* db_im, double* loss, void* stream_v, bool complex_form) {
   return guarded([&]() -> int {
-    int rc = grad_check(st, w, nsteps);
+    int rc = grad_check(st, w, nsteps, complex_form);
     if (rc) return rc;
     hipStream_t stream = static_cast<hipStream_t>(stream_v);
-    const bool real = real_path(st);
+    const bool real = !complex_form && real_path(st);
     rc = real ? to_real(st, stream) : to_complex(st, stream);
     if (rc) return rc;
     qw_ctx* ctx = st->ctx;
@@ -1868,23 +1883,39 @@ int qw_grad(qw_state* st, const double* w, int32_t nsteps, double* dvals, double
     gb.dw = static_cast<double*>(ctx_take(ctx, sizeof(double) * ctx->jtotal));
     gb.dv = static_cast<double*>(ctx_take(ctx, sizeof(double) * ctx->items));
     gb.db = static_cast<double2*>(ctx_take(ctx, sizeof(double2) * ctx->jtotal));
-    const size_t gbytes = sizeof(double) * size_t(ctx->nnz_total + 2 * ctx->ntotal);
+    const size_t gbytes = sizeof(double) * size_t((complex_form ? 2 : 1) * ctx->nnz_total + 2 * ctx->ntotal);
     gb.dg = static_cast<double*>(ctx_take(ctx, gbytes));
-    hipError_t e = (gb.dw && gb.dv && gb.db && gb.dg) ? hipSuccess : hipErrorOutOfMemory;
+    if (complex_form) gb.dvi = static_cast<double*>(ctx_take(ctx, sizeof(double) * ctx->items));
+    hipError_t e = (gb.dw && gb.dv && gb.db && gb.dg && (gb.dvi || !complex_form)) ? hipSuccess : hipErrorOutOfMemory;
     if (e == hipSuccess)
       e = hipMemcpyAsync(gb.dw, hw.data(), sizeof(double) * ctx->jtotal, hipMemcpyHostToDevice, stream);
     if (e == hipSuccess)
-      rc = grad_sweep(st, lam, real, gb, nsteps, dvals, db_re, db_im, loss, stream);
+      rc = grad_sweep(st, lam, real, gb, nsteps, dvals, dvals_im, db_re, db_im, loss, stream);
     (void)hipStreamSynchronize(stream);  // after an error too: nothing may still use the buffers
     if (gb.dw) ctx_give(ctx, gb.dw, sizeof(double) * ctx->jtotal);
     if (gb.dv) ctx_give(ctx, gb.dv, sizeof(double) * ctx->items);
     if (gb.db) ctx_give(ctx, gb.db, sizeof(double2) * ctx->jtotal);
     if (gb.dg) ctx_give(ctx, gb.dg, gbytes);
+    if (gb.dvi) ctx_give(ctx, gb.dvi, sizeof(double) * ctx->items);
     qw_state_free(lam);
     if (e != hipSuccess)
       return set_err(e == hipErrorOutOfMemory ? QW_ENOMEM : QW_EDEVICE, std::string("gradient: ") + hipGetErrorString(e));
     return rc;
   });
+}
+
+}  // namespace
+
+extern "C" {
+
+int qw_grad(qw_state* st, const double* w, int32_t nsteps, double* dvals, double* db_re, double* db_im,
+            double* loss, void* stream) {
+  return grad_impl(st, w, nsteps, dvals, nullptr, db_re, db_im, loss, stream, false);
+}
+
+int qw_grad_complex(qw_state* st, const double* w, int32_t nsteps, double* dvals_re, double* dvals_im,
+                    double* db_re, double* db_im, double* loss, void* stream) {
+  return grad_impl(st, w, nsteps, dvals_re, dvals_im, db_re, db_im, loss, stream, true);
 }
 
 int qw_grad_noalloc(qw_state* st, const double* w, int32_t nsteps, double* dvals, double* db_re, double* db_im,
@@ -1950,7 +1981,7 @@ int qw_grad_noalloc(qw_state* st, const double* w, int32_t nsteps, double* dvals
       QW_HIP(hipMemcpyAsync(gb.dw + hi.jbase, w + src, sizeof(double) * hi.n, hipMemcpyHostToDevice, stream));
       src += hi.n;
     }
-    rc = grad_sweep(st, &lam, true, gb, nsteps, dvals, db_re, db_im, loss, stream);
+    rc = grad_sweep(st, &lam, true, gb, nsteps, dvals, nullptr, db_re, db_im, loss, stream);
     (void)hipStreamSynchronize(stream);
     return rc;
   });

@@ -174,6 +174,10 @@ struct AdjArgs {
   // double arrays; the qwk_adjoint_r kernels: one pass, empty lists)
   int32_t real;
   int32_t q0;  // as StepArgs::q0
+  // dL/d(Im v) per slot (by home), accumulated: complex values only (the
+  // complex-plane kernels with Matrix::vim), NULL otherwise; dv then holds
+  // dL/d(Re v).
+  double* dvi;
 };
 
 // The host side is compiled by the host compiler and the kernels by the GPU
@@ -185,7 +189,8 @@ static_assert(sizeof(SlotRec) == 16 && offsetof(SlotRec, val) == 8, "SlotRec lay
 static_assert(sizeof(Matrix) == 184 && offsetof(Matrix, inst0) == 128, "Matrix layout");
 static_assert(sizeof(StepArgs) == 344 && offsetof(StepArgs, zskip) == 328 && offsetof(StepArgs, q0) == 336,
               "StepArgs layout");
-static_assert(sizeof(AdjArgs) == 440 && offsetof(AdjArgs, wpb) == 424 && offsetof(AdjArgs, q0) == 432,
+static_assert(sizeof(AdjArgs) == 448 && offsetof(AdjArgs, wpb) == 424 && offsetof(AdjArgs, q0) == 432 &&
+                  offsetof(AdjArgs, dvi) == 440,
               "AdjArgs layout");
 
 // The current device's `scratch` array: its device address and size, looked
@@ -237,7 +242,8 @@ hipError_t launch_import(const Matrix& m, const uint64_t* keys, const double2* a
                          uint32_t* lcnt, hipStream_t stream);
 hipError_t launch_weight(const Matrix& m, Slots in, List L, Slots out, List LL, const double* w, double* partial,
                          int grid, hipStream_t stream);
-hipError_t launch_grad_init(const Matrix& m, Slots lam, const double2* b, double* dv, double2* db,
+// dvi: dL/d(Im v) by home for complex values (Matrix::vim), NULL otherwise.
+hipError_t launch_grad_init(const Matrix& m, Slots lam, const double2* b, double* dv, double2* db, double* dvi,
                             hipStream_t stream);
 // The same three on one double per cell (the plane pointers point at double
 // arrays): the swap S (counted into acc unless NULL), the weighting, and the
@@ -247,9 +253,10 @@ hipError_t launch_weight_real(const Matrix& m, Slots in, Slots out, const double
                               hipStream_t stream);
 hipError_t launch_grad_init_real(const Matrix& m, Slots lam, const double2* b, double* dv, double2* db,
                                  hipStream_t stream);
-// gv[p] = dv[home[p]] (p < nnz) and br/bi[p] = db[row[p]] (p < n).
+// gv[p] = dv[home[p]] (p < nnz) and br/bi[p] = db[row[p]] (p < n); with
+// dvi (complex values) also gvi[p] = dvi[home[p]].
 hipError_t launch_gather_grad(const double* dv, const int32_t* home, int64_t nnz, const double2* db,
                               const int32_t* row, int64_t n, double* gv, double* br, double* bi,
-                              hipStream_t stream);
+                              const double* dvi, double* gvi, hipStream_t stream);
 
 }  // namespace qw

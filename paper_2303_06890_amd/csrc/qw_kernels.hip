@@ -143,6 +143,31 @@ __device__ __forceinline__ Rot rotation_deriv(double a, int j, int k) {
   d.g = -sg * 0.5 / sqrt(1.0 - fabs(a));
   return d;
 }
+// The same for a complex value a + i b (rot_cplx), with respect to a
+// (im = false) or to b (im = true).  Off the axis f = sqrt(a + i b) is
+// holomorphic: df/da = 1/(2f), df/db = i/(2f); |v| = hypot(a, b) gives
+// dg/da = -a/(2|v|g), dg/db = -b/(2|v|g).  On the axis rot_cplx takes the
+// real rule: with respect to a that is rotation_deriv; with respect to b the
+// principal root is analytic for a > 0 (df/db = i/(2 sqrt a), dg/db = 0) and
+// has no derivative for a <= 0 (the +-i rule sits on its cut): NaN.
+__device__ __forceinline__ Rot rotation_deriv_c(double a, double b, int j, int k, bool im) {
+  if (b == 0.0) {
+    if (!im) return rotation_deriv(a, j, k);
+    Rot d;
+    const double q = a > 0.0 ? 0.5 / sqrt(a) : __builtin_nan("");
+    d.f = make_double2(a > 0.0 ? 0.0 : q, q);
+    d.g = a > 0.0 ? 0.0 : q;
+    return d;
+  }
+  const Rot r = rot_cplx(a, b, true);  // off the axis the row order does not matter
+  const double m = hypot(a, b);
+  // 1/(2f) = conj(f) / (2|f|^2), |f|^2 = |v|
+  const double2 h = make_double2(0.5 * r.f.x / m, -0.5 * r.f.y / m);
+  Rot d;
+  d.f = im ? make_double2(-h.y, h.x) : h;
+  d.g = -0.5 * (im ? b : a) / (m * r.g);
+  return d;
+}
 // conj(f) x0 + g x1: the component of an amplitude pair along sqrt(s) phi
 __device__ __forceinline__ double2 along(const Rot& r, double2 x0, double2 x1) {
   return cadd(cjmul(r.f, x0), cscale(x1, r.g));
@@ -1055,11 +1080,15 @@ __device__ __forceinline__ void adjoint_wave(const AdjArgs& a, int64_t w, int la
       m1[i] = r1_of(a.lin, h[i]);
     }
   }
+  // complex values: the imaginary parts by home (one uniform test per wavefront)
+  const double* vim = a.m.vim;
+  double vi[SLM];
   double2 c = zero2(), d = zero2();
 #pragma unroll
   for (int i = 0; i < SLM; ++i) {
     if (i < sl) {
-      r[i] = rotation(rc[i].val, x.j, rc[i].col);
+      vi[i] = vim ? vim[h[i]] : 0.0;
+      r[i] = rotation(rc[i].val, vi[i], x.j, rc[i].col);
       c = cadd(c, along(r[i], x0[i], x1[i]));
       d = cadd(d, along(r[i], m0[i], m1[i]));
     }
@@ -1076,11 +1105,18 @@ __device__ __forceinline__ void adjoint_wave(const AdjArgs& a, int64_t w, int la
       const double2 q1 = csub(cscale(tc, r[i].g), x1[i]);
       const double2 w0 = csub(cmul(td, r[i].f), m0[i]);  // reflected adjoint
       const double2 w1 = csub(cscale(td, r[i].g), m1[i]);
-      const Rot dr = rotation_deriv(rc[i].val, x.j, rc[i].col);
       // c (conj(mu_0) f' + conj(mu_1) g') + conj(d) (conj(f') psi'_0 + g' psi'_1)
-      const double2 u = cadd(cmul(c, cadd(cjmul(m0[i], dr.f), make_double2(m1[i].x * dr.g, -m1[i].y * dr.g))),
-                             cjmul(d, cadd(cjmul(dr.f, q0), cscale(q1, dr.g))));
-      a.dv[h[i]] += 2.0 * t * u.x;
+      // for the derivative (f', g') of the rotation by one real parameter
+      const auto du = [&](const Rot& dr) {
+        return cadd(cmul(c, cadd(cjmul(m0[i], dr.f), make_double2(m1[i].x * dr.g, -m1[i].y * dr.g))),
+                    cjmul(d, cadd(cjmul(dr.f, q0), cscale(q1, dr.g))));
+      };
+      if (vim) {
+        a.dv[h[i]] += 2.0 * t * du(rotation_deriv_c(rc[i].val, vi[i], x.j, rc[i].col, false)).x;
+        a.dvi[h[i]] += 2.0 * t * du(rotation_deriv_c(rc[i].val, vi[i], x.j, rc[i].col, true)).x;
+      } else {
+        a.dv[h[i]] += 2.0 * t * du(rotation_deriv(rc[i].val, x.j, rc[i].col)).x;
+      }
       write_slot(a.in, a.out, base, h[i], rc[i].part, q0, q1, true, a.tau, cnt);
       write_slot(a.lin, a.lout, base, h[i], rc[i].part, w0, w1, true, a.tau, lcnt);
     }
@@ -1822,15 +1858,18 @@ extern "C" __global__ void __launch_bounds__(256) qwk_grad_init_real(Matrix m, S
 
 // The gradient's results in the caller's order: gv[p] = dv[home[p]] for the
 // CSC entries, br/bi[p] = db[row[p]] for the unpadded columns.
+// With dvi (complex values): gvi[p] = dvi[home[p]] too.
 extern "C" __global__ void __launch_bounds__(256) qwk_gather_grad(const double* __restrict__ dv,
                                                                   const int32_t* __restrict__ home, int64_t nnz,
                                                                   const double2* __restrict__ db,
                                                                   const int32_t* __restrict__ row, int64_t n,
-                                                                  double* gv, double* br, double* bi) {
+                                                                  double* gv, double* br, double* bi,
+                                                                  const double* __restrict__ dvi, double* gvi) {
   const int64_t stride = int64_t(gridDim.x) * blockDim.x;
   for (int64_t p = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; p < nnz + n; p += stride) {
     if (p < nnz) {
       gv[p] = dv[home[p]];
+      if (dvi) gvi[p] = dvi[home[p]];
     } else {
       const double2 v = db[row[p - nnz]];
       br[p - nnz] = v.x;
@@ -1842,9 +1881,10 @@ extern "C" __global__ void __launch_bounds__(256) qwk_gather_grad(const double* 
 // Gradient through the initial T~ (one lane per row): psi_0 holds b_j phi_j
 // in the group of j, so dL/dv_{jl} += 2 Re[b_j (conj(nu_0) f' + conj(nu_1) g')]
 // / sqrt(s) with nu the group amplitudes of lambda_0, and
-// dL/db_j = 2 <psi~_j|lambda_0>.
+// dL/db_j = 2 <psi~_j|lambda_0>.  Complex values (Matrix::vim): the same
+// with the derivatives by the real and the imaginary part, into dv and dvi.
 extern "C" __global__ void __launch_bounds__(256) qwk_grad_init(Matrix m, Slots lam, const double2* b, double* dv,
-                                                                double2* db) {
+                                                                double2* db, double* dvi) {
   const int64_t stride = int64_t(gridDim.x) * blockDim.x;
   for (int64_t it = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; it < m.rows; it += stride) {
     const Row x = row_item(m, it);
@@ -1854,10 +1894,17 @@ extern "C" __global__ void __launch_bounds__(256) qwk_grad_init(Matrix m, Slots 
       const int64_t h = home(x.I, x.j, l);
       const double2 n0 = lam.R0[h], n1 = r1_of(lam, h);
       const SlotRec rc = m.rec[h];
-      const Rot d = rotation_deriv(rc.val, x.j, rc.col);
-      const double2 u = cmul(bj, cadd(cjmul(n0, d.f), make_double2(n1.x * d.g, -n1.y * d.g)));
-      dv[h] += 2.0 * u.x * x.I.inv_sqrt_s;
-      c = cadd(c, along(rotation(rc.val, x.j, rc.col), n0, n1));
+      const double vi = m.vim ? m.vim[h] : 0.0;
+      const auto du = [&](const Rot& d) {
+        return cmul(bj, cadd(cjmul(n0, d.f), make_double2(n1.x * d.g, -n1.y * d.g)));
+      };
+      if (m.vim) {
+        dv[h] += 2.0 * du(rotation_deriv_c(rc.val, vi, x.j, rc.col, false)).x * x.I.inv_sqrt_s;
+        dvi[h] += 2.0 * du(rotation_deriv_c(rc.val, vi, x.j, rc.col, true)).x * x.I.inv_sqrt_s;
+      } else {
+        dv[h] += 2.0 * du(rotation_deriv(rc.val, x.j, rc.col)).x * x.I.inv_sqrt_s;
+      }
+      c = cadd(c, along(rotation(rc.val, vi, x.j, rc.col), n0, n1));
     }
     db[it] = cscale(c, 2.0 * x.I.inv_sqrt_s);
   }

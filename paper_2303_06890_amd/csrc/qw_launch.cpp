@@ -349,7 +349,8 @@ hipError_t launch_step(const StepArgs& a, int grid, int block, hipStream_t strea
 
 hipError_t launch_adjoint(const AdjArgs& a, int grid, int block, hipStream_t stream) {
   if (block < kWave || block > kMaxBlock || block % kWave) return hipErrorInvalidValue;
-  if (a.m.vim || a.m.angles) return hipErrorInvalidValue;  // the gradient sweep is for real FP64 matrices
+  // FP64 values only; complex values (vim) on the complex-plane kernels, with dvi
+  if (a.m.angles || (a.m.vim != nullptr) != (a.dvi != nullptr) || (a.m.vim && a.real)) return hipErrorInvalidValue;
   AdjArgs c = a;
   c.wpb = block / kWave;
   c.m.xcd = xcd_blocks(a.m, grid);
@@ -516,16 +517,18 @@ hipError_t launch_grad_init_real(const Matrix& m, Slots lam, const double2* b, d
 
 hipError_t launch_gather_grad(const double* dv, const int32_t* home, int64_t nnz, const double2* db,
                               const int32_t* row, int64_t n, double* gv, double* br, double* bi,
-                              hipStream_t stream) {
-  void* p[] = {&dv, &home, &nnz, &db, &row, &n, &gv, &br, &bi};
+                              const double* dvi, double* gvi, hipStream_t stream) {
+  if ((dvi == nullptr) != (gvi == nullptr)) return hipErrorInvalidValue;
+  void* p[] = {&dv, &home, &nnz, &db, &row, &n, &gv, &br, &bi, &dvi, &gvi};
   return launch(F_GATHER_GRAD, clamp_grid(nnz + n, 4096), 256, stream, p);
 }
 
-hipError_t launch_grad_init(const Matrix& m, Slots lam, const double2* b, double* dv, double2* db,
+hipError_t launch_grad_init(const Matrix& m, Slots lam, const double2* b, double* dv, double2* db, double* dvi,
                             hipStream_t stream) {
+  if (m.angles || (m.vim != nullptr) != (dvi != nullptr)) return hipErrorInvalidValue;
   Matrix mm = m;
   const double2* bb = b;
-  void* p[] = {&mm, &lam, &bb, &dv, &db};
+  void* p[] = {&mm, &lam, &bb, &dv, &db, &dvi};
   return launch(F_GRAD_INIT, clamp_grid(m.rows, 4096), 256, stream, p);
 }
 
