@@ -493,12 +493,21 @@ def adjoint_leg(Q, W, steps: int = 20, reps: int = 5):
     """Gradient of the total probability of 32 column outcomes after 20 steps
     w.r.t. all stored values and b (forward walk + reverse sweep with
     recomputation), against the forward walk alone: on G(1024, 8) (8192
-    values) and on the benchmark's G(16384, 8) (131072 values)."""
+    values) and on the benchmark's G(16384, 8) (131072 values), and on the
+    complex Hermitian offset matrices of the same sizes (the real and the
+    imaginary part of every value)."""
     import numpy as np
 
     out = {}
+    cases = []
     for n in (1024, 16384):
         a, b, w = W.adjoint_problem(n)
+        cases.append((f"G({n}, 8)", f"G({n}, 8)", a, b, w))
+    for n in (1024, 16384):
+        _, b, w = W.adjoint_problem(n)
+        cases.append((f"complex Hermitian {n}x8", f"complex Hermitian offset matrix n = {n}, 8 entries/column, seed 4",
+                      W.hermitian_offset_matrix(n, 8, seed=4), b, w))
+    for label, what, a, b, w in cases:
         sc = 1.0 / np.abs(a.vals).max()
         a = W.Csc(a.n, a.colptr, a.rowidx, a.vals * sc)
         walk = Q.Walk(a, scale=1.0)
@@ -520,8 +529,8 @@ def adjoint_leg(Q, W, steps: int = 20, reps: int = 5):
         st.step(steps)
         s1 = st.stats()
         upd = s1["total_written"] - s0["total_written"]
-        out[f"G({n}, 8)"] = {
-            "workload": f"G({n}, 8), uniform b, {steps} steps, loss over 32 outcomes, {a.nnz} values",
+        out[label] = {
+            "workload": f"{what}, uniform b, {steps} steps, loss over 32 outcomes, {a.nnz} values",
             "forward_ms": t_fwd,
             "forward_plus_gradient_ms": t_grad,
             "gradient_over_forward": t_grad / t_fwd,

@@ -152,3 +152,27 @@ def test_entry_points_refuse_the_other_kind(Q):
         assert rc == -5, (fn, rc)  # QW_ENOTSUP
         assert b"takes" in lib.qw_last_error()
         st.close()
+
+
+def test_complex_grad_batched_mixed_s(Q, oracle_mod):
+    """Two complex Hermitian instances of different s in one context: each
+    instance's part of the gradient equals the oracle's for that matrix alone."""
+    mats = [_scaled(W.hermitian_offset_matrix(128, 6, seed=109)), _scaled(W.hermitian_offset_matrix(64, 11, seed=110))]
+    bs = [W.uniform_b(128) * 1j, W.gaussian_b(64, seed=111) * (0.6 + 0.8j)]
+    bs[1] = bs[1] / np.linalg.norm(bs[1])
+    ws = [np.zeros(128), np.zeros(64)]
+    ws[0][::5] = 1.0
+    ws[1][1::3] = 1.0
+    nsteps = 7
+    walk = Q.Walk(mats, scale=1.0, symmetric=False)
+    assert len({d["s"] for d in walk.info}) == 2
+    st = walk.state(bs).step(nsteps)
+    gl, gg, gdb = st.grad(np.concatenate(ws), nsteps)
+    off, boff, total = 0, 0, 0.0
+    for csc, b, w, d in zip(mats, bs, ws, walk.info):
+        ol, og, odb = _oracle_csc_grad(oracle_mod, csc, b, w, nsteps)
+        total += ol
+        _check(csc, d["s"], nsteps, gg[off:off + csc.nnz], og, gdb[boff:boff + csc.n], odb, f"n={csc.n}")
+        off += csc.nnz
+        boff += csc.n
+    assert gl == pytest.approx(total, rel=1e-12)
