@@ -1823,6 +1823,9 @@ extern "C" __global__ void __launch_bounds__(256) qwk_weight_real(Matrix m, Slot
   if (threadIdx.x == 0) partial[blockIdx.x] = t;
 }
 
+// Slots of a row that the seed kernels load together.
+constexpr int kInitChunk = 8;
+
 // qwk_grad_init on the 8-byte planes (a real b): with n the cells of lambda_0
 // (imaginary R0 cells of slots of negative value held as their coefficient
 // of i), dL/dv += 2 b_j (n0 f_d' + n1 g_d) / sqrt(s) and
@@ -1837,20 +1840,39 @@ extern "C" __global__ void __launch_bounds__(256) qwk_grad_init_real(Matrix m, S
     const Row x = row_item(m, it);
     const double bj = b[it].x;
     double c = 0.0;
-    for (int l = 0; l < x.I.s; ++l) {
-      const int64_t h = home(x.I, x.j, l);
-      const double n0 = N0[h], n1 = N1[h] * lam.r1s;
-      const SlotRec rc = m.rec[h];
-      const double a = rc.val;
-      const bool upper = x.j <= rc.col;
-      const double q = sqrt(fabs(a));
-      const double f = a < 0.0 && !upper ? -q : q;
-      const double g = sqrt(1.0 - fabs(a));
-      const double fq = 0.5 / q;
-      const double fd = a > 0.0 ? fq : (a < 0.0 ? (upper ? -fq : fq) : __builtin_inf());
-      const double gd = (a > 0.0 ? -0.5 : (a < 0.0 ? 0.5 : 0.0)) / g;
-      dv[h] += 2.0 * bj * (n0 * fd + n1 * gd) * x.I.inv_sqrt_s;
-      c += f * n0 + g * n1;
+    // eight slots at a time: every load of the chunk (dL/dv's old values
+    // included) is issued before the first store, one round trip per chunk
+    for (int l0 = 0; l0 < x.I.s; l0 += kInitChunk) {
+      int64_t h[kInitChunk];
+      double n0[kInitChunk], n1[kInitChunk], av[kInitChunk], dvo[kInitChunk];
+      int col[kInitChunk];
+#pragma unroll
+      for (int i = 0; i < kInitChunk; ++i) {
+        if (l0 + i < x.I.s) {
+          h[i] = home(x.I, x.j, l0 + i);
+          n0[i] = N0[h[i]];
+          n1[i] = N1[h[i]] * lam.r1s;
+          const SlotRec rc = m.rec[h[i]];
+          av[i] = rc.val;
+          col[i] = rc.col;
+          dvo[i] = dv[h[i]];
+        }
+      }
+#pragma unroll
+      for (int i = 0; i < kInitChunk; ++i) {
+        if (l0 + i < x.I.s) {
+          const double a = av[i];
+          const bool upper = x.j <= col[i];
+          const double q = sqrt(fabs(a));
+          const double f = a < 0.0 && !upper ? -q : q;
+          const double g = sqrt(1.0 - fabs(a));
+          const double fq = 0.5 / q;
+          const double fd = a > 0.0 ? fq : (a < 0.0 ? (upper ? -fq : fq) : __builtin_inf());
+          const double gd = (a > 0.0 ? -0.5 : (a < 0.0 ? 0.5 : 0.0)) / g;
+          dv[h[i]] = dvo[i] + 2.0 * bj * (n0[i] * fd + n1[i] * gd) * x.I.inv_sqrt_s;
+          c += f * n0[i] + g * n1[i];
+        }
+      }
     }
     db[it] = make_double2(2.0 * c * x.I.inv_sqrt_s, 0.0);
   }
@@ -1890,21 +1912,42 @@ extern "C" __global__ void __launch_bounds__(256) qwk_grad_init(Matrix m, Slots 
     const Row x = row_item(m, it);
     const double2 bj = b[it];
     double2 c = zero2();
-    for (int l = 0; l < x.I.s; ++l) {
-      const int64_t h = home(x.I, x.j, l);
-      const double2 n0 = lam.R0[h], n1 = r1_of(lam, h);
-      const SlotRec rc = m.rec[h];
-      const double vi = m.vim ? m.vim[h] : 0.0;
-      const auto du = [&](const Rot& d) {
-        return cmul(bj, cadd(cjmul(n0, d.f), make_double2(n1.x * d.g, -n1.y * d.g)));
-      };
-      if (m.vim) {
-        dv[h] += 2.0 * du(rotation_deriv_c(rc.val, vi, x.j, rc.col, false)).x * x.I.inv_sqrt_s;
-        dvi[h] += 2.0 * du(rotation_deriv_c(rc.val, vi, x.j, rc.col, true)).x * x.I.inv_sqrt_s;
-      } else {
-        dv[h] += 2.0 * du(rotation_deriv(rc.val, x.j, rc.col)).x * x.I.inv_sqrt_s;
+    // eight slots at a time, every load of the chunk before the first store
+    // (as in qwk_grad_init_real)
+    for (int l0 = 0; l0 < x.I.s; l0 += kInitChunk) {
+      int64_t h[kInitChunk];
+      double2 n0[kInitChunk], n1[kInitChunk];
+      double av[kInitChunk], vi[kInitChunk], dvo[kInitChunk], dvio[kInitChunk];
+      int col[kInitChunk];
+#pragma unroll
+      for (int i = 0; i < kInitChunk; ++i) {
+        if (l0 + i < x.I.s) {
+          h[i] = home(x.I, x.j, l0 + i);
+          n0[i] = lam.R0[h[i]];
+          n1[i] = r1_of(lam, h[i]);
+          const SlotRec rc = m.rec[h[i]];
+          av[i] = rc.val;
+          col[i] = rc.col;
+          vi[i] = m.vim ? m.vim[h[i]] : 0.0;
+          dvo[i] = dv[h[i]];
+          dvio[i] = m.vim ? dvi[h[i]] : 0.0;
+        }
       }
-      c = cadd(c, along(rotation(rc.val, vi, x.j, rc.col), n0, n1));
+#pragma unroll
+      for (int i = 0; i < kInitChunk; ++i) {
+        if (l0 + i < x.I.s) {
+          const auto du = [&](const Rot& d) {
+            return cmul(bj, cadd(cjmul(n0[i], d.f), make_double2(n1[i].x * d.g, -n1[i].y * d.g)));
+          };
+          if (m.vim) {
+            dv[h[i]] = dvo[i] + 2.0 * du(rotation_deriv_c(av[i], vi[i], x.j, col[i], false)).x * x.I.inv_sqrt_s;
+            dvi[h[i]] = dvio[i] + 2.0 * du(rotation_deriv_c(av[i], vi[i], x.j, col[i], true)).x * x.I.inv_sqrt_s;
+          } else {
+            dv[h[i]] = dvo[i] + 2.0 * du(rotation_deriv(av[i], x.j, col[i])).x * x.I.inv_sqrt_s;
+          }
+          c = cadd(c, along(rotation(av[i], vi[i], x.j, col[i]), n0[i], n1[i]));
+        }
+      }
     }
     db[it] = cscale(c, 2.0 * x.I.inv_sqrt_s);
   }

@@ -512,7 +512,8 @@ hipError_t launch_grad_init_real(const Matrix& m, Slots lam, const double2* b, d
   Matrix mm = m;
   const double2* bb = b;
   void* p[] = {&mm, &lam, &bb, &dv, &db};
-  return launch(F_GRAD_INIT_REAL, clamp_grid(m.rows, 4096), 256, stream, p);
+  // one lane per row: 64-lane workgroups spread the rows over more CUs
+  return launch(F_GRAD_INIT_REAL, clamp_grid(4 * m.rows, 16384), 64, stream, p);
 }
 
 hipError_t launch_gather_grad(const double* dv, const int32_t* home, int64_t nnz, const double2* db,
@@ -529,7 +530,7 @@ hipError_t launch_grad_init(const Matrix& m, Slots lam, const double2* b, double
   Matrix mm = m;
   const double2* bb = b;
   void* p[] = {&mm, &lam, &bb, &dv, &db, &dvi};
-  return launch(F_GRAD_INIT, clamp_grid(m.rows, 4096), 256, stream, p);
+  return launch(F_GRAD_INIT, clamp_grid(4 * m.rows, 16384), 64, stream, p);  // as launch_grad_init_real
 }
 
 }  // namespace qw
