@@ -168,6 +168,29 @@ __device__ __forceinline__ Rot rotation_deriv_c(double a, double b, int j, int k
   d.g = -0.5 * (im ? b : a) / (m * r.g);
   return d;
 }
+// The rotation of a + i b and its derivatives by a and by b together
+// (rot_cplx, rotation_deriv_c): off the axis one hypot, the two square roots
+// of the rotation and two reciprocals (1/|v|, 1/g) serve all three, which
+// the reverse step needs for every slot.
+__device__ __forceinline__ void rot_and_derivs(double a, double b, int j, int k, Rot& r, Rot& da, Rot& db) {
+  if (b == 0.0) {
+    r = rot_real(a, j <= k);
+    da = rotation_deriv(a, j, k);
+    db = rotation_deriv_c(a, 0.0, j, k, true);
+    return;
+  }
+  const double m = hypot(a, b);
+  const double t = sqrt(0.5 * (m + fabs(a)));  // > 0 since b != 0
+  r.f = a >= 0.0 ? make_double2(t, 0.5 * b / t) : make_double2(0.5 * fabs(b) / t, copysign(t, b));
+  r.g = sqrt(1.0 - m);
+  const double im = 1.0 / m;
+  const double2 h = make_double2(0.5 * r.f.x * im, -0.5 * r.f.y * im);  // 1/(2f) = conj(f) / (2|v|)
+  const double kg = -0.5 * im / r.g;
+  da.f = h;
+  da.g = a * kg;
+  db.f = make_double2(-h.y, h.x);
+  db.g = b * kg;
+}
 // conj(f) x0 + g x1: the component of an amplitude pair along sqrt(s) phi
 __device__ __forceinline__ double2 along(const Rot& r, double2 x0, double2 x1) {
   return cadd(cjmul(r.f, x0), cscale(x1, r.g));
@@ -1080,15 +1103,18 @@ __device__ __forceinline__ void adjoint_wave(const AdjArgs& a, int64_t w, int la
       m1[i] = r1_of(a.lin, h[i]);
     }
   }
-  // complex values: the imaginary parts by home (one uniform test per wavefront)
+  // complex values: the imaginary parts by home (one uniform test per
+  // wavefront); the derivatives come with the rotation
   const double* vim = a.m.vim;
-  double vi[SLM];
+  Rot dra[SLM], drb[SLM];
   double2 c = zero2(), d = zero2();
 #pragma unroll
   for (int i = 0; i < SLM; ++i) {
     if (i < sl) {
-      vi[i] = vim ? vim[h[i]] : 0.0;
-      r[i] = rotation(rc[i].val, vi[i], x.j, rc[i].col);
+      if (vim)
+        rot_and_derivs(rc[i].val, vim[h[i]], x.j, rc[i].col, r[i], dra[i], drb[i]);
+      else
+        r[i] = rotation(rc[i].val, x.j, rc[i].col);
       c = cadd(c, along(r[i], x0[i], x1[i]));
       d = cadd(d, along(r[i], m0[i], m1[i]));
     }
@@ -1112,8 +1138,8 @@ __device__ __forceinline__ void adjoint_wave(const AdjArgs& a, int64_t w, int la
                     cjmul(d, cadd(cjmul(dr.f, q0), cscale(q1, dr.g))));
       };
       if (vim) {
-        a.dv[h[i]] += 2.0 * t * du(rotation_deriv_c(rc[i].val, vi[i], x.j, rc[i].col, false)).x;
-        a.dvi[h[i]] += 2.0 * t * du(rotation_deriv_c(rc[i].val, vi[i], x.j, rc[i].col, true)).x;
+        a.dv[h[i]] += 2.0 * t * du(dra[i]).x;
+        a.dvi[h[i]] += 2.0 * t * du(drb[i]).x;
       } else {
         a.dv[h[i]] += 2.0 * t * du(rotation_deriv(rc[i].val, x.j, rc[i].col)).x;
       }
@@ -1939,13 +1965,17 @@ extern "C" __global__ void __launch_bounds__(256) qwk_grad_init(Matrix m, Slots 
           const auto du = [&](const Rot& d) {
             return cmul(bj, cadd(cjmul(n0[i], d.f), make_double2(n1[i].x * d.g, -n1[i].y * d.g)));
           };
+          Rot r;
           if (m.vim) {
-            dv[h[i]] = dvo[i] + 2.0 * du(rotation_deriv_c(av[i], vi[i], x.j, col[i], false)).x * x.I.inv_sqrt_s;
-            dvi[h[i]] = dvio[i] + 2.0 * du(rotation_deriv_c(av[i], vi[i], x.j, col[i], true)).x * x.I.inv_sqrt_s;
+            Rot da, db2;
+            rot_and_derivs(av[i], vi[i], x.j, col[i], r, da, db2);
+            dv[h[i]] = dvo[i] + 2.0 * du(da).x * x.I.inv_sqrt_s;
+            dvi[h[i]] = dvio[i] + 2.0 * du(db2).x * x.I.inv_sqrt_s;
           } else {
+            r = rotation(av[i], x.j, col[i]);
             dv[h[i]] = dvo[i] + 2.0 * du(rotation_deriv(av[i], x.j, col[i])).x * x.I.inv_sqrt_s;
           }
-          c = cadd(c, along(rotation(av[i], vi[i], x.j, col[i]), n0[i], n1[i]));
+          c = cadd(c, along(r, n0[i], n1[i]));
         }
       }
     }
