@@ -184,3 +184,61 @@ def test_xcd_rows_change_nothing_in_the_solver(Q):
     xcd = Q.Walk(A, xcd=True).qls(b, eps=1e-2)
     np.testing.assert_array_equal(plain[0], xcd[0])
     assert plain[1:] == xcd[1:]
+
+
+@pytest.mark.parametrize("word", [0, 32])
+def test_split_rows_for_s64(Q, oracle_mod, word):
+    """s = 64, eight lanes per row: in workgroups of an even number of
+    wavefronts the real step kernels split each row's 64 slots over a pair of
+    wavefronts (their row sums joined through LDS); in 64-lane workgroups one
+    wavefront keeps 8 whole rows.  Both against the oracle (single launches,
+    then graphs), FP64 values and 32-bit fixed-point words; the split form
+    with and without the XCD numbering of row blocks bit for bit; the solver's
+    fused projection through the split _acc forms."""
+    n = 1024
+    csc = W.band_matrix(n, 31, seed=61) if word == 0 else W.fixed_point_band(n, 31, word, seed=61)
+    b = W.gaussian_b(n, seed=62)
+    b = b / np.linalg.norm(b)
+    om = oracle_mod.OracleMatrix(csc, word=word)
+    ost = oracle_mod.OracleState(om).set_b(b).T()
+    snaps = {}
+    done = 0
+    for t in (3, 40):
+        ost.step(t - done)
+        done = t
+        snaps[t] = ost.export()
+        assert ost.ambiguous() == 0
+    waves = n // 8
+    results = {}
+    for shape, xcd in (((256, waves // 4), False), ((128, waves // 2), False), ((64, waves), False),
+                       ((256, waves // 4), True)):
+        walk = Q.Walk(csc, word=word, lanes=8, xcd=xcd)
+        assert walk.info[0]["s"] == 64
+        st = walk.state(b)
+        st.set_launch(*shape)
+        assert st.stats()["real_amplitudes"]
+        done = 0
+        for t in (3, 40):
+            st.step(t - done)  # 3 single launches, then a graph of 37
+            done = t
+            gk, ga = st.export()
+            ok, oa = snaps[t]
+            compare_states(gk, ga, ok, oa, where=f"word={word} shape={shape} xcd={xcd} step {t}")
+        results[(shape, xcd)] = st.export()
+        walk.close()
+    split, split_x = results[((256, waves // 4), False)], results[((256, waves // 4), True)]
+    np.testing.assert_array_equal(split[0], split_x[0])
+    np.testing.assert_array_equal(split[1], split_x[1])
+    # the pair's two wavefronts in workgroups of 2 or 4: the same arithmetic
+    other = results[((128, waves // 2), False)]
+    np.testing.assert_array_equal(split[0], other[0])
+    np.testing.assert_array_equal(split[1], other[1])
+    if word == 0:
+        # a well-conditioned band (kappa of A/s about 330: some 9400 walk steps)
+        A = W.from_dense(W.band_matrix(256, 31, seed=63).dense() + 40.0 * np.eye(256))
+        walk = Q.Walk(A)
+        assert walk.info[0]["s"] == 64
+        x0 = walk.qls(W.uniform_b(256), eps=1e-2)
+        y = np.linalg.solve(A.dense(), W.uniform_b(256))
+        fid = abs(np.vdot(y / np.linalg.norm(y), x0[0])) ** 2
+        assert fid > 1 - 1e-3, fid
