@@ -770,48 +770,65 @@ __device__ __forceinline__ double prune_r(double v, double tau, unsigned& cnt) {
   return 0.0;
 }
 
-// Rows split over two wavefronts (s = 64, the real step kernels of one s
-// with eight lanes per row, in workgroups of an even number of wavefronts).
-// With eight lanes per row a wavefront covers 8 rows, so each of its loads
-// and stores touches 64-byte runs of the slot-position-major planes, half a
-// 128-byte line.  Here the two wavefronts 2p and 2p + 1 of an instance share
-// rows 16p .. 16p + 15: wavefront 2p + q takes slot positions 32q .. 32q + 31,
-// lane = g * 16 + jj holds positions 32q + 8g + i (i < 8) of row 16p + jj, so
-// every access covers 128-byte runs, with as many wavefronts as before (the
-// paper's shape E, 16384 rows: 9.4 -> 8.x us per step).  The row sum: the
-// four lanes of a row in the wavefront (lane ^ 16, lane ^ 32), then the two
-// halves through LDS, added in one order by both wavefronts.  Both members of
-// a pair lie in one workgroup (even wavefronts per workgroup, instances of
-// N / 8 wavefronts each) and are either both inside the slots or both past
-// them, so both reach the barrier or neither does.
-__device__ __forceinline__ Lanes lanes_split64(const Matrix& m, int64_t w, int lane) {
+// Rows split over K wavefronts (the real step kernels of one s >= kSplitMinS,
+// in workgroups of a multiple of K wavefronts; K = 2 with eight lanes per
+// row, K = 4 with sixteen).  With eight lanes per row a wavefront covers 8 rows
+// (four with sixteen), so each of its loads and stores touches 64-byte
+// (32-byte) runs of the slot-position-major planes, part of a 128-byte line.
+// Here wavefronts Kp .. Kp + K - 1 of an instance share rows 16p .. 16p + 15:
+// wavefront Kp + q takes slot positions q s/K .. (q + 1) s/K - 1, lane
+// g * 16 + jj holds positions q s/K + g sl + i (i < sl, the same slots per
+// lane as the whole-row mapping) of row 16p + jj, so every access covers
+// 128-byte runs with as many wavefronts as before (the paper's shape E,
+// 16384 rows with s = 64: 9.35 -> 8.92 us per step with eight lanes per row,
+// 8.3 us with sixteen, which whole rows had made the slower tile at 11.7 us).  The row sum: the four
+// lanes of a row in the wavefront (lane ^ 16, lane ^ 32), then the K parts
+// through LDS, added in one order by every wavefront of the group.  A group
+// lies in one workgroup (wavefronts per workgroup a multiple of K, instances
+// of N K / 16 wavefronts each, N >= s >= 16) and is either inside the slots
+// or past them as a whole, so all of its wavefronts reach the barrier or
+// none does.
+// The smallest s with the split mapping.  For s = 16 and 32 the same split
+// left shape D unchanged (3.23-3.25 us per step) and made shape C's
+// 64-thread whole-row launches 5 % slower (2.11 -> 2.22 us, A/B on one box:
+// the kernel holding both mappings), so those kernels keep whole rows only.
+constexpr int kSplitMinS = 64;
+template <int S, int K>
+__device__ __forceinline__ Lanes lanes_split(const Matrix& m, int64_t w, int lane) {
   Lanes x;
   x.inst = m.ninst == 1 ? 0 : uload(m.wave_inst + w);
   x.I = inst_uniform(m, x.inst);
   const int64_t lw = w - x.I.wave_base;
   x.rpw_log = 4;  // 16 rows of the wavefront in the low lane bits
-  x.h = int((lw & 1) << 2) + (lane >> 4);
-  x.j = int(((lw >> 1) << 4) + (lane & 15));
+  x.h = int((lw % K) << 2) + (lane >> 4);
+  x.j = int(((lw / K) << 4) + (lane & 15));
   x.live = true;
   return x;
 }
-__device__ __forceinline__ double join_halves(double c, int lane) {
+template <int K>
+__device__ __forceinline__ double join_parts(double c, int lane) {
   __shared__ double part[kMaxBlock / kWave][16];
   const int wib = int(threadIdx.x) >> 6;
   if (lane < 16) part[wib][lane] = c;
   __syncthreads();
-  return part[wib & ~1][lane & 15] + part[wib | 1][lane & 15];
+  const int first = wib & ~(K - 1);
+  double t = part[first][lane & 15];
+#pragma unroll
+  for (int q = 1; q < K; ++q) t += part[first + q][lane & 15];
+  return t;
 }
 
 // S: s of every instance, or 0 (read per instance, slots per lane <= SLM;
 // slots of value 0 are skipped as in step_wave when StepArgs::zskip is set).
 // EQ0: when Q0 of a slot without a partner is read (see below); both forms
 // are correct for every matrix, the launcher takes the faster one.
-// SPLIT: rows split over two wavefronts (lanes_split64; S = 64, W = 0).
-template <bool ACC, int SLM, int S, int ENC, int W = 0, bool EQ0 = false, bool SPLIT = false>
+// K > 1: rows split over K wavefronts (lanes_split; S >= kSplitMinS, K = 2
+// for W = 0, 4 for W = 1).
+template <bool ACC, int SLM, int S, int ENC, int W = 0, bool EQ0 = false, int K = 1>
 __device__ __forceinline__ unsigned step_wave_real(const StepArgs& a, int64_t w, int lane, double coef) {
-  static_assert(!SPLIT || (S == 64 && W == 0 && SLM == 8), "the split mapping is for s = 64, eight slots per lane");
-  const Lanes x = SPLIT ? lanes_split64(a.m, w, lane) : lanes_of<S, true, W>(a.m, w, lane);
+  static_assert(K == 1 || (S >= 16 && K == (W ? 4 : 2) && S / (4 * K) == Shape<S, W>::sl),
+                "the split mapping keeps the slots per lane of the whole-row mapping");
+  const Lanes x = K > 1 ? lanes_split<S, K>(a.m, w, lane) : lanes_of<S, true, W>(a.m, w, lane);
   const int sl = S ? Shape<S, W>::sl : (SLM == 1 ? 1 : x.I.sl);
   const int64_t base = x.I.item_base;
   const double* R0 = reinterpret_cast<const double*>(a.in.R0);
@@ -923,7 +940,7 @@ __device__ __forceinline__ unsigned step_wave_real(const StepArgs& a, int64_t w,
     }
   }
   c = row_sum_r<SLM>(c, x.rpw_log);
-  if constexpr (SPLIT) c = join_halves(c, lane);
+  if constexpr (K > 1) c = join_parts<K>(c, lane);
   if (ACC && x.h == 0) *yp = yv + coef * (c * x.I.inv_sqrt_s);  // the group sum is real: only Re y_j moves
   const double tc = c * two_over_s<S>(x.I);
   unsigned cnt = 0;
@@ -948,17 +965,17 @@ __device__ __forceinline__ unsigned step_wave_real(const StepArgs& a, int64_t w,
 }
 
 // One wavefront's step and its branch count.
-template <bool ACC, int SLM, int S, int ENC, int W, bool EQ0, bool SPLIT>
+template <bool ACC, int SLM, int S, int ENC, int W, bool EQ0, int K>
 __device__ __forceinline__ void step_counted(const StepArgs& a, int64_t w, int lane, int64_t wpb) {
   const double coef = ACC ? *a.coef : 0.0;
   const int64_t cidx = wave_counter(wpb);
   if (a.acc == nullptr) {  // the solver's private walk keeps no counts
-    (void)step_wave_real<ACC, SLM, S, ENC, W, EQ0, SPLIT>(a, w, lane, coef);
+    (void)step_wave_real<ACC, SLM, S, ENC, W, EQ0, K>(a, w, lane, coef);
     return;
   }
   const unsigned long long prev = a.acc[cidx];
   const unsigned long long v =
-      wave_sum_bits<CountBits<SLM>::value>(step_wave_real<ACC, SLM, S, ENC, W, EQ0, SPLIT>(a, w, lane, coef));
+      wave_sum_bits<CountBits<SLM>::value>(step_wave_real<ACC, SLM, S, ENC, W, EQ0, K>(a, w, lane, coef));
   if (lane == 0) a.acc[cidx] = prev + v;
 }
 
@@ -981,13 +998,14 @@ __device__ __forceinline__ void step_body_real(const StepArgs& a) {
   asm volatile("" ::"s"(a.m.ninst), "s"(a.m.inst0.wave_base), "s"(a.m.inst0.s), "s"(a.m.inst0.N), "s"(a.in.Q0),
                "s"(a.out.Q0), "s"(a.m.inst0.inv_sqrt_s), "s"(a.m.inst0.jbase), "s"(a.m.inst), "s"(a.m.wave_inst));
   if (w >= a.m.waves) return;  // no list: nothing to do past the slots
-  if constexpr (S == 64 && W == 0) {
-    if ((wpb & 1) == 0) {  // pairs of wavefronts in each workgroup: rows split over the pair
-      step_counted<ACC, SLM, S, ENC, W, EQ0, true>(a, w, lane, wpb);
+  if constexpr (S >= kSplitMinS) {
+    constexpr int K = W ? 4 : 2;
+    if (wpb % K == 0) {  // groups of K wavefronts in each workgroup: rows split over the group
+      step_counted<ACC, SLM, S, ENC, W, EQ0, K>(a, w, lane, wpb);
       return;
     }
   }
-  step_counted<ACC, SLM, S, ENC, W, EQ0, false>(a, w, lane, wpb);
+  step_counted<ACC, SLM, S, ENC, W, EQ0, 1>(a, w, lane, wpb);
 }
 
 // Plane conversions for the switch between the two representations.  With

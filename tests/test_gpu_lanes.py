@@ -186,33 +186,46 @@ def test_xcd_rows_change_nothing_in_the_solver(Q):
     assert plain[1:] == xcd[1:]
 
 
+_SPLIT_CASES = {}
+
+
+def _split_case(oracle_mod, word):
+    """The band of half-width 31 at n = 1024 (s = 64) and the oracle's states
+    after 3 and 40 steps, computed once per word length."""
+    if word not in _SPLIT_CASES:
+        n = 1024
+        csc = W.band_matrix(n, 31, seed=61) if word == 0 else W.fixed_point_band(n, 31, word, seed=61)
+        b = W.gaussian_b(n, seed=62)
+        b = b / np.linalg.norm(b)
+        ost = oracle_mod.OracleState(oracle_mod.OracleMatrix(csc, word=word)).set_b(b).T()
+        snaps = {}
+        done = 0
+        for t in (3, 40):
+            ost.step(t - done)
+            done = t
+            snaps[t] = ost.export()
+            assert ost.ambiguous() == 0
+        _SPLIT_CASES[word] = (csc, b, snaps)
+    return _SPLIT_CASES[word]
+
+
+@pytest.mark.parametrize("lanes", [8, 16])
 @pytest.mark.parametrize("word", [0, 32])
-def test_split_rows_for_s64(Q, oracle_mod, word):
-    """s = 64, eight lanes per row: in workgroups of an even number of
-    wavefronts the real step kernels split each row's 64 slots over a pair of
-    wavefronts (their row sums joined through LDS); in 64-lane workgroups one
-    wavefront keeps 8 whole rows.  Both against the oracle (single launches,
-    then graphs), FP64 values and 32-bit fixed-point words; the split form
-    with and without the XCD numbering of row blocks bit for bit; the solver's
-    fused projection through the split _acc forms."""
+def test_split_rows_for_s64(Q, oracle_mod, word, lanes):
+    """s = 64: in workgroups of a multiple of K wavefronts the real step
+    kernels split each row's 64 slots over K wavefronts (K = 2 with eight
+    lanes per row, 4 with sixteen; their row sums joined through LDS); in
+    other workgroups a wavefront keeps whole rows.  Both against the oracle
+    (single launches, then graphs), FP64 values and 32-bit fixed-point words;
+    the split form with and without the XCD numbering of row blocks bit for
+    bit; the solver's fused projection through the split _acc forms."""
     n = 1024
-    csc = W.band_matrix(n, 31, seed=61) if word == 0 else W.fixed_point_band(n, 31, word, seed=61)
-    b = W.gaussian_b(n, seed=62)
-    b = b / np.linalg.norm(b)
-    om = oracle_mod.OracleMatrix(csc, word=word)
-    ost = oracle_mod.OracleState(om).set_b(b).T()
-    snaps = {}
-    done = 0
-    for t in (3, 40):
-        ost.step(t - done)
-        done = t
-        snaps[t] = ost.export()
-        assert ost.ambiguous() == 0
-    waves = n // 8
+    csc, b, snaps = _split_case(oracle_mod, word)
+    waves = n // 8 if lanes == 8 else n // 4
     results = {}
     for shape, xcd in (((256, waves // 4), False), ((128, waves // 2), False), ((64, waves), False),
                        ((256, waves // 4), True)):
-        walk = Q.Walk(csc, word=word, lanes=8, xcd=xcd)
+        walk = Q.Walk(csc, word=word, lanes=lanes, xcd=xcd)
         assert walk.info[0]["s"] == 64
         st = walk.state(b)
         st.set_launch(*shape)
@@ -229,11 +242,11 @@ def test_split_rows_for_s64(Q, oracle_mod, word):
     split, split_x = results[((256, waves // 4), False)], results[((256, waves // 4), True)]
     np.testing.assert_array_equal(split[0], split_x[0])
     np.testing.assert_array_equal(split[1], split_x[1])
-    # the pair's two wavefronts in workgroups of 2 or 4: the same arithmetic
-    other = results[((128, waves // 2), False)]
-    np.testing.assert_array_equal(split[0], other[0])
-    np.testing.assert_array_equal(split[1], other[1])
-    if word == 0:
+    if lanes == 8:  # the pair's two wavefronts in workgroups of 2 or 4: the same arithmetic
+        other = results[((128, waves // 2), False)]
+        np.testing.assert_array_equal(split[0], other[0])
+        np.testing.assert_array_equal(split[1], other[1])
+    if word == 0 and lanes == 8:
         # a well-conditioned band (kappa of A/s about 330: some 9400 walk steps)
         A = W.from_dense(W.band_matrix(256, 31, seed=63).dense() + 40.0 * np.eye(256))
         walk = Q.Walk(A)
