@@ -148,13 +148,17 @@ def test_complex_solver(Q, oracle_mod):
     assert fid > 1 - 1e-4
 
 
-def test_complex_gradient_not_provided(Q):
-    from paper_2303_06890_amd import QwError
-
+def test_complex_gradient_takes_the_complex_entry_point(Q):
+    """A complex context's gradient goes through qw_grad_complex: one complex
+    entry (dL/dRe + i dL/dIm) per stored value, the loss equal to the
+    forward walk's (the entry-by-entry checks are in test_gpu_grad_complex.py)."""
     csc = W.hermitian_offset_matrix(32, 4, seed=51)
-    st = Q.Walk(csc).state(W.uniform_b(32)).step(3)
-    with pytest.raises(QwError, match="real matrices"):
-        st.grad(np.ones(32), 3)
+    walk = Q.Walk(csc)
+    st = walk.state(W.uniform_b(32)).step(3)
+    loss, dv, db = st.grad(np.ones(32), 3)
+    assert np.iscomplexobj(dv) and dv.shape == (csc.nnz,)
+    p = walk.state(W.uniform_b(32)).step(3).j_marginal()[:32]
+    assert loss == pytest.approx(float(p.sum()), rel=1e-13)
 
 
 def test_complex_chebyshev_full_size(Q):
