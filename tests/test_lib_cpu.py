@@ -249,3 +249,19 @@ def test_solver_and_kappa_argument_checks(lib):
     bp = b.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
     assert lib.qls_run(None, bp, 10.0, 1e-3, -1, None, None, None, None, None, None) == _lib.QW_EINVAL
     assert lib.qw_ctx_info(None, 0, None, None, None, None, ctypes.byref(k)) == _lib.QW_EINVAL
+
+
+def test_gradient_argument_checks(lib):
+    """The three gradient entry points reject a missing state or weight
+    vector before touching the device."""
+    from paper_2303_06890_amd import _lib
+
+    w = np.ones(4)
+    out = np.zeros(8)
+    dp = ctypes.POINTER(ctypes.c_double)
+    wp, op = w.ctypes.data_as(dp), out.ctypes.data_as(dp)
+    loss = ctypes.c_double()
+    assert lib.qw_grad(None, wp, 1, op, op, op, ctypes.byref(loss), None) == _lib.QW_EINVAL
+    assert lib.qw_grad_noalloc(None, wp, 1, op, op, op, ctypes.byref(loss), None) == _lib.QW_EINVAL
+    assert lib.qw_grad_complex(None, wp, 1, op, op, op, op, ctypes.byref(loss), None) == _lib.QW_EINVAL
+    assert b"missing" in lib.qw_last_error()
