@@ -493,9 +493,10 @@ def adjoint_leg(Q, W, steps: int = 20, reps: int = 5):
     """Gradient of the total probability of 32 column outcomes after 20 steps
     w.r.t. all stored values and b (forward walk + reverse sweep with
     recomputation), against the forward walk alone: on G(1024, 8) (8192
-    values) and on the benchmark's G(16384, 8) (131072 values), and on the
+    values) and on the benchmark's G(16384, 8) (131072 values), on the
     complex Hermitian offset matrices of the same sizes (the real and the
-    imaginary part of every value)."""
+    imaginary part of every value), and on the band of the paper's shape E
+    (s = 64)."""
     import numpy as np
 
     out = {}
@@ -507,6 +508,9 @@ def adjoint_leg(Q, W, steps: int = 20, reps: int = 5):
         _, b, w = W.adjoint_problem(n)
         cases.append((f"complex Hermitian {n}x8", f"complex Hermitian offset matrix n = {n}, 8 entries/column, seed 4",
                       W.hermitian_offset_matrix(n, 8, seed=4), b, w))
+    e_csc, e_b = W.table1_band("E")
+    _, _, e_w = W.adjoint_problem(e_csc.n)
+    cases.append(("band E", "band matrix of the paper's shape E (16384 rows, bandwidth 31, s = 64)", e_csc, e_b, e_w))
     for label, what, a, b, w in cases:
         sc = 1.0 / np.abs(a.vals).max()
         a = W.Csc(a.n, a.colptr, a.rowidx, a.vals * sc)

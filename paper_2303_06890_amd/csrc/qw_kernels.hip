@@ -822,6 +822,23 @@ __device__ __forceinline__ double join_parts(double c, int lane) {
 // slots of value 0 are skipped as in step_wave when StepArgs::zskip is set).
 // EQ0: when Q0 of a slot without a partner is read (see below); both forms
 // are correct for every matrix, the launcher takes the faster one.
+// The same join for two sums at once (the adjoint kernels' c and d).
+template <int K>
+__device__ __forceinline__ double2 join_parts2(double2 cd, int lane) {
+  __shared__ double2 part2[kMaxBlock / kWave][16];
+  const int wib = int(threadIdx.x) >> 6;
+  if (lane < 16) part2[wib][lane] = cd;
+  __syncthreads();
+  const int first = wib & ~(K - 1);
+  double2 t = part2[first][lane & 15];
+#pragma unroll
+  for (int q = 1; q < K; ++q) {
+    const double2 u = part2[first + q][lane & 15];
+    t = make_double2(t.x + u.x, t.y + u.y);
+  }
+  return t;
+}
+
 // K > 1: rows split over K wavefronts (lanes_split; S >= kSplitMinS, K = 2
 // for W = 0, 4 for W = 1).
 template <bool ACC, int SLM, int S, int ENC, int W = 0, bool EQ0 = false, int K = 1>
@@ -1264,9 +1281,12 @@ namespace qw {
 // and the outputs are the real step's for both states.  One pass over the
 // wavefronts (every row exists, empty lists).  Returns the recomputed
 // state's kept outputs, counted as the step kernels count them.
-template <int SLM, int S, int W = 0, bool EQ0 = false>
+// K > 1: rows split over K wavefronts, as in step_wave_real.
+template <int SLM, int S, int W = 0, bool EQ0 = false, int K = 1>
 __device__ __forceinline__ unsigned adjoint_wave_real(const AdjArgs& a, int64_t w, int lane) {
-  const Lanes x = lanes_of<S, true, W>(a.m, w, lane);
+  static_assert(K == 1 || (S >= 16 && K == (W ? 4 : 2) && S / (4 * K) == Shape<S, W>::sl),
+                "the split mapping keeps the slots per lane of the whole-row mapping");
+  const Lanes x = K > 1 ? lanes_split<S, K>(a.m, w, lane) : lanes_of<S, true, W>(a.m, w, lane);
   const int sl = S ? Shape<S, W>::sl : (SLM == 1 ? 1 : x.I.sl);
   const int64_t base = x.I.item_base;
   const double* R0 = reinterpret_cast<const double*>(a.in.R0);
@@ -1319,6 +1339,11 @@ __device__ __forceinline__ unsigned adjoint_wave_real(const AdjArgs& a, int64_t 
   }
   c = row_sum_r<SLM>(c, x.rpw_log);
   d = row_sum_r<SLM>(d, x.rpw_log);
+  if constexpr (K > 1) {
+    const double2 cd = join_parts2<K>(make_double2(c, d), lane);
+    c = cd.x;
+    d = cd.y;
+  }
   const double t = two_over_s<S>(x.I);
   const double tc = c * t, td = d * t;
   double* oR0 = reinterpret_cast<double*>(a.out.R0);
@@ -1368,7 +1393,15 @@ __device__ __forceinline__ void adjoint_body_real(const AdjArgs& a) {
   if (w >= a.m.waves) return;
   const int64_t cidx = wave_counter(wpb);
   const unsigned long long prev = a.acc ? a.acc[cidx] : 0ull;
-  const unsigned cnt = adjoint_wave_real<SLM, S, W, EQ0>(a, w, lane);
+  unsigned cnt;
+  if constexpr (S >= kSplitMinS) {
+    constexpr int K = W ? 4 : 2;
+    // groups of K wavefronts in each workgroup: rows split over the group
+    cnt = wpb % K == 0 ? adjoint_wave_real<SLM, S, W, EQ0, K>(a, w, lane)
+                       : adjoint_wave_real<SLM, S, W, EQ0, 1>(a, w, lane);
+  } else {
+    cnt = adjoint_wave_real<SLM, S, W, EQ0, 1>(a, w, lane);
+  }
   if (a.acc) {
     const unsigned long long v = wave_sum_bits<CountBits<SLM>::value>(cnt);
     if (lane == 0) a.acc[cidx] = prev + v;

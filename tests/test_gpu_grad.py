@@ -174,3 +174,40 @@ def test_grad_batched_mixed_s_on_real_planes(Q, oracle_mod):
         off += csc.nnz
         boff += csc.n
     assert gl == pytest.approx(total, rel=1e-12)
+
+
+@pytest.mark.parametrize("lanes", [8, 16])
+def test_grad_s64_rows_split(Q, oracle_mod, lanes):
+    """s = 64 (a band of half-width 31 on 64 rows, real b): in 256-thread
+    workgroups the one-pass adjoint kernels split each row over two (eight
+    lanes per row) or four (sixteen) wavefronts, joining both group sums
+    through LDS; the gradient entry by entry against the oracle's reverse
+    mode, and against the whole-row form of 64-thread workgroups up to
+    rounding.  (The oracle's stored-state reverse mode grows steeply with the
+    steps at s = 64: 0.5 s for 4 steps here, about 2 minutes for 4 steps on
+    128 rows.)"""
+    n, nsteps = 64, 4
+    csc = _scaled(W.band_matrix(n, 31, seed=87))
+    b = W.gaussian_b(n, seed=88)
+    b = b / np.linalg.norm(b)
+    w = np.zeros(n)
+    w[np.random.default_rng(89).choice(n, size=n // 4, replace=False)] = 1.0
+    ol, og, odb = _oracle_csc_grad(oracle_mod, csc, b, w, nsteps)
+    out = {}
+    for wg in (256, 64):
+        walk = Q.Walk(csc, scale=1.0, symmetric=False, lanes=lanes)
+        assert walk.info[0]["s"] == 64
+        waves = n * lanes // 64
+        st = walk.state(b)
+        st.set_launch(wg, waves // (wg // 64))
+        st.step(nsteps)
+        assert st.stats()["real_amplitudes"]
+        gl, gg, gdb = st.grad(w, nsteps)
+        assert gl == pytest.approx(ol, rel=1e-12)
+        fin, _, _ = _close(gg, og, _floor_dv(csc.vals, 64, nsteps), where=f"dvals lanes={lanes} wg={wg}")
+        assert fin.sum() >= csc.nnz - 2
+        _close(gdb, odb, _floor_db(64, nsteps), where=f"db lanes={lanes} wg={wg}")
+        out[wg] = (gg, gdb)
+        walk.close()
+    fin = np.isfinite(out[256][0]) & np.isfinite(out[64][0])
+    assert np.allclose(out[256][0][fin], out[64][0][fin], rtol=1e-12, atol=1e-15)
